@@ -1,0 +1,130 @@
+"""Subdomains, overlap and interface entities (CPU).
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
+
+Section 2.1 of the paper: Omega is split into N non-overlapping subdomains
+Omega_i; Omega_i' adds k layers of overlap.  The interface Gamma is split into
+vertices, edges and faces, and each such entity carries the null space of the
+operator (three velocity translations and the pressure constant).
+
+Readings (pinned by ``tests/test_oracle_decomposition.py``):
+
+* Subdomain (I, J, K) is the closed element box [I s, (I+1) s] x ... with
+  s = n / m, numbered I + m (J + m K).
+* Overlap delta = element layers: S_i holds the free DOFs of every node of
+  the closed box grown by delta elements and clipped to the cube.  For
+  delta = 1 this is one layer of matrix-graph neighbours of the closed box.
+* Gamma holds the free DOFs whose node lies in at least two closed boxes
+  (nodes on the outer boundary that belong to one box are not interface).
+* An entity is a class of Gamma nodes with the same set of subdomains; a
+  face has 2, an edge 4 and a vertex 8 subdomains.  Boundary nodes fall into
+  the class of the same subdomain set, which is how faces absorb the
+  outflow edges and edges absorb the outflow vertices.
+* Coarse DOF order: entities sorted by the smallest Q2 node id of a node that
+  carries a free DOF of the entity, then fields u_x, u_y, u_z, p.
+* I_i: free DOFs of closed box i that are not in Gamma.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def box_range_1d(coord, s, m):
+    """Indices of the closed boxes that contain a node with the given
+    coordinate (half-element units) along one axis: [lo, hi]."""
+    coord = np.asarray(coord)
+    two_s = 2 * s
+    lo = np.where(coord % two_s == 0, np.maximum(coord // two_s - 1, 0), coord // two_s)
+    hi = np.minimum(coord // two_s, m - 1)
+    return lo, hi
+
+
+class Decomposition:
+    """Structured m^3 decomposition of a ``StokesProblem``."""
+
+    def __init__(self, prob, m, overlap=1):
+        n = prob.n
+        if n % m != 0:
+            raise ValueError("n must be a multiple of m")
+        if overlap < 1:
+            raise ValueError("overlap must be >= 1")
+        self.m = m
+        self.s = n // m
+        self.overlap = overlap
+        self.n_sub = m ** 3
+        s = self.s
+        abc = prob.dof_node           # (n_free, 3) half-element units
+        field = prob.dof_field
+
+        # per-axis closed-box index ranges and the subdomain set of each free DOF
+        lo = np.zeros_like(abc)
+        hi = np.zeros_like(abc)
+        for d in range(3):
+            lo[:, d], hi[:, d] = box_range_1d(abc[:, d], s, m)
+        self.lo, self.hi = lo, hi
+        mult = np.prod(hi - lo + 1, axis=1)
+        self.multiplicity = mult
+        self.is_gamma = mult >= 2
+
+        # closed box and overlapping box membership
+        self.S = []          # overlapping index sets (sorted free DOF indices)
+        self.box = []        # closed-box DOFs
+        self.I = []          # interior DOFs (closed box, not Gamma)
+        for K in range(m):
+            for J in range(m):
+                for I in range(m):
+                    ijk = np.array([I, J, K])
+                    inside_closed = np.all((abc >= 2 * s * ijk) & (abc <= 2 * s * (ijk + 1)), axis=1)
+                    lo_o = 2 * (s * ijk - overlap)
+                    hi_o = 2 * (s * (ijk + 1) + overlap)
+                    inside_ovl = np.all((abc >= lo_o) & (abc <= hi_o), axis=1)
+                    self.S.append(np.nonzero(inside_ovl)[0])
+                    self.box.append(np.nonzero(inside_closed)[0])
+                    self.I.append(np.nonzero(inside_closed & ~self.is_gamma)[0])
+
+        # entities: classes of Gamma DOFs by subdomain set (lo, hi per axis)
+        g = np.nonzero(self.is_gamma)[0]
+        key = np.concatenate([lo[g], hi[g]], axis=1)
+        uniq, inv = np.unique(key, axis=0, return_inverse=True)
+        inv = inv.ravel()
+        # sort classes by smallest Q2 node id
+        q2id = prob.dof_q2id[g]
+        minid = np.full(len(uniq), np.iinfo(np.int64).max)
+        np.minimum.at(minid, inv, q2id)
+        order = np.argsort(minid, kind="stable")
+        rank = np.empty_like(order)
+        rank[order] = np.arange(order.size)
+        self.n_ent = len(uniq)
+        self.entity_key = uniq[order]               # (lo0..2, hi0..2)
+        self.gamma = g
+        self.gamma_entity = rank[inv]                # entity of each Gamma DOF
+        self.gamma_field = field[g]
+
+        # coarse columns (e, f) that carry at least one DOF
+        has = np.zeros((self.n_ent, 4), dtype=bool)
+        has[self.gamma_entity, self.gamma_field] = True
+        col = -np.ones((self.n_ent, 4), dtype=np.int64)
+        col[has] = np.arange(has.sum())
+        self.coarse_col = col
+        self.n_coarse = int(has.sum())
+        self.coarse_entity = np.repeat(np.arange(self.n_ent), 4).reshape(self.n_ent, 4)[has]
+        self.coarse_field = np.tile(np.arange(4), (self.n_ent, 1))[has]
+
+    # --- entity bookkeeping -------------------------------------------------
+    def entity_subdomains(self, e):
+        """Sorted subdomain indices of entity e."""
+        lo, hi = self.entity_key[e, :3], self.entity_key[e, 3:]
+        out = []
+        for K in range(lo[2], hi[2] + 1):
+            for J in range(lo[1], hi[1] + 1):
+                for I in range(lo[0], hi[0] + 1):
+                    out.append(I + self.m * (J + self.m * K))
+        return sorted(out)
+
+    def entity_kind(self, e):
+        """'face', 'edge' or 'vertex' by the number of subdomains (2, 4, 8)."""
+        k = int(np.prod(self.entity_key[e, 3:] - self.entity_key[e, :3] + 1))
+        return {2: "face", 4: "edge", 8: "vertex"}[k]
+
+    def local_sizes(self):
+        return np.array([len(S) for S in self.S])

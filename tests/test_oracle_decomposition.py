@@ -1,0 +1,74 @@
+"""Pins of the decomposition, overlap and interface entities (Section 2.1)."""
+import numpy as np
+import pytest
+
+from oracle.counts import (full_gdsw_closed_form, full_gdsw_count,
+                           paper_three_level_coarse_dim, paper_two_level_coarse_dim)
+from oracle.decomposition import Decomposition
+from oracle.stokes import StokesProblem
+
+
+@pytest.mark.parametrize("m", [2, 3, 4])
+def test_entity_counts_closed_form(m):
+    p = StokesProblem(2 * m)
+    d = Decomposition(p, m, 1)
+    assert d.n_ent == full_gdsw_closed_form(m) == full_gdsw_count(m)
+    kinds = [d.entity_kind(e) for e in range(d.n_ent)]
+    assert kinds.count("face") == 3 * (m - 1) * m * m
+    assert kinds.count("edge") == 3 * m * (m - 1) ** 2
+    assert kinds.count("vertex") == (m - 1) ** 3
+    # Q2/Q1: every entity carries all four fields
+    assert d.n_coarse == 4 * d.n_ent
+    assert [full_gdsw_closed_form(k) * 4 for k in (2, 4, 6, 8)] == [76, 1116, 4460, 11452]
+
+
+def test_paper_table_coarse_dimensions():
+    """Table 1 (GDSW*, 2nd level) and Table 2 (3rd level) coarse-DOF columns."""
+    assert paper_two_level_coarse_dim(8) == 5573
+    assert paper_two_level_coarse_dim(16) == 48781
+    assert paper_two_level_coarse_dim(32) == 407837
+    assert paper_three_level_coarse_dim(8, (2, 2, 2)) == 65
+    assert paper_three_level_coarse_dim(16, (4, 4, 4)) == 901
+    assert paper_three_level_coarse_dim(32, (8, 8, 4)) == 4213
+
+
+def test_partition_and_interface():
+    p = StokesProblem(6)
+    d = Decomposition(p, 3, 1)
+    allI = np.concatenate(d.I)
+    assert np.unique(allI).size == allI.size                   # I_i disjoint
+    assert np.intersect1d(allI, d.gamma).size == 0
+    assert allI.size + d.gamma.size == p.n_free                 # I and Gamma cover
+    # every Gamma DOF sits in >= 2 closed boxes, every I DOF in exactly one
+    cnt = np.zeros(p.n_free, dtype=int)
+    for B in d.box:
+        cnt[B] += 1
+    assert np.all(cnt[d.gamma] >= 2) and np.all(cnt[allI] == 1)
+
+
+def test_overlap_is_one_graph_layer():
+    """S_i (closed box grown by one element) = closed box plus its neighbours in
+    the sparsity graph of A."""
+    p = StokesProblem(6)
+    d = Decomposition(p, 3, 1)
+    A = p.A.tocsr()
+    for i in (0, 4, 13, 26):
+        box = d.box[i]
+        nb = np.unique(A[box].indices)
+        assert np.array_equal(np.union1d(box, nb), d.S[i])
+
+
+def test_local_sizes():
+    p = StokesProblem(4)
+    d = Decomposition(p, 2, 1)
+    sz = d.local_sizes()
+    assert sz.min() == 712 and sz.max() == 820
+    # 16^3 mesh, 4^3 subdomains: corner box grows inward only, interior by one layer
+    p = StokesProblem(16)
+    d = Decomposition(p, 4, 1)
+    sz = d.local_sizes()
+    assert sz.max() == 3 * 13 ** 3 + 7 ** 3 == 6934
+    assert sz.min() == 3 * 10 ** 3 + 6 ** 3 == 3216
+    assert int((sz.astype(np.int64) ** 2).sum()) * 8 == 13037206048
+    isz = [len(I) for I in d.I]
+    assert min(isz) == 1056 and max(isz) == 1240

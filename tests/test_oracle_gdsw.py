@@ -1,0 +1,153 @@
+"""Pins of the two-level monolithic GDSW preconditioner (eqs. 2.2-2.4)."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse.linalg as spla
+
+from oracle.decomposition import Decomposition
+from oracle.fgmres import fgmres
+from oracle.gdsw import TwoLevelGDSW
+from oracle.stokes import StokesProblem
+
+
+@pytest.fixture(scope="module")
+def n6m3():
+    p = StokesProblem(6, viscosity=0.8)
+    d = Decomposition(p, 3, 1)
+    return p, d, TwoLevelGDSW(p.A, d)
+
+
+def _touches(d, i, axis, side):
+    m = d.m
+    ijk = (i % m, (i // m) % m, i // (m * m))
+    return ijk[axis] == (0 if side == 0 else m - 1)
+
+
+def test_phi_gamma_partition_of_unity(n6m3):
+    p, d, M = n6m3
+    Phi = M.Phi.tocsr()
+    for f in range(4):
+        cols = np.nonzero(d.coarse_field == f)[0]
+        rows = d.gamma[d.gamma_field == f]
+        s = np.asarray(Phi[rows][:, cols].sum(axis=1)).ravel()
+        assert np.array_equal(s, np.ones(rows.size))          # exact
+        other = d.gamma[d.gamma_field != f]
+        assert Phi[other][:, cols].count_nonzero() == 0
+
+
+def test_extension_reproduces_constants(n6m3):
+    p, d, M = n6m3
+    Phi = M.Phi.tocsr()
+    for f in range(4):
+        cols = np.nonzero(d.coarse_field == f)[0]
+        v = np.asarray(Phi[:, cols].sum(axis=1)).ravel()
+        for i in range(d.n_sub):
+            Ii = d.I[i]
+            target = (p.dof_field[Ii] == f).astype(float)
+            if f < 3:
+                # velocity translation: subdomain must not touch Dirichlet faces
+                ok = not (_touches(d, i, 0, 0) or any(_touches(d, i, a, s) for a in (1, 2) for s in (0, 1)))
+            else:
+                ok = not _touches(d, i, 0, 1)   # pressure: away from the outflow
+            err = np.abs(v[Ii] - target).max()
+            if ok:
+                assert err < 1e-12, (f, i, err)
+    # the centre subdomain reproduces all four null-space vectors; a boundary one
+    # does not reproduce u_x (check the test has teeth)
+    cols = np.nonzero(d.coarse_field == 0)[0]
+    v = np.asarray(Phi[:, cols].sum(axis=1)).ravel()
+    I0 = d.I[0]
+    assert np.abs(v[I0] - (p.dof_field[I0] == 0)).max() > 1e-3
+
+
+def test_energy_minimising_extension_and_symmetry(n6m3):
+    p, d, M = n6m3
+    A = p.A.tocsr()
+    R = A @ M.Phi
+    for i in range(d.n_sub):
+        Ii = d.I[i]
+        res = np.abs(R[Ii].toarray()).max()
+        scale = np.abs(A[Ii]).max() * np.abs(M.Phi).max()
+        assert res < 1e-12 * scale
+    assert np.abs(M.A0 - M.A0.T).max() < 1e-12 * np.abs(M.A0).max()
+    # off-diagonal blocks Phi_{I,u0,p}, Phi_{I,p0,u} are present (monolithic)
+    Phi = M.Phi.tocsr()
+    vel_cols = np.nonzero(d.coarse_field < 3)[0]
+    p_rows = np.nonzero(p.dof_field == 3)[0]
+    assert np.abs(Phi[p_rows][:, vel_cols]).max() > 1e-6
+
+
+def test_preconditioner_symmetric_and_dense_brute_force():
+    p = StokesProblem(4)
+    d = Decomposition(p, 2, 1)
+    M = TwoLevelGDSW(p.A, d)
+    n = p.n_free
+    A = p.A.toarray()
+    # explicit eq. (2.2) with dense inverses
+    Md = np.zeros((n, n))
+    for Si in d.S:
+        Md[np.ix_(Si, Si)] += np.linalg.inv(A[np.ix_(Si, Si)])
+    Phi = M.Phi.toarray()
+    Md += Phi @ np.linalg.inv(Phi.T @ A @ Phi) @ Phi.T
+    rng = np.random.default_rng(0)
+    X = rng.standard_normal((n, 3))
+    Z = M(X)
+    assert np.abs(Z - Md @ X).max() < 1e-11 * np.abs(Z).max()
+    x, y = X[:, 0], X[:, 1]
+    assert abs(M(x) @ y - x @ M(y)) < 1e-11 * abs(M(x) @ y)
+
+
+def test_one_subdomain_is_exact_inverse():
+    p = StokesProblem(3)
+    d = Decomposition(p, 1, 1)
+    M = TwoLevelGDSW(p.A, d)
+    assert d.n_coarse == 0 and len(d.S) == 1 and d.S[0].size == p.n_free
+    r = np.random.default_rng(1).standard_normal(p.n_free)
+    assert np.allclose(M(r), spla.spsolve(p.A.tocsc(), r), rtol=1e-11, atol=1e-12)
+    x, it, rel, trel = fgmres(lambda v: p.A @ v, M, p.b, rtol=1e-10)
+    assert it == 1 and trel <= 1e-10
+
+
+def test_full_overlap_closed_form():
+    """m = 2 with overlap >= n/2: every S_i is the whole domain, so
+    B_GDSW = Phi A_0^{-1} Phi^T + 8 A^{-1}."""
+    p = StokesProblem(4)
+    d = Decomposition(p, 2, 2)
+    assert all(S.size == p.n_free for S in d.S)
+    M = TwoLevelGDSW(p.A, d)
+    A = p.A.toarray()
+    Phi = M.Phi.toarray()
+    ref = Phi @ np.linalg.solve(Phi.T @ A @ Phi, Phi.T) + 8 * np.linalg.inv(A)
+    r = np.random.default_rng(2).standard_normal(p.n_free)
+    assert np.abs(M(r) - ref @ r).max() < 1e-10 * np.abs(ref @ r).max()
+
+
+def test_fgmres_matches_direct_solution():
+    p = StokesProblem(4)
+    d = Decomposition(p, 2, 1)
+    M = TwoLevelGDSW(p.A, d)
+    xs = sla.solve(p.A.toarray(), p.b)
+    x, it, rel, trel = fgmres(lambda v: p.A @ v, M, p.b, rtol=1e-13)
+    assert trel <= 1e-13
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) < 1e-10
+    # paper tolerance
+    x8, it8, rel8, trel8 = fgmres(lambda v: p.A @ v, M, p.b, rtol=1e-8)
+    assert rel8 <= 1e-8 and trel8 <= 1e-8 and it8 < it
+
+
+def test_linearity_in_inflow_and_viscosity_scaling():
+    """x(c) = c x(1); for f = 0, u(mu) = u(1) and p(mu) = mu p(1)."""
+    res = {}
+    for mu, c in [(1.0, 1.0), (1.0, 1.7), (3.0, 1.0)]:
+        p = StokesProblem(4, viscosity=mu, inflow=c)
+        d = Decomposition(p, 2, 1)
+        M = TwoLevelGDSW(p.A, d)
+        x, it, _, _ = fgmres(lambda v: p.A @ v, M, p.b, rtol=1e-12)
+        res[(mu, c)] = (x, it, p.n_u)
+    x1, it1, nu = res[(1.0, 1.0)]
+    xc, itc, _ = res[(1.0, 1.7)]
+    assert itc == it1
+    assert np.abs(xc - 1.7 * x1).max() < 1e-9 * np.abs(x1).max() * 1.7
+    xm, _, _ = res[(3.0, 1.0)]
+    assert np.abs(xm[:nu] - x1[:nu]).max() < 1e-9 * np.abs(x1[:nu]).max()
+    assert np.abs(xm[nu:] - 3.0 * x1[nu:]).max() < 1e-9 * 3 * np.abs(x1[nu:]).max()

@@ -1,0 +1,87 @@
+"""Pins of the Q2/Q1 Stokes discretisation (Section 2, eq. 2.1)."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle.stokes import (StokesProblem, dof_count_q2p1disc, dof_count_q2q1,
+                           element_matrices)
+
+
+def test_dof_counts_closed_form():
+    for n in (1, 2, 3, 4):
+        assert StokesProblem(n).n_full == dof_count_q2q1(n)
+    # the four configured meshes
+    assert [dof_count_q2q1(n) for n in (4, 16, 24, 32)] == [2312, 112724, 368572, 859812]
+    assert dof_count_q2q1(4) - 125 == 2187
+    # Tables 1-2, #dof column (Q2 / P1-discontinuous)
+    assert [dof_count_q2p1disc(n) for n in (32, 64, 128)] == [954947, 7488643, 59312387]
+
+
+def test_free_dofs_and_symmetry():
+    p = StokesProblem(4)
+    # Dirichlet nodes: x = 0 face and the four walls; interior: a in 1..8, b, c in 1..7
+    assert p.n_u == 3 * 8 * 7 * 7
+    assert p.n_free == 1301
+    assert abs(p.A - p.A.T).max() < 1e-15
+    # velocity block first, pressure block has no diagonal
+    assert np.all(p.dof_field[:p.n_u] < 3) and np.all(p.dof_field[p.n_u:] == 3)
+    App = p.A[p.n_u:, p.n_u:]
+    assert App.count_nonzero() == 0
+
+
+def _exact_1d():
+    """Textbook 1-D Q2/Q1 element integrals on [0, 1] (exact rationals)."""
+    M = np.array([[4, 2, -1], [2, 16, 2], [-1, 2, 4]]) / 30.0      # int L_a L_b
+    S = np.array([[7, -8, 1], [-8, 16, -8], [1, -8, 7]]) / 3.0      # int L_a' L_b'
+    G = np.array([[1 / 6, 1 / 3, 0.0], [0.0, 1 / 3, 1 / 6]])        # int N_q L_a
+    C = np.array([[-5 / 6, 2 / 3, 1 / 6], [-1 / 6, -2 / 3, 5 / 6]])  # int N_q L_a'
+    return M, S, G, C
+
+
+@pytest.mark.parametrize("h,mu", [(1.0, 1.0), (0.25, 0.37)])
+def test_element_matrices_tensor_closed_form(h, mu):
+    M, S, G, C = _exact_1d()
+    k3 = lambda z, y, x: np.kron(z, np.kron(y, x))  # index a = ax + 3 (ay + 3 az)
+    K_ref = mu * h * (k3(M, M, S) + k3(M, S, M) + k3(S, M, M))
+    B_ref = np.zeros((8, 27, 3))
+    B_ref[:, :, 0] = -h * h * k3(G, G, C)
+    B_ref[:, :, 1] = -h * h * k3(G, C, G)
+    B_ref[:, :, 2] = -h * h * k3(C, G, G)
+    K, B = element_matrices(h, mu)
+    assert np.allclose(K, K_ref, rtol=0, atol=1e-14 * np.abs(K_ref).max())
+    assert np.allclose(B, B_ref, rtol=0, atol=1e-14 * np.abs(B_ref).max())
+
+
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_manufactured_poiseuille_is_exact(n):
+    """With f = (2 mu c [y(1-y) + z(1-z)], 0, 0) the quadratic profile and p = 0
+    solve the continuous problem and lie in Q2/Q1, so the discrete solution is
+    their nodal interpolant."""
+    p = StokesProblem(n, viscosity=0.7, inflow=16.0, manufactured=1)
+    x = spla.spsolve(p.A.tocsc(), p.b)
+    c = p.c
+    ref = p.interpolant(lambda X, Y, Z: np.stack([c * Y * (1 - Y) * Z * (1 - Z), 0 * X, 0 * X]),
+                        lambda X, Y, Z: 0 * X)
+    assert np.abs(p.expand(x) - ref).max() < 1e-10
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_linear_pressure_flow_is_exact(n):
+    """u = (c y(1-y), 0, 0), p = 2 mu c (1 - x) solves Stokes with f = 0 and the
+    do-nothing condition at x = 1; Dirichlet data from u on x = 0 and the walls."""
+    mu, c = 1.3, 2.0
+    u = lambda X, Y, Z: np.stack([c * Y * (1 - Y) + 0 * X, 0 * X, 0 * X])
+    pfun = lambda X, Y, Z: 2 * mu * c * (1 - X)
+    p = StokesProblem(n, viscosity=mu, inflow=c, dirichlet=u)
+    x = spla.spsolve(p.A.tocsc(), p.b)
+    assert np.abs(p.expand(x) - p.interpolant(u, pfun)).max() < 1e-10
+
+
+def test_plain_poiseuille_is_not_exact():
+    """Without the body force the product profile is not a Stokes solution."""
+    p = StokesProblem(3)
+    x = spla.spsolve(p.A.tocsc(), p.b)
+    c = p.c
+    ref = p.interpolant(lambda X, Y, Z: np.stack([c * Y * (1 - Y) * Z * (1 - Z), 0 * X, 0 * X]),
+                        lambda X, Y, Z: 0 * X)
+    assert np.abs(p.expand(x) - ref).max() > 1e-3
