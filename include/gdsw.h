@@ -1,0 +1,220 @@
+/*
+ * gdsw.h -- C ABI of the MI355X (gfx950) monolithic GDSW / FGMRES library.
+ *
+ * Problem (Section 2 of Koehler & Rheinbach, "Monolithic Multi-level
+ * Overlapping Schwarz Solvers for Fluid Problems"): the Stokes saddle-point
+ * system of eq. (2.1),
+ *
+ *     [A  B^T] [u]   [F]
+ *     [B  0  ] [p] = [0],
+ *
+ * discretised with Q2 velocity and Q1 pressure on the unit cube split into
+ * n^3 hexahedra, Poiseuille inflow u_x = c y(1-y) z(1-z) on x = 0, no-slip
+ * walls on y, z in {0, 1} and a do-nothing outflow on x = 1 (Section 4).
+ *
+ * Preconditioner: the monolithic two-level GDSW operator of eq. (2.2),
+ *     M^-1 = Phi A_0^-1 Phi^T + sum_i R_i^T A_i^-1 R_i,
+ * with A_0 = Phi^T A Phi and R_i of eq. (2.3) and the energy-minimising coarse
+ * basis Phi of eq. (2.4); or the three-level operator of eq. (2.5).  It is
+ * applied inside flexible GMRES (Tables 1-4: FGMRES, relative tolerance).
+ *
+ * Conventions shared by every entry point
+ *   - Vectors live on the FREE degrees of freedom only (Dirichlet velocity
+ *     DOFs are eliminated and their data lifted into the right-hand side):
+ *     first every free velocity DOF -- Q2 nodes (a, b, c), a, b, c in [0, 2n],
+ *     lexicographic with a fastest, then the component x, y, z -- then every
+ *     pressure DOF (Q1 nodes (i, j, k) lexicographic with i fastest).
+ *     gdsw_dof_map() reports the field and node of each free DOF.
+ *   - Vector arguments are DEVICE pointers to FP64 arrays owned by the caller
+ *     (for example torch tensors); the library never frees them.  Multi-column
+ *     arguments are column-major with leading dimension ld >= n_free.
+ *   - The library owns every internal device buffer.  They are allocated in
+ *     gdsw_setup() and released in gdsw_destroy(); gdsw_apply_precond() and
+ *     gdsw_spmv() allocate nothing.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Work is enqueued on it; calls return without waiting unless stated.
+ *   - One context must not be used from two streams at the same time.
+ *   - Every function returns a gdsw_status; no exception crosses the ABI.
+ *     On failure a message is available from gdsw_last_error().
+ *   - Results are bitwise reproducible for the same inputs, build and GPU:
+ *     every reduction runs in a fixed order, no floating-point atomics.
+ */
+#ifndef GDSW_H
+#define GDSW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gdsw_ctx gdsw_ctx; /* opaque, owned by the library */
+
+typedef enum {
+  GDSW_OK = 0,
+  GDSW_EINVAL = 1,       /* bad argument: sizes, pointers, n % m != 0, ... */
+  GDSW_ENOMEM = 2,       /* device or host memory (budget) exhausted */
+  GDSW_ESINGULAR = 3,    /* a zero or tiny pivot in a local or coarse factor */
+  GDSW_ENOCONV = 4,      /* FGMRES reached max_it; x holds the last iterate */
+  GDSW_EDEVICE = 5,      /* a HIP runtime error; its text is in last_error */
+  GDSW_EUNSUPPORTED = 6  /* valid request this build does not implement */
+} gdsw_status;
+
+typedef enum { GDSW_FP64 = 0, GDSW_FP32 = 1, GDSW_BF16 = 2 } gdsw_precision;
+
+/* The mesh: structured Q2/Q1 Stokes on the unit cube (Section 4). */
+typedef struct {
+  int32_t n;                  /* n^3 hexahedra, n >= 1 */
+  int32_t manufactured_force; /* 0: f = 0 (the paper's workload);
+                                 1: f_x = 2 mu c (y(1-y) + z(1-z)), which makes
+                                    u = (c y(1-y) z(1-z), 0, 0), p = 0 exact */
+  double viscosity;           /* mu > 0 */
+  double inflow_amplitude;    /* c */
+} gdsw_mesh;
+
+/* Decomposition, overlap and levels (Section 2.1 and 2.2). */
+typedef struct {
+  int32_t subdomains;         /* m subdomains per axis (N = m^3), n % m == 0 */
+  int32_t overlap;            /* delta >= 1 element layers; the overlapping set
+                                 of subdomain i holds the free DOFs of every
+                                 node of its closed box grown by delta */
+  int32_t levels;             /* 2: eq. (2.2);  3: eq. (2.5) */
+  int32_t group;              /* levels == 3: subdomains per subregion per axis,
+                                 m % group == 0 (N^(2) = (m/group)^3) */
+  int32_t local_precision;    /* gdsw_precision of the level-1 local factors
+                                 (the coarse levels are always FP64) */
+  int32_t tile;               /* triangular-solve tile size: 0 = default,
+                                 else 64 or 128 */
+  uint64_t device_mem_budget; /* bytes the setup may allocate; 0 = the free
+                                 device memory reported by HIP */
+} gdsw_decomposition;
+
+typedef struct {
+  double rtol;                /* stop when |g_{j+1}| / ||b||_2 <= rtol */
+  int32_t restart;            /* Krylov cycle length (1 ... 200) */
+  int32_t max_it;             /* total inner iterations */
+  int32_t use_graph;          /* 1: replay each iteration as a HIP graph */
+  int32_t reserved;
+} gdsw_fgmres_opts;
+
+typedef struct {
+  int32_t iterations;         /* preconditioner applications */
+  int32_t restarts;           /* completed cycles beyond the first */
+  double rel_res;             /* last implicit |g_{j+1}| / ||b|| */
+  double true_rel_res;        /* ||b - A x|| / ||b|| recomputed at the end */
+  double t_solve_s;           /* wall time of the solve (host clock) */
+} gdsw_fgmres_info;
+
+typedef struct {
+  int64_t n_free, n_full, n_u_free, n_p;
+  int64_t nnz;                /* nonzeros of the free-DOF CSR matrix */
+  int64_t n_sub;              /* N = m^3 */
+  int64_t n_entities;         /* interface entities (vertices, edges, faces) */
+  int64_t n_coarse;           /* columns of Phi = size of A_0 */
+  int64_t n_subregions;       /* three levels: N^(2), else 0 */
+  int64_t n_coarse3;          /* three levels: size of A_0^(3), else 0 */
+  int64_t local_min, local_max; /* smallest / largest overlapping local size */
+  uint64_t factor_bytes;      /* level-1 local factors as stored */
+  uint64_t coarse_bytes;      /* coarse factors and bases (all levels) */
+  uint64_t device_bytes;      /* everything the context holds on the device */
+  uint64_t solve_bytes;       /* algorithmic bytes the triangular solves of one
+                                 apply read: sum over every factor (local and
+                                 coarse) of n^2 * element size */
+  int64_t solve_launches;     /* triangular-solve kernel launches per apply */
+} gdsw_sizes;
+
+/* Setup ------------------------------------------------------------------- */
+
+/* Builds the problem (host: numbering, assembly, decomposition, interface
+ * entities; Section 3 calls this the symbolic setup) and the preconditioner
+ * (device: local matrices and their LU factors, Phi, A_0 and its factors;
+ * the numeric setup).  Blocks until the setup is complete.
+ * Errors: EINVAL for n < 1, m < 1, n % m, overlap < 1, levels not 2/3,
+ * m % group (3 levels), bad precision or tile; ENOMEM when the budget check
+ * fails (the message gives the bytes needed); ESINGULAR when a pivot of a
+ * local or coarse factor is tiny (the message names the factor). */
+gdsw_status gdsw_setup(const gdsw_mesh* mesh, const gdsw_decomposition* dec,
+                       void* stream, gdsw_ctx** out);
+
+/* Host-only variant: performs the symbolic setup and the assembly but touches
+ * no device.  Only gdsw_get_sizes, gdsw_dof_map, gdsw_host_matrix,
+ * gdsw_host_rhs, gdsw_last_error and gdsw_destroy accept such a context. */
+gdsw_status gdsw_setup_host(const gdsw_mesh* mesh, const gdsw_decomposition* dec,
+                            gdsw_ctx** out);
+
+gdsw_status gdsw_get_sizes(const gdsw_ctx* ctx, gdsw_sizes* out);
+
+/* field[k] in {0,1,2,3} (u_x, u_y, u_z, p) and node_abc[3k..3k+2] the Q2
+ * node coordinates (pressure nodes (i,j,k) map to (2i,2j,2k)) of free DOF k.
+ * Host arrays of n_free and 3 n_free int32. */
+gdsw_status gdsw_dof_map(const gdsw_ctx* ctx, int32_t* field, int32_t* node_abc);
+
+/* Copies the host-assembled free-DOF CSR matrix into caller host arrays of
+ * n_free + 1 (int64), nnz (int32) and nnz (double) entries. */
+gdsw_status gdsw_host_matrix(const gdsw_ctx* ctx, int64_t* row_ptr, int32_t* col,
+                             double* val);
+/* Copies the lifted right-hand side (host array of n_free doubles). */
+gdsw_status gdsw_host_rhs(const gdsw_ctx* ctx, double* b);
+
+/* Operators --------------------------------------------------------------- */
+
+/* b_dev[n_free] = lifted right-hand side of eq. (2.1) on the free DOFs. */
+gdsw_status gdsw_rhs(gdsw_ctx* ctx, double* b_dev, void* stream);
+
+/* y = A x, the free-DOF saddle-point matrix of eq. (2.1).  x and y must not
+ * overlap. */
+gdsw_status gdsw_spmv(gdsw_ctx* ctx, const double* x_dev, double* y_dev, void* stream);
+
+/* z = M^-1 r for nrhs columns (eq. 2.2, or eq. 2.5 with three levels).
+ * r and z must not overlap.  Allocates nothing. */
+gdsw_status gdsw_apply_precond(gdsw_ctx* ctx, const double* r_dev, double* z_dev,
+                               int32_t nrhs, int64_t ld, void* stream);
+
+/* Solves A x = b with right-preconditioned FGMRES for nrhs columns, one after
+ * another, from x = 0.  Blocks until every column is done (the loop reads the
+ * residual estimate back to the host once per iteration).  info[nrhs] may be
+ * NULL.  Returns ENOCONV if a column missed rtol within max_it (x then holds
+ * its last iterate and info is filled in). */
+gdsw_status gdsw_fgmres_solve(gdsw_ctx* ctx, const double* b_dev, double* x_dev,
+                              int32_t nrhs, int64_t ld, const gdsw_fgmres_opts* opts,
+                              gdsw_fgmres_info* info, void* stream);
+
+/* x_full[n_full] = free values scattered into the full DOF vector (velocity
+ * 3*node + component, then pressure) with the Dirichlet data re-inserted. */
+gdsw_status gdsw_expand_solution(const gdsw_ctx* ctx, const double* x_free_dev,
+                                 double* x_full_dev, void* stream);
+
+/* Setup results for inspection (device -> host copies, blocking) --------- */
+
+/* A_0 = Phi^T A Phi as a dense row-major n_coarse^2 host array. */
+gdsw_status gdsw_copy_coarse_matrix(const gdsw_ctx* ctx, double* a0_host);
+
+/* Phi as a dense column-major n_free x n_coarse host array (tests only:
+ * small problems). */
+gdsw_status gdsw_copy_coarse_basis(const gdsw_ctx* ctx, double* phi_host);
+
+/* Overlapping index set of subdomain i (sorted free DOF numbers), host array
+ * of local_size(i) int32; pass NULL to query the size into *size. */
+gdsw_status gdsw_local_indices(const gdsw_ctx* ctx, int32_t i, int32_t* idx_host,
+                               int32_t* size);
+
+/* Diagnostics --------------------------------------------------------------- */
+
+/* One gdsw_apply_precond() with HIP events between its phases, recorded on
+ * `stream`; blocks until done.  ms[0] = gathers and coarse restriction,
+ * ms[1] = triangular solves of the level-1 factor set (with the coarse factor
+ * when it shares the set's precision), ms[2] = triangular solves of the FP64
+ * coarse-level set, ms[3] = scatter and prolongation (milliseconds). */
+gdsw_status gdsw_profile_apply(gdsw_ctx* ctx, const double* r_dev, double* z_dev, void* stream,
+                               double* ms);
+
+/* Last error text of ctx, or of the calling thread when ctx is NULL. */
+const char* gdsw_last_error(const gdsw_ctx* ctx);
+
+/* Releases every device and host resource of ctx (NULL is allowed). */
+void gdsw_destroy(gdsw_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GDSW_H */

@@ -1,0 +1,224 @@
+"""Python binding of libgdsw (include/gdsw.h): argument marshalling only.
+
+Every operation runs in the HIP library; this module converts torch tensors
+to device pointers and the current torch stream to a hipStream_t.  Importing
+the package loads the library and raises if it has not been built
+(``python -m paper_2508_04356_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgdsw.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2508_04356_amd.build`")
+_lib = C.CDLL(LIB_PATH)
+
+FP64, FP32, BF16 = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
+STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "ESINGULAR", 4: "ENOCONV", 5: "EDEVICE", 6: "EUNSUPPORTED"}
+
+
+class Mesh(C.Structure):
+    _fields_ = [("n", C.c_int32), ("manufactured_force", C.c_int32), ("viscosity", C.c_double),
+                ("inflow_amplitude", C.c_double)]
+
+
+class Decomposition(C.Structure):
+    _fields_ = [("subdomains", C.c_int32), ("overlap", C.c_int32), ("levels", C.c_int32), ("group", C.c_int32),
+                ("local_precision", C.c_int32), ("tile", C.c_int32), ("device_mem_budget", C.c_uint64)]
+
+
+class FgmresOpts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("restart", C.c_int32), ("max_it", C.c_int32), ("use_graph", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class FgmresInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("restarts", C.c_int32), ("rel_res", C.c_double),
+                ("true_rel_res", C.c_double), ("t_solve_s", C.c_double)]
+
+
+class Sizes(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in ("n_free", "n_full", "n_u_free", "n_p", "nnz", "n_sub", "n_entities",
+                                         "n_coarse", "n_subregions", "n_coarse3", "local_min", "local_max")] + \
+               [(k, C.c_uint64) for k in ("factor_bytes", "coarse_bytes", "device_bytes", "solve_bytes")] + \
+               [("solve_launches", C.c_int64)]
+
+
+_P = C.c_void_p
+_sig = {
+    "gdsw_setup": (C.c_int, [C.POINTER(Mesh), C.POINTER(Decomposition), _P, C.POINTER(_P)]),
+    "gdsw_setup_host": (C.c_int, [C.POINTER(Mesh), C.POINTER(Decomposition), C.POINTER(_P)]),
+    "gdsw_get_sizes": (C.c_int, [_P, C.POINTER(Sizes)]),
+    "gdsw_dof_map": (C.c_int, [_P, _P, _P]),
+    "gdsw_host_matrix": (C.c_int, [_P, _P, _P, _P]),
+    "gdsw_host_rhs": (C.c_int, [_P, _P]),
+    "gdsw_rhs": (C.c_int, [_P, _P, _P]),
+    "gdsw_spmv": (C.c_int, [_P, _P, _P, _P]),
+    "gdsw_apply_precond": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int64, _P]),
+    "gdsw_fgmres_solve": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int64, C.POINTER(FgmresOpts),
+                                    C.POINTER(FgmresInfo), _P]),
+    "gdsw_expand_solution": (C.c_int, [_P, _P, _P, _P]),
+    "gdsw_copy_coarse_matrix": (C.c_int, [_P, _P]),
+    "gdsw_copy_coarse_basis": (C.c_int, [_P, _P]),
+    "gdsw_local_indices": (C.c_int, [_P, C.c_int32, _P, C.POINTER(C.c_int32)]),
+    "gdsw_profile_apply": (C.c_int, [_P, _P, _P, _P, _P]),
+    "gdsw_last_error": (C.c_char_p, [_P]),
+    "gdsw_destroy": (None, [_P]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_sig)
+
+
+class GdswError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+def _check(status, ctx=None):
+    if status != 0:
+        msg = _lib.gdsw_last_error(ctx)
+        raise GdswError(status, msg.decode() if msg else "")
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        if torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        return C.c_void_p(0)
+    return C.c_void_p(int(stream))
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if hasattr(t, "data_ptr"):
+        return C.c_void_p(t.data_ptr())
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data_as(C.c_void_p)
+    return C.c_void_p(int(t))
+
+
+class Solver:
+    """One Stokes problem with its GDSW preconditioner (a gdsw_ctx)."""
+
+    def __init__(self, n, m, overlap=1, levels=2, group=2, precision="fp64", tile=0, viscosity=1.0,
+                 inflow=16.0, manufactured=0, budget=0, host_only=False, stream=None):
+        self._ctx = C.c_void_p()
+        self.mesh = Mesh(n, manufactured, viscosity, inflow)
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self.dec = Decomposition(m, overlap, levels, group, prec, tile, budget)
+        if host_only:
+            st = _lib.gdsw_setup_host(C.byref(self.mesh), C.byref(self.dec), C.byref(self._ctx))
+        else:
+            st = _lib.gdsw_setup(C.byref(self.mesh), C.byref(self.dec), _stream(stream), C.byref(self._ctx))
+        _check(st)
+        self.host_only = host_only
+        s = self.sizes()
+        self.n_free = s.n_free
+        self.n_coarse = s.n_coarse
+
+    # -- queries -----------------------------------------------------------
+    def sizes(self) -> Sizes:
+        s = Sizes()
+        _check(_lib.gdsw_get_sizes(self._ctx, C.byref(s)), self._ctx)
+        return s
+
+    def dof_map(self):
+        field = np.zeros(self.n_free, dtype=np.int32)
+        abc = np.zeros((self.n_free, 3), dtype=np.int32)
+        _check(_lib.gdsw_dof_map(self._ctx, _ptr(field), _ptr(abc)), self._ctx)
+        return field, abc
+
+    def host_matrix(self):
+        s = self.sizes()
+        rp = np.zeros(s.n_free + 1, dtype=np.int64)
+        col = np.zeros(s.nnz, dtype=np.int32)
+        val = np.zeros(s.nnz, dtype=np.float64)
+        _check(_lib.gdsw_host_matrix(self._ctx, _ptr(rp), _ptr(col), _ptr(val)), self._ctx)
+        return rp, col, val
+
+    def host_rhs(self):
+        b = np.zeros(self.n_free)
+        _check(_lib.gdsw_host_rhs(self._ctx, _ptr(b)), self._ctx)
+        return b
+
+    def local_indices(self, i):
+        sz = C.c_int32()
+        _check(_lib.gdsw_local_indices(self._ctx, i, None, C.byref(sz)), self._ctx)
+        out = np.zeros(sz.value, dtype=np.int32)
+        _check(_lib.gdsw_local_indices(self._ctx, i, _ptr(out), C.byref(sz)), self._ctx)
+        return out
+
+    def coarse_matrix(self):
+        a = np.zeros((self.n_coarse, self.n_coarse))
+        _check(_lib.gdsw_copy_coarse_matrix(self._ctx, _ptr(a)), self._ctx)
+        return a
+
+    def coarse_basis(self):
+        phi = np.zeros((self.n_coarse, self.n_free))  # column-major n x Nc == row-major Nc x n
+        _check(_lib.gdsw_copy_coarse_basis(self._ctx, _ptr(phi)), self._ctx)
+        return phi.T
+
+    # -- device operations (torch tensors, float64, on the GPU) --------------
+    def rhs(self, b, stream=None):
+        _check(_lib.gdsw_rhs(self._ctx, _ptr(b), _stream(stream)), self._ctx)
+        return b
+
+    def spmv(self, x, y, stream=None):
+        _check(_lib.gdsw_spmv(self._ctx, _ptr(x), _ptr(y), _stream(stream)), self._ctx)
+        return y
+
+    def apply(self, r, z, nrhs=1, ld=None, stream=None):
+        ld = self.n_free if ld is None else ld
+        _check(_lib.gdsw_apply_precond(self._ctx, _ptr(r), _ptr(z), nrhs, ld, _stream(stream)), self._ctx)
+        return z
+
+    def profile_apply(self, r, z, stream=None):
+        ms = np.zeros(4)
+        _check(_lib.gdsw_profile_apply(self._ctx, _ptr(r), _ptr(z), _stream(stream), _ptr(ms)), self._ctx)
+        return ms
+
+    def fgmres(self, b, x, rtol=1e-8, restart=100, max_it=1000, use_graph=False, nrhs=1, ld=None, stream=None,
+               raise_on_noconv=True):
+        ld = self.n_free if ld is None else ld
+        opts = FgmresOpts(rtol, restart, max_it, int(use_graph), 0)
+        infos = (FgmresInfo * nrhs)()
+        st = _lib.gdsw_fgmres_solve(self._ctx, _ptr(b), _ptr(x), nrhs, ld, C.byref(opts), infos, _stream(stream))
+        if st != 4 or raise_on_noconv:
+            _check(st, self._ctx)
+        return [infos[k] for k in range(nrhs)]
+
+    def expand(self, x_free, x_full, stream=None):
+        _check(_lib.gdsw_expand_solution(self._ctx, _ptr(x_free), _ptr(x_full), _stream(stream)), self._ctx)
+        return x_full
+
+    def close(self):
+        if self._ctx:
+            _lib.gdsw_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -1,0 +1,340 @@
+// C ABI entry points (include/gdsw.h).  Exceptions never cross this file:
+// every entry point maps them to a gdsw_status and a last-error message.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstring>
+#include <new>
+#include <stdexcept>
+#include <thread>
+
+#include "../../include/gdsw.h"
+#include "context.h"
+
+using namespace gdsw;
+
+struct gdsw_ctx {
+  Context c;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+gdsw_status fail(gdsw_ctx* ctx, gdsw_status s, const std::string& msg) {
+  g_last_error = msg;
+  if (ctx) ctx->c.last_error = msg;
+  return s;
+}
+
+template <class F>
+gdsw_status guarded(gdsw_ctx* ctx, F&& f) {
+  try {
+    f();
+    return GDSW_OK;
+  } catch (const StatusError& e) {
+    return fail(ctx, (gdsw_status)e.status, e.msg);
+  } catch (const HipError& e) {
+    return fail(ctx, GDSW_EDEVICE, std::string(hipGetErrorString(e.err)) + " (" + e.where + ")");
+  } catch (const std::invalid_argument& e) {
+    return fail(ctx, GDSW_EINVAL, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(ctx, GDSW_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(ctx, GDSW_EDEVICE, e.what());
+  }
+}
+
+int host_threads() {
+  const unsigned h = std::thread::hardware_concurrency();
+  return (int)std::max(1u, std::min(16u, h));
+}
+
+ProblemSpec spec_of(const gdsw_mesh* mesh, const gdsw_decomposition* dec) {
+  if (!mesh || !dec) throw std::invalid_argument("mesh and decomposition must not be NULL");
+  ProblemSpec s;
+  s.n = mesh->n;
+  s.mu = mesh->viscosity;
+  s.c = mesh->inflow_amplitude;
+  s.manufactured = mesh->manufactured_force;
+  s.m = dec->subdomains;
+  s.overlap = dec->overlap;
+  s.levels = dec->levels;
+  s.group = dec->group;
+  if (dec->local_precision < 0 || dec->local_precision > 2) throw std::invalid_argument("bad local_precision");
+  if (dec->tile != 0 && dec->tile != 64 && dec->tile != 128) throw std::invalid_argument("tile must be 0, 64 or 128");
+  return s;
+}
+
+gdsw_status check_device_ctx(const gdsw_ctx* ctx) {
+  if (!ctx) return fail(nullptr, GDSW_EINVAL, "NULL context");
+  if (ctx->c.host_only)
+    return fail(const_cast<gdsw_ctx*>(ctx), GDSW_EINVAL, "context was created by gdsw_setup_host (no device data)");
+  return GDSW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gdsw_status gdsw_setup_host(const gdsw_mesh* mesh, const gdsw_decomposition* dec, gdsw_ctx** out) {
+  if (!out) return fail(nullptr, GDSW_EINVAL, "out must not be NULL");
+  *out = nullptr;
+  gdsw_ctx* ctx = nullptr;
+  gdsw_status s = guarded(nullptr, [&]() {
+    ProblemSpec sp = spec_of(mesh, dec);
+    ctx = new gdsw_ctx();
+    ctx->c.host_only = true;
+    ctx->c.local_prec = dec->local_precision;
+    const auto t0 = std::chrono::steady_clock::now();
+    build_problem(sp, ctx->c.P, host_threads());
+    ctx->c.t_symbolic = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  });
+  if (s != GDSW_OK) {
+    delete ctx;
+    return s;
+  }
+  *out = ctx;
+  return GDSW_OK;
+}
+
+gdsw_status gdsw_setup(const gdsw_mesh* mesh, const gdsw_decomposition* dec, void* stream, gdsw_ctx** out) {
+  if (!out) return fail(nullptr, GDSW_EINVAL, "out must not be NULL");
+  *out = nullptr;
+  gdsw_ctx* ctx = nullptr;
+  gdsw_status s = guarded(nullptr, [&]() {
+    ProblemSpec sp = spec_of(mesh, dec);
+    ctx = new gdsw_ctx();
+    Context& c = ctx->c;
+    c.local_prec = dec->local_precision;
+    GDSW_HIP(hipGetDevice(&c.device));
+    const auto t0 = std::chrono::steady_clock::now();
+    build_problem(sp, c.P, host_threads());
+    const auto t1 = std::chrono::steady_clock::now();
+    c.t_symbolic = std::chrono::duration<double>(t1 - t0).count();
+    uint64_t budget = dec->device_mem_budget;
+    if (budget == 0) {
+      size_t fr = 0, tot = 0;
+      GDSW_HIP(hipMemGetInfo(&fr, &tot));
+      budget = (uint64_t)(fr * 0.97);
+    }
+    const int nb = dec->tile ? dec->tile : 128;
+    device_setup(c, (hipStream_t)stream, budget, nb);
+    c.t_numeric = std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count();
+  });
+  if (s != GDSW_OK) {
+    if (ctx) {
+      ctx->c.arena.release_all();
+      if (ctx->c.h_pinned) (void)hipHostFree(ctx->c.h_pinned);
+    }
+    delete ctx;
+    return s;
+  }
+  *out = ctx;
+  return GDSW_OK;
+}
+
+gdsw_status gdsw_get_sizes(const gdsw_ctx* ctx, gdsw_sizes* out) {
+  if (!ctx || !out) return fail(nullptr, GDSW_EINVAL, "NULL argument");
+  const Context& c = ctx->c;
+  const Problem& P = c.P;
+  std::memset(out, 0, sizeof *out);
+  out->n_free = P.n_free;
+  out->n_full = P.n_full;
+  out->n_u_free = P.n_u;
+  out->n_p = P.n_p;
+  out->nnz = P.nnz();
+  out->n_sub = P.n_sub;
+  out->n_entities = P.n_ent;
+  out->n_coarse = P.n_coarse;
+  out->n_subregions = P.spec.levels == 3 ? P.lv2.n_sub : 0;
+  out->n_coarse3 = P.spec.levels == 3 ? P.lv2.n_coarse3 : 0;
+  int64_t mn = INT64_MAX, mx = 0;
+  for (auto& S : P.S) {
+    mn = std::min<int64_t>(mn, S.size());
+    mx = std::max<int64_t>(mx, S.size());
+  }
+  out->local_min = P.S.empty() ? 0 : mn;
+  out->local_max = mx;
+  out->factor_bytes = c.factor_bytes;
+  out->coarse_bytes = c.coarse_bytes;
+  out->device_bytes = c.arena.used;
+  if (!c.host_only) {
+    out->solve_bytes = c.L1.algorithmic_bytes() + c.HI.algorithmic_bytes();
+    int64_t l = 0;
+    for (const FactorSet* fs : {&c.L1, &c.HI})
+      for (size_t k = 0; k + 1 < fs->fwd_start.size(); ++k) {
+        l += fs->fwd_start[k + 1] > fs->fwd_start[k];
+        l += fs->bwd_start[k + 1] > fs->bwd_start[k];
+      }
+    out->solve_launches = l;
+  }
+  return GDSW_OK;
+}
+
+gdsw_status gdsw_dof_map(const gdsw_ctx* ctx, int32_t* field, int32_t* node_abc) {
+  if (!ctx || !field || !node_abc) return fail(nullptr, GDSW_EINVAL, "NULL argument");
+  const Problem& P = ctx->c.P;
+  for (int64_t d = 0; d < P.n_free; ++d) {
+    field[d] = P.field[d];
+    node_abc[3 * d] = P.abc[3 * d];
+    node_abc[3 * d + 1] = P.abc[3 * d + 1];
+    node_abc[3 * d + 2] = P.abc[3 * d + 2];
+  }
+  return GDSW_OK;
+}
+
+gdsw_status gdsw_host_matrix(const gdsw_ctx* ctx, int64_t* row_ptr, int32_t* col, double* val) {
+  if (!ctx || !row_ptr || !col || !val) return fail(nullptr, GDSW_EINVAL, "NULL argument");
+  const Problem& P = ctx->c.P;
+  for (int64_t r = 0; r <= P.n_free; ++r) row_ptr[r] = P.row_ptr[r];
+  std::memcpy(col, P.col.data(), P.col.size() * sizeof(int32_t));
+  std::memcpy(val, P.val.data(), P.val.size() * sizeof(double));
+  return GDSW_OK;
+}
+
+gdsw_status gdsw_host_rhs(const gdsw_ctx* ctx, double* b) {
+  if (!ctx || !b) return fail(nullptr, GDSW_EINVAL, "NULL argument");
+  std::memcpy(b, ctx->c.P.rhs.data(), ctx->c.P.rhs.size() * sizeof(double));
+  return GDSW_OK;
+}
+
+gdsw_status gdsw_rhs(gdsw_ctx* ctx, double* b_dev, void* stream) {
+  if (gdsw_status s = check_device_ctx(ctx)) return s;
+  if (!b_dev) return fail(ctx, GDSW_EINVAL, "NULL vector");
+  return guarded(ctx, [&]() {
+    GDSW_HIP(hipMemcpyAsync(b_dev, ctx->c.d_rhs, ctx->c.P.n_free * sizeof(double), hipMemcpyDeviceToDevice,
+                            (hipStream_t)stream));
+  });
+}
+
+gdsw_status gdsw_spmv(gdsw_ctx* ctx, const double* x_dev, double* y_dev, void* stream) {
+  if (gdsw_status s = check_device_ctx(ctx)) return s;
+  if (!x_dev || !y_dev) return fail(ctx, GDSW_EINVAL, "NULL vector");
+  if (x_dev == y_dev) return fail(ctx, GDSW_EINVAL, "x and y must not overlap");
+  return guarded(ctx, [&]() {
+    spmv(ctx->c, x_dev, y_dev, (hipStream_t)stream);
+    GDSW_HIP(hipGetLastError());
+  });
+}
+
+gdsw_status gdsw_apply_precond(gdsw_ctx* ctx, const double* r_dev, double* z_dev, int32_t nrhs, int64_t ld,
+                               void* stream) {
+  if (gdsw_status s = check_device_ctx(ctx)) return s;
+  if (!r_dev || !z_dev) return fail(ctx, GDSW_EINVAL, "NULL vector");
+  if (nrhs < 1 || ld < ctx->c.P.n_free) return fail(ctx, GDSW_EINVAL, "need nrhs >= 1 and ld >= n_free");
+  if (r_dev == z_dev) return fail(ctx, GDSW_EINVAL, "r and z must not overlap");
+  return guarded(ctx, [&]() {
+    for (int k = 0; k < nrhs; ++k)
+      apply_precond(ctx->c, r_dev + (int64_t)k * ld, z_dev + (int64_t)k * ld, (hipStream_t)stream);
+  });
+}
+
+gdsw_status gdsw_fgmres_solve(gdsw_ctx* ctx, const double* b_dev, double* x_dev, int32_t nrhs, int64_t ld,
+                              const gdsw_fgmres_opts* opts, gdsw_fgmres_info* info, void* stream) {
+  if (gdsw_status s = check_device_ctx(ctx)) return s;
+  if (!b_dev || !x_dev || !opts) return fail(ctx, GDSW_EINVAL, "NULL argument");
+  if (nrhs < 1 || ld < ctx->c.P.n_free) return fail(ctx, GDSW_EINVAL, "need nrhs >= 1 and ld >= n_free");
+  if (opts->restart < 1 || opts->restart > 200 || opts->max_it < 1 || !(opts->rtol > 0.0))
+    return fail(ctx, GDSW_EINVAL, "need 1 <= restart <= 200, max_it >= 1, rtol > 0");
+  bool all_conv = true;
+  gdsw_status s = guarded(ctx, [&]() {
+    for (int k = 0; k < nrhs; ++k) {
+      const auto t0 = std::chrono::steady_clock::now();
+      FgmresResult r = fgmres(ctx->c, b_dev + (int64_t)k * ld, x_dev + (int64_t)k * ld, opts->rtol, opts->restart,
+                              opts->max_it, opts->use_graph != 0, (hipStream_t)stream);
+      GDSW_HIP(hipStreamSynchronize((hipStream_t)stream));
+      const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (info) {
+        info[k].iterations = r.iterations;
+        info[k].restarts = r.restarts;
+        info[k].rel_res = r.rel;
+        info[k].true_rel_res = r.true_rel;
+        info[k].t_solve_s = t;
+      }
+      all_conv = all_conv && r.converged;
+    }
+  });
+  if (s != GDSW_OK) return s;
+  if (!all_conv) return fail(ctx, GDSW_ENOCONV, "FGMRES reached max_it before rtol");
+  return GDSW_OK;
+}
+
+gdsw_status gdsw_expand_solution(const gdsw_ctx* ctx, const double* x_free_dev, double* x_full_dev, void* stream) {
+  if (gdsw_status s = check_device_ctx(ctx)) return s;
+  if (!x_free_dev || !x_full_dev) return fail(const_cast<gdsw_ctx*>(ctx), GDSW_EINVAL, "NULL vector");
+  return guarded(const_cast<gdsw_ctx*>(ctx), [&]() { expand_solution(ctx->c, x_free_dev, x_full_dev, (hipStream_t)stream); });
+}
+
+gdsw_status gdsw_copy_coarse_matrix(const gdsw_ctx* ctx, double* a0_host) {
+  if (gdsw_status s = check_device_ctx(ctx)) return s;
+  if (!a0_host) return fail(const_cast<gdsw_ctx*>(ctx), GDSW_EINVAL, "NULL argument");
+  return guarded(const_cast<gdsw_ctx*>(ctx), [&]() {
+    const int64_t Nc = ctx->c.Nc;
+    if (Nc > 0) GDSW_HIP(hipMemcpy(a0_host, ctx->c.d_A0, Nc * Nc * sizeof(double), hipMemcpyDeviceToHost));
+  });
+}
+
+gdsw_status gdsw_copy_coarse_basis(const gdsw_ctx* ctx, double* phi) {
+  if (gdsw_status s = check_device_ctx(ctx)) return s;
+  if (!phi) return fail(const_cast<gdsw_ctx*>(ctx), GDSW_EINVAL, "NULL argument");
+  return guarded(const_cast<gdsw_ctx*>(ctx), [&]() {
+    const Problem& P = ctx->c.P;
+    const int64_t n = P.n_free, Nc = ctx->c.Nc;
+    std::memset(phi, 0, sizeof(double) * n * Nc);
+    for (int64_t d = 0; d < n; ++d)
+      if (P.gamma_col[d] >= 0) phi[P.gamma_col[d] * n + d] = 1.0;
+    int64_t off = 0;
+    for (int i = 0; i < P.n_sub; ++i) {
+      const int64_t ni = P.I[i].size(), nc = P.C[i].size();
+      std::vector<double> blk(ni * nc);
+      if (ni * nc)
+        GDSW_HIP(hipMemcpy(blk.data(), ctx->c.d_phi_cm + off, ni * nc * sizeof(double), hipMemcpyDeviceToHost));
+      for (int64_t j = 0; j < nc; ++j)
+        for (int64_t k = 0; k < ni; ++k) phi[(int64_t)P.C[i][j] * n + P.I[i][k]] = blk[j * ni + k];
+      off += ni * nc;
+    }
+  });
+}
+
+gdsw_status gdsw_local_indices(const gdsw_ctx* ctx, int32_t i, int32_t* idx_host, int32_t* size) {
+  if (!ctx) return fail(nullptr, GDSW_EINVAL, "NULL context");
+  const Problem& P = ctx->c.P;
+  if (i < 0 || i >= P.n_sub) return fail(const_cast<gdsw_ctx*>(ctx), GDSW_EINVAL, "subdomain index out of range");
+  if (size) *size = (int32_t)P.S[i].size();
+  if (idx_host) std::memcpy(idx_host, P.S[i].data(), P.S[i].size() * sizeof(int32_t));
+  return GDSW_OK;
+}
+
+gdsw_status gdsw_profile_apply(gdsw_ctx* ctx, const double* r_dev, double* z_dev, void* stream, double* ms) {
+  if (gdsw_status s = check_device_ctx(ctx)) return s;
+  if (!r_dev || !z_dev || !ms) return fail(ctx, GDSW_EINVAL, "NULL argument");
+  if (r_dev == z_dev) return fail(ctx, GDSW_EINVAL, "r and z must not overlap");
+  return guarded(ctx, [&]() {
+    hipEvent_t ev[5];
+    for (auto& e : ev) GDSW_HIP(hipEventCreate(&e));
+    hipStream_t st = (hipStream_t)stream;
+    apply_precond(ctx->c, r_dev, z_dev, st, ev);
+    GDSW_HIP(hipEventSynchronize(ev[4]));
+    for (int k = 0; k < 4; ++k) {
+      float t = 0.f;
+      GDSW_HIP(hipEventElapsedTime(&t, ev[k], ev[k + 1]));
+      ms[k] = t;
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+  });
+}
+
+const char* gdsw_last_error(const gdsw_ctx* ctx) {
+  if (ctx) return ctx->c.last_error.c_str();
+  return g_last_error.c_str();
+}
+
+void gdsw_destroy(gdsw_ctx* ctx) {
+  if (!ctx) return;
+  ctx->c.arena.release_all();
+  if (ctx->c.h_pinned) (void)hipHostFree(ctx->c.h_pinned);
+  delete ctx;
+}
+
+}  // extern "C"

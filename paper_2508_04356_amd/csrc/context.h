@@ -1,0 +1,183 @@
+// Device-side context of one GDSW problem (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "problem.h"
+
+namespace gdsw {
+
+struct HipError {
+  hipError_t err;
+  std::string where;
+};
+
+#define GDSW_HIP(call)                                                          \
+  do {                                                                          \
+    hipError_t e_ = (call);                                                     \
+    if (e_ != hipSuccess) throw ::gdsw::HipError{e_, std::string(#call) + " at " \
+                                                  + __FILE__ + ":" + std::to_string(__LINE__)}; \
+  } while (0)
+
+struct StatusError {  // a gdsw_status with a message
+  int status;
+  std::string msg;
+};
+
+// Device allocation tracker: every buffer of a context goes through it so
+// that the budget check and the reported device footprint are exact.
+struct DeviceArena {
+  uint64_t budget = 0;
+  uint64_t used = 0;
+  std::vector<void*> ptrs;
+  std::vector<uint64_t> sizes;
+  void* alloc(uint64_t bytes);
+  void free(void* p);
+  void release_all();
+  ~DeviceArena() { release_all(); }
+};
+
+template <class T>
+T* dalloc(DeviceArena& A, uint64_t count) {
+  return static_cast<T*>(A.alloc(count * sizeof(T)));
+}
+template <class T>
+T* dupload(DeviceArena& A, const std::vector<T>& v, hipStream_t st) {
+  T* p = dalloc<T>(A, v.empty() ? 1 : v.size());
+  if (!v.empty()) GDSW_HIP(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  return p;
+}
+
+enum Precision { P_FP64 = 0, P_FP32 = 1, P_BF16 = 2 };
+
+// A batch of dense square matrices factored as A = L U without pivoting and
+// solved by the blocked triangular-solve kernels.  Each matrix is stored
+// column-major in a zero-padded npad x npad block (npad = n rounded up to the
+// tile), and the inverses of its diagonal tiles (unit-lower L^-1 strictly
+// below the diagonal, U^-1 on and above it) are kept separately in `dinv`.
+struct FactorSet {
+  int prec = P_FP64;
+  int nb = 128;                       // tile
+  int count = 0;
+  std::vector<int32_t> n, npad, nblk; // host copies
+  std::vector<int64_t> off, doff, xoff;
+  int64_t total_elems = 0, total_dinv = 0, total_x = 0;
+  int max_nblk = 0;
+  void* store = nullptr;              // factors (prec)
+  void* dinv = nullptr;               // diagonal tile inverses (fp64 or fp32)
+  int32_t* d_n = nullptr;
+  int32_t* d_npad = nullptr;
+  int32_t* d_nblk = nullptr;
+  int64_t* d_off = nullptr;
+  int64_t* d_doff = nullptr;
+  int64_t* d_xoff = nullptr;
+  // per-launch work lists of (factor, row block) pairs
+  std::vector<int32_t> fwd_start, bwd_start;
+  int2* d_fwd = nullptr;
+  int2* d_bwd = nullptr;
+  uint64_t algorithmic_bytes() const;  // sum n^2 * sizeof(prec) + dinv
+};
+
+struct Context {
+  Problem P;
+  bool host_only = false;
+  int device = 0;
+  DeviceArena arena;
+  std::string last_error;
+  int local_prec = P_FP64;
+  int nb = 128;
+
+  // system matrix (free DOFs)
+  int32_t* d_rowptr = nullptr;
+  int32_t* d_col = nullptr;
+  double* d_val = nullptr;
+  double* d_rhs = nullptr;
+  int64_t* d_full_index = nullptr;
+  double* d_dirichlet_full = nullptr;
+
+  // level-1 local solves
+  FactorSet L1;      // level-1 local factors (local_prec)
+  FactorSet HI;      // FP64: coarse (two levels) or level-2 + level-3 factors
+  bool merged = false;  // true when L1 also holds the coarse factor(s)
+  int32_t* d_gidx = nullptr;      // wbuf position -> global DOF (or -1)
+  int64_t n_w1 = 0;               // length of the level-1 work segment
+  int32_t* d_inv_ptr = nullptr;   // per DOF: range into d_inv_pos
+  int64_t* d_inv_pos = nullptr;   // wbuf positions of each DOF's local copies
+  double* d_w = nullptr;          // work vector (all factor sets)
+  int64_t n_w = 0;
+
+  // coarse space (level 2 of eq. 2.2 / 2.5)
+  int Nc = 0;
+  int32_t* d_gamma_col = nullptr;  // per DOF: coarse column or -1
+  int32_t* d_I_ptr = nullptr;      // interior lists
+  int32_t* d_I_idx = nullptr;
+  int32_t* d_I_sub = nullptr;      // per interior DOF position: subdomain
+  int32_t* d_dof_ipos = nullptr;   // per DOF: position in the concatenated interior list or -1
+  int32_t* d_C_ptr = nullptr;      // adjacent coarse columns per subdomain
+  int32_t* d_C_idx = nullptr;
+  int64_t* d_phi_off = nullptr;    // per subdomain offset of Phi_I (|I_i| x |C_i|)
+  double* d_phi_cm = nullptr;      // Phi_I column-major (ld = |I_i|)
+  double* d_phi_rm = nullptr;      // Phi_I row-major (ld = |C_i|)
+  int32_t* d_cg_ptr = nullptr;     // per coarse column: its Gamma DOFs
+  int32_t* d_cg_dof = nullptr;
+  int32_t* d_cs_ptr = nullptr;     // per coarse column: (subdomain, local column) pairs
+  int32_t* d_cs_sub = nullptr;
+  int32_t* d_cs_lc = nullptr;
+  double* d_A0 = nullptr;          // dense A_0, row-major Nc x Nc
+  std::vector<int32_t> coarse_perm;  // factor position -> coarse column (velocity first)
+  int32_t* d_coarse_pinv = nullptr;  // coarse column -> wbuf position
+  int64_t coarse_xoff = 0;
+  double* d_r0 = nullptr;          // coarse vectors (three levels)
+  double* d_y0 = nullptr;
+
+  // three levels
+  int Nc3 = 0;
+  int n_sub2 = 0;
+  int32_t* d_g2idx = nullptr;      // level-2 work positions -> coarse index
+  int32_t* d_inv2_ptr = nullptr;
+  int64_t* d_inv2_pos = nullptr;
+  double* d_phi3 = nullptr;        // dense Phi^(3), column-major Nc x Nc3
+  int32_t* d_c3_pinv = nullptr;    // level-3 column -> wbuf position
+  double* d_A03 = nullptr;
+
+  // Krylov workspace
+  int restart = 0;
+  double* d_V = nullptr;
+  double* d_Z = nullptr;
+  double* d_H = nullptr;
+  double* d_g = nullptr;
+  double* d_cs = nullptr;
+  double* d_sn = nullptr;
+  double* d_hv = nullptr;          // CGS coefficients
+  double* d_part = nullptr;        // partial sums
+  double* d_scal = nullptr;        // scalars: norms, flags
+  double* d_t1 = nullptr;          // n-vectors
+  double* d_t2 = nullptr;
+  double* h_pinned = nullptr;      // pinned host scalars
+  int64_t ldv = 0;
+  int n_part_blocks = 0;
+
+  // diagnostics
+  double t_symbolic = 0, t_numeric = 0;
+  uint64_t factor_bytes = 0, coarse_bytes = 0;
+};
+
+// numeric setup and operators (setup.hip / solve.hip)
+void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb);
+void apply_precond(Context& ctx, const double* r, double* z, hipStream_t st, hipEvent_t* ev = nullptr);
+void spmv(Context& ctx, const double* x, double* y, hipStream_t st);
+struct FgmresResult {
+  int iterations = 0, restarts = 0;
+  double rel = 0, true_rel = 0;
+  bool converged = false;
+};
+FgmresResult fgmres(Context& ctx, const double* b, double* x, double rtol, int restart, int max_it,
+                    bool use_graph, hipStream_t st);
+void expand_solution(const Context& ctx, const double* xf, double* xfull, hipStream_t st);
+
+}  // namespace gdsw

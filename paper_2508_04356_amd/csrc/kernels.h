@@ -1,0 +1,77 @@
+// Launchers of the HIP kernels (gfx950).  All work is enqueued on `st`.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "context.h"
+
+namespace gdsw {
+
+// ---- dense batches: column-major matrices at base + off[f], leading dim ld[f]
+struct DenseBatch {
+  double* base = nullptr;
+  const int32_t* n = nullptr;
+  const int32_t* ld = nullptr;
+  const int64_t* off = nullptr;
+  int count = 0;
+  int max_n = 0;
+};
+
+// In-place LU without pivoting (A = L U, L unit lower) of every matrix of the
+// batch; right-looking with 64-wide blocks.  minpiv[f] receives the smallest
+// |u_kk| / max|a_kk| seen in matrix f (as an ordered bit pattern, see
+// minpiv_decode).
+void lu_nopiv(const DenseBatch& B, unsigned long long* minpiv, hipStream_t st);
+double minpiv_decode(unsigned long long bits);
+
+// Unblocked forward (unit L) and backward (U) substitution for nrhs[f]
+// right-hand sides held column-major at rhs + roff[f] (leading dim n[f]).
+void lu_solve_multi(const DenseBatch& B, double* rhs, const int64_t* roff, const int32_t* nrhs,
+                    int max_nrhs, hipStream_t st);
+
+// Diagonal-tile inverses of the factor set from the FP64 LU in `lu`
+// (laid out like the set), then conversion of the factors to the set's
+// precision when it is not FP64 (lu -> set.store).
+void factor_finalize(FactorSet& fs, const double* lu, hipStream_t st);
+
+// Blocked forward/backward solve, in place on the work vector w, for every
+// factor of the set.
+void trsv_set(const FactorSet& fs, double* w, hipStream_t st);
+
+// C_b = alpha * op(A_b) * B_b + beta * C_b, FP64, column-major.
+struct GemmDesc {
+  const double* A;
+  const double* B;
+  double* C;
+  int32_t m, n, k, lda, ldb, ldc, transA, pad;
+};
+void gemm_batched(const GemmDesc* d_desc, int count, int max_m, int max_n, double alpha, double beta,
+                  hipStream_t st);
+
+// ---- sparse / vector operations
+void spmv_csr(int64_t nrows, const int32_t* rowptr, const int32_t* col, const double* val,
+              const double* x, double* y, hipStream_t st);
+void gather(int64_t count, const int32_t* idx, const double* src, double* dst, hipStream_t st);
+// dense extraction of A[S_f, S_f] for every list f into a zeroed batch
+void extract_local(const DenseBatch& B, const int32_t* list_ptr, const int32_t* list_idx,
+                   const int32_t* rowptr, const int32_t* col, const double* val, int max_rows,
+                   hipStream_t st);
+// dense extraction from a dense row-major matrix M (ld = ldm)
+void extract_local_dense(const DenseBatch& B, const int32_t* list_ptr, const int32_t* list_idx,
+                         const double* M, int64_t ldm, int max_rows, hipStream_t st);
+
+void deterministic_scatter(int64_t n, const int32_t* inv_ptr, const int64_t* inv_pos, const double* w,
+                           double* z, hipStream_t st);
+
+// Krylov helpers
+void cols_dot(const double* V, int64_t ldv, int ncols, const double* w, int64_t n, double* part,
+              int nblocks, double* out, hipStream_t st);
+void gemv_sub(const double* V, int64_t ldv, int ncols, const double* h, double* w, int64_t n,
+              hipStream_t st);
+void gemv_add(const double* V, int64_t ldv, int ncols, const double* y, double* x, int64_t n,
+              hipStream_t st);
+int cols_dot_blocks(int64_t n);
+
+}  // namespace gdsw

@@ -1,0 +1,647 @@
+// Dense factorisation and triangular-solve kernels for the local and coarse
+// problems of eqs. (2.2)-(2.5) on gfx950.
+//
+// * lu_nopiv: blocked right-looking LU without pivoting (64-wide blocks):
+//   diagonal block in LDS, row/column panels by triangular solves in LDS,
+//   trailing update as a 64x64-tile FP64 product.  No pivoting is needed for
+//   the monolithic saddle-point matrices ordered velocity first: the velocity
+//   block is SPD and the Schur complement is negative definite.
+// * factor_finalize: inverts the diagonal tiles of L and U (so that the
+//   triangular solve becomes a sequence of tile products) and converts the
+//   factors to the storage precision.
+// * trsv_set: the forward-backward solve.  One launch per tile column; a
+//   work-group owns one (factor, row tile) pair, streams its tile of L (or U)
+//   exactly once with 16-byte loads, and the owner of the diagonal tile
+//   finishes the block with the inverted diagonal tile.  No work-group ever
+//   waits on another, and every reduction runs in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "kernels.h"
+
+namespace gdsw {
+namespace {
+
+constexpr int LB = 64;  // LU block
+
+__device__ inline void track_pivot(double piv, double& mn) {
+  const double a = fabs(piv);
+  if (!(a > 0.0) || !isfinite(piv)) {
+    mn = 0.0;
+  } else if (a < mn) {
+    mn = a;
+  }
+}
+
+__global__ __launch_bounds__(256) void lu_diag_kernel(double* __restrict__ base, const int32_t* __restrict__ N,
+                                                      const int32_t* __restrict__ LD,
+                                                      const int64_t* __restrict__ OFF, int k,
+                                                      unsigned long long* __restrict__ minpiv) {
+  const int f = blockIdx.x;
+  const int n = N[f];
+  const int k0 = k * LB;
+  if (k0 >= n) return;
+  const int64_t ld = LD[f];
+  double* A = base + OFF[f];
+  const int bs = min(LB, n - k0);
+  __shared__ double a[LB][LB + 1];
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < bs * bs; idx += blockDim.x) {
+    const int r = idx % bs, c = idx / bs;
+    a[r][c] = A[(int64_t)(k0 + c) * ld + k0 + r];
+  }
+  __syncthreads();
+  double mn = 1.0e308;
+  for (int j = 0; j < bs; ++j) {
+    const double piv = a[j][j];
+    if (tid == 0) track_pivot(piv, mn);
+    for (int i = j + 1 + tid; i < bs; i += blockDim.x) a[i][j] /= piv;
+    __syncthreads();
+    const int rem = bs - j - 1;
+    for (int idx = tid; idx < rem * rem; idx += blockDim.x) {
+      const int i = j + 1 + idx % rem, c = j + 1 + idx / rem;
+      a[i][c] -= a[i][j] * a[j][c];
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < bs * bs; idx += blockDim.x) {
+    const int r = idx % bs, c = idx / bs;
+    A[(int64_t)(k0 + c) * ld + k0 + r] = a[r][c];
+  }
+  if (tid == 0) atomicMin(&minpiv[f], (unsigned long long)__double_as_longlong(mn));
+}
+
+// Row panel (L21 = A21 U11^-1) and column panel (U12 = L11^-1 A12) tiles.
+__global__ __launch_bounds__(64) void lu_panel_kernel(double* __restrict__ base, const int32_t* __restrict__ N,
+                                                     const int32_t* __restrict__ LD,
+                                                     const int64_t* __restrict__ OFF, int k) {
+  const int f = blockIdx.y;
+  const int n = N[f];
+  const int k0 = k * LB;
+  if (k0 + LB >= n) return;
+  const int nrem = (n - k0 - LB + LB - 1) / LB;
+  const int t = blockIdx.x;
+  if (t >= 2 * nrem) return;
+  const int64_t ld = LD[f];
+  double* A = base + OFF[f];
+  __shared__ double D[LB][LB + 1];
+  __shared__ double T[LB][LB + 1];
+  const int tid = threadIdx.x;
+  for (int c = 0; c < LB; ++c) D[tid][c] = A[(int64_t)(k0 + c) * ld + k0 + tid];
+  if (t < nrem) {
+    const int r0 = k0 + LB + t * LB;
+    const int rb = min(LB, n - r0);
+    for (int c = 0; c < LB; ++c) T[tid][c] = tid < rb ? A[(int64_t)(k0 + c) * ld + r0 + tid] : 0.0;
+    __syncthreads();
+    if (tid < rb) {
+      for (int j = 0; j < LB; ++j) {
+        double s = T[tid][j];
+        for (int l = 0; l < j; ++l) s -= T[tid][l] * D[l][j];
+        T[tid][j] = s / D[j][j];
+      }
+    }
+    __syncthreads();
+    if (tid < rb)
+      for (int c = 0; c < LB; ++c) A[(int64_t)(k0 + c) * ld + r0 + tid] = T[tid][c];
+  } else {
+    const int c0 = k0 + LB + (t - nrem) * LB;
+    const int cb = min(LB, n - c0);
+    for (int c = 0; c < cb; ++c) T[tid][c] = A[(int64_t)(c0 + c) * ld + k0 + tid];
+    __syncthreads();
+    if (tid < cb) {
+      for (int j = 0; j < LB; ++j) {
+        double s = T[j][tid];
+        for (int l = 0; l < j; ++l) s -= D[j][l] * T[l][tid];
+        T[j][tid] = s;
+      }
+    }
+    __syncthreads();
+    for (int c = 0; c < cb; ++c) A[(int64_t)(c0 + c) * ld + k0 + tid] = T[tid][c];
+  }
+}
+
+// Trailing update A22 -= L21 U12, one 64x64 tile per work-group.
+__global__ __launch_bounds__(256) void lu_update_kernel(double* __restrict__ base, const int32_t* __restrict__ N,
+                                                       const int32_t* __restrict__ LD,
+                                                       const int64_t* __restrict__ OFF, int k) {
+  const int f = blockIdx.y;
+  const int n = N[f];
+  const int k0 = k * LB;
+  const int s0 = k0 + LB;
+  if (s0 >= n) return;
+  const int nt = (n - s0 + LB - 1) / LB;
+  const int t = blockIdx.x;
+  if (t >= nt * nt) return;
+  const int ti = t % nt, tj = t / nt;
+  const int r0 = s0 + ti * LB, c0 = s0 + tj * LB;
+  const int rb = min(LB, n - r0), cb = min(LB, n - c0);
+  const int64_t ld = LD[f];
+  double* A = base + OFF[f];
+  __shared__ double Ls[LB][LB + 1];  // [row][l]
+  __shared__ double Us[LB][LB + 1];  // [l][col]
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < LB * LB; idx += 256) {
+    const int r = idx % LB, l = idx / LB;
+    Ls[r][l] = r < rb ? A[(int64_t)(k0 + l) * ld + r0 + r] : 0.0;
+    Us[r][l] = l < cb ? A[(int64_t)(c0 + l) * ld + k0 + r] : 0.0;  // Us[l=r][col=l]
+  }
+  __syncthreads();
+  const int tx = tid & 15, ty = tid >> 4;
+  double acc[4][4] = {};
+  for (int l = 0; l < LB; ++l) {
+    double av[4], bv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) av[a] = Ls[tx + 16 * a][l];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) bv[b] = Us[l][ty + 16 * b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int c = ty + 16 * b;
+    if (c >= cb) continue;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int r = tx + 16 * a;
+      if (r < rb) A[(int64_t)(c0 + c) * ld + r0 + r] -= acc[a][b];
+    }
+  }
+}
+
+// Forward (unit L) and backward (U) substitution, column oriented, with
+// the right-hand sides resident in LDS.
+__global__ __launch_bounds__(256) void lu_solve_multi_kernel(const double* __restrict__ base,
+                                                            const int32_t* __restrict__ N,
+                                                            const int32_t* __restrict__ LD,
+                                                            const int64_t* __restrict__ OFF,
+                                                            double* __restrict__ rhs,
+                                                            const int64_t* __restrict__ roff,
+                                                            const int32_t* __restrict__ nrhs, int rg) {
+  const int f = blockIdx.y;
+  const int n = N[f];
+  const int nr = nrhs[f];
+  const int c0 = blockIdx.x * rg;
+  if (c0 >= nr || n == 0) return;
+  const int nc = min(rg, nr - c0);
+  const int64_t ld = LD[f];
+  const double* A = base + OFF[f];
+  double* R = rhs + roff[f] + (int64_t)c0 * n;
+  extern __shared__ double b[];
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < nc * n; idx += blockDim.x) b[idx] = R[idx];
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    for (int r = j + 1 + tid; r < n; r += blockDim.x) {
+      const double l = A[(int64_t)j * ld + r];
+      for (int c = 0; c < nc; ++c) b[c * n + r] -= l * b[c * n + j];
+    }
+    __syncthreads();
+  }
+  for (int j = n - 1; j >= 0; --j) {
+    if (tid < nc) b[tid * n + j] /= A[(int64_t)j * ld + j];
+    __syncthreads();
+    for (int r = tid; r < j; r += blockDim.x) {
+      const double u = A[(int64_t)j * ld + r];
+      for (int c = 0; c < nc; ++c) b[c * n + r] -= u * b[c * n + j];
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < nc * n; idx += blockDim.x) R[idx] = b[idx];
+}
+
+// Inverses of the diagonal tiles: strictly lower part holds (unit L)^-1,
+// upper part U^-1.  Rows/columns beyond n are treated as identity.
+template <typename DT>
+__global__ __launch_bounds__(256) void dinv_kernel(const double* __restrict__ lu, const int32_t* __restrict__ N,
+                                                  const int32_t* __restrict__ NP,
+                                                  const int64_t* __restrict__ OFF,
+                                                  const int32_t* __restrict__ NBLK, DT* __restrict__ dinv,
+                                                  const int64_t* __restrict__ DOFF, int nb) {
+  const int f = blockIdx.y;
+  const int s = blockIdx.x;
+  if (s >= NBLK[f]) return;
+  const int n = N[f];
+  const int64_t np = NP[f];
+  const double* A = lu + OFF[f];
+  const int o = s * nb;
+  extern __shared__ double t[];
+  double* colbuf = t + nb * (nb + 1);
+  const int P = nb + 1;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < nb * nb; idx += blockDim.x) {
+    const int r = idx % nb, c = idx / nb;
+    double v;
+    if (o + r < n && o + c < n)
+      v = A[(int64_t)(o + c) * np + o + r];
+    else
+      v = (r == c) ? 1.0 : 0.0;
+    t[c * P + r] = v;
+  }
+  __syncthreads();
+  for (int j = nb - 2; j >= 0; --j) {
+    for (int r = tid; r < nb; r += blockDim.x) colbuf[r] = t[j * P + r];
+    __syncthreads();
+    for (int i = j + 1 + tid; i < nb; i += blockDim.x) {
+      double acc = colbuf[i];
+      for (int kk = j + 1; kk < i; ++kk) acc += t[kk * P + i] * colbuf[kk];
+      t[j * P + i] = -acc;
+    }
+    __syncthreads();
+  }
+  for (int j = 0; j < nb; ++j) {
+    for (int r = tid; r <= j; r += blockDim.x) colbuf[r] = t[j * P + r];
+    __syncthreads();
+    const double dj = 1.0 / colbuf[j];
+    for (int i = tid; i <= j; i += blockDim.x) {
+      if (i == j) {
+        t[j * P + j] = dj;
+      } else {
+        double acc = 0.0;
+        for (int kk = i; kk < j; ++kk) acc += t[kk * P + i] * colbuf[kk];
+        t[j * P + i] = -acc * dj;
+      }
+    }
+    __syncthreads();
+  }
+  DT* out = dinv + DOFF[f] + (int64_t)s * nb * nb;
+  for (int idx = tid; idx < nb * nb; idx += blockDim.x) {
+    const int r = idx % nb, c = idx / nb;
+    out[idx] = (DT)t[c * P + r];
+  }
+}
+
+__device__ inline uint16_t f2bf(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__global__ void convert_kernel_f32(const double* __restrict__ src, float* __restrict__ dst, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
+}
+__global__ void convert_kernel_bf16(const double* __restrict__ src, uint16_t* __restrict__ dst, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = f2bf((float)src[i]);
+}
+
+// ---- blocked triangular solve ---------------------------------------------
+
+template <typename T>
+struct VecW;
+template <>
+struct VecW<double> {
+  static constexpr int W = 2;
+  using acc = double;
+};
+template <>
+struct VecW<float> {
+  static constexpr int W = 4;
+  using acc = float;
+};
+template <>
+struct VecW<uint16_t> {
+  static constexpr int W = 8;
+  using acc = float;
+};
+
+__device__ inline void load16(const double* p, double (&o)[2]) {
+  const double2 v = *reinterpret_cast<const double2*>(p);
+  o[0] = v.x;
+  o[1] = v.y;
+}
+__device__ inline void load16(const float* p, float (&o)[4]) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  o[0] = v.x;
+  o[1] = v.y;
+  o[2] = v.z;
+  o[3] = v.w;
+}
+__device__ inline void load16(const uint16_t* p, float (&o)[8]) {
+  const uint4 v = *reinterpret_cast<const uint4*>(p);
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    o[2 * i] = __uint_as_float(w[i] << 16);
+    o[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+  }
+}
+
+// part[(wave * GPL + g) * NB + row] = sum over this lane's columns of A[row, c] v[c]
+// MODE 0: full tile, 1: strictly lower (c < row), 2: upper (c >= row).
+template <typename T, int NB, int MODE>
+__device__ inline void tile_gemv(const T* __restrict__ A, int64_t ld, const double* __restrict__ v, int row_lim,
+                                 int col_lim, typename VecW<T>::acc* part) {
+  using AT = typename VecW<T>::acc;
+  constexpr int W = VecW<T>::W;
+  constexpr int LPC = NB / W;
+  constexpr int GPL = 64 / LPC;
+  constexpr int CPW = NB / 4;
+  constexpr int IT = CPW / GPL;
+  static_assert(GPL >= 1 && IT >= 1, "tile shape");
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int g = lane / LPC, rr = (lane % LPC) * W;
+  AT acc[W];
+#pragma unroll
+  for (int e = 0; e < W; ++e) acc[e] = 0;
+  if (rr < row_lim) {
+    AT a[IT][W];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int c = wave * CPW + it * GPL + g;
+      if (c < col_lim) {
+        load16(A + (int64_t)c * ld + rr, a[it]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < W; ++e) a[it][e] = 0;
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int c = wave * CPW + it * GPL + g;
+      const AT vc = (AT)v[c];
+#pragma unroll
+      for (int e = 0; e < W; ++e) {
+        const bool use = MODE == 0 || (MODE == 1 && c < rr + e) || (MODE == 2 && c >= rr + e);
+        if (use) acc[e] = fma(a[it][e], vc, acc[e]);
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < W; ++e) part[(wave * GPL + g) * NB + rr + e] = acc[e];
+}
+
+template <typename T, int NB>
+__device__ inline typename VecW<T>::acc part_sum(const typename VecW<T>::acc* part, int row) {
+  constexpr int GPL = 64 / (NB / VecW<T>::W);
+  typename VecW<T>::acc s = 0;
+#pragma unroll
+  for (int q = 0; q < 4 * GPL; ++q) s += part[q * NB + row];
+  return s;
+}
+
+template <typename T>
+struct DinvT {
+  using type = float;
+};
+template <>
+struct DinvT<double> {
+  using type = double;
+};
+
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void trsv_fwd_kernel(const T* __restrict__ store,
+                                                      const typename DinvT<T>::type* __restrict__ dinv,
+                                                      const int32_t* __restrict__ N, const int32_t* __restrict__ NP,
+                                                      const int64_t* __restrict__ OFF,
+                                                      const int64_t* __restrict__ DOFF,
+                                                      const int64_t* __restrict__ XOFF,
+                                                      const int2* __restrict__ items, int s,
+                                                      double* __restrict__ w) {
+  using AT = typename VecW<T>::acc;
+  using DT = typename DinvT<T>::type;
+  constexpr int GPLm = 64 / (NB / VecW<T>::W);
+  constexpr int GPLd = 64 / (NB / VecW<DT>::W);
+  constexpr int PSZ = 4 * (GPLm > GPLd ? GPLm : GPLd) * NB;
+  __shared__ double vbuf[NB];
+  __shared__ double cbuf[NB];
+  __shared__ double part_d[PSZ];  // large enough for either accumulator type
+  const int2 item = items[blockIdx.x];
+  const int f = item.x, J = item.y;
+  const int n = N[f];
+  const int64_t np = NP[f];
+  const T* A = store + OFF[f];
+  double* x = w + XOFF[f];
+  const int tid = threadIdx.x;
+  const int r0 = J * NB;
+  const int rlim = min(NB, n - r0);
+  if (s > 0) {
+    const int c0 = (s - 1) * NB;
+    if (tid < NB) vbuf[tid] = x[c0 + tid];
+    __syncthreads();
+    AT* part = reinterpret_cast<AT*>(part_d);
+    tile_gemv<T, NB, 0>(A + (int64_t)c0 * np + r0, np, vbuf, rlim, min(NB, n - c0), part);
+    __syncthreads();
+    if (tid < NB) cbuf[tid] = x[r0 + tid] - (double)part_sum<T, NB>(part, tid);
+  } else {
+    if (tid < NB) cbuf[tid] = x[r0 + tid];
+  }
+  __syncthreads();
+  if (J == s) {
+    using ADT = typename VecW<DT>::acc;
+    ADT* part = reinterpret_cast<ADT*>(part_d);
+    tile_gemv<DT, NB, 1>(dinv + DOFF[f] + (int64_t)s * NB * NB, NB, cbuf, NB, NB, part);
+    __syncthreads();
+    if (tid < NB) x[r0 + tid] = cbuf[tid] + (double)part_sum<DT, NB>(part, tid);
+  } else {
+    if (tid < NB) x[r0 + tid] = cbuf[tid];
+  }
+}
+
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void trsv_bwd_kernel(const T* __restrict__ store,
+                                                      const typename DinvT<T>::type* __restrict__ dinv,
+                                                      const int32_t* __restrict__ N, const int32_t* __restrict__ NP,
+                                                      const int32_t* __restrict__ NBLK,
+                                                      const int64_t* __restrict__ OFF,
+                                                      const int64_t* __restrict__ DOFF,
+                                                      const int64_t* __restrict__ XOFF,
+                                                      const int2* __restrict__ items, int t,
+                                                      double* __restrict__ w) {
+  using AT = typename VecW<T>::acc;
+  using DT = typename DinvT<T>::type;
+  constexpr int GPLm = 64 / (NB / VecW<T>::W);
+  constexpr int GPLd = 64 / (NB / VecW<DT>::W);
+  constexpr int PSZ = 4 * (GPLm > GPLd ? GPLm : GPLd) * NB;
+  __shared__ double vbuf[NB];
+  __shared__ double cbuf[NB];
+  __shared__ double part_d[PSZ];
+  const int2 item = items[blockIdx.x];
+  const int f = item.x, J = item.y;
+  const int n = N[f];
+  const int nblk = NBLK[f];
+  const int s = nblk - 1 - t;
+  const int64_t np = NP[f];
+  const T* A = store + OFF[f];
+  double* x = w + XOFF[f];
+  const int tid = threadIdx.x;
+  const int r0 = J * NB;
+  const int rlim = min(NB, n - r0);
+  if (s + 1 < nblk) {
+    const int c0 = (s + 1) * NB;
+    if (tid < NB) vbuf[tid] = x[c0 + tid];
+    __syncthreads();
+    AT* part = reinterpret_cast<AT*>(part_d);
+    tile_gemv<T, NB, 0>(A + (int64_t)c0 * np + r0, np, vbuf, rlim, min(NB, n - c0), part);
+    __syncthreads();
+    if (tid < NB) cbuf[tid] = x[r0 + tid] - (double)part_sum<T, NB>(part, tid);
+  } else {
+    if (tid < NB) cbuf[tid] = x[r0 + tid];
+  }
+  __syncthreads();
+  if (J == s) {
+    using ADT = typename VecW<DT>::acc;
+    ADT* part = reinterpret_cast<ADT*>(part_d);
+    tile_gemv<DT, NB, 2>(dinv + DOFF[f] + (int64_t)s * NB * NB, NB, cbuf, NB, NB, part);
+    __syncthreads();
+    if (tid < NB) x[r0 + tid] = (double)part_sum<DT, NB>(part, tid);
+  } else {
+    if (tid < NB) x[r0 + tid] = cbuf[tid];
+  }
+}
+
+template <typename T, int NB>
+void trsv_launch(const FactorSet& fs, double* w, hipStream_t st) {
+  using DT = typename DinvT<T>::type;
+  const T* store = static_cast<const T*>(fs.store);
+  const DT* dinv = static_cast<const DT*>(fs.dinv);
+  for (int s = 0; s < fs.max_nblk; ++s) {
+    const int cnt = fs.fwd_start[s + 1] - fs.fwd_start[s];
+    if (cnt == 0) continue;
+    trsv_fwd_kernel<T, NB><<<cnt, 256, 0, st>>>(store, dinv, fs.d_n, fs.d_npad, fs.d_off, fs.d_doff, fs.d_xoff,
+                                                fs.d_fwd + fs.fwd_start[s], s, w);
+  }
+  for (int t = 0; t < fs.max_nblk; ++t) {
+    const int cnt = fs.bwd_start[t + 1] - fs.bwd_start[t];
+    if (cnt == 0) continue;
+    trsv_bwd_kernel<T, NB><<<cnt, 256, 0, st>>>(store, dinv, fs.d_n, fs.d_npad, fs.d_nblk, fs.d_off, fs.d_doff,
+                                                fs.d_xoff, fs.d_bwd + fs.bwd_start[t], t, w);
+  }
+}
+
+// ---- batched FP64 GEMM (setup only) ----------------------------------------
+__global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ D, double alpha, double beta) {
+  const GemmDesc d = D[blockIdx.z];
+  const int r0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+  if (r0 >= d.m || c0 >= d.n) return;
+  __shared__ double As[16][65];
+  __shared__ double Bs[16][65];
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  double acc[4][4] = {};
+  for (int k0 = 0; k0 < d.k; k0 += 16) {
+    for (int idx = tid; idx < 16 * 64; idx += 256) {
+      const int i = idx % 64, kk = idx / 64;
+      const int r = r0 + i, kx = k0 + kk;
+      double av = 0.0;
+      if (r < d.m && kx < d.k) av = d.transA ? d.A[(int64_t)r * d.lda + kx] : d.A[(int64_t)kx * d.lda + r];
+      As[kk][i] = av;
+      const int c = c0 + i;
+      Bs[kk][i] = (c < d.n && kx < d.k) ? d.B[(int64_t)c * d.ldb + kx] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = As[kk][tx + 16 * a];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = Bs[kk][ty + 16 * b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int c = c0 + ty + 16 * b;
+    if (c >= d.n) continue;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int r = r0 + tx + 16 * a;
+      if (r >= d.m) continue;
+      double* cp = d.C + (int64_t)c * d.ldc + r;
+      *cp = alpha * acc[a][b] + (beta == 0.0 ? 0.0 : beta * *cp);
+    }
+  }
+}
+
+}  // namespace
+
+double minpiv_decode(unsigned long long bits) {
+  double d;
+  std::memcpy(&d, &bits, sizeof d);
+  return d;
+}
+
+void lu_nopiv(const DenseBatch& B, unsigned long long* minpiv, hipStream_t st) {
+  if (B.count == 0 || B.max_n == 0) return;
+  const int nblk = (B.max_n + LB - 1) / LB;
+  for (int k = 0; k < nblk; ++k) {
+    lu_diag_kernel<<<B.count, 256, 0, st>>>(B.base, B.n, B.ld, B.off, k, minpiv);
+    const int rem = nblk - k - 1;
+    if (rem <= 0) continue;
+    lu_panel_kernel<<<dim3(2 * rem, B.count), 64, 0, st>>>(B.base, B.n, B.ld, B.off, k);
+    lu_update_kernel<<<dim3(rem * rem, B.count), 256, 0, st>>>(B.base, B.n, B.ld, B.off, k);
+  }
+  GDSW_HIP(hipGetLastError());
+}
+
+void lu_solve_multi(const DenseBatch& B, double* rhs, const int64_t* roff, const int32_t* nrhs, int max_nrhs,
+                    hipStream_t st) {
+  if (B.count == 0 || max_nrhs == 0 || B.max_n == 0) return;
+  int rg = (int)std::max<int64_t>(1, (48 * 1024) / (8 * (int64_t)B.max_n));
+  rg = std::min(rg, 8);
+  const size_t shm = (size_t)rg * B.max_n * sizeof(double);
+  if (shm > 160 * 1024) throw StatusError{6, "local interior block too large for the LDS solve"};
+  GDSW_HIP(hipFuncSetAttribute((const void*)lu_solve_multi_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)shm));
+  const int groups = (max_nrhs + rg - 1) / rg;
+  lu_solve_multi_kernel<<<dim3(groups, B.count), 256, shm, st>>>(B.base, B.n, B.ld, B.off, rhs, roff, nrhs, rg);
+  GDSW_HIP(hipGetLastError());
+}
+
+void factor_finalize(FactorSet& fs, const double* lu, hipStream_t st) {
+  if (fs.count == 0) return;
+  const size_t shm = ((size_t)fs.nb * (fs.nb + 1) + fs.nb) * sizeof(double);
+  if (fs.prec == P_FP64) {
+    GDSW_HIP(hipFuncSetAttribute((const void*)dinv_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)shm));
+    dinv_kernel<double><<<dim3(fs.max_nblk, fs.count), 256, shm, st>>>(
+        lu, fs.d_n, fs.d_npad, fs.d_off, fs.d_nblk, static_cast<double*>(fs.dinv), fs.d_doff, fs.nb);
+  } else {
+    GDSW_HIP(hipFuncSetAttribute((const void*)dinv_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)shm));
+    dinv_kernel<float><<<dim3(fs.max_nblk, fs.count), 256, shm, st>>>(
+        lu, fs.d_n, fs.d_npad, fs.d_off, fs.d_nblk, static_cast<float*>(fs.dinv), fs.d_doff, fs.nb);
+    const int blocks = 4096;
+    if (fs.prec == P_FP32)
+      convert_kernel_f32<<<blocks, 256, 0, st>>>(lu, static_cast<float*>(fs.store), fs.total_elems);
+    else
+      convert_kernel_bf16<<<blocks, 256, 0, st>>>(lu, static_cast<uint16_t*>(fs.store), fs.total_elems);
+  }
+  GDSW_HIP(hipGetLastError());
+}
+
+void trsv_set(const FactorSet& fs, double* w, hipStream_t st) {
+  if (fs.count == 0) return;
+  if (fs.nb == 128) {
+    if (fs.prec == P_FP64) trsv_launch<double, 128>(fs, w, st);
+    else if (fs.prec == P_FP32) trsv_launch<float, 128>(fs, w, st);
+    else trsv_launch<uint16_t, 128>(fs, w, st);
+  } else {
+    if (fs.prec == P_FP64) trsv_launch<double, 64>(fs, w, st);
+    else if (fs.prec == P_FP32) trsv_launch<float, 64>(fs, w, st);
+    else trsv_launch<uint16_t, 64>(fs, w, st);
+  }
+  GDSW_HIP(hipGetLastError());
+}
+
+void gemm_batched(const GemmDesc* d_desc, int count, int max_m, int max_n, double alpha, double beta,
+                  hipStream_t st) {
+  if (count == 0 || max_m == 0 || max_n == 0) return;
+  dim3 grid((max_m + 63) / 64, (max_n + 63) / 64, count);
+  gemm_kernel<<<grid, 256, 0, st>>>(d_desc, alpha, beta);
+  GDSW_HIP(hipGetLastError());
+}
+
+}  // namespace gdsw

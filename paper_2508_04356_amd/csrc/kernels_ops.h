@@ -1,0 +1,57 @@
+// Coarse-space kernels: views of the device index structures and launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace gdsw {
+
+// Device index structures of the coarse basis Phi (eq. 2.4), passed by value.
+struct CoarseView {
+  const int32_t* gamma_col;  // per DOF: coarse column of its interface entity/field, or -1
+  const int32_t* dof_ipos;   // per DOF: position in the concatenated interior list, or -1
+  const int32_t* I_sub;      // per interior position: subdomain
+  const int32_t* I_ptr;      // interior list offsets per subdomain
+  const int32_t* I_idx;      // interior DOFs (sorted per subdomain)
+  const int32_t* C_ptr;      // adjacent coarse columns per subdomain
+  const int32_t* C_idx;
+  const int64_t* phi_off;    // offset of Phi_I^(i) (|I_i| x |C_i|)
+  const double* phi_cm;      // column-major Phi_I
+  const double* phi_rm;      // row-major Phi_I
+  const int32_t* cg_ptr;     // per coarse column: its Gamma DOFs
+  const int32_t* cg_dof;
+  const int32_t* cs_ptr;     // per coarse column: (subdomain, local column) pairs, ascending subdomain
+  const int32_t* cs_sub;
+  const int32_t* cs_lc;
+};
+
+// Closed subdomain boxes D_i and the nonzeros of A each box owns (a nonzero
+// belongs to the lowest-numbered box holding both of its nodes), used for
+// A_0 = sum_i Phi_box_i^T A_own_i Phi_box_i.
+struct BoxView {
+  const int32_t* D_ptr;
+  const int32_t* D_idx;
+  const int32_t* D_sub;
+  const int64_t* box_off;    // offset of the |D_i| x |C_i| blocks
+  const int64_t* own_ptr;    // per concatenated D position: owned entries
+  const int32_t* own_col;    // local column within D_i
+  const int64_t* own_vidx;   // index into the CSR values
+};
+
+void scatter_prolong(int64_t n, const int32_t* inv_ptr, const int64_t* inv_pos, const double* w,
+                     const CoarseView& cv, const double* y0, const int32_t* y0_pos, double* z, hipStream_t st);
+void restrict_coarse(int nc, const CoarseView& cv, const double* r, double* out, const int32_t* out_pos,
+                     hipStream_t st);
+void phi_rhs(int64_t total_I, const CoarseView& cv, const int32_t* rowptr, const int32_t* col, const double* val,
+             double* B, hipStream_t st);
+void phi_transpose(int64_t total_I, const CoarseView& cv, const double* cm, double* rm, hipStream_t st);
+void phibox(int64_t total_D, const CoarseView& cv, const BoxView& bv, double* out, hipStream_t st);
+void own_spmm(int nbox, int max_nd, const CoarseView& cv, const BoxView& bv, const double* val,
+              const double* phibox_, double* W, hipStream_t st);
+void a0_assemble(int Nc, const CoarseView& cv, const double* P, const int64_t* p_off, double* A0, hipStream_t st);
+void permute_dense(int n, const int32_t* perm, const double* M, int64_t ldm, double* F, int64_t ld, hipStream_t st);
+void negate(int64_t n, double* x, hipStream_t st);
+void expand(int64_t nfree, const int64_t* full_index, const double* xf, double* xfull, hipStream_t st);
+
+}  // namespace gdsw

@@ -1,0 +1,433 @@
+// Sparse, gather/scatter, coarse-space and Krylov kernels (gfx950).
+//
+// Every reduction here runs in a fixed order (per-thread sequential sums in
+// a fixed index order, then fixed-shape LDS or shuffle trees), so results are
+// bitwise reproducible run to run.  No floating-point atomics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "kernels.h"
+#include "kernels_ops.h"
+
+namespace gdsw {
+namespace {
+
+__device__ inline int lower_bound_i32(const int32_t* a, int n, int32_t key) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (a[mid] < key) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <int BS>
+__device__ inline double block_sum(double v, double* sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = BS / 2; s > 0; s >>= 1) {
+    if (tid < s) sh[tid] += sh[tid + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// y = A x, 16 lanes per row; lane-strided partial sums then a xor tree.
+__global__ __launch_bounds__(256) void spmv_kernel(int64_t nrows, const int32_t* __restrict__ rowptr,
+                                                  const int32_t* __restrict__ col, const double* __restrict__ val,
+                                                  const double* __restrict__ x, double* __restrict__ y) {
+  const int64_t row = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+  const int l = threadIdx.x & 15;
+  double s = 0.0;
+  if (row < nrows) {
+    const int b = rowptr[row], e = rowptr[row + 1];
+    for (int k = b + l; k < e; k += 16) s = fma(val[k], x[col[k]], s);
+  }
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
+  if (row < nrows && l == 0) y[row] = s;
+}
+
+__global__ void gather_kernel(int64_t count, const int32_t* __restrict__ idx, const double* __restrict__ src,
+                              double* __restrict__ dst) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < count; p += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t g = idx[p];
+    dst[p] = g >= 0 ? src[g] : 0.0;
+  }
+}
+
+// dense A[S_f, S_f] (column-major, ld[f]) from CSR; one thread per local row
+__global__ void extract_kernel(double* __restrict__ base, const int32_t* __restrict__ N, const int32_t* __restrict__ LD,
+                               const int64_t* __restrict__ OFF, const int32_t* __restrict__ lptr,
+                               const int32_t* __restrict__ lidx, const int32_t* __restrict__ rowptr,
+                               const int32_t* __restrict__ col, const double* __restrict__ val) {
+  const int f = blockIdx.y;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = N[f];
+  if (k >= n) return;
+  const int32_t* S = lidx + lptr[f];
+  const int64_t ld = LD[f];
+  double* A = base + OFF[f];
+  const int32_t g = S[k];
+  for (int e = rowptr[g]; e < rowptr[g + 1]; ++e) {
+    const int32_t c = col[e];
+    const int lc = lower_bound_i32(S, n, c);
+    if (lc < n && S[lc] == c) A[(int64_t)lc * ld + k] = val[e];
+  }
+}
+
+__global__ void extract_dense_kernel(double* __restrict__ base, const int32_t* __restrict__ N,
+                                     const int32_t* __restrict__ LD, const int64_t* __restrict__ OFF,
+                                     const int32_t* __restrict__ lptr, const int32_t* __restrict__ lidx,
+                                     const double* __restrict__ M, int64_t ldm) {
+  const int f = blockIdx.z;
+  const int n = N[f];
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (r >= n || c >= n) return;
+  const int32_t* S = lidx + lptr[f];
+  base[OFF[f] + (int64_t)c * LD[f] + r] = M[(int64_t)S[r] * ldm + S[c]];
+}
+
+__global__ void scatter_kernel(int64_t n, const int32_t* __restrict__ inv_ptr, const int64_t* __restrict__ inv_pos,
+                               const double* __restrict__ w, double* __restrict__ z) {
+  for (int64_t d = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; d < n; d += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int e = inv_ptr[d]; e < inv_ptr[d + 1]; ++e) s += w[inv_pos[e]];
+    z[d] = s;
+  }
+}
+
+// z[d] = sum of local copies (ascending subdomain) + (Phi y0)[d]
+__global__ void scatter_prolong_kernel(int64_t n, const int32_t* __restrict__ inv_ptr,
+                                       const int64_t* __restrict__ inv_pos, const double* __restrict__ w,
+                                       CoarseView cv, const double* __restrict__ y0,
+                                       const int32_t* __restrict__ y0_pos, double* __restrict__ z) {
+  for (int64_t d = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; d < n; d += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int e = inv_ptr[d]; e < inv_ptr[d + 1]; ++e) s += w[inv_pos[e]];
+    double c = 0.0;
+    const int32_t gc = cv.gamma_col[d];
+    if (gc >= 0) {
+      c = y0_pos ? w[y0_pos[gc]] : y0[gc];
+    } else {
+      const int32_t p = cv.dof_ipos[d];
+      if (p >= 0) {
+        const int i = cv.I_sub[p];
+        const int k = p - cv.I_ptr[i];
+        const int cb = cv.C_ptr[i], nc = cv.C_ptr[i + 1] - cb;
+        const double* row = cv.phi_rm + cv.phi_off[i] + (int64_t)k * nc;
+        for (int j = 0; j < nc; ++j) {
+          const int32_t cc = cv.C_idx[cb + j];
+          c = fma(row[j], y0_pos ? w[y0_pos[cc]] : y0[cc], c);
+        }
+      }
+    }
+    z[d] = s + c;
+  }
+}
+
+// r0[c] = (Phi^T r)[c]: Gamma part (indicator sum) + interior part
+__global__ __launch_bounds__(256) void restrict_kernel(int nc_total, CoarseView cv, const double* __restrict__ r,
+                                                      double* __restrict__ out, const int32_t* __restrict__ out_pos) {
+  __shared__ double sh[256];
+  const int c = blockIdx.x;
+  if (c >= nc_total) return;
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  for (int e = cv.cg_ptr[c] + tid; e < cv.cg_ptr[c + 1]; e += 256) s += r[cv.cg_dof[e]];
+  for (int e = cv.cs_ptr[c]; e < cv.cs_ptr[c + 1]; ++e) {
+    const int i = cv.cs_sub[e], lc = cv.cs_lc[e];
+    const int ib = cv.I_ptr[i], ni = cv.I_ptr[i + 1] - ib;
+    const double* ph = cv.phi_cm + cv.phi_off[i] + (int64_t)lc * ni;
+    for (int k = tid; k < ni; k += 256) s = fma(ph[k], r[cv.I_idx[ib + k]], s);
+  }
+  const double t = block_sum<256>(s, sh);
+  if (tid == 0) out[out_pos ? out_pos[c] : c] = t;
+}
+
+// -(A[I_i, Gamma] Phi_Gamma) for the extension right-hand sides, column-major
+__global__ void phi_rhs_kernel(int64_t total_I, CoarseView cv, const int32_t* __restrict__ rowptr,
+                               const int32_t* __restrict__ col, const double* __restrict__ val,
+                               double* __restrict__ B) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= total_I) return;
+  const int i = cv.I_sub[p];
+  const int ib = cv.I_ptr[i], ni = cv.I_ptr[i + 1] - ib;
+  const int k = (int)(p - ib);
+  const int cb = cv.C_ptr[i], nc = cv.C_ptr[i + 1] - cb;
+  double* Bi = B + cv.phi_off[i];
+  const int32_t g = cv.I_idx[p];
+  for (int e = rowptr[g]; e < rowptr[g + 1]; ++e) {
+    const int32_t gc = cv.gamma_col[col[e]];
+    if (gc < 0) continue;
+    const int lc = lower_bound_i32(cv.C_idx + cb, nc, gc);
+    if (lc < nc && cv.C_idx[cb + lc] == gc) Bi[(int64_t)lc * ni + k] -= val[e];
+  }
+}
+
+__global__ void phi_transpose_kernel(int64_t total_I, CoarseView cv, const double* __restrict__ cm,
+                                     double* __restrict__ rm) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= total_I) return;
+  const int i = cv.I_sub[p];
+  const int ib = cv.I_ptr[i], ni = cv.I_ptr[i + 1] - ib;
+  const int k = (int)(p - ib);
+  const int nc = cv.C_ptr[i + 1] - cv.C_ptr[i];
+  const int64_t o = cv.phi_off[i];
+  for (int j = 0; j < nc; ++j) rm[o + (int64_t)k * nc + j] = cm[o + (int64_t)j * ni + k];
+}
+
+// Phi restricted to the closed box D_i (column-major, ld = |D_i|)
+__global__ void phibox_kernel(int64_t total_D, CoarseView cv, BoxView bv, double* __restrict__ phibox) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= total_D) return;
+  const int i = bv.D_sub[p];
+  const int db = bv.D_ptr[i], nd = bv.D_ptr[i + 1] - db;
+  const int q = (int)(p - db);
+  const int32_t d = bv.D_idx[p];
+  const int cb = cv.C_ptr[i], nc = cv.C_ptr[i + 1] - cb;
+  double* out = phibox + bv.box_off[i];
+  const int32_t gc = cv.gamma_col[d];
+  if (gc >= 0) {
+    const int lc = lower_bound_i32(cv.C_idx + cb, nc, gc);
+    if (lc < nc && cv.C_idx[cb + lc] == gc) out[(int64_t)lc * nd + q] = 1.0;
+  } else {
+    const int32_t ip = cv.dof_ipos[d];
+    const int ib = cv.I_ptr[i], ni = cv.I_ptr[i + 1] - ib;
+    const int k = ip - ib;
+    if (ip < 0 || k >= ni) return;
+    const double* ph = cv.phi_cm + cv.phi_off[i];
+    for (int j = 0; j < nc; ++j) out[(int64_t)j * nd + q] = ph[(int64_t)j * ni + k];
+  }
+}
+
+// W_i = A_own_i Phi_box_i: thread per (local row, column)
+__global__ __launch_bounds__(256) void own_spmm_kernel(CoarseView cv, BoxView bv, const double* __restrict__ val,
+                                                      const double* __restrict__ phibox, double* __restrict__ W) {
+  const int i = blockIdx.y;
+  const int db = bv.D_ptr[i], nd = bv.D_ptr[i + 1] - db;
+  const int nc = cv.C_ptr[i + 1] - cv.C_ptr[i];
+  const int q = blockIdx.x * 2 + (threadIdx.x >> 7);
+  if (q >= nd) return;
+  const int64_t o = bv.box_off[i];
+  const int64_t rb = bv.own_ptr[db + q], re = bv.own_ptr[db + q + 1];
+  for (int j = threadIdx.x & 127; j < nc; j += 128) {
+    double s = 0.0;
+    const double* ph = phibox + o + (int64_t)j * nd;
+    for (int64_t e = rb; e < re; ++e) s = fma(val[bv.own_vidx[e]], ph[bv.own_col[e]], s);
+    W[o + (int64_t)j * nd + q] = s;
+  }
+}
+
+// A_0[c, :] += P_i[lc, :] over the subdomains of c in ascending order
+__global__ __launch_bounds__(256) void a0_assemble_kernel(int Nc, CoarseView cv, const double* __restrict__ P,
+                                                         const int64_t* __restrict__ p_off, double* __restrict__ A0) {
+  const int c = blockIdx.x;
+  if (c >= Nc) return;
+  double* row = A0 + (int64_t)c * Nc;
+  for (int e = cv.cs_ptr[c]; e < cv.cs_ptr[c + 1]; ++e) {
+    const int i = cv.cs_sub[e], lc = cv.cs_lc[e];
+    const int cb = cv.C_ptr[i], nc = cv.C_ptr[i + 1] - cb;
+    const double* Pi = P + p_off[i];
+    for (int j = threadIdx.x; j < nc; j += 256) row[cv.C_idx[cb + j]] += Pi[(int64_t)j * nc + lc];
+    __syncthreads();
+  }
+}
+
+// F[:, :] (column-major, ld) = M[perm, perm] (M row-major, ldm)
+__global__ void permute_dense_kernel(int n, const int32_t* __restrict__ perm, const double* __restrict__ M,
+                                     int64_t ldm, double* __restrict__ F, int64_t ld) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (r >= n) return;
+  F[(int64_t)c * ld + r] = M[(int64_t)perm[r] * ldm + perm[c]];
+}
+
+__global__ void negate_kernel(int64_t n, double* __restrict__ x) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = -x[i];
+}
+
+__global__ void expand_kernel(int64_t nfree, const int64_t* __restrict__ full_index, const double* __restrict__ xf,
+                              double* __restrict__ xfull) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nfree; i += (int64_t)gridDim.x * blockDim.x)
+    xfull[full_index[i]] = xf[i];
+}
+
+// ---- Krylov helpers --------------------------------------------------------
+constexpr int DOT_CHUNK = 1024;  // rows per partial block
+
+// part[b * ncols + j] = sum over rows of block b of V[:, j] * w
+__global__ __launch_bounds__(256) void cols_dot_partial_kernel(const double* __restrict__ V, int64_t ldv, int ncols,
+                                                              const double* __restrict__ w, int64_t n,
+                                                              double* __restrict__ part) {
+  const int b = blockIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t r0 = (int64_t)b * DOT_CHUNK;
+  const int64_t r1 = min<int64_t>(n, r0 + DOT_CHUNK);
+  double wr[DOT_CHUNK / 64];
+#pragma unroll
+  for (int q = 0; q < DOT_CHUNK / 64; ++q) {
+    const int64_t r = r0 + q * 64 + lane;
+    wr[q] = r < r1 ? w[r] : 0.0;
+  }
+  for (int j = wave; j < ncols; j += 4) {
+    const double* v = V + (int64_t)j * ldv;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < DOT_CHUNK / 64; ++q) {
+      const int64_t r = r0 + q * 64 + lane;
+      if (r < r1) s = fma(v[r], wr[q], s);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) part[(int64_t)b * ncols + j] = s;
+  }
+}
+
+__global__ __launch_bounds__(64) void cols_dot_final_kernel(const double* __restrict__ part, int nblocks, int ncols,
+                                                           double* __restrict__ out) {
+  const int j = blockIdx.x;
+  const int lane = threadIdx.x;
+  double s = 0.0;
+  for (int b = lane; b < nblocks; b += 64) s += part[(int64_t)b * ncols + j];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) out[j] = s;
+}
+
+__global__ void gemv_sub_kernel(const double* __restrict__ V, int64_t ldv, int ncols, const double* __restrict__ h,
+                                double* __restrict__ w, int64_t n) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int j = 0; j < ncols; ++j) s = fma(V[(int64_t)j * ldv + r], h[j], s);
+    w[r] -= s;
+  }
+}
+
+__global__ void gemv_add_kernel(const double* __restrict__ V, int64_t ldv, int ncols, const double* __restrict__ y,
+                                double* __restrict__ x, int64_t n) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int j = 0; j < ncols; ++j) s = fma(V[(int64_t)j * ldv + r], y[j], s);
+    x[r] += s;
+  }
+}
+
+inline int grid_for(int64_t n, int bs = 256, int cap = 65536) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(cap, (n + bs - 1) / bs));
+}
+
+}  // namespace
+
+int cols_dot_blocks(int64_t n) { return (int)((n + DOT_CHUNK - 1) / DOT_CHUNK); }
+
+void spmv_csr(int64_t nrows, const int32_t* rowptr, const int32_t* col, const double* val, const double* x,
+              double* y, hipStream_t st) {
+  if (nrows == 0) return;
+  spmv_kernel<<<(unsigned)((nrows + 15) / 16), 256, 0, st>>>(nrows, rowptr, col, val, x, y);
+}
+
+void gather(int64_t count, const int32_t* idx, const double* src, double* dst, hipStream_t st) {
+  if (count == 0) return;
+  gather_kernel<<<grid_for(count), 256, 0, st>>>(count, idx, src, dst);
+}
+
+void extract_local(const DenseBatch& B, const int32_t* lptr, const int32_t* lidx, const int32_t* rowptr,
+                   const int32_t* col, const double* val, int max_rows, hipStream_t st) {
+  if (B.count == 0 || max_rows == 0) return;
+  extract_kernel<<<dim3((max_rows + 127) / 128, B.count), 128, 0, st>>>(B.base, B.n, B.ld, B.off, lptr, lidx, rowptr,
+                                                                       col, val);
+  GDSW_HIP(hipGetLastError());
+}
+
+void extract_local_dense(const DenseBatch& B, const int32_t* lptr, const int32_t* lidx, const double* M, int64_t ldm,
+                         int max_rows, hipStream_t st) {
+  if (B.count == 0 || max_rows == 0) return;
+  extract_dense_kernel<<<dim3((max_rows + 127) / 128, max_rows, B.count), 128, 0, st>>>(B.base, B.n, B.ld, B.off,
+                                                                                        lptr, lidx, M, ldm);
+  GDSW_HIP(hipGetLastError());
+}
+
+void deterministic_scatter(int64_t n, const int32_t* inv_ptr, const int64_t* inv_pos, const double* w, double* z,
+                           hipStream_t st) {
+  if (n == 0) return;
+  scatter_kernel<<<grid_for(n), 256, 0, st>>>(n, inv_ptr, inv_pos, w, z);
+}
+
+void scatter_prolong(int64_t n, const int32_t* inv_ptr, const int64_t* inv_pos, const double* w,
+                     const CoarseView& cv, const double* y0, const int32_t* y0_pos, double* z, hipStream_t st) {
+  if (n == 0) return;
+  scatter_prolong_kernel<<<grid_for(n), 256, 0, st>>>(n, inv_ptr, inv_pos, w, cv, y0, y0_pos, z);
+}
+
+void restrict_coarse(int nc, const CoarseView& cv, const double* r, double* out, const int32_t* out_pos,
+                     hipStream_t st) {
+  if (nc == 0) return;
+  restrict_kernel<<<nc, 256, 0, st>>>(nc, cv, r, out, out_pos);
+}
+
+void phi_rhs(int64_t total_I, const CoarseView& cv, const int32_t* rowptr, const int32_t* col, const double* val,
+             double* B, hipStream_t st) {
+  if (total_I == 0) return;
+  phi_rhs_kernel<<<(unsigned)((total_I + 127) / 128), 128, 0, st>>>(total_I, cv, rowptr, col, val, B);
+}
+
+void phi_transpose(int64_t total_I, const CoarseView& cv, const double* cm, double* rm, hipStream_t st) {
+  if (total_I == 0) return;
+  phi_transpose_kernel<<<(unsigned)((total_I + 127) / 128), 128, 0, st>>>(total_I, cv, cm, rm);
+}
+
+void phibox(int64_t total_D, const CoarseView& cv, const BoxView& bv, double* out, hipStream_t st) {
+  if (total_D == 0) return;
+  phibox_kernel<<<(unsigned)((total_D + 127) / 128), 128, 0, st>>>(total_D, cv, bv, out);
+}
+
+void own_spmm(int nbox, int max_nd, const CoarseView& cv, const BoxView& bv, const double* val,
+              const double* phibox_, double* W, hipStream_t st) {
+  if (nbox == 0) return;
+  own_spmm_kernel<<<dim3((max_nd + 1) / 2, nbox), 256, 0, st>>>(cv, bv, val, phibox_, W);
+}
+
+void a0_assemble(int Nc, const CoarseView& cv, const double* P, const int64_t* p_off, double* A0, hipStream_t st) {
+  if (Nc == 0) return;
+  a0_assemble_kernel<<<Nc, 256, 0, st>>>(Nc, cv, P, p_off, A0);
+}
+
+void permute_dense(int n, const int32_t* perm, const double* M, int64_t ldm, double* F, int64_t ld, hipStream_t st) {
+  if (n == 0) return;
+  permute_dense_kernel<<<dim3((n + 127) / 128, n), 128, 0, st>>>(n, perm, M, ldm, F, ld);
+}
+
+void negate(int64_t n, double* x, hipStream_t st) {
+  if (n == 0) return;
+  negate_kernel<<<grid_for(n), 256, 0, st>>>(n, x);
+}
+
+void expand(int64_t nfree, const int64_t* full_index, const double* xf, double* xfull, hipStream_t st) {
+  if (nfree == 0) return;
+  expand_kernel<<<grid_for(nfree), 256, 0, st>>>(nfree, full_index, xf, xfull);
+}
+
+void cols_dot(const double* V, int64_t ldv, int ncols, const double* w, int64_t n, double* part, int nblocks,
+              double* out, hipStream_t st) {
+  cols_dot_partial_kernel<<<nblocks, 256, 0, st>>>(V, ldv, ncols, w, n, part);
+  cols_dot_final_kernel<<<ncols, 64, 0, st>>>(part, nblocks, ncols, out);
+}
+
+void gemv_sub(const double* V, int64_t ldv, int ncols, const double* h, double* w, int64_t n, hipStream_t st) {
+  gemv_sub_kernel<<<grid_for(n), 256, 0, st>>>(V, ldv, ncols, h, w, n);
+}
+
+void gemv_add(const double* V, int64_t ldv, int ncols, const double* y, double* x, int64_t n, hipStream_t st) {
+  gemv_add_kernel<<<grid_for(n), 256, 0, st>>>(V, ldv, ncols, y, x, n);
+}
+
+}  // namespace gdsw

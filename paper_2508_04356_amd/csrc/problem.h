@@ -1,0 +1,80 @@
+// Host-side description of one Stokes problem and its decomposition.
+//
+// Everything here is integer bookkeeping plus the finite-element assembly of
+// eq. (2.1); it runs once per problem (the paper's "symbolic setup", Section
+// 3) and is uploaded to the device by the context.
+#pragma once
+
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace gdsw {
+
+struct ProblemSpec {
+  int n = 4;            // elements per axis
+  int m = 2;            // subdomains per axis
+  int overlap = 1;      // element layers
+  int levels = 2;
+  int group = 2;        // three levels: subdomains per subregion per axis
+  double mu = 1.0;
+  double c = 16.0;
+  int manufactured = 0;
+};
+
+// Level-2 (coarse) structures for the three-level method (eq. 2.5).
+struct Level2 {
+  int n_sub = 0;                               // subregions N^(2)
+  std::vector<std::vector<int32_t>> S;         // overlapping coarse index sets
+  std::vector<std::vector<int32_t>> I;         // interior coarse DOFs per subregion
+  int n_ent3 = 0;
+  int n_coarse3 = 0;
+  std::vector<int32_t> gamma_col3;             // per level-2 coarse DOF: level-3 column or -1
+  std::vector<std::vector<int32_t>> C;         // level-3 columns adjacent to each subregion
+};
+
+struct Problem {
+  ProblemSpec spec;
+  int s = 0;                                   // elements per subdomain per axis
+  int64_t n_u = 0, n_p = 0, n_free = 0, n_full = 0;
+
+  // free-DOF CSR matrix (sorted columns) and lifted right-hand side
+  std::vector<int32_t> row_ptr;
+  std::vector<int32_t> col;
+  std::vector<double> val;
+  std::vector<double> rhs;
+
+  // per free DOF
+  std::vector<int8_t> field;                   // 0..2 velocity, 3 pressure
+  std::vector<int32_t> abc;                    // Q2 node coordinates (3 per DOF)
+  std::vector<int64_t> full_index;             // position in the full vector
+  std::vector<double> dirichlet_full;          // full vector of Dirichlet data (0 on free)
+
+  // decomposition
+  int n_sub = 0;
+  std::vector<std::vector<int32_t>> S;         // overlapping sets (sorted)
+  std::vector<std::vector<int32_t>> D;         // closed boxes (sorted)
+  std::vector<std::vector<int32_t>> I;         // interiors (sorted)
+  std::vector<int8_t> multiplicity;            // closed boxes holding each DOF
+
+  // interface entities and coarse columns
+  int n_ent = 0;
+  std::vector<std::array<int32_t, 6>> ent_key; // lo_x, lo_y, lo_z, hi_x, hi_y, hi_z
+  std::vector<int32_t> gamma_col;              // per DOF: coarse column or -1
+  int n_coarse = 0;
+  std::vector<int32_t> coarse_entity, coarse_field;
+  std::vector<std::vector<int32_t>> C;         // coarse columns adjacent to each subdomain
+
+  Level2 lv2;
+
+  int64_t nnz() const { return (int64_t)col.size(); }
+};
+
+// Builds everything above.  Throws std::invalid_argument on a bad spec.
+void build_problem(const ProblemSpec& spec, Problem& P, int threads);
+
+// Subdomains (ascending) that contain coarse column c's entity.
+std::vector<int32_t> entity_subdomains(const Problem& P, int e);
+
+}  // namespace gdsw

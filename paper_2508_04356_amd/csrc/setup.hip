@@ -1,0 +1,550 @@
+// Numeric setup on the device: local matrices and their LU factors, the
+// coarse basis Phi (eq. 2.4), A_0 = Phi^T A Phi (eq. 2.3) and its factors.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <stdexcept>
+
+#include "context.h"
+#include "kernels.h"
+#include "kernels_ops.h"
+
+namespace gdsw {
+
+void* DeviceArena::alloc(uint64_t bytes) {
+  if (bytes == 0) bytes = 256;
+  bytes = (bytes + 255) & ~uint64_t(255);
+  if (budget && used + bytes > budget)
+    throw StatusError{2, "device memory budget exceeded: need " + std::to_string(used + bytes) + " bytes, budget " +
+                             std::to_string(budget)};
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw StatusError{2, "hipMalloc of " + std::to_string(bytes) + " bytes failed (" + hipGetErrorString(e) + ")"};
+  }
+  used += bytes;
+  ptrs.push_back(p);
+  sizes.push_back(bytes);
+  return p;
+}
+
+void DeviceArena::free(void* p) {
+  for (size_t k = 0; k < ptrs.size(); ++k)
+    if (ptrs[k] == p) {
+      (void)hipFree(p);
+      used -= sizes[k];
+      ptrs.erase(ptrs.begin() + k);
+      sizes.erase(sizes.begin() + k);
+      return;
+    }
+}
+
+void DeviceArena::release_all() {
+  for (void* p : ptrs) (void)hipFree(p);
+  ptrs.clear();
+  sizes.clear();
+  used = 0;
+}
+
+static size_t elem_size(int prec) { return prec == P_FP64 ? 8 : (prec == P_FP32 ? 4 : 2); }
+
+uint64_t FactorSet::algorithmic_bytes() const {
+  uint64_t b = 0;
+  for (int f = 0; f < count; ++f) b += (uint64_t)n[f] * n[f] * elem_size(prec);
+  return b;
+}
+
+namespace {
+
+int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+// Host metadata of a factor set for the given sizes; device arrays uploaded.
+void plan_factor_set(FactorSet& fs, const std::vector<int32_t>& sizes, int prec, int nb, int64_t xbase,
+                     DeviceArena& A, hipStream_t st) {
+  fs.prec = prec;
+  fs.nb = nb;
+  fs.count = (int)sizes.size();
+  fs.n = sizes;
+  fs.npad.resize(fs.count);
+  fs.nblk.resize(fs.count);
+  fs.off.resize(fs.count);
+  fs.doff.resize(fs.count);
+  fs.xoff.resize(fs.count);
+  int64_t o = 0, d = 0, x = xbase;
+  fs.max_nblk = 0;
+  for (int f = 0; f < fs.count; ++f) {
+    const int64_t np = std::max<int64_t>(nb, round_up(sizes[f], nb));
+    fs.npad[f] = (int32_t)np;
+    fs.nblk[f] = (int32_t)(np / nb);
+    fs.off[f] = o;
+    fs.doff[f] = d;
+    fs.xoff[f] = x;
+    o += np * np;
+    d += (int64_t)fs.nblk[f] * nb * nb;
+    x += np;
+    fs.max_nblk = std::max(fs.max_nblk, fs.nblk[f]);
+  }
+  fs.total_elems = o;
+  fs.total_dinv = d;
+  fs.total_x = x - xbase;
+  // work lists: forward step s -> (f, J >= s); backward step t -> (f, J <= nblk-1-t)
+  std::vector<int2> fwd, bwd;
+  fs.fwd_start.assign(1, 0);
+  fs.bwd_start.assign(1, 0);
+  for (int s = 0; s < fs.max_nblk; ++s) {
+    for (int f = 0; f < fs.count; ++f) {
+      if (s >= fs.nblk[f]) continue;
+      for (int J = s; J < fs.nblk[f]; ++J) {
+        if (s == 0 && J > 0) continue;  // nothing to update before the first block is solved
+        fwd.push_back(make_int2(f, J));
+      }
+    }
+    fs.fwd_start.push_back((int32_t)fwd.size());
+  }
+  for (int t = 0; t < fs.max_nblk; ++t) {
+    for (int f = 0; f < fs.count; ++f) {
+      const int s = fs.nblk[f] - 1 - t;
+      if (s < 0) continue;
+      for (int J = 0; J <= s; ++J) {
+        if (t == 0 && J < s) continue;
+        bwd.push_back(make_int2(f, J));
+      }
+    }
+    fs.bwd_start.push_back((int32_t)bwd.size());
+  }
+  fs.d_n = dupload(A, fs.n, st);
+  fs.d_npad = dupload(A, fs.npad, st);
+  fs.d_nblk = dupload(A, fs.nblk, st);
+  fs.d_off = dupload(A, fs.off, st);
+  fs.d_doff = dupload(A, fs.doff, st);
+  fs.d_xoff = dupload(A, fs.xoff, st);
+  fs.d_fwd = dupload(A, fwd, st);
+  fs.d_bwd = dupload(A, bwd, st);
+}
+
+struct PivotCheck {
+  std::vector<std::string> names;
+};
+
+void check_pivots(const unsigned long long* d_minpiv, int count, double tol, const std::string& what, hipStream_t st) {
+  std::vector<unsigned long long> mp(count);
+  GDSW_HIP(hipMemcpyAsync(mp.data(), d_minpiv, count * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+  GDSW_HIP(hipStreamSynchronize(st));
+  for (int f = 0; f < count; ++f) {
+    const double v = minpiv_decode(mp[f]);
+    if (!(v > tol) || !std::isfinite(v))
+      throw StatusError{3, what + " " + std::to_string(f) + ": pivot " + std::to_string(v) +
+                               " below tolerance " + std::to_string(tol)};
+  }
+}
+
+unsigned long long* minpiv_buffer(DeviceArena& A, int count, hipStream_t st) {
+  auto* p = dalloc<unsigned long long>(A, std::max(count, 1));
+  std::vector<unsigned long long> init(std::max(count, 1), 0x7fefffffffffffffULL);  // largest finite double
+  GDSW_HIP(hipMemcpyAsync(p, init.data(), init.size() * sizeof(unsigned long long), hipMemcpyHostToDevice, st));
+  return p;
+}
+
+// Factor the matrices of `fs` in chunks: fill (callback writes the FP64
+// matrices into a zeroed staging batch laid out like the set), LU, checks,
+// diagonal-tile inverses and conversion to the storage precision.
+template <class Fill>
+void factor_set(Context& ctx, FactorSet& fs, uint64_t staging_cap, double pivot_tol, const std::string& what,
+                hipStream_t st, Fill&& fill) {
+  DeviceArena& A = ctx.arena;
+  const size_t es = elem_size(fs.prec);
+  fs.store = A.alloc((uint64_t)fs.total_elems * es);
+  fs.dinv = A.alloc((uint64_t)fs.total_dinv * (fs.prec == P_FP64 ? 8 : 4));
+  int f0 = 0;
+  while (f0 < fs.count) {
+    // chunk [f0, f1) within the staging cap
+    int f1 = f0;
+    uint64_t bytes = 0;
+    while (f1 < fs.count) {
+      const uint64_t b = (uint64_t)fs.npad[f1] * fs.npad[f1] * 8;
+      if (f1 > f0 && bytes + b > staging_cap) break;
+      bytes += b;
+      ++f1;
+    }
+    const int cnt = f1 - f0;
+    double* staging;
+    bool own_staging = fs.prec != P_FP64;
+    if (own_staging) {
+      staging = static_cast<double*>(A.alloc(bytes));
+    } else {
+      staging = static_cast<double*>(fs.store) + fs.off[f0];
+    }
+    GDSW_HIP(hipMemsetAsync(staging, 0, bytes, st));
+    // chunk-relative descriptors
+    FactorSet ch = fs;
+    ch.count = cnt;
+    ch.n.assign(fs.n.begin() + f0, fs.n.begin() + f1);
+    ch.npad.assign(fs.npad.begin() + f0, fs.npad.begin() + f1);
+    ch.nblk.assign(fs.nblk.begin() + f0, fs.nblk.begin() + f1);
+    std::vector<int64_t> off_rel(cnt), doff(cnt);
+    int max_n = 0, max_nblk = 0;
+    for (int k = 0; k < cnt; ++k) {
+      off_rel[k] = fs.off[f0 + k] - fs.off[f0];
+      doff[k] = fs.doff[f0 + k];
+      max_n = std::max(max_n, ch.n[k]);
+      max_nblk = std::max(max_nblk, ch.nblk[k]);
+    }
+    ch.max_nblk = max_nblk;
+    int32_t* d_n = dupload(A, ch.n, st);
+    int32_t* d_np = dupload(A, ch.npad, st);
+    int32_t* d_nblk = dupload(A, ch.nblk, st);
+    int64_t* d_off = dupload(A, off_rel, st);
+    int64_t* d_doff = dupload(A, doff, st);
+    DenseBatch B;
+    B.base = staging;
+    B.n = d_n;
+    B.ld = d_np;
+    B.off = d_off;
+    B.count = cnt;
+    B.max_n = max_n;
+    fill(B, f0, f1);
+    unsigned long long* mp = minpiv_buffer(A, cnt, st);
+    lu_nopiv(B, mp, st);
+    check_pivots(mp, cnt, pivot_tol, what, st);
+    // finalize: dinv + conversion on the chunk
+    ch.d_n = d_n;
+    ch.d_npad = d_np;
+    ch.d_nblk = d_nblk;
+    ch.d_off = d_off;
+    ch.d_doff = d_doff;
+    ch.total_elems = (int64_t)(bytes / 8);
+    ch.store = static_cast<char*>(fs.store) + (size_t)fs.off[f0] * es;
+    ch.dinv = fs.dinv;
+    factor_finalize(ch, staging, st);
+    GDSW_HIP(hipStreamSynchronize(st));
+    A.free(mp);
+    A.free(d_n);
+    A.free(d_np);
+    A.free(d_nblk);
+    A.free(d_off);
+    A.free(d_doff);
+    if (own_staging) A.free(staging);
+    f0 = f1;
+  }
+}
+
+template <class T>
+void concat(const std::vector<std::vector<T>>& lists, std::vector<int32_t>& ptr, std::vector<T>& idx) {
+  ptr.assign(lists.size() + 1, 0);
+  for (size_t i = 0; i < lists.size(); ++i) ptr[i + 1] = ptr[i] + (int32_t)lists[i].size();
+  idx.clear();
+  idx.reserve(ptr.back());
+  for (auto& l : lists) idx.insert(idx.end(), l.begin(), l.end());
+}
+
+}  // namespace
+
+void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
+  Problem& P = ctx.P;
+  DeviceArena& A = ctx.arena;
+  A.budget = budget;
+  ctx.nb = nb;
+  const int64_t n = P.n_free;
+  const int levels = P.spec.levels;
+  ctx.Nc = P.n_coarse;
+  const int Nc = ctx.Nc;
+
+  // ---- budget pre-check (dominant terms) --------------------------------
+  {
+    uint64_t need = 0;
+    const size_t es = elem_size(ctx.local_prec);
+    for (int i = 0; i < P.n_sub; ++i) {
+      const uint64_t np = std::max<int64_t>(nb, round_up((int64_t)P.S[i].size(), nb));
+      need += np * np * es + np * nb * (ctx.local_prec == P_FP64 ? 8 : 4);
+    }
+    need += (uint64_t)Nc * Nc * 8 * 2;
+    need += (uint64_t)P.nnz() * 12;
+    if (budget && need > budget)
+      throw StatusError{2, "device memory budget exceeded: need at least " + std::to_string(need) +
+                               " bytes for factors and coarse matrix, budget " + std::to_string(budget) +
+                               (levels == 2 ? " (try levels=3 or a lower local precision)" : "")};
+  }
+
+  // ---- system matrix ------------------------------------------------------
+  ctx.d_rowptr = dupload(A, P.row_ptr, st);
+  ctx.d_col = dupload(A, P.col, st);
+  ctx.d_val = dupload(A, P.val, st);
+  ctx.d_rhs = dupload(A, P.rhs, st);
+  ctx.d_full_index = dupload(A, P.full_index, st);
+  ctx.d_dirichlet_full = dupload(A, P.dirichlet_full, st);
+  double amax = 0.0;
+  for (double v : P.val) amax = std::max(amax, std::fabs(v));
+
+  // ---- factor sets and work vector layout ---------------------------------
+  std::vector<int32_t> l1_sizes(P.n_sub);
+  for (int i = 0; i < P.n_sub; ++i) l1_sizes[i] = (int32_t)P.S[i].size();
+  ctx.merged = (levels == 2 && ctx.local_prec == P_FP64 && Nc > 0);
+  if (ctx.merged) l1_sizes.push_back(Nc);
+  plan_factor_set(ctx.L1, l1_sizes, ctx.local_prec, nb, 0, A, st);
+  ctx.n_w1 = ctx.L1.total_x;
+  std::vector<int32_t> hi_sizes;
+  if (levels == 2 && !ctx.merged && Nc > 0) hi_sizes.push_back(Nc);
+  if (levels == 3) throw StatusError{6, "three-level setup is not built yet"};
+  plan_factor_set(ctx.HI, hi_sizes, P_FP64, nb, ctx.n_w1, A, st);
+  ctx.n_w = ctx.n_w1 + ctx.HI.total_x;
+  ctx.d_w = dalloc<double>(A, std::max<int64_t>(ctx.n_w, 1));
+  GDSW_HIP(hipMemsetAsync(ctx.d_w, 0, std::max<int64_t>(ctx.n_w, 1) * 8, st));
+
+  // gather map and inverse (scatter) map of the level-1 local copies
+  {
+    std::vector<int32_t> gidx(ctx.n_w1, -1);
+    std::vector<int32_t> cnt(n + 1, 0);
+    for (int i = 0; i < P.n_sub; ++i) {
+      const int64_t xo = ctx.L1.xoff[i];
+      for (size_t k = 0; k < P.S[i].size(); ++k) {
+        gidx[xo + k] = P.S[i][k];
+        cnt[P.S[i][k] + 1]++;
+      }
+    }
+    std::vector<int32_t> inv_ptr(n + 1, 0);
+    for (int64_t d = 0; d < n; ++d) inv_ptr[d + 1] = inv_ptr[d] + cnt[d + 1];
+    std::vector<int64_t> inv_pos(inv_ptr[n]);
+    std::vector<int32_t> fill(n, 0);
+    for (int i = 0; i < P.n_sub; ++i) {  // ascending i: fixed summation order
+      const int64_t xo = ctx.L1.xoff[i];
+      for (size_t k = 0; k < P.S[i].size(); ++k) {
+        const int32_t d = P.S[i][k];
+        inv_pos[inv_ptr[d] + fill[d]++] = xo + (int64_t)k;
+      }
+    }
+    ctx.d_gidx = dupload(A, gidx, st);
+    ctx.d_inv_ptr = dupload(A, inv_ptr, st);
+    ctx.d_inv_pos = dupload(A, inv_pos, st);
+  }
+
+  // ---- coarse basis Phi (eq. 2.4) ------------------------------------------
+  std::vector<int32_t> I_ptr, I_idx, C_ptr, C_idx;
+  concat(P.I, I_ptr, I_idx);
+  concat(P.C, C_ptr, C_idx);
+  const int64_t total_I = I_idx.size();
+  std::vector<int32_t> I_sub(total_I), dof_ipos(n, -1);
+  std::vector<int64_t> phi_off(P.n_sub + 1, 0);
+  for (int i = 0; i < P.n_sub; ++i) {
+    for (int32_t p = I_ptr[i]; p < I_ptr[i + 1]; ++p) {
+      I_sub[p] = i;
+      dof_ipos[I_idx[p]] = p;
+    }
+    phi_off[i + 1] = phi_off[i] + (int64_t)P.I[i].size() * P.C[i].size();
+  }
+  // per coarse column: Gamma DOFs and (subdomain, local column) pairs
+  std::vector<std::vector<int32_t>> cg(Nc), cs_sub(Nc), cs_lc(Nc);
+  for (int64_t d = 0; d < n; ++d)
+    if (P.gamma_col[d] >= 0) cg[P.gamma_col[d]].push_back((int32_t)d);
+  for (int i = 0; i < P.n_sub; ++i)
+    for (size_t j = 0; j < P.C[i].size(); ++j) {
+      cs_sub[P.C[i][j]].push_back(i);
+      cs_lc[P.C[i][j]].push_back((int32_t)j);
+    }
+  std::vector<int32_t> cg_ptr, cg_dof, cs_ptr, cs_s, cs_ptr2, cs_l;
+  concat(cg, cg_ptr, cg_dof);
+  concat(cs_sub, cs_ptr, cs_s);
+  concat(cs_lc, cs_ptr2, cs_l);
+  ctx.d_gamma_col = dupload(A, P.gamma_col, st);
+  ctx.d_I_ptr = dupload(A, I_ptr, st);
+  ctx.d_I_idx = dupload(A, I_idx, st);
+  ctx.d_I_sub = dupload(A, I_sub, st);
+  ctx.d_dof_ipos = dupload(A, dof_ipos, st);
+  ctx.d_C_ptr = dupload(A, C_ptr, st);
+  ctx.d_C_idx = dupload(A, C_idx, st);
+  ctx.d_phi_off = dupload(A, phi_off, st);
+  ctx.d_cg_ptr = dupload(A, cg_ptr, st);
+  ctx.d_cg_dof = dupload(A, cg_dof, st);
+  ctx.d_cs_ptr = dupload(A, cs_ptr, st);
+  ctx.d_cs_sub = dupload(A, cs_s, st);
+  ctx.d_cs_lc = dupload(A, cs_l, st);
+  ctx.d_phi_cm = dalloc<double>(A, std::max<int64_t>(phi_off.back(), 1));
+  ctx.d_phi_rm = dalloc<double>(A, std::max<int64_t>(phi_off.back(), 1));
+  CoarseView cv{ctx.d_gamma_col, ctx.d_dof_ipos, ctx.d_I_sub, ctx.d_I_ptr, ctx.d_I_idx, ctx.d_C_ptr,
+                ctx.d_C_idx, ctx.d_phi_off, ctx.d_phi_cm, ctx.d_phi_rm, ctx.d_cg_ptr, ctx.d_cg_dof,
+                ctx.d_cs_ptr, ctx.d_cs_sub, ctx.d_cs_lc};
+
+  if (Nc > 0) {
+    // A_II^(i) dense, LU, and Phi_I = -A_II^-1 A_IGamma Phi_Gamma
+    std::vector<int32_t> ni(P.n_sub), nr(P.n_sub);
+    std::vector<int64_t> aoff(P.n_sub);
+    int64_t tot = 0;
+    int max_ni = 0, max_nr = 0;
+    for (int i = 0; i < P.n_sub; ++i) {
+      ni[i] = (int32_t)P.I[i].size();
+      nr[i] = (int32_t)P.C[i].size();
+      aoff[i] = tot;
+      tot += (int64_t)ni[i] * ni[i];
+      max_ni = std::max(max_ni, ni[i]);
+      max_nr = std::max(max_nr, nr[i]);
+    }
+    double* aii = dalloc<double>(A, std::max<int64_t>(tot, 1));
+    GDSW_HIP(hipMemsetAsync(aii, 0, std::max<int64_t>(tot, 1) * 8, st));
+    int32_t* d_ni = dupload(A, ni, st);
+    int32_t* d_nr = dupload(A, nr, st);
+    int64_t* d_aoff = dupload(A, aoff, st);
+    DenseBatch B;
+    B.base = aii;
+    B.n = d_ni;
+    B.ld = d_ni;
+    B.off = d_aoff;
+    B.count = P.n_sub;
+    B.max_n = max_ni;
+    extract_local(B, ctx.d_I_ptr, ctx.d_I_idx, ctx.d_rowptr, ctx.d_col, ctx.d_val, max_ni, st);
+    unsigned long long* mp = minpiv_buffer(A, P.n_sub, st);
+    lu_nopiv(B, mp, st);
+    check_pivots(mp, P.n_sub, 1e-14 * amax, "interior block", st);
+    GDSW_HIP(hipMemsetAsync(ctx.d_phi_cm, 0, std::max<int64_t>(phi_off.back(), 1) * 8, st));
+    phi_rhs(total_I, cv, ctx.d_rowptr, ctx.d_col, ctx.d_val, ctx.d_phi_cm, st);
+    lu_solve_multi(B, ctx.d_phi_cm, ctx.d_phi_off, d_nr, max_nr, st);
+    phi_transpose(total_I, cv, ctx.d_phi_cm, ctx.d_phi_rm, st);
+    GDSW_HIP(hipStreamSynchronize(st));
+    A.free(aii);
+    A.free(d_ni);
+    A.free(d_nr);
+    A.free(d_aoff);
+    A.free(mp);
+
+    // ---- A_0 = Phi^T A Phi via box-owned nonzeros -------------------------
+    const int m = P.spec.m, s = P.s;
+    std::vector<int32_t> D_ptr, D_idx;
+    concat(P.D, D_ptr, D_idx);
+    const int64_t total_D = D_idx.size();
+    std::vector<int32_t> D_sub(total_D);
+    std::vector<int64_t> box_off(P.n_sub + 1, 0), p_off(P.n_sub + 1, 0);
+    int max_nd = 0, max_nc = 0;
+    for (int i = 0; i < P.n_sub; ++i) {
+      for (int32_t p = D_ptr[i]; p < D_ptr[i + 1]; ++p) D_sub[p] = i;
+      box_off[i + 1] = box_off[i] + (int64_t)P.D[i].size() * P.C[i].size();
+      p_off[i + 1] = p_off[i] + (int64_t)P.C[i].size() * P.C[i].size();
+      max_nd = std::max(max_nd, (int)P.D[i].size());
+      max_nc = std::max(max_nc, (int)P.C[i].size());
+    }
+    // owner of a nonzero: the lowest-numbered box containing both nodes
+    auto box_lo_hi = [&](int coord, int& lo, int& hi) {
+      const int two_s = 2 * s;
+      lo = (coord % two_s == 0) ? std::max(coord / two_s - 1, 0) : coord / two_s;
+      hi = std::min(coord / two_s, m - 1);
+    };
+    std::vector<int64_t> own_ptr(total_D + 1, 0);
+    std::vector<int32_t> own_col;
+    std::vector<int64_t> own_vidx;
+    for (int i = 0; i < P.n_sub; ++i) {
+      const auto& Di = P.D[i];
+      for (size_t q = 0; q < Di.size(); ++q) {
+        const int32_t r = Di[q];
+        int rlo[3], rhi[3];
+        for (int ax = 0; ax < 3; ++ax) box_lo_hi(P.abc[3 * (int64_t)r + ax], rlo[ax], rhi[ax]);
+        for (int32_t e = P.row_ptr[r]; e < P.row_ptr[r + 1]; ++e) {
+          const int32_t c = P.col[e];
+          int owner[3];
+          bool ok = true;
+          for (int ax = 0; ax < 3; ++ax) {
+            int clo, chi;
+            box_lo_hi(P.abc[3 * (int64_t)c + ax], clo, chi);
+            const int lo = std::max(rlo[ax], clo), hi = std::min(rhi[ax], chi);
+            if (lo > hi) ok = false;
+            owner[ax] = lo;
+          }
+          if (!ok) continue;  // cannot happen for an assembled nonzero
+          if (owner[0] + m * (owner[1] + m * owner[2]) != i) continue;
+          const auto it = std::lower_bound(Di.begin(), Di.end(), c);
+          own_col.push_back((int32_t)(it - Di.begin()));
+          own_vidx.push_back(e);
+        }
+        own_ptr[D_ptr[i] + q + 1] = (int64_t)own_col.size();
+      }
+    }
+    int32_t* d_D_ptr = dupload(A, D_ptr, st);
+    int32_t* d_D_idx = dupload(A, D_idx, st);
+    int32_t* d_D_sub = dupload(A, D_sub, st);
+    int64_t* d_box_off = dupload(A, box_off, st);
+    int64_t* d_own_ptr = dupload(A, own_ptr, st);
+    int32_t* d_own_col = dupload(A, own_col, st);
+    int64_t* d_own_vidx = dupload(A, own_vidx, st);
+    int64_t* d_p_off = dupload(A, p_off, st);
+    BoxView bv{d_D_ptr, d_D_idx, d_D_sub, d_box_off, d_own_ptr, d_own_col, d_own_vidx};
+    double* pbox = dalloc<double>(A, std::max<int64_t>(box_off.back(), 1));
+    double* W = dalloc<double>(A, std::max<int64_t>(box_off.back(), 1));
+    double* Pm = dalloc<double>(A, std::max<int64_t>(p_off.back(), 1));
+    GDSW_HIP(hipMemsetAsync(pbox, 0, std::max<int64_t>(box_off.back(), 1) * 8, st));
+    phibox(total_D, cv, bv, pbox, st);
+    own_spmm(P.n_sub, max_nd, cv, bv, ctx.d_val, pbox, W, st);
+    std::vector<GemmDesc> gd(P.n_sub);
+    for (int i = 0; i < P.n_sub; ++i) {
+      const int nd = (int)P.D[i].size(), nci = (int)P.C[i].size();
+      gd[i] = GemmDesc{pbox + box_off[i], W + box_off[i], Pm + p_off[i], nci, nci, nd, nd, nd, nci, 1, 0};
+    }
+    GemmDesc* d_gd = dupload(A, gd, st);
+    gemm_batched(d_gd, P.n_sub, max_nc, max_nc, 1.0, 0.0, st);
+    ctx.d_A0 = dalloc<double>(A, (int64_t)Nc * Nc);
+    GDSW_HIP(hipMemsetAsync(ctx.d_A0, 0, (int64_t)Nc * Nc * 8, st));
+    a0_assemble(Nc, cv, Pm, d_p_off, ctx.d_A0, st);
+    GDSW_HIP(hipStreamSynchronize(st));
+    for (void* p : {(void*)d_D_ptr, (void*)d_D_idx, (void*)d_D_sub, (void*)d_box_off, (void*)d_own_ptr,
+                    (void*)d_own_col, (void*)d_own_vidx, (void*)d_p_off, (void*)pbox, (void*)W, (void*)Pm,
+                    (void*)d_gd})
+      A.free(p);
+
+    // coarse factor order: velocity-type columns first, then pressure-type
+    ctx.coarse_perm.clear();
+    for (int c = 0; c < Nc; ++c)
+      if (P.coarse_field[c] < 3) ctx.coarse_perm.push_back(c);
+    for (int c = 0; c < Nc; ++c)
+      if (P.coarse_field[c] == 3) ctx.coarse_perm.push_back(c);
+  }
+
+  // ---- level-1 local factors (and the coarse factor when merged) -----------
+  std::vector<int32_t> S_ptr, S_idx;
+  concat(P.S, S_ptr, S_idx);
+  int32_t* d_S_ptr = dupload(A, S_ptr, st);
+  int32_t* d_S_idx = dupload(A, S_idx, st);
+  int32_t* d_perm = ctx.coarse_perm.empty() ? nullptr : dupload(A, ctx.coarse_perm, st);
+  const uint64_t staging_cap = std::max<uint64_t>(1ull << 30, std::min<uint64_t>(32ull << 30, budget / 4));
+  factor_set(ctx, ctx.L1, staging_cap, 1e-14 * amax, "local factor", st,
+             [&](DenseBatch& B, int f0, int f1) {
+               const int nloc = std::min(f1, P.n_sub) - f0;
+               if (nloc > 0) {
+                 DenseBatch Bl = B;
+                 Bl.count = nloc;
+                 int mx = 0;
+                 for (int f = f0; f < f0 + nloc; ++f) mx = std::max(mx, (int)P.S[f].size());
+                 Bl.max_n = mx;
+                 extract_local(Bl, d_S_ptr + f0, d_S_idx, ctx.d_rowptr, ctx.d_col, ctx.d_val, mx, st);
+               }
+               if (ctx.merged && f1 == ctx.L1.count) {
+                 const int fc = ctx.L1.count - 1 - f0;
+                 double* dst = B.base + (ctx.L1.off[ctx.L1.count - 1] - ctx.L1.off[f0]);
+                 permute_dense(Nc, d_perm, ctx.d_A0, Nc, dst, ctx.L1.npad[ctx.L1.count - 1], st);
+                 (void)fc;
+               }
+             });
+  if (!ctx.merged && ctx.HI.count > 0) {
+    factor_set(ctx, ctx.HI, staging_cap, 0.0, "coarse factor", st, [&](DenseBatch& B, int, int) {
+      permute_dense(Nc, d_perm, ctx.d_A0, Nc, B.base, ctx.HI.npad[0], st);
+    });
+  }
+  A.free(d_S_ptr);
+  A.free(d_S_idx);
+  // coarse column -> work-vector position
+  if (Nc > 0) {
+    const FactorSet& cs = ctx.merged ? ctx.L1 : ctx.HI;
+    const int fc = ctx.merged ? ctx.L1.count - 1 : 0;
+    ctx.coarse_xoff = cs.xoff[fc];
+    std::vector<int32_t> pinv(Nc);
+    for (int q = 0; q < Nc; ++q) pinv[ctx.coarse_perm[q]] = (int32_t)(ctx.coarse_xoff + q);
+    ctx.d_coarse_pinv = dupload(A, pinv, st);
+  }
+  if (d_perm) A.free(d_perm);
+  ctx.factor_bytes = 0;
+  for (int f = 0; f < P.n_sub; ++f)
+    ctx.factor_bytes += (uint64_t)ctx.L1.npad[f] * ctx.L1.npad[f] * elem_size(ctx.local_prec);
+  ctx.coarse_bytes = (uint64_t)Nc * Nc * 8 * 2 + (uint64_t)phi_off.back() * 16;
+  GDSW_HIP(hipStreamSynchronize(st));
+}
+
+}  // namespace gdsw

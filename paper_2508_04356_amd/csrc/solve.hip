@@ -1,0 +1,234 @@
+// Preconditioner apply (eq. 2.2) and right-preconditioned FGMRES.
+//
+// Apply: every local right-hand side R_i r is gathered into one work vector,
+// the coarse right-hand side Phi^T r is written next to them, one blocked
+// triangular solve runs over all factors (the additive sum of eq. 2.2 makes
+// the local and coarse solves independent), and one fixed-order scatter forms
+// z = sum_i R_i^T y_i + Phi y_0.
+//
+// FGMRES follows the stated reading: x_0 = 0, classical Gram-Schmidt applied
+// twice, Givens rotations, stop once |g_{j+1}| / ||b|| <= rtol, then
+// x = x_0 + Z y and a recomputed true residual; restart from x if needed.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+
+#include "context.h"
+#include "kernels.h"
+#include "kernels_ops.h"
+
+namespace gdsw {
+namespace {
+
+CoarseView coarse_view(const Context& c) {
+  return CoarseView{c.d_gamma_col, c.d_dof_ipos, c.d_I_sub,  c.d_I_ptr,  c.d_I_idx,
+                    c.d_C_ptr,     c.d_C_idx,    c.d_phi_off, c.d_phi_cm, c.d_phi_rm,
+                    c.d_cg_ptr,    c.d_cg_dof,   c.d_cs_ptr,  c.d_cs_sub, c.d_cs_lc};
+}
+
+__global__ void residual_kernel(int64_t n, const double* __restrict__ b, double* __restrict__ r) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    r[i] = b[i] - r[i];
+}
+
+// v = w / s[idx]
+__global__ void scale_div_kernel(int64_t n, const double* __restrict__ w, const double* __restrict__ s, int idx,
+                                 double* __restrict__ v) {
+  const double d = s[idx];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    v[i] = d != 0.0 ? w[i] / d : 0.0;
+}
+
+__global__ void sqrt_kernel(double* __restrict__ s, int idx) { s[idx] = sqrt(s[idx]); }
+
+// start of a cycle: g = (beta, 0, ...), beta = sqrt(ss) in scal[1]
+__global__ void cycle_start_kernel(double* __restrict__ g, int restart, double* __restrict__ scal) {
+  const double beta = sqrt(scal[0]);
+  scal[1] = beta;
+  for (int i = 0; i <= restart; ++i) g[i] = i == 0 ? beta : 0.0;
+}
+
+// Arnoldi column j: H[:j+1, j] = h1 + h2, H[j+1, j] = ||w||, previous rotations,
+// new rotation, g update; scal[2] = |g_{j+1}| / bnorm, scal[3] = ||w||.
+__global__ void arnoldi_finish_kernel(int j, int restart, const double* __restrict__ h1,
+                                      const double* __restrict__ h2, double* __restrict__ H,
+                                      double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
+                                      double* __restrict__ scal, double bnorm) {
+  const int ldh = restart + 1;
+  double* col = H + (int64_t)j * ldh;
+  for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
+  const double hn = sqrt(scal[4]);
+  col[j + 1] = hn;
+  scal[3] = hn;
+  for (int i = 0; i < j; ++i) {
+    const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+    col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+    col[i] = t;
+  }
+  const double rho = hypot(col[j], col[j + 1]);
+  cs[j] = col[j] / rho;
+  sn[j] = col[j + 1] / rho;
+  col[j] = rho;
+  col[j + 1] = 0.0;
+  g[j + 1] = -sn[j] * g[j];
+  g[j] = cs[j] * g[j];
+  scal[2] = fabs(g[j + 1]) / bnorm;
+}
+
+// back substitution y = H[:k,:k]^-1 g[:k] into y
+__global__ void back_subst_kernel(int k, int restart, const double* __restrict__ H, const double* __restrict__ g,
+                                  double* __restrict__ y) {
+  const int ldh = restart + 1;
+  for (int i = k - 1; i >= 0; --i) {
+    double s = g[i];
+    for (int l = i + 1; l < k; ++l) s -= H[(int64_t)l * ldh + i] * y[l];
+    y[i] = s / H[(int64_t)i * ldh + i];
+  }
+}
+
+inline int grid_n(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(65536, (n + 255) / 256)); }
+
+void ensure_workspace(Context& ctx, int restart) {
+  if (ctx.restart >= restart && ctx.d_V) return;
+  DeviceArena& A = ctx.arena;
+  for (void* p : {(void*)ctx.d_V, (void*)ctx.d_Z, (void*)ctx.d_H, (void*)ctx.d_g, (void*)ctx.d_cs,
+                  (void*)ctx.d_sn, (void*)ctx.d_hv, (void*)ctx.d_part, (void*)ctx.d_scal, (void*)ctx.d_t1,
+                  (void*)ctx.d_t2})
+    if (p) A.free(p);
+  const int64_t n = ctx.P.n_free;
+  ctx.ldv = (n + 63) / 64 * 64;
+  ctx.restart = restart;
+  ctx.d_V = dalloc<double>(A, ctx.ldv * (restart + 1));
+  ctx.d_Z = dalloc<double>(A, ctx.ldv * restart);
+  ctx.d_H = dalloc<double>(A, (int64_t)(restart + 1) * restart);
+  ctx.d_g = dalloc<double>(A, restart + 1);
+  ctx.d_cs = dalloc<double>(A, restart);
+  ctx.d_sn = dalloc<double>(A, restart);
+  ctx.d_hv = dalloc<double>(A, 2 * (restart + 1));
+  ctx.n_part_blocks = cols_dot_blocks(n);
+  ctx.d_part = dalloc<double>(A, (int64_t)ctx.n_part_blocks * (restart + 1));
+  ctx.d_scal = dalloc<double>(A, 16);
+  ctx.d_t1 = dalloc<double>(A, ctx.ldv);
+  ctx.d_t2 = dalloc<double>(A, ctx.ldv);
+  if (!ctx.h_pinned) GDSW_HIP(hipHostMalloc((void**)&ctx.h_pinned, 16 * sizeof(double), hipHostMallocDefault));
+}
+
+double read_scalar(Context& ctx, int idx, hipStream_t st) {
+  GDSW_HIP(hipMemcpyAsync(ctx.h_pinned, ctx.d_scal + idx, sizeof(double), hipMemcpyDeviceToHost, st));
+  GDSW_HIP(hipStreamSynchronize(st));
+  return ctx.h_pinned[0];
+}
+
+}  // namespace
+
+void spmv(Context& ctx, const double* x, double* y, hipStream_t st) {
+  spmv_csr(ctx.P.n_free, ctx.d_rowptr, ctx.d_col, ctx.d_val, x, y, st);
+}
+
+void apply_precond(Context& ctx, const double* r, double* z, hipStream_t st, hipEvent_t* ev) {
+  const CoarseView cv = coarse_view(ctx);
+  if (ev) GDSW_HIP(hipEventRecord(ev[0], st));
+  gather(ctx.n_w1, ctx.d_gidx, r, ctx.d_w, st);
+  if (ctx.Nc > 0) restrict_coarse(ctx.Nc, cv, r, ctx.d_w, ctx.d_coarse_pinv, st);
+  if (ev) GDSW_HIP(hipEventRecord(ev[1], st));
+  trsv_set(ctx.L1, ctx.d_w, st);
+  if (ev) GDSW_HIP(hipEventRecord(ev[2], st));
+  trsv_set(ctx.HI, ctx.d_w, st);
+  if (ev) GDSW_HIP(hipEventRecord(ev[3], st));
+  if (ctx.Nc > 0)
+    scatter_prolong(ctx.P.n_free, ctx.d_inv_ptr, ctx.d_inv_pos, ctx.d_w, cv, nullptr, ctx.d_coarse_pinv, z, st);
+  else
+    deterministic_scatter(ctx.P.n_free, ctx.d_inv_ptr, ctx.d_inv_pos, ctx.d_w, z, st);
+  if (ev) GDSW_HIP(hipEventRecord(ev[4], st));
+  GDSW_HIP(hipGetLastError());
+}
+
+void expand_solution(const Context& ctx, const double* xf, double* xfull, hipStream_t st) {
+  GDSW_HIP(hipMemcpyAsync(xfull, ctx.d_dirichlet_full, ctx.P.n_full * sizeof(double), hipMemcpyDeviceToDevice, st));
+  expand(ctx.P.n_free, ctx.d_full_index, xf, xfull, st);
+  GDSW_HIP(hipGetLastError());
+}
+
+FgmresResult fgmres(Context& ctx, const double* b, double* x, double rtol, int restart, int max_it, bool use_graph,
+                    hipStream_t st) {
+  (void)use_graph;
+  ensure_workspace(ctx, restart);
+  const int64_t n = ctx.P.n_free;
+  const int64_t ldv = ctx.ldv;
+  double* V = ctx.d_V;
+  double* Z = ctx.d_Z;
+  double* S = ctx.d_scal;
+  const int nb = ctx.n_part_blocks;
+  FgmresResult res;
+  // ||b||
+  cols_dot(b, ldv, 1, b, n, ctx.d_part, nb, S + 0, st);
+  const double bnorm = std::sqrt(read_scalar(ctx, 0, st));
+  GDSW_HIP(hipMemsetAsync(x, 0, n * sizeof(double), st));
+  if (bnorm == 0.0) {
+    res.converged = true;
+    return res;
+  }
+  int it = 0;
+  int cycles = 0;
+  while (true) {
+    // r = b - A x
+    spmv(ctx, x, ctx.d_t1, st);
+    residual_kernel<<<grid_n(n), 256, 0, st>>>(n, b, ctx.d_t1);
+    cols_dot(ctx.d_t1, ldv, 1, ctx.d_t1, n, ctx.d_part, nb, S + 0, st);
+    cycle_start_kernel<<<1, 1, 0, st>>>(ctx.d_g, restart, S);
+    const double beta = read_scalar(ctx, 1, st);
+    res.true_rel = beta / bnorm;
+    if (res.true_rel <= rtol) {
+      res.converged = true;
+      break;
+    }
+    if (it >= max_it) break;
+    scale_div_kernel<<<grid_n(n), 256, 0, st>>>(n, ctx.d_t1, S, 1, V);
+    int k = 0;
+    for (int j = 0; j < restart; ++j) {
+      double* vj = V + (int64_t)j * ldv;
+      double* zj = Z + (int64_t)j * ldv;
+      double* w = ctx.d_t2;
+      apply_precond(ctx, vj, zj, st);
+      spmv(ctx, zj, w, st);
+      cols_dot(V, ldv, j + 1, w, n, ctx.d_part, nb, ctx.d_hv, st);
+      gemv_sub(V, ldv, j + 1, ctx.d_hv, w, n, st);
+      cols_dot(V, ldv, j + 1, w, n, ctx.d_part, nb, ctx.d_hv + restart + 1, st);
+      gemv_sub(V, ldv, j + 1, ctx.d_hv + restart + 1, w, n, st);
+      cols_dot(w, ldv, 1, w, n, ctx.d_part, nb, S + 4, st);
+      arnoldi_finish_kernel<<<1, 1, 0, st>>>(j, restart, ctx.d_hv, ctx.d_hv + restart + 1, ctx.d_H, ctx.d_cs,
+                                             ctx.d_sn, ctx.d_g, S, bnorm);
+      scale_div_kernel<<<grid_n(n), 256, 0, st>>>(n, w, S, 3, V + (int64_t)(j + 1) * ldv);
+      GDSW_HIP(hipMemcpyAsync(ctx.h_pinned, S + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+      GDSW_HIP(hipStreamSynchronize(st));
+      const double rel = ctx.h_pinned[0];
+      const double hn = ctx.h_pinned[1];
+      ++it;
+      k = j + 1;
+      res.rel = rel;
+      if (!std::isfinite(rel)) throw StatusError{4, "FGMRES: non-finite residual estimate (NaN in the Arnoldi norm)"};
+      if (rel <= rtol || hn == 0.0 || it >= max_it) break;
+    }
+    back_subst_kernel<<<1, 1, 0, st>>>(k, restart, ctx.d_H, ctx.d_g, ctx.d_hv);
+    gemv_add(Z, ldv, k, ctx.d_hv, x, n, st);
+    ++cycles;
+    // true residual
+    spmv(ctx, x, ctx.d_t1, st);
+    residual_kernel<<<grid_n(n), 256, 0, st>>>(n, b, ctx.d_t1);
+    cols_dot(ctx.d_t1, ldv, 1, ctx.d_t1, n, ctx.d_part, nb, S + 0, st);
+    sqrt_kernel<<<1, 1, 0, st>>>(S, 0);
+    res.true_rel = read_scalar(ctx, 0, st) / bnorm;
+    if (res.true_rel <= rtol) {
+      res.converged = true;
+      break;
+    }
+    if (it >= max_it) break;
+  }
+  res.iterations = it;
+  res.restarts = std::max(0, cycles - 1);
+  GDSW_HIP(hipGetLastError());
+  return res;
+}
+
+}  // namespace gdsw

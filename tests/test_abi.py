@@ -1,0 +1,88 @@
+"""CPU checks of the C ABI: exports, host-side setup against the oracle, errors.
+
+No compute call reaches the device here; contexts are host-only.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import paper_2508_04356_amd as G
+from oracle.counts import full_gdsw_closed_form
+from oracle.decomposition import Decomposition
+from oracle.stokes import StokesProblem, dof_count_q2q1
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "gdsw.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(gdsw_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    syms = declared_symbols()
+    assert len(syms) >= 15
+    for s in syms:
+        assert hasattr(G._lib, s), s
+        assert s in G.EXPORTED, s
+
+
+@pytest.mark.parametrize("n,m,mu,c,man", [(4, 2, 1.0, 16.0, 0), (6, 3, 0.7, 3.0, 1), (6, 2, 2.0, 1.0, 0)])
+def test_host_assembly_matches_oracle(n, m, mu, c, man):
+    s = G.Solver(n, m, host_only=True, viscosity=mu, inflow=c, manufactured=man)
+    sz = s.sizes()
+    p = StokesProblem(n, viscosity=mu, inflow=c, manufactured=man)
+    assert sz.n_free == p.n_free and sz.n_full == p.n_full == dof_count_q2q1(n)
+    assert sz.n_u_free == p.n_u and sz.n_p == p.n_p
+    rp, col, val = s.host_matrix()
+    A = sp.csr_matrix((val, col, rp), shape=(sz.n_free, sz.n_free))
+    assert abs(A - p.A).max() <= 1e-15 * abs(p.A).max()
+    assert np.abs(s.host_rhs() - p.b).max() <= 1e-14 * max(1.0, np.abs(p.b).max())
+    field, abc = s.dof_map()
+    assert np.array_equal(field, p.dof_field) and np.array_equal(abc, p.dof_node)
+    d = Decomposition(p, m, 1)
+    assert sz.n_entities == d.n_ent == full_gdsw_closed_form(m)
+    assert sz.n_coarse == d.n_coarse
+    for i in range(d.n_sub):
+        assert np.array_equal(s.local_indices(i), d.S[i])
+    s.close()
+
+
+def test_host_sizes_at_16_cubed():
+    s = G.Solver(16, 4, host_only=True)
+    sz = s.sizes()
+    assert sz.n_free == 97169 and sz.n_sub == 64 and sz.n_coarse == 1116
+    assert sz.local_min == 3216 and sz.local_max == 6934
+    s.close()
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(n=5, m=2), "EINVAL"),
+    (dict(n=4, m=2, overlap=0), "EINVAL"),
+    (dict(n=4, m=2, levels=4), "EINVAL"),
+    (dict(n=4, m=4, levels=3, group=3), "EINVAL"),
+    (dict(n=4, m=2, precision=7), "EINVAL"),
+    (dict(n=4, m=2, tile=96), "EINVAL"),
+    (dict(n=4, m=2, viscosity=-1.0), "EINVAL"),
+    (dict(n=0, m=1), "EINVAL"),
+])
+def test_setup_argument_errors(kw, status):
+    with pytest.raises(G.GdswError) as e:
+        G.Solver(host_only=True, **kw)
+    assert e.value.name == status
+    assert len(str(e.value)) > 10
+
+
+def test_device_calls_rejected_on_host_context():
+    s = G.Solver(4, 2, host_only=True)
+    with pytest.raises(G.GdswError) as e:
+        s.apply(1, 2)
+    assert e.value.name == "EINVAL"
+    with pytest.raises(G.GdswError):
+        s.spmv(1, 2)
+    with pytest.raises(G.GdswError):
+        s.local_indices(99)
+    s.close()

@@ -1,0 +1,206 @@
+"""GPU parity of the HIP path against the CPU oracle (calls go through the C ABI).
+
+Tolerances (FP64): the oracle factors with partial pivoting, the library
+without pivoting and with inverted diagonal tiles, so the two local solves
+differ by about cond(A_i) * eps.  Setup results (A, Phi, A_0) are compared at
+1e-12 relative; preconditioner outputs at 1e-10 relative in the max norm;
+FGMRES solutions at 1e-10 relative with identical iteration counts.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_2508_04356_amd as G  # noqa: E402
+from inputs import random_vector, small_parity_cases, workload  # noqa: E402
+from oracle.decomposition import Decomposition  # noqa: E402
+from oracle.fgmres import fgmres as oracle_fgmres  # noqa: E402
+from oracle.gdsw import TwoLevelGDSW  # noqa: E402
+from oracle.stokes import StokesProblem  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+DEV = "cuda"
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def rel_max(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+_cache = {}
+
+
+def oracle_case(w):
+    key = (w.n, w.m, w.overlap, w.viscosity, w.inflow, w.manufactured)
+    if key not in _cache:
+        p = StokesProblem(w.n, viscosity=w.viscosity, inflow=w.inflow, manufactured=w.manufactured)
+        d = Decomposition(p, w.m, w.overlap)
+        _cache[key] = (p, d, TwoLevelGDSW(p.A, d))
+    return _cache[key]
+
+
+def gpu_case(w, **kw):
+    print(f"[gpu] setup {w.name} n={w.n} m={w.m} {kw}", flush=True)
+    return G.Solver(w.n, w.m, overlap=w.overlap, viscosity=w.viscosity, inflow=w.inflow,
+                    manufactured=w.manufactured, **kw)
+
+
+@pytest.mark.parametrize("w", small_parity_cases(), ids=lambda w: w.name)
+def test_setup_and_apply_parity(w):
+    p, d, M = oracle_case(w)
+    s = gpu_case(w)
+    n = p.n_free
+    assert s.n_free == n and s.n_coarse == d.n_coarse
+    # right-hand side and SpMV
+    b = torch.zeros(n, dtype=torch.float64, device=DEV)
+    s.rhs(b)
+    assert rel_max(host(b), p.b) < 1e-13
+    x = random_vector(n, seed=11)
+    y = torch.zeros_like(b)
+    s.spmv(dev(x), y)
+    assert rel_max(host(y), p.A @ x) < 1e-13
+    # coarse basis and coarse matrix
+    assert rel_max(s.coarse_basis(), M.Phi.toarray()) < 1e-12
+    assert rel_max(s.coarse_matrix(), M.A0) < 1e-12
+    # preconditioner apply, element by element
+    r = random_vector(n, seed=1)
+    z = torch.zeros_like(b)
+    s.apply(dev(r), z)
+    zo = M(r)
+    err = rel_max(host(z), zo)
+    print(f"[gpu] {w.name} apply rel err {err:.2e}", flush=True)
+    assert err < 1e-10
+    # bitwise repeatability
+    z2 = torch.zeros_like(b)
+    s.apply(dev(r), z2)
+    assert torch.equal(z, z2)
+    s.close()
+
+
+@pytest.mark.parametrize("tile", [64, 128])
+def test_tile_sizes_agree(tile):
+    w = workload("C1").with_(name="n6m3", n=6, m=3)
+    p, d, M = oracle_case(w)
+    s = gpu_case(w, tile=tile)
+    r = random_vector(p.n_free, seed=3)
+    z = torch.zeros(p.n_free, dtype=torch.float64, device=DEV)
+    s.apply(dev(r), z)
+    assert rel_max(host(z), M(r)) < 1e-10
+    s.close()
+
+
+@pytest.mark.parametrize("w", small_parity_cases()[:4], ids=lambda w: w.name)
+def test_fgmres_parity(w):
+    p, d, M = oracle_case(w)
+    hist = []
+    xo, ito, relo, trelo = oracle_fgmres(lambda v: p.A @ v, M, p.b, rtol=w.rtol, history=hist)
+    s = gpu_case(w)
+    b = torch.zeros(p.n_free, dtype=torch.float64, device=DEV)
+    s.rhs(b)
+    x = torch.zeros_like(b)
+    info = s.fgmres(b, x, rtol=w.rtol, restart=w.restart, max_it=w.max_it)[0]
+    print(f"[gpu] {w.name} it gpu {info.iterations} oracle {ito} true {info.true_rel_res:.2e}", flush=True)
+    assert info.iterations == ito
+    assert info.true_rel_res <= w.rtol
+    assert np.linalg.norm(host(x) - xo) / np.linalg.norm(xo) < 1e-10 + 10 * w.rtol
+    s.close()
+
+
+def test_fgmres_tight_tolerance_solution():
+    """rtol 1e-13: the GPU solution matches the oracle's to 1e-10."""
+    w = workload("C1")
+    p, d, M = oracle_case(w)
+    xo, ito, _, _ = oracle_fgmres(lambda v: p.A @ v, M, p.b, rtol=1e-13)
+    s = gpu_case(w)
+    b = torch.zeros(p.n_free, dtype=torch.float64, device=DEV)
+    s.rhs(b)
+    x = torch.zeros_like(b)
+    info = s.fgmres(b, x, rtol=1e-13)[0]
+    assert info.iterations == ito
+    assert np.linalg.norm(host(x) - xo) / np.linalg.norm(xo) < 1e-10
+    s.close()
+
+
+def test_single_subdomain_is_direct_solve():
+    """m = 1: no interface, no coarse space, B = A^-1; FGMRES needs one step."""
+    w = workload("C1").with_(name="n4m1", n=4, m=1)
+    p, d, M = oracle_case(w)
+    s = gpu_case(w)
+    assert s.n_coarse == 0
+    b = torch.zeros(p.n_free, dtype=torch.float64, device=DEV)
+    s.rhs(b)
+    x = torch.zeros_like(b)
+    info = s.fgmres(b, x, rtol=1e-10)[0]
+    assert info.iterations == 1 and info.true_rel_res <= 1e-10
+    s.close()
+
+
+def test_manufactured_poiseuille_exact_on_gpu():
+    w = workload("C1").with_(name="man", n=6, m=3, manufactured=1)
+    s = gpu_case(w)
+    p = StokesProblem(6, manufactured=1)
+    b = torch.zeros(p.n_free, dtype=torch.float64, device=DEV)
+    s.rhs(b)
+    x = torch.zeros_like(b)
+    s.fgmres(b, x, rtol=1e-13)
+    xf = torch.zeros(p.n_full, dtype=torch.float64, device=DEV)
+    s.expand(x, xf)
+    c = p.c
+    ref = p.interpolant(lambda X, Y, Z: np.stack([c * Y * (1 - Y) * Z * (1 - Z), 0 * X, 0 * X]),
+                        lambda X, Y, Z: 0 * X)
+    assert np.abs(host(xf) - ref).max() < 1e-9
+    s.close()
+
+
+def test_budget_error_is_reported():
+    w = workload("C1")
+    with pytest.raises(G.GdswError) as e:
+        gpu_case(w, budget=1 << 20)
+    assert e.value.name == "ENOMEM"
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, f"oracle_{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    with open(path) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("name", ["C1", "C2"])
+def test_workload_against_stored_oracle(name):
+    """Full-size workload: apply outputs at sampled DOFs, FGMRES iteration
+    count and solution samples against the stored oracle run."""
+    g = _golden(name)
+    w = workload(name)
+    s = gpu_case(w)
+    n = s.n_free
+    assert n == g["n_free"]
+    idx = np.array(g["idx"])
+    r = random_vector(n, seed=1)
+    z = torch.zeros(n, dtype=torch.float64, device=DEV)
+    s.apply(dev(r), z)
+    zh = host(z)
+    assert np.abs(zh[idx] - np.array(g["z"])).max() / np.abs(np.array(g["z"])).max() < 1e-10
+    assert abs(np.linalg.norm(zh) - g["z_norm"]) / g["z_norm"] < 1e-10
+    b = torch.zeros(n, dtype=torch.float64, device=DEV)
+    s.rhs(b)
+    x = torch.zeros_like(b)
+    info = s.fgmres(b, x, rtol=g["rtol"], restart=g["restart"])[0]
+    print(f"[gpu] {name} it {info.iterations} (oracle {g['iterations']}) t {info.t_solve_s:.3f}s", flush=True)
+    assert info.iterations == g["iterations"]
+    xh = host(x)
+    assert np.abs(xh[idx] - np.array(g["x"])).max() / np.abs(np.array(g["x"])).max() < 1e-10 + 10 * g["rtol"]
+    s.close()
