@@ -94,7 +94,9 @@ typedef struct {
   int32_t restart;            /* Krylov cycle length (1 ... 200) */
   int32_t max_it;             /* total inner iterations */
   int32_t use_graph;          /* 1: replay each iteration as a HIP graph */
-  int32_t reserved;
+  int32_t history_len;        /* entries available in `history` */
+  double* history;            /* host array or NULL: |g_{j+1}| / ||b|| after
+                                 each iteration (first column only) */
 } gdsw_fgmres_opts;
 
 typedef struct {
@@ -197,6 +199,15 @@ gdsw_status gdsw_copy_coarse_basis(const gdsw_ctx* ctx, double* phi_host);
  * of local_size(i) int32; pass NULL to query the size into *size. */
 gdsw_status gdsw_local_indices(const gdsw_ctx* ctx, int32_t i, int32_t* idx_host,
                                int32_t* size);
+
+/* Tuning --------------------------------------------------------------------- */
+
+/* Re-plans the launch schedule of the blocked triangular solves: the factors
+ * are split into `phases` groups (1..64) whose forward/backward sweeps start
+ * ceil(tiles / phases) launches apart, which evens out the bytes per launch.
+ * Results do not depend on it (the arithmetic of every tile is unchanged).
+ * Synchronises `stream`; must not overlap other calls on ctx. */
+gdsw_status gdsw_set_schedule(gdsw_ctx* ctx, int32_t phases, void* stream);
 
 /* Diagnostics --------------------------------------------------------------- */
 

@@ -15,9 +15,15 @@ Definitions followed, in the paper's notation:
   null-space vector of field f (a velocity translation or the pressure
   constant) restricted to interface entity e, i.e. 1 on e's f-DOFs.
 
-Local and coarse matrices are factored by LAPACK's dense LU with partial
-pivoting (``scipy.linalg.lu_factor``).  The apply sums the local corrections
-in ascending subdomain order and adds the coarse correction last.
+Local matrices are factored by LAPACK's dense LU with partial pivoting
+(``scipy.linalg.lu_factor``).  The coarse matrix is factored by plain LU
+without row exchanges after ordering the velocity-type coarse columns first
+(``lu_nopivot``): the paper names no coarse solver, and this is the textbook
+variant that exists for these saddle-point matrices (the velocity-type block
+of A_0 is SPD and its Schur complement negative definite, both pinned).  The
+FGMRES iteration count is sensitive to this choice.  The apply
+sums the local corrections in ascending subdomain order and adds the coarse
+correction last.
 
 Pins (``tests/test_oracle_gdsw.py``): Phi_Gamma is a partition of unity; the
 extension reproduces constants on subdomains away from the Dirichlet and
@@ -30,6 +36,35 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
+
+
+def lu_nopivot(M, order):
+    """Plain LU without row exchanges of M[order][:, order] (Doolittle, one
+    rank-1 elimination step per column).  Returns (L, U, order) with L unit
+    lower and U upper triangular, L U = M[order][:, order]."""
+    F = np.array(M[np.ix_(order, order)], dtype=np.float64)
+    n = F.shape[0]
+    for k in range(n - 1):
+        if F[k, k] == 0.0:
+            raise ZeroDivisionError(f"zero pivot at step {k}")
+        F[k + 1:, k] /= F[k, k]
+        F[k + 1:, k + 1:] -= np.outer(F[k + 1:, k], F[k, k + 1:])
+    return np.tril(F, -1) + np.eye(n), np.triu(F), np.asarray(order)
+
+
+def lu_nopivot_solve(fac, b):
+    L, U, order = fac
+    y = sla.solve_triangular(L, b[order], lower=True, unit_diagonal=True, check_finite=False)
+    y = sla.solve_triangular(U, y, lower=False, check_finite=False)
+    out = np.empty_like(y)
+    out[order] = y
+    return out
+
+
+def velocity_first(fields):
+    """Indices with field < 3 (velocity-type) first, then field 3, each ascending."""
+    fields = np.asarray(fields)
+    return np.concatenate([np.nonzero(fields < 3)[0], np.nonzero(fields == 3)[0]])
 
 
 def coarse_basis(A, dec):
@@ -79,7 +114,7 @@ class TwoLevelGDSW:
         if dec.n_coarse > 0:
             self.Phi = coarse_basis(self.A, dec)
             self.A0 = (self.Phi.T @ (self.A @ self.Phi)).toarray()
-            self.A0_lu = sla.lu_factor(self.A0, check_finite=False)
+            self.A0_lu = lu_nopivot(self.A0, velocity_first(dec.coarse_field))
         else:
             self.Phi = None
             self.A0 = np.zeros((0, 0))
@@ -94,7 +129,7 @@ class TwoLevelGDSW:
         return sla.lu_solve(self.local_lu[i], ri, check_finite=False)
 
     def coarse_solve(self, r0):
-        return sla.lu_solve(self.A0_lu, r0, check_finite=False)
+        return lu_nopivot_solve(self.A0_lu, r0)
 
     def apply_local(self, r):
         """sum_i R_i^T A_i^{-1} R_i r, ascending i."""

@@ -12,6 +12,11 @@ import os
 
 import numpy as np
 
+# torch ships its own HIP runtime (libamdhip64.so.7, libhsa-runtime64.so.1).
+# Loading it before the library makes the dynamic loader bind libgdsw.so to
+# that same runtime, so one process never holds two HSA runtimes.
+import torch  # noqa: F401
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgdsw.so")
 
@@ -36,7 +41,7 @@ class Decomposition(C.Structure):
 
 class FgmresOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("restart", C.c_int32), ("max_it", C.c_int32), ("use_graph", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("history_len", C.c_int32), ("history", C.POINTER(C.c_double))]
 
 
 class FgmresInfo(C.Structure):
@@ -69,6 +74,7 @@ _sig = {
     "gdsw_copy_coarse_basis": (C.c_int, [_P, _P]),
     "gdsw_local_indices": (C.c_int, [_P, C.c_int32, _P, C.POINTER(C.c_int32)]),
     "gdsw_profile_apply": (C.c_int, [_P, _P, _P, _P, _P]),
+    "gdsw_set_schedule": (C.c_int, [_P, C.c_int32, _P]),
     "gdsw_last_error": (C.c_char_p, [_P]),
     "gdsw_destroy": (None, [_P]),
 }
@@ -187,20 +193,28 @@ class Solver:
         _check(_lib.gdsw_apply_precond(self._ctx, _ptr(r), _ptr(z), nrhs, ld, _stream(stream)), self._ctx)
         return z
 
+    def set_schedule(self, phases, stream=None):
+        _check(_lib.gdsw_set_schedule(self._ctx, phases, _stream(stream)), self._ctx)
+
     def profile_apply(self, r, z, stream=None):
         ms = np.zeros(4)
         _check(_lib.gdsw_profile_apply(self._ctx, _ptr(r), _ptr(z), _stream(stream), _ptr(ms)), self._ctx)
         return ms
 
     def fgmres(self, b, x, rtol=1e-8, restart=100, max_it=1000, use_graph=False, nrhs=1, ld=None, stream=None,
-               raise_on_noconv=True):
+               raise_on_noconv=True, history=False):
         ld = self.n_free if ld is None else ld
-        opts = FgmresOpts(rtol, restart, max_it, int(use_graph), 0)
+        hist = np.zeros(max_it) if history else None
+        hp = hist.ctypes.data_as(C.POINTER(C.c_double)) if history else None
+        opts = FgmresOpts(rtol, restart, max_it, int(use_graph), max_it if history else 0, hp)
         infos = (FgmresInfo * nrhs)()
         st = _lib.gdsw_fgmres_solve(self._ctx, _ptr(b), _ptr(x), nrhs, ld, C.byref(opts), infos, _stream(stream))
         if st != 4 or raise_on_noconv:
             _check(st, self._ctx)
-        return [infos[k] for k in range(nrhs)]
+        out = [infos[k] for k in range(nrhs)]
+        if history:
+            return out, hist[:out[0].iterations].copy()
+        return out
 
     def expand(self, x_free, x_full, stream=None):
         _check(_lib.gdsw_expand_solution(self._ctx, _ptr(x_free), _ptr(x_full), _stream(stream)), self._ctx)

@@ -163,10 +163,7 @@ gdsw_status gdsw_get_sizes(const gdsw_ctx* ctx, gdsw_sizes* out) {
     out->solve_bytes = c.L1.algorithmic_bytes() + c.HI.algorithmic_bytes();
     int64_t l = 0;
     for (const FactorSet* fs : {&c.L1, &c.HI})
-      for (size_t k = 0; k + 1 < fs->fwd_start.size(); ++k) {
-        l += fs->fwd_start[k + 1] > fs->fwd_start[k];
-        l += fs->bwd_start[k + 1] > fs->bwd_start[k];
-      }
+      for (size_t k = 0; k + 1 < fs->step_start.size(); ++k) l += fs->step_start[k + 1] > fs->step_start[k];
     out->solve_launches = l;
   }
   return GDSW_OK;
@@ -242,7 +239,8 @@ gdsw_status gdsw_fgmres_solve(gdsw_ctx* ctx, const double* b_dev, double* x_dev,
     for (int k = 0; k < nrhs; ++k) {
       const auto t0 = std::chrono::steady_clock::now();
       FgmresResult r = fgmres(ctx->c, b_dev + (int64_t)k * ld, x_dev + (int64_t)k * ld, opts->rtol, opts->restart,
-                              opts->max_it, opts->use_graph != 0, (hipStream_t)stream);
+                              opts->max_it, opts->use_graph != 0, (hipStream_t)stream,
+                              k == 0 ? opts->history : nullptr, k == 0 ? opts->history_len : 0);
       GDSW_HIP(hipStreamSynchronize((hipStream_t)stream));
       const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
       if (info) {
@@ -304,6 +302,18 @@ gdsw_status gdsw_local_indices(const gdsw_ctx* ctx, int32_t i, int32_t* idx_host
   if (size) *size = (int32_t)P.S[i].size();
   if (idx_host) std::memcpy(idx_host, P.S[i].data(), P.S[i].size() * sizeof(int32_t));
   return GDSW_OK;
+}
+
+gdsw_status gdsw_set_schedule(gdsw_ctx* ctx, int32_t phases, void* stream) {
+  if (gdsw_status s = check_device_ctx(ctx)) return s;
+  if (phases < 1 || phases > 64) return fail(ctx, GDSW_EINVAL, "phases must be in 1..64");
+  return guarded(ctx, [&]() {
+    hipStream_t st = (hipStream_t)stream;
+    GDSW_HIP(hipStreamSynchronize(st));
+    plan_schedule(ctx->c.L1, phases, ctx->c.arena, st);
+    plan_schedule(ctx->c.HI, phases, ctx->c.arena, st);
+    GDSW_HIP(hipStreamSynchronize(st));
+  });
 }
 
 gdsw_status gdsw_profile_apply(gdsw_ctx* ctx, const double* r_dev, double* z_dev, void* stream, double* ms) {

@@ -76,10 +76,11 @@ struct FactorSet {
   int64_t* d_off = nullptr;
   int64_t* d_doff = nullptr;
   int64_t* d_xoff = nullptr;
-  // per-launch work lists of (factor, row block) pairs
-  std::vector<int32_t> fwd_start, bwd_start;
-  int2* d_fwd = nullptr;
-  int2* d_bwd = nullptr;
+  // launch schedule: items (factor, J, K, mode) of every launch; factors run
+  // their 2*nblk sweeps with phase offsets so that launches carry similar work
+  int phases = 1;
+  std::vector<int32_t> step_start;
+  int4* d_items = nullptr;
   uint64_t algorithmic_bytes() const;  // sum n^2 * sizeof(prec) + dinv
 };
 
@@ -168,6 +169,7 @@ struct Context {
 };
 
 // numeric setup and operators (setup.hip / solve.hip)
+void plan_schedule(FactorSet& fs, int phases, DeviceArena& A, hipStream_t st);
 void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb);
 void apply_precond(Context& ctx, const double* r, double* z, hipStream_t st, hipEvent_t* ev = nullptr);
 void spmv(Context& ctx, const double* x, double* y, hipStream_t st);
@@ -177,7 +179,7 @@ struct FgmresResult {
   bool converged = false;
 };
 FgmresResult fgmres(Context& ctx, const double* b, double* x, double rtol, int restart, int max_it,
-                    bool use_graph, hipStream_t st);
+                    bool use_graph, hipStream_t st, double* history = nullptr, int history_len = 0);
 void expand_solution(const Context& ctx, const double* xf, double* xfull, hipStream_t st);
 
 }  // namespace gdsw

@@ -31,13 +31,14 @@ double minpiv_decode(unsigned long long bits);
 void lu_solve_multi(const DenseBatch& B, double* rhs, const int64_t* roff, const int32_t* nrhs,
                     int max_nrhs, hipStream_t st);
 
-// Diagonal-tile inverses of the factor set from the FP64 LU in `lu`
-// (laid out like the set), then conversion of the factors to the set's
-// precision when it is not FP64 (lu -> set.store).
-void factor_finalize(FactorSet& fs, const double* lu, hipStream_t st);
+// From the FP64 LU in `lu` (laid out like the set): inverses of the diagonal
+// tiles (into the set's dinv, offsets relative to dbase), every off-diagonal
+// tile left-multiplied by its block row's diagonal inverse, and conversion to
+// the set's precision when it is not FP64 (lu -> set.store).
+void factor_finalize(FactorSet& fs, double* lu, int64_t dbase, hipStream_t st);
 
 // Blocked forward/backward solve, in place on the work vector w, for every
-// factor of the set.
+// factor of the set: one launch per schedule step.
 void trsv_set(const FactorSet& fs, double* w, hipStream_t st);
 
 // C_b = alpha * op(A_b) * B_b + beta * C_b, FP64, column-major.

@@ -6,14 +6,16 @@
 //   trailing update as a 64x64-tile FP64 product.  No pivoting is needed for
 //   the monolithic saddle-point matrices ordered velocity first: the velocity
 //   block is SPD and the Schur complement is negative definite.
-// * factor_finalize: inverts the diagonal tiles of L and U (so that the
-//   triangular solve becomes a sequence of tile products) and converts the
-//   factors to the storage precision.
-// * trsv_set: the forward-backward solve.  One launch per tile column; a
-//   work-group owns one (factor, row tile) pair, streams its tile of L (or U)
-//   exactly once with 16-byte loads, and the owner of the diagonal tile
-//   finishes the block with the inverted diagonal tile.  No work-group ever
-//   waits on another, and every reduction runs in a fixed order.
+// * factor_finalize: inverts the diagonal tiles of L and U and scales every
+//   off-diagonal tile by its block row's diagonal inverse, so that
+//     L y = r  becomes  y_J = L_JJ^-1 r_J - sum_{K<J} (L_JJ^-1 L_JK) y_K,
+//     U x = y  becomes  x_J = U_JJ^-1 y_J - sum_{K>J} (U_JJ^-1 U_JK) x_K,
+//   then converts the factors to the storage precision.
+// * trsv_set: the forward-backward solve as a sequence of launches in which
+//   every work-group streams exactly one tile (16-byte loads issued first)
+//   and updates one block of its factor's vector.  Factors are interleaved
+//   with phase offsets so that every launch moves a similar number of bytes.
+//   No work-group ever waits on another; every reduction has a fixed order.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -336,9 +338,12 @@ __device__ inline void load16(const uint16_t* p, float (&o)[8]) {
 
 // part[(wave * GPL + g) * NB + row] = sum over this lane's columns of A[row, c] v[c]
 // MODE 0: full tile, 1: strictly lower (c < row), 2: upper (c >= row).
+// The tile is loaded into registers first; v (NB entries at vsrc) and the
+// current values (NB entries at csrc) are staged in LDS meanwhile.
 template <typename T, int NB, int MODE>
-__device__ inline void tile_gemv(const T* __restrict__ A, int64_t ld, const double* __restrict__ v, int row_lim,
-                                 int col_lim, typename VecW<T>::acc* part) {
+__device__ inline void tile_gemv_split(const T* __restrict__ A, int64_t ld, const double* __restrict__ vsrc,
+                                       const double* __restrict__ csrc, double* vbuf, double* cur, int row_lim,
+                                       int col_lim, typename VecW<T>::acc* part) {
   using AT = typename VecW<T>::acc;
   constexpr int W = VecW<T>::W;
   constexpr int LPC = NB / W;
@@ -348,34 +353,39 @@ __device__ inline void tile_gemv(const T* __restrict__ A, int64_t ld, const doub
   static_assert(GPL >= 1 && IT >= 1, "tile shape");
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int g = lane / LPC, rr = (lane % LPC) * W;
+  AT a[IT][W];
+  const bool rows_ok = rr < row_lim;
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int c = wave * CPW + it * GPL + g;
+    if (rows_ok && c < col_lim) {
+      load16(A + (int64_t)c * ld + rr, a[it]);
+    } else {
+#pragma unroll
+      for (int e = 0; e < W; ++e) a[it][e] = 0;
+    }
+  }
+  if (tid < NB) {
+    vbuf[tid] = vsrc[tid];
+    cur[tid] = csrc[tid];
+  }
+  __syncthreads();
   AT acc[W];
 #pragma unroll
   for (int e = 0; e < W; ++e) acc[e] = 0;
-  if (rr < row_lim) {
-    AT a[IT][W];
 #pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int c = wave * CPW + it * GPL + g;
-      if (c < col_lim) {
-        load16(A + (int64_t)c * ld + rr, a[it]);
-      } else {
+  for (int it = 0; it < IT; ++it) {
+    const int c = wave * CPW + it * GPL + g;
+    const AT vc = (AT)vbuf[c];
 #pragma unroll
-        for (int e = 0; e < W; ++e) a[it][e] = 0;
-      }
-    }
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int c = wave * CPW + it * GPL + g;
-      const AT vc = (AT)v[c];
-#pragma unroll
-      for (int e = 0; e < W; ++e) {
-        const bool use = MODE == 0 || (MODE == 1 && c < rr + e) || (MODE == 2 && c >= rr + e);
-        if (use) acc[e] = fma(a[it][e], vc, acc[e]);
-      }
+    for (int e = 0; e < W; ++e) {
+      const bool use = MODE == 0 || (MODE == 1 && c < rr + e) || (MODE == 2 && c >= rr + e);
+      if (use) acc[e] = fma(a[it][e], vc, acc[e]);
     }
   }
 #pragma unroll
   for (int e = 0; e < W; ++e) part[(wave * GPL + g) * NB + rr + e] = acc[e];
+  __syncthreads();
 }
 
 template <typename T, int NB>
@@ -396,104 +406,52 @@ struct DinvT<double> {
   using type = double;
 };
 
+// One launch of the blocked solve.  Every work item is one tile:
+//   mode 0:  x_J -= T_{J,K} x_K   (T = L_JJ^-1 L_JK below, U_JJ^-1 U_JK above the diagonal)
+//   mode 1:  x_J  = L_JJ^-1 x_J   (start of the forward sweep)
+//   mode 2:  x_J  = U_JJ^-1 x_J   (start of the backward sweep)
+// The tile loads are issued before anything else, so a work-group's only
+// serial dependence is one tile read.
 template <typename T, int NB>
-__global__ __launch_bounds__(256) void trsv_fwd_kernel(const T* __restrict__ store,
-                                                      const typename DinvT<T>::type* __restrict__ dinv,
-                                                      const int32_t* __restrict__ N, const int32_t* __restrict__ NP,
-                                                      const int64_t* __restrict__ OFF,
-                                                      const int64_t* __restrict__ DOFF,
-                                                      const int64_t* __restrict__ XOFF,
-                                                      const int2* __restrict__ items, int s,
-                                                      double* __restrict__ w) {
+__global__ __launch_bounds__(256) void trsv_step_kernel(const T* __restrict__ store,
+                                                       const typename DinvT<T>::type* __restrict__ dinv,
+                                                       const int32_t* __restrict__ N, const int32_t* __restrict__ NP,
+                                                       const int64_t* __restrict__ OFF,
+                                                       const int64_t* __restrict__ DOFF,
+                                                       const int64_t* __restrict__ XOFF,
+                                                       const int4* __restrict__ items, double* __restrict__ w) {
   using AT = typename VecW<T>::acc;
   using DT = typename DinvT<T>::type;
+  using ADT = typename VecW<DT>::acc;
   constexpr int GPLm = 64 / (NB / VecW<T>::W);
   constexpr int GPLd = 64 / (NB / VecW<DT>::W);
   constexpr int PSZ = 4 * (GPLm > GPLd ? GPLm : GPLd) * NB;
   __shared__ double vbuf[NB];
-  __shared__ double cbuf[NB];
-  __shared__ double part_d[PSZ];  // large enough for either accumulator type
-  const int2 item = items[blockIdx.x];
-  const int f = item.x, J = item.y;
-  const int n = N[f];
-  const int64_t np = NP[f];
-  const T* A = store + OFF[f];
-  double* x = w + XOFF[f];
-  const int tid = threadIdx.x;
-  const int r0 = J * NB;
-  const int rlim = min(NB, n - r0);
-  if (s > 0) {
-    const int c0 = (s - 1) * NB;
-    if (tid < NB) vbuf[tid] = x[c0 + tid];
-    __syncthreads();
-    AT* part = reinterpret_cast<AT*>(part_d);
-    tile_gemv<T, NB, 0>(A + (int64_t)c0 * np + r0, np, vbuf, rlim, min(NB, n - c0), part);
-    __syncthreads();
-    if (tid < NB) cbuf[tid] = x[r0 + tid] - (double)part_sum<T, NB>(part, tid);
-  } else {
-    if (tid < NB) cbuf[tid] = x[r0 + tid];
-  }
-  __syncthreads();
-  if (J == s) {
-    using ADT = typename VecW<DT>::acc;
-    ADT* part = reinterpret_cast<ADT*>(part_d);
-    tile_gemv<DT, NB, 1>(dinv + DOFF[f] + (int64_t)s * NB * NB, NB, cbuf, NB, NB, part);
-    __syncthreads();
-    if (tid < NB) x[r0 + tid] = cbuf[tid] + (double)part_sum<DT, NB>(part, tid);
-  } else {
-    if (tid < NB) x[r0 + tid] = cbuf[tid];
-  }
-}
-
-template <typename T, int NB>
-__global__ __launch_bounds__(256) void trsv_bwd_kernel(const T* __restrict__ store,
-                                                      const typename DinvT<T>::type* __restrict__ dinv,
-                                                      const int32_t* __restrict__ N, const int32_t* __restrict__ NP,
-                                                      const int32_t* __restrict__ NBLK,
-                                                      const int64_t* __restrict__ OFF,
-                                                      const int64_t* __restrict__ DOFF,
-                                                      const int64_t* __restrict__ XOFF,
-                                                      const int2* __restrict__ items, int t,
-                                                      double* __restrict__ w) {
-  using AT = typename VecW<T>::acc;
-  using DT = typename DinvT<T>::type;
-  constexpr int GPLm = 64 / (NB / VecW<T>::W);
-  constexpr int GPLd = 64 / (NB / VecW<DT>::W);
-  constexpr int PSZ = 4 * (GPLm > GPLd ? GPLm : GPLd) * NB;
-  __shared__ double vbuf[NB];
-  __shared__ double cbuf[NB];
+  __shared__ double cur[NB];
   __shared__ double part_d[PSZ];
-  const int2 item = items[blockIdx.x];
-  const int f = item.x, J = item.y;
+  const int4 item = items[blockIdx.x];
+  const int f = item.x, J = item.y, K = item.z, mode = item.w;
   const int n = N[f];
-  const int nblk = NBLK[f];
-  const int s = nblk - 1 - t;
   const int64_t np = NP[f];
-  const T* A = store + OFF[f];
   double* x = w + XOFF[f];
   const int tid = threadIdx.x;
   const int r0 = J * NB;
-  const int rlim = min(NB, n - r0);
-  if (s + 1 < nblk) {
-    const int c0 = (s + 1) * NB;
-    if (tid < NB) vbuf[tid] = x[c0 + tid];
-    __syncthreads();
+  if (mode == 0) {
+    const int c0 = K * NB;
     AT* part = reinterpret_cast<AT*>(part_d);
-    tile_gemv<T, NB, 0>(A + (int64_t)c0 * np + r0, np, vbuf, rlim, min(NB, n - c0), part);
-    __syncthreads();
-    if (tid < NB) cbuf[tid] = x[r0 + tid] - (double)part_sum<T, NB>(part, tid);
+    tile_gemv_split<T, NB, 0>(store + OFF[f] + (int64_t)c0 * np + r0, np, x + c0, x + r0, vbuf, cur,
+                              min(NB, n - r0), min(NB, n - c0), part);
+    if (tid < NB) x[r0 + tid] = cur[tid] - (double)part_sum<T, NB>(part, tid);
   } else {
-    if (tid < NB) cbuf[tid] = x[r0 + tid];
-  }
-  __syncthreads();
-  if (J == s) {
-    using ADT = typename VecW<DT>::acc;
     ADT* part = reinterpret_cast<ADT*>(part_d);
-    tile_gemv<DT, NB, 2>(dinv + DOFF[f] + (int64_t)s * NB * NB, NB, cbuf, NB, NB, part);
-    __syncthreads();
-    if (tid < NB) x[r0 + tid] = (double)part_sum<DT, NB>(part, tid);
-  } else {
-    if (tid < NB) x[r0 + tid] = cbuf[tid];
+    const DT* D = dinv + DOFF[f] + (int64_t)J * NB * NB;
+    if (mode == 1) {
+      tile_gemv_split<DT, NB, 1>(D, NB, x + r0, x + r0, vbuf, cur, NB, NB, part);
+      if (tid < NB) x[r0 + tid] = cur[tid] + (double)part_sum<DT, NB>(part, tid);
+    } else {
+      tile_gemv_split<DT, NB, 2>(D, NB, x + r0, x + r0, vbuf, cur, NB, NB, part);
+      if (tid < NB) x[r0 + tid] = (double)part_sum<DT, NB>(part, tid);
+    }
   }
 }
 
@@ -502,18 +460,67 @@ void trsv_launch(const FactorSet& fs, double* w, hipStream_t st) {
   using DT = typename DinvT<T>::type;
   const T* store = static_cast<const T*>(fs.store);
   const DT* dinv = static_cast<const DT*>(fs.dinv);
-  for (int s = 0; s < fs.max_nblk; ++s) {
-    const int cnt = fs.fwd_start[s + 1] - fs.fwd_start[s];
+  for (size_t g = 0; g + 1 < fs.step_start.size(); ++g) {
+    const int cnt = fs.step_start[g + 1] - fs.step_start[g];
     if (cnt == 0) continue;
-    trsv_fwd_kernel<T, NB><<<cnt, 256, 0, st>>>(store, dinv, fs.d_n, fs.d_npad, fs.d_off, fs.d_doff, fs.d_xoff,
-                                                fs.d_fwd + fs.fwd_start[s], s, w);
+    trsv_step_kernel<T, NB><<<cnt, 256, 0, st>>>(store, dinv, fs.d_n, fs.d_npad, fs.d_off, fs.d_doff, fs.d_xoff,
+                                                 fs.d_items + fs.step_start[g], w);
   }
-  for (int t = 0; t < fs.max_nblk; ++t) {
-    const int cnt = fs.bwd_start[t + 1] - fs.bwd_start[t];
-    if (cnt == 0) continue;
-    trsv_bwd_kernel<T, NB><<<cnt, 256, 0, st>>>(store, dinv, fs.d_n, fs.d_npad, fs.d_nblk, fs.d_off, fs.d_doff,
-                                                fs.d_xoff, fs.d_bwd + fs.bwd_start[t], t, w);
+}
+
+// Left-multiplies every off-diagonal tile of block row J by the inverse of
+// the diagonal block: L_JK <- L_JJ^-1 L_JK (J > K), U_JK <- U_JJ^-1 U_JK
+// (J < K).  One work-group per tile, the tile resident in LDS.
+template <int NBT>
+__global__ __launch_bounds__(256) void row_scale_kernel(double* __restrict__ lu, const int32_t* __restrict__ NP,
+                                                       const int64_t* __restrict__ OFF,
+                                                       const int32_t* __restrict__ NBLK,
+                                                       const double* __restrict__ dinv,
+                                                       const int64_t* __restrict__ DOFF, int64_t dbase) {
+  constexpr int nb = NBT;
+  const int f = blockIdx.y;
+  const int nblk = NBLK[f];
+  const int J = blockIdx.x % nblk, K = blockIdx.x / nblk;
+  if (K >= nblk || J == K) return;
+  const int64_t np = NP[f];
+  double* T = lu + OFF[f] + (int64_t)K * nb * np + (int64_t)J * nb;
+  const double* S = dinv + (DOFF[f] - dbase) + (int64_t)J * nb * nb;
+  extern __shared__ double t[];
+  const int P = nb + 1;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < nb * nb; idx += blockDim.x) {
+    const int r = idx % nb, c = idx / nb;
+    t[c * P + r] = T[(int64_t)c * np + r];
   }
+  __syncthreads();
+  const bool lower = J > K;
+  // each thread: 8 rows x 8 columns (nb = 128) or 4 x 4 (nb = 64)
+  constexpr int RB = nb / 16;
+  const int tr = tid % 16, tc = tid / 16;
+  double acc[RB][RB];
+#pragma unroll
+  for (int a = 0; a < RB; ++a)
+#pragma unroll
+    for (int b = 0; b < RB; ++b) acc[a][b] = 0.0;
+  for (int k = 0; k < nb; ++k) {
+    double sv[RB], tv[RB];
+#pragma unroll
+    for (int a = 0; a < RB; ++a) {
+      const int r = tr * RB + a;
+      const double sk = S[(int64_t)k * nb + r];
+      sv[a] = lower ? (k < r ? sk : (k == r ? 1.0 : 0.0)) : (k >= r ? sk : 0.0);
+    }
+#pragma unroll
+    for (int b = 0; b < RB; ++b) tv[b] = t[(tc * RB + b) * P + k];
+#pragma unroll
+    for (int a = 0; a < RB; ++a)
+#pragma unroll
+      for (int b = 0; b < RB; ++b) acc[a][b] = fma(sv[a], tv[b], acc[a][b]);
+  }
+#pragma unroll
+  for (int a = 0; a < RB; ++a)
+#pragma unroll
+    for (int b = 0; b < RB; ++b) T[(int64_t)(tc * RB + b) * np + tr * RB + a] = acc[a][b];
 }
 
 // ---- batched FP64 GEMM (setup only) ----------------------------------------
@@ -600,24 +607,47 @@ void lu_solve_multi(const DenseBatch& B, double* rhs, const int64_t* roff, const
   GDSW_HIP(hipGetLastError());
 }
 
-void factor_finalize(FactorSet& fs, const double* lu, hipStream_t st) {
+__global__ void convert_dinv_f32(const double* __restrict__ src, float* __restrict__ dst, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
+}
+
+void factor_finalize(FactorSet& fs, double* lu, int64_t dbase, hipStream_t st) {
   if (fs.count == 0) return;
   const size_t shm = ((size_t)fs.nb * (fs.nb + 1) + fs.nb) * sizeof(double);
+  double* d64 = nullptr;
   if (fs.prec == P_FP64) {
-    GDSW_HIP(hipFuncSetAttribute((const void*)dinv_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)shm));
-    dinv_kernel<double><<<dim3(fs.max_nblk, fs.count), 256, shm, st>>>(
-        lu, fs.d_n, fs.d_npad, fs.d_off, fs.d_nblk, static_cast<double*>(fs.dinv), fs.d_doff, fs.nb);
+    d64 = static_cast<double*>(fs.dinv) + dbase;
   } else {
-    GDSW_HIP(hipFuncSetAttribute((const void*)dinv_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)shm));
-    dinv_kernel<float><<<dim3(fs.max_nblk, fs.count), 256, shm, st>>>(
-        lu, fs.d_n, fs.d_npad, fs.d_off, fs.d_nblk, static_cast<float*>(fs.dinv), fs.d_doff, fs.nb);
+    GDSW_HIP(hipStreamSynchronize(st));
+    GDSW_HIP(hipMalloc((void**)&d64, (size_t)fs.total_dinv * sizeof(double)));
+  }
+  // diagonal-tile inverses (FP64), written relative to dbase
+  GDSW_HIP(hipFuncSetAttribute((const void*)dinv_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)shm));
+  dinv_kernel<double><<<dim3(fs.max_nblk, fs.count), 256, shm, st>>>(lu, fs.d_n, fs.d_npad, fs.d_off, fs.d_nblk,
+                                                                    d64 - dbase, fs.d_doff, fs.nb);
+  // row scaling of the off-diagonal tiles
+  const size_t shm2 = (size_t)fs.nb * (fs.nb + 1) * sizeof(double);
+  const dim3 grid(fs.max_nblk * fs.max_nblk, fs.count);
+  if (fs.nb == 128) {
+    GDSW_HIP(hipFuncSetAttribute((const void*)row_scale_kernel<128>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)shm2));
+    row_scale_kernel<128><<<grid, 256, shm2, st>>>(lu, fs.d_npad, fs.d_off, fs.d_nblk, d64, fs.d_doff, dbase);
+  } else {
+    GDSW_HIP(hipFuncSetAttribute((const void*)row_scale_kernel<64>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)shm2));
+    row_scale_kernel<64><<<grid, 256, shm2, st>>>(lu, fs.d_npad, fs.d_off, fs.d_nblk, d64, fs.d_doff, dbase);
+  }
+  if (fs.prec != P_FP64) {
     const int blocks = 4096;
+    convert_dinv_f32<<<blocks, 256, 0, st>>>(d64, static_cast<float*>(fs.dinv) + dbase, fs.total_dinv);
     if (fs.prec == P_FP32)
       convert_kernel_f32<<<blocks, 256, 0, st>>>(lu, static_cast<float*>(fs.store), fs.total_elems);
     else
       convert_kernel_bf16<<<blocks, 256, 0, st>>>(lu, static_cast<uint16_t*>(fs.store), fs.total_elems);
+    GDSW_HIP(hipStreamSynchronize(st));
+    GDSW_HIP(hipFree(d64));
   }
   GDSW_HIP(hipGetLastError());
 }

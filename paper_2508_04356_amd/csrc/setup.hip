@@ -63,6 +63,51 @@ namespace {
 
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
+}  // namespace
+
+// Launch schedule with `phases` groups of factors whose sweeps start
+// ceil(max_nblk / phases) launches apart.  Local step l of a factor with nblk
+// tiles: 0 = forward start (x_J = L_JJ^-1 x_J for all J); 1 .. nblk-1 =
+// forward updates with block s = l-1 (J > s); nblk = backward start
+// (x_J = U_JJ^-1 x_J); nblk+1 .. 2 nblk-1 = backward updates with block
+// s = 2 nblk - l (J < s), i.e. s = nblk-1 down to 1.
+void plan_schedule(FactorSet& fs, int phases, DeviceArena& A, hipStream_t st) {
+  phases = std::max(1, std::min(phases, std::max(1, fs.count)));
+  fs.phases = phases;
+  const int P = (fs.max_nblk + phases - 1) / phases;
+  std::vector<int> o(fs.count);
+  int total = 0;
+  for (int f = 0; f < fs.count; ++f) {
+    o[f] = (f % phases) * P;
+    total = std::max(total, o[f] + 2 * fs.nblk[f]);
+  }
+  std::vector<int4> items;
+  fs.step_start.assign(1, 0);
+  for (int g = 0; g < total; ++g) {
+    for (int f = 0; f < fs.count; ++f) {
+      const int nb = fs.nblk[f];
+      const int l = g - o[f];
+      if (l < 0 || l >= 2 * nb) continue;
+      if (l == 0) {
+        for (int J = 0; J < nb; ++J) items.push_back(make_int4(f, J, J, 1));
+      } else if (l < nb) {
+        const int s = l - 1;
+        for (int J = s + 1; J < nb; ++J) items.push_back(make_int4(f, J, s, 0));
+      } else if (l == nb) {
+        for (int J = 0; J < nb; ++J) items.push_back(make_int4(f, J, J, 2));
+      } else {
+        const int s = 2 * nb - l;
+        for (int J = 0; J < s; ++J) items.push_back(make_int4(f, J, s, 0));
+      }
+    }
+    fs.step_start.push_back((int32_t)items.size());
+  }
+  if (fs.d_items) A.free(fs.d_items);
+  fs.d_items = dupload(A, items, st);
+}
+
+namespace {
+
 // Host metadata of a factor set for the given sizes; device arrays uploaded.
 void plan_factor_set(FactorSet& fs, const std::vector<int32_t>& sizes, int prec, int nb, int64_t xbase,
                      DeviceArena& A, hipStream_t st) {
@@ -92,39 +137,13 @@ void plan_factor_set(FactorSet& fs, const std::vector<int32_t>& sizes, int prec,
   fs.total_elems = o;
   fs.total_dinv = d;
   fs.total_x = x - xbase;
-  // work lists: forward step s -> (f, J >= s); backward step t -> (f, J <= nblk-1-t)
-  std::vector<int2> fwd, bwd;
-  fs.fwd_start.assign(1, 0);
-  fs.bwd_start.assign(1, 0);
-  for (int s = 0; s < fs.max_nblk; ++s) {
-    for (int f = 0; f < fs.count; ++f) {
-      if (s >= fs.nblk[f]) continue;
-      for (int J = s; J < fs.nblk[f]; ++J) {
-        if (s == 0 && J > 0) continue;  // nothing to update before the first block is solved
-        fwd.push_back(make_int2(f, J));
-      }
-    }
-    fs.fwd_start.push_back((int32_t)fwd.size());
-  }
-  for (int t = 0; t < fs.max_nblk; ++t) {
-    for (int f = 0; f < fs.count; ++f) {
-      const int s = fs.nblk[f] - 1 - t;
-      if (s < 0) continue;
-      for (int J = 0; J <= s; ++J) {
-        if (t == 0 && J < s) continue;
-        bwd.push_back(make_int2(f, J));
-      }
-    }
-    fs.bwd_start.push_back((int32_t)bwd.size());
-  }
   fs.d_n = dupload(A, fs.n, st);
   fs.d_npad = dupload(A, fs.npad, st);
   fs.d_nblk = dupload(A, fs.nblk, st);
   fs.d_off = dupload(A, fs.off, st);
   fs.d_doff = dupload(A, fs.doff, st);
   fs.d_xoff = dupload(A, fs.xoff, st);
-  fs.d_fwd = dupload(A, fwd, st);
-  fs.d_bwd = dupload(A, bwd, st);
+  plan_schedule(fs, 1, A, st);
 }
 
 struct PivotCheck {
@@ -220,7 +239,9 @@ void factor_set(Context& ctx, FactorSet& fs, uint64_t staging_cap, double pivot_
     ch.total_elems = (int64_t)(bytes / 8);
     ch.store = static_cast<char*>(fs.store) + (size_t)fs.off[f0] * es;
     ch.dinv = fs.dinv;
-    factor_finalize(ch, staging, st);
+    const int64_t dbase = fs.doff[f0];
+    ch.total_dinv = (f1 < fs.count ? fs.doff[f1] : fs.total_dinv) - dbase;
+    factor_finalize(ch, staging, dbase, st);
     GDSW_HIP(hipStreamSynchronize(st));
     A.free(mp);
     A.free(d_n);

@@ -151,7 +151,7 @@ void expand_solution(const Context& ctx, const double* xf, double* xfull, hipStr
 }
 
 FgmresResult fgmres(Context& ctx, const double* b, double* x, double rtol, int restart, int max_it, bool use_graph,
-                    hipStream_t st) {
+                    hipStream_t st, double* history, int history_len) {
   (void)use_graph;
   ensure_workspace(ctx, restart);
   const int64_t n = ctx.P.n_free;
@@ -204,6 +204,7 @@ FgmresResult fgmres(Context& ctx, const double* b, double* x, double rtol, int r
       GDSW_HIP(hipStreamSynchronize(st));
       const double rel = ctx.h_pinned[0];
       const double hn = ctx.h_pinned[1];
+      if (history && it < history_len) history[it] = rel;
       ++it;
       k = j + 1;
       res.rel = rel;

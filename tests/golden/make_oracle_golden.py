@@ -3,7 +3,7 @@
 Stored: FGMRES iteration count, residual history and the solution at sampled
 free DOFs; the preconditioner output z = B_GDSW r for r = random_vector(n, 1)
 at the same DOFs; and norms.  The GPU tests compare the library against these
-values.  Usage: python tests/golden/make_oracle_golden.py C2
+values.  Usage: python tests/golden/make_oracle_golden.py C2 [spread]
 """
 import json
 import os
@@ -25,6 +25,33 @@ from oracle.threelevel import ThreeLevelGDSW  # noqa: E402
 
 def sample_indices(n, k=2048):
     return np.unique(np.linspace(0, n - 1, k).astype(np.int64))
+
+
+def spread(name, k=10, eps=1e-14):
+    """Iteration counts of the oracle's FGMRES when the preconditioner output
+    and the SpMV output are perturbed entry-wise by relative noise of size eps
+    (the size of the rounding differences between two FP64 implementations).
+    Stored as oracle_<name>_spread.json."""
+    w = workload(name)
+    p = StokesProblem(w.n, viscosity=w.viscosity, inflow=w.inflow, manufactured=w.manufactured)
+    d = Decomposition(p, w.m, w.overlap)
+    M = ThreeLevelGDSW(p.A, d, w.group) if w.levels == 3 else TwoLevelGDSW(p.A, d)
+    counts = []
+    for seed in range(k):
+        rng = np.random.default_rng(100 + seed)
+
+        def noisy(v):
+            return v * (1.0 + eps * rng.standard_normal(v.size))
+
+        x, it, rel, trel = fgmres(lambda v: noisy(p.A @ v), lambda v: noisy(M(v)), p.b, rtol=w.rtol,
+                                  restart=w.restart, max_it=w.max_it)
+        counts.append(int(it))
+        print(f"seed {seed}: {it} iterations", flush=True)
+    out = {"workload": name, "eps": eps, "counts": counts, "min": min(counts), "max": max(counts)}
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"oracle_{name}_spread.json")
+    with open(path, "w") as f:
+        json.dump(out, f)
+    print("wrote", path)
 
 
 def main(name):
@@ -64,4 +91,7 @@ def main(name):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1] if len(sys.argv) > 1 else "C2")
+    if len(sys.argv) > 2 and sys.argv[2] == "spread":
+        spread(sys.argv[1])
+    else:
+        main(sys.argv[1] if len(sys.argv) > 1 else "C2")

@@ -151,3 +151,26 @@ def test_linearity_in_inflow_and_viscosity_scaling():
     xm, _, _ = res[(3.0, 1.0)]
     assert np.abs(xm[:nu] - x1[:nu]).max() < 1e-9 * np.abs(x1[:nu]).max()
     assert np.abs(xm[nu:] - 3.0 * x1[nu:]).max() < 1e-9 * 3 * np.abs(x1[nu:]).max()
+
+
+def test_coarse_lu_without_pivoting_is_valid(n6m3):
+    """The coarse factorisation reading: with velocity-type columns first, the
+    velocity block of A_0 is SPD and its Schur complement negative definite, so
+    LU without row exchanges exists; L U reproduces A_0 and the solve agrees
+    with LAPACK's pivoted solve to cond(A_0) * eps."""
+    import scipy.linalg as sla
+    from oracle.gdsw import lu_nopivot, lu_nopivot_solve, velocity_first
+    p, d, M = n6m3
+    order = velocity_first(d.coarse_field)
+    A0 = M.A0[np.ix_(order, order)]
+    nv = int((d.coarse_field < 3).sum())
+    K, Bt, C = A0[:nv, :nv], A0[:nv, nv:], A0[nv:, nv:]
+    assert np.linalg.eigvalsh(0.5 * (K + K.T)).min() > 0
+    S = C - Bt.T @ np.linalg.solve(K, Bt)
+    assert np.linalg.eigvalsh(0.5 * (S + S.T)).max() < 0
+    L, U, o = lu_nopivot(M.A0, order)
+    assert np.abs(L @ U - A0).max() < 1e-12 * np.abs(A0).max()
+    b = np.random.default_rng(7).standard_normal(d.n_coarse)
+    y = lu_nopivot_solve((L, U, o), b)
+    ref = sla.solve(M.A0, b)
+    assert np.linalg.norm(y - ref) / np.linalg.norm(ref) < np.linalg.cond(M.A0) * 1e-14
