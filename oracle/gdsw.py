@@ -16,12 +16,13 @@ Definitions followed, in the paper's notation:
   constant) restricted to interface entity e, i.e. 1 on e's f-DOFs.
 
 Local matrices are factored by LAPACK's dense LU with partial pivoting
-(``scipy.linalg.lu_factor``).  The coarse matrix is factored by plain LU
-without row exchanges after ordering the velocity-type coarse columns first
-(``lu_nopivot``): the paper names no coarse solver, and this is the textbook
-variant that exists for these saddle-point matrices (the velocity-type block
-of A_0 is SPD and its Schur complement negative definite, both pinned).  The
-FGMRES iteration count is sensitive to this choice.  The apply
+(``scipy.linalg.lu_factor``).  The interior blocks A_II of the extension and
+the coarse matrix are factored by plain LU without row exchanges with the
+velocity-type unknowns first (``lu_nopivot``): the paper names no direct
+solver, and this is the textbook variant that exists for these saddle-point
+matrices (the velocity-type block is SPD and its Schur complement negative
+definite, both pinned).  The FGMRES iteration count is sensitive to this
+choice.  The apply
 sums the local corrections in ascending subdomain order and adds the coarse
 correction last.
 
@@ -88,7 +89,9 @@ def coarse_basis(A, dec):
         used = np.nonzero(np.any(rhs != 0.0, axis=0))[0]
         if used.size == 0:
             continue
-        PhiI = -sla.solve(AII, rhs[:, used])
+        # I_i is in global order, i.e. velocity DOFs first
+        fac = lu_nopivot(AII, np.arange(Ii.size))
+        PhiI = -np.stack([lu_nopivot_solve(fac, rhs[:, k]) for k in used], 1)
         rr, cc = np.meshgrid(Ii, used, indexing="ij")
         rows.append(rr.ravel())
         cols.append(cc.ravel())

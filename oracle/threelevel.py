@@ -94,10 +94,11 @@ class ThreeLevelGDSW(TwoLevelGDSW):
         A0 = self.A0
         for j in range(self.n_subregions):
             Ij = self.I2[j]
-            if Ij.size == 0:
+            if Ij.size == 0 or self.n_coarse3 == 0:
                 continue
             rhs = A0[np.ix_(Ij, np.arange(Nc))] @ PhiG3
-            Phi3[Ij, :] = -sla.solve(A0[np.ix_(Ij, Ij)], rhs)
+            fac = lu_nopivot(A0[np.ix_(Ij, Ij)], velocity_first(c_field[Ij]))
+            Phi3[Ij, :] = -np.stack([lu_nopivot_solve(fac, rhs[:, k]) for k in range(rhs.shape[1])], 1)
         self.Phi3 = Phi3
         self.A03 = Phi3.T @ A0 @ Phi3
         f3 = np.zeros(self.n_coarse3, dtype=int)

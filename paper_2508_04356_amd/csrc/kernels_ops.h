@@ -52,6 +52,17 @@ void own_spmm(int nbox, int max_nd, const CoarseView& cv, const BoxView& bv, con
 void a0_assemble(int Nc, const CoarseView& cv, const double* P, const int64_t* p_off, double* A0, hipStream_t st);
 void permute_dense(int n, const int32_t* perm, const double* M, int64_t ldm, double* F, int64_t ld, hipStream_t st);
 void negate(int64_t n, double* x, hipStream_t st);
+// three levels (eq. 2.5) on the dense A_0 (row-major, Nc x Nc)
+void phi3_rhs(int64_t total_I, int Nc, const int32_t* I_sub, const int32_t* I_ptr, const int32_t* I_idx,
+              const int32_t* C_ptr, const int32_t* C_idx, const int64_t* off, const int32_t* gcol3, const double* A0,
+              double* B, hipStream_t st);
+void phi3_build(int64_t total_I, int Nc, const int32_t* I_sub, const int32_t* I_ptr, const int32_t* I_idx,
+                const int32_t* C_ptr, const int32_t* C_idx, const int64_t* off, const double* phiI,
+                const int32_t* gcol3, double* phi3, hipStream_t st);
+void dense_cols_dot(const double* M, int64_t ld, int nrows, int ncols, const double* v, double* out,
+                    const int32_t* pos, hipStream_t st);
+void scatter2(int Nc, const int32_t* inv_ptr, const int64_t* inv_pos, const double* w, const double* phi3, int Nc3,
+              const int32_t* y3_pos, double* y0, hipStream_t st);
 void expand(int64_t nfree, const int64_t* full_index, const double* xf, double* xfull, hipStream_t st);
 
 }  // namespace gdsw

@@ -261,6 +261,80 @@ __global__ void expand_kernel(int64_t nfree, const int64_t* __restrict__ full_in
     xfull[full_index[i]] = xf[i];
 }
 
+// ---- three-level kernels (dense A_0) ---------------------------------------
+
+// -(A_0[I_j, Gamma3] Phi_Gamma^(3)) for the level-3 extension, column-major
+__global__ void phi3_rhs_kernel(int64_t total_I, int Nc, const int32_t* __restrict__ I_sub,
+                                const int32_t* __restrict__ I_ptr, const int32_t* __restrict__ I_idx,
+                                const int32_t* __restrict__ C_ptr, const int32_t* __restrict__ C_idx,
+                                const int64_t* __restrict__ off, const int32_t* __restrict__ gcol3,
+                                const double* __restrict__ A0, double* __restrict__ B) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= total_I) return;
+  const int j = I_sub[p];
+  const int ib = I_ptr[j], ni = I_ptr[j + 1] - ib;
+  const int k = (int)(p - ib);
+  const int cb = C_ptr[j], nc = C_ptr[j + 1] - cb;
+  const int32_t c = I_idx[p];
+  double* Bj = B + off[j];
+  const double* row = A0 + (int64_t)c * Nc;
+  for (int cp = 0; cp < Nc; ++cp) {
+    const int32_t g = gcol3[cp];
+    if (g < 0) continue;
+    const int lc = lower_bound_i32(C_idx + cb, nc, g);
+    if (lc < nc && C_idx[cb + lc] == g) Bj[(int64_t)lc * ni + k] -= row[cp];
+  }
+}
+
+// dense Phi^(3) (column-major, ld = Nc): interior rows from the extension
+__global__ void phi3_interior_kernel(int64_t total_I, int Nc, const int32_t* __restrict__ I_sub,
+                                     const int32_t* __restrict__ I_ptr, const int32_t* __restrict__ I_idx,
+                                     const int32_t* __restrict__ C_ptr, const int32_t* __restrict__ C_idx,
+                                     const int64_t* __restrict__ off, const double* __restrict__ phiI,
+                                     double* __restrict__ phi3) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= total_I) return;
+  const int j = I_sub[p];
+  const int ib = I_ptr[j], ni = I_ptr[j + 1] - ib;
+  const int k = (int)(p - ib);
+  const int cb = C_ptr[j], nc = C_ptr[j + 1] - cb;
+  const int32_t c = I_idx[p];
+  for (int lc = 0; lc < nc; ++lc) phi3[(int64_t)C_idx[cb + lc] * Nc + c] = phiI[off[j] + (int64_t)lc * ni + k];
+}
+
+__global__ void phi3_gamma_kernel(int Nc, const int32_t* __restrict__ gcol3, double* __restrict__ phi3) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= Nc) return;
+  const int32_t g = gcol3[c];
+  if (g >= 0) phi3[(int64_t)g * Nc + c] = 1.0;
+}
+
+// out[pos[k]] = sum_c M[k * ld + c] v[c]   (one work-group per column)
+__global__ __launch_bounds__(256) void dense_cols_dot_kernel(const double* __restrict__ M, int64_t ld, int nrows,
+                                                            const double* __restrict__ v, double* __restrict__ out,
+                                                            const int32_t* __restrict__ pos) {
+  __shared__ double sh[256];
+  const int k = blockIdx.x;
+  const double* col = M + (int64_t)k * ld;
+  double s = 0.0;
+  for (int c = threadIdx.x; c < nrows; c += 256) s = fma(col[c], v[c], s);
+  const double t = block_sum<256>(s, sh);
+  if (threadIdx.x == 0) out[pos ? pos[k] : k] = t;
+}
+
+// y0[c] = sum of level-2 local copies (ascending subregion) + (Phi^(3) y3)[c]
+__global__ void scatter2_kernel(int Nc, const int32_t* __restrict__ inv_ptr, const int64_t* __restrict__ inv_pos,
+                                const double* __restrict__ w, const double* __restrict__ phi3, int Nc3,
+                                const int32_t* __restrict__ y3_pos, double* __restrict__ y0) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= Nc) return;
+  double s = 0.0;
+  for (int e = inv_ptr[c]; e < inv_ptr[c + 1]; ++e) s += w[inv_pos[e]];
+  double t = 0.0;
+  for (int k = 0; k < Nc3; ++k) t = fma(phi3[(int64_t)k * Nc + c], w[y3_pos[k]], t);
+  y0[c] = s + t;
+}
+
 // ---- Krylov helpers --------------------------------------------------------
 constexpr int DOT_CHUNK = 1024;  // rows per partial block
 
@@ -326,6 +400,36 @@ inline int grid_for(int64_t n, int bs = 256, int cap = 65536) {
 }
 
 }  // namespace
+
+void phi3_rhs(int64_t total_I, int Nc, const int32_t* I_sub, const int32_t* I_ptr, const int32_t* I_idx,
+              const int32_t* C_ptr, const int32_t* C_idx, const int64_t* off, const int32_t* gcol3, const double* A0,
+              double* B, hipStream_t st) {
+  if (total_I == 0) return;
+  phi3_rhs_kernel<<<(unsigned)((total_I + 63) / 64), 64, 0, st>>>(total_I, Nc, I_sub, I_ptr, I_idx, C_ptr, C_idx,
+                                                                  off, gcol3, A0, B);
+}
+
+void phi3_build(int64_t total_I, int Nc, const int32_t* I_sub, const int32_t* I_ptr, const int32_t* I_idx,
+                const int32_t* C_ptr, const int32_t* C_idx, const int64_t* off, const double* phiI,
+                const int32_t* gcol3, double* phi3, hipStream_t st) {
+  if (Nc == 0) return;
+  phi3_gamma_kernel<<<(Nc + 255) / 256, 256, 0, st>>>(Nc, gcol3, phi3);
+  if (total_I)
+    phi3_interior_kernel<<<(unsigned)((total_I + 127) / 128), 128, 0, st>>>(total_I, Nc, I_sub, I_ptr, I_idx, C_ptr,
+                                                                           C_idx, off, phiI, phi3);
+}
+
+void dense_cols_dot(const double* M, int64_t ld, int nrows, int ncols, const double* v, double* out,
+                    const int32_t* pos, hipStream_t st) {
+  if (ncols == 0) return;
+  dense_cols_dot_kernel<<<ncols, 256, 0, st>>>(M, ld, nrows, v, out, pos);
+}
+
+void scatter2(int Nc, const int32_t* inv_ptr, const int64_t* inv_pos, const double* w, const double* phi3, int Nc3,
+              const int32_t* y3_pos, double* y0, hipStream_t st) {
+  if (Nc == 0) return;
+  scatter2_kernel<<<(Nc + 255) / 256, 256, 0, st>>>(Nc, inv_ptr, inv_pos, w, phi3, Nc3, y3_pos, y0);
+}
 
 int cols_dot_blocks(int64_t n) { return (int)((n + DOT_CHUNK - 1) / DOT_CHUNK); }
 

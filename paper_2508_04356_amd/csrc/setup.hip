@@ -309,8 +309,28 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
   plan_factor_set(ctx.L1, l1_sizes, ctx.local_prec, nb, 0, A, st);
   ctx.n_w1 = ctx.L1.total_x;
   std::vector<int32_t> hi_sizes;
+  const Level2& L2 = P.lv2;
+  // level-2 index sets in factor order: velocity-type coarse DOFs first
+  std::vector<std::vector<int32_t>> S2(L2.n_sub), I2(L2.n_sub);
+  auto vfirst = [&](const std::vector<int32_t>& v) {
+    std::vector<int32_t> o;
+    for (int32_t c : v)
+      if (P.coarse_field[c] < 3) o.push_back(c);
+    for (int32_t c : v)
+      if (P.coarse_field[c] == 3) o.push_back(c);
+    return o;
+  };
   if (levels == 2 && !ctx.merged && Nc > 0) hi_sizes.push_back(Nc);
-  if (levels == 3) throw StatusError{6, "three-level setup is not built yet"};
+  if (levels == 3) {
+    ctx.n_sub2 = L2.n_sub;
+    ctx.Nc3 = L2.n_coarse3;
+    for (int j = 0; j < L2.n_sub; ++j) {
+      S2[j] = vfirst(L2.S[j]);
+      I2[j] = vfirst(L2.I[j]);
+      hi_sizes.push_back((int32_t)S2[j].size());
+    }
+    if (ctx.Nc3 > 0) hi_sizes.push_back(ctx.Nc3);
+  }
   plan_factor_set(ctx.HI, hi_sizes, P_FP64, nb, ctx.n_w1, A, st);
   ctx.n_w = ctx.n_w1 + ctx.HI.total_x;
   ctx.d_w = dalloc<double>(A, std::max<int64_t>(ctx.n_w, 1));
@@ -519,6 +539,113 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
       if (P.coarse_field[c] == 3) ctx.coarse_perm.push_back(c);
   }
 
+  // ---- three levels: Phi^(3) on A_0 (eq. 2.4 applied to A_0) and A_0^(3) ----
+  std::vector<int32_t> perm3;
+  if (levels == 3 && Nc > 0) {
+    const int Nc3 = ctx.Nc3;
+    std::vector<int32_t> i2_ptr, i2_idx, c3_ptr, c3_idx;
+    concat(I2, i2_ptr, i2_idx);
+    concat(L2.C, c3_ptr, c3_idx);
+    const int64_t total_I2 = i2_idx.size();
+    std::vector<int32_t> i2_sub(total_I2), ni2(L2.n_sub), nr2(L2.n_sub);
+    std::vector<int64_t> off2(L2.n_sub + 1, 0), aoff2(L2.n_sub);
+    int64_t atot = 0;
+    int max_ni2 = 0, max_nr2 = 0;
+    for (int j = 0; j < L2.n_sub; ++j) {
+      for (int32_t q = i2_ptr[j]; q < i2_ptr[j + 1]; ++q) i2_sub[q] = j;
+      ni2[j] = (int32_t)I2[j].size();
+      nr2[j] = (int32_t)L2.C[j].size();
+      off2[j + 1] = off2[j] + (int64_t)ni2[j] * nr2[j];
+      aoff2[j] = atot;
+      atot += (int64_t)ni2[j] * ni2[j];
+      max_ni2 = std::max(max_ni2, ni2[j]);
+      max_nr2 = std::max(max_nr2, nr2[j]);
+    }
+    int32_t* d_i2_ptr = dupload(A, i2_ptr, st);
+    int32_t* d_i2_idx = dupload(A, i2_idx, st);
+    int32_t* d_i2_sub = dupload(A, i2_sub, st);
+    int32_t* d_c3_ptr = dupload(A, c3_ptr, st);
+    int32_t* d_c3_idx = dupload(A, c3_idx, st);
+    int64_t* d_off2 = dupload(A, off2, st);
+    int64_t* d_aoff2 = dupload(A, aoff2, st);
+    int32_t* d_ni2 = dupload(A, ni2, st);
+    int32_t* d_nr2 = dupload(A, nr2, st);
+    int32_t* d_gcol3 = dupload(A, L2.gamma_col3, st);
+    double* aii = dalloc<double>(A, std::max<int64_t>(atot, 1));
+    double* phiI = dalloc<double>(A, std::max<int64_t>(off2.back(), 1));
+    GDSW_HIP(hipMemsetAsync(phiI, 0, std::max<int64_t>(off2.back(), 1) * 8, st));
+    DenseBatch B;
+    B.base = aii;
+    B.n = d_ni2;
+    B.ld = d_ni2;
+    B.off = d_aoff2;
+    B.count = L2.n_sub;
+    B.max_n = max_ni2;
+    extract_local_dense(B, d_i2_ptr, d_i2_idx, ctx.d_A0, Nc, max_ni2, st);
+    unsigned long long* mp = minpiv_buffer(A, L2.n_sub, st);
+    lu_nopiv(B, mp, st);
+    check_pivots(mp, L2.n_sub, 0.0, "level-2 interior block", st);
+    phi3_rhs(total_I2, Nc, d_i2_sub, d_i2_ptr, d_i2_idx, d_c3_ptr, d_c3_idx, d_off2, d_gcol3, ctx.d_A0, phiI, st);
+    lu_solve_multi(B, phiI, d_off2, d_nr2, max_nr2, st);
+    ctx.d_phi3 = dalloc<double>(A, std::max<int64_t>((int64_t)Nc * Nc3, 1));
+    GDSW_HIP(hipMemsetAsync(ctx.d_phi3, 0, std::max<int64_t>((int64_t)Nc * Nc3, 1) * 8, st));
+    phi3_build(total_I2, Nc, d_i2_sub, d_i2_ptr, d_i2_idx, d_c3_ptr, d_c3_idx, d_off2, phiI, d_gcol3, ctx.d_phi3,
+               st);
+    // A_0^(3) = Phi3^T (A_0 Phi3): A_0 is row-major, i.e. A_0^T column-major
+    double* T = dalloc<double>(A, std::max<int64_t>((int64_t)Nc * Nc3, 1));
+    ctx.d_A03 = dalloc<double>(A, std::max<int64_t>((int64_t)Nc3 * Nc3, 1));
+    std::vector<GemmDesc> gd = {GemmDesc{ctx.d_A0, ctx.d_phi3, T, Nc, Nc3, Nc, Nc, Nc, Nc, 1, 0}};
+    GemmDesc* d_gd = dupload(A, gd, st);
+    gemm_batched(d_gd, 1, Nc, Nc3, 1.0, 0.0, st);
+    std::vector<GemmDesc> gd2 = {GemmDesc{ctx.d_phi3, T, ctx.d_A03, Nc3, Nc3, Nc, Nc, Nc, Nc3, 1, 0}};
+    GemmDesc* d_gd2 = dupload(A, gd2, st);
+    gemm_batched(d_gd2, 1, Nc3, Nc3, 1.0, 0.0, st);
+    GDSW_HIP(hipStreamSynchronize(st));
+    for (void* q : {(void*)d_i2_ptr, (void*)d_i2_idx, (void*)d_i2_sub, (void*)d_c3_ptr, (void*)d_c3_idx,
+                    (void*)d_off2, (void*)d_aoff2, (void*)d_ni2, (void*)d_nr2, (void*)d_gcol3, (void*)aii,
+                    (void*)phiI, (void*)T, (void*)d_gd, (void*)d_gd2, (void*)mp})
+      A.free(q);
+    // level-3 factor order: velocity-type columns first
+    std::vector<int32_t> f3(Nc3, 0);
+    for (int c = 0; c < Nc; ++c)
+      if (L2.gamma_col3[c] >= 0) f3[L2.gamma_col3[c]] = P.coarse_field[c];
+    for (int k = 0; k < Nc3; ++k)
+      if (f3[k] < 3) perm3.push_back(k);
+    for (int k = 0; k < Nc3; ++k)
+      if (f3[k] == 3) perm3.push_back(k);
+    // work-vector maps of the level-2 copies and the level-3 segment
+    const int64_t hx = ctx.HI.total_x;
+    std::vector<int32_t> g2(hx, -1), cnt(Nc + 1, 0);
+    for (int j = 0; j < L2.n_sub; ++j) {
+      const int64_t xo = ctx.HI.xoff[j] - ctx.n_w1;
+      for (size_t k = 0; k < S2[j].size(); ++k) {
+        g2[xo + k] = S2[j][k];
+        cnt[S2[j][k] + 1]++;
+      }
+    }
+    std::vector<int32_t> inv2_ptr(Nc + 1, 0);
+    for (int c = 0; c < Nc; ++c) inv2_ptr[c + 1] = inv2_ptr[c] + cnt[c + 1];
+    std::vector<int64_t> inv2_pos(inv2_ptr[Nc]);
+    std::vector<int32_t> fill(Nc, 0);
+    // ascending subregion index: for each c, positions in increasing j
+    for (int j = 0; j < L2.n_sub; ++j)
+      for (size_t k = 0; k < S2[j].size(); ++k) {
+        const int32_t c = S2[j][k];
+        inv2_pos[inv2_ptr[c] + fill[c]++] = ctx.HI.xoff[j] + (int64_t)k;
+      }
+    ctx.d_g2idx = dupload(A, g2, st);
+    ctx.d_inv2_ptr = dupload(A, inv2_ptr, st);
+    ctx.d_inv2_pos = dupload(A, inv2_pos, st);
+    std::vector<int32_t> p3(Nc3);
+    if (Nc3 > 0) {
+      const int64_t x3 = ctx.HI.xoff[L2.n_sub];
+      for (int q = 0; q < Nc3; ++q) p3[perm3[q]] = (int32_t)(x3 + q);
+    }
+    ctx.d_c3_pinv = dupload(A, p3, st);
+    ctx.d_r0 = dalloc<double>(A, Nc);
+    ctx.d_y0 = dalloc<double>(A, Nc);
+  }
+
   // ---- level-1 local factors (and the coarse factor when merged) -----------
   std::vector<int32_t> S_ptr, S_idx;
   concat(P.S, S_ptr, S_idx);
@@ -544,15 +671,40 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
                  (void)fc;
                }
              });
-  if (!ctx.merged && ctx.HI.count > 0) {
+  if (!ctx.merged && ctx.HI.count > 0 && levels == 2) {
     factor_set(ctx, ctx.HI, staging_cap, 0.0, "coarse factor", st, [&](DenseBatch& B, int, int) {
       permute_dense(Nc, d_perm, ctx.d_A0, Nc, B.base, ctx.HI.npad[0], st);
     });
   }
+  if (levels == 3 && ctx.HI.count > 0) {
+    std::vector<int32_t> s2_ptr, s2_idx;
+    concat(S2, s2_ptr, s2_idx);
+    int32_t* d_s2_ptr = dupload(A, s2_ptr, st);
+    int32_t* d_s2_idx = dupload(A, s2_idx, st);
+    int32_t* d_perm3 = dupload(A, perm3, st);
+    factor_set(ctx, ctx.HI, staging_cap, 0.0, "level-2/3 factor", st, [&](DenseBatch& B, int f0, int f1) {
+      const int nloc = std::min(f1, ctx.n_sub2) - f0;
+      if (nloc > 0) {
+        DenseBatch Bl = B;
+        Bl.count = nloc;
+        int mx = 0;
+        for (int f = f0; f < f0 + nloc; ++f) mx = std::max(mx, (int)S2[f].size());
+        Bl.max_n = mx;
+        extract_local_dense(Bl, d_s2_ptr + f0, d_s2_idx, ctx.d_A0, ctx.Nc, mx, st);
+      }
+      if (ctx.Nc3 > 0 && f1 == ctx.HI.count) {
+        double* dst = B.base + (ctx.HI.off[ctx.HI.count - 1] - ctx.HI.off[f0]);
+        permute_dense(ctx.Nc3, d_perm3, ctx.d_A03, ctx.Nc3, dst, ctx.HI.npad[ctx.HI.count - 1], st);
+      }
+    });
+    A.free(d_s2_ptr);
+    A.free(d_s2_idx);
+    A.free(d_perm3);
+  }
   A.free(d_S_ptr);
   A.free(d_S_idx);
-  // coarse column -> work-vector position
-  if (Nc > 0) {
+  // coarse column -> work-vector position (two levels)
+  if (Nc > 0 && levels == 2) {
     const FactorSet& cs = ctx.merged ? ctx.L1 : ctx.HI;
     const int fc = ctx.merged ? ctx.L1.count - 1 : 0;
     ctx.coarse_xoff = cs.xoff[fc];

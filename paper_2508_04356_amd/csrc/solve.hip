@@ -128,15 +128,27 @@ void spmv(Context& ctx, const double* x, double* y, hipStream_t st) {
 
 void apply_precond(Context& ctx, const double* r, double* z, hipStream_t st, hipEvent_t* ev) {
   const CoarseView cv = coarse_view(ctx);
+  const bool three = ctx.P.spec.levels == 3 && ctx.Nc > 0;
   if (ev) GDSW_HIP(hipEventRecord(ev[0], st));
   gather(ctx.n_w1, ctx.d_gidx, r, ctx.d_w, st);
-  if (ctx.Nc > 0) restrict_coarse(ctx.Nc, cv, r, ctx.d_w, ctx.d_coarse_pinv, st);
+  if (three) {
+    // r0 = Phi^T r; level-2 copies R_j^(2) r0; level-3 right-hand side Phi3^T r0
+    restrict_coarse(ctx.Nc, cv, r, ctx.d_r0, nullptr, st);
+    gather(ctx.HI.total_x, ctx.d_g2idx, ctx.d_r0, ctx.d_w + ctx.n_w1, st);
+    dense_cols_dot(ctx.d_phi3, ctx.Nc, ctx.Nc, ctx.Nc3, ctx.d_r0, ctx.d_w, ctx.d_c3_pinv, st);
+  } else if (ctx.Nc > 0) {
+    restrict_coarse(ctx.Nc, cv, r, ctx.d_w, ctx.d_coarse_pinv, st);
+  }
   if (ev) GDSW_HIP(hipEventRecord(ev[1], st));
   trsv_set(ctx.L1, ctx.d_w, st);
   if (ev) GDSW_HIP(hipEventRecord(ev[2], st));
   trsv_set(ctx.HI, ctx.d_w, st);
   if (ev) GDSW_HIP(hipEventRecord(ev[3], st));
-  if (ctx.Nc > 0)
+  if (three) {
+    // y0 = sum_j R_j^(2)T y_j + Phi3 y3, then z = sum_i R_i^T y_i + Phi y0
+    scatter2(ctx.Nc, ctx.d_inv2_ptr, ctx.d_inv2_pos, ctx.d_w, ctx.d_phi3, ctx.Nc3, ctx.d_c3_pinv, ctx.d_y0, st);
+    scatter_prolong(ctx.P.n_free, ctx.d_inv_ptr, ctx.d_inv_pos, ctx.d_w, cv, ctx.d_y0, nullptr, z, st);
+  } else if (ctx.Nc > 0)
     scatter_prolong(ctx.P.n_free, ctx.d_inv_ptr, ctx.d_inv_pos, ctx.d_w, cv, nullptr, ctx.d_coarse_pinv, z, st);
   else
     deterministic_scatter(ctx.P.n_free, ctx.d_inv_ptr, ctx.d_inv_pos, ctx.d_w, z, st);

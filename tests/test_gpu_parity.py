@@ -118,6 +118,24 @@ def test_fgmres_parity(w):
     s.close()
 
 
+@pytest.mark.parametrize("restart", [7, 10])
+def test_fgmres_restarted_parity(restart):
+    """Short restart cycles: the cycle bookkeeping (true residual, new basis)
+    must reproduce the oracle's iteration count."""
+    w = workload("C1")
+    p, d, M = oracle_case(w)
+    xo, ito, _, _ = oracle_fgmres(lambda v: p.A @ v, M, p.b, rtol=1e-8, restart=restart)
+    s = gpu_case(w)
+    b = torch.zeros(p.n_free, dtype=torch.float64, device=DEV)
+    s.rhs(b)
+    x = torch.zeros_like(b)
+    info = s.fgmres(b, x, rtol=1e-8, restart=restart)[0]
+    print(f"[gpu] restart {restart}: it {info.iterations} oracle {ito} restarts {info.restarts}", flush=True)
+    assert info.iterations == ito and info.restarts >= 1
+    assert np.linalg.norm(host(x) - xo) / np.linalg.norm(xo) < 1e-8
+    s.close()
+
+
 def test_fgmres_tight_tolerance_solution():
     """rtol 1e-13: the GPU solution matches the oracle's to 1e-10.  This
     tolerance sits at the attainable-accuracy floor of FP64 for this operator,
