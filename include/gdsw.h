@@ -75,9 +75,9 @@ typedef struct {
 /* Decomposition, overlap and levels (Section 2.1 and 2.2). */
 typedef struct {
   int32_t subdomains;         /* m subdomains per axis (N = m^3), n % m == 0 */
-  int32_t overlap;            /* delta >= 1 element layers; the overlapping set
-                                 of subdomain i holds the free DOFs of every
-                                 node of its closed box grown by delta */
+  int32_t overlap;            /* delta >= 1 element layers: the overlapping set
+                                 of subdomain i is its closed box grown by
+                                 delta (see local_algebraic) */
   int32_t levels;             /* 2: eq. (2.2);  3: eq. (2.5) */
   int32_t group;              /* levels == 3: subdomains per subregion per axis,
                                  m % group == 0 (N^(2) = (m/group)^3) */
@@ -85,6 +85,18 @@ typedef struct {
                                  (the coarse levels are always FP64) */
   int32_t tile;               /* triangular-solve tile size: 0 = default,
                                  else 64 or 128 */
+  int32_t local_algebraic;    /* 0 (default): nodes on the artificial boundary
+                                 of the grown box (the faces inside the cube)
+                                 are left out for velocity and pressure, i.e.
+                                 homogeneous Dirichlet conditions for both on
+                                 the local problem (Section 2.1);
+                                 1: every node of the grown box (algebraic
+                                 overlap, one graph layer for delta = 1) */
+  int32_t level2_layer;       /* levels == 3.  0 (default): the level-2 local
+                                 set of a subregion holds the coarse DOFs of
+                                 its subdomains (neighbouring subregions share
+                                 their interface entities); 1: plus one layer
+                                 of the A_0 graph */
   uint64_t device_mem_budget; /* bytes the setup may allocate; 0 = the free
                                  device memory reported by HIP */
 } gdsw_decomposition;

@@ -32,6 +32,8 @@ class Workload:
     max_it: int = 1000
     precision: str = "fp64"   # local factor storage: fp64 | fp32 | bf16
     nrhs: int = 1
+    local_algebraic: int = 0  # 1: algebraic overlap instead of Dirichlet u, p on the artificial boundary
+    level2_layer: int = 0     # 1: level-2 local sets get one more A_0-graph layer
     note: str = ""
 
     def with_(self, **kw) -> "Workload":
@@ -43,6 +45,8 @@ WORKLOADS: Dict[str, Workload] = {
     "C1": Workload("C1", n=4, m=2),
     # 16^3 mesh, 4^3 subdomains of 4^3 elements, FP64 dense local LU.
     "C2": Workload("C2", n=16, m=4),
+    # the 16^3 workload with the algebraic overlap reading of the local problems
+    "C2alg": Workload("C2alg", n=16, m=4, local_algebraic=1),
     # 24^3 mesh, 6^3 subdomains; 32 right-hand sides with amplitudes ~U[0.5, 2].
     "C3": Workload("C3", n=24, m=6, nrhs=32, precision="fp32"),
     # 32^3 mesh, 8^3 subdomains, three levels with 2^3 grouping, FP32 level-1 factors.
@@ -91,4 +95,6 @@ def small_parity_cases() -> List[Workload]:
         Workload("n8m2", n=8, m=2),
         Workload("n8m4", n=8, m=4),
         Workload("n9m3", n=9, m=3, viscosity=0.37, inflow=1.3),
+        Workload("n8m4alg", n=8, m=4, local_algebraic=1),
+        Workload("n9m3alg", n=9, m=3, viscosity=0.37, inflow=1.3, local_algebraic=1),
     ]

@@ -11,9 +11,14 @@ Readings (pinned by ``tests/test_oracle_decomposition.py``):
 
 * Subdomain (I, J, K) is the closed element box [I s, (I+1) s] x ... with
   s = n / m, numbered I + m (J + m K).
-* Overlap delta = element layers: S_i holds the free DOFs of every node of
-  the closed box grown by delta elements and clipped to the cube.  For
-  delta = 1 this is one layer of matrix-graph neighbours of the closed box.
+* Overlap delta = element layers around the closed box, clipped to the cube.
+  Default (``local_dirichlet``): S_i holds the free DOFs of the grown box
+  except the nodes on its faces inside the cube, for velocity and pressure
+  alike, so the local problem carries homogeneous Dirichlet conditions for
+  both fields on its artificial boundary, which is how Section 2.1 explains
+  why the local problems are invertible.  Alternative (``local_dirichlet=
+  False``): every node of the grown box, i.e. one layer of matrix-graph
+  neighbours of the closed box for delta = 1 (algebraic overlap).
 * Gamma holds the free DOFs whose node lies in at least two closed boxes
   (nodes on the outer boundary that belong to one box are not interface).
 * An entity is a class of Gamma nodes with the same set of subdomains; a
@@ -42,7 +47,7 @@ def box_range_1d(coord, s, m):
 class Decomposition:
     """Structured m^3 decomposition of a ``StokesProblem``."""
 
-    def __init__(self, prob, m, overlap=1):
+    def __init__(self, prob, m, overlap=1, local_dirichlet=True):
         n = prob.n
         if n % m != 0:
             raise ValueError("n must be a multiple of m")
@@ -77,6 +82,9 @@ class Decomposition:
                     inside_closed = np.all((abc >= 2 * s * ijk) & (abc <= 2 * s * (ijk + 1)), axis=1)
                     lo_o = 2 * (s * ijk - overlap)
                     hi_o = 2 * (s * (ijk + 1) + overlap)
+                    if local_dirichlet:
+                        lo_o = np.where(lo_o > 0, lo_o + 1, lo_o)
+                        hi_o = np.where(hi_o < 2 * n, hi_o - 1, hi_o)
                     inside_ovl = np.all((abc >= lo_o) & (abc <= hi_o), axis=1)
                     self.S.append(np.nonzero(inside_ovl)[0])
                     self.box.append(np.nonzero(inside_closed)[0])

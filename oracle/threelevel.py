@@ -15,9 +15,11 @@ pinned by ``tests/test_oracle_threelevel.py``):
 * Subregion j is a group^3 block of subdomains (j = X + M (Y + M Z), M = m /
   group).  A level-2 coarse DOF belongs to every subregion that holds a
   subdomain of its entity.
-* Level-2 overlap: the coarse DOFs of subregion j plus one layer of the A_0
-  graph, i.e. every coarse DOF whose entity shares a subdomain with an entity
-  of subregion j (this is A_0's structural coupling).
+* Level-2 local set of subregion j (default): the coarse DOFs of the
+  subregion, i.e. of every entity that touches one of its subdomains;
+  neighbouring subregions share their interface entities.  Alternative
+  (``level2_layer``): plus one layer of the A_0 graph, every coarse DOF
+  whose entity shares a subdomain with an entity of the subregion.
 * Level-3 interface: coarse DOFs that belong to at least two subregions,
   classed by their subregion set; the level-3 null space is the indicator of
   one field (u_x, u_y, u_z or p) on a class.  Level-3 entities are ordered by
@@ -37,7 +39,7 @@ from .gdsw import TwoLevelGDSW, lu_nopivot, lu_nopivot_solve, velocity_first
 
 
 class ThreeLevelGDSW(TwoLevelGDSW):
-    def __init__(self, A, dec, group, factor_local=True):
+    def __init__(self, A, dec, group, factor_local=True, level2_layer=False):
         super().__init__(A, dec, factor_local=factor_local)
         m = dec.m
         if m % group != 0:
@@ -66,7 +68,7 @@ class ThreeLevelGDSW(TwoLevelGDSW):
             Tj = set()
             for c in Cj:
                 Tj |= c_subs[c]
-            Sj = [c for c in range(Nc) if c_subs[c] & Tj]
+            Sj = [c for c in range(Nc) if c_subs[c] & Tj] if level2_layer else Cj
             self.S2.append(np.array(sorted(Sj), dtype=np.int64))
             self.I2.append(np.array([c for c in range(Nc) if c_regions[c] == (j,)],
                                     dtype=np.int64))

@@ -36,7 +36,8 @@ class Mesh(C.Structure):
 
 class Decomposition(C.Structure):
     _fields_ = [("subdomains", C.c_int32), ("overlap", C.c_int32), ("levels", C.c_int32), ("group", C.c_int32),
-                ("local_precision", C.c_int32), ("tile", C.c_int32), ("device_mem_budget", C.c_uint64)]
+                ("local_precision", C.c_int32), ("tile", C.c_int32), ("local_algebraic", C.c_int32),
+                ("level2_layer", C.c_int32), ("device_mem_budget", C.c_uint64)]
 
 
 class FgmresOpts(C.Structure):
@@ -122,11 +123,13 @@ class Solver:
     """One Stokes problem with its GDSW preconditioner (a gdsw_ctx)."""
 
     def __init__(self, n, m, overlap=1, levels=2, group=2, precision="fp64", tile=0, viscosity=1.0,
-                 inflow=16.0, manufactured=0, budget=0, host_only=False, stream=None):
+                 inflow=16.0, manufactured=0, budget=0, host_only=False, stream=None, local_algebraic=0,
+                 level2_layer=0):
         self._ctx = C.c_void_p()
         self.mesh = Mesh(n, manufactured, viscosity, inflow)
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-        self.dec = Decomposition(m, overlap, levels, group, prec, tile, budget)
+        self.dec = Decomposition(m, overlap, levels, group, prec, tile, int(local_algebraic), int(level2_layer),
+                                 budget)
         if host_only:
             st = _lib.gdsw_setup_host(C.byref(self.mesh), C.byref(self.dec), C.byref(self._ctx))
         else:

@@ -61,6 +61,8 @@ ProblemSpec spec_of(const gdsw_mesh* mesh, const gdsw_decomposition* dec) {
   s.overlap = dec->overlap;
   s.levels = dec->levels;
   s.group = dec->group;
+  s.local_dirichlet = dec->local_algebraic == 0;
+  s.level2_layer = dec->level2_layer != 0;
   if (dec->local_precision < 0 || dec->local_precision > 2) throw std::invalid_argument("bad local_precision");
   if (dec->tile != 0 && dec->tile != 64 && dec->tile != 128) throw std::invalid_argument("tile must be 0, 64 or 128");
   return s;

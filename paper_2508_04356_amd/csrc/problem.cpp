@@ -294,7 +294,14 @@ void build_problem(const ProblemSpec& spec, Problem& P, int threads) {
         const int i = I + m * (J + m * K);
         auto lo = [&](int X) { return std::max(0, 2 * (X * s - dl)); };
         auto hi = [&](int X) { return std::min(2 * n, 2 * ((X + 1) * s + dl)); };
-        collect_box(lo(I), hi(I), lo(J), hi(J), lo(K), hi(K), P.S[i]);
+        if (spec.local_dirichlet) {
+          // leave out the faces of the grown box that lie inside the cube
+          auto lo_d = [&](int X) { return lo(X) > 0 ? lo(X) + 1 : 0; };
+          auto hi_d = [&](int X) { return hi(X) < 2 * n ? hi(X) - 1 : 2 * n; };
+          collect_box(lo_d(I), hi_d(I), lo_d(J), hi_d(J), lo_d(K), hi_d(K), P.S[i]);
+        } else {
+          collect_box(lo(I), hi(I), lo(J), hi(J), lo(K), hi(K), P.S[i]);
+        }
         collect_box(2 * I * s, 2 * (I + 1) * s, 2 * J * s, 2 * (J + 1) * s, 2 * K * s, 2 * (K + 1) * s, P.D[i]);
         P.I[i].clear();
         for (int32_t d : P.D[i])
@@ -382,8 +389,12 @@ void build_problem(const ProblemSpec& spec, Problem& P, int threads) {
               for (int32_t i : entity_subdomains(P, P.coarse_entity[c])) touched[i] = 1;
           for (int c = 0; c < Nc; ++c) {
             bool hit = false;
-            for (int32_t i : entity_subdomains(P, P.coarse_entity[c]))
-              if (touched[i]) { hit = true; break; }
+            if (spec.level2_layer) {
+              for (int32_t i : entity_subdomains(P, P.coarse_entity[c]))
+                if (touched[i]) { hit = true; break; }
+            } else {
+              hit = in_box(rkey[c], X, Y, Z);
+            }
             if (hit) L.S[j].push_back(c);
             const auto& k = rkey[c];
             if (k[0] == X && k[3] == X && k[1] == Y && k[4] == Y && k[2] == Z && k[5] == Z) L.I[j].push_back(c);

@@ -21,6 +21,8 @@ struct ProblemSpec {
   double mu = 1.0;
   double c = 16.0;
   int manufactured = 0;
+  int local_dirichlet = 1;  // 1: drop the artificial boundary of the grown box
+  int level2_layer = 0;     // 1: level-2 local sets get one more A_0-graph layer
 };
 
 // Level-2 (coarse) structures for the three-level method (eq. 2.5).

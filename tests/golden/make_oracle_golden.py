@@ -34,8 +34,9 @@ def spread(name, k=10, eps=1e-14):
     Stored as oracle_<name>_spread.json."""
     w = workload(name)
     p = StokesProblem(w.n, viscosity=w.viscosity, inflow=w.inflow, manufactured=w.manufactured)
-    d = Decomposition(p, w.m, w.overlap)
-    M = ThreeLevelGDSW(p.A, d, w.group) if w.levels == 3 else TwoLevelGDSW(p.A, d)
+    d = Decomposition(p, w.m, w.overlap, local_dirichlet=not w.local_algebraic)
+    M = (ThreeLevelGDSW(p.A, d, w.group, level2_layer=bool(w.level2_layer)) if w.levels == 3
+         else TwoLevelGDSW(p.A, d))
     counts = []
     for seed in range(k):
         rng = np.random.default_rng(100 + seed)
@@ -58,9 +59,9 @@ def main(name):
     w = workload(name)
     t0 = time.time()
     p = StokesProblem(w.n, viscosity=w.viscosity, inflow=w.inflow, manufactured=w.manufactured)
-    d = Decomposition(p, w.m, w.overlap)
+    d = Decomposition(p, w.m, w.overlap, local_dirichlet=not w.local_algebraic)
     if w.levels == 3:
-        M = ThreeLevelGDSW(p.A, d, w.group)
+        M = ThreeLevelGDSW(p.A, d, w.group, level2_layer=bool(w.level2_layer))
     else:
         M = TwoLevelGDSW(p.A, d)
     t1 = time.time()

@@ -52,10 +52,14 @@ def test_host_assembly_matches_oracle(n, m, mu, c, man):
 
 
 def test_host_sizes_at_16_cubed():
-    s = G.Solver(16, 4, host_only=True)
+    s = G.Solver(16, 4, host_only=True, local_algebraic=1)
     sz = s.sizes()
     assert sz.n_free == 97169 and sz.n_sub == 64 and sz.n_coarse == 1116
     assert sz.local_min == 3216 and sz.local_max == 6934
+    s.close()
+    s = G.Solver(16, 4, host_only=True)
+    sz = s.sizes()
+    assert sz.local_min == 2312 and sz.local_max == 4118
     s.close()
 
 
@@ -85,4 +89,14 @@ def test_device_calls_rejected_on_host_context():
         s.spmv(1, 2)
     with pytest.raises(G.GdswError):
         s.local_indices(99)
+    s.close()
+
+
+@pytest.mark.parametrize("alg", [0, 1])
+def test_host_local_sets_match_oracle(alg):
+    s = G.Solver(8, 4, host_only=True, local_algebraic=alg)
+    p = StokesProblem(8)
+    d = Decomposition(p, 4, 1, local_dirichlet=not alg)
+    for i in range(d.n_sub):
+        assert np.array_equal(s.local_indices(i), d.S[i])
     s.close()

@@ -38,12 +38,13 @@ CASES3 = [(8, 4, 2, 1.0, 16.0, 100), (12, 6, 3, 1.0, 16.0, 200), (8, 4, 2, 0.5, 
 
 
 @pytest.mark.parametrize("n,m,g,mu,c,restart", CASES3, ids=lambda v: str(v))
-def test_three_level_apply_and_fgmres_parity(n, m, g, mu, c, restart):
+@pytest.mark.parametrize("layer", [0, 1])
+def test_three_level_apply_and_fgmres_parity(n, m, g, mu, c, restart, layer):
     p = StokesProblem(n, viscosity=mu, inflow=c)
     d = Decomposition(p, m, 1)
-    M = ThreeLevelGDSW(p.A, d, g)
-    print(f"[gpu] three-level n={n} m={m} group={g}", flush=True)
-    s = G.Solver(n, m, levels=3, group=g, viscosity=mu, inflow=c)
+    M = ThreeLevelGDSW(p.A, d, g, level2_layer=bool(layer))
+    print(f"[gpu] three-level n={n} m={m} group={g} level2_layer={layer}", flush=True)
+    s = G.Solver(n, m, levels=3, group=g, viscosity=mu, inflow=c, level2_layer=layer)
     sz = s.sizes()
     assert sz.n_subregions == M.n_subregions and sz.n_coarse3 == M.n_coarse3
     assert rel_max(s.coarse_matrix(), M.A0) < 1e-12
@@ -69,14 +70,15 @@ def test_three_level_apply_and_fgmres_parity(n, m, g, mu, c, restart):
 
 
 def test_three_level_long_run():
-    """27 subregions of 2^3 subdomains: about 170 iterations without restart.
+    """27 subregions of 2^3 subdomains with the algebraic readings on both
+    levels: about 170 iterations without restart.
     The apply agrees element-wise; over that many steps the count may drift by
     a few iterations with the rounding of the Krylov process (bound: 3%)."""
     n, m, g = 12, 6, 2
     p = StokesProblem(n, viscosity=0.5, inflow=2.0)
-    d = Decomposition(p, m, 1)
-    M = ThreeLevelGDSW(p.A, d, g)
-    s = G.Solver(n, m, levels=3, group=g, viscosity=0.5, inflow=2.0)
+    d = Decomposition(p, m, 1, local_dirichlet=False)
+    M = ThreeLevelGDSW(p.A, d, g, level2_layer=True)
+    s = G.Solver(n, m, levels=3, group=g, viscosity=0.5, inflow=2.0, local_algebraic=1, level2_layer=1)
     r = random_vector(p.n_free, seed=1)
     z = torch.zeros(p.n_free, dtype=torch.float64, device=DEV)
     s.apply(dev(r), z)

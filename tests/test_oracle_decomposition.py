@@ -47,10 +47,10 @@ def test_partition_and_interface():
 
 
 def test_overlap_is_one_graph_layer():
-    """S_i (closed box grown by one element) = closed box plus its neighbours in
-    the sparsity graph of A."""
+    """Algebraic reading: S_i (closed box grown by one element) = closed box
+    plus its neighbours in the sparsity graph of A."""
     p = StokesProblem(6)
-    d = Decomposition(p, 3, 1)
+    d = Decomposition(p, 3, 1, local_dirichlet=False)
     A = p.A.tocsr()
     for i in (0, 4, 13, 26):
         box = d.box[i]
@@ -60,15 +60,41 @@ def test_overlap_is_one_graph_layer():
 
 def test_local_sizes():
     p = StokesProblem(4)
-    d = Decomposition(p, 2, 1)
+    d = Decomposition(p, 2, 1, local_dirichlet=False)
     sz = d.local_sizes()
     assert sz.min() == 712 and sz.max() == 820
     # 16^3 mesh, 4^3 subdomains: corner box grows inward only, interior by one layer
     p = StokesProblem(16)
-    d = Decomposition(p, 4, 1)
+    dd = Decomposition(p, 4, 1)                    # Dirichlet reading (default)
+    szd = dd.local_sizes()
+    assert szd.min() == 3 * 9 ** 3 + 5 ** 3 == 2312 and szd.max() == 4118
+    d = Decomposition(p, 4, 1, local_dirichlet=False)
     sz = d.local_sizes()
     assert sz.max() == 3 * 13 ** 3 + 7 ** 3 == 6934
     assert sz.min() == 3 * 10 ** 3 + 6 ** 3 == 3216
     assert int((sz.astype(np.int64) ** 2).sum()) * 8 == 13037206048
     isz = [len(I) for I in d.I]
     assert min(isz) == 1056 and max(isz) == 1240
+
+
+def test_local_dirichlet_sets_and_conditioning():
+    """Dirichlet reading of the local problems: the nodes on the faces of the
+    grown box inside the cube are left out for u and p.  Sizes follow from the
+    node counts (interior 16^3 subdomain: 11 Q2 and 5 Q1 nodes per axis), and
+    the local matrix loses the nearly singular pressure-constant mode of the
+    algebraic reading."""
+    p = StokesProblem(16)
+    d = Decomposition(p, 4, 1, local_dirichlet=True)
+    sz = d.local_sizes()
+    assert sz.max() == 3 * 11 ** 3 + 5 ** 3 == 4118
+    assert int((sz.astype(np.int64) ** 2).sum()) * 8 == 5372506496
+    from oracle.gdsw import TwoLevelGDSW
+    p8 = StokesProblem(8)
+    conds = {}
+    for ld in (False, True):
+        dd = Decomposition(p8, 4, 1, local_dirichlet=ld)
+        i = 21                                    # an interior subdomain
+        Ai = p8.A[dd.S[i]][:, dd.S[i]].toarray()
+        s = np.linalg.svd(Ai, compute_uv=False)
+        conds[ld] = s[0] / s[-1]
+    assert conds[True] * 10 < conds[False]
