@@ -72,6 +72,22 @@ def cpu_baseline(w, sample_subdomains=8, repeats=5):
                       f"factorisation untimed"}
 
 
+def measured_traffic(launches):
+    """HBM bytes per launch of the triangular solves from the committed counter
+    summary, or None when the kernel source changed since it was measured."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "trsv_step_kernel_16cubed_traffic.txt")
+    src = os.path.join(ROOT, "paper_2508_04356_amd", "csrc", "kernels_factor.hip")
+    if not os.path.exists(path):
+        return None
+    kv = dict(line.split(": ", 1) for line in open(path).read().splitlines() if ": " in line)
+    if kv.get("kernel_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    if int(kv.get("launches_per_apply", -1)) != launches:
+        return None
+    return (float(kv["fetch_bytes_per_apply"]) + float(kv["write_bytes_per_apply"])) / launches
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,7 +100,18 @@ def main():
                     help="1: algebraic overlap instead of Dirichlet u, p on the artificial boundary")
     ap.add_argument("--applies", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy a 1 GiB buffer three times (reference for HBM counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_direction": src.numel() * 4, "copies": 3}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(the multi-GPU sharding is described in DESIGN.md, not built)"}))
@@ -175,9 +202,12 @@ def main():
         "apply_phases_ms": {"gather_restrict": ph[0], "trsv_l1": ph[1], "trsv_coarse": ph[2], "scatter": ph[3]},
         "setup_s": t_setup,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "trsv_fwd_kernel + trsv_bwd_kernel (blocked triangular solves of every factor)",
-                     "bytes_per_apply": solve_bytes, "launches_per_apply": launches},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(launches) if args.workload == "C2" and not alg else None,
+                     "kernel": "trsv_step_kernel (blocked forward/backward solves of every factor)",
+                     "bytes_per_apply": solve_bytes, "launches_per_apply": launches,
+                     "bytes_per_launch": solve_bytes / launches,
+                     "avg_launch_us": t_trsv_ms * 1e3 / launches},
     }
     if not args.no_cpu_baseline and args.workload == "C2":
         log("[bench] CPU oracle sample ...")

@@ -358,7 +358,9 @@ __device__ inline void tile_gemv_split(const T* __restrict__ A, int64_t ld, cons
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
     const int c = wave * CPW + it * GPL + g;
-    if (rows_ok && c < col_lim) {
+    // triangular modes load only the columns this lane's rows use
+    const bool needed = MODE == 0 || (MODE == 1 && c < rr + W - 1) || (MODE == 2 && c >= rr);
+    if (rows_ok && c < col_lim && needed) {
       load16(A + (int64_t)c * ld + rr, a[it]);
     } else {
 #pragma unroll
