@@ -212,6 +212,58 @@ gdsw_status gdsw_copy_coarse_basis(const gdsw_ctx* ctx, double* phi_host);
 gdsw_status gdsw_local_indices(const gdsw_ctx* ctx, int32_t i, int32_t* idx_host,
                                int32_t* size);
 
+/* Learned local solve ----------------------------------------------------------
+ * A 4-layer 3x3x3 convolution network (channels 4-32-32-32-4, ReLU between
+ * layers, BF16 weights and activations with FP32 accumulation) may replace
+ * A_i^-1 of eq. (2.2) on the interior subdomains (those whose local problem
+ * does not touch the cube's boundary); FGMRES admits the variable
+ * preconditioner.  The network maps r_i / ||r_i|| on the local node grid
+ * (channels u_x, u_y, u_z, p; pressure on the Q1 nodes; velocity divided by
+ * mu) to A_i^-1 r_i / ||r_i|| scaled per channel.  The LU factors are kept:
+ * they generate the training pairs and serve as fallback. */
+typedef struct {
+  int32_t grid;               /* nodes per axis of an interior local problem */
+  int32_t subdomains;         /* interior subdomains */
+  int64_t n_params;           /* weights + biases (flat: W0 b0 W1 b1 W2 b2 W3 b3,
+                                 W_l[c_out][c_in][27]) */
+  int32_t samples;            /* training pairs generated so far */
+  int32_t reserved;
+  float sigma[4];             /* per-channel target scales */
+} gdsw_learned_info;
+
+/* Allocates the network on the device, He-normal weights from `seed`.
+ * EUNSUPPORTED when the decomposition has no interior subdomains (m < 3). */
+gdsw_status gdsw_learned_init(gdsw_ctx* ctx, uint64_t seed, gdsw_learned_info* info, void* stream);
+
+/* Generates training pairs from `solves` LU-preconditioned FGMRES solves (the
+ * assembled right-hand side, then seeded random ones): every Krylov vector
+ * restricted to every interior subdomain gives (r_i, A_i^-1 r_i) by the LU
+ * solve.  Then `steps` Adam steps (lr; beta 0.9/0.999) on random batches of
+ * `batch` pairs; loss_history[steps] (host, may be NULL) receives the mean
+ * masked squared error per step.  solves = 0 keeps the existing pairs. */
+gdsw_status gdsw_learned_train(gdsw_ctx* ctx, int32_t solves, int32_t steps, int32_t batch, double lr, uint64_t seed,
+                               double* loss_history, void* stream);
+
+/* Sets the FP32 master weights from set_host (n_params floats, may be NULL),
+ * then copies to get_host (may be NULL): which = 0 master weights, 1 the
+ * BF16-rounded working weights, 2 the last gradients. */
+gdsw_status gdsw_learned_weights(gdsw_ctx* ctx, const float* set_host, float* get_host, int32_t which, void* stream);
+
+/* Loss and gradients for host inputs x and targets t ([batch][4][grid^3]
+ * each, batch <= max(interior subdomains, 32)): forward and backward kernels
+ * exactly as in training.  For checking the kernels against a reference. */
+gdsw_status gdsw_learned_loss_grad(gdsw_ctx* ctx, const float* x_host, const float* t_host, int32_t batch,
+                                   double* loss, float* grads_host, void* stream);
+
+/* Local solver of the interior subdomains: 0 LU (default), 1 learned with the
+ * LU fallback where ||r_i - A_i y_i|| > tau ||r_i||, 2 none (no local
+ * correction there; an ablation).  Mode 1 reads one counter back to the host
+ * per apply. */
+gdsw_status gdsw_set_local_solver(gdsw_ctx* ctx, int32_t mode, double tau);
+
+/* Interior local solves done by the network and by the LU fallback so far. */
+gdsw_status gdsw_learned_stats(const gdsw_ctx* ctx, int64_t* learned_solves, int64_t* fallbacks);
+
 /* Tuning --------------------------------------------------------------------- */
 
 /* Re-plans the launch schedule of the blocked triangular solves: the factors

@@ -57,6 +57,11 @@ class Sizes(C.Structure):
                [("solve_launches", C.c_int64)]
 
 
+class LearnedInfo(C.Structure):
+    _fields_ = [("grid", C.c_int32), ("subdomains", C.c_int32), ("n_params", C.c_int64), ("samples", C.c_int32),
+                ("reserved", C.c_int32), ("sigma", C.c_float * 4)]
+
+
 _P = C.c_void_p
 _sig = {
     "gdsw_setup": (C.c_int, [C.POINTER(Mesh), C.POINTER(Decomposition), _P, C.POINTER(_P)]),
@@ -76,6 +81,12 @@ _sig = {
     "gdsw_local_indices": (C.c_int, [_P, C.c_int32, _P, C.POINTER(C.c_int32)]),
     "gdsw_profile_apply": (C.c_int, [_P, _P, _P, _P, _P]),
     "gdsw_set_schedule": (C.c_int, [_P, C.c_int32, _P]),
+    "gdsw_learned_init": (C.c_int, [_P, C.c_uint64, C.POINTER(LearnedInfo), _P]),
+    "gdsw_learned_train": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_uint64, _P, _P]),
+    "gdsw_learned_weights": (C.c_int, [_P, _P, _P, C.c_int32, _P]),
+    "gdsw_learned_loss_grad": (C.c_int, [_P, _P, _P, C.c_int32, C.POINTER(C.c_double), _P, _P]),
+    "gdsw_set_local_solver": (C.c_int, [_P, C.c_int32, C.c_double]),
+    "gdsw_learned_stats": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "gdsw_last_error": (C.c_char_p, [_P]),
     "gdsw_destroy": (None, [_P]),
 }
@@ -222,6 +233,44 @@ class Solver:
     def expand(self, x_free, x_full, stream=None):
         _check(_lib.gdsw_expand_solution(self._ctx, _ptr(x_free), _ptr(x_full), _stream(stream)), self._ctx)
         return x_full
+
+    # -- learned local solve -------------------------------------------------------
+    def learned_init(self, seed=0, stream=None):
+        info = LearnedInfo()
+        _check(_lib.gdsw_learned_init(self._ctx, seed, C.byref(info), _stream(stream)), self._ctx)
+        self.learned = info
+        return info
+
+    def learned_train(self, solves=3, steps=500, batch=32, lr=1e-3, seed=0, stream=None):
+        hist = np.zeros(max(steps, 1))
+        _check(_lib.gdsw_learned_train(self._ctx, solves, steps, batch, lr, seed, _ptr(hist), _stream(stream)),
+               self._ctx)
+        return hist[:steps]
+
+    def learned_weights(self, which=0, set_to=None, stream=None):
+        n = self.learned.n_params
+        out = np.zeros(n, dtype=np.float32)
+        src = None if set_to is None else np.ascontiguousarray(set_to, dtype=np.float32)
+        _check(_lib.gdsw_learned_weights(self._ctx, _ptr(src), _ptr(out), which, _stream(stream)), self._ctx)
+        return out
+
+    def learned_loss_grad(self, x, t, stream=None):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        t = np.ascontiguousarray(t, dtype=np.float32)
+        g = np.zeros(self.learned.n_params, dtype=np.float32)
+        loss = C.c_double()
+        _check(_lib.gdsw_learned_loss_grad(self._ctx, _ptr(x), _ptr(t), x.shape[0], C.byref(loss), _ptr(g),
+                                           _stream(stream)), self._ctx)
+        return loss.value, g
+
+    def set_local_solver(self, mode, tau=0.7):
+        _check(_lib.gdsw_set_local_solver(self._ctx, {"lu": 0, "learned": 1, "none": 2}.get(mode, mode), tau),
+               self._ctx)
+
+    def learned_stats(self):
+        a, b = C.c_int64(), C.c_int64()
+        _check(_lib.gdsw_learned_stats(self._ctx, C.byref(a), C.byref(b)), self._ctx)
+        return a.value, b.value
 
     def close(self):
         if self._ctx:

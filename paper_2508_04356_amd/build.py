@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgdsw.so")
 
-HIP_SOURCES = ["kernels_factor.hip", "kernels_ops.hip", "setup.hip", "solve.hip", "abi.hip"]
+HIP_SOURCES = ["kernels_factor.hip", "kernels_ops.hip", "kernels_learned.hip", "setup.hip", "solve.hip",
+               "learned.hip", "abi.hip"]
 CXX_SOURCES = ["problem.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

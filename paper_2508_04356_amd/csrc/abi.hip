@@ -10,6 +10,7 @@
 
 #include "../../include/gdsw.h"
 #include "context.h"
+#include "learned.h"
 
 using namespace gdsw;
 
@@ -165,7 +166,9 @@ gdsw_status gdsw_get_sizes(const gdsw_ctx* ctx, gdsw_sizes* out) {
     out->solve_bytes = c.L1.algorithmic_bytes() + c.HI.algorithmic_bytes();
     int64_t l = 0;
     for (const FactorSet* fs : {&c.L1, &c.HI})
-      for (size_t k = 0; k + 1 < fs->step_start.size(); ++k) l += fs->step_start[k + 1] > fs->step_start[k];
+      if (!fs->sched.empty())
+        for (size_t k = 0; k + 1 < fs->sched[0].step_start.size(); ++k)
+          l += fs->sched[0].step_start[k + 1] > fs->sched[0].step_start[k];
     out->solve_launches = l;
   }
   return GDSW_OK;
@@ -337,6 +340,70 @@ gdsw_status gdsw_profile_apply(gdsw_ctx* ctx, const double* r_dev, double* z_dev
   });
 }
 
+gdsw_status gdsw_learned_init(gdsw_ctx* ctx, uint64_t seed, gdsw_learned_info* info, void* stream) {
+  if (gdsw_status s = check_device_ctx(ctx)) return s;
+  return guarded(ctx, [&]() {
+    learned_init(ctx->c, seed, (hipStream_t)stream);
+    if (info) {
+      const LearnedSolve* L = ctx->c.learned;
+      info->grid = L->G;
+      info->subdomains = L->S;
+      info->n_params = L->n_params;
+      info->samples = L->N;
+      for (int k = 0; k < 4; ++k) info->sigma[k] = L->sigma[k];
+    }
+  });
+}
+
+gdsw_status gdsw_learned_train(gdsw_ctx* ctx, int32_t solves, int32_t steps, int32_t batch, double lr, uint64_t seed,
+                               double* loss_history, void* stream) {
+  if (gdsw_status s = check_device_ctx(ctx)) return s;
+  if (!ctx->c.learned) return fail(ctx, GDSW_EINVAL, "call gdsw_learned_init first");
+  if (steps < 0 || batch < 1 || !(lr > 0.0)) return fail(ctx, GDSW_EINVAL, "need steps >= 0, batch >= 1, lr > 0");
+  return guarded(ctx, [&]() {
+    hipStream_t st = (hipStream_t)stream;
+    if (solves > 0) learned_generate(ctx->c, solves, seed, st);
+    if (steps > 0) learned_train(ctx->c, steps, batch, lr, seed + 1, loss_history, st);
+  });
+}
+
+gdsw_status gdsw_learned_weights(gdsw_ctx* ctx, const float* set_host, float* get_host, int32_t which, void* stream) {
+  if (gdsw_status s = check_device_ctx(ctx)) return s;
+  if (!ctx->c.learned) return fail(ctx, GDSW_EINVAL, "call gdsw_learned_init first");
+  if (which < 0 || which > 2) return fail(ctx, GDSW_EINVAL, "which must be 0, 1 or 2");
+  return guarded(ctx, [&]() {
+    if (set_host) learned_set_weights(ctx->c, set_host, (hipStream_t)stream);
+    if (get_host) learned_get_weights(ctx->c, get_host, which, (hipStream_t)stream);
+  });
+}
+
+gdsw_status gdsw_learned_loss_grad(gdsw_ctx* ctx, const float* x_host, const float* t_host, int32_t batch,
+                                   double* loss, float* grads_host, void* stream) {
+  if (gdsw_status s = check_device_ctx(ctx)) return s;
+  if (!ctx->c.learned) return fail(ctx, GDSW_EINVAL, "call gdsw_learned_init first");
+  if (!x_host || !t_host || !loss) return fail(ctx, GDSW_EINVAL, "NULL argument");
+  return guarded(ctx, [&]() {
+    *loss = learned_loss_grad(ctx->c, x_host, t_host, batch, grads_host, (hipStream_t)stream);
+  });
+}
+
+gdsw_status gdsw_set_local_solver(gdsw_ctx* ctx, int32_t mode, double tau) {
+  if (gdsw_status s = check_device_ctx(ctx)) return s;
+  if (mode < 0 || mode > 2) return fail(ctx, GDSW_EINVAL, "mode must be 0, 1 or 2");
+  if (mode != 0 && !ctx->c.learned) return fail(ctx, GDSW_EINVAL, "call gdsw_learned_init first");
+  if (mode == 1 && !(tau > 0.0)) return fail(ctx, GDSW_EINVAL, "tau must be > 0");
+  ctx->c.local_solver = mode;
+  if (ctx->c.learned && tau > 0.0) ctx->c.learned->tau = tau;
+  return GDSW_OK;
+}
+
+gdsw_status gdsw_learned_stats(const gdsw_ctx* ctx, int64_t* learned_solves, int64_t* fallbacks) {
+  if (!ctx || !ctx->c.learned) return fail(const_cast<gdsw_ctx*>(ctx), GDSW_EINVAL, "no learned local solve");
+  if (learned_solves) *learned_solves = ctx->c.learned->learned_solves;
+  if (fallbacks) *fallbacks = ctx->c.learned->fallbacks;
+  return GDSW_OK;
+}
+
 const char* gdsw_last_error(const gdsw_ctx* ctx) {
   if (ctx) return ctx->c.last_error.c_str();
   return g_last_error.c_str();
@@ -344,6 +411,7 @@ const char* gdsw_last_error(const gdsw_ctx* ctx) {
 
 void gdsw_destroy(gdsw_ctx* ctx) {
   if (!ctx) return;
+  learned_release(ctx->c);
   ctx->c.arena.release_all();
   if (ctx->c.h_pinned) (void)hipHostFree(ctx->c.h_pinned);
   delete ctx;

@@ -76,13 +76,19 @@ struct FactorSet {
   int64_t* d_off = nullptr;
   int64_t* d_doff = nullptr;
   int64_t* d_xoff = nullptr;
-  // launch schedule: items (factor, J, K, mode) of every launch; factors run
-  // their 2*nblk sweeps with phase offsets so that launches carry similar work
+  // launch schedules: items (factor, J, K, mode) of every launch; factors run
+  // their 2*nblk sweeps with phase offsets so that launches carry similar work.
+  // Slot 0 covers every factor; further slots cover subsets (learned solve).
+  struct Schedule {
+    std::vector<int32_t> step_start;
+    int4* d_items = nullptr;
+  };
   int phases = 1;
-  std::vector<int32_t> step_start;
-  int4* d_items = nullptr;
+  std::vector<Schedule> sched;
   uint64_t algorithmic_bytes() const;  // sum n^2 * sizeof(prec) + dinv
 };
+
+struct LearnedSolve;
 
 struct Context {
   Problem P;
@@ -163,13 +169,18 @@ struct Context {
   int64_t ldv = 0;
   int n_part_blocks = 0;
 
+  // learned local solve (interior subdomains)
+  int local_solver = 0;            // 0 LU, 1 learned with LU fallback, 2 none (ablation)
+  LearnedSolve* learned = nullptr;
+
   // diagnostics
   double t_symbolic = 0, t_numeric = 0;
   uint64_t factor_bytes = 0, coarse_bytes = 0;
 };
 
 // numeric setup and operators (setup.hip / solve.hip)
-void plan_schedule(FactorSet& fs, int phases, DeviceArena& A, hipStream_t st);
+void plan_schedule(FactorSet& fs, int phases, DeviceArena& A, hipStream_t st, int slot = 0,
+                   const std::vector<char>* include = nullptr);
 void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb);
 void apply_precond(Context& ctx, const double* r, double* z, hipStream_t st, hipEvent_t* ev = nullptr);
 void spmv(Context& ctx, const double* x, double* y, hipStream_t st);

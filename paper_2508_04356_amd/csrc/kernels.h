@@ -39,7 +39,9 @@ void factor_finalize(FactorSet& fs, double* lu, int64_t dbase, hipStream_t st);
 
 // Blocked forward/backward solve, in place on the work vector w, for every
 // factor of the set: one launch per schedule step.
-void trsv_set(const FactorSet& fs, double* w, hipStream_t st);
+// `slot` selects a schedule of the set; `want` (device, per factor, or null)
+// skips the work-groups of unselected factors.
+void trsv_set(const FactorSet& fs, double* w, hipStream_t st, int slot = 0, const int32_t* want = nullptr);
 
 // C_b = alpha * op(A_b) * B_b + beta * C_b, FP64, column-major.
 struct GemmDesc {

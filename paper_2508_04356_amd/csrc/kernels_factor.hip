@@ -421,7 +421,8 @@ __global__ __launch_bounds__(256) void trsv_step_kernel(const T* __restrict__ st
                                                        const int64_t* __restrict__ OFF,
                                                        const int64_t* __restrict__ DOFF,
                                                        const int64_t* __restrict__ XOFF,
-                                                       const int4* __restrict__ items, double* __restrict__ w) {
+                                                       const int4* __restrict__ items, double* __restrict__ w,
+                                                       const int32_t* __restrict__ want) {
   using AT = typename VecW<T>::acc;
   using DT = typename DinvT<T>::type;
   using ADT = typename VecW<DT>::acc;
@@ -433,6 +434,7 @@ __global__ __launch_bounds__(256) void trsv_step_kernel(const T* __restrict__ st
   __shared__ double part_d[PSZ];
   const int4 item = items[blockIdx.x];
   const int f = item.x, J = item.y, K = item.z, mode = item.w;
+  if (want && !want[f]) return;  // uniform per work-group: factor not selected for this pass
   const int n = N[f];
   const int64_t np = NP[f];
   double* x = w + XOFF[f];
@@ -458,15 +460,16 @@ __global__ __launch_bounds__(256) void trsv_step_kernel(const T* __restrict__ st
 }
 
 template <typename T, int NB>
-void trsv_launch(const FactorSet& fs, double* w, hipStream_t st) {
+void trsv_launch(const FactorSet& fs, double* w, hipStream_t st, int slot, const int32_t* want) {
   using DT = typename DinvT<T>::type;
   const T* store = static_cast<const T*>(fs.store);
   const DT* dinv = static_cast<const DT*>(fs.dinv);
-  for (size_t g = 0; g + 1 < fs.step_start.size(); ++g) {
-    const int cnt = fs.step_start[g + 1] - fs.step_start[g];
+  const FactorSet::Schedule& S = fs.sched[slot];
+  for (size_t g = 0; g + 1 < S.step_start.size(); ++g) {
+    const int cnt = S.step_start[g + 1] - S.step_start[g];
     if (cnt == 0) continue;
     trsv_step_kernel<T, NB><<<cnt, 256, 0, st>>>(store, dinv, fs.d_n, fs.d_npad, fs.d_off, fs.d_doff, fs.d_xoff,
-                                                 fs.d_items + fs.step_start[g], w);
+                                                 S.d_items + S.step_start[g], w, want);
   }
 }
 
@@ -654,16 +657,16 @@ void factor_finalize(FactorSet& fs, double* lu, int64_t dbase, hipStream_t st) {
   GDSW_HIP(hipGetLastError());
 }
 
-void trsv_set(const FactorSet& fs, double* w, hipStream_t st) {
-  if (fs.count == 0) return;
+void trsv_set(const FactorSet& fs, double* w, hipStream_t st, int slot, const int32_t* want) {
+  if (fs.count == 0 || slot >= (int)fs.sched.size()) return;
   if (fs.nb == 128) {
-    if (fs.prec == P_FP64) trsv_launch<double, 128>(fs, w, st);
-    else if (fs.prec == P_FP32) trsv_launch<float, 128>(fs, w, st);
-    else trsv_launch<uint16_t, 128>(fs, w, st);
+    if (fs.prec == P_FP64) trsv_launch<double, 128>(fs, w, st, slot, want);
+    else if (fs.prec == P_FP32) trsv_launch<float, 128>(fs, w, st, slot, want);
+    else trsv_launch<uint16_t, 128>(fs, w, st, slot, want);
   } else {
-    if (fs.prec == P_FP64) trsv_launch<double, 64>(fs, w, st);
-    else if (fs.prec == P_FP32) trsv_launch<float, 64>(fs, w, st);
-    else trsv_launch<uint16_t, 64>(fs, w, st);
+    if (fs.prec == P_FP64) trsv_launch<double, 64>(fs, w, st, slot, want);
+    else if (fs.prec == P_FP32) trsv_launch<float, 64>(fs, w, st, slot, want);
+    else trsv_launch<uint16_t, 64>(fs, w, st, slot, want);
   }
   GDSW_HIP(hipGetLastError());
 }

@@ -1,0 +1,60 @@
+// Learned local solve state (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "context.h"
+#include "kernels_learned.h"
+
+namespace gdsw {
+
+struct LearnedSolve {
+  int G = 0;                      // grid nodes per axis of an interior local problem
+  int S = 0;                      // interior subdomains
+  std::vector<int32_t> factors;   // their level-1 factor indices
+  int32_t *d_factor = nullptr, *d_map_ptr = nullptr, *d_map = nullptr;
+  int8_t* d_field = nullptr;
+  int32_t *d_S_ptr = nullptr, *d_S_idx = nullptr;
+  float* d_mask = nullptr;
+  int64_t n_params = 0;
+  int64_t woff[4] = {}, boff[4] = {};
+  float *d_master = nullptr, *d_work = nullptr, *d_grad = nullptr, *d_m = nullptr, *d_v = nullptr;
+  int adam_t = 0;
+  float* d_sigma = nullptr;
+  float sigma[4] = {1.f, 1.f, 1.f, 1.f};
+  int max_b = 0;
+  float* act[5] = {};
+  float* gact[5] = {};
+  float* d_target = nullptr;
+  double* d_norms = nullptr;
+  float* d_lossb = nullptr;
+  double* d_rsave = nullptr;
+  int32_t* d_flags = nullptr;
+  int32_t* d_count = nullptr;
+  int32_t* h_count = nullptr;
+  int32_t* d_bidx = nullptr;
+  float* d_sign = nullptr;
+  float *Xd = nullptr, *Td = nullptr;
+  int N = 0;
+  double tau = 0.7;
+  bool trained = false;
+  int64_t fallbacks = 0, learned_solves = 0;
+};
+
+int64_t learned_param_count();
+void learned_init(Context& ctx, uint64_t seed, hipStream_t st);
+GridMap learned_gridmap(const Context& ctx);
+void learned_forward(Context& ctx, int B, hipStream_t st);
+double learned_backward(Context& ctx, int B, hipStream_t st);
+void learned_generate(Context& ctx, int nsolves, uint64_t seed, hipStream_t st);
+void learned_train(Context& ctx, int steps, int batch, double lr, uint64_t seed, double* history, hipStream_t st);
+void learned_apply_interior(Context& ctx, hipStream_t st);
+void learned_release(Context& ctx);
+void learned_set_weights(Context& ctx, const float* host, hipStream_t st);
+void learned_get_weights(Context& ctx, float* host, int which, hipStream_t st);
+double learned_loss_grad(Context& ctx, const float* X, const float* T, int B, float* grads, hipStream_t st);
+
+}  // namespace gdsw

@@ -71,9 +71,10 @@ int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 // forward updates with block s = l-1 (J > s); nblk = backward start
 // (x_J = U_JJ^-1 x_J); nblk+1 .. 2 nblk-1 = backward updates with block
 // s = 2 nblk - l (J < s), i.e. s = nblk-1 down to 1.
-void plan_schedule(FactorSet& fs, int phases, DeviceArena& A, hipStream_t st) {
+void plan_schedule(FactorSet& fs, int phases, DeviceArena& A, hipStream_t st, int slot,
+                   const std::vector<char>* include) {
   phases = std::max(1, std::min(phases, std::max(1, fs.count)));
-  fs.phases = phases;
+  if (slot == 0) fs.phases = phases;
   const int P = (fs.max_nblk + phases - 1) / phases;
   std::vector<int> o(fs.count);
   int total = 0;
@@ -81,10 +82,13 @@ void plan_schedule(FactorSet& fs, int phases, DeviceArena& A, hipStream_t st) {
     o[f] = (f % phases) * P;
     total = std::max(total, o[f] + 2 * fs.nblk[f]);
   }
+  if ((int)fs.sched.size() <= slot) fs.sched.resize(slot + 1);
+  FactorSet::Schedule& S = fs.sched[slot];
   std::vector<int4> items;
-  fs.step_start.assign(1, 0);
+  S.step_start.assign(1, 0);
   for (int g = 0; g < total; ++g) {
     for (int f = 0; f < fs.count; ++f) {
+      if (include && !(*include)[f]) continue;
       const int nb = fs.nblk[f];
       const int l = g - o[f];
       if (l < 0 || l >= 2 * nb) continue;
@@ -100,10 +104,10 @@ void plan_schedule(FactorSet& fs, int phases, DeviceArena& A, hipStream_t st) {
         for (int J = 0; J < s; ++J) items.push_back(make_int4(f, J, s, 0));
       }
     }
-    fs.step_start.push_back((int32_t)items.size());
+    S.step_start.push_back((int32_t)items.size());
   }
-  if (fs.d_items) A.free(fs.d_items);
-  fs.d_items = dupload(A, items, st);
+  if (S.d_items) A.free(S.d_items);
+  S.d_items = dupload(A, items, st);
 }
 
 namespace {

@@ -16,7 +16,9 @@
 
 #include "context.h"
 #include "kernels.h"
+#include "kernels_learned.h"
 #include "kernels_ops.h"
+#include "learned.h"
 
 namespace gdsw {
 namespace {
@@ -140,7 +142,19 @@ void apply_precond(Context& ctx, const double* r, double* z, hipStream_t st, hip
     restrict_coarse(ctx.Nc, cv, r, ctx.d_w, ctx.d_coarse_pinv, st);
   }
   if (ev) GDSW_HIP(hipEventRecord(ev[1], st));
-  trsv_set(ctx.L1, ctx.d_w, st);
+  if (ctx.local_solver != 0 && ctx.learned) {
+    // interior subdomains: learned solve (1) or no local correction (2)
+    const GridMap gm = learned_gridmap(ctx);
+    LearnedSolve* L = ctx.learned;
+    copy_segments(gm, L->S, ctx.d_w, L->d_rsave, nullptr, st);
+    trsv_set(ctx.L1, ctx.d_w, st, 1);
+    if (ctx.local_solver == 1)
+      learned_apply_interior(ctx, st);
+    else
+      zero_segments(gm, L->S, ctx.d_w, st);
+  } else {
+    trsv_set(ctx.L1, ctx.d_w, st);
+  }
   if (ev) GDSW_HIP(hipEventRecord(ev[2], st));
   trsv_set(ctx.HI, ctx.d_w, st);
   if (ev) GDSW_HIP(hipEventRecord(ev[3], st));
