@@ -62,6 +62,16 @@ typedef enum {
 
 typedef enum { GDSW_FP64 = 0, GDSW_FP32 = 1, GDSW_BF16 = 2 } gdsw_precision;
 
+/* How the local solves A_i^-1 R_i r of eq. (2.2) / (2.5), and the coarse
+ * solves, are carried out.  Both give A_i^-1 v up to rounding.
+ *   GDSW_SOLVE_INVERSE (default): the setup forms A_i^-1 explicitly by
+ *     Gauss-Jordan elimination without pivoting (velocity DOFs first; its
+ *     pivots are those of the no-pivoting LU) and stores it in place of the
+ *     factors (same n^2 entries); an apply is one batched dense product.
+ *   GDSW_SOLVE_TRIANGULAR: LU factors without pivoting and a blocked
+ *     forward/backward substitution (2 * ceil(n / tile) dependent steps). */
+typedef enum { GDSW_SOLVE_INVERSE = 0, GDSW_SOLVE_TRIANGULAR = 1 } gdsw_local_solve;
+
 /* The mesh: structured Q2/Q1 Stokes on the unit cube (Section 4). */
 typedef struct {
   int32_t n;                  /* n^3 hexahedra, n >= 1 */
@@ -83,7 +93,8 @@ typedef struct {
                                  m % group == 0 (N^(2) = (m/group)^3) */
   int32_t local_precision;    /* gdsw_precision of the level-1 local factors
                                  (the coarse levels are always FP64) */
-  int32_t tile;               /* triangular-solve tile size: 0 = default,
+  int32_t tile;               /* tile size of the factor layout and of the
+                                 triangular solves: 0 = default (128),
                                  else 64 or 128 */
   int32_t local_algebraic;    /* 0 (default): nodes on the artificial boundary
                                  of the grown box (the faces inside the cube)
@@ -99,6 +110,8 @@ typedef struct {
                                  of the A_0 graph */
   uint64_t device_mem_budget; /* bytes the setup may allocate; 0 = the free
                                  device memory reported by HIP */
+  int32_t local_solve;        /* gdsw_local_solve: how A_i^-1 (and the coarse
+                                 inverses) are applied */
 } gdsw_decomposition;
 
 typedef struct {
@@ -268,10 +281,11 @@ gdsw_status gdsw_learned_stats(const gdsw_ctx* ctx, int64_t* learned_solves, int
 
 /* Re-plans the launch schedule of the blocked triangular solves: the factors
  * are split into `phases` groups (1..64) whose forward/backward sweeps start
- * ceil(tiles / phases) launches apart, which evens out the bytes per launch.
- * Results do not depend on it (the arithmetic of every tile is unchanged).
+ * ceil(tiles / phases) launches apart, which evens out the bytes per launch;
+ * `waves` (4 or 8) sets the work-group size of the tile kernel (64 * waves
+ * threads; 8 needs tile 128).  Results do not depend on either.
  * Synchronises `stream`; must not overlap other calls on ctx. */
-gdsw_status gdsw_set_schedule(gdsw_ctx* ctx, int32_t phases, void* stream);
+gdsw_status gdsw_set_schedule(gdsw_ctx* ctx, int32_t phases, int32_t waves, void* stream);
 
 /* Diagnostics --------------------------------------------------------------- */
 

@@ -26,6 +26,7 @@ _lib = C.CDLL(LIB_PATH)
 
 FP64, FP32, BF16 = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
+LOCAL_SOLVES = {"inverse": 0, "triangular": 1}
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "ESINGULAR", 4: "ENOCONV", 5: "EDEVICE", 6: "EUNSUPPORTED"}
 
 
@@ -37,7 +38,7 @@ class Mesh(C.Structure):
 class Decomposition(C.Structure):
     _fields_ = [("subdomains", C.c_int32), ("overlap", C.c_int32), ("levels", C.c_int32), ("group", C.c_int32),
                 ("local_precision", C.c_int32), ("tile", C.c_int32), ("local_algebraic", C.c_int32),
-                ("level2_layer", C.c_int32), ("device_mem_budget", C.c_uint64)]
+                ("level2_layer", C.c_int32), ("device_mem_budget", C.c_uint64), ("local_solve", C.c_int32)]
 
 
 class FgmresOpts(C.Structure):
@@ -80,7 +81,7 @@ _sig = {
     "gdsw_copy_coarse_basis": (C.c_int, [_P, _P]),
     "gdsw_local_indices": (C.c_int, [_P, C.c_int32, _P, C.POINTER(C.c_int32)]),
     "gdsw_profile_apply": (C.c_int, [_P, _P, _P, _P, _P]),
-    "gdsw_set_schedule": (C.c_int, [_P, C.c_int32, _P]),
+    "gdsw_set_schedule": (C.c_int, [_P, C.c_int32, C.c_int32, _P]),
     "gdsw_learned_init": (C.c_int, [_P, C.c_uint64, C.POINTER(LearnedInfo), _P]),
     "gdsw_learned_train": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_uint64, _P, _P]),
     "gdsw_learned_weights": (C.c_int, [_P, _P, _P, C.c_int32, _P]),
@@ -135,12 +136,13 @@ class Solver:
 
     def __init__(self, n, m, overlap=1, levels=2, group=2, precision="fp64", tile=0, viscosity=1.0,
                  inflow=16.0, manufactured=0, budget=0, host_only=False, stream=None, local_algebraic=0,
-                 level2_layer=0):
+                 level2_layer=0, local_solve="inverse"):
         self._ctx = C.c_void_p()
         self.mesh = Mesh(n, manufactured, viscosity, inflow)
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        solve = LOCAL_SOLVES[local_solve] if isinstance(local_solve, str) else int(local_solve)
         self.dec = Decomposition(m, overlap, levels, group, prec, tile, int(local_algebraic), int(level2_layer),
-                                 budget)
+                                 budget, solve)
         if host_only:
             st = _lib.gdsw_setup_host(C.byref(self.mesh), C.byref(self.dec), C.byref(self._ctx))
         else:
@@ -207,8 +209,8 @@ class Solver:
         _check(_lib.gdsw_apply_precond(self._ctx, _ptr(r), _ptr(z), nrhs, ld, _stream(stream)), self._ctx)
         return z
 
-    def set_schedule(self, phases, stream=None):
-        _check(_lib.gdsw_set_schedule(self._ctx, phases, _stream(stream)), self._ctx)
+    def set_schedule(self, phases, waves=4, stream=None):
+        _check(_lib.gdsw_set_schedule(self._ctx, phases, waves, _stream(stream)), self._ctx)
 
     def profile_apply(self, r, z, stream=None):
         ms = np.zeros(4)

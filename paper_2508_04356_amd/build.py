@@ -1,6 +1,6 @@
 """Builds libgdsw.so (HIP for gfx950) in the package directory.
 
-Usage: python -m paper_2508_04356_amd.build   (or call build()).
+Usage: python paper_2508_04356_amd/build.py   (or call build()).
 Every call recompiles every source.
 """
 from __future__ import annotations
@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgdsw.so")
 
-HIP_SOURCES = ["kernels_factor.hip", "kernels_ops.hip", "kernels_learned.hip", "setup.hip", "solve.hip",
+HIP_SOURCES = ["kernels_factor.hip", "kernels_inverse.hip", "kernels_ops.hip", "kernels_learned.hip", "setup.hip", "solve.hip",
                "learned.hip", "abi.hip"]
 CXX_SOURCES = ["problem.cpp"]
 

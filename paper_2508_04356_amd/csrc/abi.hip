@@ -66,6 +66,8 @@ ProblemSpec spec_of(const gdsw_mesh* mesh, const gdsw_decomposition* dec) {
   s.level2_layer = dec->level2_layer != 0;
   if (dec->local_precision < 0 || dec->local_precision > 2) throw std::invalid_argument("bad local_precision");
   if (dec->tile != 0 && dec->tile != 64 && dec->tile != 128) throw std::invalid_argument("tile must be 0, 64 or 128");
+  if (dec->local_solve != GDSW_SOLVE_INVERSE && dec->local_solve != GDSW_SOLVE_TRIANGULAR)
+    throw std::invalid_argument("local_solve must be GDSW_SOLVE_INVERSE or GDSW_SOLVE_TRIANGULAR");
   return s;
 }
 
@@ -110,6 +112,7 @@ gdsw_status gdsw_setup(const gdsw_mesh* mesh, const gdsw_decomposition* dec, voi
     ctx = new gdsw_ctx();
     Context& c = ctx->c;
     c.local_prec = dec->local_precision;
+    c.solve_mode = dec->local_solve == GDSW_SOLVE_TRIANGULAR ? SOLVE_TRSV : SOLVE_INVERSE;
     GDSW_HIP(hipGetDevice(&c.device));
     const auto t0 = std::chrono::steady_clock::now();
     build_problem(sp, c.P, host_threads());
@@ -164,12 +167,7 @@ gdsw_status gdsw_get_sizes(const gdsw_ctx* ctx, gdsw_sizes* out) {
   out->device_bytes = c.arena.used;
   if (!c.host_only) {
     out->solve_bytes = c.L1.algorithmic_bytes() + c.HI.algorithmic_bytes();
-    int64_t l = 0;
-    for (const FactorSet* fs : {&c.L1, &c.HI})
-      if (!fs->sched.empty())
-        for (size_t k = 0; k + 1 < fs->sched[0].step_start.size(); ++k)
-          l += fs->sched[0].step_start[k + 1] > fs->sched[0].step_start[k];
-    out->solve_launches = l;
+    out->solve_launches = c.L1.launches() + c.HI.launches();
   }
   return GDSW_OK;
 }
@@ -309,14 +307,30 @@ gdsw_status gdsw_local_indices(const gdsw_ctx* ctx, int32_t i, int32_t* idx_host
   return GDSW_OK;
 }
 
-gdsw_status gdsw_set_schedule(gdsw_ctx* ctx, int32_t phases, void* stream) {
+gdsw_status gdsw_set_schedule(gdsw_ctx* ctx, int32_t phases, int32_t waves, void* stream) {
   if (gdsw_status s = check_device_ctx(ctx)) return s;
   if (phases < 1 || phases > 64) return fail(ctx, GDSW_EINVAL, "phases must be in 1..64");
+  if (waves != 4 && waves != 8) return fail(ctx, GDSW_EINVAL, "waves must be 4 or 8");
+  if (waves == 8 && ctx->c.nb != 128) return fail(ctx, GDSW_EINVAL, "8 waves need tile 128");
+  if (ctx->c.solve_mode != SOLVE_TRSV) return GDSW_OK;  // nothing to schedule for the inverse product
   return guarded(ctx, [&]() {
     hipStream_t st = (hipStream_t)stream;
     GDSW_HIP(hipStreamSynchronize(st));
-    plan_schedule(ctx->c.L1, phases, ctx->c.arena, st);
-    plan_schedule(ctx->c.HI, phases, ctx->c.arena, st);
+    for (FactorSet* fs : {&ctx->c.L1, &ctx->c.HI}) {
+      fs->waves = waves;
+      const size_t nsl = fs->sched.size();
+      plan_schedule(*fs, phases, ctx->c.arena, st);
+      (void)nsl;
+    }
+    if (ctx->c.learned) {
+      std::vector<char> inc(ctx->c.L1.count, 1), only(ctx->c.L1.count, 0);
+      for (int32_t f : ctx->c.learned->factors) {
+        inc[f] = 0;
+        only[f] = 1;
+      }
+      plan_schedule(ctx->c.L1, phases, ctx->c.arena, st, 1, &inc);
+      plan_schedule(ctx->c.L1, phases, ctx->c.arena, st, 2, &only);
+    }
     GDSW_HIP(hipStreamSynchronize(st));
   });
 }

@@ -60,7 +60,12 @@ enum Precision { P_FP64 = 0, P_FP32 = 1, P_BF16 = 2 };
 // column-major in a zero-padded npad x npad block (npad = n rounded up to the
 // tile), and the inverses of its diagonal tiles (unit-lower L^-1 strictly
 // below the diagonal, U^-1 on and above it) are kept separately in `dinv`.
+constexpr int SOLVE_INVERSE = 0;  // explicit inverse, applied as a dense matrix-vector product
+constexpr int SOLVE_TRSV = 1;     // LU factors, blocked forward/backward substitution
+constexpr int GEMV_CW = 256;      // columns per matrix-vector work item
+
 struct FactorSet {
+  int mode = SOLVE_INVERSE;
   int prec = P_FP64;
   int nb = 128;                       // tile
   int count = 0;
@@ -84,8 +89,21 @@ struct FactorSet {
     int4* d_items = nullptr;
   };
   int phases = 1;
+  int waves = 4;                      // work-group size of the solve kernel: 64 * waves
   std::vector<Schedule> sched;
-  uint64_t algorithmic_bytes() const;  // sum n^2 * sizeof(prec) + dinv
+  // explicit-inverse mode: work items of the two matrix-vector kernels per
+  // slot (partials: (f, r0, c0, p); sums: (f, r0, p0, count)) and the
+  // partial-sum buffer (64 * E doubles per item of the largest slot)
+  struct GemvPlan {
+    int n1 = 0, n2 = 0;
+    int4* d_items1 = nullptr;
+    int4* d_items2 = nullptr;
+  };
+  std::vector<GemvPlan> gemv;
+  double* d_partial = nullptr;
+  int64_t partial_len = 0;
+  uint64_t algorithmic_bytes() const;  // sum n^2 * sizeof(prec)
+  int64_t launches() const;            // solve kernel launches per pass (slot 0)
 };
 
 struct LearnedSolve;
@@ -97,6 +115,7 @@ struct Context {
   DeviceArena arena;
   std::string last_error;
   int local_prec = P_FP64;
+  int solve_mode = SOLVE_INVERSE;
   int nb = 128;
 
   // system matrix (free DOFs)

@@ -43,6 +43,21 @@ void factor_finalize(FactorSet& fs, double* lu, int64_t dbase, hipStream_t st);
 // skips the work-groups of unselected factors.
 void trsv_set(const FactorSet& fs, double* w, hipStream_t st, int slot = 0, const int32_t* want = nullptr);
 
+// In-place inverse of every matrix of the batch by blocked Gauss-Jordan
+// elimination without pivoting (64-wide blocks).  Pbuf: count * 64 * 64
+// doubles; Tbuf: count * tstride doubles with tstride >= 64 * max ld.
+// minpiv as for lu_nopiv (the pivots are those of the no-pivoting LU).
+void gj_invert(const DenseBatch& B, double* Pbuf, double* Tbuf, int64_t tstride, unsigned long long* minpiv,
+               hipStream_t st);
+// FP64 -> FP32 / BF16 (round to nearest even) conversion of count entries.
+void convert_store(int prec, const double* src, void* dst, int64_t count, hipStream_t st);
+// Rows per matrix-vector work item for a storage precision (64 lanes x 16 bytes).
+int gemv_rows(int prec);
+// x_f <- M_f x_f for every stored inverse M_f of the set, in place on w.
+void gemv_set(const FactorSet& fs, double* w, hipStream_t st, int slot = 0, const int32_t* want = nullptr);
+// The set's local solve in its mode (inverse product or triangular solves).
+void local_solve_set(const FactorSet& fs, double* w, hipStream_t st, int slot = 0, const int32_t* want = nullptr);
+
 // C_b = alpha * op(A_b) * B_b + beta * C_b, FP64, column-major.
 struct GemmDesc {
   const double* A;

@@ -23,6 +23,7 @@
 #include <cstring>
 
 #include "kernels.h"
+#include "vec16.h"
 
 namespace gdsw {
 namespace {
@@ -296,51 +297,11 @@ __global__ void convert_kernel_bf16(const double* __restrict__ src, uint16_t* __
 
 // ---- blocked triangular solve ---------------------------------------------
 
-template <typename T>
-struct VecW;
-template <>
-struct VecW<double> {
-  static constexpr int W = 2;
-  using acc = double;
-};
-template <>
-struct VecW<float> {
-  static constexpr int W = 4;
-  using acc = float;
-};
-template <>
-struct VecW<uint16_t> {
-  static constexpr int W = 8;
-  using acc = float;
-};
-
-__device__ inline void load16(const double* p, double (&o)[2]) {
-  const double2 v = *reinterpret_cast<const double2*>(p);
-  o[0] = v.x;
-  o[1] = v.y;
-}
-__device__ inline void load16(const float* p, float (&o)[4]) {
-  const float4 v = *reinterpret_cast<const float4*>(p);
-  o[0] = v.x;
-  o[1] = v.y;
-  o[2] = v.z;
-  o[3] = v.w;
-}
-__device__ inline void load16(const uint16_t* p, float (&o)[8]) {
-  const uint4 v = *reinterpret_cast<const uint4*>(p);
-  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    o[2 * i] = __uint_as_float(w[i] << 16);
-    o[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
-  }
-}
-
 // part[(wave * GPL + g) * NB + row] = sum over this lane's columns of A[row, c] v[c]
 // MODE 0: full tile, 1: strictly lower (c < row), 2: upper (c >= row).
 // The tile is loaded into registers first; v (NB entries at vsrc) and the
 // current values (NB entries at csrc) are staged in LDS meanwhile.
-template <typename T, int NB, int MODE>
+template <typename T, int NB, int MODE, int NW = 4>
 __device__ inline void tile_gemv_split(const T* __restrict__ A, int64_t ld, const double* __restrict__ vsrc,
                                        const double* __restrict__ csrc, double* vbuf, double* cur, int row_lim,
                                        int col_lim, typename VecW<T>::acc* part) {
@@ -348,7 +309,7 @@ __device__ inline void tile_gemv_split(const T* __restrict__ A, int64_t ld, cons
   constexpr int W = VecW<T>::W;
   constexpr int LPC = NB / W;
   constexpr int GPL = 64 / LPC;
-  constexpr int CPW = NB / 4;
+  constexpr int CPW = NB / NW;
   constexpr int IT = CPW / GPL;
   static_assert(GPL >= 1 && IT >= 1, "tile shape");
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -390,12 +351,12 @@ __device__ inline void tile_gemv_split(const T* __restrict__ A, int64_t ld, cons
   __syncthreads();
 }
 
-template <typename T, int NB>
+template <typename T, int NB, int NW = 4>
 __device__ inline typename VecW<T>::acc part_sum(const typename VecW<T>::acc* part, int row) {
   constexpr int GPL = 64 / (NB / VecW<T>::W);
   typename VecW<T>::acc s = 0;
 #pragma unroll
-  for (int q = 0; q < 4 * GPL; ++q) s += part[q * NB + row];
+  for (int q = 0; q < NW * GPL; ++q) s += part[q * NB + row];
   return s;
 }
 
@@ -414,8 +375,8 @@ struct DinvT<double> {
 //   mode 2:  x_J  = U_JJ^-1 x_J   (start of the backward sweep)
 // The tile loads are issued before anything else, so a work-group's only
 // serial dependence is one tile read.
-template <typename T, int NB>
-__global__ __launch_bounds__(256) void trsv_step_kernel(const T* __restrict__ store,
+template <typename T, int NB, int NW>
+__global__ __launch_bounds__(64 * NW) void trsv_step_kernel(const T* __restrict__ store,
                                                        const typename DinvT<T>::type* __restrict__ dinv,
                                                        const int32_t* __restrict__ N, const int32_t* __restrict__ NP,
                                                        const int64_t* __restrict__ OFF,
@@ -428,7 +389,7 @@ __global__ __launch_bounds__(256) void trsv_step_kernel(const T* __restrict__ st
   using ADT = typename VecW<DT>::acc;
   constexpr int GPLm = 64 / (NB / VecW<T>::W);
   constexpr int GPLd = 64 / (NB / VecW<DT>::W);
-  constexpr int PSZ = 4 * (GPLm > GPLd ? GPLm : GPLd) * NB;
+  constexpr int PSZ = NW * (GPLm > GPLd ? GPLm : GPLd) * NB;
   __shared__ double vbuf[NB];
   __shared__ double cur[NB];
   __shared__ double part_d[PSZ];
@@ -443,23 +404,23 @@ __global__ __launch_bounds__(256) void trsv_step_kernel(const T* __restrict__ st
   if (mode == 0) {
     const int c0 = K * NB;
     AT* part = reinterpret_cast<AT*>(part_d);
-    tile_gemv_split<T, NB, 0>(store + OFF[f] + (int64_t)c0 * np + r0, np, x + c0, x + r0, vbuf, cur,
-                              min(NB, n - r0), min(NB, n - c0), part);
-    if (tid < NB) x[r0 + tid] = cur[tid] - (double)part_sum<T, NB>(part, tid);
+    tile_gemv_split<T, NB, 0, NW>(store + OFF[f] + (int64_t)c0 * np + r0, np, x + c0, x + r0, vbuf, cur,
+                                  min(NB, n - r0), min(NB, n - c0), part);
+    if (tid < NB) x[r0 + tid] = cur[tid] - (double)part_sum<T, NB, NW>(part, tid);
   } else {
     ADT* part = reinterpret_cast<ADT*>(part_d);
     const DT* D = dinv + DOFF[f] + (int64_t)J * NB * NB;
     if (mode == 1) {
-      tile_gemv_split<DT, NB, 1>(D, NB, x + r0, x + r0, vbuf, cur, NB, NB, part);
-      if (tid < NB) x[r0 + tid] = cur[tid] + (double)part_sum<DT, NB>(part, tid);
+      tile_gemv_split<DT, NB, 1, NW>(D, NB, x + r0, x + r0, vbuf, cur, NB, NB, part);
+      if (tid < NB) x[r0 + tid] = cur[tid] + (double)part_sum<DT, NB, NW>(part, tid);
     } else {
-      tile_gemv_split<DT, NB, 2>(D, NB, x + r0, x + r0, vbuf, cur, NB, NB, part);
-      if (tid < NB) x[r0 + tid] = (double)part_sum<DT, NB>(part, tid);
+      tile_gemv_split<DT, NB, 2, NW>(D, NB, x + r0, x + r0, vbuf, cur, NB, NB, part);
+      if (tid < NB) x[r0 + tid] = (double)part_sum<DT, NB, NW>(part, tid);
     }
   }
 }
 
-template <typename T, int NB>
+template <typename T, int NB, int NW>
 void trsv_launch(const FactorSet& fs, double* w, hipStream_t st, int slot, const int32_t* want) {
   using DT = typename DinvT<T>::type;
   const T* store = static_cast<const T*>(fs.store);
@@ -468,8 +429,8 @@ void trsv_launch(const FactorSet& fs, double* w, hipStream_t st, int slot, const
   for (size_t g = 0; g + 1 < S.step_start.size(); ++g) {
     const int cnt = S.step_start[g + 1] - S.step_start[g];
     if (cnt == 0) continue;
-    trsv_step_kernel<T, NB><<<cnt, 256, 0, st>>>(store, dinv, fs.d_n, fs.d_npad, fs.d_off, fs.d_doff, fs.d_xoff,
-                                                 S.d_items + S.step_start[g], w, want);
+    trsv_step_kernel<T, NB, NW><<<cnt, 64 * NW, 0, st>>>(store, dinv, fs.d_n, fs.d_npad, fs.d_off, fs.d_doff,
+                                                         fs.d_xoff, S.d_items + S.step_start[g], w, want);
   }
 }
 
@@ -659,14 +620,15 @@ void factor_finalize(FactorSet& fs, double* lu, int64_t dbase, hipStream_t st) {
 
 void trsv_set(const FactorSet& fs, double* w, hipStream_t st, int slot, const int32_t* want) {
   if (fs.count == 0 || slot >= (int)fs.sched.size()) return;
+  const bool w8 = fs.waves == 8;
   if (fs.nb == 128) {
-    if (fs.prec == P_FP64) trsv_launch<double, 128>(fs, w, st, slot, want);
-    else if (fs.prec == P_FP32) trsv_launch<float, 128>(fs, w, st, slot, want);
-    else trsv_launch<uint16_t, 128>(fs, w, st, slot, want);
+    if (fs.prec == P_FP64) w8 ? trsv_launch<double, 128, 8>(fs, w, st, slot, want) : trsv_launch<double, 128, 4>(fs, w, st, slot, want);
+    else if (fs.prec == P_FP32) w8 ? trsv_launch<float, 128, 8>(fs, w, st, slot, want) : trsv_launch<float, 128, 4>(fs, w, st, slot, want);
+    else w8 ? trsv_launch<uint16_t, 128, 8>(fs, w, st, slot, want) : trsv_launch<uint16_t, 128, 4>(fs, w, st, slot, want);
   } else {
-    if (fs.prec == P_FP64) trsv_launch<double, 64>(fs, w, st, slot, want);
-    else if (fs.prec == P_FP32) trsv_launch<float, 64>(fs, w, st, slot, want);
-    else trsv_launch<uint16_t, 64>(fs, w, st, slot, want);
+    if (fs.prec == P_FP64) trsv_launch<double, 64, 4>(fs, w, st, slot, want);
+    else if (fs.prec == P_FP32) trsv_launch<float, 64, 4>(fs, w, st, slot, want);
+    else trsv_launch<uint16_t, 64, 4>(fs, w, st, slot, want);
   }
   GDSW_HIP(hipGetLastError());
 }

@@ -1,0 +1,419 @@
+// Explicit inverses of the local (and coarse) matrices, and their application.
+//
+// The preconditioner of eq. (2.2) / (2.5) needs A_i^-1 R_i r for every local
+// matrix A_i, and the same for the coarse matrices.  Instead of a forward and
+// backward substitution, whose 2 * nblk dependent steps are latency bound on
+// a 256-CU device, the setup forms A_i^-1 once (Gauss-Jordan elimination
+// without pivoting, in the velocity-first order whose pivots are the pivots
+// of the no-pivoting LU) and every apply is one batched dense
+// matrix-vector product: the same n^2 entries per matrix are streamed from HBM
+// as by the triangular solves, with no dependency chain.
+//
+// * gj_invert: blocked in-place Gauss-Jordan with 64-wide blocks.  Step k
+//   inverts the pivot block P = A_kk^-1 (one work-group per matrix, in LDS),
+//   forms T = P A_k* (row panel), updates A_ij -= A_ik T_j for every i, j != k
+//   (64 x 64 tiles), then sets A_ik <- -A_ik P and A_kj <- T_j.
+// * gemv_set: y = A^-1 x for every matrix of a factor set, in place on the
+//   work vector.  Kernel 1: one work-group per (matrix, row block of 64 * E
+//   rows, chunk of 256 columns), each lane owning E consecutive rows of a
+//   column (one 16-byte load per column), the waves splitting the columns;
+//   it writes one partial vector per item.  Kernel 2 sums the partials of a
+//   row block in chunk order (a fixed order: results are bitwise
+//   reproducible) and writes the result over x.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "kernels.h"
+#include "vec16.h"
+
+namespace gdsw {
+namespace {
+
+constexpr int GB = 64;  // Gauss-Jordan block
+
+__device__ inline void track_min_pivot(double piv, double& mn) {
+  const double a = fabs(piv);
+  if (!(a > 0.0) || !isfinite(piv)) {
+    mn = 0.0;
+  } else if (a < mn) {
+    mn = a;
+  }
+}
+
+// P = A_kk^-1 by Gauss-Jordan without pivoting in LDS; rows and columns
+// beyond n are identity.  Writes P (64 x 64, column-major) and A_kk <- P.
+__global__ __launch_bounds__(256) void gj_diag_kernel(double* __restrict__ base, const int32_t* __restrict__ N,
+                                                      const int32_t* __restrict__ LD,
+                                                      const int64_t* __restrict__ OFF, int k,
+                                                      double* __restrict__ Pbuf,
+                                                      unsigned long long* __restrict__ minpiv) {
+  const int f = blockIdx.x;
+  const int n = N[f];
+  const int k0 = k * GB;
+  if (k0 >= n) return;
+  const int64_t ld = LD[f];
+  double* A = base + OFF[f];
+  const int bs = min(GB, n - k0);
+  __shared__ double a[GB][GB + 1];
+  __shared__ double prow[GB];
+  __shared__ double pcol[GB];
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < GB * GB; idx += blockDim.x) {
+    const int r = idx % GB, c = idx / GB;
+    a[r][c] = (r < bs && c < bs) ? A[(int64_t)(k0 + c) * ld + k0 + r] : (r == c ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  double mn = 1.0e308;
+  for (int j = 0; j < GB; ++j) {
+    const double piv = a[j][j];
+    if (tid == 0 && j < bs) track_min_pivot(piv, mn);
+    const double p = 1.0 / piv;
+    // scaled pivot row and the pivot column, copied so that the update reads
+    // values no thread is writing
+    if (tid < GB) {
+      prow[tid] = tid == j ? p : a[j][tid] * p;
+      pcol[tid] = a[tid][j];
+    }
+    __syncthreads();
+    for (int idx = tid; idx < GB * GB; idx += blockDim.x) {
+      const int i = idx % GB, c = idx / GB;
+      if (i == j) {
+        a[i][c] = prow[c];
+      } else if (c == j) {
+        a[i][c] = -pcol[i] * p;
+      } else {
+        a[i][c] -= pcol[i] * prow[c];
+      }
+    }
+    __syncthreads();
+  }
+  double* P = Pbuf + (int64_t)f * GB * GB;
+  for (int idx = tid; idx < GB * GB; idx += blockDim.x) {
+    const int r = idx % GB, c = idx / GB;
+    P[idx] = a[r][c];
+    if (r < bs && c < bs) A[(int64_t)(k0 + c) * ld + k0 + r] = a[r][c];
+  }
+  if (tid == 0) atomicMin(&minpiv[f], (unsigned long long)__double_as_longlong(mn));
+}
+
+// 64 x 64 x 64 product in a work-group: acc = X Y with X[r][l] and Y[l][c]
+// staged in LDS.  Thread (tx, ty) owns rows tx + 16 a, columns ty + 16 b.
+__device__ inline void tile_mm64(const double (*X)[GB + 1], const double (*Y)[GB + 1], int tx, int ty,
+                                 double (&acc)[4][4]) {
+  for (int l = 0; l < GB; ++l) {
+    double av[4], bv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) av[a] = X[tx + 16 * a][l];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) bv[b] = Y[l][ty + 16 * b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+  }
+}
+
+// T_j = P A_kj for every column tile j != k (T: 64 rows, column-major, ld 64).
+__global__ __launch_bounds__(256) void gj_row_kernel(const double* __restrict__ base, const int32_t* __restrict__ N,
+                                                     const int32_t* __restrict__ LD,
+                                                     const int64_t* __restrict__ OFF, int k,
+                                                     const double* __restrict__ Pbuf, double* __restrict__ Tbuf,
+                                                     int64_t tstride) {
+  const int f = blockIdx.y;
+  const int n = N[f];
+  const int k0 = k * GB;
+  if (k0 >= n) return;
+  const int nt = (n + GB - 1) / GB;
+  const int j = blockIdx.x;
+  if (j >= nt || j == k) return;
+  const int c0 = j * GB;
+  const int cb = min(GB, n - c0);
+  const int bs = min(GB, n - k0);
+  const int64_t ld = LD[f];
+  const double* A = base + OFF[f];
+  const double* P = Pbuf + (int64_t)f * GB * GB;
+  __shared__ double Xs[GB][GB + 1];
+  __shared__ double Ys[GB][GB + 1];
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < GB * GB; idx += 256) {
+    const int r = idx % GB, c = idx / GB;
+    Xs[r][c] = P[idx];
+    Ys[r][c] = (r < bs && c < cb) ? A[(int64_t)(c0 + c) * ld + k0 + r] : 0.0;
+  }
+  __syncthreads();
+  const int tx = tid & 15, ty = tid >> 4;
+  double acc[4][4] = {};
+  tile_mm64(Xs, Ys, tx, ty, acc);
+  double* T = Tbuf + (int64_t)f * tstride;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int c = ty + 16 * b;
+    if (c >= cb) continue;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) T[(int64_t)(c0 + c) * GB + tx + 16 * a] = acc[a][b];
+  }
+}
+
+// A_ij -= A_ik T_j for every tile with i != k and j != k.
+__global__ __launch_bounds__(256) void gj_update_kernel(double* __restrict__ base, const int32_t* __restrict__ N,
+                                                        const int32_t* __restrict__ LD,
+                                                        const int64_t* __restrict__ OFF, int k,
+                                                        const double* __restrict__ Tbuf, int64_t tstride) {
+  const int f = blockIdx.y;
+  const int n = N[f];
+  const int k0 = k * GB;
+  if (k0 >= n) return;
+  const int nt = (n + GB - 1) / GB;
+  const int t = blockIdx.x;
+  if (t >= nt * nt) return;
+  const int ti = t % nt, tj = t / nt;
+  if (ti == k || tj == k) return;
+  const int r0 = ti * GB, c0 = tj * GB;
+  const int rb = min(GB, n - r0), cb = min(GB, n - c0);
+  const int bs = min(GB, n - k0);
+  const int64_t ld = LD[f];
+  double* A = base + OFF[f];
+  const double* T = Tbuf + (int64_t)f * tstride;
+  __shared__ double Xs[GB][GB + 1];  // [row][l]
+  __shared__ double Ys[GB][GB + 1];  // [l][col]
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < GB * GB; idx += 256) {
+    const int r = idx % GB, l = idx / GB;
+    Xs[r][l] = (r < rb && l < bs) ? A[(int64_t)(k0 + l) * ld + r0 + r] : 0.0;
+    Ys[r][l] = (l < cb && r < bs) ? T[(int64_t)(c0 + l) * GB + r] : 0.0;  // Ys[l = r][col = l]
+  }
+  __syncthreads();
+  const int tx = tid & 15, ty = tid >> 4;
+  double acc[4][4] = {};
+  tile_mm64(Xs, Ys, tx, ty, acc);
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int c = ty + 16 * b;
+    if (c >= cb) continue;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int r = tx + 16 * a;
+      if (r < rb) A[(int64_t)(c0 + c) * ld + r0 + r] -= acc[a][b];
+    }
+  }
+}
+
+// Column panel A_ik <- -A_ik P (i != k) and row panel A_kj <- T_j (j != k).
+__global__ __launch_bounds__(256) void gj_panel_kernel(double* __restrict__ base, const int32_t* __restrict__ N,
+                                                       const int32_t* __restrict__ LD,
+                                                       const int64_t* __restrict__ OFF, int k,
+                                                       const double* __restrict__ Pbuf,
+                                                       const double* __restrict__ Tbuf, int64_t tstride) {
+  const int f = blockIdx.y;
+  const int n = N[f];
+  const int k0 = k * GB;
+  if (k0 >= n) return;
+  const int nt = (n + GB - 1) / GB;
+  const int t = blockIdx.x;
+  if (t >= 2 * nt) return;
+  const int bs = min(GB, n - k0);
+  const int64_t ld = LD[f];
+  double* A = base + OFF[f];
+  const int tid = threadIdx.x;
+  if (t >= nt) {
+    const int j = t - nt;
+    if (j == k) return;
+    const int c0 = j * GB;
+    const int cb = min(GB, n - c0);
+    const double* T = Tbuf + (int64_t)f * tstride;
+    for (int idx = tid; idx < GB * GB; idx += 256) {
+      const int r = idx % GB, c = idx / GB;
+      if (r < bs && c < cb) A[(int64_t)(c0 + c) * ld + k0 + r] = T[(int64_t)(c0 + c) * GB + r];
+    }
+    return;
+  }
+  const int i = t;
+  if (i == k) return;
+  const int r0 = i * GB;
+  const int rb = min(GB, n - r0);
+  const double* P = Pbuf + (int64_t)f * GB * GB;
+  __shared__ double Xs[GB][GB + 1];
+  __shared__ double Ys[GB][GB + 1];
+  for (int idx = tid; idx < GB * GB; idx += 256) {
+    const int r = idx % GB, c = idx / GB;
+    Xs[r][c] = (r < rb && c < bs) ? A[(int64_t)(k0 + c) * ld + r0 + r] : 0.0;
+    Ys[r][c] = P[idx];
+  }
+  __syncthreads();
+  const int tx = tid & 15, ty = tid >> 4;
+  double acc[4][4] = {};
+  tile_mm64(Xs, Ys, tx, ty, acc);
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int c = ty + 16 * b;
+    if (c >= bs) continue;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int r = tx + 16 * a;
+      if (r < rb) A[(int64_t)(k0 + c) * ld + r0 + r] = -acc[a][b];
+    }
+  }
+}
+
+// ---- batched dense matrix-vector product ----------------------------------
+
+// Item (f, r0, c0, p): rows [r0, r0 + 64 E) and columns [c0, c0 + GEMV_CW)
+// of matrix f; partial[p * 64 E + row] = sum over those columns of M x.
+template <typename T, int NW>
+__global__ __launch_bounds__(64 * NW) void gemv_part_kernel(const T* __restrict__ store,
+                                                           const int64_t* __restrict__ OFF,
+                                                           const int32_t* __restrict__ N,
+                                                           const int32_t* __restrict__ NP,
+                                                           const int64_t* __restrict__ XOFF,
+                                                           const int4* __restrict__ items,
+                                                           const double* __restrict__ w,
+                                                           double* __restrict__ partial,
+                                                           const int32_t* __restrict__ want) {
+  using AT = typename VecW<T>::acc;
+  constexpr int E = VecW<T>::W;
+  constexpr int RB = 64 * E;
+  __shared__ AT xs[GEMV_CW];
+  __shared__ AT red[NW][RB];
+  const int4 item = items[blockIdx.x];
+  const int f = item.x, r0 = item.y, c0 = item.z, p = item.w;
+  if (want && !want[f]) return;  // uniform per work-group
+  const int n = N[f];
+  const int64_t np = NP[f];
+  const int ncols = min(GEMV_CW, n - c0);
+  const int tid = threadIdx.x;
+  const double* x = w + XOFF[f] + c0;
+  for (int i = tid; i < GEMV_CW; i += 64 * NW) xs[i] = i < ncols ? (AT)x[i] : (AT)0;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int rr = r0 + lane * E;
+  const bool active = rr < n;
+  const T* col = store + OFF[f] + (int64_t)c0 * np + rr;
+  AT acc[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) acc[e] = 0;
+  __syncthreads();
+  if (active) {
+    constexpr int U = 8;
+    int c = wave;
+    for (; c + (U - 1) * NW < ncols; c += U * NW) {
+      AT v[U][E];
+#pragma unroll
+      for (int u = 0; u < U; ++u) load16(col + (int64_t)(c + u * NW) * np, v[u]);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const AT xv = xs[c + u * NW];
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[e] = fma(v[u][e], xv, acc[e]);
+      }
+    }
+    for (; c < ncols; c += NW) {
+      AT v[E];
+      load16(col + (int64_t)c * np, v);
+      const AT xv = xs[c];
+#pragma unroll
+      for (int e = 0; e < E; ++e) acc[e] = fma(v[e], xv, acc[e]);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) red[wave][lane * E + e] = acc[e];
+  __syncthreads();
+  for (int r = tid; r < RB; r += 64 * NW) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) s += (double)red[q][r];
+    partial[(int64_t)p * RB + r] = s;
+  }
+}
+
+// Item (f, r0, p0, cnt): x[r0 + t] = sum_{q < cnt} partial[(p0 + q) * RB + t].
+template <int RB>
+__global__ __launch_bounds__(256) void gemv_sum_kernel(const int32_t* __restrict__ N,
+                                                       const int64_t* __restrict__ XOFF,
+                                                       const int4* __restrict__ items,
+                                                       const double* __restrict__ partial, double* __restrict__ w,
+                                                       const int32_t* __restrict__ want) {
+  const int4 item = items[blockIdx.x];
+  const int f = item.x, r0 = item.y, p0 = item.z, cnt = item.w;
+  if (want && !want[f]) return;
+  const int n = N[f];
+  for (int t = threadIdx.x; t < RB; t += 256) {
+    if (r0 + t >= n) break;
+    double s = 0.0;
+    for (int q = 0; q < cnt; ++q) s += partial[(int64_t)(p0 + q) * RB + t];
+    w[XOFF[f] + r0 + t] = s;
+  }
+}
+
+__global__ void convert_f32_kernel(const double* __restrict__ src, float* __restrict__ dst, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
+}
+
+__device__ inline uint16_t to_bf16(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+  return (uint16_t)(u >> 16);
+}
+
+__global__ void convert_bf16_kernel(const double* __restrict__ src, uint16_t* __restrict__ dst, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = to_bf16((float)src[i]);
+}
+
+template <typename T>
+void gemv_launch(const FactorSet& fs, double* w, hipStream_t st, int slot, const int32_t* want) {
+  const FactorSet::GemvPlan& G = fs.gemv[slot];
+  if (G.n1 == 0) return;
+  constexpr int RB = 64 * VecW<T>::W;
+  gemv_part_kernel<T, 4><<<G.n1, 256, 0, st>>>(static_cast<const T*>(fs.store), fs.d_off, fs.d_n, fs.d_npad,
+                                               fs.d_xoff, G.d_items1, w, fs.d_partial, want);
+  gemv_sum_kernel<RB><<<G.n2, 256, 0, st>>>(fs.d_n, fs.d_xoff, G.d_items2, fs.d_partial, w, want);
+}
+
+}  // namespace
+
+int gemv_rows(int prec) { return prec == P_FP64 ? 128 : prec == P_FP32 ? 256 : 512; }
+
+void gj_invert(const DenseBatch& B, double* Pbuf, double* Tbuf, int64_t tstride, unsigned long long* minpiv,
+               hipStream_t st) {
+  if (B.count == 0 || B.max_n == 0) return;
+  const int nt = (B.max_n + GB - 1) / GB;
+  for (int k = 0; k < nt; ++k) {
+    gj_diag_kernel<<<B.count, 256, 0, st>>>(B.base, B.n, B.ld, B.off, k, Pbuf, minpiv);
+    gj_row_kernel<<<dim3(nt, B.count), 256, 0, st>>>(B.base, B.n, B.ld, B.off, k, Pbuf, Tbuf, tstride);
+    gj_update_kernel<<<dim3(nt * nt, B.count), 256, 0, st>>>(B.base, B.n, B.ld, B.off, k, Tbuf, tstride);
+    gj_panel_kernel<<<dim3(2 * nt, B.count), 256, 0, st>>>(B.base, B.n, B.ld, B.off, k, Pbuf, Tbuf, tstride);
+  }
+  GDSW_HIP(hipGetLastError());
+}
+
+void convert_store(int prec, const double* src, void* dst, int64_t count, hipStream_t st) {
+  if (count == 0) return;
+  if (prec == P_FP32)
+    convert_f32_kernel<<<4096, 256, 0, st>>>(src, static_cast<float*>(dst), count);
+  else if (prec == P_BF16)
+    convert_bf16_kernel<<<4096, 256, 0, st>>>(src, static_cast<uint16_t*>(dst), count);
+  GDSW_HIP(hipGetLastError());
+}
+
+void gemv_set(const FactorSet& fs, double* w, hipStream_t st, int slot, const int32_t* want) {
+  if (fs.count == 0 || slot >= (int)fs.gemv.size()) return;
+  if (fs.prec == P_FP64)
+    gemv_launch<double>(fs, w, st, slot, want);
+  else if (fs.prec == P_FP32)
+    gemv_launch<float>(fs, w, st, slot, want);
+  else
+    gemv_launch<uint16_t>(fs, w, st, slot, want);
+  GDSW_HIP(hipGetLastError());
+}
+
+void local_solve_set(const FactorSet& fs, double* w, hipStream_t st, int slot, const int32_t* want) {
+  if (fs.mode == SOLVE_INVERSE)
+    gemv_set(fs, w, st, slot, want);
+  else
+    trsv_set(fs, w, st, slot, want);
+}
+
+}  // namespace gdsw

@@ -210,7 +210,7 @@ void learned_generate(Context& ctx, int nsolves, uint64_t seed, hipStream_t st) 
       const double* vj = ctx.d_V + (int64_t)j * ctx.ldv;
       gather(ctx.n_w1, ctx.d_gidx, vj, ctx.d_w, st);
       to_grid(gm, per_col, L->G, ctx.d_w, L->Xd + (int64_t)N * 4 * G3, norms, mu, st);
-      trsv_set(ctx.L1, ctx.d_w, st);
+      local_solve_set(ctx.L1, ctx.d_w, st);
       to_grid(gm, per_col, L->G, ctx.d_w, L->Td + (int64_t)N * 4 * G3, norms, mu, st, /*given_norms=*/true);
       N += per_col;
     }
@@ -297,7 +297,7 @@ void learned_apply_interior(Context& ctx, hipStream_t st) {
   L->fallbacks += nfb;
   if (nfb > 0) {
     copy_segments(gm, L->S, L->d_rsave, ctx.d_w, L->d_flags, st);
-    trsv_set(ctx.L1, ctx.d_w, st, 2, L->d_flags);
+    local_solve_set(ctx.L1, ctx.d_w, st, 2, L->d_flags);
   }
 }
 

@@ -59,6 +59,15 @@ uint64_t FactorSet::algorithmic_bytes() const {
   return b;
 }
 
+int64_t FactorSet::launches() const {
+  if (count == 0) return 0;
+  if (mode == SOLVE_INVERSE) return gemv.empty() || gemv[0].n1 == 0 ? 0 : 2;
+  int64_t l = 0;
+  if (!sched.empty())
+    for (size_t k = 0; k + 1 < sched[0].step_start.size(); ++k) l += sched[0].step_start[k + 1] > sched[0].step_start[k];
+  return l;
+}
+
 namespace {
 
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
@@ -71,8 +80,50 @@ int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 // forward updates with block s = l-1 (J > s); nblk = backward start
 // (x_J = U_JJ^-1 x_J); nblk+1 .. 2 nblk-1 = backward updates with block
 // s = 2 nblk - l (J < s), i.e. s = nblk-1 down to 1.
+namespace {
+
+// Work items of the explicit-inverse product for the factors selected by
+// `include`: partial items in (factor, column chunk, row block) order, so
+// that consecutive work-groups stream consecutive rows of the same columns;
+// partial index p in (factor, row block, column chunk) order, so that the
+// partials of one row block are contiguous for the summation kernel.
+void plan_gemv(FactorSet& fs, DeviceArena& A, hipStream_t st, int slot, const std::vector<char>* include) {
+  const int RB = gemv_rows(fs.prec);
+  std::vector<int4> it1, it2;
+  int p = 0;
+  for (int f = 0; f < fs.count; ++f) {
+    if (include && !(*include)[f]) continue;
+    const int n = fs.n[f];
+    const int nr = (n + RB - 1) / RB, nc = (n + GEMV_CW - 1) / GEMV_CW;
+    for (int c = 0; c < nc; ++c)
+      for (int J = 0; J < nr; ++J) it1.push_back(make_int4(f, J * RB, c * GEMV_CW, p + J * nc + c));
+    for (int J = 0; J < nr; ++J) it2.push_back(make_int4(f, J * RB, p + J * nc, nc));
+    p += nr * nc;
+  }
+  if ((int)fs.gemv.size() <= slot) fs.gemv.resize(slot + 1);
+  FactorSet::GemvPlan& G = fs.gemv[slot];
+  if (G.d_items1) A.free(G.d_items1);
+  if (G.d_items2) A.free(G.d_items2);
+  G.n1 = (int)it1.size();
+  G.n2 = (int)it2.size();
+  G.d_items1 = it1.empty() ? nullptr : dupload(A, it1, st);
+  G.d_items2 = it2.empty() ? nullptr : dupload(A, it2, st);
+  const int64_t need = (int64_t)p * RB;
+  if (need > fs.partial_len) {
+    if (fs.d_partial) A.free(fs.d_partial);
+    fs.d_partial = dalloc<double>(A, need);
+    fs.partial_len = need;
+  }
+}
+
+}  // namespace
+
 void plan_schedule(FactorSet& fs, int phases, DeviceArena& A, hipStream_t st, int slot,
                    const std::vector<char>* include) {
+  if (fs.mode == SOLVE_INVERSE) {
+    plan_gemv(fs, A, st, slot, include);
+    return;
+  }
   phases = std::max(1, std::min(phases, std::max(1, fs.count)));
   if (slot == 0) fs.phases = phases;
   const int P = (fs.max_nblk + phases - 1) / phases;
@@ -114,7 +165,8 @@ namespace {
 
 // Host metadata of a factor set for the given sizes; device arrays uploaded.
 void plan_factor_set(FactorSet& fs, const std::vector<int32_t>& sizes, int prec, int nb, int64_t xbase,
-                     DeviceArena& A, hipStream_t st) {
+                     int mode, DeviceArena& A, hipStream_t st) {
+  fs.mode = mode;
   fs.prec = prec;
   fs.nb = nb;
   fs.count = (int)sizes.size();
@@ -134,7 +186,7 @@ void plan_factor_set(FactorSet& fs, const std::vector<int32_t>& sizes, int prec,
     fs.doff[f] = d;
     fs.xoff[f] = x;
     o += np * np;
-    d += (int64_t)fs.nblk[f] * nb * nb;
+    if (mode == SOLVE_TRSV) d += (int64_t)fs.nblk[f] * nb * nb;
     x += np;
     fs.max_nblk = std::max(fs.max_nblk, fs.nblk[f]);
   }
@@ -182,7 +234,7 @@ void factor_set(Context& ctx, FactorSet& fs, uint64_t staging_cap, double pivot_
   DeviceArena& A = ctx.arena;
   const size_t es = elem_size(fs.prec);
   fs.store = A.alloc((uint64_t)fs.total_elems * es);
-  fs.dinv = A.alloc((uint64_t)fs.total_dinv * (fs.prec == P_FP64 ? 8 : 4));
+  if (fs.mode == SOLVE_TRSV) fs.dinv = A.alloc((uint64_t)fs.total_dinv * (fs.prec == P_FP64 ? 8 : 4));
   int f0 = 0;
   while (f0 < fs.count) {
     // chunk [f0, f1) within the staging cap
@@ -232,6 +284,30 @@ void factor_set(Context& ctx, FactorSet& fs, uint64_t staging_cap, double pivot_
     B.max_n = max_n;
     fill(B, f0, f1);
     unsigned long long* mp = minpiv_buffer(A, cnt, st);
+    if (fs.mode == SOLVE_INVERSE) {
+      int64_t max_np = 0;
+      for (int k = 0; k < cnt; ++k) max_np = std::max<int64_t>(max_np, ch.npad[k]);
+      const int64_t tstride = 64 * max_np;
+      double* Pbuf = dalloc<double>(A, (int64_t)cnt * 64 * 64);
+      double* Tbuf = dalloc<double>(A, (int64_t)cnt * tstride);
+      gj_invert(B, Pbuf, Tbuf, tstride, mp, st);
+      check_pivots(mp, cnt, pivot_tol, what, st);
+      if (fs.prec != P_FP64)
+        convert_store(fs.prec, staging, static_cast<char*>(fs.store) + (size_t)fs.off[f0] * es, (int64_t)(bytes / 8),
+                      st);
+      GDSW_HIP(hipStreamSynchronize(st));
+      A.free(Tbuf);
+      A.free(Pbuf);
+      A.free(mp);
+      A.free(d_n);
+      A.free(d_np);
+      A.free(d_nblk);
+      A.free(d_off);
+      A.free(d_doff);
+      if (own_staging) A.free(staging);
+      f0 = f1;
+      continue;
+    }
     lu_nopiv(B, mp, st);
     check_pivots(mp, cnt, pivot_tol, what, st);
     // finalize: dinv + conversion on the chunk
@@ -310,7 +386,7 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
   for (int i = 0; i < P.n_sub; ++i) l1_sizes[i] = (int32_t)P.S[i].size();
   ctx.merged = (levels == 2 && ctx.local_prec == P_FP64 && Nc > 0);
   if (ctx.merged) l1_sizes.push_back(Nc);
-  plan_factor_set(ctx.L1, l1_sizes, ctx.local_prec, nb, 0, A, st);
+  plan_factor_set(ctx.L1, l1_sizes, ctx.local_prec, nb, 0, ctx.solve_mode, A, st);
   ctx.n_w1 = ctx.L1.total_x;
   std::vector<int32_t> hi_sizes;
   const Level2& L2 = P.lv2;
@@ -335,7 +411,7 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
     }
     if (ctx.Nc3 > 0) hi_sizes.push_back(ctx.Nc3);
   }
-  plan_factor_set(ctx.HI, hi_sizes, P_FP64, nb, ctx.n_w1, A, st);
+  plan_factor_set(ctx.HI, hi_sizes, P_FP64, nb, ctx.n_w1, ctx.solve_mode, A, st);
   ctx.n_w = ctx.n_w1 + ctx.HI.total_x;
   ctx.d_w = dalloc<double>(A, std::max<int64_t>(ctx.n_w, 1));
   GDSW_HIP(hipMemsetAsync(ctx.d_w, 0, std::max<int64_t>(ctx.n_w, 1) * 8, st));

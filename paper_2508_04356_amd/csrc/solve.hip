@@ -147,16 +147,16 @@ void apply_precond(Context& ctx, const double* r, double* z, hipStream_t st, hip
     const GridMap gm = learned_gridmap(ctx);
     LearnedSolve* L = ctx.learned;
     copy_segments(gm, L->S, ctx.d_w, L->d_rsave, nullptr, st);
-    trsv_set(ctx.L1, ctx.d_w, st, 1);
+    local_solve_set(ctx.L1, ctx.d_w, st, 1);
     if (ctx.local_solver == 1)
       learned_apply_interior(ctx, st);
     else
       zero_segments(gm, L->S, ctx.d_w, st);
   } else {
-    trsv_set(ctx.L1, ctx.d_w, st);
+    local_solve_set(ctx.L1, ctx.d_w, st);
   }
   if (ev) GDSW_HIP(hipEventRecord(ev[2], st));
-  trsv_set(ctx.HI, ctx.d_w, st);
+  local_solve_set(ctx.HI, ctx.d_w, st);
   if (ev) GDSW_HIP(hipEventRecord(ev[3], st));
   if (three) {
     // y0 = sum_j R_j^(2)T y_j + Phi3 y3, then z = sum_i R_i^T y_i + Phi y0

@@ -1,8 +1,9 @@
 """GPU parity of the HIP path against the CPU oracle (calls go through the C ABI).
 
 Tolerances (FP64): the oracle factors with partial pivoting, the library
-without pivoting and with inverted diagonal tiles, so the two local solves
-differ by about cond(A_i) * eps.  Setup results (A, Phi, A_0) are compared at
+either forms A_i^-1 by Gauss-Jordan without pivoting or factors without
+pivoting and inverts the diagonal tiles, so the local solves differ by about
+cond(A_i) * eps.  Setup results (A, Phi, A_0) are compared at
 1e-12 relative; preconditioner outputs at 1e-10 relative in the max norm;
 FGMRES solutions at 1e-10 relative with identical iteration counts.
 """
@@ -58,10 +59,11 @@ def gpu_case(w, **kw):
                     manufactured=w.manufactured, **kw)
 
 
+@pytest.mark.parametrize("solve", ["inverse", "triangular"])
 @pytest.mark.parametrize("w", small_parity_cases(), ids=lambda w: w.name)
-def test_setup_and_apply_parity(w):
+def test_setup_and_apply_parity(w, solve):
     p, d, M = oracle_case(w)
-    s = gpu_case(w)
+    s = gpu_case(w, local_solve=solve)
     n = p.n_free
     assert s.n_free == n and s.n_coarse == d.n_coarse
     # right-hand side and SpMV
@@ -94,7 +96,7 @@ def test_setup_and_apply_parity(w):
 def test_tile_sizes_agree(tile):
     w = workload("C1").with_(name="n6m3", n=6, m=3)
     p, d, M = oracle_case(w)
-    s = gpu_case(w, tile=tile)
+    s = gpu_case(w, tile=tile, local_solve="triangular")
     r = random_vector(p.n_free, seed=3)
     z = torch.zeros(p.n_free, dtype=torch.float64, device=DEV)
     s.apply(dev(r), z)
