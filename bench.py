@@ -1,15 +1,17 @@
 """Benchmark: FGMRES + two-level GDSW on the 16^3 Q2/Q1 Poiseuille problem.
 
 One step = one FGMRES solve to a 1e-8 relative residual from x = 0 on the
-16^3 mesh with 4^3 subdomains (overlap 1, FP64 dense local LU): every
-preconditioner apply (gathers, batched triangular solves, coarse restriction,
-coarse solve, prolongation, scatter), the block SpMV and the CGS2 Arnoldi
-steps.  The right-hand side is resident on the GPU before timing starts.
+16^3 mesh with 4^3 subdomains (overlap 1, FP64 local solves): every
+preconditioner apply (gathers, coarse restriction, the batched local and
+coarse solves, prolongation, scatter), the SpMV and the CGS2 Arnoldi steps.
+The right-hand side is resident on the GPU before timing starts.
 
 value = preconditioner applications per second over the timed solves
 (iterations / time).  The JSON line also reports the time to tolerance, the
-stand-alone apply rate, the roofline of the dominant kernel (the batched
-triangular solve, HBM bound) and the CPU oracle timed on a bounded sample.
+stand-alone apply rate, the roofline of the dominant kernel (the level-1
+local solve: by default the batched product with the explicit inverses,
+HBM bound), timed with HIP events around each of its launches during the
+timed solves, and the CPU oracle timed on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu-baseline]
 """
@@ -72,12 +74,19 @@ def cpu_baseline(w, sample_subdomains=8, repeats=5):
                       f"factorisation untimed"}
 
 
-def measured_traffic(launches):
-    """HBM bytes per launch of the triangular solves from the committed counter
+TRAFFIC = {  # committed counter summaries of the dominant kernel on the 16^3 FP64 workload
+    "inverse": ("gemv_part_kernel_16cubed_traffic.txt", "kernels_gemv.hip"),
+    "triangular": ("trsv_step_kernel_16cubed_traffic.txt", "kernels_factor.hip"),
+}
+
+
+def measured_traffic(solve, launches):
+    """HBM bytes per launch of the dominant kernel from the committed counter
     summary, or None when the kernel source changed since it was measured."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "trsv_step_kernel_16cubed_traffic.txt")
-    src = os.path.join(ROOT, "paper_2508_04356_amd", "csrc", "kernels_factor.hip")
+    name, srcname = TRAFFIC[solve]
+    path = os.path.join(ROOT, "profiles", name)
+    src = os.path.join(ROOT, "paper_2508_04356_amd", "csrc", srcname)
     if not os.path.exists(path):
         return None
     kv = dict(line.split(": ", 1) for line in open(path).read().splitlines() if ": " in line)
@@ -86,6 +95,95 @@ def measured_traffic(launches):
     if int(kv.get("launches_per_apply", -1)) != launches:
         return None
     return (float(kv["fetch_bytes_per_apply"]) + float(kv["write_bytes_per_apply"])) / launches
+
+
+MFMA_PEAK_TFS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
+
+
+def run_multi(args, w, prec, nrhs):
+    """Several right-hand sides: b_k = c_k b(1) with c_k ~ U[0.5, 2] (the
+    32-RHS workload), FGMRES in lockstep, local solves as MFMA products."""
+    import torch
+
+    import paper_2508_04356_amd as G
+    from inputs import c3_inflow_amplitudes, random_vector
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    K = min(nrhs, 32)
+    log(f"[bench] setup {w.name}: n={w.n} m={w.m} precision={prec} nrhs={nrhs}")
+    t0 = time.perf_counter()
+    s = G.Solver(w.n, w.m, overlap=w.overlap, levels=w.levels, group=w.group, viscosity=w.viscosity,
+                 inflow=w.inflow, precision=prec, local_algebraic=w.local_algebraic, max_rhs=K)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    sz = s.sizes()
+    n = sz.n_free
+    cs = c3_inflow_amplitudes(nrhs)
+    b1 = torch.zeros(n, dtype=torch.float64, device=dev)
+    s.rhs(b1)
+    B = torch.cat([b1 * float(c) for c in cs])
+    X = torch.zeros_like(B)
+    for _ in range(args.warmup):
+        s.fgmres(B, X, rtol=w.rtol, restart=w.restart, max_it=w.max_it, nrhs=nrhs)
+    torch.cuda.synchronize()
+    s.kernel_timer(True)
+    t0 = time.perf_counter()
+    col_its = 0
+    for _ in range(args.steps):
+        infos = s.fgmres(B, X, rtol=w.rtol, restart=w.restart, max_it=w.max_it, nrhs=nrhs)
+        col_its += sum(i.iterations for i in infos)
+    torch.cuda.synchronize()
+    t_steps = time.perf_counter() - t0
+    s.kernel_timer(False)
+    k_ms, k_launches, k_bytes = s.kernel_timer_read()
+    its = [i.iterations for i in infos]
+    ms_per_step = 1e3 * t_steps / args.steps
+    # stand-alone batched applies
+    R = torch.as_tensor(np.concatenate([random_vector(n, seed=1 + j) for j in range(nrhs)]), device=dev)
+    Z = torch.zeros_like(R)
+    for _ in range(3):
+        s.apply(R, Z, nrhs=nrhs)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.applies):
+        s.apply(R, Z, nrhs=nrhs)
+    e1.record()
+    torch.cuda.synchronize()
+    t_apply_ms = e0.elapsed_time(e1) / args.applies
+    k_avg_us = 1e3 * k_ms / max(k_launches, 1)
+    achieved = k_bytes / (k_avg_us * 1e-6) / 1e9
+    elem = {"fp64": 8, "fp32": 4, "bf16": 2}[prec]
+    flops = 2.0 * (k_bytes / elem) * K
+    tfs = flops / (k_avg_us * 1e-6) / 1e12
+    log(f"[bench] {args.steps} lockstep solves: {ms_per_step:.1f} ms each, iterations {its[:4]}...; "
+        f"{nrhs}-column apply {t_apply_ms:.3f} ms; MFMA product {k_avg_us:.1f} us avg over {k_launches} launches "
+        f"-> {achieved:.0f} GB/s, {tfs:.1f} TFLOP/s")
+    out = {
+        "metric": f"column applies/s of M^-1 inside lockstep FGMRES to 1e-8 ({nrhs} right-hand sides, {prec} local inverses)",
+        "value": float(col_its / t_steps),
+        "unit": "column applies/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else f"f64 (local inverses {prec}, matrix-core products, fp32 accumulation)",
+        "data": "synthetic: Poiseuille Stokes problem generated in-library; b_k = c_k b(1), c_k ~ U[0.5, 2] (seed 3)",
+        "config": {"workload": f"{w.name}: {w.n}^3 Q2/Q1 hexahedra, {w.m}^3 subdomains, overlap {w.overlap}, "
+                               f"2-level GDSW, {nrhs} right-hand sides, FGMRES rtol {w.rtol:g} restart {w.restart}",
+                   "n_free": n, "n_coarse": int(sz.n_coarse)},
+        "iterations": its,
+        "time_to_tol_s": ms_per_step / 1e3,
+        "apply_columns_per_s": nrhs * 1e3 / t_apply_ms,
+        "setup_s": t_setup,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": f"gemm_part_kernel ({prec} level-1 inverses x {K} right-hand sides on the matrix cores)",
+                     "bytes_per_launch": k_bytes, "launches_timed": k_launches, "avg_launch_us": k_avg_us,
+                     "mfma_tflops": tfs, "mfma_peak_tflops": MFMA_PEAK_TFS[prec],
+                     "mfma_frac": tfs / MFMA_PEAK_TFS[prec]},
+    }
+    s.close()
+    print(json.dumps(out))
 
 
 def main():
@@ -98,6 +196,10 @@ def main():
     ap.add_argument("--precision", default=None, help="local factor precision (default: the workload's)")
     ap.add_argument("--local-algebraic", type=int, default=None,
                     help="1: algebraic overlap instead of Dirichlet u, p on the artificial boundary")
+    ap.add_argument("--local-solve", default="inverse", choices=["inverse", "triangular"],
+                    help="explicit inverses (default) or LU triangular solves")
+    ap.add_argument("--nrhs", type=int, default=None,
+                    help="right-hand sides solved together (default: the workload's; C3 has 32)")
     ap.add_argument("--applies", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -124,6 +226,10 @@ def main():
 
     w = workload(args.workload)
     prec = args.precision or (w.precision if args.workload not in ("C2", "C2alg") else "fp64")
+    nrhs = w.nrhs if args.nrhs is None else args.nrhs
+    if nrhs > 1:
+        run_multi(args, w, prec, nrhs)
+        return
     alg = w.local_algebraic if args.local_algebraic is None else args.local_algebraic
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -131,7 +237,7 @@ def main():
     t0 = time.perf_counter()
     s = G.Solver(w.n, w.m, overlap=w.overlap, levels=w.levels, group=w.group, viscosity=w.viscosity,
                  inflow=w.inflow, tile=args.tile, precision=prec, local_algebraic=alg,
-                 level2_layer=w.level2_layer)
+                 level2_layer=w.level2_layer, local_solve=args.local_solve)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     sz = s.sizes()
@@ -146,12 +252,15 @@ def main():
         s.fgmres(b, x, rtol=w.rtol, restart=w.restart, max_it=w.max_it)
     torch.cuda.synchronize()
     its = []
+    s.kernel_timer(True)
     t0 = time.perf_counter()
     for k in range(args.steps):
         info = s.fgmres(b, x, rtol=w.rtol, restart=w.restart, max_it=w.max_it)[0]
         its.append(info.iterations)
     torch.cuda.synchronize()
     t_steps = time.perf_counter() - t0
+    s.kernel_timer(False)
+    k_ms, k_launches, k_bytes = s.kernel_timer_read()
     ms_per_step = 1e3 * t_steps / args.steps
     log(f"[bench] {args.steps} solves: {ms_per_step:.2f} ms each, iterations {its}, true rel {info.true_rel_res:.2e}")
 
@@ -170,12 +279,16 @@ def main():
     t_apply_ms = e0.elapsed_time(e1) / args.applies
     phases = np.array([s.profile_apply(r, z) for _ in range(10)])
     ph = phases.mean(axis=0)
-    t_trsv_ms = float(ph[1] + ph[2])
     solve_bytes = float(sz.solve_bytes)
-    achieved = solve_bytes / (t_trsv_ms * 1e-3) / 1e9
     launches = int(sz.solve_launches)
-    log(f"[bench] apply {t_apply_ms:.3f} ms; phases ms gather/restrict {ph[0]:.3f} trsv {ph[1]:.3f}+{ph[2]:.3f} "
-        f"scatter {ph[3]:.3f}; trsv {achieved:.0f} GB/s over {launches} launches")
+    k_avg_us = 1e3 * k_ms / max(k_launches, 1)
+    achieved = k_bytes / (k_avg_us * 1e-6) / 1e9
+    per_apply = k_launches / max(sum(its), 1)
+    kname = ("gemv_part_kernel (level-1 explicit inverses times the local vectors)" if args.local_solve == "inverse"
+             else "trsv_step_kernel (blocked forward/backward solves of the level-1 factors)")
+    log(f"[bench] apply {t_apply_ms:.3f} ms; phases ms gather/restrict {ph[0]:.3f} solve {ph[1]:.3f}+{ph[2]:.3f} "
+        f"scatter {ph[3]:.3f}; dominant kernel {k_launches} launches in the timed solves, {k_avg_us:.1f} us avg, "
+        f"{k_bytes:.3e} B each -> {achieved:.0f} GB/s")
 
     out = {
         "metric": f"M^-1 applies/s inside FGMRES to 1e-8 rel. residual ({w.levels}-level monolithic GDSW, {prec})",
@@ -199,15 +312,17 @@ def main():
         "time_to_tol_s": ms_per_step / 1e3,
         "true_rel_res": info.true_rel_res,
         "apply_only_per_s": 1e3 / t_apply_ms,
-        "apply_phases_ms": {"gather_restrict": ph[0], "trsv_l1": ph[1], "trsv_coarse": ph[2], "scatter": ph[3]},
+        "apply_phases_ms": {"gather_restrict": ph[0], "solve_l1": ph[1], "solve_coarse": ph[2], "scatter": ph[3]},
         "setup_s": t_setup,
+        "local_solve": args.local_solve,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(launches) if args.workload == "C2" and not alg else None,
-                     "kernel": "trsv_step_kernel (blocked forward/backward solves of every factor)",
-                     "bytes_per_apply": solve_bytes, "launches_per_apply": launches,
-                     "bytes_per_launch": solve_bytes / launches,
-                     "avg_launch_us": t_trsv_ms * 1e3 / launches},
+                     "traffic": (measured_traffic(args.local_solve, round(per_apply))
+                                 if args.workload == "C2" and not alg and prec == "fp64" else None),
+                     "kernel": kname,
+                     "bytes_per_launch": k_bytes, "launches_timed": k_launches,
+                     "launches_per_apply": per_apply, "avg_launch_us": k_avg_us,
+                     "solve_bytes_per_apply_all_sets": solve_bytes, "solve_launches_per_apply_all_sets": launches},
     }
     if not args.no_cpu_baseline and args.workload == "C2":
         log("[bench] CPU oracle sample ...")

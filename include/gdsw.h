@@ -112,6 +112,16 @@ typedef struct {
                                  device memory reported by HIP */
   int32_t local_solve;        /* gdsw_local_solve: how A_i^-1 (and the coarse
                                  inverses) are applied */
+  int32_t max_rhs;            /* 0 or 1: one column at a time.  2..32: the
+                                 setup also allocates work buffers for that
+                                 many columns, and gdsw_apply_precond /
+                                 gdsw_fgmres_solve then process up to max_rhs
+                                 columns together (two levels,
+                                 GDSW_SOLVE_INVERSE, LU local solver): one
+                                 MFMA product per factor set for all of them,
+                                 FGMRES in lockstep with per-column stopping.
+                                 With BF16 factors the columns are rounded to
+                                 BF16 for the products (FP32 accumulation). */
 } gdsw_decomposition;
 
 typedef struct {
@@ -192,13 +202,18 @@ gdsw_status gdsw_rhs(gdsw_ctx* ctx, double* b_dev, void* stream);
  * overlap. */
 gdsw_status gdsw_spmv(gdsw_ctx* ctx, const double* x_dev, double* y_dev, void* stream);
 
-/* z = M^-1 r for nrhs columns (eq. 2.2, or eq. 2.5 with three levels).
- * r and z must not overlap.  Allocates nothing. */
+/* z = M^-1 r for nrhs columns (eq. 2.2, or eq. 2.5 with three levels),
+ * column-major with leading dimension ld.  r and z must not overlap.
+ * Allocates nothing.  Columns are processed max_rhs at a time when the
+ * context was set up for several right-hand sides (see max_rhs), else one
+ * by one. */
 gdsw_status gdsw_apply_precond(gdsw_ctx* ctx, const double* r_dev, double* z_dev,
                                int32_t nrhs, int64_t ld, void* stream);
 
-/* Solves A x = b with right-preconditioned FGMRES for nrhs columns, one after
- * another, from x = 0.  Blocks until every column is done (the loop reads the
+/* Solves A x = b with right-preconditioned FGMRES for nrhs columns from
+ * x = 0: max_rhs columns at a time in lockstep when the context was set up
+ * for several right-hand sides (every column keeps its own Krylov space,
+ * stopping test and iteration count), else one after another.  Blocks until every column is done (the loop reads the
  * residual estimate back to the host once per iteration).  info[nrhs] may be
  * NULL.  Returns ENOCONV if a column missed rtol within max_it (x then holds
  * its last iterate and info is filled in). */
@@ -296,6 +311,19 @@ gdsw_status gdsw_set_schedule(gdsw_ctx* ctx, int32_t phases, int32_t waves, void
  * coarse-level set, ms[3] = scatter and prolongation (milliseconds). */
 gdsw_status gdsw_profile_apply(gdsw_ctx* ctx, const double* r_dev, double* z_dev, void* stream,
                                double* ms);
+
+/* Event timing of the dominant solve kernel.  While enabled, every launch of
+ * the level-1 solve kernel in a full apply (the partial-product kernel of
+ * GDSW_SOLVE_INVERSE, single- or multi-column, or each sweep step of
+ * GDSW_SOLVE_TRIANGULAR) is bracketed by two HIP events on the stream it runs
+ * on, up to 8192 launches.  gdsw_kernel_timer(ctx, 1) resets the count and
+ * starts; (ctx, 0) stops.  gdsw_kernel_timer_read waits for the last recorded
+ * event and returns the summed kernel time (ms), the number of timed launches
+ * and the mean algorithmic bytes per launch (a product launch reads every
+ * level-1 matrix once: sum of n^2 * element size; a sweep step is charged
+ * that sum divided by the steps of one apply). */
+gdsw_status gdsw_kernel_timer(gdsw_ctx* ctx, int32_t enable);
+gdsw_status gdsw_kernel_timer_read(gdsw_ctx* ctx, double* total_ms, int64_t* launches, uint64_t* bytes_per_launch);
 
 /* Last error text of ctx, or of the calling thread when ctx is NULL. */
 const char* gdsw_last_error(const gdsw_ctx* ctx);

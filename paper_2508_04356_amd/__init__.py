@@ -18,10 +18,12 @@ import numpy as np
 import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgdsw.so")
+# GDSW_LIBRARY selects another build of the same library (e.g. one compiled
+# with different launch-shape constants by build.py --out ... -D ...).
+LIB_PATH = os.environ.get("GDSW_LIBRARY") or os.path.join(_HERE, "libgdsw.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2508_04356_amd.build`")
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2508_04356_amd/build.py`")
 _lib = C.CDLL(LIB_PATH)
 
 FP64, FP32, BF16 = 0, 1, 2
@@ -38,7 +40,8 @@ class Mesh(C.Structure):
 class Decomposition(C.Structure):
     _fields_ = [("subdomains", C.c_int32), ("overlap", C.c_int32), ("levels", C.c_int32), ("group", C.c_int32),
                 ("local_precision", C.c_int32), ("tile", C.c_int32), ("local_algebraic", C.c_int32),
-                ("level2_layer", C.c_int32), ("device_mem_budget", C.c_uint64), ("local_solve", C.c_int32)]
+                ("level2_layer", C.c_int32), ("device_mem_budget", C.c_uint64), ("local_solve", C.c_int32),
+                ("max_rhs", C.c_int32)]
 
 
 class FgmresOpts(C.Structure):
@@ -81,6 +84,8 @@ _sig = {
     "gdsw_copy_coarse_basis": (C.c_int, [_P, _P]),
     "gdsw_local_indices": (C.c_int, [_P, C.c_int32, _P, C.POINTER(C.c_int32)]),
     "gdsw_profile_apply": (C.c_int, [_P, _P, _P, _P, _P]),
+    "gdsw_kernel_timer": (C.c_int, [_P, C.c_int32]),
+    "gdsw_kernel_timer_read": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_uint64)]),
     "gdsw_set_schedule": (C.c_int, [_P, C.c_int32, C.c_int32, _P]),
     "gdsw_learned_init": (C.c_int, [_P, C.c_uint64, C.POINTER(LearnedInfo), _P]),
     "gdsw_learned_train": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_uint64, _P, _P]),
@@ -136,13 +141,13 @@ class Solver:
 
     def __init__(self, n, m, overlap=1, levels=2, group=2, precision="fp64", tile=0, viscosity=1.0,
                  inflow=16.0, manufactured=0, budget=0, host_only=False, stream=None, local_algebraic=0,
-                 level2_layer=0, local_solve="inverse"):
+                 level2_layer=0, local_solve="inverse", max_rhs=1):
         self._ctx = C.c_void_p()
         self.mesh = Mesh(n, manufactured, viscosity, inflow)
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         solve = LOCAL_SOLVES[local_solve] if isinstance(local_solve, str) else int(local_solve)
         self.dec = Decomposition(m, overlap, levels, group, prec, tile, int(local_algebraic), int(level2_layer),
-                                 budget, solve)
+                                 budget, solve, int(max_rhs))
         if host_only:
             st = _lib.gdsw_setup_host(C.byref(self.mesh), C.byref(self.dec), C.byref(self._ctx))
         else:
@@ -208,6 +213,15 @@ class Solver:
         ld = self.n_free if ld is None else ld
         _check(_lib.gdsw_apply_precond(self._ctx, _ptr(r), _ptr(z), nrhs, ld, _stream(stream)), self._ctx)
         return z
+
+    def kernel_timer(self, enable):
+        _check(_lib.gdsw_kernel_timer(self._ctx, int(bool(enable))), self._ctx)
+
+    def kernel_timer_read(self):
+        """(total ms, launches, algorithmic bytes per launch) of the timed level-1 solve kernel."""
+        ms, n, b = C.c_double(), C.c_int64(), C.c_uint64()
+        _check(_lib.gdsw_kernel_timer_read(self._ctx, C.byref(ms), C.byref(n), C.byref(b)), self._ctx)
+        return ms.value, n.value, b.value
 
     def set_schedule(self, phases, waves=4, stream=None):
         _check(_lib.gdsw_set_schedule(self._ctx, phases, waves, _stream(stream)), self._ctx)

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgdsw.so")
 
-HIP_SOURCES = ["kernels_factor.hip", "kernels_inverse.hip", "kernels_ops.hip", "kernels_learned.hip", "setup.hip", "solve.hip",
+HIP_SOURCES = ["kernels_factor.hip", "kernels_inverse.hip", "kernels_gemv.hip", "kernels_gemm.hip", "kernels_multi.hip", "kernels_ops.hip", "kernels_learned.hip", "setup.hip", "solve.hip", "solve_multi.hip",
                "learned.hip", "abi.hip"]
 CXX_SOURCES = ["problem.cpp"]
 
@@ -36,27 +36,38 @@ def _run(cmd):
     return p.stdout
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
+    """Compiles every source and links `out`; `defines` ("NAME=VALUE") are
+    passed to every compile (launch-shape constants of the kernels)."""
+    bdir = BUILD if out == LIB else out + ".build"
+    os.makedirs(bdir, exist_ok=True)
+    dflags = [f"-D{d}" for d in defines]
     jobs = []
     for src in HIP_SOURCES:
-        obj = os.path.join(BUILD, src + ".o")
-        jobs.append([HIPCC, *COMMON, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+        obj = os.path.join(bdir, src + ".o")
+        jobs.append([HIPCC, *COMMON, *HIP_FLAGS, *dflags, "-c", os.path.join(CSRC, src), "-o", obj])
     for src in CXX_SOURCES:
-        obj = os.path.join(BUILD, src + ".o")
-        jobs.append(["g++", *COMMON, "-c", os.path.join(CSRC, src), "-o", obj])
+        obj = os.path.join(bdir, src + ".o")
+        jobs.append(["g++", *COMMON, *dflags, "-c", os.path.join(CSRC, src), "-o", obj])
     with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 4)) as ex:
         outs = list(ex.map(_run, jobs))
     if verbose:
         for o in outs:
             if o.strip():
                 print(o)
-    objs = [os.path.join(BUILD, s + ".o") for s in HIP_SOURCES + CXX_SOURCES]
-    tmp = LIB + ".tmp"
+    objs = [os.path.join(bdir, s + ".o") for s in HIP_SOURCES + CXX_SOURCES]
+    tmp = out + ".tmp"
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"])
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    import argparse
+
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("-v", action="store_true", help="print compiler output")
+    ap.add_argument("--out", default=LIB, help="library path (default: the package's libgdsw.so)")
+    ap.add_argument("-D", dest="defines", action="append", default=[], help="NAME=VALUE for every compile")
+    a = ap.parse_args()
+    print(build(verbose=a.v, out=os.path.abspath(a.out), defines=a.defines))

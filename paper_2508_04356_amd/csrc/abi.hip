@@ -10,6 +10,7 @@
 
 #include "../../include/gdsw.h"
 #include "context.h"
+#include "kernels_multi.h"
 #include "learned.h"
 
 using namespace gdsw;
@@ -68,6 +69,7 @@ ProblemSpec spec_of(const gdsw_mesh* mesh, const gdsw_decomposition* dec) {
   if (dec->tile != 0 && dec->tile != 64 && dec->tile != 128) throw std::invalid_argument("tile must be 0, 64 or 128");
   if (dec->local_solve != GDSW_SOLVE_INVERSE && dec->local_solve != GDSW_SOLVE_TRIANGULAR)
     throw std::invalid_argument("local_solve must be GDSW_SOLVE_INVERSE or GDSW_SOLVE_TRIANGULAR");
+  if (dec->max_rhs < 0 || dec->max_rhs > 32) throw std::invalid_argument("max_rhs must be in 0..32");
   return s;
 }
 
@@ -113,6 +115,7 @@ gdsw_status gdsw_setup(const gdsw_mesh* mesh, const gdsw_decomposition* dec, voi
     Context& c = ctx->c;
     c.local_prec = dec->local_precision;
     c.solve_mode = dec->local_solve == GDSW_SOLVE_TRIANGULAR ? SOLVE_TRSV : SOLVE_INVERSE;
+    c.max_rhs = std::max(1, dec->max_rhs);
     GDSW_HIP(hipGetDevice(&c.device));
     const auto t0 = std::chrono::steady_clock::now();
     build_problem(sp, c.P, host_threads());
@@ -225,8 +228,20 @@ gdsw_status gdsw_apply_precond(gdsw_ctx* ctx, const double* r_dev, double* z_dev
   if (nrhs < 1 || ld < ctx->c.P.n_free) return fail(ctx, GDSW_EINVAL, "need nrhs >= 1 and ld >= n_free");
   if (r_dev == z_dev) return fail(ctx, GDSW_EINVAL, "r and z must not overlap");
   return guarded(ctx, [&]() {
-    for (int k = 0; k < nrhs; ++k)
-      apply_precond(ctx->c, r_dev + (int64_t)k * ld, z_dev + (int64_t)k * ld, (hipStream_t)stream);
+    Context& c = ctx->c;
+    hipStream_t st = (hipStream_t)stream;
+    if (nrhs > 1 && multi_supported(c)) {
+      const int64_t n = c.P.n_free;
+      for (int k0 = 0; k0 < nrhs; k0 += c.max_rhs) {
+        const int K = std::min(c.max_rhs, nrhs - k0);
+        cm_to_il(n, K, r_dev + (int64_t)k0 * ld, ld, c.d_xin, st);
+        apply_precond_multi(c, c.d_xin, c.d_xout, K, st);
+        il_to_cm(n, K, c.d_xout, z_dev + (int64_t)k0 * ld, ld, st);
+      }
+      GDSW_HIP(hipGetLastError());
+      return;
+    }
+    for (int k = 0; k < nrhs; ++k) apply_precond(c, r_dev + (int64_t)k * ld, z_dev + (int64_t)k * ld, st);
   });
 }
 
@@ -239,6 +254,34 @@ gdsw_status gdsw_fgmres_solve(gdsw_ctx* ctx, const double* b_dev, double* x_dev,
     return fail(ctx, GDSW_EINVAL, "need 1 <= restart <= 200, max_it >= 1, rtol > 0");
   bool all_conv = true;
   gdsw_status s = guarded(ctx, [&]() {
+    Context& c = ctx->c;
+    hipStream_t st = (hipStream_t)stream;
+    if (nrhs > 1 && multi_supported(c)) {
+      const int64_t n = c.P.n_free;
+      for (int k0 = 0; k0 < nrhs; k0 += c.max_rhs) {
+        const int K = std::min(c.max_rhs, nrhs - k0);
+        const auto t0 = std::chrono::steady_clock::now();
+        GDSW_HIP(hipStreamSynchronize(st));
+        ensure_multi_workspace(c, opts->restart, K);  // before the right-hand sides are placed in it
+        cm_to_il(n, K, b_dev + (int64_t)k0 * ld, ld, c.mk.b, st);
+        std::vector<FgmresResult> r =
+            fgmres_multi(c, c.mk.b, c.mk.x, K, opts->rtol, opts->restart, opts->max_it, st);
+        il_to_cm(n, K, c.mk.x, x_dev + (int64_t)k0 * ld, ld, st);
+        GDSW_HIP(hipStreamSynchronize(st));
+        const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        for (int j = 0; j < K; ++j) {
+          if (info) {
+            info[k0 + j].iterations = r[j].iterations;
+            info[k0 + j].restarts = r[j].restarts;
+            info[k0 + j].rel_res = r[j].rel;
+            info[k0 + j].true_rel_res = r[j].true_rel;
+            info[k0 + j].t_solve_s = t;
+          }
+          all_conv = all_conv && r[j].converged;
+        }
+      }
+      return;
+    }
     for (int k = 0; k < nrhs; ++k) {
       const auto t0 = std::chrono::steady_clock::now();
       FgmresResult r = fgmres(ctx->c, b_dev + (int64_t)k * ld, x_dev + (int64_t)k * ld, opts->rtol, opts->restart,
@@ -354,6 +397,43 @@ gdsw_status gdsw_profile_apply(gdsw_ctx* ctx, const double* r_dev, double* z_dev
   });
 }
 
+gdsw_status gdsw_kernel_timer(gdsw_ctx* ctx, int32_t enable) {
+  if (gdsw_status s = check_device_ctx(ctx)) return s;
+  return guarded(ctx, [&]() {
+    KernelTimer& T = ctx->c.timer;
+    if (enable) {
+      if (T.ev.empty()) {
+        T.ev.resize(2 * KernelTimer::CAP);
+        for (auto& e : T.ev) GDSW_HIP(hipEventCreate(&e));
+      }
+      T.used = 0;
+      T.bytes = 0.0;
+      T.on = true;
+      ctx->c.L1.timer = &T;
+    } else {
+      T.on = false;
+    }
+  });
+}
+
+gdsw_status gdsw_kernel_timer_read(gdsw_ctx* ctx, double* total_ms, int64_t* launches, uint64_t* bytes_per_launch) {
+  if (gdsw_status s = check_device_ctx(ctx)) return s;
+  if (!total_ms || !launches || !bytes_per_launch) return fail(ctx, GDSW_EINVAL, "NULL argument");
+  return guarded(ctx, [&]() {
+    const KernelTimer& T = ctx->c.timer;
+    double tot = 0.0;
+    if (T.used > 0) GDSW_HIP(hipEventSynchronize(T.ev[2 * T.used - 1]));
+    for (int i = 0; i < T.used; ++i) {
+      float t = 0.f;
+      GDSW_HIP(hipEventElapsedTime(&t, T.ev[2 * i], T.ev[2 * i + 1]));
+      tot += t;
+    }
+    *total_ms = tot;
+    *launches = T.used;
+    *bytes_per_launch = T.used > 0 ? (uint64_t)(T.bytes / T.used) : 0;
+  });
+}
+
 gdsw_status gdsw_learned_init(gdsw_ctx* ctx, uint64_t seed, gdsw_learned_info* info, void* stream) {
   if (gdsw_status s = check_device_ctx(ctx)) return s;
   return guarded(ctx, [&]() {
@@ -426,6 +506,9 @@ const char* gdsw_last_error(const gdsw_ctx* ctx) {
 void gdsw_destroy(gdsw_ctx* ctx) {
   if (!ctx) return;
   learned_release(ctx->c);
+  for (auto& e : ctx->c.timer.ev) (void)hipEventDestroy(e);
+  if (ctx->c.mk.h_pinned) (void)hipHostFree(ctx->c.mk.h_pinned);
+  if (ctx->c.mk.h_active) (void)hipHostFree(ctx->c.mk.h_active);
   ctx->c.arena.release_all();
   if (ctx->c.h_pinned) (void)hipHostFree(ctx->c.h_pinned);
   delete ctx;

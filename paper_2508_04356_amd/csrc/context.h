@@ -62,10 +62,24 @@ enum Precision { P_FP64 = 0, P_FP32 = 1, P_BF16 = 2 };
 // below the diagonal, U^-1 on and above it) are kept separately in `dinv`.
 constexpr int SOLVE_INVERSE = 0;  // explicit inverse, applied as a dense matrix-vector product
 constexpr int SOLVE_TRSV = 1;     // LU factors, blocked forward/backward substitution
-constexpr int GEMV_CW = 256;      // columns per matrix-vector work item
+#ifndef GDSW_GEMV_CW
+#define GDSW_GEMV_CW 1024
+#endif
+constexpr int GEMV_CW = GDSW_GEMV_CW;  // columns per matrix-vector work item
+
+// HIP events around each launch of a set's dominant solve kernel (slot 0),
+// for measuring its average duration inside a timed region.
+struct KernelTimer {
+  static constexpr int CAP = 8192;   // launch pairs recorded before it stops
+  bool on = false;
+  int used = 0;
+  double bytes = 0.0;                // algorithmic bytes of the recorded launches
+  std::vector<hipEvent_t> ev;        // 2 * CAP events, created on first enable
+};
 
 struct FactorSet {
   int mode = SOLVE_INVERSE;
+  KernelTimer* timer = nullptr;      // set while timing is enabled
   int prec = P_FP64;
   int nb = 128;                       // tile
   int count = 0;
@@ -102,7 +116,10 @@ struct FactorSet {
   std::vector<GemvPlan> gemv;
   double* d_partial = nullptr;
   int64_t partial_len = 0;
+  GemvPlan gemm;                     // several right-hand sides (all factors)
+  void* d_partial_m = nullptr;       // 32 * rows partial sums per gemm item
   uint64_t algorithmic_bytes() const;  // sum n^2 * sizeof(prec)
+  uint64_t alg_bytes = 0;              // algorithmic_bytes(), set when planned
   int64_t launches() const;            // solve kernel launches per pass (slot 0)
 };
 
@@ -117,6 +134,24 @@ struct Context {
   int local_prec = P_FP64;
   int solve_mode = SOLVE_INVERSE;
   int nb = 128;
+  KernelTimer timer;
+
+  // several right-hand sides (two levels, explicit inverses): up to max_rhs
+  // columns per pass, interleaved (entry (d, j) at x[d * max_rhs + j])
+  int max_rhs = 1;
+  double* d_wm = nullptr;          // n_w x max_rhs work vectors
+  double* d_xin = nullptr;         // n_free x max_rhs (ABI column-major input, interleaved)
+  double* d_xout = nullptr;
+  struct MultiKrylov {
+    int restart = 0, K = 0, nblocks = 0;
+    int64_t ldv = 0;               // n_free * K
+    double *V = nullptr, *Z = nullptr, *H = nullptr, *g = nullptr, *cs = nullptr, *sn = nullptr;
+    double *h1 = nullptr, *h2 = nullptr, *part = nullptr, *scal = nullptr, *t1 = nullptr, *t2 = nullptr;
+    double *b = nullptr, *x = nullptr, *y = nullptr;
+    int32_t* active = nullptr;
+    double* h_pinned = nullptr;    // 4 * K doubles
+    int32_t* h_active = nullptr;   // K ints (pinned)
+  } mk;
 
   // system matrix (free DOFs)
   int32_t* d_rowptr = nullptr;
@@ -211,5 +246,14 @@ struct FgmresResult {
 FgmresResult fgmres(Context& ctx, const double* b, double* x, double rtol, int restart, int max_it,
                     bool use_graph, hipStream_t st, double* history = nullptr, int history_len = 0);
 void expand_solution(const Context& ctx, const double* xf, double* xfull, hipStream_t st);
+
+// several right-hand sides (solve_multi.hip): blocks of K <= max_rhs
+// interleaved columns (entry (d, j) at x[d * K + j])
+void plan_gemm(FactorSet& fs, DeviceArena& A, hipStream_t st);
+bool multi_supported(const Context& ctx);
+void ensure_multi_workspace(Context& ctx, int restart, int K);
+void apply_precond_multi(Context& ctx, const double* r, double* z, int K, hipStream_t st);
+std::vector<FgmresResult> fgmres_multi(Context& ctx, const double* b_il, double* x_il, int K, double rtol,
+                                       int restart, int max_it, hipStream_t st);
 
 }  // namespace gdsw

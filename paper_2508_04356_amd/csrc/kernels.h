@@ -55,6 +55,15 @@ void convert_store(int prec, const double* src, void* dst, int64_t count, hipStr
 int gemv_rows(int prec);
 // x_f <- M_f x_f for every stored inverse M_f of the set, in place on w.
 void gemv_set(const FactorSet& fs, double* w, hipStream_t st, int slot = 0, const int32_t* want = nullptr);
+// Rows per multi-RHS work item for a storage precision.
+int gemm_rows(int prec);
+// M <- (M + M^T) / 2 for every matrix of the batch.
+void symmetrize(const DenseBatch& B, hipStream_t st);
+// X_f <- M_f X_f for nrhs right-hand sides of the interleaved work buffer
+// (entry (row, j) at w[row * ldk + j]), every stored inverse of the set
+// (MFMA; FP32 accumulation for FP32 and BF16 storage, the right-hand sides
+// rounded to the storage type).
+void gemm_set(const FactorSet& fs, double* w, int64_t ldk, int nrhs, hipStream_t st);
 // The set's local solve in its mode (inverse product or triangular solves).
 void local_solve_set(const FactorSet& fs, double* w, hipStream_t st, int slot = 0, const int32_t* want = nullptr);
 

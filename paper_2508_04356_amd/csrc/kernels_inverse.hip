@@ -1,25 +1,19 @@
-// Explicit inverses of the local (and coarse) matrices, and their application.
+// Explicit inverses of the local and coarse matrices (setup).
 //
 // The preconditioner of eq. (2.2) / (2.5) needs A_i^-1 R_i r for every local
 // matrix A_i, and the same for the coarse matrices.  Instead of a forward and
 // backward substitution, whose 2 * nblk dependent steps are latency bound on
 // a 256-CU device, the setup forms A_i^-1 once (Gauss-Jordan elimination
 // without pivoting, in the velocity-first order whose pivots are the pivots
-// of the no-pivoting LU) and every apply is one batched dense
-// matrix-vector product: the same n^2 entries per matrix are streamed from HBM
-// as by the triangular solves, with no dependency chain.
+// of the no-pivoting LU), symmetrises it (A_i is symmetric, eq. 2.1) and
+// stores it in the precision of the set.  Every apply then streams the same
+// n^2 entries per matrix as the triangular solves would, with no dependency
+// chain (kernels_gemv.hip, kernels_gemm.hip).
 //
-// * gj_invert: blocked in-place Gauss-Jordan with 64-wide blocks.  Step k
-//   inverts the pivot block P = A_kk^-1 (one work-group per matrix, in LDS),
-//   forms T = P A_k* (row panel), updates A_ij -= A_ik T_j for every i, j != k
-//   (64 x 64 tiles), then sets A_ik <- -A_ik P and A_kj <- T_j.
-// * gemv_set: y = A^-1 x for every matrix of a factor set, in place on the
-//   work vector.  Kernel 1: one work-group per (matrix, row block of 64 * E
-//   rows, chunk of 256 columns), each lane owning E consecutive rows of a
-//   column (one 16-byte load per column), the waves splitting the columns;
-//   it writes one partial vector per item.  Kernel 2 sums the partials of a
-//   row block in chunk order (a fixed order: results are bitwise
-//   reproducible) and writes the result over x.
+// gj_invert: blocked in-place Gauss-Jordan with 64-wide blocks.  Step k
+// inverts the pivot block P = A_kk^-1 (one work-group per matrix, in LDS),
+// forms T = P A_k* (row panel), updates A_ij -= A_ik T_j for every i, j != k
+// (64 x 64 tiles), then sets A_ik <- -A_ik P and A_kj <- T_j.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -257,104 +251,9 @@ __global__ __launch_bounds__(256) void gj_panel_kernel(double* __restrict__ base
   }
 }
 
-// ---- batched dense matrix-vector product ----------------------------------
-
-// Item (f, r0, c0, p): rows [r0, r0 + 64 E) and columns [c0, c0 + GEMV_CW)
-// of matrix f; partial[p * 64 E + row] = sum over those columns of M x.
-template <typename T, int NW>
-__global__ __launch_bounds__(64 * NW) void gemv_part_kernel(const T* __restrict__ store,
-                                                           const int64_t* __restrict__ OFF,
-                                                           const int32_t* __restrict__ N,
-                                                           const int32_t* __restrict__ NP,
-                                                           const int64_t* __restrict__ XOFF,
-                                                           const int4* __restrict__ items,
-                                                           const double* __restrict__ w,
-                                                           double* __restrict__ partial,
-                                                           const int32_t* __restrict__ want) {
-  using AT = typename VecW<T>::acc;
-  constexpr int E = VecW<T>::W;
-  constexpr int RB = 64 * E;
-  __shared__ AT xs[GEMV_CW];
-  __shared__ AT red[NW][RB];
-  const int4 item = items[blockIdx.x];
-  const int f = item.x, r0 = item.y, c0 = item.z, p = item.w;
-  if (want && !want[f]) return;  // uniform per work-group
-  const int n = N[f];
-  const int64_t np = NP[f];
-  const int ncols = min(GEMV_CW, n - c0);
-  const int tid = threadIdx.x;
-  const double* x = w + XOFF[f] + c0;
-  for (int i = tid; i < GEMV_CW; i += 64 * NW) xs[i] = i < ncols ? (AT)x[i] : (AT)0;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int rr = r0 + lane * E;
-  const bool active = rr < n;
-  const T* col = store + OFF[f] + (int64_t)c0 * np + rr;
-  AT acc[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) acc[e] = 0;
-  __syncthreads();
-  if (active) {
-    constexpr int U = 8;
-    int c = wave;
-    for (; c + (U - 1) * NW < ncols; c += U * NW) {
-      AT v[U][E];
-#pragma unroll
-      for (int u = 0; u < U; ++u) load16(col + (int64_t)(c + u * NW) * np, v[u]);
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const AT xv = xs[c + u * NW];
-#pragma unroll
-        for (int e = 0; e < E; ++e) acc[e] = fma(v[u][e], xv, acc[e]);
-      }
-    }
-    for (; c < ncols; c += NW) {
-      AT v[E];
-      load16(col + (int64_t)c * np, v);
-      const AT xv = xs[c];
-#pragma unroll
-      for (int e = 0; e < E; ++e) acc[e] = fma(v[e], xv, acc[e]);
-    }
-  }
-#pragma unroll
-  for (int e = 0; e < E; ++e) red[wave][lane * E + e] = acc[e];
-  __syncthreads();
-  for (int r = tid; r < RB; r += 64 * NW) {
-    double s = 0.0;
-#pragma unroll
-    for (int q = 0; q < NW; ++q) s += (double)red[q][r];
-    partial[(int64_t)p * RB + r] = s;
-  }
-}
-
-// Item (f, r0, p0, cnt): x[r0 + t] = sum_{q < cnt} partial[(p0 + q) * RB + t].
-template <int RB>
-__global__ __launch_bounds__(256) void gemv_sum_kernel(const int32_t* __restrict__ N,
-                                                       const int64_t* __restrict__ XOFF,
-                                                       const int4* __restrict__ items,
-                                                       const double* __restrict__ partial, double* __restrict__ w,
-                                                       const int32_t* __restrict__ want) {
-  const int4 item = items[blockIdx.x];
-  const int f = item.x, r0 = item.y, p0 = item.z, cnt = item.w;
-  if (want && !want[f]) return;
-  const int n = N[f];
-  for (int t = threadIdx.x; t < RB; t += 256) {
-    if (r0 + t >= n) break;
-    double s = 0.0;
-    for (int q = 0; q < cnt; ++q) s += partial[(int64_t)(p0 + q) * RB + t];
-    w[XOFF[f] + r0 + t] = s;
-  }
-}
-
 __global__ void convert_f32_kernel(const double* __restrict__ src, float* __restrict__ dst, int64_t count) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
     dst[i] = (float)src[i];
-}
-
-__device__ inline uint16_t to_bf16(float x) {
-  uint32_t u = __float_as_uint(x);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
-  return (uint16_t)(u >> 16);
 }
 
 __global__ void convert_bf16_kernel(const double* __restrict__ src, uint16_t* __restrict__ dst, int64_t count) {
@@ -362,19 +261,25 @@ __global__ void convert_bf16_kernel(const double* __restrict__ src, uint16_t* __
     dst[i] = to_bf16((float)src[i]);
 }
 
-template <typename T>
-void gemv_launch(const FactorSet& fs, double* w, hipStream_t st, int slot, const int32_t* want) {
-  const FactorSet::GemvPlan& G = fs.gemv[slot];
-  if (G.n1 == 0) return;
-  constexpr int RB = 64 * VecW<T>::W;
-  gemv_part_kernel<T, 4><<<G.n1, 256, 0, st>>>(static_cast<const T*>(fs.store), fs.d_off, fs.d_n, fs.d_npad,
-                                               fs.d_xoff, G.d_items1, w, fs.d_partial, want);
-  gemv_sum_kernel<RB><<<G.n2, 256, 0, st>>>(fs.d_n, fs.d_xoff, G.d_items2, fs.d_partial, w, want);
+// M <- (M + M^T) / 2 on the n x n block of every matrix (the inverse of a
+// symmetric matrix, freed of the asymmetry left by rounding).  One thread
+// per pair (r > c) of a 64 x 64 tile pair.
+__global__ void symmetrize_kernel(double* __restrict__ base, const int32_t* __restrict__ N,
+                                  const int32_t* __restrict__ LD, const int64_t* __restrict__ OFF) {
+  const int f = blockIdx.z;
+  const int n = N[f];
+  const int r = blockIdx.x * 16 + (threadIdx.x & 15);
+  const int c = blockIdx.y * 16 + (threadIdx.x >> 4);
+  if (r >= n || c >= n || r <= c) return;
+  const int64_t ld = LD[f];
+  double* A = base + OFF[f];
+  const double a = A[(int64_t)c * ld + r], b = A[(int64_t)r * ld + c];
+  const double m = 0.5 * (a + b);
+  A[(int64_t)c * ld + r] = m;
+  A[(int64_t)r * ld + c] = m;
 }
 
 }  // namespace
-
-int gemv_rows(int prec) { return prec == P_FP64 ? 128 : prec == P_FP32 ? 256 : 512; }
 
 void gj_invert(const DenseBatch& B, double* Pbuf, double* Tbuf, int64_t tstride, unsigned long long* minpiv,
                hipStream_t st) {
@@ -398,22 +303,11 @@ void convert_store(int prec, const double* src, void* dst, int64_t count, hipStr
   GDSW_HIP(hipGetLastError());
 }
 
-void gemv_set(const FactorSet& fs, double* w, hipStream_t st, int slot, const int32_t* want) {
-  if (fs.count == 0 || slot >= (int)fs.gemv.size()) return;
-  if (fs.prec == P_FP64)
-    gemv_launch<double>(fs, w, st, slot, want);
-  else if (fs.prec == P_FP32)
-    gemv_launch<float>(fs, w, st, slot, want);
-  else
-    gemv_launch<uint16_t>(fs, w, st, slot, want);
+void symmetrize(const DenseBatch& B, hipStream_t st) {
+  if (B.count == 0 || B.max_n == 0) return;
+  const int t = (B.max_n + 15) / 16;
+  symmetrize_kernel<<<dim3(t, t, B.count), 256, 0, st>>>(B.base, B.n, B.ld, B.off);
   GDSW_HIP(hipGetLastError());
-}
-
-void local_solve_set(const FactorSet& fs, double* w, hipStream_t st, int slot, const int32_t* want) {
-  if (fs.mode == SOLVE_INVERSE)
-    gemv_set(fs, w, st, slot, want);
-  else
-    trsv_set(fs, w, st, slot, want);
 }
 
 }  // namespace gdsw

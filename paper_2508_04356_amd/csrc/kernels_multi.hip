@@ -1,0 +1,274 @@
+// Several right-hand sides at once: vector kernels on the interleaved layout.
+//
+// A block of K <= 32 vectors of length n is stored interleaved: entry (d, j)
+// at x[d * K + j], so that the K values of one DOF are contiguous and every
+// kernel below reads and writes whole rows of K values.  The ABI's
+// column-major blocks are converted at entry and exit (tiled transposes).
+// Reductions run in a fixed order per right-hand side, as in the single
+// vector kernels, so results are bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "kernels.h"
+#include "kernels_multi.h"
+
+namespace gdsw {
+namespace {
+
+inline int grid_for(int64_t n, int bs = 256, int cap = 65536) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(cap, (n + bs - 1) / bs));
+}
+
+// column-major (ld) <-> interleaved (K), 64 rows x K columns per block via LDS
+__global__ __launch_bounds__(256) void cm_to_il_kernel(int64_t n, int K, const double* __restrict__ src, int64_t ld,
+                                                       double* __restrict__ dst) {
+  __shared__ double t[32][65];
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  for (int e = threadIdx.x; e < 64 * K; e += 256) {
+    const int r = e % 64, j = e / 64;
+    t[j][r] = r0 + r < n ? src[(int64_t)j * ld + r0 + r] : 0.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * K; e += 256) {
+    const int j = e % K, r = e / K;
+    if (r0 + r < n) dst[(r0 + r) * K + j] = t[j][r];
+  }
+}
+
+__global__ __launch_bounds__(256) void il_to_cm_kernel(int64_t n, int K, const double* __restrict__ src,
+                                                       double* __restrict__ dst, int64_t ld) {
+  __shared__ double t[32][65];
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  for (int e = threadIdx.x; e < 64 * K; e += 256) {
+    const int j = e % K, r = e / K;
+    t[j][r] = r0 + r < n ? src[(r0 + r) * K + j] : 0.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * K; e += 256) {
+    const int r = e % 64, j = e / 64;
+    if (r0 + r < n) dst[(int64_t)j * ld + r0 + r] = t[j][r];
+  }
+}
+
+// w[p, :] = r[idx[p], :] (0 where idx < 0)
+__global__ void gather_il_kernel(int64_t count, int K, const int32_t* __restrict__ idx, const double* __restrict__ src,
+                                 double* __restrict__ dst) {
+  const int64_t total = count * K;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = e / K;
+    const int j = (int)(e - p * K);
+    const int32_t g = idx[p];
+    dst[e] = g >= 0 ? src[(int64_t)g * K + j] : 0.0;
+  }
+}
+
+// w[out_pos[c], :] = (Phi^T r)[c, :]; one block per coarse column, threads
+// (8 entry lanes) x (32 right-hand sides), fixed-order combination.
+__global__ __launch_bounds__(256) void restrict_il_kernel(int nc, int K, CoarseView cv, const double* __restrict__ r,
+                                                          double* __restrict__ w, const int32_t* __restrict__ out_pos) {
+  __shared__ double sh[8][32];
+  const int c = blockIdx.x;
+  const int j = threadIdx.x & 31, el = threadIdx.x >> 5;
+  double s = 0.0;
+  if (j < K) {
+    for (int e = cv.cg_ptr[c] + el; e < cv.cg_ptr[c + 1]; e += 8) s += r[(int64_t)cv.cg_dof[e] * K + j];
+    for (int e = cv.cs_ptr[c]; e < cv.cs_ptr[c + 1]; ++e) {
+      const int i = cv.cs_sub[e], lc = cv.cs_lc[e];
+      const int ib = cv.I_ptr[i], ni = cv.I_ptr[i + 1] - ib;
+      const double* ph = cv.phi_cm + cv.phi_off[i] + (int64_t)lc * ni;
+      for (int k = el; k < ni; k += 8) s = fma(ph[k], r[(int64_t)cv.I_idx[ib + k] * K + j], s);
+    }
+  }
+  sh[el][j] = s;
+  __syncthreads();
+  if (el == 0 && j < K) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) t += sh[q][j];
+    w[(int64_t)out_pos[c] * K + j] = t;
+  }
+}
+
+// z[d, :] = sum of local copies (ascending subdomain) + (Phi y_0)[d, :],
+// y_0 read from the work vector at y0_pos (or absent when cv.gamma_col is null).
+__global__ void scatter_prolong_il_kernel(int64_t n, int K, const int32_t* __restrict__ inv_ptr,
+                                          const int64_t* __restrict__ inv_pos, const double* __restrict__ w,
+                                          CoarseView cv, const int32_t* __restrict__ y0_pos, double* __restrict__ z) {
+  const int64_t total = n * K;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t d = e / K;
+    const int j = (int)(e - d * K);
+    double s = 0.0;
+    for (int q = inv_ptr[d]; q < inv_ptr[d + 1]; ++q) s += w[inv_pos[q] * K + j];
+    double c = 0.0;
+    if (y0_pos) {
+      const int32_t gc = cv.gamma_col[d];
+      if (gc >= 0) {
+        c = w[(int64_t)y0_pos[gc] * K + j];
+      } else {
+        const int32_t p = cv.dof_ipos[d];
+        if (p >= 0) {
+          const int i = cv.I_sub[p];
+          const int k = p - cv.I_ptr[i];
+          const int cb = cv.C_ptr[i], ncol = cv.C_ptr[i + 1] - cb;
+          const double* row = cv.phi_rm + cv.phi_off[i] + (int64_t)k * ncol;
+          for (int q = 0; q < ncol; ++q) c = fma(row[q], w[(int64_t)y0_pos[cv.C_idx[cb + q]] * K + j], c);
+        }
+      }
+    }
+    z[e] = s + c;
+  }
+}
+
+// Y = A X for K interleaved vectors: 8 rows per block, one lane per right-hand side.
+__global__ __launch_bounds__(256) void spmm_il_kernel(int64_t nrows, int K, const int32_t* __restrict__ rowptr,
+                                                      const int32_t* __restrict__ col, const double* __restrict__ val,
+                                                      const double* __restrict__ x, double* __restrict__ y) {
+  const int64_t row = (int64_t)blockIdx.x * 8 + (threadIdx.x >> 5);
+  const int j = threadIdx.x & 31;
+  if (row >= nrows || j >= K) return;
+  double s = 0.0;
+  for (int k = rowptr[row]; k < rowptr[row + 1]; ++k) s = fma(val[k], x[(int64_t)col[k] * K + j], s);
+  y[row * K + j] = s;
+}
+
+constexpr int DCH = 256;  // rows per partial block of the dot products
+
+// part[(b * ncols + i) * K + j] = sum over rows of block b of V_i[r, j] * w[r, j]
+__global__ __launch_bounds__(256) void dots_il_partial_kernel(const double* __restrict__ V, int64_t ldv, int ncols,
+                                                              const double* __restrict__ w, int64_t n, int K,
+                                                              double* __restrict__ part) {
+  __shared__ double sh[8][32];
+  const int b = blockIdx.x;
+  const int j = threadIdx.x & 31, rl = threadIdx.x >> 5;
+  const int64_t r0 = (int64_t)b * DCH;
+  double wr[DCH / 8];
+#pragma unroll
+  for (int q = 0; q < DCH / 8; ++q) {
+    const int64_t r = r0 + q * 8 + rl;
+    wr[q] = (r < n && j < K) ? w[r * K + j] : 0.0;
+  }
+  for (int i = 0; i < ncols; ++i) {
+    const double* v = V + (int64_t)i * ldv;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < DCH / 8; ++q) {
+      const int64_t r = r0 + q * 8 + rl;
+      if (r < n && j < K) s = fma(v[r * K + j], wr[q], s);
+    }
+    sh[rl][j] = s;
+    __syncthreads();
+    if (rl == 0 && j < K) {
+      double t = 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) t += sh[q][j];
+      part[((int64_t)b * ncols + i) * K + j] = t;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void dots_il_final_kernel(const double* __restrict__ part, int nblocks, int ncols,
+                                                            int K, double* __restrict__ out) {
+  __shared__ double sh[8][32];
+  const int i = blockIdx.x;
+  const int j = threadIdx.x & 31, bl = threadIdx.x >> 5;
+  double s = 0.0;
+  if (j < K)
+    for (int b = bl; b < nblocks; b += 8) s += part[((int64_t)b * ncols + i) * K + j];
+  sh[bl][j] = s;
+  __syncthreads();
+  if (bl == 0 && j < K) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) t += sh[q][j];
+    out[(int64_t)i * K + j] = t;
+  }
+}
+
+// w[r, j] -= sum_i V_i[r, j] h[i, j]   (sign = -1)   or   x += ...   (sign = +1)
+__global__ void gemv_il_kernel(const double* __restrict__ V, int64_t ldv, int ncols, const double* __restrict__ h,
+                               double* __restrict__ w, int64_t n, int K, double sign) {
+  const int64_t total = n * K;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(e % K);
+    double s = 0.0;
+    for (int i = 0; i < ncols; ++i) s = fma(V[(int64_t)i * ldv + e], h[(int64_t)i * K + j], s);
+    w[e] += sign * s;
+  }
+}
+
+// v[r, j] = active[j] && s[j] != 0 ? w[r, j] / s[j] : 0
+__global__ void scale_il_kernel(int64_t n, int K, const double* __restrict__ w, const double* __restrict__ s,
+                                const int32_t* __restrict__ active, double* __restrict__ v) {
+  const int64_t total = n * K;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(e % K);
+    const double d = s[j];
+    v[e] = (active[j] && d != 0.0) ? w[e] / d : 0.0;
+  }
+}
+
+__global__ void sub_il_kernel(int64_t total, const double* __restrict__ b, double* __restrict__ r) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
+    r[e] = b[e] - r[e];
+}
+
+}  // namespace
+
+void cm_to_il(int64_t n, int K, const double* src, int64_t ld, double* dst, hipStream_t st) {
+  if (n == 0) return;
+  cm_to_il_kernel<<<(unsigned)((n + 63) / 64), 256, 0, st>>>(n, K, src, ld, dst);
+}
+
+void il_to_cm(int64_t n, int K, const double* src, double* dst, int64_t ld, hipStream_t st) {
+  if (n == 0) return;
+  il_to_cm_kernel<<<(unsigned)((n + 63) / 64), 256, 0, st>>>(n, K, src, dst, ld);
+}
+
+void gather_il(int64_t count, int K, const int32_t* idx, const double* src, double* dst, hipStream_t st) {
+  if (count == 0) return;
+  gather_il_kernel<<<grid_for(count * K), 256, 0, st>>>(count, K, idx, src, dst);
+}
+
+void restrict_il(int nc, int K, const CoarseView& cv, const double* r, double* w, const int32_t* out_pos,
+                 hipStream_t st) {
+  if (nc == 0) return;
+  restrict_il_kernel<<<nc, 256, 0, st>>>(nc, K, cv, r, w, out_pos);
+}
+
+void scatter_prolong_il(int64_t n, int K, const int32_t* inv_ptr, const int64_t* inv_pos, const double* w,
+                        const CoarseView& cv, const int32_t* y0_pos, double* z, hipStream_t st) {
+  if (n == 0) return;
+  scatter_prolong_il_kernel<<<grid_for(n * K), 256, 0, st>>>(n, K, inv_ptr, inv_pos, w, cv, y0_pos, z);
+}
+
+void spmm_il(int64_t nrows, int K, const int32_t* rowptr, const int32_t* col, const double* val, const double* x,
+             double* y, hipStream_t st) {
+  if (nrows == 0) return;
+  spmm_il_kernel<<<(unsigned)((nrows + 7) / 8), 256, 0, st>>>(nrows, K, rowptr, col, val, x, y);
+}
+
+int dots_il_blocks(int64_t n) { return (int)((n + DCH - 1) / DCH); }
+
+void dots_il(const double* V, int64_t ldv, int ncols, const double* w, int64_t n, int K, double* part, int nblocks,
+             double* out, hipStream_t st) {
+  dots_il_partial_kernel<<<nblocks, 256, 0, st>>>(V, ldv, ncols, w, n, K, part);
+  dots_il_final_kernel<<<ncols, 256, 0, st>>>(part, nblocks, ncols, K, out);
+}
+
+void gemv_il(const double* V, int64_t ldv, int ncols, const double* h, double* w, int64_t n, int K, double sign,
+             hipStream_t st) {
+  gemv_il_kernel<<<grid_for(n * K), 256, 0, st>>>(V, ldv, ncols, h, w, n, K, sign);
+}
+
+void scale_il(int64_t n, int K, const double* w, const double* s, const int32_t* active, double* v, hipStream_t st) {
+  scale_il_kernel<<<grid_for(n * K), 256, 0, st>>>(n, K, w, s, active, v);
+}
+
+void sub_il(int64_t total, const double* b, double* r, hipStream_t st) {
+  sub_il_kernel<<<grid_for(total), 256, 0, st>>>(total, b, r);
+}
+
+}  // namespace gdsw

@@ -118,6 +118,31 @@ void plan_gemv(FactorSet& fs, DeviceArena& A, hipStream_t st, int slot, const st
 
 }  // namespace
 
+void plan_gemm(FactorSet& fs, DeviceArena& A, hipStream_t st) {
+  if (fs.mode != SOLVE_INVERSE || fs.count == 0) return;
+  const int RB = gemm_rows(fs.prec);
+  std::vector<int4> it1, it2;
+  int p = 0;
+  for (int f = 0; f < fs.count; ++f) {
+    const int n = fs.n[f];
+    const int nr = (n + RB - 1) / RB, nc = (n + GEMV_CW - 1) / GEMV_CW;
+    for (int c = 0; c < nc; ++c)
+      for (int J = 0; J < nr; ++J) it1.push_back(make_int4(f, J * RB, c * GEMV_CW, p + J * nc + c));
+    for (int J = 0; J < nr; ++J) it2.push_back(make_int4(f, J * RB, p + J * nc, nc));
+    p += nr * nc;
+  }
+  FactorSet::GemvPlan& G = fs.gemm;
+  if (G.d_items1) A.free(G.d_items1);
+  if (G.d_items2) A.free(G.d_items2);
+  if (fs.d_partial_m) A.free(fs.d_partial_m);
+  G.n1 = (int)it1.size();
+  G.n2 = (int)it2.size();
+  G.d_items1 = it1.empty() ? nullptr : dupload(A, it1, st);
+  G.d_items2 = it2.empty() ? nullptr : dupload(A, it2, st);
+  const size_t psz = fs.prec == P_FP64 ? 8 : 4;
+  fs.d_partial_m = A.alloc((uint64_t)std::max(p, 1) * RB * 32 * psz);
+}
+
 void plan_schedule(FactorSet& fs, int phases, DeviceArena& A, hipStream_t st, int slot,
                    const std::vector<char>* include) {
   if (fs.mode == SOLVE_INVERSE) {
@@ -199,6 +224,7 @@ void plan_factor_set(FactorSet& fs, const std::vector<int32_t>& sizes, int prec,
   fs.d_off = dupload(A, fs.off, st);
   fs.d_doff = dupload(A, fs.doff, st);
   fs.d_xoff = dupload(A, fs.xoff, st);
+  fs.alg_bytes = fs.algorithmic_bytes();
   plan_schedule(fs, 1, A, st);
 }
 
@@ -292,6 +318,7 @@ void factor_set(Context& ctx, FactorSet& fs, uint64_t staging_cap, double pivot_
       double* Tbuf = dalloc<double>(A, (int64_t)cnt * tstride);
       gj_invert(B, Pbuf, Tbuf, tstride, mp, st);
       check_pivots(mp, cnt, pivot_tol, what, st);
+      symmetrize(B, st);
       if (fs.prec != P_FP64)
         convert_store(fs.prec, staging, static_cast<char*>(fs.store) + (size_t)fs.off[f0] * es, (int64_t)(bytes / 8),
                       st);
@@ -797,6 +824,15 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
   for (int f = 0; f < P.n_sub; ++f)
     ctx.factor_bytes += (uint64_t)ctx.L1.npad[f] * ctx.L1.npad[f] * elem_size(ctx.local_prec);
   ctx.coarse_bytes = (uint64_t)Nc * Nc * 8 * 2 + (uint64_t)phi_off.back() * 16;
+  // several right-hand sides: MFMA work plans and interleaved work buffers
+  if (ctx.max_rhs > 1 && ctx.solve_mode == SOLVE_INVERSE) {
+    plan_gemm(ctx.L1, A, st);
+    plan_gemm(ctx.HI, A, st);
+    const int K = ctx.max_rhs;
+    ctx.d_wm = dalloc<double>(A, std::max<int64_t>(ctx.n_w, 1) * K);
+    ctx.d_xin = dalloc<double>(A, std::max<int64_t>(n, 1) * K);
+    ctx.d_xout = dalloc<double>(A, std::max<int64_t>(n, 1) * K);
+  }
   GDSW_HIP(hipStreamSynchronize(st));
 }
 

@@ -26,6 +26,33 @@ struct VecW<uint16_t> {
   using acc = float;
 };
 
+// Streaming variants: the loads carry the non-temporal hint, so data read
+// once does not displace reusable lines from the caches.
+typedef double gdsw_d2 __attribute__((ext_vector_type(2)));
+typedef float gdsw_f4 __attribute__((ext_vector_type(4)));
+typedef uint32_t gdsw_u4 __attribute__((ext_vector_type(4)));
+__device__ inline void load16_nt(const double* p, double (&o)[2]) {
+  const gdsw_d2 v = __builtin_nontemporal_load(reinterpret_cast<const gdsw_d2*>(p));
+  o[0] = v.x;
+  o[1] = v.y;
+}
+__device__ inline void load16_nt(const float* p, float (&o)[4]) {
+  const gdsw_f4 v = __builtin_nontemporal_load(reinterpret_cast<const gdsw_f4*>(p));
+  o[0] = v.x;
+  o[1] = v.y;
+  o[2] = v.z;
+  o[3] = v.w;
+}
+__device__ inline void load16_nt(const uint16_t* p, float (&o)[8]) {
+  const gdsw_u4 v = __builtin_nontemporal_load(reinterpret_cast<const gdsw_u4*>(p));
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    o[2 * i] = __uint_as_float(w[i] << 16);
+    o[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+  }
+}
+
 __device__ inline void load16(const double* p, double (&o)[2]) {
   const double2 v = *reinterpret_cast<const double2*>(p);
   o[0] = v.x;
@@ -46,6 +73,14 @@ __device__ inline void load16(const uint16_t* p, float (&o)[8]) {
     o[2 * i] = __uint_as_float(w[i] << 16);
     o[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
   }
+}
+
+// FP32 -> BF16 bits, round to nearest even (NaN stays NaN).
+__device__ inline uint16_t to_bf16(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+  return (uint16_t)(u >> 16);
 }
 
 }  // namespace gdsw
