@@ -331,6 +331,48 @@ const char* gdsw_last_error(const gdsw_ctx* ctx);
 /* Releases every device and host resource of ctx (NULL is allowed). */
 void gdsw_destroy(gdsw_ctx* ctx);
 
+/* Batches of independent problems ----------------------------------------
+ * count problems (each its own mesh and decomposition, e.g. different n,
+ * viscosity and inflow), each with its own context, whose level-1 and
+ * coarse-level inverse products run as ONE launch pair per level over the
+ * matrices of every member (longest matrix first).  Every member must use
+ * GDSW_SOLVE_INVERSE and the same local_precision.  A member computes
+ * exactly what it computes alone (same kernels and summation orders: the
+ * results are bitwise those of the member's own gdsw_apply_precond and
+ * gdsw_fgmres_solve). */
+typedef struct gdsw_batch gdsw_batch; /* opaque, owned by the library */
+
+/* Sets up every member (as gdsw_setup, each with its own budget check), then
+ * the merged launch plans.  On failure nothing is kept; the message names
+ * the member. */
+gdsw_status gdsw_setup_batch(const gdsw_mesh* meshes, const gdsw_decomposition* decs, int32_t count,
+                             void* stream, gdsw_batch** out);
+
+/* The context of member k (owned by the batch: use it for gdsw_rhs,
+ * gdsw_get_sizes, gdsw_spmv, gdsw_expand_solution; never destroy it). */
+gdsw_status gdsw_batch_member(gdsw_batch* batch, int32_t k, gdsw_ctx** member);
+
+/* z_k = M_k^-1 r_k for every member; r and z are host arrays of count
+ * device pointers (member k's vectors, length n_free of member k). */
+gdsw_status gdsw_apply_precond_batch(gdsw_batch* batch, const double* const* r_dev, double* const* z_dev,
+                                     void* stream);
+
+/* FGMRES on every member in lockstep from x = 0: one iteration advances
+ * every member that has not yet met its stopping test; a member that has is
+ * masked out of the shared launches.  info[count] may be NULL.  ENOCONV if
+ * a member reached max_it first. */
+gdsw_status gdsw_fgmres_solve_batch(gdsw_batch* batch, const double* const* b_dev, double* const* x_dev,
+                                    const gdsw_fgmres_opts* opts, gdsw_fgmres_info* info, void* stream);
+
+/* As gdsw_kernel_timer / gdsw_kernel_timer_read for the batch's merged
+ * level-1 partial-product launches (bytes: the matrices of the members
+ * active in each launch). */
+gdsw_status gdsw_batch_kernel_timer(gdsw_batch* batch, int32_t enable);
+gdsw_status gdsw_batch_kernel_timer_read(gdsw_batch* batch, double* total_ms, int64_t* launches,
+                                         uint64_t* bytes_per_launch);
+
+void gdsw_destroy_batch(gdsw_batch* batch);
+
 #ifdef __cplusplus
 }
 #endif

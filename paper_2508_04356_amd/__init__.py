@@ -95,6 +95,15 @@ _sig = {
     "gdsw_learned_stats": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "gdsw_last_error": (C.c_char_p, [_P]),
     "gdsw_destroy": (None, [_P]),
+    "gdsw_setup_batch": (C.c_int, [C.POINTER(Mesh), C.POINTER(Decomposition), C.c_int32, _P, C.POINTER(_P)]),
+    "gdsw_batch_member": (C.c_int, [_P, C.c_int32, C.POINTER(_P)]),
+    "gdsw_apply_precond_batch": (C.c_int, [_P, C.POINTER(_P), C.POINTER(_P), _P]),
+    "gdsw_fgmres_solve_batch": (C.c_int, [_P, C.POINTER(_P), C.POINTER(_P), C.POINTER(FgmresOpts),
+                                          C.POINTER(FgmresInfo), _P]),
+    "gdsw_batch_kernel_timer": (C.c_int, [_P, C.c_int32]),
+    "gdsw_batch_kernel_timer_read": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                               C.POINTER(C.c_uint64)]),
+    "gdsw_destroy_batch": (None, [_P]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -288,10 +297,22 @@ class Solver:
         _check(_lib.gdsw_learned_stats(self._ctx, C.byref(a), C.byref(b)), self._ctx)
         return a.value, b.value
 
+    @classmethod
+    def _borrowed(cls, ctx):
+        """A view of a context owned elsewhere (a batch member); close() leaves it alone."""
+        self = cls.__new__(cls)
+        self._ctx = ctx
+        self._owned = False
+        self.host_only = False
+        s = self.sizes()
+        self.n_free = s.n_free
+        self.n_coarse = s.n_coarse
+        return self
+
     def close(self):
-        if self._ctx:
+        if self._ctx and getattr(self, "_owned", True):
             _lib.gdsw_destroy(self._ctx)
-            self._ctx = C.c_void_p()
+        self._ctx = C.c_void_p()
 
     def __del__(self):
         try:
@@ -304,3 +325,67 @@ class Solver:
 
     def __exit__(self, *a):
         self.close()
+
+
+def _ptr_array(ts):
+    arr = (_P * len(ts))()
+    for k, t in enumerate(ts):
+        arr[k] = _ptr(t).value
+    return arr
+
+
+class Batch:
+    """Independent problems whose local and coarse inverse products share one
+    launch pair per level (a gdsw_batch).  problems: dicts with keys n, m and
+    optionally viscosity, inflow, manufactured, overlap."""
+
+    def __init__(self, problems, precision="fp64", stream=None, budget=0):
+        k = len(problems)
+        meshes = (Mesh * k)()
+        decs = (Decomposition * k)()
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        for i, p in enumerate(problems):
+            meshes[i] = Mesh(int(p["n"]), int(p.get("manufactured", 0)), float(p.get("viscosity", 1.0)),
+                             float(p.get("inflow", 16.0)))
+            decs[i] = Decomposition(int(p["m"]), int(p.get("overlap", 1)), 2, 2, prec, 0, 0, 0, budget, 0, 1)
+        self._b = C.c_void_p()
+        _check(_lib.gdsw_setup_batch(meshes, decs, k, _stream(stream), C.byref(self._b)))
+        self.members = []
+        for i in range(k):
+            c = C.c_void_p()
+            _check(_lib.gdsw_batch_member(self._b, i, C.byref(c)))
+            self.members.append(Solver._borrowed(c))
+
+    def apply(self, rs, zs, stream=None):
+        _check(_lib.gdsw_apply_precond_batch(self._b, _ptr_array(rs), _ptr_array(zs), _stream(stream)))
+        return zs
+
+    def fgmres(self, bs, xs, rtol=1e-8, restart=100, max_it=1000, stream=None, raise_on_noconv=True):
+        opts = FgmresOpts(rtol, restart, max_it, 0, 0, None)
+        infos = (FgmresInfo * len(self.members))()
+        st = _lib.gdsw_fgmres_solve_batch(self._b, _ptr_array(bs), _ptr_array(xs), C.byref(opts), infos,
+                                          _stream(stream))
+        if st != 4 or raise_on_noconv:
+            _check(st)
+        return [infos[k] for k in range(len(self.members))]
+
+    def kernel_timer(self, enable):
+        _check(_lib.gdsw_batch_kernel_timer(self._b, int(bool(enable))))
+
+    def kernel_timer_read(self):
+        ms, n, b = C.c_double(), C.c_int64(), C.c_uint64()
+        _check(_lib.gdsw_batch_kernel_timer_read(self._b, C.byref(ms), C.byref(n), C.byref(b)))
+        return ms.value, n.value, b.value
+
+    def close(self):
+        for m in self.members:
+            m._ctx = C.c_void_p()
+        if self._b:
+            _lib.gdsw_destroy_batch(self._b)
+            self._b = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -19,6 +19,11 @@ struct gdsw_ctx {
   Context c;
 };
 
+struct gdsw_batch {
+  std::vector<gdsw_ctx*> members;
+  Batch b;
+};
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -512,6 +517,125 @@ void gdsw_destroy(gdsw_ctx* ctx) {
   ctx->c.arena.release_all();
   if (ctx->c.h_pinned) (void)hipHostFree(ctx->c.h_pinned);
   delete ctx;
+}
+
+gdsw_status gdsw_setup_batch(const gdsw_mesh* meshes, const gdsw_decomposition* decs, int32_t count, void* stream,
+                             gdsw_batch** out) {
+  if (!out || !meshes || !decs) return fail(nullptr, GDSW_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (count < 1) return fail(nullptr, GDSW_EINVAL, "count must be >= 1");
+  gdsw_batch* bt = new (std::nothrow) gdsw_batch();
+  if (!bt) return fail(nullptr, GDSW_ENOMEM, "host allocation failed");
+  for (int k = 0; k < count; ++k) {
+    if (decs[k].local_solve != GDSW_SOLVE_INVERSE) {
+      gdsw_destroy_batch(bt);
+      return fail(nullptr, GDSW_EINVAL, "batch members need local_solve = GDSW_SOLVE_INVERSE");
+    }
+    gdsw_ctx* c = nullptr;
+    const gdsw_status s = gdsw_setup(&meshes[k], &decs[k], stream, &c);
+    if (s != GDSW_OK) {
+      const std::string msg = "batch member " + std::to_string(k) + ": " + g_last_error;
+      gdsw_destroy_batch(bt);
+      return fail(nullptr, s, msg);
+    }
+    bt->members.push_back(c);
+    bt->b.m.push_back(&c->c);
+  }
+  const gdsw_status s = guarded(nullptr, [&]() { batch_build(bt->b, (hipStream_t)stream); });
+  if (s != GDSW_OK) {
+    gdsw_destroy_batch(bt);
+    return s;
+  }
+  *out = bt;
+  return GDSW_OK;
+}
+
+gdsw_status gdsw_batch_member(gdsw_batch* batch, int32_t k, gdsw_ctx** member) {
+  if (!batch || !member) return fail(nullptr, GDSW_EINVAL, "NULL argument");
+  if (k < 0 || k >= (int32_t)batch->members.size()) return fail(nullptr, GDSW_EINVAL, "member index out of range");
+  *member = batch->members[k];
+  return GDSW_OK;
+}
+
+gdsw_status gdsw_apply_precond_batch(gdsw_batch* batch, const double* const* r_dev, double* const* z_dev,
+                                     void* stream) {
+  if (!batch || !r_dev || !z_dev) return fail(nullptr, GDSW_EINVAL, "NULL argument");
+  for (size_t k = 0; k < batch->members.size(); ++k)
+    if (!r_dev[k] || !z_dev[k] || r_dev[k] == z_dev[k]) return fail(nullptr, GDSW_EINVAL, "bad vector for a member");
+  return guarded(nullptr, [&]() { apply_precond_batch(batch->b, r_dev, z_dev, (hipStream_t)stream); });
+}
+
+gdsw_status gdsw_fgmres_solve_batch(gdsw_batch* batch, const double* const* b_dev, double* const* x_dev,
+                                    const gdsw_fgmres_opts* opts, gdsw_fgmres_info* info, void* stream) {
+  if (!batch || !b_dev || !x_dev || !opts) return fail(nullptr, GDSW_EINVAL, "NULL argument");
+  if (opts->restart < 1 || opts->restart > 200 || opts->max_it < 1 || !(opts->rtol > 0.0))
+    return fail(nullptr, GDSW_EINVAL, "need 1 <= restart <= 200, max_it >= 1, rtol > 0");
+  for (size_t k = 0; k < batch->members.size(); ++k)
+    if (!b_dev[k] || !x_dev[k]) return fail(nullptr, GDSW_EINVAL, "NULL vector for a member");
+  bool all_conv = true;
+  const gdsw_status s = guarded(nullptr, [&]() {
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<FgmresResult> r =
+        fgmres_batch(batch->b, b_dev, x_dev, opts->rtol, opts->restart, opts->max_it, (hipStream_t)stream);
+    GDSW_HIP(hipStreamSynchronize((hipStream_t)stream));
+    const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (size_t k = 0; k < r.size(); ++k) {
+      if (info) {
+        info[k].iterations = r[k].iterations;
+        info[k].restarts = r[k].restarts;
+        info[k].rel_res = r[k].rel;
+        info[k].true_rel_res = r[k].true_rel;
+        info[k].t_solve_s = t;
+      }
+      all_conv = all_conv && r[k].converged;
+    }
+  });
+  if (s != GDSW_OK) return s;
+  if (!all_conv) return fail(nullptr, GDSW_ENOCONV, "a batch member reached max_it before rtol");
+  return GDSW_OK;
+}
+
+gdsw_status gdsw_batch_kernel_timer(gdsw_batch* batch, int32_t enable) {
+  if (!batch) return fail(nullptr, GDSW_EINVAL, "NULL batch");
+  return guarded(nullptr, [&]() {
+    KernelTimer& T = batch->b.timer;
+    if (enable) {
+      if (T.ev.empty()) {
+        T.ev.resize(2 * KernelTimer::CAP);
+        for (auto& e : T.ev) GDSW_HIP(hipEventCreate(&e));
+      }
+      T.used = 0;
+      T.bytes = 0.0;
+      T.on = true;
+    } else {
+      T.on = false;
+    }
+  });
+}
+
+gdsw_status gdsw_batch_kernel_timer_read(gdsw_batch* batch, double* total_ms, int64_t* launches,
+                                         uint64_t* bytes_per_launch) {
+  if (!batch || !total_ms || !launches || !bytes_per_launch) return fail(nullptr, GDSW_EINVAL, "NULL argument");
+  return guarded(nullptr, [&]() {
+    const KernelTimer& T = batch->b.timer;
+    double tot = 0.0;
+    if (T.used > 0) GDSW_HIP(hipEventSynchronize(T.ev[2 * T.used - 1]));
+    for (int i = 0; i < T.used; ++i) {
+      float t = 0.f;
+      GDSW_HIP(hipEventElapsedTime(&t, T.ev[2 * i], T.ev[2 * i + 1]));
+      tot += t;
+    }
+    *total_ms = tot;
+    *launches = T.used;
+    *bytes_per_launch = T.used > 0 ? (uint64_t)(T.bytes / T.used) : 0;
+  });
+}
+
+void gdsw_destroy_batch(gdsw_batch* batch) {
+  if (!batch) return;
+  batch_release(batch->b);
+  for (gdsw_ctx* c : batch->members) gdsw_destroy(c);
+  delete batch;
 }
 
 }  // extern "C"

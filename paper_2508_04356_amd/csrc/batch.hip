@@ -1,0 +1,135 @@
+// A batch of independent Stokes problems (eq. 2.1 with their own meshes,
+// viscosities and inflows), each with its own GDSW preconditioner, whose
+// local and coarse solves run together: one partial-product launch and one
+// summation launch per level cover the stored inverses of every member.
+// The work items are ordered longest matrix first, so the largest members'
+// matrices start first and the small ones fill in at the end.  Members that
+// have stopped (converged or out of iterations) are masked out of the
+// launches through a per-matrix flag.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <numeric>
+
+#include "context.h"
+#include "kernels.h"
+
+namespace gdsw {
+namespace {
+
+void build_set(Batch& b, BatchSet& S, bool level1, hipStream_t st) {
+  std::vector<GemvDesc> desc;
+  S.owner.clear();
+  S.bytes.clear();
+  S.prec = -1;
+  for (size_t k = 0; k < b.m.size(); ++k) {
+    Context& c = *b.m[k];
+    const FactorSet& fs = level1 ? c.L1 : c.HI;
+    if (fs.count == 0) continue;
+    if (fs.mode != SOLVE_INVERSE) throw StatusError{1, "batched solves need GDSW_SOLVE_INVERSE"};
+    if (S.prec >= 0 && S.prec != fs.prec) throw StatusError{1, "batch members must share the local precision"};
+    S.prec = fs.prec;
+    std::vector<GemvDesc> d = gemv_descs(fs, c.d_w);
+    for (int f = 0; f < fs.count; ++f) {
+      desc.push_back(d[f]);
+      S.owner.push_back((int)k);
+      S.bytes.push_back((uint64_t)fs.n[f] * fs.n[f] * elem_size(fs.prec));
+    }
+  }
+  S.count = (int)desc.size();
+  if (S.count == 0) return;
+  // longest matrix first (stable: ties keep member order)
+  std::vector<int> order(S.count);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return desc[a].n > desc[c].n; });
+  std::vector<GemvDesc> sd(S.count);
+  std::vector<int> so(S.count);
+  std::vector<uint64_t> sb(S.count);
+  for (int g = 0; g < S.count; ++g) {
+    sd[g] = desc[order[g]];
+    so[g] = S.owner[order[g]];
+    sb[g] = S.bytes[order[g]];
+  }
+  S.owner = so;
+  S.bytes = sb;
+  const int RB = gemv_rows(S.prec);
+  std::vector<int4> it1, it2;
+  int p = 0;
+  for (int f = 0; f < S.count; ++f) {
+    const int n = sd[f].n;
+    const int nr = (n + RB - 1) / RB, nc = (n + GEMV_CW - 1) / GEMV_CW;
+    for (int c = 0; c < nc; ++c)
+      for (int J = 0; J < nr; ++J) it1.push_back(make_int4(f, J * RB, c * GEMV_CW, p + J * nc + c));
+    for (int J = 0; J < nr; ++J) it2.push_back(make_int4(f, J * RB, p + J * nc, nc));
+    p += nr * nc;
+  }
+  DeviceArena& A = b.arena;
+  S.d_desc = dupload(A, sd, st);
+  S.plan.n1 = (int)it1.size();
+  S.plan.n2 = (int)it2.size();
+  S.plan.d_items1 = dupload(A, it1, st);
+  S.plan.d_items2 = dupload(A, it2, st);
+  S.d_partial = dalloc<double>(A, (int64_t)std::max(p, 1) * RB);
+  S.h_want.assign(S.count, 1);
+  S.d_want = dupload(A, S.h_want, st);
+  S.active_bytes = 0.0;
+  for (uint64_t v : S.bytes) S.active_bytes += (double)v;
+}
+
+void select_set(BatchSet& S, const std::vector<char>& active, hipStream_t st) {
+  if (S.count == 0) return;
+  bool same = true;
+  S.active_bytes = 0.0;
+  for (int g = 0; g < S.count; ++g) {
+    const int32_t v = active[S.owner[g]] ? 1 : 0;
+    same = same && v == S.h_want[g];
+    S.h_want[g] = v;
+    if (v) S.active_bytes += (double)S.bytes[g];
+  }
+  if (same) return;
+  // the stream is idle here (callers synchronise before selecting), so the
+  // host vector may be reused by the next call
+  GDSW_HIP(hipMemcpyAsync(S.d_want, S.h_want.data(), S.count * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  GDSW_HIP(hipStreamSynchronize(st));
+}
+
+}  // namespace
+
+void batch_build(Batch& b, hipStream_t st) {
+  build_set(b, b.s1, true, st);
+  build_set(b, b.s2, false, st);
+  GDSW_HIP(hipHostMalloc((void**)&b.h_pinned, std::max<size_t>(1, 4 * b.m.size()) * sizeof(double),
+                         hipHostMallocDefault));
+  GDSW_HIP(hipStreamSynchronize(st));
+}
+
+void batch_select(Batch& b, const std::vector<char>& member_active, hipStream_t st) {
+  select_set(b.s1, member_active, st);
+  select_set(b.s2, member_active, st);
+}
+
+void batch_local_solve(Batch& b, hipStream_t st) {
+  if (b.s1.count)
+    gemv_desc_launch(b.s1.prec, b.s1.d_desc, b.s1.plan, b.s1.d_partial, st, b.s1.d_want, &b.timer,
+                     b.s1.active_bytes);
+  if (b.s2.count)
+    gemv_desc_launch(b.s2.prec, b.s2.d_desc, b.s2.plan, b.s2.d_partial, st, b.s2.d_want, nullptr, 0.0);
+}
+
+void batch_release(Batch& b) {
+  for (auto& e : b.timer.ev) (void)hipEventDestroy(e);
+  b.timer.ev.clear();
+  if (b.h_pinned) (void)hipHostFree(b.h_pinned);
+  b.h_pinned = nullptr;
+  b.arena.release_all();
+}
+
+void apply_precond_batch(Batch& b, const double* const* r, double* const* z, hipStream_t st) {
+  batch_select(b, std::vector<char>(b.m.size(), 1), st);
+  for (size_t k = 0; k < b.m.size(); ++k) apply_pre(*b.m[k], r[k], st);
+  batch_local_solve(b, st);
+  for (size_t k = 0; k < b.m.size(); ++k) apply_post(*b.m[k], z[k], st);
+  GDSW_HIP(hipGetLastError());
+}
+
+}  // namespace gdsw

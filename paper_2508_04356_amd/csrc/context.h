@@ -54,6 +54,7 @@ T* dupload(DeviceArena& A, const std::vector<T>& v, hipStream_t st) {
 }
 
 enum Precision { P_FP64 = 0, P_FP32 = 1, P_BF16 = 2 };
+inline size_t elem_size(int prec) { return prec == P_FP64 ? 8 : (prec == P_FP32 ? 4 : 2); }
 
 // A batch of dense square matrices factored as A = L U without pivoting and
 // solved by the blocked triangular-solve kernels.  Each matrix is stored
@@ -66,6 +67,15 @@ constexpr int SOLVE_TRSV = 1;     // LU factors, blocked forward/backward substi
 #define GDSW_GEMV_CW 1024
 #endif
 constexpr int GEMV_CW = GDSW_GEMV_CW;  // columns per matrix-vector work item
+
+// One stored inverse for the matrix-vector kernels: its entries (column-major,
+// leading dimension np, in the set's precision) and its segment of a work
+// vector (n entries, overwritten with the product).
+struct GemvDesc {
+  const void* a;
+  double* x;
+  int32_t n, np;
+};
 
 // HIP events around each launch of a set's dominant solve kernel (slot 0),
 // for measuring its average duration inside a timed region.
@@ -114,6 +124,7 @@ struct FactorSet {
     int4* d_items2 = nullptr;
   };
   std::vector<GemvPlan> gemv;
+  GemvDesc* d_desc = nullptr;        // per factor, built once the store and work vector exist
   double* d_partial = nullptr;
   int64_t partial_len = 0;
   GemvPlan gemm;                     // several right-hand sides (all factors)
@@ -237,6 +248,10 @@ void plan_schedule(FactorSet& fs, int phases, DeviceArena& A, hipStream_t st, in
                    const std::vector<char>* include = nullptr);
 void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb);
 void apply_precond(Context& ctx, const double* r, double* z, hipStream_t st, hipEvent_t* ev = nullptr);
+// the two halves of apply_precond around the local and coarse solves:
+// right-hand sides into the work vector, and the sum back into z
+void apply_pre(Context& ctx, const double* r, hipStream_t st);
+void apply_post(Context& ctx, double* z, hipStream_t st);
 void spmv(Context& ctx, const double* x, double* y, hipStream_t st);
 struct FgmresResult {
   int iterations = 0, restarts = 0;
@@ -247,9 +262,44 @@ FgmresResult fgmres(Context& ctx, const double* b, double* x, double rtol, int r
                     bool use_graph, hipStream_t st, double* history = nullptr, int history_len = 0);
 void expand_solution(const Context& ctx, const double* xf, double* xfull, hipStream_t st);
 
+// A batch of independent problems (own contexts) whose local and coarse
+// inverse products run as one launch pair per level over all members, in
+// longest-first order of the matrices (batch.hip).
+struct BatchSet {
+  int prec = P_FP64;
+  int count = 0;                     // matrices over all members
+  std::vector<int> owner;            // member of each matrix
+  std::vector<uint64_t> bytes;       // algorithmic bytes of each matrix
+  GemvDesc* d_desc = nullptr;
+  FactorSet::GemvPlan plan;
+  double* d_partial = nullptr;
+  int32_t* d_want = nullptr;
+  std::vector<int32_t> h_want;       // host copy of the last upload
+  double active_bytes = 0.0;
+};
+
+struct Batch {
+  std::vector<Context*> m;
+  DeviceArena arena;
+  BatchSet s1, s2;                   // level-1 inverses; coarse-level inverses
+  KernelTimer timer;                 // times the level-1 partial-product launches
+  double* h_pinned = nullptr;        // 4 doubles per member, read-back staging
+};
+
+void batch_build(Batch& b, hipStream_t st);
+// member_active[k] selects the members whose matrices the next products touch
+void batch_select(Batch& b, const std::vector<char>& member_active, hipStream_t st);
+void batch_local_solve(Batch& b, hipStream_t st);
+void batch_release(Batch& b);
+void apply_precond_batch(Batch& b, const double* const* r, double* const* z, hipStream_t st);
+std::vector<FgmresResult> fgmres_batch(Batch& b, const double* const* bvec, double* const* x, double rtol,
+                                       int restart, int max_it, hipStream_t st);
+
 // several right-hand sides (solve_multi.hip): blocks of K <= max_rhs
 // interleaved columns (entry (d, j) at x[d * K + j])
 void plan_gemm(FactorSet& fs, DeviceArena& A, hipStream_t st);
+// descriptors of the set's inverses against the work vector w (device_setup)
+std::vector<GemvDesc> gemv_descs(const FactorSet& fs, double* w);
 bool multi_supported(const Context& ctx);
 void ensure_multi_workspace(Context& ctx, int restart, int K);
 void apply_precond_multi(Context& ctx, const double* r, double* z, int K, hipStream_t st);

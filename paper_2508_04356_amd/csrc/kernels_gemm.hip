@@ -126,15 +126,19 @@ __global__ __launch_bounds__(256) void gemm_part_kernel(const T* __restrict__ st
       }
     }
   }
-  // D_v[i'][j] = y[Rw + E i' + v][16 g + j]; lane holds i' = 4 kq + t, j = i
+  // D_v[i'][j] = y[Rw + E i' + v][16 g + j], j = i.  Accumulator register t
+  // of a lane holds output row i' = 4 kq + t for the f32 shape and
+  // i' = kq + 4 t for the f64 shape (groups of one row strided by 4).
   P* out = partial + (int64_t)p * RB * 32;
 #pragma unroll
   for (int g = 0; g < G; ++g)
 #pragma unroll
     for (int v = 0; v < E; ++v)
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-        out[(int64_t)(wave * (RB / 4) + E * (4 * kq + t) + v) * 32 + g * 16 + i] = (P)acc[v][g][t];
+      for (int t = 0; t < 4; ++t) {
+        const int ip = sizeof(T) == 8 ? kq + 4 * t : 4 * kq + t;
+        out[(int64_t)(wave * (RB / 4) + E * ip + v) * 32 + g * 16 + i] = (P)acc[v][g][t];
+      }
 }
 
 // BF16 storage (the stored inverse is symmetric): lane l loads 2 x 8

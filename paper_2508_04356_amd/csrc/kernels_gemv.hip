@@ -38,15 +38,10 @@ __device__ inline void gemv_load(const T* p, V& o) {
 // ---- batched dense matrix-vector product ----------------------------------
 
 // Item (f, r0, c0, p): rows [r0, r0 + 64 E) and columns [c0, c0 + GEMV_CW)
-// of matrix f; partial[p * 64 E + row] = sum over those columns of M x.
+// of matrix D[f]; partial[p * 64 E + row] = sum over those columns of M x.
 template <typename T, int NW>
-__global__ __launch_bounds__(64 * NW) void gemv_part_kernel(const T* __restrict__ store,
-                                                           const int64_t* __restrict__ OFF,
-                                                           const int32_t* __restrict__ N,
-                                                           const int32_t* __restrict__ NP,
-                                                           const int64_t* __restrict__ XOFF,
+__global__ __launch_bounds__(64 * NW) void gemv_part_kernel(const GemvDesc* __restrict__ D,
                                                            const int4* __restrict__ items,
-                                                           const double* __restrict__ w,
                                                            double* __restrict__ partial,
                                                            const int32_t* __restrict__ want) {
   using AT = typename VecW<T>::acc;
@@ -57,16 +52,17 @@ __global__ __launch_bounds__(64 * NW) void gemv_part_kernel(const T* __restrict_
   const int4 item = items[blockIdx.x];
   const int f = item.x, r0 = item.y, c0 = item.z, p = item.w;
   if (want && !want[f]) return;  // uniform per work-group
-  const int n = N[f];
-  const int64_t np = NP[f];
+  const GemvDesc d = D[f];
+  const int n = d.n;
+  const int64_t np = d.np;
   const int ncols = min(GEMV_CW, n - c0);
   const int tid = threadIdx.x;
-  const double* x = w + XOFF[f] + c0;
+  const double* x = d.x + c0;
   for (int i = tid; i < GEMV_CW; i += 64 * NW) xs[i] = i < ncols ? (AT)x[i] : (AT)0;
   const int lane = tid & 63, wave = tid >> 6;
   const int rr = r0 + lane * E;
   const bool active = rr < n;
-  const T* col = store + OFF[f] + (int64_t)c0 * np + rr;
+  const T* col = static_cast<const T*>(d.a) + (int64_t)c0 * np + rr;
   AT acc[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) acc[e] = 0;
@@ -104,54 +100,61 @@ __global__ __launch_bounds__(64 * NW) void gemv_part_kernel(const T* __restrict_
   }
 }
 
-// Item (f, r0, p0, cnt): x[r0 + t] = sum_{q < cnt} partial[(p0 + q) * RB + t].
+// Item (f, r0, p0, cnt): x_f[r0 + t] = sum_{q < cnt} partial[(p0 + q) * RB + t].
 template <int RB>
-__global__ __launch_bounds__(256) void gemv_sum_kernel(const int32_t* __restrict__ N,
-                                                       const int64_t* __restrict__ XOFF,
+__global__ __launch_bounds__(256) void gemv_sum_kernel(const GemvDesc* __restrict__ D,
                                                        const int4* __restrict__ items,
-                                                       const double* __restrict__ partial, double* __restrict__ w,
+                                                       const double* __restrict__ partial,
                                                        const int32_t* __restrict__ want) {
   const int4 item = items[blockIdx.x];
   const int f = item.x, r0 = item.y, p0 = item.z, cnt = item.w;
   if (want && !want[f]) return;
-  const int n = N[f];
+  const int n = D[f].n;
+  double* x = D[f].x;
   for (int t = threadIdx.x; t < RB; t += 256) {
     if (r0 + t >= n) break;
     double s = 0.0;
     for (int q = 0; q < cnt; ++q) s += partial[(int64_t)(p0 + q) * RB + t];
-    w[XOFF[f] + r0 + t] = s;
+    x[r0 + t] = s;
   }
 }
 
 template <typename T>
-void gemv_launch(const FactorSet& fs, double* w, hipStream_t st, int slot, const int32_t* want) {
-  const FactorSet::GemvPlan& G = fs.gemv[slot];
+void gemv_launch(const GemvDesc* desc, const FactorSet::GemvPlan& G, double* partial, hipStream_t st,
+                 const int32_t* want, KernelTimer* tm, double bytes) {
   if (G.n1 == 0) return;
   constexpr int RB = 64 * VecW<T>::W;
-  KernelTimer* tm = (slot == 0 && fs.timer && fs.timer->on && fs.timer->used < KernelTimer::CAP) ? fs.timer : nullptr;
   if (tm) GDSW_HIP(hipEventRecord(tm->ev[2 * tm->used], st));
-  gemv_part_kernel<T, GDSW_GEMV_NW><<<G.n1, 64 * GDSW_GEMV_NW, 0, st>>>(
-      static_cast<const T*>(fs.store), fs.d_off, fs.d_n, fs.d_npad, fs.d_xoff, G.d_items1, w, fs.d_partial, want);
+  gemv_part_kernel<T, GDSW_GEMV_NW><<<G.n1, 64 * GDSW_GEMV_NW, 0, st>>>(desc, G.d_items1, partial, want);
   if (tm) {
     GDSW_HIP(hipEventRecord(tm->ev[2 * tm->used++ + 1], st));
-    tm->bytes += (double)fs.alg_bytes;
+    tm->bytes += bytes;
   }
-  gemv_sum_kernel<RB><<<G.n2, 256, 0, st>>>(fs.d_n, fs.d_xoff, G.d_items2, fs.d_partial, w, want);
+  gemv_sum_kernel<RB><<<G.n2, 256, 0, st>>>(desc, G.d_items2, partial, want);
 }
 
 }  // namespace
 
 int gemv_rows(int prec) { return prec == P_FP64 ? 128 : prec == P_FP32 ? 256 : 512; }
 
-void gemv_set(const FactorSet& fs, double* w, hipStream_t st, int slot, const int32_t* want) {
-  if (fs.count == 0 || slot >= (int)fs.gemv.size()) return;
-  if (fs.prec == P_FP64)
-    gemv_launch<double>(fs, w, st, slot, want);
-  else if (fs.prec == P_FP32)
-    gemv_launch<float>(fs, w, st, slot, want);
+void gemv_desc_launch(int prec, const GemvDesc* desc, const FactorSet::GemvPlan& G, double* partial,
+                      hipStream_t st, const int32_t* want, KernelTimer* tm, double bytes) {
+  if (tm && (!tm->on || tm->used >= KernelTimer::CAP)) tm = nullptr;
+  if (prec == P_FP64)
+    gemv_launch<double>(desc, G, partial, st, want, tm, bytes);
+  else if (prec == P_FP32)
+    gemv_launch<float>(desc, G, partial, st, want, tm, bytes);
   else
-    gemv_launch<uint16_t>(fs, w, st, slot, want);
+    gemv_launch<uint16_t>(desc, G, partial, st, want, tm, bytes);
   GDSW_HIP(hipGetLastError());
+}
+
+void gemv_set(const FactorSet& fs, double* w, hipStream_t st, int slot, const int32_t* want) {
+  (void)w;  // the descriptors address the set's own work vector segments
+  if (fs.count == 0 || slot >= (int)fs.gemv.size()) return;
+  if (!fs.d_desc) throw StatusError{5, "inverse set used before its descriptors were built"};
+  gemv_desc_launch(fs.prec, fs.d_desc, fs.gemv[slot], fs.d_partial, st, want, slot == 0 ? fs.timer : nullptr,
+                   (double)fs.alg_bytes);
 }
 
 void local_solve_set(const FactorSet& fs, double* w, hipStream_t st, int slot, const int32_t* want) {

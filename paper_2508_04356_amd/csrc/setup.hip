@@ -51,12 +51,19 @@ void DeviceArena::release_all() {
   used = 0;
 }
 
-static size_t elem_size(int prec) { return prec == P_FP64 ? 8 : (prec == P_FP32 ? 4 : 2); }
 
 uint64_t FactorSet::algorithmic_bytes() const {
   uint64_t b = 0;
   for (int f = 0; f < count; ++f) b += (uint64_t)n[f] * n[f] * elem_size(prec);
   return b;
+}
+
+std::vector<GemvDesc> gemv_descs(const FactorSet& fs, double* w) {
+  std::vector<GemvDesc> d(fs.count);
+  const size_t es = elem_size(fs.prec);
+  for (int f = 0; f < fs.count; ++f)
+    d[f] = GemvDesc{static_cast<const char*>(fs.store) + (size_t)fs.off[f] * es, w + fs.xoff[f], fs.n[f], fs.npad[f]};
+  return d;
 }
 
 int64_t FactorSet::launches() const {
@@ -824,6 +831,9 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
   for (int f = 0; f < P.n_sub; ++f)
     ctx.factor_bytes += (uint64_t)ctx.L1.npad[f] * ctx.L1.npad[f] * elem_size(ctx.local_prec);
   ctx.coarse_bytes = (uint64_t)Nc * Nc * 8 * 2 + (uint64_t)phi_off.back() * 16;
+  // descriptors of the stored inverses against the work vector
+  for (FactorSet* fs : {&ctx.L1, &ctx.HI})
+    if (fs->mode == SOLVE_INVERSE && fs->count > 0) fs->d_desc = dupload(A, gemv_descs(*fs, ctx.d_w), st);
   // several right-hand sides: MFMA work plans and interleaved work buffers
   if (ctx.max_rhs > 1 && ctx.solve_mode == SOLVE_INVERSE) {
     plan_gemm(ctx.L1, A, st);

@@ -128,10 +128,9 @@ void spmv(Context& ctx, const double* x, double* y, hipStream_t st) {
   spmv_csr(ctx.P.n_free, ctx.d_rowptr, ctx.d_col, ctx.d_val, x, y, st);
 }
 
-void apply_precond(Context& ctx, const double* r, double* z, hipStream_t st, hipEvent_t* ev) {
+void apply_pre(Context& ctx, const double* r, hipStream_t st) {
   const CoarseView cv = coarse_view(ctx);
   const bool three = ctx.P.spec.levels == 3 && ctx.Nc > 0;
-  if (ev) GDSW_HIP(hipEventRecord(ev[0], st));
   gather(ctx.n_w1, ctx.d_gidx, r, ctx.d_w, st);
   if (three) {
     // r0 = Phi^T r; level-2 copies R_j^(2) r0; level-3 right-hand side Phi3^T r0
@@ -141,6 +140,25 @@ void apply_precond(Context& ctx, const double* r, double* z, hipStream_t st, hip
   } else if (ctx.Nc > 0) {
     restrict_coarse(ctx.Nc, cv, r, ctx.d_w, ctx.d_coarse_pinv, st);
   }
+}
+
+void apply_post(Context& ctx, double* z, hipStream_t st) {
+  const CoarseView cv = coarse_view(ctx);
+  const bool three = ctx.P.spec.levels == 3 && ctx.Nc > 0;
+  if (three) {
+    // y0 = sum_j R_j^(2)T y_j + Phi3 y3, then z = sum_i R_i^T y_i + Phi y0
+    scatter2(ctx.Nc, ctx.d_inv2_ptr, ctx.d_inv2_pos, ctx.d_w, ctx.d_phi3, ctx.Nc3, ctx.d_c3_pinv, ctx.d_y0, st);
+    scatter_prolong(ctx.P.n_free, ctx.d_inv_ptr, ctx.d_inv_pos, ctx.d_w, cv, ctx.d_y0, nullptr, z, st);
+  } else if (ctx.Nc > 0) {
+    scatter_prolong(ctx.P.n_free, ctx.d_inv_ptr, ctx.d_inv_pos, ctx.d_w, cv, nullptr, ctx.d_coarse_pinv, z, st);
+  } else {
+    deterministic_scatter(ctx.P.n_free, ctx.d_inv_ptr, ctx.d_inv_pos, ctx.d_w, z, st);
+  }
+}
+
+void apply_precond(Context& ctx, const double* r, double* z, hipStream_t st, hipEvent_t* ev) {
+  if (ev) GDSW_HIP(hipEventRecord(ev[0], st));
+  apply_pre(ctx, r, st);
   if (ev) GDSW_HIP(hipEventRecord(ev[1], st));
   if (ctx.local_solver != 0 && ctx.learned) {
     // interior subdomains: learned solve (1) or no local correction (2)
@@ -158,14 +176,7 @@ void apply_precond(Context& ctx, const double* r, double* z, hipStream_t st, hip
   if (ev) GDSW_HIP(hipEventRecord(ev[2], st));
   local_solve_set(ctx.HI, ctx.d_w, st);
   if (ev) GDSW_HIP(hipEventRecord(ev[3], st));
-  if (three) {
-    // y0 = sum_j R_j^(2)T y_j + Phi3 y3, then z = sum_i R_i^T y_i + Phi y0
-    scatter2(ctx.Nc, ctx.d_inv2_ptr, ctx.d_inv2_pos, ctx.d_w, ctx.d_phi3, ctx.Nc3, ctx.d_c3_pinv, ctx.d_y0, st);
-    scatter_prolong(ctx.P.n_free, ctx.d_inv_ptr, ctx.d_inv_pos, ctx.d_w, cv, ctx.d_y0, nullptr, z, st);
-  } else if (ctx.Nc > 0)
-    scatter_prolong(ctx.P.n_free, ctx.d_inv_ptr, ctx.d_inv_pos, ctx.d_w, cv, nullptr, ctx.d_coarse_pinv, z, st);
-  else
-    deterministic_scatter(ctx.P.n_free, ctx.d_inv_ptr, ctx.d_inv_pos, ctx.d_w, z, st);
+  apply_post(ctx, z, st);
   if (ev) GDSW_HIP(hipEventRecord(ev[4], st));
   GDSW_HIP(hipGetLastError());
 }
@@ -254,6 +265,122 @@ FgmresResult fgmres(Context& ctx, const double* b, double* x, double rtol, int r
   }
   res.iterations = it;
   res.restarts = std::max(0, cycles - 1);
+  GDSW_HIP(hipGetLastError());
+  return res;
+}
+
+// Lockstep FGMRES over the members of a batch: every member runs exactly the
+// steps of fgmres() above (same kernels, same order, hence bitwise the same
+// iterates as a solve of that member alone); per iteration the members'
+// local and coarse solves share one launch pair per level, and the host
+// reads every member's residual estimate after one synchronisation.
+std::vector<FgmresResult> fgmres_batch(Batch& bt, const double* const* bvec, double* const* xv, double rtol,
+                                       int restart, int max_it, hipStream_t st) {
+  const int K = (int)bt.m.size();
+  std::vector<FgmresResult> res(K);
+  std::vector<double> bnorm(K, 0.0);
+  std::vector<char> done(K, 0), in_cycle(K, 0);
+  std::vector<int> kc(K, 0), cycles(K, 0);
+  double* hp = bt.h_pinned;
+  for (int k = 0; k < K; ++k) {
+    Context& c = *bt.m[k];
+    ensure_workspace(c, restart);
+    cols_dot(bvec[k], c.ldv, 1, bvec[k], c.P.n_free, c.d_part, c.n_part_blocks, c.d_scal + 0, st);
+    GDSW_HIP(hipMemcpyAsync(hp + k, c.d_scal + 0, sizeof(double), hipMemcpyDeviceToHost, st));
+    GDSW_HIP(hipMemsetAsync(xv[k], 0, c.P.n_free * sizeof(double), st));
+  }
+  GDSW_HIP(hipStreamSynchronize(st));
+  for (int k = 0; k < K; ++k) {
+    bnorm[k] = std::sqrt(hp[k]);
+    if (bnorm[k] == 0.0) {
+      res[k].converged = true;
+      done[k] = 1;
+    }
+  }
+  while (true) {
+    // r = b - A x and beta for every member still running
+    for (int k = 0; k < K; ++k) {
+      if (done[k]) continue;
+      Context& c = *bt.m[k];
+      const int64_t n = c.P.n_free;
+      spmv(c, xv[k], c.d_t1, st);
+      residual_kernel<<<grid_n(n), 256, 0, st>>>(n, bvec[k], c.d_t1);
+      cols_dot(c.d_t1, c.ldv, 1, c.d_t1, n, c.d_part, c.n_part_blocks, c.d_scal + 0, st);
+      cycle_start_kernel<<<1, 1, 0, st>>>(c.d_g, restart, c.d_scal);
+      GDSW_HIP(hipMemcpyAsync(hp + k, c.d_scal + 1, sizeof(double), hipMemcpyDeviceToHost, st));
+    }
+    GDSW_HIP(hipStreamSynchronize(st));
+    int running = 0;
+    for (int k = 0; k < K; ++k) {
+      in_cycle[k] = 0;
+      kc[k] = 0;
+      if (done[k]) continue;
+      res[k].true_rel = hp[k] / bnorm[k];
+      if (res[k].true_rel <= rtol) {
+        res[k].converged = true;
+        done[k] = 1;
+      } else if (res[k].iterations >= max_it) {
+        done[k] = 1;
+      } else {
+        in_cycle[k] = 1;
+        ++cycles[k];
+        ++running;
+        Context& c = *bt.m[k];
+        scale_div_kernel<<<grid_n(c.P.n_free), 256, 0, st>>>(c.P.n_free, c.d_t1, c.d_scal, 1, c.d_V);
+      }
+    }
+    if (running == 0) break;
+    batch_select(bt, in_cycle, st);
+    for (int j = 0; j < restart && running > 0; ++j) {
+      for (int k = 0; k < K; ++k)
+        if (in_cycle[k]) apply_pre(*bt.m[k], bt.m[k]->d_V + (int64_t)j * bt.m[k]->ldv, st);
+      batch_local_solve(bt, st);
+      for (int k = 0; k < K; ++k) {
+        if (!in_cycle[k]) continue;
+        Context& c = *bt.m[k];
+        const int64_t n = c.P.n_free;
+        double* V = c.d_V;
+        double* zj = c.d_Z + (int64_t)j * c.ldv;
+        double* w = c.d_t2;
+        apply_post(c, zj, st);
+        spmv(c, zj, w, st);
+        cols_dot(V, c.ldv, j + 1, w, n, c.d_part, c.n_part_blocks, c.d_hv, st);
+        gemv_sub(V, c.ldv, j + 1, c.d_hv, w, n, st);
+        cols_dot(V, c.ldv, j + 1, w, n, c.d_part, c.n_part_blocks, c.d_hv + restart + 1, st);
+        gemv_sub(V, c.ldv, j + 1, c.d_hv + restart + 1, w, n, st);
+        cols_dot(w, c.ldv, 1, w, n, c.d_part, c.n_part_blocks, c.d_scal + 4, st);
+        arnoldi_finish_kernel<<<1, 1, 0, st>>>(j, restart, c.d_hv, c.d_hv + restart + 1, c.d_H, c.d_cs, c.d_sn,
+                                               c.d_g, c.d_scal, bnorm[k]);
+        scale_div_kernel<<<grid_n(n), 256, 0, st>>>(n, w, c.d_scal, 3, V + (int64_t)(j + 1) * c.ldv);
+        GDSW_HIP(hipMemcpyAsync(hp + 2 * k, c.d_scal + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+      }
+      GDSW_HIP(hipStreamSynchronize(st));
+      bool changed = false;
+      for (int k = 0; k < K; ++k) {
+        if (!in_cycle[k]) continue;
+        const double rel = hp[2 * k], hn = hp[2 * k + 1];
+        if (!std::isfinite(rel))
+          throw StatusError{4, "FGMRES: non-finite residual estimate in batch member " + std::to_string(k)};
+        res[k].iterations += 1;
+        res[k].rel = rel;
+        kc[k] = j + 1;
+        if (rel <= rtol || hn == 0.0 || res[k].iterations >= max_it) {
+          in_cycle[k] = 0;
+          changed = true;
+          --running;
+        }
+      }
+      if (changed && running > 0) batch_select(bt, in_cycle, st);
+    }
+    // x += Z y for every member that took part in this cycle
+    for (int k = 0; k < K; ++k) {
+      if (kc[k] == 0) continue;
+      Context& c = *bt.m[k];
+      back_subst_kernel<<<1, 1, 0, st>>>(kc[k], restart, c.d_H, c.d_g, c.d_hv);
+      gemv_add(c.d_Z, c.ldv, kc[k], c.d_hv, xv[k], c.P.n_free, st);
+    }
+  }
+  for (int k = 0; k < K; ++k) res[k].restarts = std::max(0, cycles[k] - 1);
   GDSW_HIP(hipGetLastError());
   return res;
 }

@@ -40,7 +40,7 @@ def block(n, k, seed):
 
 def dev_cm(a):
     """Column-major device copy: column j at offset j * n."""
-    return torch.as_tensor(np.ascontiguousarray(a.T), dtype=torch.float64, device=DEV)
+    return torch.as_tensor(np.ascontiguousarray(a.T).ravel(), dtype=torch.float64, device=DEV)
 
 
 def relmax(a, b):
