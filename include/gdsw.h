@@ -312,6 +312,17 @@ gdsw_status gdsw_set_schedule(gdsw_ctx* ctx, int32_t phases, int32_t waves, void
 gdsw_status gdsw_profile_apply(gdsw_ctx* ctx, const double* r_dev, double* z_dev, void* stream,
                                double* ms);
 
+/* Launch-shape autotuner of the level-1 inverse product (GDSW_SOLVE_INVERSE):
+ * times the partial-product kernel with column chunks of 512, 1024 and 2048
+ * columns per work item on this context's own matrices (10 products each,
+ * HIP events on `stream`), keeps the fastest and re-plans.  The chunk sets
+ * the grouping of the partial sums, so results can change in the last bits;
+ * they are again bitwise reproducible for the chosen chunk.  chosen (may be
+ * NULL) receives the chunk, ms[3] (may be NULL) the mean time of each.
+ * Call before gdsw_learned_init; EUNSUPPORTED otherwise or in triangular
+ * mode.  Synchronises `stream`. */
+gdsw_status gdsw_autotune(gdsw_ctx* ctx, void* stream, int32_t* chosen, double* ms);
+
 /* Event timing of the dominant solve kernel.  While enabled, every launch of
  * the level-1 solve kernel in a full apply (the partial-product kernel of
  * GDSW_SOLVE_INVERSE, single- or multi-column, or each sweep step of

@@ -84,6 +84,7 @@ _sig = {
     "gdsw_copy_coarse_basis": (C.c_int, [_P, _P]),
     "gdsw_local_indices": (C.c_int, [_P, C.c_int32, _P, C.POINTER(C.c_int32)]),
     "gdsw_profile_apply": (C.c_int, [_P, _P, _P, _P, _P]),
+    "gdsw_autotune": (C.c_int, [_P, _P, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "gdsw_kernel_timer": (C.c_int, [_P, C.c_int32]),
     "gdsw_kernel_timer_read": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_uint64)]),
     "gdsw_set_schedule": (C.c_int, [_P, C.c_int32, C.c_int32, _P]),
@@ -222,6 +223,13 @@ class Solver:
         ld = self.n_free if ld is None else ld
         _check(_lib.gdsw_apply_precond(self._ctx, _ptr(r), _ptr(z), nrhs, ld, _stream(stream)), self._ctx)
         return z
+
+    def autotune(self, stream=None):
+        """Picks the column chunk of the inverse product; returns (chunk, [ms for 512, 1024, 2048])."""
+        ch = C.c_int32()
+        ms = (C.c_double * 3)()
+        _check(_lib.gdsw_autotune(self._ctx, _stream(stream), C.byref(ch), ms), self._ctx)
+        return ch.value, list(ms)
 
     def kernel_timer(self, enable):
         _check(_lib.gdsw_kernel_timer(self._ctx, int(bool(enable))), self._ctx)

@@ -10,6 +10,7 @@
 
 #include "../../include/gdsw.h"
 #include "context.h"
+#include "kernels.h"
 #include "kernels_multi.h"
 #include "learned.h"
 
@@ -439,6 +440,48 @@ gdsw_status gdsw_kernel_timer_read(gdsw_ctx* ctx, double* total_ms, int64_t* lau
   });
 }
 
+gdsw_status gdsw_autotune(gdsw_ctx* ctx, void* stream, int32_t* chosen, double* ms) {
+  if (gdsw_status s = check_device_ctx(ctx)) return s;
+  Context& c = ctx->c;
+  if (c.solve_mode != SOLVE_INVERSE) return fail(ctx, GDSW_EUNSUPPORTED, "autotuning applies to GDSW_SOLVE_INVERSE");
+  if (c.learned) return fail(ctx, GDSW_EUNSUPPORTED, "autotune before gdsw_learned_init");
+  return guarded(ctx, [&]() {
+    hipStream_t st = (hipStream_t)stream;
+    FactorSet& fs = c.L1;
+    const int cand[3] = {512, 1024, 2048};
+    double t[3] = {0, 0, 0};
+    hipEvent_t e0, e1;
+    GDSW_HIP(hipEventCreate(&e0));
+    GDSW_HIP(hipEventCreate(&e1));
+    KernelTimer* tm = fs.timer;
+    fs.timer = nullptr;
+    int best = 1;
+    for (int q = 0; q < 3; ++q) {
+      fs.cw = cand[q];
+      plan_schedule(fs, 1, c.arena, st, 0);
+      for (int w = 0; w < 3; ++w) local_solve_set(fs, c.d_w, st);
+      GDSW_HIP(hipEventRecord(e0, st));
+      for (int r = 0; r < 10; ++r) local_solve_set(fs, c.d_w, st);
+      GDSW_HIP(hipEventRecord(e1, st));
+      GDSW_HIP(hipEventSynchronize(e1));
+      float el = 0.f;
+      GDSW_HIP(hipEventElapsedTime(&el, e0, e1));
+      t[q] = el / 10.0;
+      if (t[q] < t[best]) best = q;
+    }
+    fs.cw = cand[best];
+    plan_schedule(fs, 1, c.arena, st, 0);
+    fs.timer = tm;
+    GDSW_HIP(hipMemsetAsync(c.d_w, 0, std::max<int64_t>(c.n_w, 1) * sizeof(double), st));
+    GDSW_HIP(hipStreamSynchronize(st));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (chosen) *chosen = fs.cw;
+    if (ms)
+      for (int q = 0; q < 3; ++q) ms[q] = t[q];
+  });
+}
+
 gdsw_status gdsw_learned_init(gdsw_ctx* ctx, uint64_t seed, gdsw_learned_info* info, void* stream) {
   if (gdsw_status s = check_device_ctx(ctx)) return s;
   return guarded(ctx, [&]() {
@@ -512,6 +555,7 @@ void gdsw_destroy(gdsw_ctx* ctx) {
   if (!ctx) return;
   learned_release(ctx->c);
   for (auto& e : ctx->c.timer.ev) (void)hipEventDestroy(e);
+  release_graphs(ctx->c);
   if (ctx->c.mk.h_pinned) (void)hipHostFree(ctx->c.mk.h_pinned);
   if (ctx->c.mk.h_active) (void)hipHostFree(ctx->c.mk.h_active);
   ctx->c.arena.release_all();

@@ -110,10 +110,10 @@ void batch_select(Batch& b, const std::vector<char>& member_active, hipStream_t 
 
 void batch_local_solve(Batch& b, hipStream_t st) {
   if (b.s1.count)
-    gemv_desc_launch(b.s1.prec, b.s1.d_desc, b.s1.plan, b.s1.d_partial, st, b.s1.d_want, &b.timer,
+    gemv_desc_launch(b.s1.prec, b.s1.d_desc, b.s1.plan, GEMV_CW, b.s1.d_partial, st, b.s1.d_want, &b.timer,
                      b.s1.active_bytes);
   if (b.s2.count)
-    gemv_desc_launch(b.s2.prec, b.s2.d_desc, b.s2.plan, b.s2.d_partial, st, b.s2.d_want, nullptr, 0.0);
+    gemv_desc_launch(b.s2.prec, b.s2.d_desc, b.s2.plan, GEMV_CW, b.s2.d_partial, st, b.s2.d_want, nullptr, 0.0);
 }
 
 void batch_release(Batch& b) {

@@ -124,6 +124,7 @@ struct FactorSet {
     int4* d_items2 = nullptr;
   };
   std::vector<GemvPlan> gemv;
+  int cw = GEMV_CW;                  // columns per partial-product item (512, 1024 or 2048)
   GemvDesc* d_desc = nullptr;        // per factor, built once the store and work vector exist
   double* d_partial = nullptr;
   int64_t partial_len = 0;
@@ -149,6 +150,14 @@ struct Context {
 
   // several right-hand sides (two levels, explicit inverses): up to max_rhs
   // columns per pass, interleaved (entry (d, j) at x[d * max_rhs + j])
+  // captured FGMRES iterations (one executable graph per basis index)
+  struct IterGraphs {
+    int restart = 0;
+    const double* V = nullptr;       // workspace the graphs were captured against
+    hipStream_t stream = nullptr;    // own stream when the caller passes the default one
+    std::vector<hipGraphExec_t> exec;
+  } graphs;
+
   int max_rhs = 1;
   double* d_wm = nullptr;          // n_w x max_rhs work vectors
   double* d_xin = nullptr;         // n_free x max_rhs (ABI column-major input, interleaved)
@@ -204,6 +213,9 @@ struct Context {
   std::vector<int32_t> coarse_perm;  // factor position -> coarse column (velocity first)
   int32_t* d_coarse_pinv = nullptr;  // coarse column -> wbuf position
   int64_t coarse_xoff = 0;
+  int n_pairs = 0;                 // (subdomain, local coarse column) pairs
+  int max_ni = 0;                  // largest interior set |I_i|
+  double* d_pair_t = nullptr;      // per pair: Phi_I column^T r (restriction)
   double* d_r0 = nullptr;          // coarse vectors (three levels)
   double* d_y0 = nullptr;
 
@@ -261,6 +273,7 @@ struct FgmresResult {
 FgmresResult fgmres(Context& ctx, const double* b, double* x, double rtol, int restart, int max_it,
                     bool use_graph, hipStream_t st, double* history = nullptr, int history_len = 0);
 void expand_solution(const Context& ctx, const double* xf, double* xfull, hipStream_t st);
+void release_graphs(Context& ctx);
 
 // A batch of independent problems (own contexts) whose local and coarse
 // inverse products run as one launch pair per level over all members, in

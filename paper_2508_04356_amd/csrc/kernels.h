@@ -54,10 +54,11 @@ void convert_store(int prec, const double* src, void* dst, int64_t count, hipStr
 // Rows per matrix-vector work item for a storage precision (64 lanes x 16 bytes).
 int gemv_rows(int prec);
 // Partial-product and summation launches of the matrix-vector product for
-// the inverses in desc (items of plan G, partial sums in `partial`); `want`
+// the inverses in desc (items of plan G built with column chunk cw, partial
+// sums in `partial`); `want`
 // (per descriptor, or null) skips unselected matrices; tm (or null) times the
 // partial-product launch and charges it `bytes`.
-void gemv_desc_launch(int prec, const GemvDesc* desc, const FactorSet::GemvPlan& G, double* partial,
+void gemv_desc_launch(int prec, const GemvDesc* desc, const FactorSet::GemvPlan& G, int cw, double* partial,
                       hipStream_t st, const int32_t* want, KernelTimer* tm, double bytes);
 // x_f <- M_f x_f for every stored inverse M_f of the set, in place on w.
 void gemv_set(const FactorSet& fs, double* w, hipStream_t st, int slot = 0, const int32_t* want = nullptr);

@@ -37,9 +37,9 @@ __device__ inline void gemv_load(const T* p, V& o) {
 
 // ---- batched dense matrix-vector product ----------------------------------
 
-// Item (f, r0, c0, p): rows [r0, r0 + 64 E) and columns [c0, c0 + GEMV_CW)
-// of matrix D[f]; partial[p * 64 E + row] = sum over those columns of M x.
-template <typename T, int NW>
+// Item (f, r0, c0, p): rows [r0, r0 + 64 E) and columns [c0, c0 + CW) of
+// matrix D[f]; partial[p * 64 E + row] = sum over those columns of M x.
+template <typename T, int NW, int CW>
 __global__ __launch_bounds__(64 * NW) void gemv_part_kernel(const GemvDesc* __restrict__ D,
                                                            const int4* __restrict__ items,
                                                            double* __restrict__ partial,
@@ -47,7 +47,7 @@ __global__ __launch_bounds__(64 * NW) void gemv_part_kernel(const GemvDesc* __re
   using AT = typename VecW<T>::acc;
   constexpr int E = VecW<T>::W;
   constexpr int RB = 64 * E;
-  __shared__ AT xs[GEMV_CW];
+  __shared__ AT xs[CW];
   __shared__ AT red[NW][RB];
   const int4 item = items[blockIdx.x];
   const int f = item.x, r0 = item.y, c0 = item.z, p = item.w;
@@ -55,10 +55,10 @@ __global__ __launch_bounds__(64 * NW) void gemv_part_kernel(const GemvDesc* __re
   const GemvDesc d = D[f];
   const int n = d.n;
   const int64_t np = d.np;
-  const int ncols = min(GEMV_CW, n - c0);
+  const int ncols = min(CW, n - c0);
   const int tid = threadIdx.x;
   const double* x = d.x + c0;
-  for (int i = tid; i < GEMV_CW; i += 64 * NW) xs[i] = i < ncols ? (AT)x[i] : (AT)0;
+  for (int i = tid; i < CW; i += 64 * NW) xs[i] = i < ncols ? (AT)x[i] : (AT)0;
   const int lane = tid & 63, wave = tid >> 6;
   const int rr = r0 + lane * E;
   const bool active = rr < n;
@@ -120,12 +120,18 @@ __global__ __launch_bounds__(256) void gemv_sum_kernel(const GemvDesc* __restric
 }
 
 template <typename T>
-void gemv_launch(const GemvDesc* desc, const FactorSet::GemvPlan& G, double* partial, hipStream_t st,
+void gemv_launch(const GemvDesc* desc, const FactorSet::GemvPlan& G, int cw, double* partial, hipStream_t st,
                  const int32_t* want, KernelTimer* tm, double bytes) {
   if (G.n1 == 0) return;
   constexpr int RB = 64 * VecW<T>::W;
+  constexpr int NW = GDSW_GEMV_NW;
   if (tm) GDSW_HIP(hipEventRecord(tm->ev[2 * tm->used], st));
-  gemv_part_kernel<T, GDSW_GEMV_NW><<<G.n1, 64 * GDSW_GEMV_NW, 0, st>>>(desc, G.d_items1, partial, want);
+  if (cw == 512)
+    gemv_part_kernel<T, NW, 512><<<G.n1, 64 * NW, 0, st>>>(desc, G.d_items1, partial, want);
+  else if (cw == 2048)
+    gemv_part_kernel<T, NW, 2048><<<G.n1, 64 * NW, 0, st>>>(desc, G.d_items1, partial, want);
+  else
+    gemv_part_kernel<T, NW, 1024><<<G.n1, 64 * NW, 0, st>>>(desc, G.d_items1, partial, want);
   if (tm) {
     GDSW_HIP(hipEventRecord(tm->ev[2 * tm->used++ + 1], st));
     tm->bytes += bytes;
@@ -137,15 +143,16 @@ void gemv_launch(const GemvDesc* desc, const FactorSet::GemvPlan& G, double* par
 
 int gemv_rows(int prec) { return prec == P_FP64 ? 128 : prec == P_FP32 ? 256 : 512; }
 
-void gemv_desc_launch(int prec, const GemvDesc* desc, const FactorSet::GemvPlan& G, double* partial,
+void gemv_desc_launch(int prec, const GemvDesc* desc, const FactorSet::GemvPlan& G, int cw, double* partial,
                       hipStream_t st, const int32_t* want, KernelTimer* tm, double bytes) {
+  if (cw != 512 && cw != 1024 && cw != 2048) throw StatusError{1, "column chunk must be 512, 1024 or 2048"};
   if (tm && (!tm->on || tm->used >= KernelTimer::CAP)) tm = nullptr;
   if (prec == P_FP64)
-    gemv_launch<double>(desc, G, partial, st, want, tm, bytes);
+    gemv_launch<double>(desc, G, cw, partial, st, want, tm, bytes);
   else if (prec == P_FP32)
-    gemv_launch<float>(desc, G, partial, st, want, tm, bytes);
+    gemv_launch<float>(desc, G, cw, partial, st, want, tm, bytes);
   else
-    gemv_launch<uint16_t>(desc, G, partial, st, want, tm, bytes);
+    gemv_launch<uint16_t>(desc, G, cw, partial, st, want, tm, bytes);
   GDSW_HIP(hipGetLastError());
 }
 
@@ -153,8 +160,8 @@ void gemv_set(const FactorSet& fs, double* w, hipStream_t st, int slot, const in
   (void)w;  // the descriptors address the set's own work vector segments
   if (fs.count == 0 || slot >= (int)fs.gemv.size()) return;
   if (!fs.d_desc) throw StatusError{5, "inverse set used before its descriptors were built"};
-  gemv_desc_launch(fs.prec, fs.d_desc, fs.gemv[slot], fs.d_partial, st, want, slot == 0 ? fs.timer : nullptr,
-                   (double)fs.alg_bytes);
+  gemv_desc_launch(fs.prec, fs.d_desc, fs.gemv[slot], fs.cw, fs.d_partial, st, want,
+                   slot == 0 ? fs.timer : nullptr, (double)fs.alg_bytes);
 }
 
 void local_solve_set(const FactorSet& fs, double* w, hipStream_t st, int slot, const int32_t* want) {

@@ -39,10 +39,17 @@ struct BoxView {
   const int64_t* own_vidx;   // index into the CSR values
 };
 
+// z = sum_i R_i^T y_i + Phi y0.  With nsub > 0 the Phi_I y0 term runs as a
+// second, per-subdomain kernel over the column-major Phi_I (max_ni: largest
+// interior set); the result is the same either way.
 void scatter_prolong(int64_t n, const int32_t* inv_ptr, const int64_t* inv_pos, const double* w,
-                     const CoarseView& cv, const double* y0, const int32_t* y0_pos, double* z, hipStream_t st);
+                     const CoarseView& cv, const double* y0, const int32_t* y0_pos, double* z, hipStream_t st,
+                     int nsub = 0, int max_ni = 0);
+// out[pos[c]] = (Phi^T r)[c].  With t (n_pairs doubles, one per (subdomain,
+// local column) pair) the interior part is first reduced per pair, then
+// assembled per column in ascending subdomain order.
 void restrict_coarse(int nc, const CoarseView& cv, const double* r, double* out, const int32_t* out_pos,
-                     hipStream_t st);
+                     hipStream_t st, int n_pairs = 0, double* t = nullptr);
 void phi_rhs(int64_t total_I, const CoarseView& cv, const int32_t* rowptr, const int32_t* col, const double* val,
              double* B, hipStream_t st);
 void phi_transpose(int64_t total_I, const CoarseView& cv, const double* cm, double* rm, hipStream_t st);

@@ -105,10 +105,12 @@ __global__ void scatter_kernel(int64_t n, const int32_t* __restrict__ inv_ptr, c
 }
 
 // z[d] = sum of local copies (ascending subdomain) + (Phi y0)[d]
+// With `split`, interior DOFs receive only their local copies here and the
+// Phi_I y0 term is added by phi_prolong_kernel (same operands, same order).
 __global__ void scatter_prolong_kernel(int64_t n, const int32_t* __restrict__ inv_ptr,
                                        const int64_t* __restrict__ inv_pos, const double* __restrict__ w,
                                        CoarseView cv, const double* __restrict__ y0,
-                                       const int32_t* __restrict__ y0_pos, double* __restrict__ z) {
+                                       const int32_t* __restrict__ y0_pos, double* __restrict__ z, int split) {
   for (int64_t d = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; d < n; d += (int64_t)gridDim.x * blockDim.x) {
     double s = 0.0;
     for (int e = inv_ptr[d]; e < inv_ptr[d + 1]; ++e) s += w[inv_pos[e]];
@@ -116,7 +118,7 @@ __global__ void scatter_prolong_kernel(int64_t n, const int32_t* __restrict__ in
     const int32_t gc = cv.gamma_col[d];
     if (gc >= 0) {
       c = y0_pos ? w[y0_pos[gc]] : y0[gc];
-    } else {
+    } else if (!split) {
       const int32_t p = cv.dof_ipos[d];
       if (p >= 0) {
         const int i = cv.I_sub[p];
@@ -150,6 +152,61 @@ __global__ __launch_bounds__(256) void restrict_kernel(int nc_total, CoarseView 
   }
   const double t = block_sum<256>(s, sh);
   if (tid == 0) out[out_pos ? out_pos[c] : c] = t;
+}
+
+// z[I_i[k]] += sum_j Phi_I^(i)[k, j] y0[C_i[j]]: one thread per interior
+// row, the column-major Phi_I read contiguously across the threads.
+__global__ __launch_bounds__(256) void phi_prolong_kernel(CoarseView cv, const double* __restrict__ w,
+                                                          const double* __restrict__ y0,
+                                                          const int32_t* __restrict__ y0_pos,
+                                                          double* __restrict__ z) {
+  const int i = blockIdx.y;
+  const int ib = cv.I_ptr[i], ni = cv.I_ptr[i + 1] - ib;
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= ni) return;
+  const int cb = cv.C_ptr[i], nc = cv.C_ptr[i + 1] - cb;
+  const double* ph = cv.phi_cm + cv.phi_off[i] + k;
+  double c = 0.0;
+  for (int j = 0; j < nc; ++j) {
+    const int32_t cc = cv.C_idx[cb + j];
+    c = fma(ph[(int64_t)j * ni], y0_pos ? w[y0_pos[cc]] : y0[cc], c);
+  }
+  const int32_t d = cv.I_idx[ib + k];
+  z[d] = z[d] + c;
+}
+
+// t[e] = Phi_I^(i)[:, lc]^T r[I_i] for every (subdomain, local column) pair e
+__global__ __launch_bounds__(256) void phi_t_kernel(CoarseView cv, const double* __restrict__ r,
+                                                    double* __restrict__ t) {
+  __shared__ double sh[256];
+  const int e = blockIdx.x;
+  const int i = cv.cs_sub[e], lc = cv.cs_lc[e];
+  const int ib = cv.I_ptr[i], ni = cv.I_ptr[i + 1] - ib;
+  const double* ph = cv.phi_cm + cv.phi_off[i] + (int64_t)lc * ni;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < ni; k += 256) s = fma(ph[k], r[cv.I_idx[ib + k]], s);
+  const double v = block_sum<256>(s, sh);
+  if (threadIdx.x == 0) t[e] = v;
+}
+
+// out[c] = sum of r over the Gamma DOFs of column c + sum_e t[e] over its
+// pairs in ascending subdomain order; one wave per coarse column.
+__global__ __launch_bounds__(256) void restrict_assemble_kernel(int nc_total, CoarseView cv,
+                                                                const double* __restrict__ r,
+                                                                const double* __restrict__ t,
+                                                                double* __restrict__ out,
+                                                                const int32_t* __restrict__ out_pos) {
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (c >= nc_total) return;
+  double s = 0.0;
+  for (int e = cv.cg_ptr[c] + lane; e < cv.cg_ptr[c + 1]; e += 64) s += r[cv.cg_dof[e]];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) {
+    for (int e = cv.cs_ptr[c]; e < cv.cs_ptr[c + 1]; ++e) s += t[e];
+    out[out_pos ? out_pos[c] : c] = s;
+  }
 }
 
 // -(A[I_i, Gamma] Phi_Gamma) for the extension right-hand sides, column-major
@@ -467,15 +524,23 @@ void deterministic_scatter(int64_t n, const int32_t* inv_ptr, const int64_t* inv
 }
 
 void scatter_prolong(int64_t n, const int32_t* inv_ptr, const int64_t* inv_pos, const double* w,
-                     const CoarseView& cv, const double* y0, const int32_t* y0_pos, double* z, hipStream_t st) {
+                     const CoarseView& cv, const double* y0, const int32_t* y0_pos, double* z, hipStream_t st,
+                     int nsub, int max_ni) {
   if (n == 0) return;
-  scatter_prolong_kernel<<<grid_for(n), 256, 0, st>>>(n, inv_ptr, inv_pos, w, cv, y0, y0_pos, z);
+  const int split = nsub > 0 && max_ni > 0;
+  scatter_prolong_kernel<<<grid_for(n), 256, 0, st>>>(n, inv_ptr, inv_pos, w, cv, y0, y0_pos, z, split);
+  if (split) phi_prolong_kernel<<<dim3((max_ni + 255) / 256, nsub), 256, 0, st>>>(cv, w, y0, y0_pos, z);
 }
 
 void restrict_coarse(int nc, const CoarseView& cv, const double* r, double* out, const int32_t* out_pos,
-                     hipStream_t st) {
+                     hipStream_t st, int n_pairs, double* t) {
   if (nc == 0) return;
-  restrict_kernel<<<nc, 256, 0, st>>>(nc, cv, r, out, out_pos);
+  if (n_pairs > 0 && t) {
+    phi_t_kernel<<<n_pairs, 256, 0, st>>>(cv, r, t);
+    restrict_assemble_kernel<<<(nc + 3) / 4, 256, 0, st>>>(nc, cv, r, t, out, out_pos);
+  } else {
+    restrict_kernel<<<nc, 256, 0, st>>>(nc, cv, r, out, out_pos);
+  }
 }
 
 void phi_rhs(int64_t total_I, const CoarseView& cv, const int32_t* rowptr, const int32_t* col, const double* val,

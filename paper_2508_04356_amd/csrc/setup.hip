@@ -96,14 +96,15 @@ namespace {
 // partials of one row block are contiguous for the summation kernel.
 void plan_gemv(FactorSet& fs, DeviceArena& A, hipStream_t st, int slot, const std::vector<char>* include) {
   const int RB = gemv_rows(fs.prec);
+  const int CW = fs.cw;
   std::vector<int4> it1, it2;
   int p = 0;
   for (int f = 0; f < fs.count; ++f) {
     if (include && !(*include)[f]) continue;
     const int n = fs.n[f];
-    const int nr = (n + RB - 1) / RB, nc = (n + GEMV_CW - 1) / GEMV_CW;
+    const int nr = (n + RB - 1) / RB, nc = (n + CW - 1) / CW;
     for (int c = 0; c < nc; ++c)
-      for (int J = 0; J < nr; ++J) it1.push_back(make_int4(f, J * RB, c * GEMV_CW, p + J * nc + c));
+      for (int J = 0; J < nr; ++J) it1.push_back(make_int4(f, J * RB, c * CW, p + J * nc + c));
     for (int J = 0; J < nr; ++J) it2.push_back(make_int4(f, J * RB, p + J * nc, nc));
     p += nr * nc;
   }
@@ -517,6 +518,10 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
   ctx.d_cs_ptr = dupload(A, cs_ptr, st);
   ctx.d_cs_sub = dupload(A, cs_s, st);
   ctx.d_cs_lc = dupload(A, cs_l, st);
+  ctx.n_pairs = (int)cs_s.size();
+  ctx.d_pair_t = dalloc<double>(A, std::max(ctx.n_pairs, 1));
+  ctx.max_ni = 0;
+  for (int i = 0; i < P.n_sub; ++i) ctx.max_ni = std::max(ctx.max_ni, I_ptr[i + 1] - I_ptr[i]);
   ctx.d_phi_cm = dalloc<double>(A, std::max<int64_t>(phi_off.back(), 1));
   ctx.d_phi_rm = dalloc<double>(A, std::max<int64_t>(phi_off.back(), 1));
   CoarseView cv{ctx.d_gamma_col, ctx.d_dof_ipos, ctx.d_I_sub, ctx.d_I_ptr, ctx.d_I_idx, ctx.d_C_ptr,

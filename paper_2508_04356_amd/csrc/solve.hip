@@ -52,11 +52,12 @@ __global__ void cycle_start_kernel(double* __restrict__ g, int restart, double* 
 }
 
 // Arnoldi column j: H[:j+1, j] = h1 + h2, H[j+1, j] = ||w||, previous rotations,
-// new rotation, g update; scal[2] = |g_{j+1}| / bnorm, scal[3] = ||w||.
+// new rotation, g update; scal[2] = |g_{j+1}| / ||b||, scal[3] = ||w||.
 __global__ void arnoldi_finish_kernel(int j, int restart, const double* __restrict__ h1,
                                       const double* __restrict__ h2, double* __restrict__ H,
                                       double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
-                                      double* __restrict__ scal, double bnorm) {
+                                      double* __restrict__ scal) {
+  const double bnorm = scal[5];  // ||b||, stored once per solve (a captured graph reads it too)
   const int ldh = restart + 1;
   double* col = H + (int64_t)j * ldh;
   for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
@@ -91,8 +92,16 @@ __global__ void back_subst_kernel(int k, int restart, const double* __restrict__
 
 inline int grid_n(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(65536, (n + 255) / 256)); }
 
+void drop_graphs(Context& ctx) {
+  for (hipGraphExec_t& e : ctx.graphs.exec)
+    if (e) (void)hipGraphExecDestroy(e);
+  ctx.graphs.exec.clear();
+  ctx.graphs.V = nullptr;
+}
+
 void ensure_workspace(Context& ctx, int restart) {
   if (ctx.restart >= restart && ctx.d_V) return;
+  drop_graphs(ctx);
   DeviceArena& A = ctx.arena;
   for (void* p : {(void*)ctx.d_V, (void*)ctx.d_Z, (void*)ctx.d_H, (void*)ctx.d_g, (void*)ctx.d_cs,
                   (void*)ctx.d_sn, (void*)ctx.d_hv, (void*)ctx.d_part, (void*)ctx.d_scal, (void*)ctx.d_t1,
@@ -134,11 +143,11 @@ void apply_pre(Context& ctx, const double* r, hipStream_t st) {
   gather(ctx.n_w1, ctx.d_gidx, r, ctx.d_w, st);
   if (three) {
     // r0 = Phi^T r; level-2 copies R_j^(2) r0; level-3 right-hand side Phi3^T r0
-    restrict_coarse(ctx.Nc, cv, r, ctx.d_r0, nullptr, st);
+    restrict_coarse(ctx.Nc, cv, r, ctx.d_r0, nullptr, st, ctx.n_pairs, ctx.d_pair_t);
     gather(ctx.HI.total_x, ctx.d_g2idx, ctx.d_r0, ctx.d_w + ctx.n_w1, st);
     dense_cols_dot(ctx.d_phi3, ctx.Nc, ctx.Nc, ctx.Nc3, ctx.d_r0, ctx.d_w, ctx.d_c3_pinv, st);
   } else if (ctx.Nc > 0) {
-    restrict_coarse(ctx.Nc, cv, r, ctx.d_w, ctx.d_coarse_pinv, st);
+    restrict_coarse(ctx.Nc, cv, r, ctx.d_w, ctx.d_coarse_pinv, st, ctx.n_pairs, ctx.d_pair_t);
   }
 }
 
@@ -148,9 +157,11 @@ void apply_post(Context& ctx, double* z, hipStream_t st) {
   if (three) {
     // y0 = sum_j R_j^(2)T y_j + Phi3 y3, then z = sum_i R_i^T y_i + Phi y0
     scatter2(ctx.Nc, ctx.d_inv2_ptr, ctx.d_inv2_pos, ctx.d_w, ctx.d_phi3, ctx.Nc3, ctx.d_c3_pinv, ctx.d_y0, st);
-    scatter_prolong(ctx.P.n_free, ctx.d_inv_ptr, ctx.d_inv_pos, ctx.d_w, cv, ctx.d_y0, nullptr, z, st);
+    scatter_prolong(ctx.P.n_free, ctx.d_inv_ptr, ctx.d_inv_pos, ctx.d_w, cv, ctx.d_y0, nullptr, z, st,
+                    ctx.P.n_sub, ctx.max_ni);
   } else if (ctx.Nc > 0) {
-    scatter_prolong(ctx.P.n_free, ctx.d_inv_ptr, ctx.d_inv_pos, ctx.d_w, cv, nullptr, ctx.d_coarse_pinv, z, st);
+    scatter_prolong(ctx.P.n_free, ctx.d_inv_ptr, ctx.d_inv_pos, ctx.d_w, cv, nullptr, ctx.d_coarse_pinv, z, st,
+                    ctx.P.n_sub, ctx.max_ni);
   } else {
     deterministic_scatter(ctx.P.n_free, ctx.d_inv_ptr, ctx.d_inv_pos, ctx.d_w, z, st);
   }
@@ -187,10 +198,45 @@ void expand_solution(const Context& ctx, const double* xf, double* xfull, hipStr
   GDSW_HIP(hipGetLastError());
 }
 
+namespace {
+
+void put_bnorm(Context& ctx, double bnorm, hipStream_t st) {
+  ctx.h_pinned[8] = bnorm;
+  GDSW_HIP(hipMemcpyAsync(ctx.d_scal + 5, ctx.h_pinned + 8, sizeof(double), hipMemcpyHostToDevice, st));
+  GDSW_HIP(hipStreamSynchronize(st));
+}
+
+}  // namespace
+
+void release_graphs(Context& ctx) {
+  drop_graphs(ctx);
+  if (ctx.graphs.stream) (void)hipStreamDestroy(ctx.graphs.stream);
+  ctx.graphs.stream = nullptr;
+}
+
 FgmresResult fgmres(Context& ctx, const double* b, double* x, double rtol, int restart, int max_it, bool use_graph,
                     hipStream_t st, double* history, int history_len) {
-  (void)use_graph;
   ensure_workspace(ctx, restart);
+  // Graph mode: the iteration body for basis index j is captured once into a
+  // HIP graph (no memset nodes; every argument is fixed for a given j and
+  // workspace) and replayed in every later cycle and solve.  Capture needs a
+  // stream other than the legacy default one: the context's own stream then
+  // carries the whole solve.  The learned solve reads back counts inside the
+  // apply and stays eager.
+  const bool graph = use_graph && !(ctx.local_solver != 0 && ctx.learned);
+  if (graph) {
+    if (ctx.graphs.V != ctx.d_V || ctx.graphs.restart != restart) {
+      drop_graphs(ctx);
+      ctx.graphs.V = ctx.d_V;
+      ctx.graphs.restart = restart;
+      ctx.graphs.exec.assign(restart, nullptr);
+    }
+    if (st == nullptr) {
+      if (!ctx.graphs.stream) GDSW_HIP(hipStreamCreateWithFlags(&ctx.graphs.stream, hipStreamNonBlocking));
+      GDSW_HIP(hipStreamSynchronize(nullptr));  // the caller's earlier work on the default stream
+      st = ctx.graphs.stream;
+    }
+  }
   const int64_t n = ctx.P.n_free;
   const int64_t ldv = ctx.ldv;
   double* V = ctx.d_V;
@@ -204,8 +250,26 @@ FgmresResult fgmres(Context& ctx, const double* b, double* x, double rtol, int r
   GDSW_HIP(hipMemsetAsync(x, 0, n * sizeof(double), st));
   if (bnorm == 0.0) {
     res.converged = true;
+    GDSW_HIP(hipStreamSynchronize(st));
     return res;
   }
+  put_bnorm(ctx, bnorm, st);
+  auto body = [&](int j) {
+    double* vj = V + (int64_t)j * ldv;
+    double* zj = Z + (int64_t)j * ldv;
+    double* w = ctx.d_t2;
+    apply_precond(ctx, vj, zj, st);
+    spmv(ctx, zj, w, st);
+    cols_dot(V, ldv, j + 1, w, n, ctx.d_part, nb, ctx.d_hv, st);
+    gemv_sub(V, ldv, j + 1, ctx.d_hv, w, n, st);
+    cols_dot(V, ldv, j + 1, w, n, ctx.d_part, nb, ctx.d_hv + restart + 1, st);
+    gemv_sub(V, ldv, j + 1, ctx.d_hv + restart + 1, w, n, st);
+    cols_dot(w, ldv, 1, w, n, ctx.d_part, nb, S + 4, st);
+    arnoldi_finish_kernel<<<1, 1, 0, st>>>(j, restart, ctx.d_hv, ctx.d_hv + restart + 1, ctx.d_H, ctx.d_cs,
+                                           ctx.d_sn, ctx.d_g, S);
+    scale_div_kernel<<<grid_n(n), 256, 0, st>>>(n, w, S, 3, V + (int64_t)(j + 1) * ldv);
+    GDSW_HIP(hipMemcpyAsync(ctx.h_pinned, S + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  };
   int it = 0;
   int cycles = 0;
   while (true) {
@@ -224,20 +288,23 @@ FgmresResult fgmres(Context& ctx, const double* b, double* x, double rtol, int r
     scale_div_kernel<<<grid_n(n), 256, 0, st>>>(n, ctx.d_t1, S, 1, V);
     int k = 0;
     for (int j = 0; j < restart; ++j) {
-      double* vj = V + (int64_t)j * ldv;
-      double* zj = Z + (int64_t)j * ldv;
-      double* w = ctx.d_t2;
-      apply_precond(ctx, vj, zj, st);
-      spmv(ctx, zj, w, st);
-      cols_dot(V, ldv, j + 1, w, n, ctx.d_part, nb, ctx.d_hv, st);
-      gemv_sub(V, ldv, j + 1, ctx.d_hv, w, n, st);
-      cols_dot(V, ldv, j + 1, w, n, ctx.d_part, nb, ctx.d_hv + restart + 1, st);
-      gemv_sub(V, ldv, j + 1, ctx.d_hv + restart + 1, w, n, st);
-      cols_dot(w, ldv, 1, w, n, ctx.d_part, nb, S + 4, st);
-      arnoldi_finish_kernel<<<1, 1, 0, st>>>(j, restart, ctx.d_hv, ctx.d_hv + restart + 1, ctx.d_H, ctx.d_cs,
-                                             ctx.d_sn, ctx.d_g, S, bnorm);
-      scale_div_kernel<<<grid_n(n), 256, 0, st>>>(n, w, S, 3, V + (int64_t)(j + 1) * ldv);
-      GDSW_HIP(hipMemcpyAsync(ctx.h_pinned, S + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+      if (graph) {
+        hipGraphExec_t& e = ctx.graphs.exec[j];
+        if (!e) {
+          KernelTimer* tm = ctx.L1.timer;
+          ctx.L1.timer = nullptr;  // no event nodes in the graph
+          hipGraph_t g = nullptr;
+          GDSW_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+          body(j);
+          GDSW_HIP(hipStreamEndCapture(st, &g));
+          ctx.L1.timer = tm;
+          GDSW_HIP(hipGraphInstantiate(&e, g, nullptr, nullptr, 0));
+          GDSW_HIP(hipGraphDestroy(g));
+        }
+        GDSW_HIP(hipGraphLaunch(e, st));
+      } else {
+        body(j);
+      }
       GDSW_HIP(hipStreamSynchronize(st));
       const double rel = ctx.h_pinned[0];
       const double hn = ctx.h_pinned[1];
@@ -265,6 +332,7 @@ FgmresResult fgmres(Context& ctx, const double* b, double* x, double rtol, int r
   }
   res.iterations = it;
   res.restarts = std::max(0, cycles - 1);
+  GDSW_HIP(hipStreamSynchronize(st));
   GDSW_HIP(hipGetLastError());
   return res;
 }
@@ -295,6 +363,8 @@ std::vector<FgmresResult> fgmres_batch(Batch& bt, const double* const* bvec, dou
     if (bnorm[k] == 0.0) {
       res[k].converged = true;
       done[k] = 1;
+    } else {
+      put_bnorm(*bt.m[k], bnorm[k], st);
     }
   }
   while (true) {
@@ -350,7 +420,7 @@ std::vector<FgmresResult> fgmres_batch(Batch& bt, const double* const* bvec, dou
         gemv_sub(V, c.ldv, j + 1, c.d_hv + restart + 1, w, n, st);
         cols_dot(w, c.ldv, 1, w, n, c.d_part, c.n_part_blocks, c.d_scal + 4, st);
         arnoldi_finish_kernel<<<1, 1, 0, st>>>(j, restart, c.d_hv, c.d_hv + restart + 1, c.d_H, c.d_cs, c.d_sn,
-                                               c.d_g, c.d_scal, bnorm[k]);
+                                               c.d_g, c.d_scal);
         scale_div_kernel<<<grid_n(n), 256, 0, st>>>(n, w, c.d_scal, 3, V + (int64_t)(j + 1) * c.ldv);
         GDSW_HIP(hipMemcpyAsync(hp + 2 * k, c.d_scal + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
       }
