@@ -264,6 +264,7 @@ def main():
                     help="explicit inverses (default) or LU triangular solves")
     ap.add_argument("--nrhs", type=int, default=None,
                     help="right-hand sides solved together (default: the workload's; C3 has 32)")
+    ap.add_argument("--graph", action="store_true", help="replay each FGMRES iteration as a captured HIP graph")
     ap.add_argument("--applies", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -316,13 +317,13 @@ def main():
     x = torch.zeros_like(b)
 
     for _ in range(args.warmup):
-        s.fgmres(b, x, rtol=w.rtol, restart=w.restart, max_it=w.max_it)
+        s.fgmres(b, x, rtol=w.rtol, restart=w.restart, max_it=w.max_it, use_graph=args.graph)
     torch.cuda.synchronize()
     its = []
     s.kernel_timer(True)
     t0 = time.perf_counter()
     for k in range(args.steps):
-        info = s.fgmres(b, x, rtol=w.rtol, restart=w.restart, max_it=w.max_it)[0]
+        info = s.fgmres(b, x, rtol=w.rtol, restart=w.restart, max_it=w.max_it, use_graph=args.graph)[0]
         its.append(info.iterations)
     torch.cuda.synchronize()
     t_steps = time.perf_counter() - t0
@@ -344,13 +345,22 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     t_apply_ms = e0.elapsed_time(e1) / args.applies
+    timed_in = "the timed FGMRES solves"
+    if k_launches == 0:  # graph replays carry no event nodes: time the same kernel in eager applies
+        s.kernel_timer(True)
+        for _ in range(args.applies):
+            s.apply(r, z)
+        torch.cuda.synchronize()
+        s.kernel_timer(False)
+        k_ms, k_launches, k_bytes = s.kernel_timer_read()
+        timed_in = "eager applies after the graph-replayed solves"
     phases = np.array([s.profile_apply(r, z) for _ in range(10)])
     ph = phases.mean(axis=0)
     solve_bytes = float(sz.solve_bytes)
     launches = int(sz.solve_launches)
     k_avg_us = 1e3 * k_ms / max(k_launches, 1)
     achieved = k_bytes / (k_avg_us * 1e-6) / 1e9
-    per_apply = k_launches / max(sum(its), 1)
+    per_apply = k_launches / max(sum(its), 1) if timed_in.startswith("the timed") else k_launches / args.applies
     kname = ("gemv_part_kernel (level-1 explicit inverses times the local vectors)" if args.local_solve == "inverse"
              else "trsv_step_kernel (blocked forward/backward solves of the level-1 factors)")
     log(f"[bench] apply {t_apply_ms:.3f} ms; phases ms gather/restrict {ph[0]:.3f} solve {ph[1]:.3f}+{ph[2]:.3f} "
@@ -382,13 +392,14 @@ def main():
         "apply_phases_ms": {"gather_restrict": ph[0], "solve_l1": ph[1], "solve_coarse": ph[2], "scatter": ph[3]},
         "setup_s": t_setup,
         "local_solve": args.local_solve,
+        "graph": bool(args.graph),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": (measured_traffic(args.local_solve, round(per_apply))
                                  if args.workload == "C2" and not alg and prec == "fp64" else None),
                      "kernel": kname,
                      "bytes_per_launch": k_bytes, "launches_timed": k_launches,
-                     "launches_per_apply": per_apply, "avg_launch_us": k_avg_us,
+                     "launches_per_apply": per_apply, "avg_launch_us": k_avg_us, "timed_in": timed_in,
                      "solve_bytes_per_apply_all_sets": solve_bytes, "solve_launches_per_apply_all_sets": launches},
     }
     if not args.no_cpu_baseline and args.workload == "C2":
