@@ -162,6 +162,7 @@ struct Context {
   double* d_wm = nullptr;          // n_w x max_rhs work vectors
   double* d_xin = nullptr;         // n_free x max_rhs (ABI column-major input, interleaved)
   double* d_xout = nullptr;
+  double* d_pair_tm = nullptr;     // n_pairs x max_rhs per-pair restriction sums
   struct MultiKrylov {
     int restart = 0, K = 0, nblocks = 0;
     int64_t ldv = 0;               // n_free * K

@@ -27,21 +27,34 @@ typedef float mf_f4 __attribute__((ext_vector_type(4)));
 typedef double mf_d4 __attribute__((ext_vector_type(4)));
 typedef __bf16 mf_bf8 __attribute__((ext_vector_type(8)));
 
+#ifndef GDSW_GEMM_H
+#define GDSW_GEMM_H 1     // FP64/FP32: row groups of 16 E rows per wave
+#endif
+#ifndef GDSW_GEMM_HB
+#define GDSW_GEMM_HB 4    // BF16: 16-row output tiles per wave
+#endif
+#ifndef GDSW_GEMM_SC
+#define GDSW_GEMM_SC 64   // FP64/FP32: columns staged per step
+#endif
+#ifndef GDSW_GEMM_SCB
+#define GDSW_GEMM_SCB 128 // BF16: columns staged per step
+#endif
+
 template <typename T>
 struct MultiShape;
 template <>
 struct MultiShape<double> {  // v_mfma_f64_16x16x4: a lane's 16-byte load = 2 rows of one column
-  static constexpr int RB = 128, SC = 64;
+  static constexpr int H = GDSW_GEMM_H, RB = 4 * H * 32, SC = GDSW_GEMM_SC;
   using P = double;
 };
 template <>
 struct MultiShape<float> {  // v_mfma_f32_16x16x4f32: 4 rows of one column
-  static constexpr int RB = 256, SC = 64;
+  static constexpr int H = GDSW_GEMM_H, RB = 4 * H * 64, SC = GDSW_GEMM_SC;
   using P = float;
 };
 template <>
 struct MultiShape<uint16_t> {  // v_mfma_f32_16x16x32_bf16: 8 entries along the summation index
-  static constexpr int RB = 256, SC = 256;
+  static constexpr int H = GDSW_GEMM_HB, RB = 4 * H * 16, SC = GDSW_GEMM_SCB;
   using P = float;
 };
 
@@ -66,9 +79,10 @@ __device__ inline void stage_x(XT* xs, const double* __restrict__ x, int64_t ldk
   }
 }
 
-// FP64 and FP32 storage: lane l loads E = 16 / sizeof(T) consecutive rows
-// (Rw + E * (l % 16) + v) of column c + l / 16; MFMA v uses A[i][k] =
-// M[Rw + E i + v][c + k] and B[k][j] = x[c + k][j].
+// FP64 and FP32 storage: for each of H row groups h, lane l loads
+// E = 16 / sizeof(T) consecutive rows (Rw + 16 E h + E (l % 16) + v) of
+// column c + l / 16; MFMA (h, v) uses A[i][k] = M[Rw + 16 E h + E i + v][c + k]
+// and B[k][j] = x[c + k][j].
 template <typename T, int G>
 __global__ __launch_bounds__(256) void gemm_part_kernel(const T* __restrict__ store, const int64_t* __restrict__ OFF,
                                                         const int32_t* __restrict__ N, const int32_t* __restrict__ NP,
@@ -80,7 +94,7 @@ __global__ __launch_bounds__(256) void gemm_part_kernel(const T* __restrict__ st
   using P = typename S::P;
   using ACC = typename std::conditional<sizeof(T) == 8, mf_d4, mf_f4>::type;
   constexpr int E = 16 / sizeof(T);
-  constexpr int RB = S::RB, SC = S::SC;
+  constexpr int H = S::H, RB = S::RB, SC = S::SC;
   __shared__ T xs[SC * 32];
   const int4 item = items[blockIdx.x];
   const int f = item.x, r0 = item.y, c0 = item.z, p = item.w;
@@ -90,55 +104,71 @@ __global__ __launch_bounds__(256) void gemm_part_kernel(const T* __restrict__ st
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = lane & 15, kq = lane >> 4;
   const int Rw = r0 + wave * (RB / 4);
-  const int row = Rw + E * i;
-  const bool rok = row < n;
-  const T* base = store + OFF[f] + row;
+  bool rok[H];
+#pragma unroll
+  for (int h = 0; h < H; ++h) rok[h] = Rw + 16 * E * h + E * i < n;
+  const T* base = store + OFF[f] + Rw + E * i;
   const double* x = w + XOFF[f] * ldk;
-  ACC acc[E][G];
+  ACC acc[H][E][G];
 #pragma unroll
-  for (int v = 0; v < E; ++v)
+  for (int h = 0; h < H; ++h)
 #pragma unroll
-    for (int g = 0; g < G; ++g) acc[v][g] = ACC{0, 0, 0, 0};
+    for (int v = 0; v < E; ++v)
+#pragma unroll
+      for (int g = 0; g < G; ++g) acc[h][v][g] = ACC{0, 0, 0, 0};
   for (int c = c0; c < cend; c += SC) {
-    __syncthreads();
-    stage_x<T, T, SC, false>(xs, x + (int64_t)c * ldk, ldk, nrhs, min(SC, cend - c));
-    __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < SC; kk += 4) {
-      const int col = c + kk + kq;
-      T a[E];
-      if (rok && col < cend) {
-        load16_nt(base + (int64_t)col * np, a);
-      } else {
+    // every matrix load of the step is issued first (they do not depend on
+    // the staged right-hand sides), then the staging, then the products
+    constexpr int Q = SC / 4;
+    T a[Q][H][E];
 #pragma unroll
-        for (int v = 0; v < E; ++v) a[v] = 0;
-      }
+    for (int q = 0; q < Q; ++q) {
+      const int col = c + 4 * q + kq;
 #pragma unroll
-      for (int g = 0; g < G; ++g) {
-        const T b = xs[(kk + kq) * 32 + g * 16 + i];
+      for (int h = 0; h < H; ++h) {
+        if (rok[h] && col < cend) {
+          load16_nt(base + 16 * E * h + (int64_t)col * np, a[q][h]);
+        } else {
 #pragma unroll
-        for (int v = 0; v < E; ++v) {
-          if constexpr (sizeof(T) == 8)
-            acc[v][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[v], b, acc[v][g], 0, 0, 0);
-          else
-            acc[v][g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[v], b, acc[v][g], 0, 0, 0);
+          for (int v = 0; v < E; ++v) a[q][h][v] = 0;
         }
       }
     }
+    __syncthreads();
+    stage_x<T, T, SC, false>(xs, x + (int64_t)c * ldk, ldk, nrhs, min(SC, cend - c));
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const T b = xs[(4 * q + kq) * 32 + g * 16 + i];
+#pragma unroll
+        for (int h = 0; h < H; ++h)
+#pragma unroll
+          for (int v = 0; v < E; ++v) {
+            if constexpr (sizeof(T) == 8)
+              acc[h][v][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q][h][v], b, acc[h][v][g], 0, 0, 0);
+            else
+              acc[h][v][g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q][h][v], b, acc[h][v][g], 0, 0, 0);
+          }
+      }
+    }
   }
-  // D_v[i'][j] = y[Rw + E i' + v][16 g + j], j = i.  Accumulator register t
-  // of a lane holds output row i' = 4 kq + t for the f32 shape and
+  // D_(h,v)[i'][j] = y[Rw + 16 E h + E i' + v][16 g + j], j = i.  Accumulator
+  // register t of a lane holds output row i' = 4 kq + t for the f32 shape and
   // i' = kq + 4 t for the f64 shape (groups of one row strided by 4).
   P* out = partial + (int64_t)p * RB * 32;
 #pragma unroll
   for (int g = 0; g < G; ++g)
 #pragma unroll
-    for (int v = 0; v < E; ++v)
+    for (int h = 0; h < H; ++h)
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int ip = sizeof(T) == 8 ? kq + 4 * t : 4 * kq + t;
-        out[(int64_t)(wave * (RB / 4) + E * ip + v) * 32 + g * 16 + i] = (P)acc[v][g][t];
-      }
+      for (int v = 0; v < E; ++v)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int ip = sizeof(T) == 8 ? kq + 4 * t : 4 * kq + t;
+          out[(int64_t)(wave * (RB / 4) + 16 * E * h + E * ip + v) * 32 + g * 16 + i] = (P)acc[h][v][g][t];
+        }
 }
 
 // BF16 storage (the stored inverse is symmetric): lane l loads 2 x 8
@@ -154,7 +184,7 @@ __global__ __launch_bounds__(256) void gemm_part_bf16_kernel(const uint16_t* __r
                                                              const double* __restrict__ w, int64_t ldk, int nrhs,
                                                              float* __restrict__ partial) {
   using S = MultiShape<uint16_t>;
-  constexpr int RB = S::RB, SC = S::SC;
+  constexpr int H = S::H, RB = S::RB, SC = S::SC;
   __shared__ uint16_t xs[32 * SC];  // [rhs][col]
   const int4 item = items[blockIdx.x];
   const int f = item.x, r0 = item.y, c0 = item.z, p = item.w;
@@ -165,34 +195,45 @@ __global__ __launch_bounds__(256) void gemm_part_bf16_kernel(const uint16_t* __r
   const int i = lane & 15, kq = lane >> 4;
   const int Rw = r0 + wave * (RB / 4);
   const double* x = w + XOFF[f] * ldk;
-  mf_f4 acc[4][G];
+  mf_f4 acc[H][G];
 #pragma unroll
-  for (int h = 0; h < 4; ++h)
+  for (int h = 0; h < H; ++h)
 #pragma unroll
     for (int g = 0; g < G; ++g) acc[h][g] = mf_f4{0, 0, 0, 0};
   for (int c = c0; c < cend; c += SC) {
+    // matrix loads of the step first, then the staging, then the products
+    constexpr int Q = SC / 64;
+    gdsw_u4 a[Q][H][2];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int r = c + 64 * q + 16 * kq;  // first summation index of this lane
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
+        const int ocol = Rw + 16 * h + i;  // output row = storage column (symmetry)
+        a[q][h][0] = gdsw_u4{0, 0, 0, 0};
+        a[q][h][1] = gdsw_u4{0, 0, 0, 0};
+        if (ocol < n && r < cend) {
+          const uint16_t* src = store + OFF[f] + (int64_t)ocol * np + r;
+          a[q][h][0] = __builtin_nontemporal_load(reinterpret_cast<const gdsw_u4*>(src));
+          a[q][h][1] = __builtin_nontemporal_load(reinterpret_cast<const gdsw_u4*>(src + 8));
+        }
+      }
+    }
     __syncthreads();
     stage_x<uint16_t, uint16_t, SC, true>(xs, x + (int64_t)c * ldk, ldk, nrhs, min(SC, cend - c));
     __syncthreads();
-    for (int kk = 0; kk < SC && c + kk < cend; kk += 64) {
-      const int r = c + kk + 16 * kq;  // first summation index of this lane
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
       mf_bf8 bx[G][2];
 #pragma unroll
       for (int g = 0; g < G; ++g)
 #pragma unroll
         for (int s2 = 0; s2 < 2; ++s2)
-          bx[g][s2] = *reinterpret_cast<const mf_bf8*>(&xs[(g * 16 + i) * SC + kk + 16 * kq + 8 * s2]);
+          bx[g][s2] = *reinterpret_cast<const mf_bf8*>(&xs[(g * 16 + i) * SC + 64 * q + 16 * kq + 8 * s2]);
 #pragma unroll
-      for (int h = 0; h < 4; ++h) {
-        const int ocol = Rw + 16 * h + i;  // output row = storage column (symmetry)
-        gdsw_u4 a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0};
-        if (ocol < n && r < cend) {
-          const uint16_t* src = store + OFF[f] + (int64_t)ocol * np + r;
-          a0 = __builtin_nontemporal_load(reinterpret_cast<const gdsw_u4*>(src));
-          a1 = __builtin_nontemporal_load(reinterpret_cast<const gdsw_u4*>(src + 8));
-        }
-        const mf_bf8 A0 = __builtin_bit_cast(mf_bf8, a0);
-        const mf_bf8 A1 = __builtin_bit_cast(mf_bf8, a1);
+      for (int h = 0; h < H; ++h) {
+        const mf_bf8 A0 = __builtin_bit_cast(mf_bf8, a[q][h][0]);
+        const mf_bf8 A1 = __builtin_bit_cast(mf_bf8, a[q][h][1]);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
           acc[h][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, bx[g][0], acc[h][g], 0, 0, 0);
@@ -205,7 +246,7 @@ __global__ __launch_bounds__(256) void gemm_part_bf16_kernel(const uint16_t* __r
 #pragma unroll
   for (int g = 0; g < G; ++g)
 #pragma unroll
-    for (int h = 0; h < 4; ++h)
+    for (int h = 0; h < H; ++h)
 #pragma unroll
       for (int t = 0; t < 4; ++t)
         out[(int64_t)(wave * (RB / 4) + 16 * h + 4 * kq + t) * 32 + g * 16 + i] = acc[h][g][t];
@@ -265,7 +306,9 @@ void gemm_launch(const FactorSet& fs, double* w, int64_t ldk, int nrhs, hipStrea
 
 }  // namespace
 
-int gemm_rows(int prec) { return prec == P_FP64 ? MultiShape<double>::RB : MultiShape<float>::RB; }
+int gemm_rows(int prec) {
+  return prec == P_FP64 ? MultiShape<double>::RB : prec == P_FP32 ? MultiShape<float>::RB : MultiShape<uint16_t>::RB;
+}
 
 void gemm_set(const FactorSet& fs, double* w, int64_t ldk, int nrhs, hipStream_t st) {
   if (fs.count == 0 || nrhs == 0) return;

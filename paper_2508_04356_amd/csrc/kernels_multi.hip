@@ -90,11 +90,69 @@ __global__ __launch_bounds__(256) void restrict_il_kernel(int nc, int K, CoarseV
   }
 }
 
+// t[e, j] = Phi_I^(i)[:, lc]^T r[I_i, j] for every (subdomain, local column)
+// pair e: 8 row lanes x 32 right-hand sides, fixed-order combination.
+__global__ __launch_bounds__(256) void phi_t_il_kernel(int K, CoarseView cv, const double* __restrict__ r,
+                                                       double* __restrict__ t) {
+  __shared__ double sh[8][32];
+  const int e = blockIdx.x;
+  const int j = threadIdx.x & 31, rl = threadIdx.x >> 5;
+  const int i = cv.cs_sub[e], lc = cv.cs_lc[e];
+  const int ib = cv.I_ptr[i], ni = cv.I_ptr[i + 1] - ib;
+  const double* ph = cv.phi_cm + cv.phi_off[i] + (int64_t)lc * ni;
+  double s = 0.0;
+  if (j < K)
+    for (int k = rl; k < ni; k += 8) s = fma(ph[k], r[(int64_t)cv.I_idx[ib + k] * K + j], s);
+  sh[rl][j] = s;
+  __syncthreads();
+  if (rl == 0 && j < K) {
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v += sh[q][j];
+    t[(int64_t)e * K + j] = v;
+  }
+}
+
+// w[out_pos[c], j] = sum over the Gamma DOFs of column c of r[d, j] + sum of
+// t[e, j] over its pairs in ascending subdomain order; 8 columns per block.
+__global__ __launch_bounds__(256) void restrict_assemble_il_kernel(int nc, int K, CoarseView cv,
+                                                                   const double* __restrict__ r,
+                                                                   const double* __restrict__ t,
+                                                                   double* __restrict__ w,
+                                                                   const int32_t* __restrict__ out_pos) {
+  const int c = blockIdx.x * 8 + (threadIdx.x >> 5);
+  const int j = threadIdx.x & 31;
+  if (c >= nc || j >= K) return;
+  double s = 0.0;
+  for (int e = cv.cg_ptr[c]; e < cv.cg_ptr[c + 1]; ++e) s += r[(int64_t)cv.cg_dof[e] * K + j];
+  for (int e = cv.cs_ptr[c]; e < cv.cs_ptr[c + 1]; ++e) s += t[(int64_t)e * K + j];
+  w[(int64_t)out_pos[c] * K + j] = s;
+}
+
+// z[I_i[k], j] += sum_q Phi_I^(i)[k, q] y0[C_i[q], j]: block (row chunk,
+// subdomain), threads (8 rows) x (32 right-hand sides).
+__global__ __launch_bounds__(256) void phi_prolong_il_kernel(int K, CoarseView cv, const double* __restrict__ w,
+                                                             const int32_t* __restrict__ y0_pos,
+                                                             double* __restrict__ z) {
+  const int i = blockIdx.y;
+  const int ib = cv.I_ptr[i], ni = cv.I_ptr[i + 1] - ib;
+  const int k = blockIdx.x * 8 + (threadIdx.x >> 5);
+  const int j = threadIdx.x & 31;
+  if (k >= ni || j >= K) return;
+  const int cb = cv.C_ptr[i], nc = cv.C_ptr[i + 1] - cb;
+  const double* ph = cv.phi_cm + cv.phi_off[i] + k;
+  double c = 0.0;
+  for (int q = 0; q < nc; ++q) c = fma(ph[(int64_t)q * ni], w[(int64_t)y0_pos[cv.C_idx[cb + q]] * K + j], c);
+  const int64_t d = cv.I_idx[ib + k];
+  z[d * K + j] += c;
+}
+
 // z[d, :] = sum of local copies (ascending subdomain) + (Phi y_0)[d, :],
 // y_0 read from the work vector at y0_pos (or absent when cv.gamma_col is null).
 __global__ void scatter_prolong_il_kernel(int64_t n, int K, const int32_t* __restrict__ inv_ptr,
                                           const int64_t* __restrict__ inv_pos, const double* __restrict__ w,
-                                          CoarseView cv, const int32_t* __restrict__ y0_pos, double* __restrict__ z) {
+                                          CoarseView cv, const int32_t* __restrict__ y0_pos, double* __restrict__ z,
+                                          int split) {
   const int64_t total = n * K;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t d = e / K;
@@ -106,7 +164,7 @@ __global__ void scatter_prolong_il_kernel(int64_t n, int K, const int32_t* __res
       const int32_t gc = cv.gamma_col[d];
       if (gc >= 0) {
         c = w[(int64_t)y0_pos[gc] * K + j];
-      } else {
+      } else if (!split) {
         const int32_t p = cv.dof_ipos[d];
         if (p >= 0) {
           const int i = cv.I_sub[p];
@@ -233,15 +291,23 @@ void gather_il(int64_t count, int K, const int32_t* idx, const double* src, doub
 }
 
 void restrict_il(int nc, int K, const CoarseView& cv, const double* r, double* w, const int32_t* out_pos,
-                 hipStream_t st) {
+                 hipStream_t st, int n_pairs, double* t) {
   if (nc == 0) return;
-  restrict_il_kernel<<<nc, 256, 0, st>>>(nc, K, cv, r, w, out_pos);
+  if (n_pairs > 0 && t) {
+    phi_t_il_kernel<<<n_pairs, 256, 0, st>>>(K, cv, r, t);
+    restrict_assemble_il_kernel<<<(nc + 7) / 8, 256, 0, st>>>(nc, K, cv, r, t, w, out_pos);
+  } else {
+    restrict_il_kernel<<<nc, 256, 0, st>>>(nc, K, cv, r, w, out_pos);
+  }
 }
 
 void scatter_prolong_il(int64_t n, int K, const int32_t* inv_ptr, const int64_t* inv_pos, const double* w,
-                        const CoarseView& cv, const int32_t* y0_pos, double* z, hipStream_t st) {
+                        const CoarseView& cv, const int32_t* y0_pos, double* z, hipStream_t st, int nsub,
+                        int max_ni) {
   if (n == 0) return;
-  scatter_prolong_il_kernel<<<grid_for(n * K), 256, 0, st>>>(n, K, inv_ptr, inv_pos, w, cv, y0_pos, z);
+  const int split = y0_pos && nsub > 0 && max_ni > 0;
+  scatter_prolong_il_kernel<<<grid_for(n * K), 256, 0, st>>>(n, K, inv_ptr, inv_pos, w, cv, y0_pos, z, split);
+  if (split) phi_prolong_il_kernel<<<dim3((max_ni + 7) / 8, nsub), 256, 0, st>>>(K, cv, w, y0_pos, z);
 }
 
 void spmm_il(int64_t nrows, int K, const int32_t* rowptr, const int32_t* col, const double* val, const double* x,

@@ -847,6 +847,7 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
     ctx.d_wm = dalloc<double>(A, std::max<int64_t>(ctx.n_w, 1) * K);
     ctx.d_xin = dalloc<double>(A, std::max<int64_t>(n, 1) * K);
     ctx.d_xout = dalloc<double>(A, std::max<int64_t>(n, 1) * K);
+    ctx.d_pair_tm = dalloc<double>(A, (int64_t)std::max(ctx.n_pairs, 1) * K);
   }
   GDSW_HIP(hipStreamSynchronize(st));
 }
