@@ -80,6 +80,25 @@ TRAFFIC = {  # committed counter summaries of the dominant kernel on the 16^3 FP
 }
 
 
+def copy_bandwidth(torch, dev, gib=1, reps=5):
+    """HBM bandwidth of a 1 GiB device-to-device copy (bytes read + written
+    per second), the practical ceiling the roofline fraction is compared with."""
+    n = (gib << 30) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2.0 * n * 4 / (ms * 1e-3) / 1e9
+
+
 def measured_traffic(solve, launches):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary, or None when the kernel source changed since it was measured."""
@@ -402,6 +421,10 @@ def main():
                      "launches_per_apply": per_apply, "avg_launch_us": k_avg_us, "timed_in": timed_in,
                      "solve_bytes_per_apply_all_sets": solve_bytes, "solve_launches_per_apply_all_sets": launches},
     }
+    cbw = copy_bandwidth(torch, dev)
+    out["roofline"]["measured_copy_gbs"] = cbw
+    out["roofline"]["frac_of_copy"] = achieved / cbw
+    log(f"[bench] 1 GiB copy: {cbw:.0f} GB/s (read + write); dominant kernel at {achieved / cbw:.3f} of it")
     if not args.no_cpu_baseline and args.workload == "C2":
         log("[bench] CPU oracle sample ...")
         out["cpu_baseline"] = cpu_baseline(w)
