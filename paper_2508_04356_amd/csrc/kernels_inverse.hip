@@ -26,6 +26,7 @@ namespace gdsw {
 namespace {
 
 constexpr int GB = 64;  // Gauss-Jordan block
+typedef double mf64x4 __attribute__((ext_vector_type(4)));
 
 __device__ inline void track_min_pivot(double piv, double& mn) {
   const double a = fabs(piv);
@@ -179,18 +180,40 @@ __global__ __launch_bounds__(256) void gj_update_kernel(double* __restrict__ bas
     Ys[r][l] = (l < cb && r < bs) ? T[(int64_t)(c0 + l) * GB + r] : 0.0;  // Ys[l = r][col = l]
   }
   __syncthreads();
-  const int tx = tid & 15, ty = tid >> 4;
-  double acc[4][4] = {};
-  tile_mm64(Xs, Ys, tx, ty, acc);
+  // 64 x 64 x 64 product on the matrix cores (v_mfma_f64_16x16x4), computed
+  // transposed, D = (X Y)^T, so that a lane's results are consecutive rows
+  // of the column-major tile: wave w owns the 32 x 32 quadrant (w / 2, w % 2)
+  // as 2 x 2 blocks of 16 x 16; lane (i, kq) feeds A[i][kq] = Y[kq][col i]
+  // and B[kq][i] = X[row i][kq] of every 4-deep step.
+  const int lane = tid & 63, wave = tid >> 6;
+  const int i = lane & 15, kq = lane >> 4;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  mf64x4 acc[2][2];  // [row block][column block]
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const int c = ty + 16 * b;
-    if (c >= cb) continue;
+  for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int r = tx + 16 * a;
-      if (r < rb) A[(int64_t)(c0 + c) * ld + r0 + r] -= acc[a][b];
-    }
+    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = mf64x4{0, 0, 0, 0};
+#pragma unroll 4
+  for (int l0 = 0; l0 < GB; l0 += 4) {
+    const double x0 = Xs[wr + i][l0 + kq], x1 = Xs[wr + 16 + i][l0 + kq];
+    const double y0 = Ys[l0 + kq][wc + i], y1 = Ys[l0 + kq][wc + 16 + i];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0, x0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(y1, x0, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0, x1, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(y1, x1, acc[1][1], 0, 0, 0);
+  }
+  // accumulator register t of a lane: D row kq + 4 t = tile column, D column i = tile row
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi) {
+    const int r = wr + 16 * bi + i;
+    if (r >= rb) continue;
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int t4 = 0; t4 < 4; ++t4) {
+        const int c = wc + 16 * bj + kq + 4 * t4;
+        if (c < cb) A[(int64_t)(c0 + c) * ld + r0 + r] -= acc[bi][bj][t4];
+      }
   }
 }
 

@@ -393,7 +393,7 @@ __global__ void scatter2_kernel(int Nc, const int32_t* __restrict__ inv_ptr, con
 }
 
 // ---- Krylov helpers --------------------------------------------------------
-constexpr int DOT_CHUNK = 1024;  // rows per partial block
+constexpr int DOT_CHUNK = 256;  // rows per partial block (enough blocks to fill the device at 1e5 rows)
 
 // part[b * ncols + j] = sum over rows of block b of V[:, j] * w
 __global__ __launch_bounds__(256) void cols_dot_partial_kernel(const double* __restrict__ V, int64_t ldv, int ncols,
