@@ -80,6 +80,37 @@ TRAFFIC = {  # committed counter summaries of the dominant kernel on the 16^3 FP
 }
 
 
+def learned_variant(s, b, w, steps):
+    """Train the conv-net local solve on method-generated pairs, then time
+    FGMRES to the same tolerance with it (with and without the exact
+    fallback) beside the exact local solves."""
+    import torch
+
+    t0 = time.perf_counter()
+    info = s.learned_init(seed=7)
+    hist = s.learned_train(solves=4, steps=600, batch=32, lr=2e-3, seed=3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    res = {"interior_subdomains": info.subdomains, "grid": info.grid, "train_s": t_train,
+           "loss_first": float(np.mean(hist[:20])), "loss_last": float(np.mean(hist[-20:]))}
+    for name, mode, tau in (("exact", "lu", 0.7), ("learned", "learned", 1e30), ("learned_fallback", "learned", 0.7)):
+        s.set_local_solver(mode, tau)
+        x = torch.zeros_like(b)
+        s.fgmres(b, x, rtol=w.rtol, restart=w.restart, max_it=w.max_it, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            inf = s.fgmres(b, x, rtol=w.rtol, restart=w.restart, max_it=w.max_it, raise_on_noconv=False)[0]
+        torch.cuda.synchronize()
+        res[name] = {"iterations": inf.iterations, "true_rel_res": inf.true_rel_res,
+                     "time_to_tol_ms": 1e3 * (time.perf_counter() - t0) / steps}
+        log(f"[bench] {name}: {inf.iterations} iterations, {res[name]['time_to_tol_ms']:.1f} ms")
+    n_l, n_fb = s.learned_stats()
+    res["learned_solves"], res["fallbacks"] = n_l, n_fb
+    s.set_local_solver("lu")
+    return res
+
+
 def copy_bandwidth(torch, dev, gib=1, reps=5):
     """HBM bandwidth of a 1 GiB device-to-device copy (bytes read + written
     per second), the practical ceiling the roofline fraction is compared with."""
@@ -284,6 +315,8 @@ def main():
     ap.add_argument("--nrhs", type=int, default=None,
                     help="right-hand sides solved together (default: the workload's; C3 has 32)")
     ap.add_argument("--graph", action="store_true", help="replay each FGMRES iteration as a captured HIP graph")
+    ap.add_argument("--learned", action="store_true",
+                    help="also train the conv-net local solve (interior subdomains) and time FGMRES with it")
     ap.add_argument("--applies", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -421,6 +454,8 @@ def main():
                      "launches_per_apply": per_apply, "avg_launch_us": k_avg_us, "timed_in": timed_in,
                      "solve_bytes_per_apply_all_sets": solve_bytes, "solve_launches_per_apply_all_sets": launches},
     }
+    if args.learned:
+        out["learned"] = learned_variant(s, b, w, args.steps)
     cbw = copy_bandwidth(torch, dev)
     out["roofline"]["measured_copy_gbs"] = cbw
     out["roofline"]["frac_of_copy"] = achieved / cbw

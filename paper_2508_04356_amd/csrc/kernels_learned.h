@@ -7,8 +7,12 @@
 
 namespace gdsw {
 
+// Wb (optional): the layer's weights as BF16 [27][32][32] (tap, out, in,
+// zero-padded) for the matrix-core path (Cin and Cout each 4 or 32)
 void conv_fwd(const float* X, int Cin, const float* W, const float* bias, float* Y, int Cout, int G, bool relu, int B,
-              hipStream_t st);
+              hipStream_t st, const uint16_t* Wb = nullptr);
+// Wb[t][co][ci] = W[co][ci][t] as BF16 bits, zero-padded to 32 x 32 channels
+void conv_weights_bf16(const float* W, int Cin, int Cout, uint16_t* Wb, hipStream_t st);
 // dX may be null (first layer)
 void conv_bwd(const float* X, int Cin, const float* W, const float* dY, int Cout, int G, int B, float* dX, float* dW,
               float* db, hipStream_t st);
@@ -36,6 +40,12 @@ void to_grid(const GridMap& gm, int S, int G, const double* src, float* X, doubl
 void from_grid(const GridMap& gm, int S, int G, const float* Y, const float* sigma, const double* norms, double mu,
                double* dst, hipStream_t st);
 // flags[s] = ||r_s - A_s y_s|| > tau ||r_s||; count += flags.  r from rsave (copy of the inputs)
+// ||r_s - A_s y_s|| > tau ||r_s|| per interior subdomain s, with A_s in CSR
+// (local rows from row_off[s] in lrow, local column indices in lcol); part:
+// 2 * S * ceil(max_n / 256) doubles.
+void local_residual_check_csr(const GridMap& gm, int S, int max_n, const double* rsave, const double* w,
+                              const int64_t* row_off, const int64_t* lrow, const int32_t* lcol, const double* lval,
+                              double tau, double* part, int32_t* flags, int32_t* count, hipStream_t st);
 void local_residual_check(const GridMap& gm, int S, const double* rsave, const double* w, const int32_t* S_ptr,
                           const int32_t* S_idx, const int32_t* rowptr, const int32_t* col, const double* val,
                           double tau, int32_t* flags, int32_t* count, hipStream_t st);

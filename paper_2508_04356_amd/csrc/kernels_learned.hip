@@ -63,6 +63,110 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const float* __restrict__
   }
 }
 
+// ---- 32 -> 32 channel layers on the matrix cores ---------------------------
+//
+// Implicit GEMM per tap: for tap t, D[co][v] += sum_ci W[co][ci][t] X[ci][v + t]
+// as v_mfma_f32_16x16x32_bf16 (16 output channels x 16 voxels x 32 input
+// channels), FP32 accumulation.  A block takes 256 consecutive voxels of one
+// sample; their neighbourhood (the voxels within one z-plane, one row and
+// one node of them) is staged in LDS channel-last as BF16 so that a lane's
+// 8 consecutive input channels are one 16-byte read.  Weights come
+// pre-arranged as Wb[t][co][ci] BF16 (conv_weights_bf16).
+typedef __bf16 lbf8 __attribute__((ext_vector_type(8)));
+typedef float lf4 __attribute__((ext_vector_type(4)));
+typedef uint32_t lu4 __attribute__((ext_vector_type(4)));
+
+__device__ inline uint16_t bits_bf16(float x) { return (uint16_t)(__float_as_uint(bf16_round(x)) >> 16); }
+
+// Wb[t][co][ci] (co < 32, ci < 32) = W[co][ci][t] for co < Cout, ci < Cin, else 0
+__global__ void conv_weights_bf16_kernel(const float* __restrict__ W, int Cin, int Cout, uint16_t* __restrict__ Wb) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;  // (t, co, ci)
+  if (idx >= 27 * 32 * 32) return;
+  const int ci = idx % 32, co = (idx / 32) % 32, t = idx / 1024;
+  Wb[idx] = (ci < Cin && co < Cout) ? bits_bf16(W[(co * Cin + ci) * 27 + t]) : (uint16_t)0;
+}
+
+constexpr int CV_TILE = 256;
+
+// CIN input channels (4 or 32, zero-padded to 32 in LDS), COUT output
+// channels (4 or 32; 16-row output blocks, the padded rows are not written).
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void conv_fwd_mfma_kernel(const float* __restrict__ X,
+                                                           const uint16_t* __restrict__ Wb,
+                                                           const float* __restrict__ bias, float* __restrict__ Y,
+                                                           int G, int relu) {
+  constexpr int NCB = (COUT + 15) / 16;
+  extern __shared__ uint16_t xs[];  // [(CV_TILE + 2 H) voxels][32 channels]
+  const int G3 = G * G * G;
+  const int H = G * G + G + 1;
+  const int nr = CV_TILE + 2 * H;
+  const int b = blockIdx.y;
+  const int v0 = blockIdx.x * CV_TILE;
+  const float* Xb = X + (int64_t)b * CIN * G3;
+  for (int idx = threadIdx.x; idx < nr * 32; idx += 256) {
+    const int vr = idx % nr, ci = idx / nr;  // consecutive threads: consecutive voxels of one channel
+    const int v = v0 - H + vr;
+    const float val = (ci < CIN && v >= 0 && v < G3) ? Xb[(int64_t)ci * G3 + v] : 0.f;
+    xs[vr * 32 + ci] = bits_bf16(val);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, kq = lane >> 4;
+  lf4 acc[4][NCB];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) acc[q][cb] = lf4{0.f, 0.f, 0.f, 0.f};
+  int vx[4], vy[4], vz[4];
+  bool vin[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int v = v0 + 64 * wave + 16 * q + i;
+    vin[q] = v < G3;
+    vx[q] = v % G;
+    vy[q] = (v / G) % G;
+    vz[q] = v / (G * G);
+  }
+  for (int t = 0; t < 27; ++t) {
+    const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+    const int off = (dz * G + dy) * G + dx;
+    lbf8 a[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+      a[cb] = __builtin_bit_cast(lbf8, *reinterpret_cast<const lu4*>(Wb + ((t * 32 + cb * 16 + i) * 32 + 8 * kq)));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const bool ok = vin[q] && vz[q] + dz >= 0 && vz[q] + dz < G && vy[q] + dy >= 0 && vy[q] + dy < G &&
+                      vx[q] + dx >= 0 && vx[q] + dx < G;
+      lu4 raw = {0u, 0u, 0u, 0u};
+      if (ok) {
+        const int vr = 64 * wave + 16 * q + i + H + off;
+        raw = *reinterpret_cast<const lu4*>(xs + vr * 32 + 8 * kq);
+      }
+      const lbf8 bx = __builtin_bit_cast(lbf8, raw);
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+        acc[q][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[cb], bx, acc[q][cb], 0, 0, 0);
+    }
+  }
+  // lane holds D[co = 16 cb + 4 kq + r][voxel i]
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int v = v0 + 64 * wave + 16 * q + i;
+    if (!vin[q]) continue;
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int co = 16 * cb + 4 * kq + r;
+        if (co >= COUT) continue;
+        float o = acc[q][cb][r] + bias[co];
+        if (relu) o = fmaxf(o, 0.f);
+        Y[((int64_t)b * COUT + co) * G3 + v] = bf16_round(o);
+      }
+  }
+}
+
 // dX[b][ci][v] = sum_{co,t} W[co][ci][t] dY[b][co][v - t + 1]
 __global__ __launch_bounds__(256) void conv_bwd_data_kernel(const float* __restrict__ dY, int Cout,
                                                            const float* __restrict__ W, float* __restrict__ dX,
@@ -203,12 +307,33 @@ inline int g1(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(40
 
 }  // namespace
 
+void conv_weights_bf16(const float* W, int Cin, int Cout, uint16_t* Wb, hipStream_t st) {
+  conv_weights_bf16_kernel<<<(27 * 32 * 32 + 255) / 256, 256, 0, st>>>(W, Cin, Cout, Wb);
+}
+
 void conv_fwd(const float* X, int Cin, const float* W, const float* bias, float* Y, int Cout, int G, bool relu, int B,
-              hipStream_t st) {
+              hipStream_t st, const uint16_t* Wb) {
   const int G3 = G * G * G;
-  const size_t shm = (size_t)COB * Cin * 27 * sizeof(float);
+  const size_t shm = (size_t)(CV_TILE + 2 * (G * G + G + 1)) * 32 * sizeof(uint16_t);
+  if (Wb && shm <= 64 * 1024) {
+    const dim3 grid((G3 + CV_TILE - 1) / CV_TILE, B);
+    const int rl = relu ? 1 : 0;
+    if (Cin == 32 && Cout == 32) {
+      conv_fwd_mfma_kernel<32, 32><<<grid, 256, shm, st>>>(X, Wb, bias, Y, G, rl);
+      return;
+    }
+    if (Cin == 4 && Cout == 32) {
+      conv_fwd_mfma_kernel<4, 32><<<grid, 256, shm, st>>>(X, Wb, bias, Y, G, rl);
+      return;
+    }
+    if (Cin == 32 && Cout == 4) {
+      conv_fwd_mfma_kernel<32, 4><<<grid, 256, shm, st>>>(X, Wb, bias, Y, G, rl);
+      return;
+    }
+  }
+  const size_t shm_w = (size_t)COB * Cin * 27 * sizeof(float);
   dim3 grid((G3 + 255) / 256, (Cout + COB - 1) / COB, B);
-  conv_fwd_kernel<<<grid, 256, shm, st>>>(X, Cin, W, bias, Y, Cout, G, relu ? 1 : 0, B);
+  conv_fwd_kernel<<<grid, 256, shm_w, st>>>(X, Cin, W, bias, Y, Cout, G, relu ? 1 : 0, B);
 }
 
 void conv_bwd(const float* X, int Cin, const float* W, const float* dY, int Cout, int G, int B, float* dX, float* dW,
@@ -299,6 +424,62 @@ __device__ inline int lb32(const int32_t* a, int n, int32_t key) {
   return lo;
 }
 
+// Per interior subdomain s and row block: partial sums of |r|^2 and
+// |r - A_s y|^2 with the local matrix A_s in CSR (local column indices).
+__global__ __launch_bounds__(256) void residual_part_kernel(GridMap gm, const double* __restrict__ rsave,
+                                                           const double* __restrict__ w,
+                                                           const int64_t* __restrict__ row_off,
+                                                           const int64_t* __restrict__ lrow,
+                                                           const int32_t* __restrict__ lcol,
+                                                           const double* __restrict__ lval,
+                                                           double* __restrict__ part) {
+  __shared__ double red0[256], red1[256];
+  const int s = blockIdx.y;
+  const int f = gm.factor[s];
+  const int n = gm.n[f];
+  const double* y = w + gm.xoff[f];
+  const double* r = rsave + gm.xoff[f];
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  double rr = 0.0, ee = 0.0;
+  if (k < n) {
+    const int64_t ro = row_off[s] + k;
+    double ay = 0.0;
+    for (int64_t e = lrow[ro]; e < lrow[ro + 1]; ++e) ay = fma(lval[e], y[lcol[e]], ay);
+    const double d = r[k] - ay;
+    rr = r[k] * r[k];
+    ee = d * d;
+  }
+  red0[threadIdx.x] = rr;
+  red1[threadIdx.x] = ee;
+  __syncthreads();
+  for (int q = 128; q > 0; q >>= 1) {
+    if ((int)threadIdx.x < q) {
+      red0[threadIdx.x] += red0[threadIdx.x + q];
+      red1[threadIdx.x] += red1[threadIdx.x + q];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[((int64_t)s * gridDim.x + blockIdx.x) * 2] = red0[0];
+    part[((int64_t)s * gridDim.x + blockIdx.x) * 2 + 1] = red1[0];
+  }
+}
+
+// flags[f] = 1 where ||r - A y|| > tau ||r||, summing the row blocks in order
+__global__ void residual_flag_kernel(GridMap gm, int S, int nblk, const double* __restrict__ part, double tau,
+                                     int32_t* __restrict__ flags, int32_t* __restrict__ count) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  double rr = 0.0, ee = 0.0;
+  for (int q = 0; q < nblk; ++q) {
+    rr += part[((int64_t)s * nblk + q) * 2];
+    ee += part[((int64_t)s * nblk + q) * 2 + 1];
+  }
+  const bool bad = !(sqrt(ee) <= tau * sqrt(rr));
+  flags[gm.factor[s]] = bad ? 1 : 0;
+  if (bad) atomicAdd(count, 1);
+}
+
 __global__ __launch_bounds__(256) void residual_check_kernel(GridMap gm, const double* __restrict__ rsave,
                                                             const double* __restrict__ w,
                                                             const int32_t* __restrict__ S_ptr,
@@ -386,6 +567,15 @@ void from_grid(const GridMap& gm, int S, int G, const float* Y, const float* sig
   if (S == 0) return;
   const int maxn = 4 * G * G * G;
   from_grid_kernel<<<dim3((maxn + 255) / 256, S), 256, 0, st>>>(gm, G, Y, sigma, norms, mu, dst);
+}
+
+void local_residual_check_csr(const GridMap& gm, int S, int max_n, const double* rsave, const double* w,
+                              const int64_t* row_off, const int64_t* lrow, const int32_t* lcol, const double* lval,
+                              double tau, double* part, int32_t* flags, int32_t* count, hipStream_t st) {
+  if (S == 0) return;
+  const int nblk = (max_n + 255) / 256;
+  residual_part_kernel<<<dim3(nblk, S), 256, 0, st>>>(gm, rsave, w, row_off, lrow, lcol, lval, part);
+  residual_flag_kernel<<<(S + 255) / 256, 256, 0, st>>>(gm, S, nblk, part, tau, flags, count);
 }
 
 void local_residual_check(const GridMap& gm, int S, const double* rsave, const double* w, const int32_t* S_ptr,

@@ -22,6 +22,13 @@ struct LearnedSolve {
   int64_t n_params = 0;
   int64_t woff[4] = {}, boff[4] = {};
   float *d_master = nullptr, *d_work = nullptr, *d_grad = nullptr, *d_m = nullptr, *d_v = nullptr;
+  uint16_t* d_wb = nullptr;       // BF16 [27][32][32] weights of the 4 layers (matrix-core path)
+  int64_t* d_lrow_off = nullptr;  // local CSR of the interior matrices (residual check)
+  int64_t* d_lrow = nullptr;
+  int32_t* d_lcol = nullptr;
+  double* d_lval = nullptr;
+  double* d_rpart = nullptr;
+  int max_n = 0;
   int adam_t = 0;
   float* d_sigma = nullptr;
   float sigma[4] = {1.f, 1.f, 1.f, 1.f};

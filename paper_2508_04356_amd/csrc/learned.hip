@@ -90,6 +90,35 @@ void learned_init(Context& ctx, uint64_t seed, hipStream_t st) {
   }
   L->d_S_ptr = dupload(A, S_ptr, st);
   L->d_S_idx = dupload(A, S_idx, st);
+  // local CSR of every interior matrix A_s = A[S_s, S_s] (local column indices)
+  {
+    std::vector<int64_t> row_off, lrow(1, 0);
+    std::vector<int32_t> lcol;
+    std::vector<double> lval;
+    L->max_n = 0;
+    for (int32_t f : L->factors) {
+      const std::vector<int32_t>& Sf = P.S[f];
+      const int n = (int)Sf.size();
+      L->max_n = std::max(L->max_n, n);
+      row_off.push_back((int64_t)lrow.size() - 1);
+      for (int k = 0; k < n; ++k) {
+        const int32_t g = Sf[k];
+        for (int32_t e = P.row_ptr[g]; e < P.row_ptr[g + 1]; ++e) {
+          const auto it = std::lower_bound(Sf.begin(), Sf.end(), P.col[e]);
+          if (it != Sf.end() && *it == P.col[e]) {
+            lcol.push_back((int32_t)(it - Sf.begin()));
+            lval.push_back(P.val[e]);
+          }
+        }
+        lrow.push_back((int64_t)lcol.size());
+      }
+    }
+    L->d_lrow_off = dupload(A, row_off, st);
+    L->d_lrow = dupload(A, lrow, st);
+    L->d_lcol = dupload(A, lcol, st);
+    L->d_lval = dupload(A, lval, st);
+    L->d_rpart = dalloc<double>(A, std::max<int64_t>(1, 2 * (int64_t)L->factors.size() * ((L->max_n + 255) / 256)));
+  }
   // parameters (flat: W0 b0 W1 b1 W2 b2 W3 b3), He-normal init
   const int64_t np = learned_param_count();
   L->n_params = np;
@@ -106,6 +135,7 @@ void learned_init(Context& ctx, uint64_t seed, hipStream_t st) {
   }
   L->d_master = dupload(A, h, st);
   L->d_work = dalloc<float>(A, np);
+  L->d_wb = dalloc<uint16_t>(A, 4 * 27 * 32 * 32);
   L->d_grad = dalloc<float>(A, np);
   L->d_m = dalloc<float>(A, np);
   L->d_v = dalloc<float>(A, np);
@@ -148,9 +178,11 @@ GridMap learned_gridmap(const Context& ctx) {
 // forward pass of B samples in act[0] -> act[4]
 void learned_forward(Context& ctx, int B, hipStream_t st) {
   LearnedSolve* L = ctx.learned;
+  // every layer runs on the matrix cores (channels zero-padded to 32 in, 16 out)
+  for (int l = 0; l < 4; ++l) conv_weights_bf16(L->d_work + L->woff[l], kCh[l], kCh[l + 1], L->d_wb + l * 27 * 32 * 32, st);
   for (int l = 0; l < 4; ++l)
     conv_fwd(L->act[l], kCh[l], L->d_work + L->woff[l], L->d_work + L->boff[l], L->act[l + 1], kCh[l + 1], L->G, l < 3,
-             B, st);
+             B, st, L->d_wb + l * 27 * 32 * 32);
 }
 
 // loss of act[4] against d_target and gradients into d_grad; returns the loss
@@ -288,8 +320,8 @@ void learned_apply_interior(Context& ctx, hipStream_t st) {
   learned_forward(ctx, L->S, st);
   from_grid(gm, L->S, L->G, L->act[4], L->d_sigma, L->d_norms, mu, ctx.d_w, st);
   GDSW_HIP(hipMemsetAsync(L->d_count, 0, sizeof(int32_t), st));
-  local_residual_check(gm, L->S, L->d_rsave, ctx.d_w, L->d_S_ptr, L->d_S_idx, ctx.d_rowptr, ctx.d_col, ctx.d_val,
-                       L->tau, L->d_flags, L->d_count, st);
+  local_residual_check_csr(gm, L->S, L->max_n, L->d_rsave, ctx.d_w, L->d_lrow_off, L->d_lrow, L->d_lcol, L->d_lval,
+                           L->tau, L->d_rpart, L->d_flags, L->d_count, st);
   GDSW_HIP(hipMemcpyAsync(L->h_count, L->d_count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   GDSW_HIP(hipStreamSynchronize(st));
   const int nfb = *L->h_count;
