@@ -219,6 +219,7 @@ struct Context {
   double* d_pair_t = nullptr;      // per pair: Phi_I column^T r (restriction)
   double* d_r0 = nullptr;          // coarse vectors (three levels)
   double* d_y0 = nullptr;
+  double* d_s2part = nullptr;      // chunk partials of Phi^(3) y3
 
   // three levels
   int Nc3 = 0;

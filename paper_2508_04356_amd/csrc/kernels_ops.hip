@@ -379,16 +379,38 @@ __global__ __launch_bounds__(256) void dense_cols_dot_kernel(const double* __res
   if (threadIdx.x == 0) out[pos ? pos[k] : k] = t;
 }
 
-// y0[c] = sum of level-2 local copies (ascending subregion) + (Phi^(3) y3)[c]
+// Phi^(3) y3 in column chunks: part[q * Nc + c] = sum over k in chunk q of
+// Phi^(3)[c, k] y3[k] (ascending k); one work-group per (256 rows, chunk), so
+// the dense Nc x Nc3 basis is streamed by many work-groups at once.
+constexpr int S2_CHUNK = 32;
+
+__global__ __launch_bounds__(256) void scatter2_part_kernel(int Nc, const double* __restrict__ w,
+                                                            const double* __restrict__ phi3, int Nc3,
+                                                            const int32_t* __restrict__ y3_pos,
+                                                            double* __restrict__ part) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  const int k0 = blockIdx.y * S2_CHUNK;
+  const int k1 = min(Nc3, k0 + S2_CHUNK);
+  __shared__ double y3[S2_CHUNK];
+  if (threadIdx.x < k1 - k0) y3[threadIdx.x] = w[y3_pos[k0 + threadIdx.x]];
+  __syncthreads();
+  if (c >= Nc) return;
+  double t = 0.0;
+  for (int k = k0; k < k1; ++k) t = fma(phi3[(int64_t)k * Nc + c], y3[k - k0], t);
+  part[(int64_t)blockIdx.y * Nc + c] = t;
+}
+
+// y0[c] = sum of level-2 local copies (ascending subregion) + the chunk
+// partials of Phi^(3) y3 (ascending chunk)
 __global__ void scatter2_kernel(int Nc, const int32_t* __restrict__ inv_ptr, const int64_t* __restrict__ inv_pos,
-                                const double* __restrict__ w, const double* __restrict__ phi3, int Nc3,
-                                const int32_t* __restrict__ y3_pos, double* __restrict__ y0) {
+                                const double* __restrict__ w, const double* __restrict__ part, int nchunk,
+                                double* __restrict__ y0) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= Nc) return;
   double s = 0.0;
   for (int e = inv_ptr[c]; e < inv_ptr[c + 1]; ++e) s += w[inv_pos[e]];
   double t = 0.0;
-  for (int k = 0; k < Nc3; ++k) t = fma(phi3[(int64_t)k * Nc + c], w[y3_pos[k]], t);
+  for (int q = 0; q < nchunk; ++q) t += part[(int64_t)q * Nc + c];
   y0[c] = s + t;
 }
 
@@ -482,10 +504,15 @@ void dense_cols_dot(const double* M, int64_t ld, int nrows, int ncols, const dou
   dense_cols_dot_kernel<<<ncols, 256, 0, st>>>(M, ld, nrows, v, out, pos);
 }
 
+int64_t scatter2_part_len(int Nc, int Nc3) { return (int64_t)Nc * ((Nc3 + S2_CHUNK - 1) / S2_CHUNK); }
+
 void scatter2(int Nc, const int32_t* inv_ptr, const int64_t* inv_pos, const double* w, const double* phi3, int Nc3,
-              const int32_t* y3_pos, double* y0, hipStream_t st) {
+              const int32_t* y3_pos, double* part, double* y0, hipStream_t st) {
   if (Nc == 0) return;
-  scatter2_kernel<<<(Nc + 255) / 256, 256, 0, st>>>(Nc, inv_ptr, inv_pos, w, phi3, Nc3, y3_pos, y0);
+  const int nchunk = (Nc3 + S2_CHUNK - 1) / S2_CHUNK;
+  if (nchunk > 0)
+    scatter2_part_kernel<<<dim3((Nc + 255) / 256, nchunk), 256, 0, st>>>(Nc, w, phi3, Nc3, y3_pos, part);
+  scatter2_kernel<<<(Nc + 255) / 256, 256, 0, st>>>(Nc, inv_ptr, inv_pos, w, part, nchunk, y0);
 }
 
 int cols_dot_blocks(int64_t n) { return (int)((n + DOT_CHUNK - 1) / DOT_CHUNK); }

@@ -763,6 +763,7 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
     ctx.d_c3_pinv = dupload(A, p3, st);
     ctx.d_r0 = dalloc<double>(A, Nc);
     ctx.d_y0 = dalloc<double>(A, Nc);
+    ctx.d_s2part = dalloc<double>(A, std::max<int64_t>(1, scatter2_part_len(Nc, Nc3)));
   }
 
   // ---- level-1 local factors (and the coarse factor when merged) -----------

@@ -156,7 +156,8 @@ void apply_post(Context& ctx, double* z, hipStream_t st) {
   const bool three = ctx.P.spec.levels == 3 && ctx.Nc > 0;
   if (three) {
     // y0 = sum_j R_j^(2)T y_j + Phi3 y3, then z = sum_i R_i^T y_i + Phi y0
-    scatter2(ctx.Nc, ctx.d_inv2_ptr, ctx.d_inv2_pos, ctx.d_w, ctx.d_phi3, ctx.Nc3, ctx.d_c3_pinv, ctx.d_y0, st);
+    scatter2(ctx.Nc, ctx.d_inv2_ptr, ctx.d_inv2_pos, ctx.d_w, ctx.d_phi3, ctx.Nc3, ctx.d_c3_pinv, ctx.d_s2part,
+             ctx.d_y0, st);
     scatter_prolong(ctx.P.n_free, ctx.d_inv_ptr, ctx.d_inv_pos, ctx.d_w, cv, ctx.d_y0, nullptr, z, st,
                     ctx.P.n_sub, ctx.max_ni);
   } else if (ctx.Nc > 0) {

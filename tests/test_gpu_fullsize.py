@@ -1,0 +1,66 @@
+"""Properties that hold at any size, checked at the full workload sizes the
+benchmarks run (24^3 with 6^3 subdomains in FP64 / BF16, 32^3 three-level
+with FP32 local inverses), where the CPU oracle is too slow to compare
+element by element:
+
+* M^-1 is symmetric (every local, coarse and level-2/3 matrix is symmetric
+  and the restrictions enter as R^T ... R): <M x, y> = <x, M y>, to rounding
+  of the precision the inverses are stored in;
+* with the manufactured body force the discrete solution is the nodal
+  interpolant of u = (c y(1-y) z(1-z), 0, 0), p = 0 (Q2 reproduces the
+  quadratic profile), so FGMRES must reach it to the solver tolerance;
+* the true residual recomputed with the library's SpMV meets rtol.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_2508_04356_amd as G  # noqa: E402
+from inputs import random_vector  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+CASES = [
+    ("24^3 fp64", dict(n=24, m=6), 1e-12, 1e-11),
+    ("24^3 bf16", dict(n=24, m=6, precision="bf16"), 1e-5, 1e-10),
+    ("32^3 fp32 three-level", dict(n=32, m=8, levels=3, group=2, precision="fp32"), 1e-5, 1e-10),
+]
+
+
+@pytest.mark.parametrize("name,kw,sym_tol,rtol", CASES, ids=[c[0] for c in CASES])
+def test_fullsize_properties(name, kw, sym_tol, rtol):
+    print(f"[gpu] full size {name}", flush=True)
+    c0 = 16.0
+    s = G.Solver(manufactured=1, inflow=c0, **kw)
+    n = s.n_free
+    # symmetry of the preconditioner
+    x = torch.as_tensor(random_vector(n, seed=21), device=DEV)
+    y = torch.as_tensor(random_vector(n, seed=22), device=DEV)
+    mx, my = torch.zeros_like(x), torch.zeros_like(y)
+    s.apply(x, mx)
+    s.apply(y, my)
+    torch.cuda.synchronize()
+    lhs, rhs = float(torch.dot(mx, y)), float(torch.dot(x, my))
+    print(f"[gpu] {name}: <Mx,y> {lhs:.15e} <x,My> {rhs:.15e} rel {abs(lhs - rhs) / abs(lhs):.2e}", flush=True)
+    assert abs(lhs - rhs) <= sym_tol * abs(lhs)
+    # manufactured Poiseuille solution
+    b = torch.zeros(n, dtype=torch.float64, device=DEV)
+    s.rhs(b)
+    u = torch.zeros_like(b)
+    info = s.fgmres(b, u, rtol=rtol, restart=100, max_it=1000)[0]
+    field, abc = s.dof_map()
+    h2 = 1.0 / (2 * kw["n"])
+    Y, Z = abc[:, 1] * h2, abc[:, 2] * h2
+    exact = np.where(field == 0, c0 * Y * (1 - Y) * Z * (1 - Z), 0.0)
+    got = u.cpu().numpy()
+    err = np.abs(got - exact).max() / np.abs(exact).max()
+    r = torch.zeros_like(b)
+    s.spmv(u, r)
+    res = float(torch.linalg.norm(b - r) / torch.linalg.norm(b))
+    print(f"[gpu] {name}: {info.iterations} iterations, true residual {res:.2e}, max error {err:.2e}", flush=True)
+    assert res <= 2 * rtol
+    assert abs(res - info.true_rel_res) <= 0.1 * res
+    assert err <= 1e4 * rtol
+    s.close()
