@@ -130,6 +130,9 @@ struct FactorSet {
   int64_t partial_len = 0;
   GemvPlan gemm;                     // several right-hand sides (all factors)
   void* d_partial_m = nullptr;       // 32 * rows partial sums per gemm item
+  int max_np = 0;                    // BF16 products: right-hand sides as BF16,
+  int64_t* d_xpoff = nullptr;        //   xb[32 * xpoff[f] + j * npad[f] + row]
+  uint16_t* d_xb = nullptr;
   uint64_t algorithmic_bytes() const;  // sum n^2 * sizeof(prec)
   uint64_t alg_bytes = 0;              // algorithmic_bytes(), set when planned
   int64_t launches() const;            // solve kernel launches per pass (slot 0)

@@ -17,72 +17,110 @@ namespace {
 // ---- several right-hand sides: MFMA products with the stored inverses ------
 //
 // Item (f, r0, c0, p) of a multi-RHS plan: output rows [r0, r0 + RB) and
-// summation columns [c0, c0 + GEMV_CW) of matrix f for up to 32 right-hand
-// sides (two groups of 16).  The work vectors are interleaved: entry
-// (row, j) at w[row * ldk + j].  The right-hand sides of the chunk are staged
-// in LDS SC columns at a time; each wave owns RB / 4 output rows.  partial
-// layout: partial[(p * RB + row) * 32 + j].  Columns beyond the chunk (or n)
-// are staged as zero, so padded or foreign matrix entries never contribute.
+// summation columns [c0, c0 + GEMM_CW) of matrix f for up to 32 right-hand
+// sides (two groups of 16).  Each wave owns RB / 4 output rows and reads its
+// MFMA operands straight from memory (no LDS, no barriers): the matrix
+// fragments with 16-byte loads (non-temporal for FP64/FP32 storage), the
+// right-hand-side fragments (small, re-read by every row block of the
+// matrix, so cached) from the work vectors (FP64/FP32) or from a BF16 copy
+// made once per launch.  The loads of the next step are issued before the
+// products of the current one (two register buffers).  partial layout:
+// partial[(p * RB + row) * 32 + j].  Summation entries past n meet zero
+// right-hand sides, so padded entries never contribute; rows and
+// right-hand sides past n and nrhs give outputs that are never read.
 typedef float mf_f4 __attribute__((ext_vector_type(4)));
 typedef double mf_d4 __attribute__((ext_vector_type(4)));
 typedef __bf16 mf_bf8 __attribute__((ext_vector_type(8)));
 
+#ifndef GDSW_GEMM_HD
+#define GDSW_GEMM_HD 2    // FP64: row groups of 32 rows per wave
+#endif
 #ifndef GDSW_GEMM_H
-#define GDSW_GEMM_H 1     // FP64/FP32: row groups of 16 E rows per wave
+#define GDSW_GEMM_H 1     // FP32: row groups of 64 rows per wave
 #endif
 #ifndef GDSW_GEMM_HB
 #define GDSW_GEMM_HB 4    // BF16: 16-row output tiles per wave
 #endif
-#ifndef GDSW_GEMM_SC
-#define GDSW_GEMM_SC 64   // FP64/FP32: columns staged per step
+#ifndef GDSW_GEMM_Q
+#define GDSW_GEMM_Q 4     // FP64/FP32: groups of 4 summation columns per step
 #endif
-#ifndef GDSW_GEMM_SCB
-#define GDSW_GEMM_SCB 128 // BF16: columns staged per step
+#ifndef GDSW_GEMM_CW
+#define GDSW_GEMM_CW 2048 // summation columns per work item
 #endif
+#ifndef GDSW_GEMM_NTA
+#define GDSW_GEMM_NTA 0   // BF16: non-temporal matrix loads
+#endif
+
+constexpr int GEMM_CW = GDSW_GEMM_CW;
+static_assert(GEMM_CW % 64 == 0, "chunks must hold whole 64-entry BF16 steps");
 
 template <typename T>
 struct MultiShape;
 template <>
 struct MultiShape<double> {  // v_mfma_f64_16x16x4: a lane's 16-byte load = 2 rows of one column
-  static constexpr int H = GDSW_GEMM_H, RB = 4 * H * 32, SC = GDSW_GEMM_SC;
+  static constexpr int H = GDSW_GEMM_HD, RB = 4 * H * 32;
   using P = double;
 };
 template <>
 struct MultiShape<float> {  // v_mfma_f32_16x16x4f32: 4 rows of one column
-  static constexpr int H = GDSW_GEMM_H, RB = 4 * H * 64, SC = GDSW_GEMM_SC;
+  static constexpr int H = GDSW_GEMM_H, RB = 4 * H * 64;
   using P = float;
 };
 template <>
 struct MultiShape<uint16_t> {  // v_mfma_f32_16x16x32_bf16: 8 entries along the summation index
-  static constexpr int H = GDSW_GEMM_HB, RB = 4 * H * 16, SC = GDSW_GEMM_SCB;
+  static constexpr int H = GDSW_GEMM_HB, RB = 4 * H * 16;
   using P = float;
 };
 
-__device__ inline uint16_t bf16_bits(double x) { return to_bf16((float)x); }
+// FP64 and FP32 storage.  One step covers 4 Q summation columns.  For each
+// of H row groups h, lane l loads E = 16 / sizeof(T) consecutive rows
+// (Rw + 16 E h + E (l % 16) + v) of column c + 4 q + l / 16; MFMA (h, v)
+// uses A[i][k] = M[Rw + 16 E h + E i + v][c + 4 q + k] and
+// B[k][j] = x[c + 4 q + k][16 g + j] (rounded to T).
+template <typename T, int G>
+struct StepRegs {
+  static constexpr int E = 16 / sizeof(T), H = MultiShape<T>::H, Q = GDSW_GEMM_Q;
+  T a[Q][H][E];
+  double b[Q][G];  // right-hand sides as loaded; rounded to T at the product
+};
 
-// Stage rows [c, c + SC) x 32 right-hand sides of the work vectors into LDS
-// as the MFMA B operand type.
-template <typename T, typename XT, int SC, bool RHS_MAJOR>
-__device__ inline void stage_x(XT* xs, const double* __restrict__ x, int64_t ldk, int nrhs, int ccount) {
-  for (int idx = threadIdx.x; idx < SC * 32; idx += 256) {
-    const int j = idx % 32, col = idx / 32;  // consecutive threads: consecutive right-hand sides of one row
-    const double v = (col < ccount && j < nrhs) ? x[(int64_t)col * ldk + j] : 0.0;
-    XT o;
-    if constexpr (sizeof(XT) == 2)
-      o = bf16_bits(v);
-    else
-      o = (XT)v;
-    if constexpr (RHS_MAJOR)
-      xs[j * SC + col] = o;
-    else
-      xs[col * 32 + j] = o;
+// Every load is unconditional (addresses clamped into the matrix and the
+// work vector), so that the loads of the next step stay in flight while the
+// products of the current one run; rows and right-hand sides beyond n and
+// nrhs produce outputs that are never read, and summation columns beyond
+// the chunk get a zero right-hand side.
+template <typename T, int G>
+__device__ inline void load_step(StepRegs<T, G>& R, const T* const (&arow)[MultiShape<T>::H], int64_t np,
+                                 const double* const (&xj)[G], int64_t ldk, int c, int cend) {
+  using S = StepRegs<T, G>;
+#pragma unroll
+  for (int q = 0; q < S::Q; ++q) {
+    const int col = c + 4 * q;  // + l / 16, folded into the pointers
+#pragma unroll
+    for (int h = 0; h < S::H; ++h) load16_nt(arow[h] + (int64_t)col * np, R.a[q][h]);
+#pragma unroll
+    for (int g = 0; g < G; ++g) R.b[q][g] = xj[g][(int64_t)col * ldk];
   }
 }
 
-// FP64 and FP32 storage: for each of H row groups h, lane l loads
-// E = 16 / sizeof(T) consecutive rows (Rw + 16 E h + E (l % 16) + v) of
-// column c + l / 16; MFMA (h, v) uses A[i][k] = M[Rw + 16 E h + E i + v][c + k]
-// and B[k][j] = x[c + k][j].
+template <typename T, int G, typename ACC>
+__device__ inline void mma_step(ACC (&acc)[MultiShape<T>::H][16 / sizeof(T)][G], const StepRegs<T, G>& R) {
+  using S = StepRegs<T, G>;
+#pragma unroll
+  for (int q = 0; q < S::Q; ++q)
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int h = 0; h < S::H; ++h)
+#pragma unroll
+        for (int v = 0; v < S::E; ++v) {
+          if constexpr (sizeof(T) == 8)
+            acc[h][v][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(R.a[q][h][v], R.b[q][g], acc[h][v][g], 0, 0, 0);
+          else
+            acc[h][v][g] = __builtin_amdgcn_mfma_f32_16x16x4f32(R.a[q][h][v], (float)R.b[q][g], acc[h][v][g], 0, 0, 0);
+        }
+}
+
 template <typename T, int G>
 __global__ __launch_bounds__(256) void gemm_part_kernel(const T* __restrict__ store, const int64_t* __restrict__ OFF,
                                                         const int32_t* __restrict__ N, const int32_t* __restrict__ NP,
@@ -94,21 +132,22 @@ __global__ __launch_bounds__(256) void gemm_part_kernel(const T* __restrict__ st
   using P = typename S::P;
   using ACC = typename std::conditional<sizeof(T) == 8, mf_d4, mf_f4>::type;
   constexpr int E = 16 / sizeof(T);
-  constexpr int H = S::H, RB = S::RB, SC = S::SC;
-  __shared__ T xs[SC * 32];
+  constexpr int H = S::H, RB = S::RB, SK = 4 * GDSW_GEMM_Q;
   const int4 item = items[blockIdx.x];
   const int f = item.x, r0 = item.y, c0 = item.z, p = item.w;
   const int n = N[f];
   const int64_t np = NP[f];
-  const int cend = min(c0 + GEMV_CW, n);
+  const int cend = min(c0 + GEMM_CW, n);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = lane & 15, kq = lane >> 4;
   const int Rw = r0 + wave * (RB / 4);
-  bool rok[H];
+  const T* arow[H];
 #pragma unroll
-  for (int h = 0; h < H; ++h) rok[h] = Rw + 16 * E * h + E * i < n;
-  const T* base = store + OFF[f] + Rw + E * i;
-  const double* x = w + XOFF[f] * ldk;
+  for (int h = 0; h < H; ++h)
+    arow[h] = store + OFF[f] + min<int64_t>(Rw + 16 * E * h + E * i, np - E) + (int64_t)kq * np;
+  const double* xj[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) xj[g] = w + (XOFF[f] + kq) * ldk + min(16 * g + i, nrhs - 1);
   ACC acc[H][E][G];
 #pragma unroll
   for (int h = 0; h < H; ++h)
@@ -116,42 +155,42 @@ __global__ __launch_bounds__(256) void gemm_part_kernel(const T* __restrict__ st
     for (int v = 0; v < E; ++v)
 #pragma unroll
       for (int g = 0; g < G; ++g) acc[h][v][g] = ACC{0, 0, 0, 0};
-  for (int c = c0; c < cend; c += SC) {
-    // every matrix load of the step is issued first (they do not depend on
-    // the staged right-hand sides), then the staging, then the products
-    constexpr int Q = SC / 4;
-    T a[Q][H][E];
+  // steps of SK columns; the last one may run past n into the padding
+  // (zero right-hand side there, columns < np)
+  const int nstep = (cend - c0 + SK - 1) / SK;
+  const int clast = c0 + (nstep - 1) * SK;
+  const bool tail = cend % SK != 0;  // only the last step can be partial
+  StepRegs<T, G> R0, R1;
+  int c = c0;
+  auto fix_tail = [&](StepRegs<T, G>& R, int cs) {
+    if (tail && cs == clast) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int col = c + 4 * q + kq;
+      for (int q = 0; q < GDSW_GEMM_Q; ++q)
 #pragma unroll
-      for (int h = 0; h < H; ++h) {
-        if (rok[h] && col < cend) {
-          load16_nt(base + 16 * E * h + (int64_t)col * np, a[q][h]);
-        } else {
-#pragma unroll
-          for (int v = 0; v < E; ++v) a[q][h][v] = 0;
-        }
-      }
+        for (int g = 0; g < G; ++g)
+          if (cs + 4 * q + kq >= cend) R.b[q][g] = 0.0;
     }
-    __syncthreads();
-    stage_x<T, T, SC, false>(xs, x + (int64_t)c * ldk, ldk, nrhs, min(SC, cend - c));
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-#pragma unroll
-      for (int g = 0; g < G; ++g) {
-        const T b = xs[(4 * q + kq) * 32 + g * 16 + i];
-#pragma unroll
-        for (int h = 0; h < H; ++h)
-#pragma unroll
-          for (int v = 0; v < E; ++v) {
-            if constexpr (sizeof(T) == 8)
-              acc[h][v][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q][h][v], b, acc[h][v][g], 0, 0, 0);
-            else
-              acc[h][v][g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q][h][v], b, acc[h][v][g], 0, 0, 0);
-          }
-      }
+  };
+  if (nstep & 1) {
+    load_step(R0, arow, np, xj, ldk, c, cend);
+    fix_tail(R0, c);
+    mma_step<T, G>(acc, R0);
+    c += SK;
+  }
+  if (c < cend) {
+    load_step(R0, arow, np, xj, ldk, c, cend);
+    for (; c < cend; c += 2 * SK) {
+      // the scheduling barriers keep the next step's loads ahead of the
+      // current step's products (the scheduler would otherwise sink them)
+      load_step(R1, arow, np, xj, ldk, c + SK, cend);
+      __builtin_amdgcn_sched_barrier(0);
+      mma_step<T, G>(acc, R0);
+      __builtin_amdgcn_sched_barrier(0);
+      load_step(R0, arow, np, xj, ldk, min(c + 2 * SK, clast), cend);
+      __builtin_amdgcn_sched_barrier(0);
+      fix_tail(R1, c + SK);
+      mma_step<T, G>(acc, R1);
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
   // D_(h,v)[i'][j] = y[Rw + 16 E h + E i' + v][16 g + j], j = i.  Accumulator
@@ -171,75 +210,139 @@ __global__ __launch_bounds__(256) void gemm_part_kernel(const T* __restrict__ st
         }
 }
 
+// BF16 right-hand sides for the BF16 products, stored right-hand side by
+// right-hand side per matrix: xb[32 XP_f + j np_f + d] = bf16(x_f[d][j]),
+// zero for d >= n_f and j >= nrhs.  One work-group per (64 rows, matrix),
+// transposed through LDS.
+__global__ __launch_bounds__(256) void stage_bf16_kernel(const int32_t* __restrict__ N, const int32_t* __restrict__ NP,
+                                                         const int64_t* __restrict__ XOFF,
+                                                         const int64_t* __restrict__ XPOFF,
+                                                         const double* __restrict__ w, int64_t ldk, int nrhs,
+                                                         uint16_t* __restrict__ xb) {
+  const int f = blockIdx.y;
+  const int n = N[f];
+  const int64_t np = NP[f];
+  const int d0 = blockIdx.x * 64;
+  if (d0 >= np) return;  // uniform over the work-group
+  __shared__ double t[64][33];
+  const double* x = w + XOFF[f] * ldk;
+  for (int e = threadIdx.x; e < 64 * 32; e += 256) {
+    const int d = e >> 5, j = e & 31;
+    t[d][j] = (d0 + d < n && j < nrhs) ? x[(int64_t)(d0 + d) * ldk + j] : 0.0;
+  }
+  __syncthreads();
+  uint16_t* o = xb + XPOFF[f] * 32 + d0;
+  for (int e = threadIdx.x; e < 64 * 32; e += 256) {
+    const int j = e >> 6, d = e & 63;
+    o[(int64_t)j * np + d] = to_bf16((float)t[d][j]);
+  }
+}
+
 // BF16 storage (the stored inverse is symmetric): lane l loads 2 x 8
-// entries of column Rw + 16 h + (l % 16), rows c + 16 (l / 16) + 0..15, i.e.
-// 16 consecutive summation entries of output row Rw + 16 h + (l % 16).
+// entries of storage column Rw + 16 h + (l % 16), rows c + 16 (l / 16) + 0..15,
+// i.e. 16 consecutive summation entries of output row Rw + 16 h + (l % 16),
+// and the same 16 entries of right-hand side 16 g + (l % 16) from xb.
+template <int G>
+struct StepRegsB {
+  static constexpr int H = MultiShape<uint16_t>::H;
+  gdsw_u4 a[H][2];
+  gdsw_u4 b[G][2];
+};
+
+// Unconditional loads (see load_step): output rows beyond n read a clamped
+// column and are never used; summation entries in [n, np) meet zeros in xb.
+template <int G>
+__device__ inline void load_step_bf16(StepRegsB<G>& R, const uint16_t* const (&srcA)[MultiShape<uint16_t>::H],
+                                      const uint16_t* const (&srcB)[G], int c) {
+  constexpr int H = StepRegsB<G>::H;
+#pragma unroll
+  for (int h = 0; h < H; ++h) {
+#if GDSW_GEMM_NTA
+    R.a[h][0] = __builtin_nontemporal_load(reinterpret_cast<const gdsw_u4*>(srcA[h] + c));
+    R.a[h][1] = __builtin_nontemporal_load(reinterpret_cast<const gdsw_u4*>(srcA[h] + c + 8));
+#else
+    R.a[h][0] = *reinterpret_cast<const gdsw_u4*>(srcA[h] + c);
+    R.a[h][1] = *reinterpret_cast<const gdsw_u4*>(srcA[h] + c + 8);
+#endif
+  }
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    R.b[g][0] = *reinterpret_cast<const gdsw_u4*>(srcB[g] + c);
+    R.b[g][1] = *reinterpret_cast<const gdsw_u4*>(srcB[g] + c + 8);
+  }
+}
+
+template <int G>
+__device__ inline void mma_step_bf16(mf_f4 (&acc)[MultiShape<uint16_t>::H][G], const StepRegsB<G>& R) {
+#pragma unroll
+  for (int h = 0; h < StepRegsB<G>::H; ++h) {
+    const mf_bf8 A0 = __builtin_bit_cast(mf_bf8, R.a[h][0]);
+    const mf_bf8 A1 = __builtin_bit_cast(mf_bf8, R.a[h][1]);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      acc[h][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, __builtin_bit_cast(mf_bf8, R.b[g][0]), acc[h][g], 0, 0,
+                                                          0);
+      acc[h][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, __builtin_bit_cast(mf_bf8, R.b[g][1]), acc[h][g], 0, 0,
+                                                          0);
+    }
+  }
+}
+
 template <int G>
 __global__ __launch_bounds__(256) void gemm_part_bf16_kernel(const uint16_t* __restrict__ store,
                                                              const int64_t* __restrict__ OFF,
                                                              const int32_t* __restrict__ N,
                                                              const int32_t* __restrict__ NP,
-                                                             const int64_t* __restrict__ XOFF,
+                                                             const int64_t* __restrict__ XPOFF,
                                                              const int4* __restrict__ items,
-                                                             const double* __restrict__ w, int64_t ldk, int nrhs,
+                                                             const uint16_t* __restrict__ xb,
                                                              float* __restrict__ partial) {
   using S = MultiShape<uint16_t>;
-  constexpr int H = S::H, RB = S::RB, SC = S::SC;
-  __shared__ uint16_t xs[32 * SC];  // [rhs][col]
+  constexpr int H = S::H, RB = S::RB;
   const int4 item = items[blockIdx.x];
   const int f = item.x, r0 = item.y, c0 = item.z, p = item.w;
   const int n = N[f];
   const int64_t np = NP[f];
-  const int cend = min(c0 + GEMV_CW, n);
+  const int cend = min(c0 + GEMM_CW, n);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = lane & 15, kq = lane >> 4;
   const int Rw = r0 + wave * (RB / 4);
-  const double* x = w + XOFF[f] * ldk;
+  const int r = 16 * kq;  // first summation entry of this lane within a step
+  const uint16_t* srcA[H];
+#pragma unroll
+  for (int h = 0; h < H; ++h) {
+    const int ocol = min(Rw + 16 * h + i, n - 1);  // output row = storage column (symmetry)
+    srcA[h] = store + OFF[f] + (int64_t)ocol * np + r;
+  }
+  const uint16_t* srcB[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) srcB[g] = xb + XPOFF[f] * 32 + (int64_t)(16 * g + i) * np + r;
   mf_f4 acc[H][G];
 #pragma unroll
   for (int h = 0; h < H; ++h)
 #pragma unroll
     for (int g = 0; g < G; ++g) acc[h][g] = mf_f4{0, 0, 0, 0};
-  for (int c = c0; c < cend; c += SC) {
-    // matrix loads of the step first, then the staging, then the products
-    constexpr int Q = SC / 64;
-    gdsw_u4 a[Q][H][2];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int r = c + 64 * q + 16 * kq;  // first summation index of this lane
-#pragma unroll
-      for (int h = 0; h < H; ++h) {
-        const int ocol = Rw + 16 * h + i;  // output row = storage column (symmetry)
-        a[q][h][0] = gdsw_u4{0, 0, 0, 0};
-        a[q][h][1] = gdsw_u4{0, 0, 0, 0};
-        if (ocol < n && r < cend) {
-          const uint16_t* src = store + OFF[f] + (int64_t)ocol * np + r;
-          a[q][h][0] = __builtin_nontemporal_load(reinterpret_cast<const gdsw_u4*>(src));
-          a[q][h][1] = __builtin_nontemporal_load(reinterpret_cast<const gdsw_u4*>(src + 8));
-        }
-      }
-    }
-    __syncthreads();
-    stage_x<uint16_t, uint16_t, SC, true>(xs, x + (int64_t)c * ldk, ldk, nrhs, min(SC, cend - c));
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      mf_bf8 bx[G][2];
-#pragma unroll
-      for (int g = 0; g < G; ++g)
-#pragma unroll
-        for (int s2 = 0; s2 < 2; ++s2)
-          bx[g][s2] = *reinterpret_cast<const mf_bf8*>(&xs[(g * 16 + i) * SC + 64 * q + 16 * kq + 8 * s2]);
-#pragma unroll
-      for (int h = 0; h < H; ++h) {
-        const mf_bf8 A0 = __builtin_bit_cast(mf_bf8, a[q][h][0]);
-        const mf_bf8 A1 = __builtin_bit_cast(mf_bf8, a[q][h][1]);
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-          acc[h][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, bx[g][0], acc[h][g], 0, 0, 0);
-          acc[h][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, bx[g][1], acc[h][g], 0, 0, 0);
-        }
-      }
+  // steps of 64 summation entries; the last one may run into [n, np)
+  const int nstep = (cend - c0 + 63) / 64;
+  const int clast = c0 + (nstep - 1) * 64;
+  StepRegsB<G> R0, R1;
+  int c = c0;
+  if (nstep & 1) {
+    load_step_bf16(R0, srcA, srcB, c);
+    mma_step_bf16<G>(acc, R0);
+    c += 64;
+  }
+  if (c < cend) {
+    load_step_bf16(R0, srcA, srcB, c);
+    for (; c < cend; c += 128) {
+      load_step_bf16(R1, srcA, srcB, c + 64);
+      __builtin_amdgcn_sched_barrier(0);
+      mma_step_bf16<G>(acc, R0);
+      __builtin_amdgcn_sched_barrier(0);
+      load_step_bf16(R0, srcA, srcB, min(c + 128, clast));
+      __builtin_amdgcn_sched_barrier(0);
+      mma_step_bf16<G>(acc, R1);
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
   float* out = partial + (int64_t)p * RB * 32;
@@ -280,15 +383,19 @@ void gemm_launch(const FactorSet& fs, double* w, int64_t ldk, int nrhs, hipStrea
     const int nr = std::min(32, nrhs - j0);
     double* wj = w + j0;
     KernelTimer* tm = (fs.timer && fs.timer->on && fs.timer->used < KernelTimer::CAP) ? fs.timer : nullptr;
-    if (tm) GDSW_HIP(hipEventRecord(tm->ev[2 * tm->used], st));
     if constexpr (sizeof(T) == 2) {
+      const uint16_t* store = static_cast<const uint16_t*>(fs.store);
+      stage_bf16_kernel<<<dim3((fs.max_np + 63) / 64, fs.count), 256, 0, st>>>(fs.d_n, fs.d_npad, fs.d_xoff,
+                                                                            fs.d_xpoff, wj, ldk, nr, fs.d_xb);
+      if (tm) GDSW_HIP(hipEventRecord(tm->ev[2 * tm->used], st));
       if (nr > 16)
-        gemm_part_bf16_kernel<2><<<G.n1, 256, 0, st>>>(static_cast<const uint16_t*>(fs.store), fs.d_off, fs.d_n,
-                                                      fs.d_npad, fs.d_xoff, G.d_items1, wj, ldk, nr, part);
+        gemm_part_bf16_kernel<2><<<G.n1, 256, 0, st>>>(store, fs.d_off, fs.d_n, fs.d_npad, fs.d_xpoff, G.d_items1,
+                                                      fs.d_xb, part);
       else
-        gemm_part_bf16_kernel<1><<<G.n1, 256, 0, st>>>(static_cast<const uint16_t*>(fs.store), fs.d_off, fs.d_n,
-                                                      fs.d_npad, fs.d_xoff, G.d_items1, wj, ldk, nr, part);
+        gemm_part_bf16_kernel<1><<<G.n1, 256, 0, st>>>(store, fs.d_off, fs.d_n, fs.d_npad, fs.d_xpoff, G.d_items1,
+                                                      fs.d_xb, part);
     } else {
+      if (tm) GDSW_HIP(hipEventRecord(tm->ev[2 * tm->used], st));
       if (nr > 16)
         gemm_part_kernel<T, 2><<<G.n1, 256, 0, st>>>(static_cast<const T*>(fs.store), fs.d_off, fs.d_n, fs.d_npad,
                                                      fs.d_xoff, G.d_items1, wj, ldk, nr, part);
@@ -305,6 +412,8 @@ void gemm_launch(const FactorSet& fs, double* w, int64_t ldk, int nrhs, hipStrea
 }
 
 }  // namespace
+
+int gemm_cols() { return GEMM_CW; }
 
 int gemm_rows(int prec) {
   return prec == P_FP64 ? MultiShape<double>::RB : prec == P_FP32 ? MultiShape<float>::RB : MultiShape<uint16_t>::RB;

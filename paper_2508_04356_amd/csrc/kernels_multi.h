@@ -13,9 +13,11 @@ namespace gdsw {
 void cm_to_il(int64_t n, int K, const double* src, int64_t ld, double* dst, hipStream_t st);
 void il_to_cm(int64_t n, int K, const double* src, double* dst, int64_t ld, hipStream_t st);
 void gather_il(int64_t count, int K, const int32_t* idx, const double* src, double* dst, hipStream_t st);
-// with t (n_pairs * K doubles): per-pair reductions first, then assembly
+// with t (phi_t_splits(nsub) * n_pairs * K doubles) and nsub subdomains:
+// per-subdomain pair partials first, then assembly
+int phi_t_splits(int nsub);
 void restrict_il(int nc, int K, const CoarseView& cv, const double* r, double* w, const int32_t* out_pos,
-                 hipStream_t st, int n_pairs = 0, double* t = nullptr);
+                 hipStream_t st, int n_pairs = 0, double* t = nullptr, int nsub = 0);
 // y0_pos == nullptr: no coarse term; nsub > 0: the Phi_I y0 term runs per
 // subdomain over the column-major Phi_I (same operands and order)
 void scatter_prolong_il(int64_t n, int K, const int32_t* inv_ptr, const int64_t* inv_pos, const double* w,

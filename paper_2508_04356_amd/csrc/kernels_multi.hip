@@ -90,61 +90,171 @@ __global__ __launch_bounds__(256) void restrict_il_kernel(int nc, int K, CoarseV
   }
 }
 
-// t[e, j] = Phi_I^(i)[:, lc]^T r[I_i, j] for every (subdomain, local column)
-// pair e: 8 row lanes x 32 right-hand sides, fixed-order combination.
-__global__ __launch_bounds__(256) void phi_t_il_kernel(int K, CoarseView cv, const double* __restrict__ r,
-                                                       double* __restrict__ t) {
-  __shared__ double sh[8][32];
-  const int e = blockIdx.x;
-  const int j = threadIdx.x & 31, rl = threadIdx.x >> 5;
-  const int i = cv.cs_sub[e], lc = cv.cs_lc[e];
-  const int ib = cv.I_ptr[i], ni = cv.I_ptr[i + 1] - ib;
-  const double* ph = cv.phi_cm + cv.phi_off[i] + (int64_t)lc * ni;
-  double s = 0.0;
-  if (j < K)
-    for (int k = rl; k < ni; k += 8) s = fma(ph[k], r[(int64_t)cv.I_idx[ib + k] * K + j], s);
-  sh[rl][j] = s;
-  __syncthreads();
-  if (rl == 0 && j < K) {
-    double v = 0.0;
+// Per-subdomain pair partials of Phi^T r: tpart[(s * n_pairs + C_ptr[i] + q) * K + j]
+// = sum over rows k of split s (ascending) of Phi_I^(i)[k, q] r[I_i[k], j].
+// Work-group (split s, subdomain i); rows staged 32 at a time in LDS (the
+// gathered right-hand sides and the row-major Phi rows, contiguous when a
+// subdomain has at most 128 coarse columns), so each right-hand-side row is
+// read once per split instead of once per coarse column.  Every thread
+// issues all of its staging loads before its first LDS store.  Columns are
+// handled 128 at a time; thread (column group cg, right-hand side j) owns
+// columns cg, cg + 8, ...
+constexpr int PT_ROWS = 32, PT_COLS = 128;
+
+// ps[kk * qn + q] = Phi[(k0 + kk) * nc + qb + q] for kk < rows, q < qn
+__device__ inline void stage_phi_rows(double* ps, const double* __restrict__ phi, int k0, int rows, int nc, int qb,
+                                      int qn) {
+  const int total = rows * qn;
+  double v[PT_ROWS * PT_COLS / 256];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) v += sh[q][j];
-    t[(int64_t)e * K + j] = v;
+  for (int u = 0; u < PT_ROWS * PT_COLS / 256; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    const int kk = e / qn, q = e - kk * qn;
+    v[u] = e < total ? phi[(int64_t)(k0 + kk) * nc + qb + q] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < PT_ROWS * PT_COLS / 256; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    if (e < total) ps[e] = v[u];
+  }
+}
+
+__global__ __launch_bounds__(256) void phi_t_il_kernel(int K, CoarseView cv, const double* __restrict__ r,
+                                                       double* __restrict__ tpart, int n_pairs, int nsplit) {
+  __shared__ double rs[PT_ROWS][33];
+  __shared__ double ps[PT_ROWS * PT_COLS];
+  const int i = blockIdx.y, sp = blockIdx.x;
+  const int ib = cv.I_ptr[i], ni = cv.I_ptr[i + 1] - ib;
+  const int cb = cv.C_ptr[i], nc = cv.C_ptr[i + 1] - cb;
+  const int per = (ni + nsplit - 1) / nsplit;
+  const int k0 = min(ni, sp * per), k1 = min(ni, k0 + per);
+  const int j = threadIdx.x & 31, cg = threadIdx.x >> 5;
+  const double* phi = cv.phi_rm + cv.phi_off[i];
+  for (int qb = 0; qb < nc; qb += PT_COLS) {
+    const int qn = min(PT_COLS, nc - qb);
+    double acc[PT_COLS / 8];
+#pragma unroll
+    for (int u = 0; u < PT_COLS / 8; ++u) acc[u] = 0.0;
+    for (int kc = k0; kc < k1; kc += PT_ROWS) {
+      const int rows = min(PT_ROWS, k1 - kc);
+      __syncthreads();
+      {
+        double v[PT_ROWS * 32 / 256];
+#pragma unroll
+        for (int u = 0; u < PT_ROWS * 32 / 256; ++u) {
+          const int e = threadIdx.x + 256 * u, kk = e >> 5, jj = e & 31;
+          v[u] = (kk < rows && jj < K) ? r[(int64_t)cv.I_idx[ib + kc + kk] * K + jj] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < PT_ROWS * 32 / 256; ++u) {
+          const int e = threadIdx.x + 256 * u;
+          rs[e >> 5][e & 31] = v[u];
+        }
+      }
+      stage_phi_rows(ps, phi, kc, rows, nc, qb, qn);
+      __syncthreads();
+      for (int kk = 0; kk < rows; ++kk) {
+        const double rv = rs[kk][j];
+#pragma unroll
+        for (int u = 0; u < PT_COLS / 8; ++u)
+          if (cg + 8 * u < qn) acc[u] = fma(ps[kk * qn + cg + 8 * u], rv, acc[u]);
+      }
+    }
+    if (j < K) {
+#pragma unroll
+      for (int u = 0; u < PT_COLS / 8; ++u)
+        if (cg + 8 * u < qn) tpart[((int64_t)sp * n_pairs + cb + qb + cg + 8 * u) * K + j] = acc[u];
+    }
   }
 }
 
 // w[out_pos[c], j] = sum over the Gamma DOFs of column c of r[d, j] + sum of
-// t[e, j] over its pairs in ascending subdomain order; 8 columns per block.
+// the pair values over its pairs in ascending subdomain order (each pair
+// value the sum of its split partials in split order); 8 columns per block.
 __global__ __launch_bounds__(256) void restrict_assemble_il_kernel(int nc, int K, CoarseView cv,
                                                                    const double* __restrict__ r,
-                                                                   const double* __restrict__ t,
-                                                                   double* __restrict__ w,
+                                                                   const double* __restrict__ tpart, int n_pairs,
+                                                                   int nsplit, double* __restrict__ w,
                                                                    const int32_t* __restrict__ out_pos) {
   const int c = blockIdx.x * 8 + (threadIdx.x >> 5);
   const int j = threadIdx.x & 31;
   if (c >= nc || j >= K) return;
   double s = 0.0;
   for (int e = cv.cg_ptr[c]; e < cv.cg_ptr[c + 1]; ++e) s += r[(int64_t)cv.cg_dof[e] * K + j];
-  for (int e = cv.cs_ptr[c]; e < cv.cs_ptr[c + 1]; ++e) s += t[(int64_t)e * K + j];
+  for (int e = cv.cs_ptr[c]; e < cv.cs_ptr[c + 1]; ++e) {
+    const int64_t pe = cv.C_ptr[cv.cs_sub[e]] + cv.cs_lc[e];
+    double t = 0.0;
+    for (int sp = 0; sp < nsplit; ++sp) t += tpart[((int64_t)sp * n_pairs + pe) * K + j];
+    s += t;
+  }
   w[(int64_t)out_pos[c] * K + j] = s;
 }
 
-// z[I_i[k], j] += sum_q Phi_I^(i)[k, q] y0[C_i[q], j]: block (row chunk,
-// subdomain), threads (8 rows) x (32 right-hand sides).
+// z[I_i[k], j] += sum_q Phi_I^(i)[k, q] y0[C_i[q], j] (ascending q):
+// work-group (128-row chunk, subdomain).  The subdomain's coarse values
+// (128 columns at a time) and 32 Phi rows at a time are staged in LDS;
+// thread (row lane rl, j) owns rows rl, rl + 8, ... of the chunk.
+constexpr int PP_ROWS = 128;
+
 __global__ __launch_bounds__(256) void phi_prolong_il_kernel(int K, CoarseView cv, const double* __restrict__ w,
                                                              const int32_t* __restrict__ y0_pos,
                                                              double* __restrict__ z) {
+  __shared__ double ys[PT_COLS][33];
+  __shared__ double ps[PT_ROWS * PT_COLS];
   const int i = blockIdx.y;
   const int ib = cv.I_ptr[i], ni = cv.I_ptr[i + 1] - ib;
-  const int k = blockIdx.x * 8 + (threadIdx.x >> 5);
-  const int j = threadIdx.x & 31;
-  if (k >= ni || j >= K) return;
+  const int k0 = blockIdx.x * PP_ROWS;
+  if (k0 >= ni) return;  // uniform over the work-group
+  const int k1 = min(ni, k0 + PP_ROWS);
   const int cb = cv.C_ptr[i], nc = cv.C_ptr[i + 1] - cb;
-  const double* ph = cv.phi_cm + cv.phi_off[i] + k;
-  double c = 0.0;
-  for (int q = 0; q < nc; ++q) c = fma(ph[(int64_t)q * ni], w[(int64_t)y0_pos[cv.C_idx[cb + q]] * K + j], c);
-  const int64_t d = cv.I_idx[ib + k];
-  z[d * K + j] += c;
+  const int j = threadIdx.x & 31, rl = threadIdx.x >> 5;
+  const double* phi = cv.phi_rm + cv.phi_off[i];
+  double c[PP_ROWS / 8];
+#pragma unroll
+  for (int u = 0; u < PP_ROWS / 8; ++u) c[u] = 0.0;
+  for (int qb = 0; qb < nc; qb += PT_COLS) {
+    const int qn = min(PT_COLS, nc - qb);
+    __syncthreads();
+    {
+      double v[PT_COLS * 32 / 256];
+#pragma unroll
+      for (int u = 0; u < PT_COLS * 32 / 256; ++u) {
+        const int e = threadIdx.x + 256 * u, q = e >> 5, jj = e & 31;
+        v[u] = (q < qn && jj < K) ? w[(int64_t)y0_pos[cv.C_idx[cb + qb + q]] * K + jj] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < PT_COLS * 32 / 256; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        ys[e >> 5][e & 31] = v[u];
+      }
+    }
+#pragma unroll
+    for (int sc = 0; sc < PP_ROWS / PT_ROWS; ++sc) {
+      const int kc = k0 + sc * PT_ROWS;
+      const int rows = max(0, min(PT_ROWS, k1 - kc));
+      __syncthreads();
+      stage_phi_rows(ps, phi, kc, rows, nc, qb, qn);
+      __syncthreads();
+#pragma unroll
+      for (int v = 0; v < PT_ROWS / 8; ++v) {
+        const int kk = rl + 8 * v;
+        if (kk < rows) {
+          double a = c[sc * (PT_ROWS / 8) + v];
+          for (int q = 0; q < qn; ++q) a = fma(ps[kk * qn + q], ys[q][j], a);
+          c[sc * (PT_ROWS / 8) + v] = a;
+        }
+      }
+    }
+  }
+  if (j < K) {
+#pragma unroll
+    for (int sc = 0; sc < PP_ROWS / PT_ROWS; ++sc)
+#pragma unroll
+      for (int v = 0; v < PT_ROWS / 8; ++v) {
+        const int k = k0 + sc * PT_ROWS + rl + 8 * v;
+        if (k < k1) z[(int64_t)cv.I_idx[ib + k] * K + j] += c[sc * (PT_ROWS / 8) + v];
+      }
+  }
 }
 
 // z[d, :] = sum of local copies (ascending subdomain) + (Phi y_0)[d, :],
@@ -290,12 +400,15 @@ void gather_il(int64_t count, int K, const int32_t* idx, const double* src, doub
   gather_il_kernel<<<grid_for(count * K), 256, 0, st>>>(count, K, idx, src, dst);
 }
 
+int phi_t_splits(int nsub) { return nsub > 0 ? std::max(1, std::min(8, (2048 + nsub - 1) / nsub)) : 1; }
+
 void restrict_il(int nc, int K, const CoarseView& cv, const double* r, double* w, const int32_t* out_pos,
-                 hipStream_t st, int n_pairs, double* t) {
+                 hipStream_t st, int n_pairs, double* t, int nsub) {
+  const int nsplit = phi_t_splits(nsub);
   if (nc == 0) return;
-  if (n_pairs > 0 && t) {
-    phi_t_il_kernel<<<n_pairs, 256, 0, st>>>(K, cv, r, t);
-    restrict_assemble_il_kernel<<<(nc + 7) / 8, 256, 0, st>>>(nc, K, cv, r, t, w, out_pos);
+  if (n_pairs > 0 && t && nsub > 0) {
+    phi_t_il_kernel<<<dim3(nsplit, nsub), 256, 0, st>>>(K, cv, r, t, n_pairs, nsplit);
+    restrict_assemble_il_kernel<<<(nc + 7) / 8, 256, 0, st>>>(nc, K, cv, r, t, n_pairs, nsplit, w, out_pos);
   } else {
     restrict_il_kernel<<<nc, 256, 0, st>>>(nc, K, cv, r, w, out_pos);
   }
@@ -307,7 +420,7 @@ void scatter_prolong_il(int64_t n, int K, const int32_t* inv_ptr, const int64_t*
   if (n == 0) return;
   const int split = y0_pos && nsub > 0 && max_ni > 0;
   scatter_prolong_il_kernel<<<grid_for(n * K), 256, 0, st>>>(n, K, inv_ptr, inv_pos, w, cv, y0_pos, z, split);
-  if (split) phi_prolong_il_kernel<<<dim3((max_ni + 7) / 8, nsub), 256, 0, st>>>(K, cv, w, y0_pos, z);
+  if (split) phi_prolong_il_kernel<<<dim3((max_ni + PP_ROWS - 1) / PP_ROWS, nsub), 256, 0, st>>>(K, cv, w, y0_pos, z);
 }
 
 void spmm_il(int64_t nrows, int K, const int32_t* rowptr, const int32_t* col, const double* val, const double* x,

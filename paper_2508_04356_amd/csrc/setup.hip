@@ -11,6 +11,7 @@
 
 #include "context.h"
 #include "kernels.h"
+#include "kernels_multi.h"
 #include "kernels_ops.h"
 
 namespace gdsw {
@@ -128,14 +129,14 @@ void plan_gemv(FactorSet& fs, DeviceArena& A, hipStream_t st, int slot, const st
 
 void plan_gemm(FactorSet& fs, DeviceArena& A, hipStream_t st) {
   if (fs.mode != SOLVE_INVERSE || fs.count == 0) return;
-  const int RB = gemm_rows(fs.prec);
+  const int RB = gemm_rows(fs.prec), CW = gemm_cols();
   std::vector<int4> it1, it2;
   int p = 0;
   for (int f = 0; f < fs.count; ++f) {
     const int n = fs.n[f];
-    const int nr = (n + RB - 1) / RB, nc = (n + GEMV_CW - 1) / GEMV_CW;
+    const int nr = (n + RB - 1) / RB, nc = (n + CW - 1) / CW;
     for (int c = 0; c < nc; ++c)
-      for (int J = 0; J < nr; ++J) it1.push_back(make_int4(f, J * RB, c * GEMV_CW, p + J * nc + c));
+      for (int J = 0; J < nr; ++J) it1.push_back(make_int4(f, J * RB, c * CW, p + J * nc + c));
     for (int J = 0; J < nr; ++J) it2.push_back(make_int4(f, J * RB, p + J * nc, nc));
     p += nr * nc;
   }
@@ -149,6 +150,18 @@ void plan_gemm(FactorSet& fs, DeviceArena& A, hipStream_t st) {
   G.d_items2 = it2.empty() ? nullptr : dupload(A, it2, st);
   const size_t psz = fs.prec == P_FP64 ? 8 : 4;
   fs.d_partial_m = A.alloc((uint64_t)std::max(p, 1) * RB * 32 * psz);
+  // BF16 products read their right-hand sides as BF16, right-hand side by
+  // right-hand side per matrix (32 * sum of padded sizes entries)
+  if (fs.prec == P_BF16 && !fs.d_xb) {
+    std::vector<int64_t> xp(fs.count + 1, 0);
+    fs.max_np = 0;
+    for (int f = 0; f < fs.count; ++f) {
+      xp[f + 1] = xp[f] + fs.npad[f];
+      fs.max_np = std::max(fs.max_np, fs.npad[f]);
+    }
+    fs.d_xpoff = dupload(A, xp, st);
+    fs.d_xb = static_cast<uint16_t*>(A.alloc((uint64_t)std::max<int64_t>(xp.back(), 1) * 32 * sizeof(uint16_t)));
+  }
 }
 
 void plan_schedule(FactorSet& fs, int phases, DeviceArena& A, hipStream_t st, int slot,
@@ -848,7 +861,7 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
     ctx.d_wm = dalloc<double>(A, std::max<int64_t>(ctx.n_w, 1) * K);
     ctx.d_xin = dalloc<double>(A, std::max<int64_t>(n, 1) * K);
     ctx.d_xout = dalloc<double>(A, std::max<int64_t>(n, 1) * K);
-    ctx.d_pair_tm = dalloc<double>(A, (int64_t)std::max(ctx.n_pairs, 1) * K);
+    ctx.d_pair_tm = dalloc<double>(A, (int64_t)phi_t_splits(P.n_sub) * std::max(ctx.n_pairs, 1) * K);
   }
   GDSW_HIP(hipStreamSynchronize(st));
 }

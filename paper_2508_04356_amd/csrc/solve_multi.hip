@@ -151,7 +151,8 @@ void apply_precond_multi(Context& ctx, const double* r, double* z, int K, hipStr
   const CoarseView cv = coarse_view_m(ctx);
   const bool coarse = ctx.Nc > 0;
   gather_il(ctx.n_w1, K, ctx.d_gidx, r, ctx.d_wm, st);
-  if (coarse) restrict_il(ctx.Nc, K, cv, r, ctx.d_wm, ctx.d_coarse_pinv, st, ctx.n_pairs, ctx.d_pair_tm);
+  if (coarse) restrict_il(ctx.Nc, K, cv, r, ctx.d_wm, ctx.d_coarse_pinv, st, ctx.n_pairs, ctx.d_pair_tm,
+                          ctx.P.n_sub);
   gemm_set(ctx.L1, ctx.d_wm, K, K, st);
   gemm_set(ctx.HI, ctx.d_wm, K, K, st);
   scatter_prolong_il(ctx.P.n_free, K, ctx.d_inv_ptr, ctx.d_inv_pos, ctx.d_wm, cv,
