@@ -100,7 +100,28 @@ void batch_build(Batch& b, hipStream_t st) {
   build_set(b, b.s2, false, st);
   GDSW_HIP(hipHostMalloc((void**)&b.h_pinned, std::max<size_t>(1, 4 * b.m.size()) * sizeof(double),
                          hipHostMallocDefault));
+  // four lanes: the number of hardware queues a process gets by default
+  const size_t nl = std::max<size_t>(1, std::min<size_t>(4, b.m.size()));
+  b.lanes.assign(nl, nullptr);
+  b.join.assign(nl, nullptr);
+  for (size_t l = 0; l < nl; ++l) {
+    GDSW_HIP(hipStreamCreateWithFlags(&b.lanes[l], hipStreamNonBlocking));
+    GDSW_HIP(hipEventCreateWithFlags(&b.join[l], hipEventDisableTiming));
+  }
+  GDSW_HIP(hipEventCreateWithFlags(&b.fork, hipEventDisableTiming));
   GDSW_HIP(hipStreamSynchronize(st));
+}
+
+void batch_fork(Batch& b, hipStream_t st) {
+  GDSW_HIP(hipEventRecord(b.fork, st));
+  for (hipStream_t l : b.lanes) GDSW_HIP(hipStreamWaitEvent(l, b.fork, 0));
+}
+
+void batch_join(Batch& b, hipStream_t st) {
+  for (size_t l = 0; l < b.lanes.size(); ++l) {
+    GDSW_HIP(hipEventRecord(b.join[l], b.lanes[l]));
+    GDSW_HIP(hipStreamWaitEvent(st, b.join[l], 0));
+  }
 }
 
 void batch_select(Batch& b, const std::vector<char>& member_active, hipStream_t st) {
@@ -119,16 +140,27 @@ void batch_local_solve(Batch& b, hipStream_t st) {
 void batch_release(Batch& b) {
   for (auto& e : b.timer.ev) (void)hipEventDestroy(e);
   b.timer.ev.clear();
+  for (hipStream_t l : b.lanes) (void)hipStreamSynchronize(l);
   if (b.h_pinned) (void)hipHostFree(b.h_pinned);
   b.h_pinned = nullptr;
+  for (hipStream_t l : b.lanes) (void)hipStreamDestroy(l);
+  for (hipEvent_t e : b.join) (void)hipEventDestroy(e);
+  if (b.fork) (void)hipEventDestroy(b.fork);
+  b.lanes.clear();
+  b.join.clear();
+  b.fork = nullptr;
   b.arena.release_all();
 }
 
 void apply_precond_batch(Batch& b, const double* const* r, double* const* z, hipStream_t st) {
   batch_select(b, std::vector<char>(b.m.size(), 1), st);
-  for (size_t k = 0; k < b.m.size(); ++k) apply_pre(*b.m[k], r[k], st);
+  batch_fork(b, st);
+  for (size_t k = 0; k < b.m.size(); ++k) apply_pre(*b.m[k], r[k], batch_lane(b, k));
+  batch_join(b, st);
   batch_local_solve(b, st);
-  for (size_t k = 0; k < b.m.size(); ++k) apply_post(*b.m[k], z[k], st);
+  batch_fork(b, st);
+  for (size_t k = 0; k < b.m.size(); ++k) apply_post(*b.m[k], z[k], batch_lane(b, k));
+  batch_join(b, st);
   GDSW_HIP(hipGetLastError());
 }
 

@@ -302,7 +302,19 @@ struct Batch {
   BatchSet s1, s2;                   // level-1 inverses; coarse-level inverses
   KernelTimer timer;                 // times the level-1 partial-product launches
   double* h_pinned = nullptr;        // 4 doubles per member, read-back staging
+  // per-member work (gathers, scatters, SpMV, orthogonalisation) runs on
+  // lanes[k % lanes.size()], forked from and joined back into the caller's
+  // stream around each phase, so that the members' small kernels overlap
+  std::vector<hipStream_t> lanes;
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
 };
+
+// Make every lane wait for the work queued on st so far / make st wait for
+// everything queued on the lanes.
+void batch_fork(Batch& b, hipStream_t st);
+void batch_join(Batch& b, hipStream_t st);
+inline hipStream_t batch_lane(const Batch& b, size_t k) { return b.lanes[k % b.lanes.size()]; }
 
 void batch_build(Batch& b, hipStream_t st);
 // member_active[k] selects the members whose matrices the next products touch

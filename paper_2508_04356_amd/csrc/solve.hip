@@ -351,13 +351,16 @@ std::vector<FgmresResult> fgmres_batch(Batch& bt, const double* const* bvec, dou
   std::vector<char> done(K, 0), in_cycle(K, 0);
   std::vector<int> kc(K, 0), cycles(K, 0);
   double* hp = bt.h_pinned;
+  for (int k = 0; k < K; ++k) ensure_workspace(*bt.m[k], restart);
+  batch_fork(bt, st);
   for (int k = 0; k < K; ++k) {
     Context& c = *bt.m[k];
-    ensure_workspace(c, restart);
-    cols_dot(bvec[k], c.ldv, 1, bvec[k], c.P.n_free, c.d_part, c.n_part_blocks, c.d_scal + 0, st);
-    GDSW_HIP(hipMemcpyAsync(hp + k, c.d_scal + 0, sizeof(double), hipMemcpyDeviceToHost, st));
-    GDSW_HIP(hipMemsetAsync(xv[k], 0, c.P.n_free * sizeof(double), st));
+    const hipStream_t ls = batch_lane(bt, k);
+    cols_dot(bvec[k], c.ldv, 1, bvec[k], c.P.n_free, c.d_part, c.n_part_blocks, c.d_scal + 0, ls);
+    GDSW_HIP(hipMemcpyAsync(hp + k, c.d_scal + 0, sizeof(double), hipMemcpyDeviceToHost, ls));
+    GDSW_HIP(hipMemsetAsync(xv[k], 0, c.P.n_free * sizeof(double), ls));
   }
+  batch_join(bt, st);
   GDSW_HIP(hipStreamSynchronize(st));
   for (int k = 0; k < K; ++k) {
     bnorm[k] = std::sqrt(hp[k]);
@@ -370,16 +373,19 @@ std::vector<FgmresResult> fgmres_batch(Batch& bt, const double* const* bvec, dou
   }
   while (true) {
     // r = b - A x and beta for every member still running
+    batch_fork(bt, st);
     for (int k = 0; k < K; ++k) {
       if (done[k]) continue;
       Context& c = *bt.m[k];
+      const hipStream_t ls = batch_lane(bt, k);
       const int64_t n = c.P.n_free;
-      spmv(c, xv[k], c.d_t1, st);
-      residual_kernel<<<grid_n(n), 256, 0, st>>>(n, bvec[k], c.d_t1);
-      cols_dot(c.d_t1, c.ldv, 1, c.d_t1, n, c.d_part, c.n_part_blocks, c.d_scal + 0, st);
-      cycle_start_kernel<<<1, 1, 0, st>>>(c.d_g, restart, c.d_scal);
-      GDSW_HIP(hipMemcpyAsync(hp + k, c.d_scal + 1, sizeof(double), hipMemcpyDeviceToHost, st));
+      spmv(c, xv[k], c.d_t1, ls);
+      residual_kernel<<<grid_n(n), 256, 0, ls>>>(n, bvec[k], c.d_t1);
+      cols_dot(c.d_t1, c.ldv, 1, c.d_t1, n, c.d_part, c.n_part_blocks, c.d_scal + 0, ls);
+      cycle_start_kernel<<<1, 1, 0, ls>>>(c.d_g, restart, c.d_scal);
+      GDSW_HIP(hipMemcpyAsync(hp + k, c.d_scal + 1, sizeof(double), hipMemcpyDeviceToHost, ls));
     }
+    batch_join(bt, st);
     GDSW_HIP(hipStreamSynchronize(st));
     int running = 0;
     for (int k = 0; k < K; ++k) {
@@ -403,28 +409,33 @@ std::vector<FgmresResult> fgmres_batch(Batch& bt, const double* const* bvec, dou
     if (running == 0) break;
     batch_select(bt, in_cycle, st);
     for (int j = 0; j < restart && running > 0; ++j) {
+      batch_fork(bt, st);
       for (int k = 0; k < K; ++k)
-        if (in_cycle[k]) apply_pre(*bt.m[k], bt.m[k]->d_V + (int64_t)j * bt.m[k]->ldv, st);
+        if (in_cycle[k]) apply_pre(*bt.m[k], bt.m[k]->d_V + (int64_t)j * bt.m[k]->ldv, batch_lane(bt, k));
+      batch_join(bt, st);
       batch_local_solve(bt, st);
+      batch_fork(bt, st);
       for (int k = 0; k < K; ++k) {
         if (!in_cycle[k]) continue;
         Context& c = *bt.m[k];
+        const hipStream_t ls = batch_lane(bt, k);
         const int64_t n = c.P.n_free;
         double* V = c.d_V;
         double* zj = c.d_Z + (int64_t)j * c.ldv;
         double* w = c.d_t2;
-        apply_post(c, zj, st);
-        spmv(c, zj, w, st);
-        cols_dot(V, c.ldv, j + 1, w, n, c.d_part, c.n_part_blocks, c.d_hv, st);
-        gemv_sub(V, c.ldv, j + 1, c.d_hv, w, n, st);
-        cols_dot(V, c.ldv, j + 1, w, n, c.d_part, c.n_part_blocks, c.d_hv + restart + 1, st);
-        gemv_sub(V, c.ldv, j + 1, c.d_hv + restart + 1, w, n, st);
-        cols_dot(w, c.ldv, 1, w, n, c.d_part, c.n_part_blocks, c.d_scal + 4, st);
-        arnoldi_finish_kernel<<<1, 1, 0, st>>>(j, restart, c.d_hv, c.d_hv + restart + 1, c.d_H, c.d_cs, c.d_sn,
+        apply_post(c, zj, ls);
+        spmv(c, zj, w, ls);
+        cols_dot(V, c.ldv, j + 1, w, n, c.d_part, c.n_part_blocks, c.d_hv, ls);
+        gemv_sub(V, c.ldv, j + 1, c.d_hv, w, n, ls);
+        cols_dot(V, c.ldv, j + 1, w, n, c.d_part, c.n_part_blocks, c.d_hv + restart + 1, ls);
+        gemv_sub(V, c.ldv, j + 1, c.d_hv + restart + 1, w, n, ls);
+        cols_dot(w, c.ldv, 1, w, n, c.d_part, c.n_part_blocks, c.d_scal + 4, ls);
+        arnoldi_finish_kernel<<<1, 1, 0, ls>>>(j, restart, c.d_hv, c.d_hv + restart + 1, c.d_H, c.d_cs, c.d_sn,
                                                c.d_g, c.d_scal);
-        scale_div_kernel<<<grid_n(n), 256, 0, st>>>(n, w, c.d_scal, 3, V + (int64_t)(j + 1) * c.ldv);
-        GDSW_HIP(hipMemcpyAsync(hp + 2 * k, c.d_scal + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        scale_div_kernel<<<grid_n(n), 256, 0, ls>>>(n, w, c.d_scal, 3, V + (int64_t)(j + 1) * c.ldv);
+        GDSW_HIP(hipMemcpyAsync(hp + 2 * k, c.d_scal + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, ls));
       }
+      batch_join(bt, st);
       GDSW_HIP(hipStreamSynchronize(st));
       bool changed = false;
       for (int k = 0; k < K; ++k) {
@@ -444,12 +455,15 @@ std::vector<FgmresResult> fgmres_batch(Batch& bt, const double* const* bvec, dou
       if (changed && running > 0) batch_select(bt, in_cycle, st);
     }
     // x += Z y for every member that took part in this cycle
+    batch_fork(bt, st);
     for (int k = 0; k < K; ++k) {
       if (kc[k] == 0) continue;
       Context& c = *bt.m[k];
-      back_subst_kernel<<<1, 1, 0, st>>>(kc[k], restart, c.d_H, c.d_g, c.d_hv);
-      gemv_add(c.d_Z, c.ldv, kc[k], c.d_hv, xv[k], c.P.n_free, st);
+      const hipStream_t ls = batch_lane(bt, k);
+      back_subst_kernel<<<1, 1, 0, ls>>>(kc[k], restart, c.d_H, c.d_g, c.d_hv);
+      gemv_add(c.d_Z, c.ldv, kc[k], c.d_hv, xv[k], c.P.n_free, ls);
     }
+    batch_join(bt, st);
   }
   for (int k = 0; k < K; ++k) res[k].restarts = std::max(0, cycles[k] - 1);
   GDSW_HIP(hipGetLastError());
