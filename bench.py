@@ -296,8 +296,57 @@ def run_batch(args, prec):
                      "kernel": "gemv_part_kernel over the merged level-1 inverses of the active members",
                      "bytes_per_launch": k_bytes, "launches_timed": k_launches, "avg_launch_us": k_avg_us},
     }
+    if args.learned:
+        out["learned"] = batch_learned_variant(bt, bs, xs, args.steps)
     bt.close()
     print(json.dumps(out))
+
+
+def batch_learned_variant(bt, bs, xs, steps):
+    """One conv net, trained on a unit-viscosity 16^3 problem with the same
+    4^3-element subdomains and copied to every member with interior
+    subdomains (all share its node grid; each member scales its local
+    problems to unit viscosity); lockstep batch FGMRES with the learned
+    interior solves (with and without the exact fallback) beside the exact
+    ones."""
+    import torch
+
+    import paper_2508_04356_amd as G
+
+    t0 = time.perf_counter()
+    ref = G.Solver(16, 4, viscosity=1.0, inflow=1.0)
+    info = ref.learned_init(seed=7)
+    hist = ref.learned_train(solves=4, steps=600, batch=32, lr=2e-3, seed=3)
+    learned = []
+    for k, m in enumerate(bt.members):
+        if m.sizes().n_sub >= 27:
+            m.learned_init(seed=1)
+            m.learned_copy(ref)
+            learned.append(k)
+    ref.close()
+    torch.cuda.synchronize()
+    res = {"trained_on": "16^3, 4^3 subdomains, viscosity 1", "members_with_learned_solve": learned,
+           "interior_subdomains": int(sum(bt.members[k].learned.subdomains for k in learned)),
+           "grid": info.grid, "train_s": time.perf_counter() - t0,
+           "loss_first": float(np.mean(hist[:20])), "loss_last": float(np.mean(hist[-20:]))}
+    for name, mode, tau in (("learned", "learned", 1e30), ("learned_fallback", "learned", 0.7)):
+        for k in learned:
+            bt.members[k].set_local_solver(mode, tau)
+        bt.fgmres(bs, xs, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            infos = bt.fgmres(bs, xs, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        res[name] = {"iterations": [i.iterations for i in infos], "time_to_tol_ms": ms,
+                     "max_true_rel_res": max(i.true_rel_res for i in infos)}
+        log(f"[bench] batch {name}: {ms:.1f} ms, iterations {[i.iterations for i in infos]}")
+    stats = [bt.members[k].learned_stats() for k in learned]
+    res["learned_solves"], res["fallbacks"] = sum(a for a, _ in stats), sum(b for _, b in stats)
+    for k in learned:
+        bt.members[k].set_local_solver("lu")
+    return res
 
 
 def main():

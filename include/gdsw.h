@@ -289,6 +289,14 @@ gdsw_status gdsw_learned_loss_grad(gdsw_ctx* ctx, const float* x_host, const flo
  * per apply. */
 gdsw_status gdsw_set_local_solver(gdsw_ctx* ctx, int32_t mode, double tau);
 
+/* Copies the trained network of src (weights and per-channel output scales)
+ * into dst, so that one training serves several problems whose interior
+ * subdomains share the node grid (EINVAL otherwise).  The network works at
+ * unit viscosity; each problem scales its velocity right-hand sides by 1/mu
+ * and the pressure solution by mu, so the problems may differ in viscosity
+ * and inflow.  Both contexts need gdsw_learned_init; src may be a batch member. */
+gdsw_status gdsw_learned_copy(gdsw_ctx* dst, const gdsw_ctx* src, void* stream);
+
 /* Interior local solves done by the network and by the LU fallback so far. */
 gdsw_status gdsw_learned_stats(const gdsw_ctx* ctx, int64_t* learned_solves, int64_t* fallbacks);
 

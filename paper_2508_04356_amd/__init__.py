@@ -94,6 +94,7 @@ _sig = {
     "gdsw_learned_loss_grad": (C.c_int, [_P, _P, _P, C.c_int32, C.POINTER(C.c_double), _P, _P]),
     "gdsw_set_local_solver": (C.c_int, [_P, C.c_int32, C.c_double]),
     "gdsw_learned_stats": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "gdsw_learned_copy": (C.c_int, [_P, _P, _P]),
     "gdsw_last_error": (C.c_char_p, [_P]),
     "gdsw_destroy": (None, [_P]),
     "gdsw_setup_batch": (C.c_int, [C.POINTER(Mesh), C.POINTER(Decomposition), C.c_int32, _P, C.POINTER(_P)]),
@@ -299,6 +300,10 @@ class Solver:
     def set_local_solver(self, mode, tau=0.7):
         _check(_lib.gdsw_set_local_solver(self._ctx, {"lu": 0, "learned": 1, "none": 2}.get(mode, mode), tau),
                self._ctx)
+
+    def learned_copy(self, src, stream=None):
+        """Takes over src's trained network (src: another Solver or batch member)."""
+        _check(_lib.gdsw_learned_copy(self._ctx, src._ctx, _stream(stream)), self._ctx)
 
     def learned_stats(self):
         a, b = C.c_int64(), C.c_int64()

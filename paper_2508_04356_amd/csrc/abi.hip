@@ -539,6 +539,13 @@ gdsw_status gdsw_set_local_solver(gdsw_ctx* ctx, int32_t mode, double tau) {
   return GDSW_OK;
 }
 
+gdsw_status gdsw_learned_copy(gdsw_ctx* dst, const gdsw_ctx* src, void* stream) {
+  if (gdsw_status s = check_device_ctx(dst)) return s;
+  if (!src) return fail(dst, GDSW_EINVAL, "NULL source context");
+  if (!dst->c.learned || !src->c.learned) return fail(dst, GDSW_EINVAL, "call gdsw_learned_init on both first");
+  return guarded(dst, [&]() { learned_copy(dst->c, src->c, (hipStream_t)stream); });
+}
+
 gdsw_status gdsw_learned_stats(const gdsw_ctx* ctx, int64_t* learned_solves, int64_t* fallbacks) {
   if (!ctx || !ctx->c.learned) return fail(const_cast<gdsw_ctx*>(ctx), GDSW_EINVAL, "no learned local solve");
   if (learned_solves) *learned_solves = ctx->c.learned->learned_solves;

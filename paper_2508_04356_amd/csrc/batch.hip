@@ -13,6 +13,8 @@
 
 #include "context.h"
 #include "kernels.h"
+#include "kernels_learned.h"
+#include "learned.h"
 
 namespace gdsw {
 namespace {
@@ -20,6 +22,7 @@ namespace {
 void build_set(Batch& b, BatchSet& S, bool level1, hipStream_t st) {
   std::vector<GemvDesc> desc;
   S.owner.clear();
+  S.fidx.clear();
   S.bytes.clear();
   S.prec = -1;
   for (size_t k = 0; k < b.m.size(); ++k) {
@@ -33,6 +36,7 @@ void build_set(Batch& b, BatchSet& S, bool level1, hipStream_t st) {
     for (int f = 0; f < fs.count; ++f) {
       desc.push_back(d[f]);
       S.owner.push_back((int)k);
+      S.fidx.push_back(f);
       S.bytes.push_back((uint64_t)fs.n[f] * fs.n[f] * elem_size(fs.prec));
     }
   }
@@ -43,14 +47,16 @@ void build_set(Batch& b, BatchSet& S, bool level1, hipStream_t st) {
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return desc[a].n > desc[c].n; });
   std::vector<GemvDesc> sd(S.count);
-  std::vector<int> so(S.count);
+  std::vector<int> so(S.count), sf(S.count);
   std::vector<uint64_t> sb(S.count);
   for (int g = 0; g < S.count; ++g) {
     sd[g] = desc[order[g]];
     so[g] = S.owner[order[g]];
+    sf[g] = S.fidx[order[g]];
     sb[g] = S.bytes[order[g]];
   }
   S.owner = so;
+  S.fidx = sf;
   S.bytes = sb;
   const int RB = gemv_rows(S.prec);
   std::vector<int4> it1, it2;
@@ -76,12 +82,24 @@ void build_set(Batch& b, BatchSet& S, bool level1, hipStream_t st) {
   for (uint64_t v : S.bytes) S.active_bytes += (double)v;
 }
 
-void select_set(BatchSet& S, const std::vector<char>& active, hipStream_t st) {
+// want[g] = member of matrix g active, and g not an interior matrix of a
+// member whose interior solves are learned (or dropped) instead
+void select_set(const Batch& b, BatchSet& S, const std::vector<char>& active, bool level1, hipStream_t st) {
   if (S.count == 0) return;
+  std::vector<std::vector<char>> skip(b.m.size());
+  if (level1)
+    for (size_t k = 0; k < b.m.size(); ++k) {
+      const Context& c = *b.m[k];
+      if (!batch_learned(c)) continue;
+      skip[k].assign(c.L1.count, 0);
+      for (int32_t f : c.learned->factors) skip[k][f] = 1;
+    }
   bool same = true;
   S.active_bytes = 0.0;
   for (int g = 0; g < S.count; ++g) {
-    const int32_t v = active[S.owner[g]] ? 1 : 0;
+    const int k = S.owner[g];
+    const bool off = !skip[k].empty() && skip[k][S.fidx[g]];
+    const int32_t v = (active[k] && !off) ? 1 : 0;
     same = same && v == S.h_want[g];
     S.h_want[g] = v;
     if (v) S.active_bytes += (double)S.bytes[g];
@@ -124,9 +142,38 @@ void batch_join(Batch& b, hipStream_t st) {
   }
 }
 
+bool batch_learned(const Context& c) { return c.local_solver != 0 && c.learned && c.learned->S > 0; }
+
+void batch_save_interior(Context& c, hipStream_t ls) {
+  copy_segments(learned_gridmap(c), c.learned->S, c.d_w, c.learned->d_rsave, nullptr, ls);
+}
+
+void batch_learned_solves(Batch& b, const std::vector<char>& on, hipStream_t st) {
+  bool any = false;
+  batch_fork(b, st);
+  for (size_t k = 0; k < b.m.size(); ++k) {
+    Context& c = *b.m[k];
+    if (!on[k] || !batch_learned(c)) continue;
+    if (c.local_solver == 1) {
+      learned_interior_begin(c, batch_lane(b, k));
+      any = true;
+    } else {
+      zero_segments(learned_gridmap(c), c.learned->S, c.d_w, batch_lane(b, k));
+    }
+  }
+  batch_join(b, st);
+  if (!any) return;
+  GDSW_HIP(hipStreamSynchronize(st));
+  batch_fork(b, st);
+  for (size_t k = 0; k < b.m.size(); ++k)
+    if (on[k] && batch_learned(*b.m[k]) && b.m[k]->local_solver == 1)
+      learned_interior_finish(*b.m[k], batch_lane(b, k));
+  batch_join(b, st);
+}
+
 void batch_select(Batch& b, const std::vector<char>& member_active, hipStream_t st) {
-  select_set(b.s1, member_active, st);
-  select_set(b.s2, member_active, st);
+  select_set(b, b.s1, member_active, true, st);
+  select_set(b, b.s2, member_active, false, st);
 }
 
 void batch_local_solve(Batch& b, hipStream_t st) {
@@ -153,11 +200,16 @@ void batch_release(Batch& b) {
 }
 
 void apply_precond_batch(Batch& b, const double* const* r, double* const* z, hipStream_t st) {
-  batch_select(b, std::vector<char>(b.m.size(), 1), st);
+  const std::vector<char> all(b.m.size(), 1);
+  batch_select(b, all, st);
   batch_fork(b, st);
-  for (size_t k = 0; k < b.m.size(); ++k) apply_pre(*b.m[k], r[k], batch_lane(b, k));
+  for (size_t k = 0; k < b.m.size(); ++k) {
+    apply_pre(*b.m[k], r[k], batch_lane(b, k));
+    if (batch_learned(*b.m[k])) batch_save_interior(*b.m[k], batch_lane(b, k));
+  }
   batch_join(b, st);
   batch_local_solve(b, st);
+  batch_learned_solves(b, all, st);
   batch_fork(b, st);
   for (size_t k = 0; k < b.m.size(); ++k) apply_post(*b.m[k], z[k], batch_lane(b, k));
   batch_join(b, st);

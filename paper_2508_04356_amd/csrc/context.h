@@ -287,6 +287,7 @@ struct BatchSet {
   int prec = P_FP64;
   int count = 0;                     // matrices over all members
   std::vector<int> owner;            // member of each matrix
+  std::vector<int> fidx;             // its factor index within the member
   std::vector<uint64_t> bytes;       // algorithmic bytes of each matrix
   GemvDesc* d_desc = nullptr;
   FactorSet::GemvPlan plan;
@@ -315,6 +316,12 @@ struct Batch {
 void batch_fork(Batch& b, hipStream_t st);
 void batch_join(Batch& b, hipStream_t st);
 inline hipStream_t batch_lane(const Batch& b, size_t k) { return b.lanes[k % b.lanes.size()]; }
+// Members whose interior subdomains use the learned solve (local_solver 1)
+// or none (2): the merged product skips those matrices; their inputs are
+// saved after the gathers and the network (or zero) fills them in after it.
+bool batch_learned(const Context& c);
+void batch_save_interior(Context& c, hipStream_t ls);
+void batch_learned_solves(Batch& b, const std::vector<char>& on, hipStream_t st);
 
 void batch_build(Batch& b, hipStream_t st);
 // member_active[k] selects the members whose matrices the next products touch

@@ -32,8 +32,12 @@ struct GridMap {
   const int32_t* map;     // grid index (ch * G^3 + voxel) of each local DOF
   const int8_t* field;    // field of each local DOF (0..3)
 };
-// X[s] = grid(r_s) / ||r_s|| (velocity divided by mu); norms[s] = ||r_s||.
-// With given_norms the norms are read instead (targets share their inputs' scale).
+// X[s] = grid(r~_s) / ||r~_s|| with r~_s = r_s, velocity divided by mu (the
+// right-hand side of the unit-viscosity problem); norms[s] = ||r~_s||.
+// With given_norms the norms are read instead and the pressure, not the
+// velocity, is divided by mu: targets A_i^-1 r_s share their inputs' scale
+// and are mapped to the unit-viscosity problem (mu K u + B^T p = f is
+// K u + B^T (p / mu) = f / mu).
 void to_grid(const GridMap& gm, int S, int G, const double* src, float* X, double* norms, double mu, hipStream_t st,
              bool given_norms = false);
 // dst segment of sample s = ungrid(Y[s]) * sigma[ch] * norms[s] (pressure times mu)

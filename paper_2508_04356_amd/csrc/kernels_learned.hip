@@ -377,8 +377,13 @@ __global__ __launch_bounds__(256) void to_grid_kernel(GridMap gm, int G, const d
   const int f = gm.factor[s];
   const int n = gm.n[f];
   const double* r = src + gm.xoff[f];
+  const int8_t* fl = gm.field + gm.map_ptr[s];
+  // the norm of the input as the unit-viscosity problem sees it, (f / mu, g)
   double acc = 0.0;
-  for (int k = threadIdx.x; k < n; k += 256) acc += r[k] * r[k];
+  for (int k = threadIdx.x; k < n; k += 256) {
+    const double v = fl[k] < 3 ? r[k] / mu : r[k];
+    acc += v * v;
+  }
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int q = 128; q > 0; q >>= 1) {
@@ -392,9 +397,10 @@ __global__ __launch_bounds__(256) void to_grid_kernel(GridMap gm, int G, const d
   const int G3 = G * G * G;
   float* Xs = X + (int64_t)s * 4 * G3;
   const int32_t* mp = gm.map + gm.map_ptr[s];
-  const int8_t* fl = gm.field + gm.map_ptr[s];
+  // inputs r = (f, g): the unit-viscosity problem sees (f / mu, g); targets
+  // A_i^-1 r = (u, p): its solution is (u, p / mu)
   for (int k = threadIdx.x; k < n; k += 256) {
-    const double scale = fl[k] < 3 ? inv / mu : inv;
+    const double scale = given ? (fl[k] < 3 ? inv : inv / mu) : (fl[k] < 3 ? inv / mu : inv);
     Xs[mp[k]] = bf16_round((float)(r[k] * scale));
   }
 }

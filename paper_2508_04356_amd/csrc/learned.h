@@ -59,6 +59,13 @@ double learned_backward(Context& ctx, int B, hipStream_t st);
 void learned_generate(Context& ctx, int nsolves, uint64_t seed, hipStream_t st);
 void learned_train(Context& ctx, int steps, int batch, double lr, uint64_t seed, double* history, hipStream_t st);
 void learned_apply_interior(Context& ctx, hipStream_t st);
+// The two halves of learned_apply_interior: the network's solves and their
+// residual check (the fallback count is copied to pinned memory), then,
+// once the caller has synchronised, the exact re-solve of flagged ones.
+void learned_interior_begin(Context& ctx, hipStream_t st);
+void learned_interior_finish(Context& ctx, hipStream_t st);
+// dst's network (weights and output scales) <- src's; same interior grid.
+void learned_copy(Context& dst, const Context& src, hipStream_t st);
 void learned_release(Context& ctx);
 void learned_set_weights(Context& ctx, const float* host, hipStream_t st);
 void learned_get_weights(Context& ctx, float* host, int which, hipStream_t st);

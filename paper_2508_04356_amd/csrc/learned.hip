@@ -312,7 +312,7 @@ void learned_train(Context& ctx, int steps, int batch, double lr, uint64_t seed,
 }
 
 // interior local solves in the apply: network, residual check, LU fallback
-void learned_apply_interior(Context& ctx, hipStream_t st) {
+void learned_interior_begin(Context& ctx, hipStream_t st) {
   LearnedSolve* L = ctx.learned;
   GridMap gm = learned_gridmap(ctx);
   const double mu = ctx.P.spec.mu;
@@ -323,14 +323,39 @@ void learned_apply_interior(Context& ctx, hipStream_t st) {
   local_residual_check_csr(gm, L->S, L->max_n, L->d_rsave, ctx.d_w, L->d_lrow_off, L->d_lrow, L->d_lcol, L->d_lval,
                            L->tau, L->d_rpart, L->d_flags, L->d_count, st);
   GDSW_HIP(hipMemcpyAsync(L->h_count, L->d_count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  GDSW_HIP(hipStreamSynchronize(st));
+}
+
+void learned_interior_finish(Context& ctx, hipStream_t st) {
+  LearnedSolve* L = ctx.learned;
   const int nfb = *L->h_count;
   L->learned_solves += L->S - nfb;
   L->fallbacks += nfb;
   if (nfb > 0) {
-    copy_segments(gm, L->S, L->d_rsave, ctx.d_w, L->d_flags, st);
+    copy_segments(learned_gridmap(ctx), L->S, L->d_rsave, ctx.d_w, L->d_flags, st);
     local_solve_set(ctx.L1, ctx.d_w, st, 2, L->d_flags);
   }
+}
+
+void learned_apply_interior(Context& ctx, hipStream_t st) {
+  learned_interior_begin(ctx, st);
+  GDSW_HIP(hipStreamSynchronize(st));
+  learned_interior_finish(ctx, st);
+}
+
+void learned_copy(Context& dst, const Context& src, hipStream_t st) {
+  LearnedSolve* D = dst.learned;
+  const LearnedSolve* S = src.learned;
+  if (!D || !S) throw StatusError{1, "both contexts need gdsw_learned_init"};
+  if (D->G != S->G || D->n_params != S->n_params) throw StatusError{1, "the interior local grids differ"};
+  GDSW_HIP(hipMemcpyAsync(D->d_master, S->d_master, D->n_params * sizeof(float), hipMemcpyDeviceToDevice, st));
+  round_bf16(D->d_master, D->d_work, D->n_params, st);
+  GDSW_HIP(hipMemcpyAsync(D->d_sigma, S->d_sigma, 4 * sizeof(float), hipMemcpyDeviceToDevice, st));
+  for (int ch = 0; ch < 4; ++ch) D->sigma[ch] = S->sigma[ch];
+  GDSW_HIP(hipMemsetAsync(D->d_m, 0, D->n_params * 4, st));
+  GDSW_HIP(hipMemsetAsync(D->d_v, 0, D->n_params * 4, st));
+  D->adam_t = 0;
+  D->trained = S->trained;
+  GDSW_HIP(hipStreamSynchronize(st));
 }
 
 void learned_release(Context& ctx) {

@@ -410,10 +410,14 @@ std::vector<FgmresResult> fgmres_batch(Batch& bt, const double* const* bvec, dou
     batch_select(bt, in_cycle, st);
     for (int j = 0; j < restart && running > 0; ++j) {
       batch_fork(bt, st);
-      for (int k = 0; k < K; ++k)
-        if (in_cycle[k]) apply_pre(*bt.m[k], bt.m[k]->d_V + (int64_t)j * bt.m[k]->ldv, batch_lane(bt, k));
+      for (int k = 0; k < K; ++k) {
+        if (!in_cycle[k]) continue;
+        apply_pre(*bt.m[k], bt.m[k]->d_V + (int64_t)j * bt.m[k]->ldv, batch_lane(bt, k));
+        if (batch_learned(*bt.m[k])) batch_save_interior(*bt.m[k], batch_lane(bt, k));
+      }
       batch_join(bt, st);
       batch_local_solve(bt, st);
+      batch_learned_solves(bt, in_cycle, st);
       batch_fork(bt, st);
       for (int k = 0; k < K; ++k) {
         if (!in_cycle[k]) continue;
