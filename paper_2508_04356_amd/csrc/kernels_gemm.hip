@@ -18,41 +18,39 @@ namespace {
 //
 // Item (f, r0, c0, p) of a multi-RHS plan: output rows [r0, r0 + RB) and
 // summation columns [c0, c0 + GEMM_CW) of matrix f for up to 32 right-hand
-// sides (two groups of 16).  Each wave owns RB / 4 output rows and reads its
-// MFMA operands straight from memory (no LDS, no barriers): the matrix
-// fragments with 16-byte loads (non-temporal for FP64/FP32 storage), the
-// right-hand-side fragments (small, re-read by every row block of the
-// matrix, so cached) from the work vectors (FP64/FP32) or from a BF16 copy
-// made once per launch.  The loads of the next step are issued before the
-// products of the current one (two register buffers).  partial layout:
-// partial[(p * RB + row) * 32 + j].  Summation entries past n meet zero
-// right-hand sides, so padded entries never contribute; rows and
-// right-hand sides past n and nrhs give outputs that are never read.
+// sides (two groups of 16).  partial layout: partial[(p * RB + row) * 32 + j].
+// FP64/FP32 storage: each wave owns RB / 4 output rows and reads its MFMA
+// operands straight from memory (no LDS, no barriers): the matrix fragments
+// with non-temporal 16-byte loads (each instruction covers 4 columns x 16
+// consecutive row pairs/quads), the right-hand-side fragments (re-read by
+// every row block of the matrix, so cached) from the work vectors; the
+// loads of the next step are issued before the products of the current one.
+// BF16 storage: tiles staged through LDS (gemm_part_bf16_lds_kernel), with
+// the right-hand sides from a BF16 copy made once per launch.  Summation
+// entries past n meet zero right-hand sides, so padded entries never
+// contribute; rows and right-hand sides past n and nrhs give outputs that
+// are never read.
 typedef float mf_f4 __attribute__((ext_vector_type(4)));
 typedef double mf_d4 __attribute__((ext_vector_type(4)));
 typedef __bf16 mf_bf8 __attribute__((ext_vector_type(8)));
 
 #ifndef GDSW_GEMM_HD
-#define GDSW_GEMM_HD 2    // FP64: row groups of 32 rows per wave
+#define GDSW_GEMM_HD 4    // FP64: row groups of 32 rows per wave
 #endif
 #ifndef GDSW_GEMM_H
 #define GDSW_GEMM_H 1     // FP32: row groups of 64 rows per wave
 #endif
-#ifndef GDSW_GEMM_HB
-#define GDSW_GEMM_HB 4    // BF16: 16-row output tiles per wave
-#endif
 #ifndef GDSW_GEMM_Q
-#define GDSW_GEMM_Q 4     // FP64/FP32: groups of 4 summation columns per step
+#define GDSW_GEMM_Q 2     // FP64/FP32: groups of 4 summation columns per step
 #endif
 #ifndef GDSW_GEMM_CW
 #define GDSW_GEMM_CW 2048 // summation columns per work item
 #endif
-#ifndef GDSW_GEMM_NTA
-#define GDSW_GEMM_NTA 0   // BF16: non-temporal matrix loads
+#ifndef GDSW_GEMM_SBL
+#define GDSW_GEMM_SBL 256 // BF16: summation entries per staged step
 #endif
 
 constexpr int GEMM_CW = GDSW_GEMM_CW;
-static_assert(GEMM_CW % 64 == 0, "chunks must hold whole 64-entry BF16 steps");
 
 template <typename T>
 struct MultiShape;
@@ -67,8 +65,8 @@ struct MultiShape<float> {  // v_mfma_f32_16x16x4f32: 4 rows of one column
   using P = float;
 };
 template <>
-struct MultiShape<uint16_t> {  // v_mfma_f32_16x16x32_bf16: 8 entries along the summation index
-  static constexpr int H = GDSW_GEMM_HB, RB = 4 * H * 16;
+struct MultiShape<uint16_t> {  // v_mfma_f32_16x16x32_bf16, staged through LDS (gemm_part_bf16_lds_kernel)
+  static constexpr int RB = 64;
   using P = float;
 };
 
@@ -238,67 +236,71 @@ __global__ __launch_bounds__(256) void stage_bf16_kernel(const int32_t* __restri
   }
 }
 
-// BF16 storage (the stored inverse is symmetric): lane l loads 2 x 8
-// entries of storage column Rw + 16 h + (l % 16), rows c + 16 (l / 16) + 0..15,
-// i.e. 16 consecutive summation entries of output row Rw + 16 h + (l % 16),
-// and the same 16 entries of right-hand side 16 g + (l % 16) from xb.
-template <int G>
-struct StepRegsB {
-  static constexpr int H = MultiShape<uint16_t>::H;
-  gdsw_u4 a[H][2];
-  gdsw_u4 b[G][2];
+// BF16 storage, tiles staged through LDS.  Item (f, r0, c0, p): 64 output
+// rows (= storage columns r0.., the inverse being symmetric) and GEMM_CW
+// summation entries.  Each step stages SB entries of those 64 columns
+// (each column's SB entries are contiguous: 2 SB bytes per column, read by
+// consecutive lanes, so every load instruction covers whole runs of a
+// column) and the same SB entries of the 32 BF16 right-hand sides; wave w
+// then runs the MFMAs of output rows 16 w .. 16 w + 15 from LDS.  The next
+// step's loads are issued before the current step's products.  Columns
+// past n read a clamped column (outputs never used); entries past np read
+// clamped addresses and get zero right-hand sides.
+constexpr int BL_RB = 64, BL_SB = GDSW_GEMM_SBL, BL_PAD = BL_SB + 8;
+constexpr int BL_APIECES = BL_RB * BL_SB / 8 / 256;  // 16-byte pieces per thread per step (A)
+constexpr int BL_BPIECES = 32 * BL_SB / 8 / 256;     // (right-hand sides)
+static_assert(BL_APIECES >= 1 && BL_BPIECES >= 1 && GEMM_CW % BL_SB == 0, "BF16 LDS step shape");
+
+struct BlRegs {
+  gdsw_u4 a[BL_APIECES];
+  gdsw_u4 b[BL_BPIECES];
 };
 
-// Unconditional loads (see load_step): output rows beyond n read a clamped
-// column and are never used; summation entries in [n, np) meet zeros in xb.
-template <int G>
-__device__ inline void load_step_bf16(StepRegsB<G>& R, const uint16_t* const (&srcA)[MultiShape<uint16_t>::H],
-                                      const uint16_t* const (&srcB)[G], int c) {
-  constexpr int H = StepRegsB<G>::H;
+__device__ inline void bl_load(BlRegs& R, const uint16_t* __restrict__ A, const uint16_t* __restrict__ X, int r0,
+                               int n, int64_t np, int c) {
+  constexpr int PPC = BL_SB / 8;  // pieces per column
 #pragma unroll
-  for (int h = 0; h < H; ++h) {
-#if GDSW_GEMM_NTA
-    R.a[h][0] = __builtin_nontemporal_load(reinterpret_cast<const gdsw_u4*>(srcA[h] + c));
-    R.a[h][1] = __builtin_nontemporal_load(reinterpret_cast<const gdsw_u4*>(srcA[h] + c + 8));
-#else
-    R.a[h][0] = *reinterpret_cast<const gdsw_u4*>(srcA[h] + c);
-    R.a[h][1] = *reinterpret_cast<const gdsw_u4*>(srcA[h] + c + 8);
-#endif
+  for (int u = 0; u < BL_APIECES; ++u) {
+    const int e = threadIdx.x + 256 * u, cc = e / PPC, pc = e % PPC;
+    const int64_t col = min(r0 + cc, n - 1);
+    const int64_t ent = min<int64_t>(c + 8 * pc, np - 8);
+    R.a[u] = *reinterpret_cast<const gdsw_u4*>(A + col * np + ent);
   }
 #pragma unroll
-  for (int g = 0; g < G; ++g) {
-    R.b[g][0] = *reinterpret_cast<const gdsw_u4*>(srcB[g] + c);
-    R.b[g][1] = *reinterpret_cast<const gdsw_u4*>(srcB[g] + c + 8);
+  for (int u = 0; u < BL_BPIECES; ++u) {
+    const int e = threadIdx.x + 256 * u, j = e / PPC, pc = e % PPC;
+    const int64_t ent = c + 8 * pc;
+    const gdsw_u4 v = *reinterpret_cast<const gdsw_u4*>(X + j * np + min<int64_t>(ent, np - 8));
+    const gdsw_u4 z = {0, 0, 0, 0};
+    R.b[u] = ent < np ? v : z;
+  }
+}
+
+__device__ inline void bl_store(const BlRegs& R, uint16_t* As, uint16_t* Bs) {
+  constexpr int PPC = BL_SB / 8;
+#pragma unroll
+  for (int u = 0; u < BL_APIECES; ++u) {
+    const int e = threadIdx.x + 256 * u, cc = e / PPC, pc = e % PPC;
+    *reinterpret_cast<gdsw_u4*>(As + cc * BL_PAD + 8 * pc) = R.a[u];
+  }
+#pragma unroll
+  for (int u = 0; u < BL_BPIECES; ++u) {
+    const int e = threadIdx.x + 256 * u, j = e / PPC, pc = e % PPC;
+    *reinterpret_cast<gdsw_u4*>(Bs + j * BL_PAD + 8 * pc) = R.b[u];
   }
 }
 
 template <int G>
-__device__ inline void mma_step_bf16(mf_f4 (&acc)[MultiShape<uint16_t>::H][G], const StepRegsB<G>& R) {
-#pragma unroll
-  for (int h = 0; h < StepRegsB<G>::H; ++h) {
-    const mf_bf8 A0 = __builtin_bit_cast(mf_bf8, R.a[h][0]);
-    const mf_bf8 A1 = __builtin_bit_cast(mf_bf8, R.a[h][1]);
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      acc[h][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, __builtin_bit_cast(mf_bf8, R.b[g][0]), acc[h][g], 0, 0,
-                                                          0);
-      acc[h][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, __builtin_bit_cast(mf_bf8, R.b[g][1]), acc[h][g], 0, 0,
-                                                          0);
-    }
-  }
-}
-
-template <int G>
-__global__ __launch_bounds__(256) void gemm_part_bf16_kernel(const uint16_t* __restrict__ store,
-                                                             const int64_t* __restrict__ OFF,
-                                                             const int32_t* __restrict__ N,
-                                                             const int32_t* __restrict__ NP,
-                                                             const int64_t* __restrict__ XPOFF,
-                                                             const int4* __restrict__ items,
-                                                             const uint16_t* __restrict__ xb,
-                                                             float* __restrict__ partial) {
-  using S = MultiShape<uint16_t>;
-  constexpr int H = S::H, RB = S::RB;
+__global__ __launch_bounds__(256) void gemm_part_bf16_lds_kernel(const uint16_t* __restrict__ store,
+                                                                 const int64_t* __restrict__ OFF,
+                                                                 const int32_t* __restrict__ N,
+                                                                 const int32_t* __restrict__ NP,
+                                                                 const int64_t* __restrict__ XPOFF,
+                                                                 const int4* __restrict__ items,
+                                                                 const uint16_t* __restrict__ xb,
+                                                                 float* __restrict__ partial) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[BL_RB * BL_PAD];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[32 * BL_PAD];
   const int4 item = items[blockIdx.x];
   const int f = item.x, r0 = item.y, c0 = item.z, p = item.w;
   const int n = N[f];
@@ -306,53 +308,39 @@ __global__ __launch_bounds__(256) void gemm_part_bf16_kernel(const uint16_t* __r
   const int cend = min(c0 + GEMM_CW, n);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = lane & 15, kq = lane >> 4;
-  const int Rw = r0 + wave * (RB / 4);
-  const int r = 16 * kq;  // first summation entry of this lane within a step
-  const uint16_t* srcA[H];
+  const uint16_t* A = store + OFF[f];
+  const uint16_t* X = xb + XPOFF[f] * 32;
+  const int nstep = (cend - c0 + BL_SB - 1) / BL_SB;
+  const int clast = c0 + (nstep - 1) * BL_SB;
+  mf_f4 acc[G];
 #pragma unroll
-  for (int h = 0; h < H; ++h) {
-    const int ocol = min(Rw + 16 * h + i, n - 1);  // output row = storage column (symmetry)
-    srcA[h] = store + OFF[f] + (int64_t)ocol * np + r;
-  }
-  const uint16_t* srcB[G];
+  for (int g = 0; g < G; ++g) acc[g] = mf_f4{0, 0, 0, 0};
+  auto products = [&]() {
+    const uint16_t* arow = As + (16 * wave + i) * BL_PAD + 8 * kq;
 #pragma unroll
-  for (int g = 0; g < G; ++g) srcB[g] = xb + XPOFF[f] * 32 + (int64_t)(16 * g + i) * np + r;
-  mf_f4 acc[H][G];
+    for (int t = 0; t < BL_SB / 32; ++t) {
+      const mf_bf8 a = *reinterpret_cast<const mf_bf8*>(arow + 32 * t);
 #pragma unroll
-  for (int h = 0; h < H; ++h)
-#pragma unroll
-    for (int g = 0; g < G; ++g) acc[h][g] = mf_f4{0, 0, 0, 0};
-  // steps of 64 summation entries; the last one may run into [n, np)
-  const int nstep = (cend - c0 + 63) / 64;
-  const int clast = c0 + (nstep - 1) * 64;
-  StepRegsB<G> R0, R1;
-  int c = c0;
-  if (nstep & 1) {
-    load_step_bf16(R0, srcA, srcB, c);
-    mma_step_bf16<G>(acc, R0);
-    c += 64;
-  }
-  if (c < cend) {
-    load_step_bf16(R0, srcA, srcB, c);
-    for (; c < cend; c += 128) {
-      load_step_bf16(R1, srcA, srcB, c + 64);
-      __builtin_amdgcn_sched_barrier(0);
-      mma_step_bf16<G>(acc, R0);
-      __builtin_amdgcn_sched_barrier(0);
-      load_step_bf16(R0, srcA, srcB, min(c + 128, clast));
-      __builtin_amdgcn_sched_barrier(0);
-      mma_step_bf16<G>(acc, R1);
-      __builtin_amdgcn_sched_barrier(0);
+      for (int g = 0; g < G; ++g) {
+        const mf_bf8 b = *reinterpret_cast<const mf_bf8*>(Bs + (16 * g + i) * BL_PAD + 8 * kq + 32 * t);
+        acc[g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[g], 0, 0, 0);
+      }
     }
+  };
+  BlRegs R;
+  bl_load(R, A, X, r0, n, np, c0);
+  for (int c = c0; c < cend; c += BL_SB) {
+    __syncthreads();  // the previous step's products are done with LDS
+    bl_store(R, As, Bs);
+    __syncthreads();
+    bl_load(R, A, X, r0, n, np, min(c + BL_SB, clast));  // next step (the last one reloads, unused)
+    products();
   }
-  float* out = partial + (int64_t)p * RB * 32;
+  float* out = partial + (int64_t)p * BL_RB * 32;
 #pragma unroll
   for (int g = 0; g < G; ++g)
 #pragma unroll
-    for (int h = 0; h < H; ++h)
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
-        out[(int64_t)(wave * (RB / 4) + 16 * h + 4 * kq + t) * 32 + g * 16 + i] = acc[h][g][t];
+    for (int t = 0; t < 4; ++t) out[(int64_t)(16 * wave + 4 * kq + t) * 32 + g * 16 + i] = acc[g][t];
 }
 
 // Item (f, r0, p0, cnt): w[(XOFF + r0 + t) * ldk + j] = sum_q partial[((p0 + q) * RB + t) * 32 + j].
@@ -389,11 +377,11 @@ void gemm_launch(const FactorSet& fs, double* w, int64_t ldk, int nrhs, hipStrea
                                                                             fs.d_xpoff, wj, ldk, nr, fs.d_xb);
       if (tm) GDSW_HIP(hipEventRecord(tm->ev[2 * tm->used], st));
       if (nr > 16)
-        gemm_part_bf16_kernel<2><<<G.n1, 256, 0, st>>>(store, fs.d_off, fs.d_n, fs.d_npad, fs.d_xpoff, G.d_items1,
-                                                      fs.d_xb, part);
+        gemm_part_bf16_lds_kernel<2><<<G.n1, 256, 0, st>>>(store, fs.d_off, fs.d_n, fs.d_npad, fs.d_xpoff,
+                                                          G.d_items1, fs.d_xb, part);
       else
-        gemm_part_bf16_kernel<1><<<G.n1, 256, 0, st>>>(store, fs.d_off, fs.d_n, fs.d_npad, fs.d_xpoff, G.d_items1,
-                                                      fs.d_xb, part);
+        gemm_part_bf16_lds_kernel<1><<<G.n1, 256, 0, st>>>(store, fs.d_off, fs.d_n, fs.d_npad, fs.d_xpoff,
+                                                          G.d_items1, fs.d_xb, part);
     } else {
       if (tm) GDSW_HIP(hipEventRecord(tm->ev[2 * tm->used], st));
       if (nr > 16)
