@@ -296,8 +296,25 @@ __global__ __launch_bounds__(256) void spmm_il_kernel(int64_t nrows, int K, cons
   const int64_t row = (int64_t)blockIdx.x * 8 + (threadIdx.x >> 5);
   const int j = threadIdx.x & 31;
   if (row >= nrows || j >= K) return;
+  // eight nonzeros' loads issued together; the products are summed in
+  // ascending k as in the one-column SpMV
+  const int k0 = rowptr[row], k1 = rowptr[row + 1];
   double s = 0.0;
-  for (int k = rowptr[row]; k < rowptr[row + 1]; ++k) s = fma(val[k], x[(int64_t)col[k] * K + j], s);
+  int k = k0;
+  for (; k + 8 <= k1; k += 8) {
+    int32_t c[8];
+    double v[8], xv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      c[u] = col[k + u];
+      v[u] = val[k + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) xv[u] = x[(int64_t)c[u] * K + j];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s = fma(v[u], xv[u], s);
+  }
+  for (; k < k1; ++k) s = fma(val[k], x[(int64_t)col[k] * K + j], s);
   y[row * K + j] = s;
 }
 
