@@ -379,7 +379,15 @@ __global__ void gemv_il_kernel(const double* __restrict__ V, int64_t ldv, int nc
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int j = (int)(e % K);
     double s = 0.0;
-    for (int i = 0; i < ncols; ++i) s = fma(V[(int64_t)i * ldv + e], h[(int64_t)i * K + j], s);
+    int i = 0;
+    for (; i + 8 <= ncols; i += 8) {  // eight columns' loads issued together, summed in ascending i
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = V[(int64_t)(i + u) * ldv + e];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s = fma(v[u], h[(int64_t)(i + u) * K + j], s);
+    }
+    for (; i < ncols; ++i) s = fma(V[(int64_t)i * ldv + e], h[(int64_t)i * K + j], s);
     w[e] += sign * s;
   }
 }

@@ -417,7 +417,13 @@ __global__ void scatter2_kernel(int Nc, const int32_t* __restrict__ inv_ptr, con
 // ---- Krylov helpers --------------------------------------------------------
 constexpr int DOT_CHUNK = 256;  // rows per partial block (enough blocks to fill the device at 1e5 rows)
 
-// part[b * ncols + j] = sum over rows of block b of V[:, j] * w
+// part[b * ncols + j] = sum over rows of block b of V[:, j] * w.  Wave w
+// takes columns w, w + 4, ...; it issues the loads of COLS_AT_ONCE of them
+// before reducing any, so their memory latencies overlap.  Per column: each
+// lane sums its rows in ascending order, then the lanes combine by the
+// xor-shuffle tree.
+constexpr int COLS_AT_ONCE = 4;
+
 __global__ __launch_bounds__(256) void cols_dot_partial_kernel(const double* __restrict__ V, int64_t ldv, int ncols,
                                                               const double* __restrict__ w, int64_t n,
                                                               double* __restrict__ part) {
@@ -431,17 +437,31 @@ __global__ __launch_bounds__(256) void cols_dot_partial_kernel(const double* __r
     const int64_t r = r0 + q * 64 + lane;
     wr[q] = r < r1 ? w[r] : 0.0;
   }
-  for (int j = wave; j < ncols; j += 4) {
-    const double* v = V + (int64_t)j * ldv;
-    double s = 0.0;
+  for (int j0 = wave; j0 < ncols; j0 += 4 * COLS_AT_ONCE) {
+    double vv[COLS_AT_ONCE][DOT_CHUNK / 64];
 #pragma unroll
-    for (int q = 0; q < DOT_CHUNK / 64; ++q) {
-      const int64_t r = r0 + q * 64 + lane;
-      if (r < r1) s = fma(v[r], wr[q], s);
+    for (int c = 0; c < COLS_AT_ONCE; ++c) {
+      const int j = j0 + 4 * c;
+      const double* v = V + (int64_t)min(j, ncols - 1) * ldv;
+#pragma unroll
+      for (int q = 0; q < DOT_CHUNK / 64; ++q) {
+        const int64_t r = r0 + q * 64 + lane;
+        vv[c][q] = r < r1 ? v[r] : 0.0;
+      }
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if (lane == 0) part[(int64_t)b * ncols + j] = s;
+    for (int c = 0; c < COLS_AT_ONCE; ++c) {
+      const int j = j0 + 4 * c;
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < DOT_CHUNK / 64; ++q) {
+        const int64_t r = r0 + q * 64 + lane;
+        if (r < r1) s = fma(vv[c][q], wr[q], s);
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+      if (lane == 0 && j < ncols) part[(int64_t)b * ncols + j] = s;
+    }
   }
 }
 
@@ -456,22 +476,32 @@ __global__ __launch_bounds__(64) void cols_dot_final_kernel(const double* __rest
   if (lane == 0) out[j] = s;
 }
 
+// sum_j V[r, j] h[j] in ascending j, eight columns' loads issued together
+__device__ inline double row_combination(const double* __restrict__ V, int64_t ldv, int ncols,
+                                         const double* __restrict__ h, int64_t r) {
+  double s = 0.0;
+  int j = 0;
+  for (; j + 8 <= ncols; j += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = V[(int64_t)(j + u) * ldv + r];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s = fma(v[u], h[j + u], s);
+  }
+  for (; j < ncols; ++j) s = fma(V[(int64_t)j * ldv + r], h[j], s);
+  return s;
+}
+
 __global__ void gemv_sub_kernel(const double* __restrict__ V, int64_t ldv, int ncols, const double* __restrict__ h,
                                 double* __restrict__ w, int64_t n) {
-  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int j = 0; j < ncols; ++j) s = fma(V[(int64_t)j * ldv + r], h[j], s);
-    w[r] -= s;
-  }
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+    w[r] -= row_combination(V, ldv, ncols, h, r);
 }
 
 __global__ void gemv_add_kernel(const double* __restrict__ V, int64_t ldv, int ncols, const double* __restrict__ y,
                                 double* __restrict__ x, int64_t n) {
-  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int j = 0; j < ncols; ++j) s = fma(V[(int64_t)j * ldv + r], y[j], s);
-    x[r] += s;
-  }
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+    x[r] += row_combination(V, ldv, ncols, y, r);
 }
 
 inline int grid_for(int64_t n, int bs = 256, int cap = 65536) {
