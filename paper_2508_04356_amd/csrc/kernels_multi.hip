@@ -101,22 +101,19 @@ __global__ __launch_bounds__(256) void restrict_il_kernel(int nc, int K, CoarseV
 // columns cg, cg + 8, ...
 constexpr int PT_ROWS = 32, PT_COLS = 128;
 
-// ps[kk * qn + q] = Phi[(k0 + kk) * nc + qb + q] for kk < rows, q < qn
+// ps[kk * PT_COLS + q] = Phi[(k0 + kk) * nc + qb + q] for kk < rows, q < qn,
+// zero elsewhere in the 32 x 128 tile (so the products need no predicates)
 __device__ inline void stage_phi_rows(double* ps, const double* __restrict__ phi, int k0, int rows, int nc, int qb,
                                       int qn) {
-  const int total = rows * qn;
   double v[PT_ROWS * PT_COLS / 256];
 #pragma unroll
   for (int u = 0; u < PT_ROWS * PT_COLS / 256; ++u) {
     const int e = threadIdx.x + 256 * u;
-    const int kk = e / qn, q = e - kk * qn;
-    v[u] = e < total ? phi[(int64_t)(k0 + kk) * nc + qb + q] : 0.0;
+    const int kk = e / PT_COLS, q = e % PT_COLS;
+    v[u] = (kk < rows && q < qn) ? phi[(int64_t)(k0 + kk) * nc + qb + q] : 0.0;
   }
 #pragma unroll
-  for (int u = 0; u < PT_ROWS * PT_COLS / 256; ++u) {
-    const int e = threadIdx.x + 256 * u;
-    if (e < total) ps[e] = v[u];
-  }
+  for (int u = 0; u < PT_ROWS * PT_COLS / 256; ++u) ps[threadIdx.x + 256 * u] = v[u];
 }
 
 __global__ __launch_bounds__(256) void phi_t_il_kernel(int K, CoarseView cv, const double* __restrict__ r,
@@ -156,8 +153,7 @@ __global__ __launch_bounds__(256) void phi_t_il_kernel(int K, CoarseView cv, con
       for (int kk = 0; kk < rows; ++kk) {
         const double rv = rs[kk][j];
 #pragma unroll
-        for (int u = 0; u < PT_COLS / 8; ++u)
-          if (cg + 8 * u < qn) acc[u] = fma(ps[kk * qn + cg + 8 * u], rv, acc[u]);
+        for (int u = 0; u < PT_COLS / 8; ++u) acc[u] = fma(ps[kk * PT_COLS + cg + 8 * u], rv, acc[u]);
       }
     }
     if (j < K) {
@@ -235,15 +231,18 @@ __global__ __launch_bounds__(256) void phi_prolong_il_kernel(int K, CoarseView c
       __syncthreads();
       stage_phi_rows(ps, phi, kc, rows, nc, qb, qn);
       __syncthreads();
+      // the four rows of this thread advance together (independent sums,
+      // each in ascending q); rows past the chunk read zero Phi rows
+      double a[PT_ROWS / 8];
 #pragma unroll
-      for (int v = 0; v < PT_ROWS / 8; ++v) {
-        const int kk = rl + 8 * v;
-        if (kk < rows) {
-          double a = c[sc * (PT_ROWS / 8) + v];
-          for (int q = 0; q < qn; ++q) a = fma(ps[kk * qn + q], ys[q][j], a);
-          c[sc * (PT_ROWS / 8) + v] = a;
-        }
+      for (int v = 0; v < PT_ROWS / 8; ++v) a[v] = c[sc * (PT_ROWS / 8) + v];
+      for (int q = 0; q < qn; ++q) {
+        const double y = ys[q][j];
+#pragma unroll
+        for (int v = 0; v < PT_ROWS / 8; ++v) a[v] = fma(ps[(rl + 8 * v) * PT_COLS + q], y, a[v]);
       }
+#pragma unroll
+      for (int v = 0; v < PT_ROWS / 8; ++v) c[sc * (PT_ROWS / 8) + v] = a[v];
     }
   }
   if (j < K) {
@@ -320,13 +319,21 @@ __global__ __launch_bounds__(256) void spmm_il_kernel(int64_t nrows, int K, cons
 
 constexpr int DCH = 256;  // rows per partial block of the dot products
 
-// part[(b * ncols + i) * K + j] = sum over rows of block b of V_i[r, j] * w[r, j]
+// part[(b * ncols + i) * K + j] = sum over rows of block b of V_i[r, j] * w[r, j]:
+// thread (row lane rl, j) sums rows r0 + rl, r0 + rl + 8, ... in ascending
+// order, the 8 row lanes are combined in ascending order.  Four columns
+// per barrier; every load is unconditional (rows past n read row n - 1
+// against a zero w, lanes past K read column K - 1 and are not written), so
+// the loads stay in flight together.
+constexpr int DCOLS = 4;
+
 __global__ __launch_bounds__(256) void dots_il_partial_kernel(const double* __restrict__ V, int64_t ldv, int ncols,
                                                               const double* __restrict__ w, int64_t n, int K,
                                                               double* __restrict__ part) {
-  __shared__ double sh[8][32];
+  __shared__ double sh[DCOLS][8][32];
   const int b = blockIdx.x;
   const int j = threadIdx.x & 31, rl = threadIdx.x >> 5;
+  const int jj = min(j, K - 1);
   const int64_t r0 = (int64_t)b * DCH;
   double wr[DCH / 8];
 #pragma unroll
@@ -334,23 +341,30 @@ __global__ __launch_bounds__(256) void dots_il_partial_kernel(const double* __re
     const int64_t r = r0 + q * 8 + rl;
     wr[q] = (r < n && j < K) ? w[r * K + j] : 0.0;
   }
-  for (int i = 0; i < ncols; ++i) {
-    const double* v = V + (int64_t)i * ldv;
-    double s = 0.0;
+  for (int i0 = 0; i0 < ncols; i0 += DCOLS) {
+    double s[DCOLS];
+#pragma unroll
+    for (int c = 0; c < DCOLS; ++c) s[c] = 0.0;
 #pragma unroll
     for (int q = 0; q < DCH / 8; ++q) {
-      const int64_t r = r0 + q * 8 + rl;
-      if (r < n && j < K) s = fma(v[r * K + j], wr[q], s);
+      const int64_t rr = min<int64_t>(r0 + q * 8 + rl, n - 1);
+#pragma unroll
+      for (int c = 0; c < DCOLS; ++c) {
+        const int64_t ic = min(i0 + c, ncols - 1);
+        s[c] = fma(V[ic * ldv + rr * K + jj], wr[q], s[c]);
+      }
     }
-    sh[rl][j] = s;
+    __syncthreads();  // the previous group's sums have been read
+#pragma unroll
+    for (int c = 0; c < DCOLS; ++c) sh[c][rl][j] = s[c];
     __syncthreads();
-    if (rl == 0 && j < K) {
+    const int c = threadIdx.x >> 5;  // threads (c < DCOLS, j) combine column i0 + c
+    if (c < DCOLS && i0 + c < ncols && j < K) {
       double t = 0.0;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) t += sh[q][j];
-      part[((int64_t)b * ncols + i) * K + j] = t;
+      for (int q = 0; q < 8; ++q) t += sh[c][q][j];
+      part[((int64_t)b * ncols + i0 + c) * K + j] = t;
     }
-    __syncthreads();
   }
 }
 
