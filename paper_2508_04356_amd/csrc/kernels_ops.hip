@@ -160,19 +160,31 @@ __global__ __launch_bounds__(256) void phi_prolong_kernel(CoarseView cv, const d
                                                           const double* __restrict__ y0,
                                                           const int32_t* __restrict__ y0_pos,
                                                           double* __restrict__ z) {
+  // the subdomain's coarse values are gathered into LDS once (in parallel),
+  // 256 columns at a time; then each row sums over the columns in order
+  __shared__ double yv[256];
   const int i = blockIdx.y;
   const int ib = cv.I_ptr[i], ni = cv.I_ptr[i + 1] - ib;
-  const int k = blockIdx.x * 256 + threadIdx.x;
-  if (k >= ni) return;
+  const int k0 = blockIdx.x * 256;
+  if (k0 >= ni) return;  // uniform over the work-group
+  const int k = k0 + threadIdx.x;
   const int cb = cv.C_ptr[i], nc = cv.C_ptr[i + 1] - cb;
-  const double* ph = cv.phi_cm + cv.phi_off[i] + k;
+  const double* ph = cv.phi_cm + cv.phi_off[i] + min(k, ni - 1);
   double c = 0.0;
-  for (int j = 0; j < nc; ++j) {
-    const int32_t cc = cv.C_idx[cb + j];
-    c = fma(ph[(int64_t)j * ni], y0_pos ? w[y0_pos[cc]] : y0[cc], c);
+  for (int j0 = 0; j0 < nc; j0 += 256) {
+    const int jn = min(256, nc - j0);
+    __syncthreads();
+    if ((int)threadIdx.x < jn) {
+      const int32_t cc = cv.C_idx[cb + j0 + threadIdx.x];
+      yv[threadIdx.x] = y0_pos ? w[y0_pos[cc]] : y0[cc];
+    }
+    __syncthreads();
+    for (int j = 0; j < jn; ++j) c = fma(ph[(int64_t)(j0 + j) * ni], yv[j], c);
   }
-  const int32_t d = cv.I_idx[ib + k];
-  z[d] = z[d] + c;
+  if (k < ni) {
+    const int32_t d = cv.I_idx[ib + k];
+    z[d] = z[d] + c;
+  }
 }
 
 // t[e] = Phi_I^(i)[:, lc]^T r[I_i] for every (subdomain, local column) pair e
@@ -183,8 +195,24 @@ __global__ __launch_bounds__(256) void phi_t_kernel(CoarseView cv, const double*
   const int i = cv.cs_sub[e], lc = cv.cs_lc[e];
   const int ib = cv.I_ptr[i], ni = cv.I_ptr[i + 1] - ib;
   const double* ph = cv.phi_cm + cv.phi_off[i] + (int64_t)lc * ni;
+  // thread rows tid, tid + 256, ... in ascending order; four rows' loads
+  // (clamped into range) are issued before their products
   double s = 0.0;
-  for (int k = threadIdx.x; k < ni; k += 256) s = fma(ph[k], r[cv.I_idx[ib + k]], s);
+  for (int k0 = 0; k0 < ni; k0 += 1024) {
+    double pv[4], rv[4];
+    int32_t idx[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int kc = min(k0 + (int)threadIdx.x + 256 * u, ni - 1);
+      idx[u] = cv.I_idx[ib + kc];
+      pv[u] = ph[kc];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) rv[u] = r[idx[u]];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (k0 + (int)threadIdx.x + 256 * u < ni) s = fma(pv[u], rv[u], s);
+  }
   const double v = block_sum<256>(s, sh);
   if (threadIdx.x == 0) t[e] = v;
 }
