@@ -386,22 +386,28 @@ __global__ __launch_bounds__(256) void dots_il_final_kernel(const double* __rest
   }
 }
 
-// w[r, j] -= sum_i V_i[r, j] h[i, j]   (sign = -1)   or   x += ...   (sign = +1)
-__global__ void gemv_il_kernel(const double* __restrict__ V, int64_t ldv, int ncols, const double* __restrict__ h,
-                               double* __restrict__ w, int64_t n, int K, double sign) {
+// w[r, j] -= sum_i V_i[r, j] h[i, j]   (sign = -1)   or   x += ...   (sign = +1),
+// summed in ascending i.  The coefficients h (ncols x K) are staged in LDS
+// by each work-group, which then strides over many elements.
+__global__ __launch_bounds__(256) void gemv_il_kernel(const double* __restrict__ V, int64_t ldv, int ncols,
+                                                     const double* __restrict__ h, double* __restrict__ w, int64_t n,
+                                                     int K, double sign) {
+  extern __shared__ double hs[];
+  for (int t = threadIdx.x; t < ncols * K; t += 256) hs[t] = h[t];
+  __syncthreads();
   const int64_t total = n * K;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int j = (int)(e % K);
     double s = 0.0;
     int i = 0;
-    for (; i + 8 <= ncols; i += 8) {  // eight columns' loads issued together, summed in ascending i
+    for (; i + 8 <= ncols; i += 8) {  // eight columns' loads issued together
       double v[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) v[u] = V[(int64_t)(i + u) * ldv + e];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) s = fma(v[u], h[(int64_t)(i + u) * K + j], s);
+      for (int u = 0; u < 8; ++u) s = fma(v[u], hs[(i + u) * K + j], s);
     }
-    for (; i < ncols; ++i) s = fma(V[(int64_t)i * ldv + e], h[(int64_t)i * K + j], s);
+    for (; i < ncols; ++i) s = fma(V[(int64_t)i * ldv + e], hs[i * K + j], s);
     w[e] += sign * s;
   }
 }
@@ -478,7 +484,10 @@ void dots_il(const double* V, int64_t ldv, int ncols, const double* w, int64_t n
 
 void gemv_il(const double* V, int64_t ldv, int ncols, const double* h, double* w, int64_t n, int K, double sign,
              hipStream_t st) {
-  gemv_il_kernel<<<grid_for(n * K), 256, 0, st>>>(V, ldv, ncols, h, w, n, K, sign);
+  if (n == 0 || ncols == 0) return;
+  // at most 201 x 32 coefficients (restart <= 200): 51.5 KB of LDS
+  gemv_il_kernel<<<grid_for(n * K, 256, 1024), 256, (size_t)ncols * K * sizeof(double), st>>>(V, ldv, ncols, h, w, n,
+                                                                                               K, sign);
 }
 
 void scale_il(int64_t n, int K, const double* w, const double* s, const int32_t* active, double* v, hipStream_t st) {
