@@ -129,6 +129,8 @@ struct FactorSet {
   double* d_partial = nullptr;
   int64_t partial_len = 0;
   GemvPlan gemm;                     // several right-hand sides (all factors)
+  int gemm_rb = 0, gemm_cw = 0;      // its rows and summation columns per item
+  bool gemm_lds = false;             // FP64: LDS-staged kernel (few matrices)
   void* d_partial_m = nullptr;       // 32 * rows partial sums per gemm item
   int max_np = 0;                    // BF16 products: right-hand sides as BF16,
   int64_t* d_xpoff = nullptr;        //   xb[32 * xpoff[f] + j * npad[f] + row]

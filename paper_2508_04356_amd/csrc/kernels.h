@@ -62,10 +62,9 @@ void gemv_desc_launch(int prec, const GemvDesc* desc, const FactorSet::GemvPlan&
                       hipStream_t st, const int32_t* want, KernelTimer* tm, double bytes);
 // x_f <- M_f x_f for every stored inverse M_f of the set, in place on w.
 void gemv_set(const FactorSet& fs, double* w, hipStream_t st, int slot = 0, const int32_t* want = nullptr);
-// Rows per multi-RHS work item for a storage precision, and summation
-// columns per item.
-int gemm_rows(int prec);
-int gemm_cols();
+// Shape of the set's several-column products: rows and summation columns
+// per work item and which kernel (fs.gemm_rb, gemm_cw, gemm_lds).
+void gemm_choose(FactorSet& fs);
 // M <- (M + M^T) / 2 for every matrix of the batch.
 void symmetrize(const DenseBatch& B, hipStream_t st);
 // X_f <- M_f X_f for nrhs right-hand sides of the interleaved work buffer

@@ -32,6 +32,7 @@ namespace {
 // are never read.
 typedef float mf_f4 __attribute__((ext_vector_type(4)));
 typedef double mf_d4 __attribute__((ext_vector_type(4)));
+typedef double mf_d2 __attribute__((ext_vector_type(2)));
 typedef __bf16 mf_bf8 __attribute__((ext_vector_type(8)));
 
 #ifndef GDSW_GEMM_HD
@@ -56,7 +57,7 @@ template <typename T>
 struct MultiShape;
 template <>
 struct MultiShape<double> {  // v_mfma_f64_16x16x4: a lane's 16-byte load = 2 rows of one column
-  static constexpr int H = GDSW_GEMM_HD, RB = 4 * H * 32;
+  static constexpr int H = GDSW_GEMM_HD, RB = 4 * H * 32;  // direct kernel (the LDS one: DL_RB)
   using P = double;
 };
 template <>
@@ -124,7 +125,7 @@ __global__ __launch_bounds__(256) void gemm_part_kernel(const T* __restrict__ st
                                                         const int32_t* __restrict__ N, const int32_t* __restrict__ NP,
                                                         const int64_t* __restrict__ XOFF,
                                                         const int4* __restrict__ items, const double* __restrict__ w,
-                                                        int64_t ldk, int nrhs,
+                                                        int64_t ldk, int nrhs, int cw,
                                                         typename MultiShape<T>::P* __restrict__ partial) {
   using S = MultiShape<T>;
   using P = typename S::P;
@@ -135,7 +136,7 @@ __global__ __launch_bounds__(256) void gemm_part_kernel(const T* __restrict__ st
   const int f = item.x, r0 = item.y, c0 = item.z, p = item.w;
   const int n = N[f];
   const int64_t np = NP[f];
-  const int cend = min(c0 + GEMM_CW, n);
+  const int cend = min(c0 + cw, n);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = lane & 15, kq = lane >> 4;
   const int Rw = r0 + wave * (RB / 4);
@@ -249,7 +250,7 @@ __global__ __launch_bounds__(256) void stage_bf16_kernel(const int32_t* __restri
 constexpr int BL_RB = 64, BL_SB = GDSW_GEMM_SBL, BL_PAD = BL_SB + 8;
 constexpr int BL_APIECES = BL_RB * BL_SB / 8 / 256;  // 16-byte pieces per thread per step (A)
 constexpr int BL_BPIECES = 32 * BL_SB / 8 / 256;     // (right-hand sides)
-static_assert(BL_APIECES >= 1 && BL_BPIECES >= 1 && GEMM_CW % BL_SB == 0, "BF16 LDS step shape");
+static_assert(BL_APIECES >= 1 && BL_BPIECES >= 1 && 256 % BL_SB == 0, "BF16 LDS step shape: chunks are multiples of 256");
 
 struct BlRegs {
   gdsw_u4 a[BL_APIECES];
@@ -297,7 +298,7 @@ __global__ __launch_bounds__(256) void gemm_part_bf16_lds_kernel(const uint16_t*
                                                                  const int32_t* __restrict__ NP,
                                                                  const int64_t* __restrict__ XPOFF,
                                                                  const int4* __restrict__ items,
-                                                                 const uint16_t* __restrict__ xb,
+                                                                 const uint16_t* __restrict__ xb, int cw,
                                                                  float* __restrict__ partial) {
   __shared__ __attribute__((aligned(16))) uint16_t As[BL_RB * BL_PAD];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[32 * BL_PAD];
@@ -305,7 +306,7 @@ __global__ __launch_bounds__(256) void gemm_part_bf16_lds_kernel(const uint16_t*
   const int f = item.x, r0 = item.y, c0 = item.z, p = item.w;
   const int n = N[f];
   const int64_t np = NP[f];
-  const int cend = min(c0 + GEMM_CW, n);
+  const int cend = min(c0 + cw, n);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = lane & 15, kq = lane >> 4;
   const uint16_t* A = store + OFF[f];
@@ -343,6 +344,115 @@ __global__ __launch_bounds__(256) void gemm_part_bf16_lds_kernel(const uint16_t*
     for (int t = 0; t < 4; ++t) out[(int64_t)(16 * wave + 4 * kq + t) * 32 + g * 16 + i] = acc[g][t];
 }
 
+// FP64 storage, tiles staged through LDS.  Item (f, r0, c0, p): 128 output
+// rows and GEMM_CW summation columns.  Each step stages 32 columns of those
+// rows (1 KB contiguous per column, read by 64 consecutive lanes) and the
+// 32 x 32 right-hand-side block of the same columns; wave w then runs the
+// MFMAs of rows 32 w .. 32 w + 31 (two 16-row tiles) from LDS.  The next
+// step's loads are issued before the current step's products.  Rows past np
+// read a clamped row (outputs never used); columns past the chunk get zero
+// right-hand sides; right-hand sides past nrhs read a clamped one (outputs
+// never used).
+constexpr int DL_RB = 128, DL_SK = 32, DL_APAD = DL_RB + 4, DL_BPAD = 32 + 1;
+constexpr int DL_APIECES = DL_SK * DL_RB / 2 / 256;  // 16-byte pieces per thread per step
+constexpr int DL_BVALS = DL_SK * 32 / 256;           // right-hand-side values per thread per step
+static_assert(256 % DL_SK == 0, "FP64 LDS step shape: chunks are multiples of 256");
+
+struct DlRegs {
+  mf_d2 a[DL_APIECES];
+  double b[DL_BVALS];
+};
+
+__device__ inline void dl_load(DlRegs& R, const double* __restrict__ A, const double* __restrict__ x, int64_t ldk,
+                               int nrhs, int r0, int64_t np, int c, int cend) {
+#pragma unroll
+  for (int u = 0; u < DL_APIECES; ++u) {
+    const int e = threadIdx.x + 256 * u, col = e / (DL_RB / 2), pc = e % (DL_RB / 2);
+    const int64_t row = min<int64_t>(r0 + 2 * pc, np - 2);
+    R.a[u] = __builtin_nontemporal_load(reinterpret_cast<const mf_d2*>(A + (int64_t)(c + col) * np + row));
+  }
+#pragma unroll
+  for (int u = 0; u < DL_BVALS; ++u) {
+    const int e = threadIdx.x + 256 * u, kk = e / 32, j = e % 32;
+    const double v = x[(int64_t)(c + kk) * ldk + min(j, nrhs - 1)];
+    R.b[u] = c + kk < cend ? v : 0.0;
+  }
+}
+
+__device__ inline void dl_store(const DlRegs& R, double* As, double* Bs) {
+#pragma unroll
+  for (int u = 0; u < DL_APIECES; ++u) {
+    const int e = threadIdx.x + 256 * u, col = e / (DL_RB / 2), pc = e % (DL_RB / 2);
+    As[col * DL_APAD + 2 * pc] = R.a[u].x;
+    As[col * DL_APAD + 2 * pc + 1] = R.a[u].y;
+  }
+#pragma unroll
+  for (int u = 0; u < DL_BVALS; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    Bs[(e / 32) * DL_BPAD + e % 32] = R.b[u];
+  }
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void gemm_part_f64_lds_kernel(const double* __restrict__ store,
+                                                                const int64_t* __restrict__ OFF,
+                                                                const int32_t* __restrict__ N,
+                                                                const int32_t* __restrict__ NP,
+                                                                const int64_t* __restrict__ XOFF,
+                                                                const int4* __restrict__ items,
+                                                                const double* __restrict__ w, int64_t ldk, int nrhs,
+                                                                int cw, double* __restrict__ partial) {
+  __shared__ double As[DL_SK * DL_APAD];
+  __shared__ double Bs[DL_SK * DL_BPAD];
+  const int4 item = items[blockIdx.x];
+  const int f = item.x, r0 = item.y, c0 = item.z, p = item.w;
+  const int n = N[f];
+  const int64_t np = NP[f];
+  const int cend = min(c0 + cw, n);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, kq = lane >> 4;
+  const double* A = store + OFF[f];
+  const double* x = w + XOFF[f] * ldk;
+  const int nstep = (cend - c0 + DL_SK - 1) / DL_SK;
+  const int clast = c0 + (nstep - 1) * DL_SK;
+  mf_d4 acc[2][G];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int g = 0; g < G; ++g) acc[t][g] = mf_d4{0, 0, 0, 0};
+  DlRegs R;
+  dl_load(R, A, x, ldk, nrhs, r0, np, c0, cend);
+  for (int c = c0; c < cend; c += DL_SK) {
+    __syncthreads();  // the previous step's products are done with LDS
+    dl_store(R, As, Bs);
+    __syncthreads();
+    const int cn = min(c + DL_SK, clast);  // next step (the last one reloads, unused)
+    dl_load(R, A, x, ldk, nrhs, r0, np, cn, cn == c + DL_SK ? cend : cn + DL_SK);
+#pragma unroll
+    for (int s4 = 0; s4 < DL_SK / 4; ++s4) {
+      const int col = 4 * s4 + kq;
+      double a[2], b[G];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) a[t] = As[col * DL_APAD + 32 * wave + 16 * t + i];
+#pragma unroll
+      for (int g = 0; g < G; ++g) b[g] = Bs[col * DL_BPAD + 16 * g + i];
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int g = 0; g < G; ++g) acc[t][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[g], acc[t][g], 0, 0, 0);
+    }
+  }
+  // accumulator register q of a lane holds output row kq + 4 q of its tile
+  double* out = partial + (int64_t)p * DL_RB * 32;
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        out[(int64_t)(32 * wave + 16 * t + kq + 4 * q) * 32 + 16 * g + i] = acc[t][g][q];
+}
+
 // Item (f, r0, p0, cnt): w[(XOFF + r0 + t) * ldk + j] = sum_q partial[((p0 + q) * RB + t) * 32 + j].
 template <typename P, int RB>
 __global__ __launch_bounds__(256) void gemm_sum_kernel(const int32_t* __restrict__ N, const int64_t* __restrict__ XOFF,
@@ -371,40 +481,71 @@ void gemm_launch(const FactorSet& fs, double* w, int64_t ldk, int nrhs, hipStrea
     const int nr = std::min(32, nrhs - j0);
     double* wj = w + j0;
     KernelTimer* tm = (fs.timer && fs.timer->on && fs.timer->used < KernelTimer::CAP) ? fs.timer : nullptr;
-    if constexpr (sizeof(T) == 2) {
-      const uint16_t* store = static_cast<const uint16_t*>(fs.store);
+    const int cw = fs.gemm_cw;
+    if constexpr (sizeof(T) == 2)
       stage_bf16_kernel<<<dim3((fs.max_np + 63) / 64, fs.count), 256, 0, st>>>(fs.d_n, fs.d_npad, fs.d_xoff,
                                                                             fs.d_xpoff, wj, ldk, nr, fs.d_xb);
-      if (tm) GDSW_HIP(hipEventRecord(tm->ev[2 * tm->used], st));
+    if (tm) GDSW_HIP(hipEventRecord(tm->ev[2 * tm->used], st));
+    if constexpr (sizeof(T) == 2) {
+      const uint16_t* store = static_cast<const uint16_t*>(fs.store);
       if (nr > 16)
         gemm_part_bf16_lds_kernel<2><<<G.n1, 256, 0, st>>>(store, fs.d_off, fs.d_n, fs.d_npad, fs.d_xpoff,
-                                                          G.d_items1, fs.d_xb, part);
+                                                          G.d_items1, fs.d_xb, cw, part);
       else
         gemm_part_bf16_lds_kernel<1><<<G.n1, 256, 0, st>>>(store, fs.d_off, fs.d_n, fs.d_npad, fs.d_xpoff,
-                                                          G.d_items1, fs.d_xb, part);
+                                                          G.d_items1, fs.d_xb, cw, part);
+    } else if (sizeof(T) == 8 && fs.gemm_lds) {
+      const double* store = reinterpret_cast<const double*>(fs.store);
+      double* pd = reinterpret_cast<double*>(part);
+      if (nr > 16)
+        gemm_part_f64_lds_kernel<2><<<G.n1, 256, 0, st>>>(store, fs.d_off, fs.d_n, fs.d_npad, fs.d_xoff, G.d_items1,
+                                                         wj, ldk, nr, cw, pd);
+      else
+        gemm_part_f64_lds_kernel<1><<<G.n1, 256, 0, st>>>(store, fs.d_off, fs.d_n, fs.d_npad, fs.d_xoff, G.d_items1,
+                                                         wj, ldk, nr, cw, pd);
     } else {
-      if (tm) GDSW_HIP(hipEventRecord(tm->ev[2 * tm->used], st));
       if (nr > 16)
         gemm_part_kernel<T, 2><<<G.n1, 256, 0, st>>>(static_cast<const T*>(fs.store), fs.d_off, fs.d_n, fs.d_npad,
-                                                     fs.d_xoff, G.d_items1, wj, ldk, nr, part);
+                                                     fs.d_xoff, G.d_items1, wj, ldk, nr, cw, part);
       else
         gemm_part_kernel<T, 1><<<G.n1, 256, 0, st>>>(static_cast<const T*>(fs.store), fs.d_off, fs.d_n, fs.d_npad,
-                                                     fs.d_xoff, G.d_items1, wj, ldk, nr, part);
+                                                     fs.d_xoff, G.d_items1, wj, ldk, nr, cw, part);
     }
     if (tm) {
       GDSW_HIP(hipEventRecord(tm->ev[2 * tm->used++ + 1], st));
       tm->bytes += (double)fs.alg_bytes;
     }
-    gemm_sum_kernel<P, S::RB><<<G.n2, 256, 0, st>>>(fs.d_n, fs.d_xoff, G.d_items2, part, wj, ldk, nr);
+    if (sizeof(T) == 8 && fs.gemm_lds)
+      gemm_sum_kernel<P, DL_RB><<<G.n2, 256, 0, st>>>(fs.d_n, fs.d_xoff, G.d_items2, part, wj, ldk, nr);
+    else
+      gemm_sum_kernel<P, S::RB><<<G.n2, 256, 0, st>>>(fs.d_n, fs.d_xoff, G.d_items2, part, wj, ldk, nr);
   }
 }
 
 }  // namespace
 
-int gemm_cols() { return GEMM_CW; }
-
-int gemm_rows(int prec) {
-  return prec == P_FP64 ? MultiShape<double>::RB : prec == P_FP32 ? MultiShape<float>::RB : MultiShape<uint16_t>::RB;
+void gemm_choose(FactorSet& fs) {
+  // items of a shape: sum over matrices of row blocks x column chunks
+  auto items = [&](int rb, int cw) {
+    int64_t t = 0;
+    for (int f = 0; f < fs.count; ++f) t += (int64_t)((fs.n[f] + rb - 1) / rb) * ((fs.n[f] + cw - 1) / cw);
+    return t;
+  };
+  fs.gemm_lds = false;
+  fs.gemm_cw = GEMM_CW;
+  if (fs.prec == P_FP32) {
+    fs.gemm_rb = MultiShape<float>::RB;
+  } else if (fs.prec == P_BF16) {
+    fs.gemm_rb = MultiShape<uint16_t>::RB;
+  } else if (items(MultiShape<double>::RB, GEMM_CW) >= 2048) {
+    fs.gemm_rb = MultiShape<double>::RB;  // many matrices: direct fragments, long rows per wave
+  } else {
+    // few matrices (a coarse level): 128-row LDS tiles and narrower
+    // column chunks, so that the launch still fills the device
+    fs.gemm_lds = true;
+    fs.gemm_rb = DL_RB;
+    while (fs.gemm_cw > 256 && items(DL_RB, fs.gemm_cw) < 2048) fs.gemm_cw /= 2;
+  }
 }
 
 void gemm_set(const FactorSet& fs, double* w, int64_t ldk, int nrhs, hipStream_t st) {

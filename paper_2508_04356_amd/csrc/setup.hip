@@ -129,7 +129,8 @@ void plan_gemv(FactorSet& fs, DeviceArena& A, hipStream_t st, int slot, const st
 
 void plan_gemm(FactorSet& fs, DeviceArena& A, hipStream_t st) {
   if (fs.mode != SOLVE_INVERSE || fs.count == 0) return;
-  const int RB = gemm_rows(fs.prec), CW = gemm_cols();
+  gemm_choose(fs);
+  const int RB = fs.gemm_rb, CW = fs.gemm_cw;
   std::vector<int4> it1, it2;
   int p = 0;
   for (int f = 0; f < fs.count; ++f) {
