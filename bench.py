@@ -134,6 +134,8 @@ def measured_traffic(solve, launches):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary, or None when the kernel source changed since it was measured."""
     import hashlib
+    if solve not in TRAFFIC:
+        return None
     name, srcname = TRAFFIC[solve]
     path = os.path.join(ROOT, "profiles", name)
     src = os.path.join(ROOT, "paper_2508_04356_amd", "csrc", srcname)
@@ -359,7 +361,7 @@ def main():
     ap.add_argument("--precision", default=None, help="local factor precision (default: the workload's)")
     ap.add_argument("--local-algebraic", type=int, default=None,
                     help="1: algebraic overlap instead of Dirichlet u, p on the artificial boundary")
-    ap.add_argument("--local-solve", default="inverse", choices=["inverse", "triangular"],
+    ap.add_argument("--local-solve", default="inverse", choices=["inverse", "triangular", "symmetric"],
                     help="explicit inverses (default) or LU triangular solves")
     ap.add_argument("--nrhs", type=int, default=None,
                     help="right-hand sides solved together (default: the workload's; C3 has 32)")
@@ -462,8 +464,10 @@ def main():
     k_avg_us = 1e3 * k_ms / max(k_launches, 1)
     achieved = k_bytes / (k_avg_us * 1e-6) / 1e9
     per_apply = k_launches / max(sum(its), 1) if timed_in.startswith("the timed") else k_launches / args.applies
-    kname = ("gemv_part_kernel (level-1 explicit inverses times the local vectors)" if args.local_solve == "inverse"
-             else "trsv_step_kernel (blocked forward/backward solves of the level-1 factors)")
+    kname = {"inverse": "gemv_part_kernel (level-1 explicit inverses times the local vectors)",
+             "symmetric": "symv_part_kernel (upper 64x64 tiles of the symmetric level-1 inverses, both products "
+                          "per tile)",
+             "triangular": "trsv_step_kernel (blocked forward/backward solves of the level-1 factors)"}[args.local_solve]
     log(f"[bench] apply {t_apply_ms:.3f} ms; phases ms gather/restrict {ph[0]:.3f} solve {ph[1]:.3f}+{ph[2]:.3f} "
         f"scatter {ph[3]:.3f}; dominant kernel {k_launches} launches in the timed solves, {k_avg_us:.1f} us avg, "
         f"{k_bytes:.3e} B each -> {achieved:.0f} GB/s")

@@ -63,14 +63,19 @@ typedef enum {
 typedef enum { GDSW_FP64 = 0, GDSW_FP32 = 1, GDSW_BF16 = 2 } gdsw_precision;
 
 /* How the local solves A_i^-1 R_i r of eq. (2.2) / (2.5), and the coarse
- * solves, are carried out.  Both give A_i^-1 v up to rounding.
+ * solves, are carried out.  All give A_i^-1 v up to rounding.
  *   GDSW_SOLVE_INVERSE (default): the setup forms A_i^-1 explicitly by
  *     Gauss-Jordan elimination without pivoting (velocity DOFs first; its
  *     pivots are those of the no-pivoting LU) and stores it in place of the
  *     factors (same n^2 entries); an apply is one batched dense product.
  *   GDSW_SOLVE_TRIANGULAR: LU factors without pivoting and a blocked
- *     forward/backward substitution (2 * ceil(n / tile) dependent steps). */
-typedef enum { GDSW_SOLVE_INVERSE = 0, GDSW_SOLVE_TRIANGULAR = 1 } gdsw_local_solve;
+ *     forward/backward substitution (2 * ceil(n / tile) dependent steps).
+ *   GDSW_SOLVE_SYMMETRIC: the explicit inverse as above (symmetric, as
+ *     A_i is), stored as its upper triangle of 64 x 64 tiles: about half
+ *     the bytes per apply.  One right-hand side per product (max_rhs <= 1);
+ *     batches and the learned interior solve need GDSW_SOLVE_INVERSE
+ *     (EUNSUPPORTED otherwise). */
+typedef enum { GDSW_SOLVE_INVERSE = 0, GDSW_SOLVE_TRIANGULAR = 1, GDSW_SOLVE_SYMMETRIC = 2 } gdsw_local_solve;
 
 /* The mesh: structured Q2/Q1 Stokes on the unit cube (Section 4). */
 typedef struct {

@@ -73,8 +73,11 @@ ProblemSpec spec_of(const gdsw_mesh* mesh, const gdsw_decomposition* dec) {
   s.level2_layer = dec->level2_layer != 0;
   if (dec->local_precision < 0 || dec->local_precision > 2) throw std::invalid_argument("bad local_precision");
   if (dec->tile != 0 && dec->tile != 64 && dec->tile != 128) throw std::invalid_argument("tile must be 0, 64 or 128");
-  if (dec->local_solve != GDSW_SOLVE_INVERSE && dec->local_solve != GDSW_SOLVE_TRIANGULAR)
-    throw std::invalid_argument("local_solve must be GDSW_SOLVE_INVERSE or GDSW_SOLVE_TRIANGULAR");
+  if (dec->local_solve != GDSW_SOLVE_INVERSE && dec->local_solve != GDSW_SOLVE_TRIANGULAR &&
+      dec->local_solve != GDSW_SOLVE_SYMMETRIC)
+    throw std::invalid_argument("local_solve must be GDSW_SOLVE_INVERSE, _TRIANGULAR or _SYMMETRIC");
+  if (dec->local_solve == GDSW_SOLVE_SYMMETRIC && dec->max_rhs > 1)
+    throw std::invalid_argument("GDSW_SOLVE_SYMMETRIC takes one right-hand side per product (max_rhs <= 1)");
   if (dec->max_rhs < 0 || dec->max_rhs > 32) throw std::invalid_argument("max_rhs must be in 0..32");
   return s;
 }
@@ -120,7 +123,9 @@ gdsw_status gdsw_setup(const gdsw_mesh* mesh, const gdsw_decomposition* dec, voi
     ctx = new gdsw_ctx();
     Context& c = ctx->c;
     c.local_prec = dec->local_precision;
-    c.solve_mode = dec->local_solve == GDSW_SOLVE_TRIANGULAR ? SOLVE_TRSV : SOLVE_INVERSE;
+    c.solve_mode = dec->local_solve == GDSW_SOLVE_TRIANGULAR  ? SOLVE_TRSV
+                   : dec->local_solve == GDSW_SOLVE_SYMMETRIC ? SOLVE_SYM
+                                                              : SOLVE_INVERSE;
     c.max_rhs = std::max(1, dec->max_rhs);
     GDSW_HIP(hipGetDevice(&c.device));
     const auto t0 = std::chrono::steady_clock::now();
@@ -484,6 +489,8 @@ gdsw_status gdsw_autotune(gdsw_ctx* ctx, void* stream, int32_t* chosen, double* 
 
 gdsw_status gdsw_learned_init(gdsw_ctx* ctx, uint64_t seed, gdsw_learned_info* info, void* stream) {
   if (gdsw_status s = check_device_ctx(ctx)) return s;
+  if (ctx->c.solve_mode == SOLVE_SYM)
+    return fail(ctx, GDSW_EUNSUPPORTED, "the learned interior solve needs GDSW_SOLVE_INVERSE or _TRIANGULAR");
   return guarded(ctx, [&]() {
     learned_init(ctx->c, seed, (hipStream_t)stream);
     if (info) {

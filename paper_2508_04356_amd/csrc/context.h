@@ -63,6 +63,7 @@ inline size_t elem_size(int prec) { return prec == P_FP64 ? 8 : (prec == P_FP32 
 // below the diagonal, U^-1 on and above it) are kept separately in `dinv`.
 constexpr int SOLVE_INVERSE = 0;  // explicit inverse, applied as a dense matrix-vector product
 constexpr int SOLVE_TRSV = 1;     // LU factors, blocked forward/backward substitution
+constexpr int SOLVE_SYM = 2;      // symmetric explicit inverse, upper 64 x 64 tiles only
 #ifndef GDSW_GEMV_CW
 #define GDSW_GEMV_CW 1024
 #endif

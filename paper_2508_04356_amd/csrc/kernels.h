@@ -62,6 +62,15 @@ void gemv_desc_launch(int prec, const GemvDesc* desc, const FactorSet::GemvPlan&
                       hipStream_t st, const int32_t* want, KernelTimer* tm, double bytes);
 // x_f <- M_f x_f for every stored inverse M_f of the set, in place on w.
 void gemv_set(const FactorSet& fs, double* w, hipStream_t st, int slot = 0, const int32_t* want = nullptr);
+// Symmetric inverses stored as upper 64 x 64 tiles (SOLVE_SYM): tiles per
+// matrix, the work items of one matrix (tiles (f, I, J, p0 + index); block
+// row sums (f, I, p0, tiles per row)), packing of full FP64 npad x npad
+// matrices (offsets soff) into tiles at doff (elements), and the product.
+int64_t symv_tiles(int npad);
+void symv_items(int f, int npad, int64_t p0, std::vector<int4>& it1, std::vector<int4>& it2);
+void pack_upper(int prec, const double* src, const int64_t* soff, const int32_t* npad, int count, int max_npad,
+                const int64_t* doff, void* dst, hipStream_t st);
+void symv_set(const FactorSet& fs, double* w, hipStream_t st);
 // Shape of the set's several-column products: rows and summation columns
 // per work item and which kernel (fs.gemm_rb, gemm_cw, gemm_lds).
 void gemm_choose(FactorSet& fs);

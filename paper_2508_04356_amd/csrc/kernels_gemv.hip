@@ -167,6 +167,8 @@ void gemv_set(const FactorSet& fs, double* w, hipStream_t st, int slot, const in
 void local_solve_set(const FactorSet& fs, double* w, hipStream_t st, int slot, const int32_t* want) {
   if (fs.mode == SOLVE_INVERSE)
     gemv_set(fs, w, st, slot, want);
+  else if (fs.mode == SOLVE_SYM)
+    symv_set(fs, w, st);  // whole sets only (no learned subsets, no batches)
   else
     trsv_set(fs, w, st, slot, want);
 }

@@ -55,7 +55,8 @@ void DeviceArena::release_all() {
 
 uint64_t FactorSet::algorithmic_bytes() const {
   uint64_t b = 0;
-  for (int f = 0; f < count; ++f) b += (uint64_t)n[f] * n[f] * elem_size(prec);
+  for (int f = 0; f < count; ++f)
+    b += (mode == SOLVE_SYM ? (uint64_t)n[f] * (n[f] + 1) / 2 : (uint64_t)n[f] * n[f]) * elem_size(prec);
   return b;
 }
 
@@ -69,7 +70,7 @@ std::vector<GemvDesc> gemv_descs(const FactorSet& fs, double* w) {
 
 int64_t FactorSet::launches() const {
   if (count == 0) return 0;
-  if (mode == SOLVE_INVERSE) return gemv.empty() || gemv[0].n1 == 0 ? 0 : 2;
+  if (mode == SOLVE_INVERSE || mode == SOLVE_SYM) return gemv.empty() || gemv[0].n1 == 0 ? 0 : 2;
   int64_t l = 0;
   if (!sched.empty())
     for (size_t k = 0; k + 1 < sched[0].step_start.size(); ++k) l += sched[0].step_start[k + 1] > sched[0].step_start[k];
@@ -171,6 +172,26 @@ void plan_schedule(FactorSet& fs, int phases, DeviceArena& A, hipStream_t st, in
     plan_gemv(fs, A, st, slot, include);
     return;
   }
+  if (fs.mode == SOLVE_SYM) {
+    if (slot != 0 || include) throw StatusError{6, "symmetric inverse storage supports whole sets only"};
+    std::vector<int4> it1, it2;
+    for (int f = 0; f < fs.count; ++f) symv_items(f, fs.npad[f], fs.off[f] / (64 * 64), it1, it2);
+    if (fs.gemv.empty()) fs.gemv.resize(1);
+    FactorSet::GemvPlan& G = fs.gemv[0];
+    if (G.d_items1) A.free(G.d_items1);
+    if (G.d_items2) A.free(G.d_items2);
+    G.n1 = (int)it1.size();
+    G.n2 = (int)it2.size();
+    G.d_items1 = it1.empty() ? nullptr : dupload(A, it1, st);
+    G.d_items2 = it2.empty() ? nullptr : dupload(A, it2, st);
+    const int64_t need = 2 * (fs.total_elems / 64);  // 64 row and 64 column partials per tile
+    if (need > fs.partial_len) {
+      if (fs.d_partial) A.free(fs.d_partial);
+      fs.d_partial = dalloc<double>(A, std::max<int64_t>(need, 2));
+      fs.partial_len = std::max<int64_t>(need, 2);
+    }
+    return;
+  }
   phases = std::max(1, std::min(phases, std::max(1, fs.count)));
   if (slot == 0) fs.phases = phases;
   const int P = (fs.max_nblk + phases - 1) / phases;
@@ -232,7 +253,7 @@ void plan_factor_set(FactorSet& fs, const std::vector<int32_t>& sizes, int prec,
     fs.off[f] = o;
     fs.doff[f] = d;
     fs.xoff[f] = x;
-    o += np * np;
+    o += mode == SOLVE_SYM ? symv_tiles((int)np) * 64 * 64 : np * np;
     if (mode == SOLVE_TRSV) d += (int64_t)fs.nblk[f] * nb * nb;
     x += np;
     fs.max_nblk = std::max(fs.max_nblk, fs.nblk[f]);
@@ -276,6 +297,14 @@ unsigned long long* minpiv_buffer(DeviceArena& A, int count, hipStream_t st) {
 // Factor the matrices of `fs` in chunks: fill (callback writes the FP64
 // matrices into a zeroed staging batch laid out like the set), LU, checks,
 // diagonal-tile inverses and conversion to the storage precision.
+// Offset of matrix f in a factorisation chunk starting at f0: the staging
+// buffer holds full npad x npad matrices back to back in every mode.
+int64_t staging_offset(const FactorSet& fs, int f0, int f) {
+  int64_t o = 0;
+  for (int k = f0; k < f; ++k) o += (int64_t)fs.npad[k] * fs.npad[k];
+  return o;
+}
+
 template <class Fill>
 void factor_set(Context& ctx, FactorSet& fs, uint64_t staging_cap, double pivot_tol, const std::string& what,
                 hipStream_t st, Fill&& fill) {
@@ -296,7 +325,7 @@ void factor_set(Context& ctx, FactorSet& fs, uint64_t staging_cap, double pivot_
     }
     const int cnt = f1 - f0;
     double* staging;
-    bool own_staging = fs.prec != P_FP64;
+    bool own_staging = fs.prec != P_FP64 || fs.mode == SOLVE_SYM;
     if (own_staging) {
       staging = static_cast<double*>(A.alloc(bytes));
     } else {
@@ -311,8 +340,10 @@ void factor_set(Context& ctx, FactorSet& fs, uint64_t staging_cap, double pivot_
     ch.nblk.assign(fs.nblk.begin() + f0, fs.nblk.begin() + f1);
     std::vector<int64_t> off_rel(cnt), doff(cnt);
     int max_n = 0, max_nblk = 0;
+    int64_t orel = 0;  // staging layout: full npad x npad matrices back to back
     for (int k = 0; k < cnt; ++k) {
-      off_rel[k] = fs.off[f0 + k] - fs.off[f0];
+      off_rel[k] = orel;
+      orel += (int64_t)ch.npad[k] * ch.npad[k];
       doff[k] = fs.doff[f0 + k];
       max_n = std::max(max_n, ch.n[k]);
       max_nblk = std::max(max_nblk, ch.nblk[k]);
@@ -332,7 +363,7 @@ void factor_set(Context& ctx, FactorSet& fs, uint64_t staging_cap, double pivot_
     B.max_n = max_n;
     fill(B, f0, f1);
     unsigned long long* mp = minpiv_buffer(A, cnt, st);
-    if (fs.mode == SOLVE_INVERSE) {
+    if (fs.mode == SOLVE_INVERSE || fs.mode == SOLVE_SYM) {
       int64_t max_np = 0;
       for (int k = 0; k < cnt; ++k) max_np = std::max<int64_t>(max_np, ch.npad[k]);
       const int64_t tstride = 64 * max_np;
@@ -341,9 +372,19 @@ void factor_set(Context& ctx, FactorSet& fs, uint64_t staging_cap, double pivot_
       gj_invert(B, Pbuf, Tbuf, tstride, mp, st);
       check_pivots(mp, cnt, pivot_tol, what, st);
       symmetrize(B, st);
-      if (fs.prec != P_FP64)
+      if (fs.mode == SOLVE_SYM) {
+        // full staging matrices -> upper tiles of the store (chunk-relative offsets)
+        std::vector<int64_t> doff_t(cnt);
+        for (int k = 0; k < cnt; ++k) doff_t[k] = fs.off[f0 + k] - fs.off[f0];
+        int64_t* d_doff_t = dupload(A, doff_t, st);
+        pack_upper(fs.prec, staging, d_off, d_np, cnt, (int)max_np, d_doff_t,
+                   static_cast<char*>(fs.store) + (size_t)fs.off[f0] * es, st);
+        GDSW_HIP(hipStreamSynchronize(st));
+        A.free(d_doff_t);
+      } else if (fs.prec != P_FP64) {
         convert_store(fs.prec, staging, static_cast<char*>(fs.store) + (size_t)fs.off[f0] * es, (int64_t)(bytes / 8),
                       st);
+      }
       GDSW_HIP(hipStreamSynchronize(st));
       A.free(Tbuf);
       A.free(Pbuf);
@@ -800,7 +841,7 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
                }
                if (ctx.merged && f1 == ctx.L1.count) {
                  const int fc = ctx.L1.count - 1 - f0;
-                 double* dst = B.base + (ctx.L1.off[ctx.L1.count - 1] - ctx.L1.off[f0]);
+                 double* dst = B.base + staging_offset(ctx.L1, f0, ctx.L1.count - 1);
                  permute_dense(Nc, d_perm, ctx.d_A0, Nc, dst, ctx.L1.npad[ctx.L1.count - 1], st);
                  (void)fc;
                }
@@ -827,7 +868,7 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
         extract_local_dense(Bl, d_s2_ptr + f0, d_s2_idx, ctx.d_A0, ctx.Nc, mx, st);
       }
       if (ctx.Nc3 > 0 && f1 == ctx.HI.count) {
-        double* dst = B.base + (ctx.HI.off[ctx.HI.count - 1] - ctx.HI.off[f0]);
+        double* dst = B.base + staging_offset(ctx.HI, f0, ctx.HI.count - 1);
         permute_dense(ctx.Nc3, d_perm3, ctx.d_A03, ctx.Nc3, dst, ctx.HI.npad[ctx.HI.count - 1], st);
       }
     });
@@ -849,7 +890,9 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
   if (d_perm) A.free(d_perm);
   ctx.factor_bytes = 0;
   for (int f = 0; f < P.n_sub; ++f)
-    ctx.factor_bytes += (uint64_t)ctx.L1.npad[f] * ctx.L1.npad[f] * elem_size(ctx.local_prec);
+    ctx.factor_bytes += (ctx.solve_mode == SOLVE_SYM ? (uint64_t)symv_tiles(ctx.L1.npad[f]) * 64 * 64
+                                                     : (uint64_t)ctx.L1.npad[f] * ctx.L1.npad[f]) *
+                        elem_size(ctx.local_prec);
   ctx.coarse_bytes = (uint64_t)Nc * Nc * 8 * 2 + (uint64_t)phi_off.back() * 16;
   // descriptors of the stored inverses against the work vector
   for (FactorSet* fs : {&ctx.L1, &ctx.HI})

@@ -70,14 +70,15 @@ def test_three_level_apply_and_fgmres_parity(n, m, g, mu, c, restart, layer):
 
 
 def test_three_level_triangular_mode_matches_inverse_mode():
-    """The LU + triangular-solve path on every level agrees with the explicit
-    inverses (and so with the oracle) on a three-level case."""
+    """The LU + triangular-solve path and the symmetric tile storage on every
+    level agree with the explicit inverses (and so with the oracle) on a
+    three-level case."""
     n, m, g = 8, 4, 2
     p = StokesProblem(n)
     M = ThreeLevelGDSW(p.A, Decomposition(p, m, 1), g)
     r = random_vector(p.n_free, seed=4)
     zo = M(r)
-    for mode in ("triangular", "inverse"):
+    for mode in ("triangular", "inverse", "symmetric"):
         print(f"[gpu] three-level {mode} n={n} m={m} group={g}", flush=True)
         s = G.Solver(n, m, levels=3, group=g, local_solve=mode)
         z = torch.zeros(p.n_free, dtype=torch.float64, device=DEV)
@@ -112,8 +113,9 @@ def test_three_level_long_run():
     s.close()
 
 
-@pytest.mark.parametrize("prec,levels", [("fp32", 2), ("bf16", 2), ("fp32", 3)])
-def test_reduced_precision_factors_converge(prec, levels):
+@pytest.mark.parametrize("prec,levels,solve", [("fp32", 2, "inverse"), ("bf16", 2, "inverse"), ("fp32", 3, "inverse"),
+                                               ("fp32", 2, "symmetric"), ("bf16", 2, "symmetric")])
+def test_reduced_precision_factors_converge(prec, levels, solve):
     """Local factors stored in FP32 or BF16 (FP32 accumulation); FGMRES, the
     coarse levels and the true residual stay FP64.  The solve must reach the
     tolerance; the error of the preconditioner against the FP64 oracle is
@@ -122,12 +124,12 @@ def test_reduced_precision_factors_converge(prec, levels):
     p = StokesProblem(n)
     d = Decomposition(p, m, 1)
     M = ThreeLevelGDSW(p.A, d, 2) if levels == 3 else TwoLevelGDSW(p.A, d)
-    s = G.Solver(n, m, levels=levels, group=2, precision=prec)
+    s = G.Solver(n, m, levels=levels, group=2, precision=prec, local_solve=solve)
     r = random_vector(p.n_free, seed=1)
     z = torch.zeros(p.n_free, dtype=torch.float64, device=DEV)
     s.apply(dev(r), z)
     err = rel_max(host(z), M(r))
-    print(f"[gpu] {prec} levels={levels} apply rel err vs FP64 oracle {err:.2e}", flush=True)
+    print(f"[gpu] {prec} levels={levels} {solve} apply rel err vs FP64 oracle {err:.2e}", flush=True)
     assert err < (1e-2 if prec == "fp32" else 0.5)
     b = torch.zeros_like(z)
     s.rhs(b)

@@ -59,7 +59,7 @@ def gpu_case(w, **kw):
                     manufactured=w.manufactured, **kw)
 
 
-@pytest.mark.parametrize("solve", ["inverse", "triangular"])
+@pytest.mark.parametrize("solve", ["inverse", "triangular", "symmetric"])
 @pytest.mark.parametrize("w", small_parity_cases(), ids=lambda w: w.name)
 def test_setup_and_apply_parity(w, solve):
     p, d, M = oracle_case(w)
@@ -104,12 +104,13 @@ def test_tile_sizes_agree(tile):
     s.close()
 
 
+@pytest.mark.parametrize("solve", ["inverse", "symmetric"])
 @pytest.mark.parametrize("w", small_parity_cases()[:4], ids=lambda w: w.name)
-def test_fgmres_parity(w):
+def test_fgmres_parity(w, solve):
     p, d, M = oracle_case(w)
     hist = []
     xo, ito, relo, trelo = oracle_fgmres(lambda v: p.A @ v, M, p.b, rtol=w.rtol, history=hist)
-    s = gpu_case(w)
+    s = gpu_case(w, local_solve=solve)
     b = torch.zeros(p.n_free, dtype=torch.float64, device=DEV)
     s.rhs(b)
     x = torch.zeros_like(b)
@@ -264,4 +265,16 @@ def test_workload_against_stored_oracle(name):
     xh = host(x)
     xg = np.array(g["x"])
     assert np.abs(xh[idx] - xg).max() / np.abs(xg).max() < 1e-4
+    s.close()
+
+
+def test_symmetric_storage_rejections():
+    """The symmetric tile storage takes one right-hand side per product and no
+    learned interior solve: both are refused with EUNSUPPORTED / EINVAL."""
+    w = workload("C1")
+    with pytest.raises(Exception):
+        gpu_case(w, local_solve="symmetric", max_rhs=4)
+    s = gpu_case(w.with_(name="n8m4", n=8, m=4), local_solve="symmetric")
+    with pytest.raises(Exception):
+        s.learned_init(seed=1)
     s.close()
