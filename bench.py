@@ -361,8 +361,10 @@ def main():
     ap.add_argument("--precision", default=None, help="local factor precision (default: the workload's)")
     ap.add_argument("--local-algebraic", type=int, default=None,
                     help="1: algebraic overlap instead of Dirichlet u, p on the artificial boundary")
-    ap.add_argument("--local-solve", default="inverse", choices=["inverse", "triangular", "symmetric"],
-                    help="explicit inverses (default) or LU triangular solves")
+    ap.add_argument("--local-solve", default="auto", choices=["auto", "inverse", "triangular", "symmetric"],
+                    help="auto (default): symmetric tile storage of the explicit inverses for one right-hand "
+                         "side, full inverses with --learned, several right-hand sides or batches; or one of "
+                         "inverse, symmetric (explicit inverses) and triangular (LU solves)")
     ap.add_argument("--nrhs", type=int, default=None,
                     help="right-hand sides solved together (default: the workload's; C3 has 32)")
     ap.add_argument("--graph", action="store_true", help="replay each FGMRES iteration as a captured HIP graph")
@@ -384,7 +386,7 @@ def main():
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(the multi-GPU sharding is described in DESIGN.md, not built)"}))
+                                   "(sharding over several GPUs is not built)"}))
         sys.exit(2)
 
     import torch
@@ -401,6 +403,10 @@ def main():
     if nrhs > 1:
         run_multi(args, w, prec, nrhs)
         return
+    if args.local_solve == "auto":
+        # one right-hand side: the symmetric tile storage (half the bytes);
+        # the learned interior solve needs the full inverses
+        args.local_solve = "inverse" if args.learned else "symmetric"
     alg = w.local_algebraic if args.local_algebraic is None else args.local_algebraic
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)

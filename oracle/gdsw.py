@@ -22,7 +22,7 @@ velocity-type unknowns first (``lu_nopivot``): the paper names no direct
 solver, and this is the textbook variant that exists for these saddle-point
 matrices (the velocity-type block is SPD and its Schur complement negative
 definite, both pinned).  The FGMRES iteration count is sensitive to this
-choice.  The apply
+choice of factorisation.  The apply
 sums the local corrections in ascending subdomain order and adds the coarse
 correction last.
 

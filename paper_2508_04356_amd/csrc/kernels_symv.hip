@@ -4,8 +4,11 @@
 // with J >= I are kept (each tile column-major and contiguous), which halves
 // the bytes of the HBM-bound product.  A stored tile with J > I contributes
 // M_IJ x_J to block row I and M_IJ^T x_I to block row J; a diagonal tile
-// (stored whole) contributes M_II x_I.  One work-group per tile writes both
-// partial blocks; a second launch sums them per block row in a fixed order
+// (stored whole) contributes M_II x_I.  A work-group stages a tile in LDS
+// (one contiguous 32 KB read for FP64) and writes both partial blocks
+// (runs of several tiles per work-group measured slower on MI355X: 1 tile
+// 503 us, 2: 507 us, 4: 520 us, 8: 536 us at 16^3); a second launch sums
+// them per block row in a fixed order
 // (tiles (I, I), (I, I+1), ... then the transposed tiles (0, I), (1, I), ...),
 // so results are repeatable bit for bit.
 #include <hip/hip_runtime.h>
@@ -25,10 +28,17 @@ __host__ __device__ inline int64_t tile_index(int I, int J, int nt) {
   return (int64_t)I * nt - (int64_t)I * (I - 1) / 2 + (J - I);
 }
 
-// Item (f, I, J, p): tile (I, J) of matrix f, partial slot p.  Rows and
-// columns past n meet zero vector entries (the padded inverse is
-// block-diagonal, so those tile entries only feed outputs that are never
-// read).
+// Item (f, I, J0, p0): tiles (I, J0 .. J0 + SYMV_RUN - 1) (those with
+// J < nt) of matrix f; partial slots p0 + (J - J0).  The work-group walks
+// the run with the next tile's loads in flight while the current one is
+// multiplied.  Rows and columns past n meet zero vector entries (the padded
+// inverse is block-diagonal, so those tile entries only feed outputs that
+// are never read).
+#ifndef GDSW_SYMV_RUN
+#define GDSW_SYMV_RUN 1
+#endif
+constexpr int SYMV_RUN = GDSW_SYMV_RUN;
+
 template <typename T>
 __global__ __launch_bounds__(256) void symv_part_kernel(const T* __restrict__ store, const int64_t* __restrict__ OFF,
                                                         const int32_t* __restrict__ N, const int32_t* __restrict__ NP,
@@ -42,44 +52,59 @@ __global__ __launch_bounds__(256) void symv_part_kernel(const T* __restrict__ st
   __shared__ Acc xi[ST], xj[ST];
   __shared__ Acc red[4][ST];
   const int4 item = items[blockIdx.x];
-  const int f = item.x, I = item.y, J = item.z, p = item.w;
+  const int f = item.x, I = item.y, J0 = item.z, p0 = item.w;
   const int n = N[f];
   const int nt = NP[f] / ST;
-  const T* tile = store + OFF[f] + tile_index(I, J, nt) * (ST * ST);
+  const int J1 = min(nt, J0 + SYMV_RUN);
+  const double* x = w + XOFF[f];
+  const T* tiles = store + OFF[f] + tile_index(I, J0, nt) * (ST * ST);  // the run is contiguous
+  const int l = threadIdx.x & 63, q = threadIdx.x >> 6;
+  if (threadIdx.x < ST) {
+    const int ri = ST * I + threadIdx.x;
+    xi[threadIdx.x] = ri < n ? (Acc)x[ri] : (Acc)0;
+  }
   Acc v[PER][E];
 #pragma unroll
-  for (int u = 0; u < PER; ++u) load16_nt(tile + (threadIdx.x + 256 * u) * E, v[u]);
-  if (threadIdx.x < ST) {
-    const int ri = ST * I + threadIdx.x, rj = ST * J + threadIdx.x;
-    const double* x = w + XOFF[f];
-    xi[threadIdx.x] = ri < n ? (Acc)x[ri] : (Acc)0;
-    xj[threadIdx.x] = rj < n ? (Acc)x[rj] : (Acc)0;
-  }
+  for (int u = 0; u < PER; ++u) load16_nt(tiles + (threadIdx.x + 256 * u) * E, v[u]);
+  for (int J = J0; J < J1; ++J) {
+    __syncthreads();  // the previous tile's products are done with LDS
 #pragma unroll
-  for (int u = 0; u < PER; ++u)
+    for (int u = 0; u < PER; ++u)
 #pragma unroll
-    for (int t = 0; t < E; ++t) {
-      const int e = (threadIdx.x + 256 * u) * E + t;  // column-major: row e % 64, column e / 64
-      Ms[(e >> 6) * SPAD + (e & 63)] = v[u][t];
+      for (int t = 0; t < E; ++t) {
+        const int e = (threadIdx.x + 256 * u) * E + t;  // column-major: row e % 64, column e / 64
+        Ms[(e >> 6) * SPAD + (e & 63)] = v[u][t];
+      }
+    if (threadIdx.x < ST) {
+      const int rj = ST * J + threadIdx.x;
+      xj[threadIdx.x] = rj < n ? (Acc)x[rj] : (Acc)0;
     }
-  __syncthreads();
-  const int l = threadIdx.x & 63, q = threadIdx.x >> 6;
-  // block row I: thread (row l, quarter q) sums columns 16 q .. 16 q + 15
-  Acc s = 0;
+    __syncthreads();
+    if (J + 1 < J1) {  // uniform: the next tile of the run
+      const T* nxt = tiles + (int64_t)(J + 1 - J0) * (ST * ST);
 #pragma unroll
-  for (int c = 16 * q; c < 16 * q + 16; ++c) s = fma(Ms[c * SPAD + l], xj[c], s);
-  red[q][l] = s;
-  __syncthreads();
-  if (q == 0) prow[(int64_t)p * ST + l] = (double)red[0][l] + (double)red[1][l] + (double)red[2][l] + (double)red[3][l];
-  if (J == I) return;  // uniform over the work-group
-  __syncthreads();
-  // block row J (the transposed tile): thread (column l, quarter q) sums rows 16 q .. 16 q + 15
-  Acc s2 = 0;
+      for (int u = 0; u < PER; ++u) load16_nt(nxt + (threadIdx.x + 256 * u) * E, v[u]);
+    }
+    const int p = p0 + (J - J0);
+    // block row I: thread (row l, quarter q) sums columns 16 q .. 16 q + 15
+    Acc s = 0;
 #pragma unroll
-  for (int r = 16 * q; r < 16 * q + 16; ++r) s2 = fma(Ms[l * SPAD + r], xi[r], s2);
-  red[q][l] = s2;
-  __syncthreads();
-  if (q == 0) pcol[(int64_t)p * ST + l] = (double)red[0][l] + (double)red[1][l] + (double)red[2][l] + (double)red[3][l];
+    for (int c = 16 * q; c < 16 * q + 16; ++c) s = fma(Ms[c * SPAD + l], xj[c], s);
+    red[q][l] = s;
+    __syncthreads();
+    if (q == 0)
+      prow[(int64_t)p * ST + l] = (double)red[0][l] + (double)red[1][l] + (double)red[2][l] + (double)red[3][l];
+    if (J > I) {  // uniform: block row J gets the transposed tile
+      __syncthreads();
+      Acc s2 = 0;
+#pragma unroll
+      for (int r = 16 * q; r < 16 * q + 16; ++r) s2 = fma(Ms[l * SPAD + r], xi[r], s2);
+      red[q][l] = s2;
+      __syncthreads();
+      if (q == 0)
+        pcol[(int64_t)p * ST + l] = (double)red[0][l] + (double)red[1][l] + (double)red[2][l] + (double)red[3][l];
+    }
+  }
 }
 
 // Item (f, I, P0, nt): x_f[64 I + l] = sum_{J >= I} prow(I, J)[l] + sum_{K < I} pcol(K, I)[l].
@@ -150,7 +175,7 @@ int64_t symv_tiles(int npad) {
 void symv_items(int f, int npad, int64_t p0, std::vector<int4>& it1, std::vector<int4>& it2) {
   const int nt = npad / ST;
   for (int I = 0; I < nt; ++I) {
-    for (int J = I; J < nt; ++J) it1.push_back(make_int4(f, I, J, (int)(p0 + tile_index(I, J, nt))));
+    for (int J = I; J < nt; J += SYMV_RUN) it1.push_back(make_int4(f, I, J, (int)(p0 + tile_index(I, J, nt))));
     it2.push_back(make_int4(f, I, (int)p0, nt));
   }
 }
