@@ -77,6 +77,7 @@ def cpu_baseline(w, sample_subdomains=8, repeats=5):
 TRAFFIC = {  # committed counter summaries of the dominant kernel on the 16^3 FP64 workload
     "inverse": ("gemv_part_kernel_16cubed_traffic.txt", "kernels_gemv.hip"),
     "triangular": ("trsv_step_kernel_16cubed_traffic.txt", "kernels_factor.hip"),
+    "symmetric": ("symv_part_kernel_16cubed_traffic.txt", "kernels_symv.hip"),
 }
 
 
