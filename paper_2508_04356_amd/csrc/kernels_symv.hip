@@ -4,11 +4,11 @@
 // with J >= I are kept (each tile column-major and contiguous), which halves
 // the bytes of the HBM-bound product.  A stored tile with J > I contributes
 // M_IJ x_J to block row I and M_IJ^T x_I to block row J; a diagonal tile
-// (stored whole) contributes M_II x_I.  A work-group stages a tile in LDS
-// (one contiguous 32 KB read for FP64) and writes both partial blocks
-// (runs of several tiles per work-group measured slower on MI355X: 1 tile
-// 503 us, 2: 507 us, 4: 520 us, 8: 536 us at 16^3); a second launch sums
-// them per block row in a fixed order
+// (stored whole) contributes M_II x_I.  A work-group reads a run of tiles
+// of one block row (each a contiguous 32 KB read for FP64) and writes both
+// partial blocks of each (runs of 1 / 2 / 4 / 8 / 16 tiles measured 498 /
+// 495 / 507 / 524 / 544 us at 16^3 on MI355X); a second launch sums them per
+// block row in a fixed order
 // (tiles (I, I), (I, I+1), ... then the transposed tiles (0, I), (1, I), ...),
 // so results are repeatable bit for bit.
 #include <hip/hip_runtime.h>
@@ -22,20 +22,24 @@ namespace gdsw {
 namespace {
 
 constexpr int ST = 64;        // tile edge
-constexpr int SPAD = ST + 1;  // LDS column stride
 
 __host__ __device__ inline int64_t tile_index(int I, int J, int nt) {
   return (int64_t)I * nt - (int64_t)I * (I - 1) / 2 + (J - I);
 }
 
 // Item (f, I, J0, p0): tiles (I, J0 .. J0 + SYMV_RUN - 1) (those with
-// J < nt) of matrix f; partial slots p0 + (J - J0).  The work-group walks
-// the run with the next tile's loads in flight while the current one is
-// multiplied.  Rows and columns past n meet zero vector entries (the padded
-// inverse is block-diagonal, so those tile entries only feed outputs that
-// are never read).
+// J < nt, contiguous in the store) of matrix f, partial slots p0 + J - J0.
+// Thread t loads 16-byte pieces of E consecutive rows: rows r0 = E (t % PPC)
+// .. r0 + E - 1 of columns t / PPC + CPT u (PPC pieces per column, CPT
+// columns per 256 pieces), so a tile is read once, contiguously, straight
+// into registers, the next tile's pieces in flight while the current one is
+// multiplied.  The thread's share of the row product (E rows over its
+// columns) and of the column product (its columns over E rows) go through
+// small LDS reductions in a fixed order.  Rows and columns past n meet zero
+// vector entries (the padded inverse is block-diagonal, so those tile
+// entries only feed outputs that are never read).
 #ifndef GDSW_SYMV_RUN
-#define GDSW_SYMV_RUN 1
+#define GDSW_SYMV_RUN 2
 #endif
 constexpr int SYMV_RUN = GDSW_SYMV_RUN;
 
@@ -46,65 +50,85 @@ __global__ __launch_bounds__(256) void symv_part_kernel(const T* __restrict__ st
                                                         const int4* __restrict__ items, const double* __restrict__ w,
                                                         double* __restrict__ prow, double* __restrict__ pcol) {
   using Acc = typename VecW<T>::acc;
-  constexpr int E = VecW<T>::W;  // entries per 16-byte load
-  constexpr int PER = ST * ST / E / 256;
-  __shared__ Acc Ms[ST * SPAD];
-  __shared__ Acc xi[ST], xj[ST];
-  __shared__ Acc red[4][ST];
+  constexpr int E = VecW<T>::W;        // rows per 16-byte piece
+  constexpr int PPC = ST / E;          // pieces per column
+  constexpr int CPT = 256 / PPC;       // columns covered by one piece per thread
+  constexpr int PER = ST / CPT;        // pieces per thread
+  __shared__ Acc xi[ST], xj[SYMV_RUN][ST];  // the vector blocks of row I and of every tile of the run
+  __shared__ Acc rred[CPT][ST];        // row partials per column group
+  __shared__ Acc cred[ST][PPC + 1];    // column partials per row group
   const int4 item = items[blockIdx.x];
   const int f = item.x, I = item.y, J0 = item.z, p0 = item.w;
   const int n = N[f];
   const int nt = NP[f] / ST;
   const int J1 = min(nt, J0 + SYMV_RUN);
+  const T* tiles = store + OFF[f] + tile_index(I, J0, nt) * (ST * ST);
   const double* x = w + XOFF[f];
-  const T* tiles = store + OFF[f] + tile_index(I, J0, nt) * (ST * ST);  // the run is contiguous
-  const int l = threadIdx.x & 63, q = threadIdx.x >> 6;
-  if (threadIdx.x < ST) {
-    const int ri = ST * I + threadIdx.x;
-    xi[threadIdx.x] = ri < n ? (Acc)x[ri] : (Acc)0;
-  }
-  Acc v[PER][E];
+  const int t = threadIdx.x;
+  const int rg = t % PPC, cg = t / PPC, r0 = E * rg;
+  Acc v[PER][E], vn[PER][E];
 #pragma unroll
-  for (int u = 0; u < PER; ++u) load16_nt(tiles + (threadIdx.x + 256 * u) * E, v[u]);
-  for (int J = J0; J < J1; ++J) {
-    __syncthreads();  // the previous tile's products are done with LDS
+  for (int u = 0; u < PER; ++u) load16_nt(tiles + (t + 256 * u) * E, v[u]);
+  if (t < ST) {
+    const int ri = ST * I + t;
+    xi[t] = ri < n ? (Acc)x[ri] : (Acc)0;
+  }
+  for (int e = t; e < SYMV_RUN * ST; e += 256) {
+    const int rj = ST * J0 + e;
+    xj[e / ST][e % ST] = rj < n ? (Acc)x[rj] : (Acc)0;
+  }
+  // products of tile J held in v: row part into rred, transposed part into cred
+  auto products = [&](int J) {
+    const int b = J - J0;
+    __syncthreads();  // xi / xj written; the previous tile's reductions read
+    Acc rs[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) rs[e] = 0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {  // block row I: rows r0 .. r0 + E - 1 over columns cg + CPT u
+      const Acc xc = xj[b][cg + CPT * u];
+#pragma unroll
+      for (int e = 0; e < E; ++e) rs[e] = fma(v[u][e], xc, rs[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) rred[cg][r0 + e] = rs[e];
+    if (J > I) {  // uniform: block row J gets the transposed tile
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        Acc cs = 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) cs = fma(v[u][e], xi[r0 + e], cs);
+        cred[cg + CPT * u][rg] = cs;
+      }
+    }
+    __syncthreads();
+    const int p = p0 + b;
+    if (t < ST) {
+      double s = 0.0;
+#pragma unroll
+      for (int g = 0; g < CPT; ++g) s += (double)rred[g][t];
+      prow[(int64_t)p * ST + t] = s;
+    } else if (t < 2 * ST && J > I) {
+      const int c = t - ST;
+      double s = 0.0;
+#pragma unroll
+      for (int g = 0; g < PPC; ++g) s += (double)cred[c][g];
+      pcol[(int64_t)p * ST + c] = s;
+    }
+  };
+  for (int J = J0; J + 1 < J1; ++J) {
+    // the next tile's pieces, issued before this tile's products (unconditional
+    // inside the loop, so that they stay in flight meanwhile)
+    const T* nxt = tiles + (int64_t)(J + 1 - J0) * (ST * ST);
+#pragma unroll
+    for (int u = 0; u < PER; ++u) load16_nt(nxt + (t + 256 * u) * E, vn[u]);
+    products(J);
 #pragma unroll
     for (int u = 0; u < PER; ++u)
 #pragma unroll
-      for (int t = 0; t < E; ++t) {
-        const int e = (threadIdx.x + 256 * u) * E + t;  // column-major: row e % 64, column e / 64
-        Ms[(e >> 6) * SPAD + (e & 63)] = v[u][t];
-      }
-    if (threadIdx.x < ST) {
-      const int rj = ST * J + threadIdx.x;
-      xj[threadIdx.x] = rj < n ? (Acc)x[rj] : (Acc)0;
-    }
-    __syncthreads();
-    if (J + 1 < J1) {  // uniform: the next tile of the run
-      const T* nxt = tiles + (int64_t)(J + 1 - J0) * (ST * ST);
-#pragma unroll
-      for (int u = 0; u < PER; ++u) load16_nt(nxt + (threadIdx.x + 256 * u) * E, v[u]);
-    }
-    const int p = p0 + (J - J0);
-    // block row I: thread (row l, quarter q) sums columns 16 q .. 16 q + 15
-    Acc s = 0;
-#pragma unroll
-    for (int c = 16 * q; c < 16 * q + 16; ++c) s = fma(Ms[c * SPAD + l], xj[c], s);
-    red[q][l] = s;
-    __syncthreads();
-    if (q == 0)
-      prow[(int64_t)p * ST + l] = (double)red[0][l] + (double)red[1][l] + (double)red[2][l] + (double)red[3][l];
-    if (J > I) {  // uniform: block row J gets the transposed tile
-      __syncthreads();
-      Acc s2 = 0;
-#pragma unroll
-      for (int r = 16 * q; r < 16 * q + 16; ++r) s2 = fma(Ms[l * SPAD + r], xi[r], s2);
-      red[q][l] = s2;
-      __syncthreads();
-      if (q == 0)
-        pcol[(int64_t)p * ST + l] = (double)red[0][l] + (double)red[1][l] + (double)red[2][l] + (double)red[3][l];
-    }
+      for (int e = 0; e < E; ++e) v[u][e] = vn[u][e];
   }
+  products(J1 - 1);
 }
 
 // Item (f, I, P0, nt): x_f[64 I + l] = sum_{J >= I} prow(I, J)[l] + sum_{K < I} pcol(K, I)[l].
