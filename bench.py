@@ -252,9 +252,13 @@ def run_batch(args, prec):
     torch.cuda.set_device(dev)
     draws = c5_batch_draws()
     problems = [dict(n=n, m=n // 4, viscosity=mu, inflow=c) for n, mu, c in draws]
-    log(f"[bench] setup C5 batch: n = {[p['n'] for p in problems]} precision={prec}")
+    # the learned interior solve needs the full inverses
+    solve = args.local_solve if args.local_solve != "auto" else ("inverse" if args.learned else "symmetric")
+    if solve == "triangular":
+        raise SystemExit("batches need explicit inverses (inverse or symmetric)")
+    log(f"[bench] setup C5 batch: n = {[p['n'] for p in problems]} precision={prec} local solve {solve}")
     t0 = time.perf_counter()
-    bt = G.Batch(problems, precision=prec)
+    bt = G.Batch(problems, precision=prec, local_solve=solve)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     bs, xs = [], []
@@ -293,10 +297,12 @@ def run_batch(args, prec):
         "config": {"workload": "C5: 16 uneven Q2/Q1 problems, 4^3-element subdomains, overlap 1, 2-level GDSW, "
                                "FGMRES rtol 1e-08 restart 100",
                    "n": [p["n"] for p in problems], "factor_bytes_total": fb},
-        "iterations": its, "time_to_tol_s": ms_per_step / 1e3, "setup_s": t_setup,
+        "iterations": its, "time_to_tol_s": ms_per_step / 1e3, "setup_s": t_setup, "local_solve": solve,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "gemv_part_kernel over the merged level-1 inverses of the active members",
+                     "kernel": ("symv_part_kernel over the merged upper tiles of the active members' level-1 "
+                                "inverses" if solve == "symmetric" else
+                                "gemv_part_kernel over the merged level-1 inverses of the active members"),
                      "bytes_per_launch": k_bytes, "launches_timed": k_launches, "avg_launch_us": k_avg_us},
     }
     if args.learned:

@@ -352,15 +352,16 @@ class Batch:
     launch pair per level (a gdsw_batch).  problems: dicts with keys n, m and
     optionally viscosity, inflow, manufactured, overlap."""
 
-    def __init__(self, problems, precision="fp64", stream=None, budget=0):
+    def __init__(self, problems, precision="fp64", stream=None, budget=0, local_solve="inverse"):
         k = len(problems)
         meshes = (Mesh * k)()
         decs = (Decomposition * k)()
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        solve = LOCAL_SOLVES[local_solve] if isinstance(local_solve, str) else int(local_solve)
         for i, p in enumerate(problems):
             meshes[i] = Mesh(int(p["n"]), int(p.get("manufactured", 0)), float(p.get("viscosity", 1.0)),
                              float(p.get("inflow", 16.0)))
-            decs[i] = Decomposition(int(p["m"]), int(p.get("overlap", 1)), 2, 2, prec, 0, 0, 0, budget, 0, 1)
+            decs[i] = Decomposition(int(p["m"]), int(p.get("overlap", 1)), 2, 2, prec, 0, 0, 0, budget, solve, 1)
         self._b = C.c_void_p()
         _check(_lib.gdsw_setup_batch(meshes, decs, k, _stream(stream), C.byref(self._b)))
         self.members = []

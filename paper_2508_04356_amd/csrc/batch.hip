@@ -29,15 +29,19 @@ void build_set(Batch& b, BatchSet& S, bool level1, hipStream_t st) {
     Context& c = *b.m[k];
     const FactorSet& fs = level1 ? c.L1 : c.HI;
     if (fs.count == 0) continue;
-    if (fs.mode != SOLVE_INVERSE) throw StatusError{1, "batched solves need GDSW_SOLVE_INVERSE"};
+    if (fs.mode != SOLVE_INVERSE && fs.mode != SOLVE_SYM)
+      throw StatusError{1, "batched solves need explicit inverses (full or symmetric)"};
     if (S.prec >= 0 && S.prec != fs.prec) throw StatusError{1, "batch members must share the local precision"};
+    if (S.prec >= 0 && S.sym != (fs.mode == SOLVE_SYM)) throw StatusError{1, "batch members must share the storage"};
     S.prec = fs.prec;
+    S.sym = fs.mode == SOLVE_SYM;
     std::vector<GemvDesc> d = gemv_descs(fs, c.d_w);
     for (int f = 0; f < fs.count; ++f) {
       desc.push_back(d[f]);
       S.owner.push_back((int)k);
       S.fidx.push_back(f);
-      S.bytes.push_back((uint64_t)fs.n[f] * fs.n[f] * elem_size(fs.prec));
+      S.bytes.push_back((fs.mode == SOLVE_SYM ? (uint64_t)fs.n[f] * (fs.n[f] + 1) / 2 : (uint64_t)fs.n[f] * fs.n[f]) *
+                        elem_size(fs.prec));
     }
   }
   S.count = (int)desc.size();
@@ -60,13 +64,18 @@ void build_set(Batch& b, BatchSet& S, bool level1, hipStream_t st) {
   S.bytes = sb;
   const int RB = gemv_rows(S.prec);
   std::vector<int4> it1, it2;
-  int p = 0;
+  int64_t p = 0;
   for (int f = 0; f < S.count; ++f) {
     const int n = sd[f].n;
+    if (S.sym) {  // the same tile runs and slots as the member's own plan
+      symv_items(f, sd[f].np, p, it1, it2);
+      p += symv_tiles(sd[f].np);
+      continue;
+    }
     const int nr = (n + RB - 1) / RB, nc = (n + GEMV_CW - 1) / GEMV_CW;
     for (int c = 0; c < nc; ++c)
-      for (int J = 0; J < nr; ++J) it1.push_back(make_int4(f, J * RB, c * GEMV_CW, p + J * nc + c));
-    for (int J = 0; J < nr; ++J) it2.push_back(make_int4(f, J * RB, p + J * nc, nc));
+      for (int J = 0; J < nr; ++J) it1.push_back(make_int4(f, J * RB, c * GEMV_CW, (int)(p + J * nc + c)));
+    for (int J = 0; J < nr; ++J) it2.push_back(make_int4(f, J * RB, (int)(p + J * nc), nc));
     p += nr * nc;
   }
   DeviceArena& A = b.arena;
@@ -75,7 +84,8 @@ void build_set(Batch& b, BatchSet& S, bool level1, hipStream_t st) {
   S.plan.n2 = (int)it2.size();
   S.plan.d_items1 = dupload(A, it1, st);
   S.plan.d_items2 = dupload(A, it2, st);
-  S.d_partial = dalloc<double>(A, (int64_t)std::max(p, 1) * RB);
+  S.partial_len = S.sym ? 2 * 64 * std::max<int64_t>(p, 1) : std::max<int64_t>(p, 1) * RB;
+  S.d_partial = dalloc<double>(A, S.partial_len);
   S.h_want.assign(S.count, 1);
   S.d_want = dupload(A, S.h_want, st);
   S.active_bytes = 0.0;
@@ -177,11 +187,15 @@ void batch_select(Batch& b, const std::vector<char>& member_active, hipStream_t 
 }
 
 void batch_local_solve(Batch& b, hipStream_t st) {
-  if (b.s1.count)
-    gemv_desc_launch(b.s1.prec, b.s1.d_desc, b.s1.plan, GEMV_CW, b.s1.d_partial, st, b.s1.d_want, &b.timer,
-                     b.s1.active_bytes);
-  if (b.s2.count)
-    gemv_desc_launch(b.s2.prec, b.s2.d_desc, b.s2.plan, GEMV_CW, b.s2.d_partial, st, b.s2.d_want, nullptr, 0.0);
+  for (BatchSet* S : {&b.s1, &b.s2}) {
+    if (!S->count) continue;
+    KernelTimer* tm = S == &b.s1 ? &b.timer : nullptr;
+    const double bytes = S == &b.s1 ? S->active_bytes : 0.0;
+    if (S->sym)
+      symv_desc_launch(S->prec, S->d_desc, S->plan, S->d_partial, S->partial_len, st, S->d_want, tm, bytes);
+    else
+      gemv_desc_launch(S->prec, S->d_desc, S->plan, GEMV_CW, S->d_partial, st, S->d_want, tm, bytes);
+  }
 }
 
 void batch_release(Batch& b) {

@@ -295,6 +295,8 @@ struct BatchSet {
   GemvDesc* d_desc = nullptr;
   FactorSet::GemvPlan plan;
   double* d_partial = nullptr;
+  int64_t partial_len = 0;
+  bool sym = false;                  // symmetric tile storage (symv kernels)
   int32_t* d_want = nullptr;
   std::vector<int32_t> h_want;       // host copy of the last upload
   double active_bytes = 0.0;

@@ -71,6 +71,11 @@ void symv_items(int f, int npad, int64_t p0, std::vector<int4>& it1, std::vector
 void pack_upper(int prec, const double* src, const int64_t* soff, const int32_t* npad, int count, int max_npad,
                 const int64_t* doff, void* dst, hipStream_t st);
 void symv_set(const FactorSet& fs, double* w, hipStream_t st);
+// The same product over the matrices of a descriptor list (desc[g].a: the
+// tiles of matrix g; items of symv_items with g for f); want (or null)
+// skips unselected matrices; tm (or null) times the tile launch.
+void symv_desc_launch(int prec, const GemvDesc* desc, const FactorSet::GemvPlan& G, double* partial,
+                      int64_t partial_len, hipStream_t st, const int32_t* want, KernelTimer* tm, double bytes);
 // Shape of the set's several-column products: rows and summation columns
 // per work item and which kernel (fs.gemm_rb, gemm_cw, gemm_lds).
 void gemm_choose(FactorSet& fs);

@@ -44,11 +44,9 @@ __host__ __device__ inline int64_t tile_index(int I, int J, int nt) {
 constexpr int SYMV_RUN = GDSW_SYMV_RUN;
 
 template <typename T>
-__global__ __launch_bounds__(256) void symv_part_kernel(const T* __restrict__ store, const int64_t* __restrict__ OFF,
-                                                        const int32_t* __restrict__ N, const int32_t* __restrict__ NP,
-                                                        const int64_t* __restrict__ XOFF,
-                                                        const int4* __restrict__ items, const double* __restrict__ w,
-                                                        double* __restrict__ prow, double* __restrict__ pcol) {
+__global__ __launch_bounds__(256) void symv_part_kernel(const GemvDesc* __restrict__ desc,
+                                                        const int4* __restrict__ items, double* __restrict__ prow,
+                                                        double* __restrict__ pcol, const int32_t* __restrict__ want) {
   using Acc = typename VecW<T>::acc;
   constexpr int E = VecW<T>::W;        // rows per 16-byte piece
   constexpr int PPC = ST / E;          // pieces per column
@@ -58,12 +56,14 @@ __global__ __launch_bounds__(256) void symv_part_kernel(const T* __restrict__ st
   __shared__ Acc rred[CPT][ST];        // row partials per column group
   __shared__ Acc cred[ST][PPC + 1];    // column partials per row group
   const int4 item = items[blockIdx.x];
-  const int f = item.x, I = item.y, J0 = item.z, p0 = item.w;
-  const int n = N[f];
-  const int nt = NP[f] / ST;
+  const int g = item.x, I = item.y, J0 = item.z, p0 = item.w;
+  if (want && !want[g]) return;  // uniform: a matrix left out of this launch
+  const GemvDesc d = desc[g];
+  const int n = d.n;
+  const int nt = d.np / ST;
   const int J1 = min(nt, J0 + SYMV_RUN);
-  const T* tiles = store + OFF[f] + tile_index(I, J0, nt) * (ST * ST);
-  const double* x = w + XOFF[f];
+  const T* tiles = static_cast<const T*>(d.a) + tile_index(I, J0, nt) * (ST * ST);
+  const double* x = d.x;
   const int t = threadIdx.x;
   const int rg = t % PPC, cg = t / PPC, r0 = E * rg;
   Acc v[PER][E], vn[PER][E];
@@ -131,19 +131,20 @@ __global__ __launch_bounds__(256) void symv_part_kernel(const T* __restrict__ st
   products(J1 - 1);
 }
 
-// Item (f, I, P0, nt): x_f[64 I + l] = sum_{J >= I} prow(I, J)[l] + sum_{K < I} pcol(K, I)[l].
-__global__ __launch_bounds__(64) void symv_sum_kernel(const int32_t* __restrict__ N, const int64_t* __restrict__ XOFF,
+// Item (g, I, P0, nt): x_g[64 I + l] = sum_{J >= I} prow(I, J)[l] + sum_{K < I} pcol(K, I)[l].
+__global__ __launch_bounds__(64) void symv_sum_kernel(const GemvDesc* __restrict__ desc,
                                                       const int4* __restrict__ items,
                                                       const double* __restrict__ prow,
-                                                      const double* __restrict__ pcol, double* __restrict__ w) {
+                                                      const double* __restrict__ pcol, const int32_t* __restrict__ want) {
   const int4 item = items[blockIdx.x];
-  const int f = item.x, I = item.y, P0 = item.z, nt = item.w;
+  const int g = item.x, I = item.y, P0 = item.z, nt = item.w;
+  if (want && !want[g]) return;
   const int l = threadIdx.x;
   double s = 0.0;
   for (int J = I; J < nt; ++J) s += prow[(P0 + tile_index(I, J, nt)) * ST + l];
   for (int K = 0; K < I; ++K) s += pcol[(P0 + tile_index(K, I, nt)) * ST + l];
   const int r = ST * I + l;
-  if (r < N[f]) w[XOFF[f] + r] = s;
+  if (r < desc[g].n) desc[g].x[r] = s;
 }
 
 // Upper tiles of npad x npad column-major FP64 matrices, converted to the
@@ -173,20 +174,18 @@ __global__ __launch_bounds__(256) void pack_upper_kernel(const double* __restric
 }
 
 template <typename T>
-void symv_launch(const FactorSet& fs, double* w, hipStream_t st) {
-  const FactorSet::GemvPlan& G = fs.gemv[0];
+void symv_launch(const GemvDesc* desc, const FactorSet::GemvPlan& G, double* partial, int64_t partial_len,
+                 hipStream_t st, const int32_t* want, KernelTimer* tm, double bytes) {
   if (G.n1 == 0) return;
-  double* prow = fs.d_partial;
-  double* pcol = fs.d_partial + fs.partial_len / 2;
-  KernelTimer* tm = (fs.timer && fs.timer->on && fs.timer->used < KernelTimer::CAP) ? fs.timer : nullptr;
+  double* prow = partial;
+  double* pcol = partial + partial_len / 2;
   if (tm) GDSW_HIP(hipEventRecord(tm->ev[2 * tm->used], st));
-  symv_part_kernel<T><<<G.n1, 256, 0, st>>>(static_cast<const T*>(fs.store), fs.d_off, fs.d_n, fs.d_npad, fs.d_xoff,
-                                            G.d_items1, w, prow, pcol);
+  symv_part_kernel<T><<<G.n1, 256, 0, st>>>(desc, G.d_items1, prow, pcol, want);
   if (tm) {
     GDSW_HIP(hipEventRecord(tm->ev[2 * tm->used++ + 1], st));
-    tm->bytes += (double)fs.alg_bytes;
+    tm->bytes += bytes;
   }
-  symv_sum_kernel<<<G.n2, 64, 0, st>>>(fs.d_n, fs.d_xoff, G.d_items2, prow, pcol, w);
+  symv_sum_kernel<<<G.n2, 64, 0, st>>>(desc, G.d_items2, prow, pcol, want);
 }
 
 }  // namespace
@@ -218,15 +217,24 @@ void pack_upper(int prec, const double* src, const int64_t* soff, const int32_t*
   GDSW_HIP(hipGetLastError());
 }
 
-void symv_set(const FactorSet& fs, double* w, hipStream_t st) {
-  if (fs.count == 0) return;
-  if (fs.prec == P_FP64)
-    symv_launch<double>(fs, w, st);
-  else if (fs.prec == P_FP32)
-    symv_launch<float>(fs, w, st);
+void symv_desc_launch(int prec, const GemvDesc* desc, const FactorSet::GemvPlan& G, double* partial,
+                      int64_t partial_len, hipStream_t st, const int32_t* want, KernelTimer* tm, double bytes) {
+  if (tm && (!tm->on || tm->used >= KernelTimer::CAP)) tm = nullptr;
+  if (prec == P_FP64)
+    symv_launch<double>(desc, G, partial, partial_len, st, want, tm, bytes);
+  else if (prec == P_FP32)
+    symv_launch<float>(desc, G, partial, partial_len, st, want, tm, bytes);
   else
-    symv_launch<uint16_t>(fs, w, st);
+    symv_launch<uint16_t>(desc, G, partial, partial_len, st, want, tm, bytes);
   GDSW_HIP(hipGetLastError());
+}
+
+void symv_set(const FactorSet& fs, double* w, hipStream_t st) {
+  (void)w;  // the descriptors address the set's own work vector segments
+  if (fs.count == 0 || fs.gemv.empty()) return;
+  if (!fs.d_desc) throw StatusError{5, "symmetric set used before its descriptors were built"};
+  symv_desc_launch(fs.prec, fs.d_desc, fs.gemv[0], fs.d_partial, fs.partial_len, st, nullptr, fs.timer,
+                   (double)fs.alg_bytes);
 }
 
 }  // namespace gdsw

@@ -896,7 +896,8 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
   ctx.coarse_bytes = (uint64_t)Nc * Nc * 8 * 2 + (uint64_t)phi_off.back() * 16;
   // descriptors of the stored inverses against the work vector
   for (FactorSet* fs : {&ctx.L1, &ctx.HI})
-    if (fs->mode == SOLVE_INVERSE && fs->count > 0) fs->d_desc = dupload(A, gemv_descs(*fs, ctx.d_w), st);
+    if ((fs->mode == SOLVE_INVERSE || fs->mode == SOLVE_SYM) && fs->count > 0)
+      fs->d_desc = dupload(A, gemv_descs(*fs, ctx.d_w), st);
   // several right-hand sides: MFMA work plans and interleaved work buffers
   if (ctx.max_rhs > 1 && ctx.solve_mode == SOLVE_INVERSE) {
     plan_gemm(ctx.L1, A, st);

@@ -1,6 +1,6 @@
 """A batch of independent, uneven problems (different n, m, viscosity,
 inflow) whose local and coarse inverse products share one launch pair per
-level.  A member must compute exactly what it computes alone: the batched
+level (full inverses or symmetric tile storage).  A member must compute exactly what it computes alone: the batched
 apply and the lockstep FGMRES are compared bitwise with each member's own
 apply and FGMRES, and one member against the CPU oracle (1e-10)."""
 import numpy as np
@@ -25,10 +25,10 @@ PROBLEMS = [
 ]
 
 
-@pytest.fixture(scope="module")
-def batch():
-    print(f"[gpu] batch setup {PROBLEMS}", flush=True)
-    b = G.Batch(PROBLEMS)
+@pytest.fixture(scope="module", params=["inverse", "symmetric"])
+def batch(request):
+    print(f"[gpu] batch setup {PROBLEMS} {request.param}", flush=True)
+    b = G.Batch(PROBLEMS, local_solve=request.param)
     yield b
     b.close()
 
