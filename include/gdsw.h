@@ -72,9 +72,9 @@ typedef enum { GDSW_FP64 = 0, GDSW_FP32 = 1, GDSW_BF16 = 2 } gdsw_precision;
  *     forward/backward substitution (2 * ceil(n / tile) dependent steps).
  *   GDSW_SOLVE_SYMMETRIC: the explicit inverse as above (symmetric, as
  *     A_i is), stored as its upper triangle of 64 x 64 tiles: about half
- *     the bytes per apply.  One right-hand side per product (max_rhs <= 1);
- *     batches and the learned interior solve need GDSW_SOLVE_INVERSE
- *     (EUNSUPPORTED otherwise). */
+ *     the bytes per apply.  One right-hand side per product (max_rhs <= 1,
+ *     EINVAL otherwise); batches accept it (every member the same); the
+ *     learned interior solve needs GDSW_SOLVE_INVERSE (EUNSUPPORTED). */
 typedef enum { GDSW_SOLVE_INVERSE = 0, GDSW_SOLVE_TRIANGULAR = 1, GDSW_SOLVE_SYMMETRIC = 2 } gdsw_local_solve;
 
 /* The mesh: structured Q2/Q1 Stokes on the unit cube (Section 4). */
@@ -360,7 +360,8 @@ void gdsw_destroy(gdsw_ctx* ctx);
  * viscosity and inflow), each with its own context, whose level-1 and
  * coarse-level inverse products run as ONE launch pair per level over the
  * matrices of every member (longest matrix first).  Every member must use
- * GDSW_SOLVE_INVERSE and the same local_precision.  A member computes
+ * the same local_solve, GDSW_SOLVE_INVERSE or GDSW_SOLVE_SYMMETRIC (EINVAL
+ * otherwise), and the same local_precision.  A member computes
  * exactly what it computes alone (same kernels and summation orders: the
  * results are bitwise those of the member's own gdsw_apply_precond and
  * gdsw_fgmres_solve). */
