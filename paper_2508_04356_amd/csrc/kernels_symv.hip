@@ -42,6 +42,18 @@ __host__ __device__ inline int64_t tile_index(int I, int J, int nt) {
 #define GDSW_SYMV_RUN 2
 #endif
 constexpr int SYMV_RUN = GDSW_SYMV_RUN;
+#ifndef GDSW_SYMV_NT
+#define GDSW_SYMV_NT 1  // non-temporal tile loads
+#endif
+
+template <typename T, typename A>
+__device__ inline void tile_load16(const T* p, A (&o)[VecW<T>::W]) {
+#if GDSW_SYMV_NT
+  load16_nt(p, o);
+#else
+  load16(p, o);
+#endif
+}
 
 template <typename T>
 __global__ __launch_bounds__(256) void symv_part_kernel(const GemvDesc* __restrict__ desc,
@@ -68,7 +80,7 @@ __global__ __launch_bounds__(256) void symv_part_kernel(const GemvDesc* __restri
   const int rg = t % PPC, cg = t / PPC, r0 = E * rg;
   Acc v[PER][E], vn[PER][E];
 #pragma unroll
-  for (int u = 0; u < PER; ++u) load16_nt(tiles + (t + 256 * u) * E, v[u]);
+  for (int u = 0; u < PER; ++u) tile_load16(tiles + (t + 256 * u) * E, v[u]);
   if (t < ST) {
     const int ri = ST * I + t;
     xi[t] = ri < n ? (Acc)x[ri] : (Acc)0;
@@ -121,7 +133,7 @@ __global__ __launch_bounds__(256) void symv_part_kernel(const GemvDesc* __restri
     // inside the loop, so that they stay in flight meanwhile)
     const T* nxt = tiles + (int64_t)(J + 1 - J0) * (ST * ST);
 #pragma unroll
-    for (int u = 0; u < PER; ++u) load16_nt(nxt + (t + 256 * u) * E, vn[u]);
+    for (int u = 0; u < PER; ++u) tile_load16(nxt + (t + 256 * u) * E, vn[u]);
     products(J);
 #pragma unroll
     for (int u = 0; u < PER; ++u)
