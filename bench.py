@@ -252,8 +252,7 @@ def run_batch(args, prec):
     torch.cuda.set_device(dev)
     draws = c5_batch_draws()
     problems = [dict(n=n, m=n // 4, viscosity=mu, inflow=c) for n, mu, c in draws]
-    # the learned interior solve needs the full inverses
-    solve = args.local_solve if args.local_solve != "auto" else ("inverse" if args.learned else "symmetric")
+    solve = args.local_solve if args.local_solve != "auto" else "symmetric"
     if solve == "triangular":
         raise SystemExit("batches need explicit inverses (inverse or symmetric)")
     log(f"[bench] setup C5 batch: n = {[p['n'] for p in problems]} precision={prec} local solve {solve}")
@@ -370,8 +369,8 @@ def main():
                     help="1: algebraic overlap instead of Dirichlet u, p on the artificial boundary")
     ap.add_argument("--local-solve", default="auto", choices=["auto", "inverse", "triangular", "symmetric"],
                     help="auto (default): symmetric tile storage of the explicit inverses for one right-hand "
-                         "side, full inverses with --learned, several right-hand sides or batches; or one of "
-                         "inverse, symmetric (explicit inverses) and triangular (LU solves)")
+                         "side (single problems and batches), full inverses for several right-hand sides; or "
+                         "one of inverse, symmetric (explicit inverses) and triangular (LU solves)")
     ap.add_argument("--nrhs", type=int, default=None,
                     help="right-hand sides solved together (default: the workload's; C3 has 32)")
     ap.add_argument("--graph", action="store_true", help="replay each FGMRES iteration as a captured HIP graph")
@@ -411,9 +410,7 @@ def main():
         run_multi(args, w, prec, nrhs)
         return
     if args.local_solve == "auto":
-        # one right-hand side: the symmetric tile storage (half the bytes);
-        # the learned interior solve needs the full inverses
-        args.local_solve = "inverse" if args.learned else "symmetric"
+        args.local_solve = "symmetric"  # one right-hand side: the upper tiles, half the bytes
     alg = w.local_algebraic if args.local_algebraic is None else args.local_algebraic
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)

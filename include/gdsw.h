@@ -73,8 +73,7 @@ typedef enum { GDSW_FP64 = 0, GDSW_FP32 = 1, GDSW_BF16 = 2 } gdsw_precision;
  *   GDSW_SOLVE_SYMMETRIC: the explicit inverse as above (symmetric, as
  *     A_i is), stored as its upper triangle of 64 x 64 tiles: about half
  *     the bytes per apply.  One right-hand side per product (max_rhs <= 1,
- *     EINVAL otherwise); batches accept it (every member the same); the
- *     learned interior solve needs GDSW_SOLVE_INVERSE (EUNSUPPORTED). */
+ *     EINVAL otherwise); batches and the learned interior solve accept it. */
 typedef enum { GDSW_SOLVE_INVERSE = 0, GDSW_SOLVE_TRIANGULAR = 1, GDSW_SOLVE_SYMMETRIC = 2 } gdsw_local_solve;
 
 /* The mesh: structured Q2/Q1 Stokes on the unit cube (Section 4). */

@@ -489,8 +489,6 @@ gdsw_status gdsw_autotune(gdsw_ctx* ctx, void* stream, int32_t* chosen, double* 
 
 gdsw_status gdsw_learned_init(gdsw_ctx* ctx, uint64_t seed, gdsw_learned_info* info, void* stream) {
   if (gdsw_status s = check_device_ctx(ctx)) return s;
-  if (ctx->c.solve_mode == SOLVE_SYM)
-    return fail(ctx, GDSW_EUNSUPPORTED, "the learned interior solve needs GDSW_SOLVE_INVERSE or _TRIANGULAR");
   return guarded(ctx, [&]() {
     learned_init(ctx->c, seed, (hipStream_t)stream);
     if (info) {

@@ -70,7 +70,7 @@ int64_t symv_tiles(int npad);
 void symv_items(int f, int npad, int64_t p0, std::vector<int4>& it1, std::vector<int4>& it2);
 void pack_upper(int prec, const double* src, const int64_t* soff, const int32_t* npad, int count, int max_npad,
                 const int64_t* doff, void* dst, hipStream_t st);
-void symv_set(const FactorSet& fs, double* w, hipStream_t st);
+void symv_set(const FactorSet& fs, double* w, hipStream_t st, int slot = 0, const int32_t* want = nullptr);
 // The same product over the matrices of a descriptor list (desc[g].a: the
 // tiles of matrix g; items of symv_items with g for f); want (or null)
 // skips unselected matrices; tm (or null) times the tile launch.

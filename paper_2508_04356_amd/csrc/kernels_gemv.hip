@@ -168,7 +168,7 @@ void local_solve_set(const FactorSet& fs, double* w, hipStream_t st, int slot, c
   if (fs.mode == SOLVE_INVERSE)
     gemv_set(fs, w, st, slot, want);
   else if (fs.mode == SOLVE_SYM)
-    symv_set(fs, w, st);  // whole sets only (no learned subsets, no batches)
+    symv_set(fs, w, st, slot, want);
   else
     trsv_set(fs, w, st, slot, want);
 }

@@ -241,12 +241,12 @@ void symv_desc_launch(int prec, const GemvDesc* desc, const FactorSet::GemvPlan&
   GDSW_HIP(hipGetLastError());
 }
 
-void symv_set(const FactorSet& fs, double* w, hipStream_t st) {
+void symv_set(const FactorSet& fs, double* w, hipStream_t st, int slot, const int32_t* want) {
   (void)w;  // the descriptors address the set's own work vector segments
-  if (fs.count == 0 || fs.gemv.empty()) return;
+  if (fs.count == 0 || slot >= (int)fs.gemv.size()) return;
   if (!fs.d_desc) throw StatusError{5, "symmetric set used before its descriptors were built"};
-  symv_desc_launch(fs.prec, fs.d_desc, fs.gemv[0], fs.d_partial, fs.partial_len, st, nullptr, fs.timer,
-                   (double)fs.alg_bytes);
+  symv_desc_launch(fs.prec, fs.d_desc, fs.gemv[slot], fs.d_partial, fs.partial_len, st, want,
+                   slot == 0 ? fs.timer : nullptr, (double)fs.alg_bytes);
 }
 
 }  // namespace gdsw

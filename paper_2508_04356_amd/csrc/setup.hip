@@ -173,11 +173,13 @@ void plan_schedule(FactorSet& fs, int phases, DeviceArena& A, hipStream_t st, in
     return;
   }
   if (fs.mode == SOLVE_SYM) {
-    if (slot != 0 || include) throw StatusError{6, "symmetric inverse storage supports whole sets only"};
+    // slots (learned solve) cover subsets of the matrices; partial slots
+    // stay the global tile indices
     std::vector<int4> it1, it2;
-    for (int f = 0; f < fs.count; ++f) symv_items(f, fs.npad[f], fs.off[f] / (64 * 64), it1, it2);
-    if (fs.gemv.empty()) fs.gemv.resize(1);
-    FactorSet::GemvPlan& G = fs.gemv[0];
+    for (int f = 0; f < fs.count; ++f)
+      if (!include || (*include)[f]) symv_items(f, fs.npad[f], fs.off[f] / (64 * 64), it1, it2);
+    if ((int)fs.gemv.size() <= slot) fs.gemv.resize(slot + 1);
+    FactorSet::GemvPlan& G = fs.gemv[slot];
     if (G.d_items1) A.free(G.d_items1);
     if (G.d_items2) A.free(G.d_items2);
     G.n1 = (int)it1.size();

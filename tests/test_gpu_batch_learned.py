@@ -23,10 +23,10 @@ PROBLEMS = [
 ]
 
 
-@pytest.fixture(scope="module")
-def batch():
-    print(f"[gpu] learned batch setup {PROBLEMS}", flush=True)
-    b = G.Batch(PROBLEMS)
+@pytest.fixture(scope="module", params=["inverse", "symmetric"])
+def batch(request):
+    print(f"[gpu] learned batch setup {PROBLEMS} {request.param}", flush=True)
+    b = G.Batch(PROBLEMS, local_solve=request.param)
     src = b.members[0]
     src.learned_init(seed=7)
     src.learned_train(solves=2, steps=150, batch=16, lr=2e-3, seed=3)
