@@ -57,7 +57,7 @@ __global__ __launch_bounds__(64 * NW) void gemv_part_kernel(const GemvDesc* __re
   const int64_t np = d.np;
   const int ncols = min(CW, n - c0);
   const int tid = threadIdx.x;
-  const double* x = d.x + c0;
+  const auto* x = as_global<double>(d.x + c0);
   for (int i = tid; i < CW; i += 64 * NW) xs[i] = i < ncols ? (AT)x[i] : (AT)0;
   const int lane = tid & 63, wave = tid >> 6;
   const int rr = r0 + lane * E;

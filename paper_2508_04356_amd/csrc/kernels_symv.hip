@@ -10,7 +10,9 @@
 // 495 / 507 / 524 / 544 us at 16^3 on MI355X); a second launch sums them per
 // block row in a fixed order
 // (tiles (I, I), (I, I+1), ... then the transposed tiles (0, I), (1, I), ...),
-// so results are repeatable bit for bit.
+// so results are repeatable bit for bit.  Tried and measured slower: a gap
+// between stored tiles (off the 32 KB stride), runs of 3 or 4 tiles, and
+// fewer resident work-groups that each walk many items.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -78,17 +80,21 @@ __global__ __launch_bounds__(256) void symv_part_kernel(const GemvDesc* __restri
   const double* x = d.x;
   const int t = threadIdx.x;
   const int rg = t % PPC, cg = t / PPC, r0 = E * rg;
+  // the vector entries first (every thread loads, clamped to the np entries
+  // the work vector holds for this matrix, so that no load sits in a
+  // branch), then the first tile; they reach LDS only once the next tile's
+  // loads are issued too
+  static_assert(SYMV_RUN * ST <= 256, "one vector entry per thread");
+  const auto* xg = as_global<double>(x);
+  const int ri = ST * I + (t % ST), rj = ST * J0 + (t % (SYMV_RUN * ST));
+  const double xiv = xg[min(ri, d.np - 1)], xjv = xg[min(rj, d.np - 1)];
   Acc v[PER][E], vn[PER][E];
 #pragma unroll
   for (int u = 0; u < PER; ++u) tile_load16(tiles + (t + 256 * u) * E, v[u]);
-  if (t < ST) {
-    const int ri = ST * I + t;
-    xi[t] = ri < n ? (Acc)x[ri] : (Acc)0;
-  }
-  for (int e = t; e < SYMV_RUN * ST; e += 256) {
-    const int rj = ST * J0 + e;
-    xj[e / ST][e % ST] = rj < n ? (Acc)x[rj] : (Acc)0;
-  }
+  auto store_x = [&]() {
+    if (t < ST) xi[t] = ri < n ? (Acc)xiv : (Acc)0;
+    if (t < SYMV_RUN * ST) xj[t / ST][t % ST] = rj < n ? (Acc)xjv : (Acc)0;
+  };
   // products of tile J held in v: row part into rred, transposed part into cred
   auto products = [&](int J) {
     const int b = J - J0;
@@ -134,12 +140,14 @@ __global__ __launch_bounds__(256) void symv_part_kernel(const GemvDesc* __restri
     const T* nxt = tiles + (int64_t)(J + 1 - J0) * (ST * ST);
 #pragma unroll
     for (int u = 0; u < PER; ++u) tile_load16(nxt + (t + 256 * u) * E, vn[u]);
+    if (J == J0) store_x();
     products(J);
 #pragma unroll
     for (int u = 0; u < PER; ++u)
 #pragma unroll
       for (int e = 0; e < E; ++e) v[u][e] = vn[u][e];
   }
+  if (J1 - 1 == J0) store_x();
   products(J1 - 1);
 }
 

@@ -31,20 +31,31 @@ struct VecW<uint16_t> {
 typedef double gdsw_d2 __attribute__((ext_vector_type(2)));
 typedef float gdsw_f4 __attribute__((ext_vector_type(4)));
 typedef uint32_t gdsw_u4 __attribute__((ext_vector_type(4)));
+
+// Factor storage is always device (global) memory.  Its pointers often come
+// out of descriptors in memory, where the compiler cannot tell their address
+// space and would emit flat loads; a flat load also counts as an LDS access,
+// so the wait before the next LDS barrier would wait for every tile load in
+// flight.  The cast makes them global loads, counted as vector memory only.
+template <typename V>
+__device__ inline const __attribute__((address_space(1))) V* as_global(const void* p) {
+  return (const __attribute__((address_space(1))) V*)p;
+}
+
 __device__ inline void load16_nt(const double* p, double (&o)[2]) {
-  const gdsw_d2 v = __builtin_nontemporal_load(reinterpret_cast<const gdsw_d2*>(p));
+  const gdsw_d2 v = __builtin_nontemporal_load(as_global<gdsw_d2>(p));
   o[0] = v.x;
   o[1] = v.y;
 }
 __device__ inline void load16_nt(const float* p, float (&o)[4]) {
-  const gdsw_f4 v = __builtin_nontemporal_load(reinterpret_cast<const gdsw_f4*>(p));
+  const gdsw_f4 v = __builtin_nontemporal_load(as_global<gdsw_f4>(p));
   o[0] = v.x;
   o[1] = v.y;
   o[2] = v.z;
   o[3] = v.w;
 }
 __device__ inline void load16_nt(const uint16_t* p, float (&o)[8]) {
-  const gdsw_u4 v = __builtin_nontemporal_load(reinterpret_cast<const gdsw_u4*>(p));
+  const gdsw_u4 v = __builtin_nontemporal_load(as_global<gdsw_u4>(p));
   const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -54,19 +65,19 @@ __device__ inline void load16_nt(const uint16_t* p, float (&o)[8]) {
 }
 
 __device__ inline void load16(const double* p, double (&o)[2]) {
-  const double2 v = *reinterpret_cast<const double2*>(p);
+  const gdsw_d2 v = *as_global<gdsw_d2>(p);
   o[0] = v.x;
   o[1] = v.y;
 }
 __device__ inline void load16(const float* p, float (&o)[4]) {
-  const float4 v = *reinterpret_cast<const float4*>(p);
+  const gdsw_f4 v = *as_global<gdsw_f4>(p);
   o[0] = v.x;
   o[1] = v.y;
   o[2] = v.z;
   o[3] = v.w;
 }
 __device__ inline void load16(const uint16_t* p, float (&o)[8]) {
-  const uint4 v = *reinterpret_cast<const uint4*>(p);
+  const gdsw_u4 v = *as_global<gdsw_u4>(p);
   const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
