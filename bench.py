@@ -131,19 +131,27 @@ def copy_bandwidth(torch, dev, gib=1, reps=5):
     return 2.0 * n * 4 / (ms * 1e-3) / 1e9
 
 
+def kernel_source_sha256(srcname):
+    """Digest of a kernel's source file followed by the device load helpers
+    it includes (vec16.h): a change to either invalidates its counters."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in (srcname, "vec16.h"):
+        h.update(open(os.path.join(ROOT, "paper_2508_04356_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(solve, launches):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary, or None when the kernel source changed since it was measured."""
-    import hashlib
     if solve not in TRAFFIC:
         return None
     name, srcname = TRAFFIC[solve]
     path = os.path.join(ROOT, "profiles", name)
-    src = os.path.join(ROOT, "paper_2508_04356_amd", "csrc", srcname)
     if not os.path.exists(path):
         return None
     kv = dict(line.split(": ", 1) for line in open(path).read().splitlines() if ": " in line)
-    if kv.get("kernel_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+    if kv.get("kernel_source_sha256") != kernel_source_sha256(srcname):
         return None
     if int(kv.get("launches_per_apply", -1)) != launches:
         return None
