@@ -337,14 +337,15 @@ gdsw_status gdsw_autotune(gdsw_ctx* ctx, void* stream, int32_t* chosen, double* 
 
 /* Event timing of the dominant solve kernel.  While enabled, every launch of
  * the level-1 solve kernel in a full apply (the partial-product kernel of
- * GDSW_SOLVE_INVERSE, single- or multi-column, or each sweep step of
- * GDSW_SOLVE_TRIANGULAR) is bracketed by two HIP events on the stream it runs
- * on, up to 8192 launches.  gdsw_kernel_timer(ctx, 1) resets the count and
- * starts; (ctx, 0) stops.  gdsw_kernel_timer_read waits for the last recorded
- * event and returns the summed kernel time (ms), the number of timed launches
- * and the mean algorithmic bytes per launch (a product launch reads every
- * level-1 matrix once: sum of n^2 * element size; a sweep step is charged
- * that sum divided by the steps of one apply). */
+ * GDSW_SOLVE_INVERSE, single- or multi-column, that of GDSW_SOLVE_SYMMETRIC,
+ * or each sweep step of GDSW_SOLVE_TRIANGULAR) is bracketed by two HIP events
+ * on the stream it runs on, up to 16384 launches.  gdsw_kernel_timer(ctx, 1)
+ * resets the count and starts; (ctx, 0) stops.  gdsw_kernel_timer_read waits
+ * for the last recorded event and returns the summed kernel time (ms), the
+ * number of timed launches and the mean algorithmic bytes per launch (a
+ * product launch reads every level-1 matrix once: sum of n^2 * element size,
+ * n (n + 1) / 2 * element size for the symmetric storage; a sweep step is
+ * charged that sum divided by the steps of one apply). */
 gdsw_status gdsw_kernel_timer(gdsw_ctx* ctx, int32_t enable);
 gdsw_status gdsw_kernel_timer_read(gdsw_ctx* ctx, double* total_ms, int64_t* launches, uint64_t* bytes_per_launch);
 

@@ -81,7 +81,7 @@ struct GemvDesc {
 // HIP events around each launch of a set's dominant solve kernel (slot 0),
 // for measuring its average duration inside a timed region.
 struct KernelTimer {
-  static constexpr int CAP = 8192;   // launch pairs recorded before it stops
+  static constexpr int CAP = 16384;  // launch pairs recorded before it stops
   bool on = false;
   int used = 0;
   double bytes = 0.0;                // algorithmic bytes of the recorded launches

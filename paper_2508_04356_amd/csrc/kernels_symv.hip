@@ -4,15 +4,16 @@
 // with J >= I are kept (each tile column-major and contiguous), which halves
 // the bytes of the HBM-bound product.  A stored tile with J > I contributes
 // M_IJ x_J to block row I and M_IJ^T x_I to block row J; a diagonal tile
-// (stored whole) contributes M_II x_I.  A work-group reads a run of tiles
-// of one block row (each a contiguous 32 KB read for FP64) and writes both
-// partial blocks of each (runs of 1 / 2 / 4 / 8 / 16 tiles measured 498 /
-// 495 / 507 / 524 / 544 us at 16^3 on MI355X); a second launch sums them per
-// block row in a fixed order
-// (tiles (I, I), (I, I+1), ... then the transposed tiles (0, I), (1, I), ...),
-// so results are repeatable bit for bit.  Tried and measured slower: a gap
-// between stored tiles (off the 32 KB stride), runs of 3 or 4 tiles, and
-// fewer resident work-groups that each walk many items.
+// (stored whole) contributes M_II x_I.  A work-group reads a run of two
+// tiles of one block row (each a contiguous 32 KB read for FP64) and writes
+// one row partial for the run (block row I) and one column partial per
+// off-diagonal tile (block rows J); a second launch sums them per block row
+// in a fixed order (the runs of row I from the diagonal on, then the
+// transposed tiles (0, I), (1, I), ...), so results are repeatable bit for
+// bit.  Tried and measured slower at 16^3 on MI355X: runs of 1, 3 or 4 tiles
+// (also in FP32 and BF16), staging tiles in LDS, a gap between stored tiles
+// (off the 32 KB stride), and fewer resident work-groups that each walk
+// many items.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -95,7 +96,10 @@ __global__ __launch_bounds__(256) void symv_part_kernel(const GemvDesc* __restri
     if (t < ST) xi[t] = ri < n ? (Acc)xiv : (Acc)0;
     if (t < SYMV_RUN * ST) xj[t / ST][t % ST] = rj < n ? (Acc)xjv : (Acc)0;
   };
-  // products of tile J held in v: row part into rred, transposed part into cred
+  // products of tile J held in v: row part into rred, transposed part into
+  // cred; the row parts of the run's tiles all belong to block row I and are
+  // summed here (in tile order), written once, to the run's first slot
+  double racc = 0.0;
   auto products = [&](int J) {
     const int b = J - J0;
     __syncthreads();  // xi / xj written; the previous tile's reductions read
@@ -125,7 +129,8 @@ __global__ __launch_bounds__(256) void symv_part_kernel(const GemvDesc* __restri
       double s = 0.0;
 #pragma unroll
       for (int g = 0; g < CPT; ++g) s += (double)rred[g][t];
-      prow[(int64_t)p * ST + t] = s;
+      racc += s;
+      if (J == J1 - 1) prow[(int64_t)p0 * ST + t] = racc;
     } else if (t < 2 * ST && J > I) {
       const int c = t - ST;
       double s = 0.0;
@@ -151,7 +156,8 @@ __global__ __launch_bounds__(256) void symv_part_kernel(const GemvDesc* __restri
   products(J1 - 1);
 }
 
-// Item (g, I, P0, nt): x_g[64 I + l] = sum_{J >= I} prow(I, J)[l] + sum_{K < I} pcol(K, I)[l].
+// Item (g, I, P0, nt): x_g[64 I + l] = sum over the runs of block row I of
+// their row partial + sum_{K < I} pcol(K, I)[l].
 __global__ __launch_bounds__(64) void symv_sum_kernel(const GemvDesc* __restrict__ desc,
                                                       const int4* __restrict__ items,
                                                       const double* __restrict__ prow,
@@ -161,7 +167,7 @@ __global__ __launch_bounds__(64) void symv_sum_kernel(const GemvDesc* __restrict
   if (want && !want[g]) return;
   const int l = threadIdx.x;
   double s = 0.0;
-  for (int J = I; J < nt; ++J) s += prow[(P0 + tile_index(I, J, nt)) * ST + l];
+  for (int J = I; J < nt; J += SYMV_RUN) s += prow[(P0 + tile_index(I, J, nt)) * ST + l];  // one per run
   for (int K = 0; K < I; ++K) s += pcol[(P0 + tile_index(K, I, nt)) * ST + l];
   const int r = ST * I + l;
   if (r < desc[g].n) desc[g].x[r] = s;
