@@ -157,20 +157,32 @@ __global__ __launch_bounds__(256) void symv_part_kernel(const GemvDesc* __restri
 }
 
 // Item (g, I, P0, nt): x_g[64 I + l] = sum over the runs of block row I of
-// their row partial + sum_{K < I} pcol(K, I)[l].
-__global__ __launch_bounds__(64) void symv_sum_kernel(const GemvDesc* __restrict__ desc,
-                                                      const int4* __restrict__ items,
-                                                      const double* __restrict__ prow,
-                                                      const double* __restrict__ pcol, const int32_t* __restrict__ want) {
+// their row partial + sum_{K < I} pcol(K, I)[l].  The terms, in the order
+// (runs of row I from the diagonal on, then K = 0 .. I - 1), are dealt to
+// the four waves in turn; each wave sums its terms in order and the four
+// sums are added in wave order, so the result is repeatable bit for bit.
+__global__ __launch_bounds__(256) void symv_sum_kernel(const GemvDesc* __restrict__ desc,
+                                                       const int4* __restrict__ items,
+                                                       const double* __restrict__ prow,
+                                                       const double* __restrict__ pcol, const int32_t* __restrict__ want) {
+  __shared__ double red[4][ST];
   const int4 item = items[blockIdx.x];
   const int g = item.x, I = item.y, P0 = item.z, nt = item.w;
-  if (want && !want[g]) return;
-  const int l = threadIdx.x;
+  if (want && !want[g]) return;  // uniform over the work-group
+  const int l = threadIdx.x % ST, w = threadIdx.x / ST;
+  const int na = (nt - I + SYMV_RUN - 1) / SYMV_RUN;  // runs of row I
   double s = 0.0;
-  for (int J = I; J < nt; J += SYMV_RUN) s += prow[(P0 + tile_index(I, J, nt)) * ST + l];  // one per run
-  for (int K = 0; K < I; ++K) s += pcol[(P0 + tile_index(K, I, nt)) * ST + l];
-  const int r = ST * I + l;
-  if (r < desc[g].n) desc[g].x[r] = s;
+  for (int q = w; q < na + I; q += 4) {
+    const int64_t slot = q < na ? P0 + tile_index(I, I + SYMV_RUN * q, nt) : P0 + tile_index(q - na, I, nt);
+    s += (q < na ? prow : pcol)[slot * ST + l];
+  }
+  red[w][l] = s;
+  __syncthreads();
+  if (w == 0) {
+    const double x = ((red[0][l] + red[1][l]) + red[2][l]) + red[3][l];
+    const int r = ST * I + l;
+    if (r < desc[g].n) desc[g].x[r] = x;
+  }
 }
 
 // Upper tiles of npad x npad column-major FP64 matrices, converted to the
@@ -211,7 +223,7 @@ void symv_launch(const GemvDesc* desc, const FactorSet::GemvPlan& G, double* par
     GDSW_HIP(hipEventRecord(tm->ev[2 * tm->used++ + 1], st));
     tm->bytes += bytes;
   }
-  symv_sum_kernel<<<G.n2, 64, 0, st>>>(desc, G.d_items2, prow, pcol, want);
+  symv_sum_kernel<<<G.n2, 256, 0, st>>>(desc, G.d_items2, prow, pcol, want);
 }
 
 }  // namespace
