@@ -154,22 +154,25 @@ __global__ __launch_bounds__(256) void restrict_kernel(int nc_total, CoarseView 
   if (tid == 0) out[out_pos ? out_pos[c] : c] = t;
 }
 
-// z[I_i[k]] += sum_j Phi_I^(i)[k, j] y0[C_i[j]]: one thread per interior
-// row, the column-major Phi_I read contiguously across the threads.
+// z[I_i[k]] += sum_j Phi_I^(i)[k, j] y0[C_i[j]]: 64 interior rows per
+// work-group (lanes = rows, so the column-major Phi_I is read contiguously);
+// wave w takes the columns j = w, w + 4, ... in ascending order with eight
+// loads in flight, and the four sums are added in wave order.
 __global__ __launch_bounds__(256) void phi_prolong_kernel(CoarseView cv, const double* __restrict__ w,
                                                           const double* __restrict__ y0,
                                                           const int32_t* __restrict__ y0_pos,
                                                           double* __restrict__ z) {
   // the subdomain's coarse values are gathered into LDS once (in parallel),
-  // 256 columns at a time; then each row sums over the columns in order
+  // 256 columns at a time
   __shared__ double yv[256];
+  __shared__ double red[4][64];
   const int i = blockIdx.y;
   const int ib = cv.I_ptr[i], ni = cv.I_ptr[i + 1] - ib;
-  const int k0 = blockIdx.x * 256;
+  const int k0 = blockIdx.x * 64;
   if (k0 >= ni) return;  // uniform over the work-group
-  const int k = k0 + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int cb = cv.C_ptr[i], nc = cv.C_ptr[i + 1] - cb;
-  const double* ph = cv.phi_cm + cv.phi_off[i] + min(k, ni - 1);
+  const double* ph = cv.phi_cm + cv.phi_off[i] + min(k0 + lane, ni - 1);
   double c = 0.0;
   for (int j0 = 0; j0 < nc; j0 += 256) {
     const int jn = min(256, nc - j0);
@@ -179,11 +182,20 @@ __global__ __launch_bounds__(256) void phi_prolong_kernel(CoarseView cv, const d
       yv[threadIdx.x] = y0_pos ? w[y0_pos[cc]] : y0[cc];
     }
     __syncthreads();
-    for (int j = 0; j < jn; ++j) c = fma(ph[(int64_t)(j0 + j) * ni], yv[j], c);
+    for (int j = wave; j < jn; j += 32) {
+      double pv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) pv[u] = ph[(int64_t)(j0 + min(j + 4 * u, jn - 1)) * ni];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) c = j + 4 * u < jn ? fma(pv[u], yv[min(j + 4 * u, jn - 1)], c) : c;
+    }
   }
-  if (k < ni) {
-    const int32_t d = cv.I_idx[ib + k];
-    z[d] = z[d] + c;
+  red[wave][lane] = c;
+  __syncthreads();
+  if (wave == 0 && k0 + lane < ni) {
+    const double v = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+    const int32_t d = cv.I_idx[ib + k0 + lane];
+    z[d] = z[d] + v;
   }
 }
 
@@ -614,7 +626,7 @@ void scatter_prolong(int64_t n, const int32_t* inv_ptr, const int64_t* inv_pos, 
   if (n == 0) return;
   const int split = nsub > 0 && max_ni > 0;
   scatter_prolong_kernel<<<grid_for(n), 256, 0, st>>>(n, inv_ptr, inv_pos, w, cv, y0, y0_pos, z, split);
-  if (split) phi_prolong_kernel<<<dim3((max_ni + 255) / 256, nsub), 256, 0, st>>>(cv, w, y0, y0_pos, z);
+  if (split) phi_prolong_kernel<<<dim3((max_ni + 63) / 64, nsub), 256, 0, st>>>(cv, w, y0, y0_pos, z);
 }
 
 void restrict_coarse(int nc, const CoarseView& cv, const double* r, double* out, const int32_t* out_pos,
