@@ -119,6 +119,10 @@ void cols_dot(const double* V, int64_t ldv, int ncols, const double* w, int64_t 
               int nblocks, double* out, hipStream_t st);
 void gemv_sub(const double* V, int64_t ldv, int ncols, const double* h, double* w, int64_t n,
               hipStream_t st);
+// w -= V h followed by cols_dot(V, w) (or, with self, cols_dot(w, w)) into
+// out, in two launches instead of four, with the same results bit for bit
+void sub_dots(const double* V, int64_t ldv, int ncols, const double* h, double* w, int64_t n, double* part,
+              int nblocks, double* out, bool self, hipStream_t st);
 void gemv_add(const double* V, int64_t ldv, int ncols, const double* y, double* x, int64_t n,
               hipStream_t st);
 int cols_dot_blocks(int64_t n);

@@ -538,6 +538,60 @@ __global__ void gemv_sub_kernel(const double* __restrict__ V, int64_t ldv, int n
     w[r] -= row_combination(V, ldv, ncols, h, r);
 }
 
+// One CGS2 pass fused with the next dot products: rows [r0, r0 + 256) of
+// block b (one per thread) get w[r] -= sum_j V[r, j] h[j] exactly as in
+// gemv_sub_kernel; the new values then give part[b * nd + j] = sum over the
+// block's rows of V[:, j] * w (nd = ncols), or of w * w (self, nd = 1),
+// with the lane/row mapping and shuffle tree of cols_dot_partial_kernel, so
+// the results equal those of the two separate launches bit for bit.
+static_assert(DOT_CHUNK == 256, "one row per thread");
+__global__ __launch_bounds__(256) void sub_dots_partial_kernel(const double* __restrict__ V, int64_t ldv, int ncols,
+                                                              const double* __restrict__ h, double* __restrict__ w,
+                                                              int64_t n, int self, double* __restrict__ part) {
+  __shared__ double wsh[DOT_CHUNK];
+  const int b = blockIdx.x;
+  const int64_t r0 = (int64_t)b * DOT_CHUNK;
+  const int64_t r1 = min<int64_t>(n, r0 + DOT_CHUNK);
+  const int64_t r = r0 + threadIdx.x;
+  double wn = 0.0;
+  if (r < r1) {
+    wn = w[r] - row_combination(V, ldv, ncols, h, r);
+    w[r] = wn;
+  }
+  wsh[threadIdx.x] = wn;
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double wr[DOT_CHUNK / 64];
+#pragma unroll
+  for (int q = 0; q < DOT_CHUNK / 64; ++q) wr[q] = wsh[q * 64 + lane];
+  const int nd = self ? 1 : ncols;
+  for (int j0 = wave; j0 < nd; j0 += 4 * COLS_AT_ONCE) {
+    double vv[COLS_AT_ONCE][DOT_CHUNK / 64];
+#pragma unroll
+    for (int c = 0; c < COLS_AT_ONCE; ++c) {
+      const double* v = V + (int64_t)min(j0 + 4 * c, nd - 1) * ldv;
+#pragma unroll
+      for (int q = 0; q < DOT_CHUNK / 64; ++q) {
+        const int64_t rq = r0 + q * 64 + lane;
+        vv[c][q] = self ? wr[q] : (rq < r1 ? v[rq] : 0.0);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < COLS_AT_ONCE; ++c) {
+      const int j = j0 + 4 * c;
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < DOT_CHUNK / 64; ++q) {
+        const int64_t rq = r0 + q * 64 + lane;
+        if (rq < r1) s = fma(vv[c][q], wr[q], s);
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+      if (lane == 0 && j < nd) part[(int64_t)b * nd + j] = s;
+    }
+  }
+}
+
 __global__ void gemv_add_kernel(const double* __restrict__ V, int64_t ldv, int ncols, const double* __restrict__ y,
                                 double* __restrict__ x, int64_t n) {
   for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
@@ -690,6 +744,15 @@ void cols_dot(const double* V, int64_t ldv, int ncols, const double* w, int64_t 
 
 void gemv_sub(const double* V, int64_t ldv, int ncols, const double* h, double* w, int64_t n, hipStream_t st) {
   gemv_sub_kernel<<<grid_for(n), 256, 0, st>>>(V, ldv, ncols, h, w, n);
+}
+
+void sub_dots(const double* V, int64_t ldv, int ncols, const double* h, double* w, int64_t n, double* part,
+              int nblocks, double* out, bool self, hipStream_t st) {
+  if (n == 0) return;
+  if ((int64_t)nblocks * DOT_CHUNK < n) throw StatusError{1, "sub_dots: partial blocks do not cover the rows"};
+  sub_dots_partial_kernel<<<nblocks, 256, 0, st>>>(V, ldv, ncols, h, w, n, self ? 1 : 0, part);
+  const int nd = self ? 1 : ncols;
+  cols_dot_final_kernel<<<nd, 64, 0, st>>>(part, nblocks, nd, out);
 }
 
 void gemv_add(const double* V, int64_t ldv, int ncols, const double* y, double* x, int64_t n, hipStream_t st) {

@@ -261,11 +261,10 @@ FgmresResult fgmres(Context& ctx, const double* b, double* x, double rtol, int r
     double* w = ctx.d_t2;
     apply_precond(ctx, vj, zj, st);
     spmv(ctx, zj, w, st);
+    // CGS2: two projections, each fused with the dot products that follow it
     cols_dot(V, ldv, j + 1, w, n, ctx.d_part, nb, ctx.d_hv, st);
-    gemv_sub(V, ldv, j + 1, ctx.d_hv, w, n, st);
-    cols_dot(V, ldv, j + 1, w, n, ctx.d_part, nb, ctx.d_hv + restart + 1, st);
-    gemv_sub(V, ldv, j + 1, ctx.d_hv + restart + 1, w, n, st);
-    cols_dot(w, ldv, 1, w, n, ctx.d_part, nb, S + 4, st);
+    sub_dots(V, ldv, j + 1, ctx.d_hv, w, n, ctx.d_part, nb, ctx.d_hv + restart + 1, false, st);
+    sub_dots(V, ldv, j + 1, ctx.d_hv + restart + 1, w, n, ctx.d_part, nb, S + 4, true, st);
     arnoldi_finish_kernel<<<1, 1, 0, st>>>(j, restart, ctx.d_hv, ctx.d_hv + restart + 1, ctx.d_H, ctx.d_cs,
                                            ctx.d_sn, ctx.d_g, S);
     scale_div_kernel<<<grid_n(n), 256, 0, st>>>(n, w, S, 3, V + (int64_t)(j + 1) * ldv);
@@ -430,10 +429,8 @@ std::vector<FgmresResult> fgmres_batch(Batch& bt, const double* const* bvec, dou
         apply_post(c, zj, ls);
         spmv(c, zj, w, ls);
         cols_dot(V, c.ldv, j + 1, w, n, c.d_part, c.n_part_blocks, c.d_hv, ls);
-        gemv_sub(V, c.ldv, j + 1, c.d_hv, w, n, ls);
-        cols_dot(V, c.ldv, j + 1, w, n, c.d_part, c.n_part_blocks, c.d_hv + restart + 1, ls);
-        gemv_sub(V, c.ldv, j + 1, c.d_hv + restart + 1, w, n, ls);
-        cols_dot(w, c.ldv, 1, w, n, c.d_part, c.n_part_blocks, c.d_scal + 4, ls);
+        sub_dots(V, c.ldv, j + 1, c.d_hv, w, n, c.d_part, c.n_part_blocks, c.d_hv + restart + 1, false, ls);
+        sub_dots(V, c.ldv, j + 1, c.d_hv + restart + 1, w, n, c.d_part, c.n_part_blocks, c.d_scal + 4, true, ls);
         arnoldi_finish_kernel<<<1, 1, 0, ls>>>(j, restart, c.d_hv, c.d_hv + restart + 1, c.d_H, c.d_cs, c.d_sn,
                                                c.d_g, c.d_scal);
         scale_div_kernel<<<grid_n(n), 256, 0, ls>>>(n, w, c.d_scal, 3, V + (int64_t)(j + 1) * c.ldv);
