@@ -46,8 +46,24 @@ __global__ __launch_bounds__(256) void spmv_kernel(int64_t nrows, const int32_t*
   const int l = threadIdx.x & 15;
   double s = 0.0;
   if (row < nrows) {
+    // lane l takes the nonzeros b + l, b + l + 16, ... in ascending order,
+    // eight at a time: their indices and values (clamped into the row), then
+    // the eight x entries, are loaded before any product
     const int b = rowptr[row], e = rowptr[row + 1];
-    for (int k = b + l; k < e; k += 16) s = fma(val[k], x[col[k]], s);
+    for (int k0 = b + l; k0 < e; k0 += 128) {
+      int32_t c[8];
+      double v[8], xv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = min(k0 + 16 * u, e - 1);
+        c[u] = col[k];
+        v[u] = val[k];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) xv[u] = x[c[u]];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s = k0 + 16 * u < e ? fma(v[u], xv[u], s) : s;
+    }
   }
 #pragma unroll
   for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
