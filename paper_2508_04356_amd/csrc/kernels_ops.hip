@@ -128,8 +128,20 @@ __global__ void scatter_prolong_kernel(int64_t n, const int32_t* __restrict__ in
                                        CoarseView cv, const double* __restrict__ y0,
                                        const int32_t* __restrict__ y0_pos, double* __restrict__ z, int split) {
   for (int64_t d = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; d < n; d += (int64_t)gridDim.x * blockDim.x) {
+    // the local copies (ascending subdomain), four positions then four
+    // values loaded before the sum
     double s = 0.0;
-    for (int e = inv_ptr[d]; e < inv_ptr[d + 1]; ++e) s += w[inv_pos[e]];
+    const int e0 = inv_ptr[d], e1 = inv_ptr[d + 1];
+    for (int e = e0; e < e1; e += 4) {
+      int64_t pos[4];
+      double wv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) pos[u] = inv_pos[min(e + u, e1 - 1)];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) wv[u] = w[pos[u]];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) s = e + u < e1 ? s + wv[u] : s;
+    }
     double c = 0.0;
     const int32_t gc = cv.gamma_col[d];
     if (gc >= 0) {
@@ -223,23 +235,23 @@ __global__ __launch_bounds__(256) void phi_t_kernel(CoarseView cv, const double*
   const int i = cv.cs_sub[e], lc = cv.cs_lc[e];
   const int ib = cv.I_ptr[i], ni = cv.I_ptr[i + 1] - ib;
   const double* ph = cv.phi_cm + cv.phi_off[i] + (int64_t)lc * ni;
-  // thread rows tid, tid + 256, ... in ascending order; four rows' loads
-  // (clamped into range) are issued before their products
+  // thread rows tid, tid + 256, ... in ascending order; eight rows' loads
+  // (clamped into range) are issued before their products, so an interior
+  // set of up to 2048 rows takes one round of dependent loads
   double s = 0.0;
-  for (int k0 = 0; k0 < ni; k0 += 1024) {
-    double pv[4], rv[4];
-    int32_t idx[4];
+  for (int k0 = 0; k0 < ni; k0 += 2048) {
+    double pv[8], rv[8];
+    int32_t idx[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 8; ++u) {
       const int kc = min(k0 + (int)threadIdx.x + 256 * u, ni - 1);
       idx[u] = cv.I_idx[ib + kc];
       pv[u] = ph[kc];
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) rv[u] = r[idx[u]];
+    for (int u = 0; u < 8; ++u) rv[u] = r[idx[u]];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (k0 + (int)threadIdx.x + 256 * u < ni) s = fma(pv[u], rv[u], s);
+    for (int u = 0; u < 8; ++u) s = k0 + (int)threadIdx.x + 256 * u < ni ? fma(pv[u], rv[u], s) : s;
   }
   const double v = block_sum<256>(s, sh);
   if (threadIdx.x == 0) t[e] = v;
