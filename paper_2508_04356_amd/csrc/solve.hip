@@ -79,6 +79,69 @@ __global__ void arnoldi_finish_kernel(int j, int restart, const double* __restri
   scal[2] = fabs(g[j + 1]) / bnorm;
 }
 
+inline int grid_n(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(65536, (n + 255) / 256)); }
+
+// arnoldi_finish_kernel and scale_div_kernel(n, w, scal, 3, v) in one
+// launch: every work-group scales w into the next basis vector by
+// ||w|| = sqrt(scal[4]); the first also finishes column j of H, its threads
+// loading the column and the previous rotations into LDS together and one
+// thread applying the rotations in order (the same operations as
+// arnoldi_finish_kernel).  For restart <= ARN_LDS.
+constexpr int ARN_LDS = 512;
+__global__ __launch_bounds__(256) void arnoldi_scale_kernel(int j, int restart, const double* __restrict__ h1,
+                                                            const double* __restrict__ h2, double* __restrict__ H,
+                                                            double* __restrict__ cs, double* __restrict__ sn,
+                                                            double* __restrict__ g, double* __restrict__ scal,
+                                                            int64_t n, const double* __restrict__ w,
+                                                            double* __restrict__ v) {
+  __shared__ double cl[ARN_LDS + 2], cs_l[ARN_LDS], sn_l[ARN_LDS];
+  const double hn = sqrt(scal[4]);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    v[i] = hn != 0.0 ? w[i] / hn : 0.0;
+  if (blockIdx.x != 0) return;  // uniform over the work-group
+  const int t = threadIdx.x;
+  for (int i = t; i <= j; i += 256) cl[i] = h1[i] + h2[i];
+  for (int i = t; i < j; i += 256) {
+    cs_l[i] = cs[i];
+    sn_l[i] = sn[i];
+  }
+  __syncthreads();
+  if (t == 0) {
+    cl[j + 1] = hn;
+    scal[3] = hn;
+    for (int i = 0; i < j; ++i) {
+      const double u = cs_l[i] * cl[i] + sn_l[i] * cl[i + 1];
+      cl[i + 1] = -sn_l[i] * cl[i] + cs_l[i] * cl[i + 1];
+      cl[i] = u;
+    }
+    const double rho = hypot(cl[j], cl[j + 1]);
+    const double c = cl[j] / rho, sj = cl[j + 1] / rho;
+    cs[j] = c;
+    sn[j] = sj;
+    cl[j] = rho;
+    cl[j + 1] = 0.0;
+    const double gj = g[j];
+    g[j + 1] = -sj * gj;
+    g[j] = c * gj;
+    scal[2] = fabs(g[j + 1]) / scal[5];
+  }
+  __syncthreads();
+  const int ldh = restart + 1;
+  for (int i = t; i <= j + 1; i += 256) H[(int64_t)j * ldh + i] = cl[i];
+}
+
+// column j of the Arnoldi process after the projections: H, rotations, g,
+// residual estimate, and the next basis vector
+void arnoldi_step(int j, int restart, const double* h1, const double* h2, double* H, double* cs, double* sn,
+                  double* g, double* scal, int64_t n, const double* w, double* v, hipStream_t st) {
+  if (restart <= ARN_LDS) {
+    arnoldi_scale_kernel<<<grid_n(n), 256, 0, st>>>(j, restart, h1, h2, H, cs, sn, g, scal, n, w, v);
+  } else {
+    arnoldi_finish_kernel<<<1, 1, 0, st>>>(j, restart, h1, h2, H, cs, sn, g, scal);
+    scale_div_kernel<<<grid_n(n), 256, 0, st>>>(n, w, scal, 3, v);
+  }
+}
+
 // back substitution y = H[:k,:k]^-1 g[:k] into y
 __global__ void back_subst_kernel(int k, int restart, const double* __restrict__ H, const double* __restrict__ g,
                                   double* __restrict__ y) {
@@ -90,7 +153,6 @@ __global__ void back_subst_kernel(int k, int restart, const double* __restrict__
   }
 }
 
-inline int grid_n(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(65536, (n + 255) / 256)); }
 
 void drop_graphs(Context& ctx) {
   for (hipGraphExec_t& e : ctx.graphs.exec)
@@ -265,9 +327,8 @@ FgmresResult fgmres(Context& ctx, const double* b, double* x, double rtol, int r
     cols_dot(V, ldv, j + 1, w, n, ctx.d_part, nb, ctx.d_hv, st);
     sub_dots(V, ldv, j + 1, ctx.d_hv, w, n, ctx.d_part, nb, ctx.d_hv + restart + 1, false, st);
     sub_dots(V, ldv, j + 1, ctx.d_hv + restart + 1, w, n, ctx.d_part, nb, S + 4, true, st);
-    arnoldi_finish_kernel<<<1, 1, 0, st>>>(j, restart, ctx.d_hv, ctx.d_hv + restart + 1, ctx.d_H, ctx.d_cs,
-                                           ctx.d_sn, ctx.d_g, S);
-    scale_div_kernel<<<grid_n(n), 256, 0, st>>>(n, w, S, 3, V + (int64_t)(j + 1) * ldv);
+    arnoldi_step(j, restart, ctx.d_hv, ctx.d_hv + restart + 1, ctx.d_H, ctx.d_cs, ctx.d_sn, ctx.d_g, S, n, w,
+                 V + (int64_t)(j + 1) * ldv, st);
     GDSW_HIP(hipMemcpyAsync(ctx.h_pinned, S + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
   };
   int it = 0;
@@ -431,9 +492,8 @@ std::vector<FgmresResult> fgmres_batch(Batch& bt, const double* const* bvec, dou
         cols_dot(V, c.ldv, j + 1, w, n, c.d_part, c.n_part_blocks, c.d_hv, ls);
         sub_dots(V, c.ldv, j + 1, c.d_hv, w, n, c.d_part, c.n_part_blocks, c.d_hv + restart + 1, false, ls);
         sub_dots(V, c.ldv, j + 1, c.d_hv + restart + 1, w, n, c.d_part, c.n_part_blocks, c.d_scal + 4, true, ls);
-        arnoldi_finish_kernel<<<1, 1, 0, ls>>>(j, restart, c.d_hv, c.d_hv + restart + 1, c.d_H, c.d_cs, c.d_sn,
-                                               c.d_g, c.d_scal);
-        scale_div_kernel<<<grid_n(n), 256, 0, ls>>>(n, w, c.d_scal, 3, V + (int64_t)(j + 1) * c.ldv);
+        arnoldi_step(j, restart, c.d_hv, c.d_hv + restart + 1, c.d_H, c.d_cs, c.d_sn, c.d_g, c.d_scal, n, w,
+                     V + (int64_t)(j + 1) * c.ldv, ls);
         GDSW_HIP(hipMemcpyAsync(hp + 2 * k, c.d_scal + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, ls));
       }
       batch_join(bt, st);
