@@ -120,11 +120,14 @@ void cols_dot(const double* V, int64_t ldv, int ncols, const double* w, int64_t 
 void gemv_sub(const double* V, int64_t ldv, int ncols, const double* h, double* w, int64_t n,
               hipStream_t st);
 // w -= V h followed by cols_dot(V, w) (or, with self, cols_dot(w, w)) into
-// out, in two launches instead of four, with the same results bit for bit
+// out, in two launches instead of four, with the same results bit for bit;
+// with out null only the partial blocks are written (nblocks x columns in
+// part), for a consumer that finishes the sums itself (cols_dot_finish)
 void sub_dots(const double* V, int64_t ldv, int ncols, const double* h, double* w, int64_t n, double* part,
               int nblocks, double* out, bool self, hipStream_t st);
 void gemv_add(const double* V, int64_t ldv, int ncols, const double* y, double* x, int64_t n,
               hipStream_t st);
 int cols_dot_blocks(int64_t n);
+void cols_dot_finish(const double* part, int nblocks, int ncols, double* out, hipStream_t st);
 
 }  // namespace gdsw

@@ -779,8 +779,11 @@ void sub_dots(const double* V, int64_t ldv, int ncols, const double* h, double* 
   if (n == 0) return;
   if ((int64_t)nblocks * DOT_CHUNK < n) throw StatusError{1, "sub_dots: partial blocks do not cover the rows"};
   sub_dots_partial_kernel<<<nblocks, 256, 0, st>>>(V, ldv, ncols, h, w, n, self ? 1 : 0, part);
-  const int nd = self ? 1 : ncols;
-  cols_dot_final_kernel<<<nd, 64, 0, st>>>(part, nblocks, nd, out);
+  if (out) cols_dot_final_kernel<<<self ? 1 : ncols, 64, 0, st>>>(part, nblocks, self ? 1 : ncols, out);
+}
+
+void cols_dot_finish(const double* part, int nblocks, int ncols, double* out, hipStream_t st) {
+  cols_dot_final_kernel<<<ncols, 64, 0, st>>>(part, nblocks, ncols, out);
 }
 
 void gemv_add(const double* V, int64_t ldv, int ncols, const double* y, double* x, int64_t n, hipStream_t st) {

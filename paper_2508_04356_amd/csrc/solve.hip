@@ -81,9 +81,12 @@ __global__ void arnoldi_finish_kernel(int j, int restart, const double* __restri
 
 inline int grid_n(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(65536, (n + 255) / 256)); }
 
-// arnoldi_finish_kernel and scale_div_kernel(n, w, scal, 3, v) in one
-// launch: every work-group scales w into the next basis vector by
-// ||w|| = sqrt(scal[4]); the first also finishes column j of H, its threads
+// cols_dot_final_kernel of ||w||^2, arnoldi_finish_kernel and
+// scale_div_kernel(n, w, scal, 3, v) in one launch: every work-group sums the
+// partial blocks of ||w||^2 (one wave, lane-strided, xor tree: the same sum
+// as cols_dot_final_kernel) and scales w into the next basis vector by
+// ||w||; the first also stores ||w||^2 in scal[4] and finishes column j of
+// H, its threads
 // loading the column and the previous rotations into LDS together and one
 // thread applying the rotations in order (the same operations as
 // arnoldi_finish_kernel).  For restart <= ARN_LDS.
@@ -92,10 +95,20 @@ __global__ __launch_bounds__(256) void arnoldi_scale_kernel(int j, int restart, 
                                                             const double* __restrict__ h2, double* __restrict__ H,
                                                             double* __restrict__ cs, double* __restrict__ sn,
                                                             double* __restrict__ g, double* __restrict__ scal,
+                                                            const double* __restrict__ part, int nblocks,
                                                             int64_t n, const double* __restrict__ w,
                                                             double* __restrict__ v) {
   __shared__ double cl[ARN_LDS + 2], cs_l[ARN_LDS], sn_l[ARN_LDS];
-  const double hn = sqrt(scal[4]);
+  __shared__ double ww;
+  if (threadIdx.x < 64) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 64) s += part[b];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (threadIdx.x == 0) ww = s;
+  }
+  __syncthreads();
+  const double hn = sqrt(ww);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     v[i] = hn != 0.0 ? w[i] / hn : 0.0;
   if (blockIdx.x != 0) return;  // uniform over the work-group
@@ -107,6 +120,7 @@ __global__ __launch_bounds__(256) void arnoldi_scale_kernel(int j, int restart, 
   }
   __syncthreads();
   if (t == 0) {
+    scal[4] = ww;
     cl[j + 1] = hn;
     scal[3] = hn;
     for (int i = 0; i < j; ++i) {
@@ -130,13 +144,16 @@ __global__ __launch_bounds__(256) void arnoldi_scale_kernel(int j, int restart, 
   for (int i = t; i <= j + 1; i += 256) H[(int64_t)j * ldh + i] = cl[i];
 }
 
-// column j of the Arnoldi process after the projections: H, rotations, g,
-// residual estimate, and the next basis vector
+// column j of the Arnoldi process after the projections (part: the
+// partial blocks of ||w||^2): H, rotations, g, residual estimate, and the
+// next basis vector
 void arnoldi_step(int j, int restart, const double* h1, const double* h2, double* H, double* cs, double* sn,
-                  double* g, double* scal, int64_t n, const double* w, double* v, hipStream_t st) {
+                  double* g, double* scal, const double* part, int nblocks, int64_t n, const double* w, double* v,
+                  hipStream_t st) {
   if (restart <= ARN_LDS) {
-    arnoldi_scale_kernel<<<grid_n(n), 256, 0, st>>>(j, restart, h1, h2, H, cs, sn, g, scal, n, w, v);
+    arnoldi_scale_kernel<<<grid_n(n), 256, 0, st>>>(j, restart, h1, h2, H, cs, sn, g, scal, part, nblocks, n, w, v);
   } else {
+    cols_dot_finish(part, nblocks, 1, scal + 4, st);
     arnoldi_finish_kernel<<<1, 1, 0, st>>>(j, restart, h1, h2, H, cs, sn, g, scal);
     scale_div_kernel<<<grid_n(n), 256, 0, st>>>(n, w, scal, 3, v);
   }
@@ -326,9 +343,9 @@ FgmresResult fgmres(Context& ctx, const double* b, double* x, double rtol, int r
     // CGS2: two projections, each fused with the dot products that follow it
     cols_dot(V, ldv, j + 1, w, n, ctx.d_part, nb, ctx.d_hv, st);
     sub_dots(V, ldv, j + 1, ctx.d_hv, w, n, ctx.d_part, nb, ctx.d_hv + restart + 1, false, st);
-    sub_dots(V, ldv, j + 1, ctx.d_hv + restart + 1, w, n, ctx.d_part, nb, S + 4, true, st);
-    arnoldi_step(j, restart, ctx.d_hv, ctx.d_hv + restart + 1, ctx.d_H, ctx.d_cs, ctx.d_sn, ctx.d_g, S, n, w,
-                 V + (int64_t)(j + 1) * ldv, st);
+    sub_dots(V, ldv, j + 1, ctx.d_hv + restart + 1, w, n, ctx.d_part, nb, nullptr, true, st);
+    arnoldi_step(j, restart, ctx.d_hv, ctx.d_hv + restart + 1, ctx.d_H, ctx.d_cs, ctx.d_sn, ctx.d_g, S, ctx.d_part,
+                 nb, n, w, V + (int64_t)(j + 1) * ldv, st);
     GDSW_HIP(hipMemcpyAsync(ctx.h_pinned, S + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
   };
   int it = 0;
@@ -491,9 +508,9 @@ std::vector<FgmresResult> fgmres_batch(Batch& bt, const double* const* bvec, dou
         spmv(c, zj, w, ls);
         cols_dot(V, c.ldv, j + 1, w, n, c.d_part, c.n_part_blocks, c.d_hv, ls);
         sub_dots(V, c.ldv, j + 1, c.d_hv, w, n, c.d_part, c.n_part_blocks, c.d_hv + restart + 1, false, ls);
-        sub_dots(V, c.ldv, j + 1, c.d_hv + restart + 1, w, n, c.d_part, c.n_part_blocks, c.d_scal + 4, true, ls);
-        arnoldi_step(j, restart, c.d_hv, c.d_hv + restart + 1, c.d_H, c.d_cs, c.d_sn, c.d_g, c.d_scal, n, w,
-                     V + (int64_t)(j + 1) * c.ldv, ls);
+        sub_dots(V, c.ldv, j + 1, c.d_hv + restart + 1, w, n, c.d_part, c.n_part_blocks, nullptr, true, ls);
+        arnoldi_step(j, restart, c.d_hv, c.d_hv + restart + 1, c.d_H, c.d_cs, c.d_sn, c.d_g, c.d_scal, c.d_part,
+                     c.n_part_blocks, n, w, V + (int64_t)(j + 1) * c.ldv, ls);
         GDSW_HIP(hipMemcpyAsync(hp + 2 * k, c.d_scal + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, ls));
       }
       batch_join(bt, st);
