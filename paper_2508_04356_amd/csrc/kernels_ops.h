@@ -48,8 +48,11 @@ void scatter_prolong(int64_t n, const int32_t* inv_ptr, const int64_t* inv_pos, 
 // out[pos[c]] = (Phi^T r)[c].  With t (n_pairs doubles, one per (subdomain,
 // local column) pair) the interior part is first reduced per pair, then
 // assembled per column in ascending subdomain order.
+// With gcount > 0 the same launch also performs gather(gcount, gidx, r, gdst)
+// (before the restriction is assembled).
 void restrict_coarse(int nc, const CoarseView& cv, const double* r, double* out, const int32_t* out_pos,
-                     hipStream_t st, int n_pairs = 0, double* t = nullptr);
+                     hipStream_t st, int n_pairs = 0, double* t = nullptr, int64_t gcount = 0,
+                     const int32_t* gidx = nullptr, double* gdst = nullptr);
 void phi_rhs(int64_t total_I, const CoarseView& cv, const int32_t* rowptr, const int32_t* col, const double* val,
              double* B, hipStream_t st);
 void phi_transpose(int64_t total_I, const CoarseView& cv, const double* cm, double* rm, hipStream_t st);

@@ -228,10 +228,21 @@ __global__ __launch_bounds__(256) void phi_prolong_kernel(CoarseView cv, const d
 }
 
 // t[e] = Phi_I^(i)[:, lc]^T r[I_i] for every (subdomain, local column) pair e
+// Work-groups n_pairs and up (when gcount > 0) copy the local restrictions
+// instead, as gather_kernel does: dst[p] = r[gidx[p]] (0 where gidx < 0).
 __global__ __launch_bounds__(256) void phi_t_kernel(CoarseView cv, const double* __restrict__ r,
-                                                    double* __restrict__ t) {
+                                                    double* __restrict__ t, int n_pairs, int64_t gcount,
+                                                    const int32_t* __restrict__ gidx, double* __restrict__ gdst) {
   __shared__ double sh[256];
   const int e = blockIdx.x;
+  if (e >= n_pairs) {  // uniform over the work-group
+    const int64_t nb = (int64_t)gridDim.x - n_pairs;
+    for (int64_t p = (int64_t)(e - n_pairs) * blockDim.x + threadIdx.x; p < gcount; p += nb * blockDim.x) {
+      const int32_t g = gidx[p];
+      gdst[p] = g >= 0 ? r[g] : 0.0;
+    }
+    return;
+  }
   const int i = cv.cs_sub[e], lc = cv.cs_lc[e];
   const int ib = cv.I_ptr[i], ni = cv.I_ptr[i + 1] - ib;
   const double* ph = cv.phi_cm + cv.phi_off[i] + (int64_t)lc * ni;
@@ -712,12 +723,17 @@ void scatter_prolong(int64_t n, const int32_t* inv_ptr, const int64_t* inv_pos, 
 }
 
 void restrict_coarse(int nc, const CoarseView& cv, const double* r, double* out, const int32_t* out_pos,
-                     hipStream_t st, int n_pairs, double* t) {
-  if (nc == 0) return;
+                     hipStream_t st, int n_pairs, double* t, int64_t gcount, const int32_t* gidx, double* gdst) {
+  if (nc == 0) {
+    if (gcount > 0) gather(gcount, gidx, r, gdst, st);
+    return;
+  }
   if (n_pairs > 0 && t) {
-    phi_t_kernel<<<n_pairs, 256, 0, st>>>(cv, r, t);
+    const int gb = gcount > 0 ? grid_for(gcount, 256, 1024) : 0;
+    phi_t_kernel<<<n_pairs + gb, 256, 0, st>>>(cv, r, t, n_pairs, gb > 0 ? gcount : 0, gidx, gdst);
     restrict_assemble_kernel<<<(nc + 3) / 4, 256, 0, st>>>(nc, cv, r, t, out, out_pos);
   } else {
+    if (gcount > 0) gather(gcount, gidx, r, gdst, st);
     restrict_kernel<<<nc, 256, 0, st>>>(nc, cv, r, out, out_pos);
   }
 }

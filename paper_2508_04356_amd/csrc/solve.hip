@@ -219,14 +219,18 @@ void spmv(Context& ctx, const double* x, double* y, hipStream_t st) {
 void apply_pre(Context& ctx, const double* r, hipStream_t st) {
   const CoarseView cv = coarse_view(ctx);
   const bool three = ctx.P.spec.levels == 3 && ctx.Nc > 0;
-  gather(ctx.n_w1, ctx.d_gidx, r, ctx.d_w, st);
   if (three) {
+    gather(ctx.n_w1, ctx.d_gidx, r, ctx.d_w, st);
     // r0 = Phi^T r; level-2 copies R_j^(2) r0; level-3 right-hand side Phi3^T r0
     restrict_coarse(ctx.Nc, cv, r, ctx.d_r0, nullptr, st, ctx.n_pairs, ctx.d_pair_t);
     gather(ctx.HI.total_x, ctx.d_g2idx, ctx.d_r0, ctx.d_w + ctx.n_w1, st);
     dense_cols_dot(ctx.d_phi3, ctx.Nc, ctx.Nc, ctx.Nc3, ctx.d_r0, ctx.d_w, ctx.d_c3_pinv, st);
   } else if (ctx.Nc > 0) {
-    restrict_coarse(ctx.Nc, cv, r, ctx.d_w, ctx.d_coarse_pinv, st, ctx.n_pairs, ctx.d_pair_t);
+    // the local copies are gathered by the same launch as the restriction
+    restrict_coarse(ctx.Nc, cv, r, ctx.d_w, ctx.d_coarse_pinv, st, ctx.n_pairs, ctx.d_pair_t, ctx.n_w1, ctx.d_gidx,
+                    ctx.d_w);
+  } else {
+    gather(ctx.n_w1, ctx.d_gidx, r, ctx.d_w, st);
   }
 }
 
