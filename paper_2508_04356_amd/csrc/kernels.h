@@ -117,10 +117,8 @@ void deterministic_scatter(int64_t n, const int32_t* inv_ptr, const int64_t* inv
 // Krylov helpers
 void cols_dot(const double* V, int64_t ldv, int ncols, const double* w, int64_t n, double* part,
               int nblocks, double* out, hipStream_t st);
-void gemv_sub(const double* V, int64_t ldv, int ncols, const double* h, double* w, int64_t n,
-              hipStream_t st);
-// w -= V h followed by cols_dot(V, w) (or, with self, cols_dot(w, w)) into
-// out, in two launches instead of four, with the same results bit for bit;
+// w -= V h (each row summed in ascending column order) followed by
+// cols_dot(V, w) (or, with self, cols_dot(w, w)) into out, in two launches;
 // with out null only the partial blocks are written (nblocks x columns in
 // part), for a consumer that finishes the sums itself (cols_dot_finish)
 void sub_dots(const double* V, int64_t ldv, int ncols, const double* h, double* w, int64_t n, double* part,

@@ -571,15 +571,9 @@ __device__ inline double row_combination(const double* __restrict__ V, int64_t l
   return s;
 }
 
-__global__ void gemv_sub_kernel(const double* __restrict__ V, int64_t ldv, int ncols, const double* __restrict__ h,
-                                double* __restrict__ w, int64_t n) {
-  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
-    w[r] -= row_combination(V, ldv, ncols, h, r);
-}
-
 // One CGS2 pass fused with the next dot products: rows [r0, r0 + 256) of
-// block b (one per thread) get w[r] -= sum_j V[r, j] h[j] exactly as in
-// gemv_sub_kernel; the new values then give part[b * nd + j] = sum over the
+// block b (one per thread) get w[r] -= sum_j V[r, j] h[j] (row_combination,
+// ascending j); the new values then give part[b * nd + j] = sum over the
 // block's rows of V[:, j] * w (nd = ncols), or of w * w (self, nd = 1),
 // with the lane/row mapping and shuffle tree of cols_dot_partial_kernel, so
 // the results equal those of the two separate launches bit for bit.
@@ -784,10 +778,6 @@ void cols_dot(const double* V, int64_t ldv, int ncols, const double* w, int64_t 
               double* out, hipStream_t st) {
   cols_dot_partial_kernel<<<nblocks, 256, 0, st>>>(V, ldv, ncols, w, n, part);
   cols_dot_final_kernel<<<ncols, 64, 0, st>>>(part, nblocks, ncols, out);
-}
-
-void gemv_sub(const double* V, int64_t ldv, int ncols, const double* h, double* w, int64_t n, hipStream_t st) {
-  gemv_sub_kernel<<<grid_for(n), 256, 0, st>>>(V, ldv, ncols, h, w, n);
 }
 
 void sub_dots(const double* V, int64_t ldv, int ncols, const double* h, double* w, int64_t n, double* part,
