@@ -35,43 +35,81 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, sample_subdomains=8, repeats=5):
-    """Oracle apply on a bounded sample: the local solves of `sample_subdomains`
-    of the m^3 subdomains plus the full coarse correction; the local part is
-    scaled to all subdomains."""
-    from threadpoolctl import threadpool_info
+def cpu_model():
+    """The host CPU's model name from /proc/cpuinfo (Linux), else the platform string."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(w, repeats=3, solve=True):
+    """The CPU oracle on the same workload, as it stands: its preconditioner
+    apply (all subdomains' LU solves in ascending order, then the coarse
+    correction) timed with every host thread the BLAS offers and with one
+    thread; the same local solves spread over the subdomains on a thread pool
+    of one BLAS thread each (the oracle's own per-subdomain function, only
+    scheduled in parallel here); and one oracle FGMRES solve to the workload's
+    tolerance.  Factorisations are set-up work and untimed."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     from inputs import random_vector
     from oracle.decomposition import Decomposition
+    from oracle.fgmres import fgmres
     from oracle.gdsw import TwoLevelGDSW
     from oracle.stokes import StokesProblem
-    import scipy.linalg as sla
 
+    t0 = time.perf_counter()
     p = StokesProblem(w.n, viscosity=w.viscosity, inflow=w.inflow)
-    d = Decomposition(p, w.m, w.overlap)
-    M = TwoLevelGDSW(p.A, d, factor_local=False)
-    nsub = d.n_sub
-    pick = np.linspace(0, nsub - 1, sample_subdomains).astype(int)
-    lus = {int(i): sla.lu_factor(M.local_matrix(int(i)), check_finite=False) for i in pick}
-    r = random_vector(p.n_free, seed=1)
-    t_loc, t_crs = [], []
-    for _ in range(repeats):
-        t0 = time.perf_counter()
-        z = np.zeros_like(r)
-        for i in pick:
-            S = d.S[i]
-            z[S] += sla.lu_solve(lus[int(i)], r[S], check_finite=False)
-        t1 = time.perf_counter()
-        z += M.apply_coarse(r)
-        t2 = time.perf_counter()
-        t_loc.append(t1 - t0)
-        t_crs.append(t2 - t1)
-    t_apply = float(np.median(t_loc)) * nsub / len(pick) + float(np.median(t_crs))
+    d = Decomposition(p, w.m, w.overlap, local_dirichlet=not w.local_algebraic)
+    M = TwoLevelGDSW(p.A, d)
+    t_setup = time.perf_counter() - t0
     threads = max([int(x.get("num_threads", 1)) for x in threadpool_info()] or [1])
-    return {"value": 1.0 / t_apply, "unit": "applies/s", "cores": threads, "kind": "oracle",
-            "sample": f"M^-1 apply on the 16^3 workload: local LU solves of {len(pick)} of {nsub} subdomains "
-                      f"(scaled x{nsub / len(pick):g}) + the full coarse correction; median of {repeats}; "
-                      f"factorisation untimed"}
+    r = random_vector(p.n_free, seed=1)
+
+    def timed(f, k):
+        f()
+        ts = []
+        for _ in range(k):
+            t = time.perf_counter()
+            f()
+            ts.append(time.perf_counter() - t)
+        return float(np.median(ts))
+
+    t_all = timed(lambda: M(r), repeats)
+    with threadpool_limits(limits=1):
+        t_one = timed(lambda: M(r), repeats)
+
+        def par_apply():
+            parts = list(pool.map(lambda i: M.local_solve(i, r[d.S[i]]), range(d.n_sub)))
+            z = np.zeros_like(r)
+            for i, y in enumerate(parts):  # ascending subdomain order, as the oracle sums
+                z[d.S[i]] += y
+            return z + M.apply_coarse(r)
+
+        with ThreadPoolExecutor(max_workers=threads) as pool:
+            t_par = timed(par_apply, repeats)
+    out = {"value": 1.0 / t_all, "unit": "applies/s", "cores": threads, "kind": "oracle",
+           "sample": f"the oracle's whole M^-1 apply on the {w.n}^3 workload ({d.n_sub} subdomain LU solves "
+                     f"+ coarse correction), median of {repeats} after one warm-up; LU factorisations untimed",
+           "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+           "one_thread_applies_per_s": 1.0 / t_one,
+           "subdomain_parallel_applies_per_s": 1.0 / t_par,
+           "subdomain_parallel_workers": threads,
+           "oracle_setup_s": t_setup}
+    if solve:
+        t = time.perf_counter()
+        x, it, rel, trel = fgmres(lambda v: p.A @ v, M, p.b, rtol=w.rtol, restart=w.restart, max_it=w.max_it)
+        out["fgmres_time_to_tol_s"] = time.perf_counter() - t
+        out["fgmres_iterations"] = int(it)
+        out["fgmres_true_rel_res"] = float(trel)
+    return out
 
 
 TRAFFIC = {  # committed counter summaries of the dominant kernel on the 16^3 FP64 workload
@@ -110,6 +148,45 @@ def learned_variant(s, b, w, steps):
     res["learned_solves"], res["fallbacks"] = n_l, n_fb
     s.set_local_solver("lu")
     return res
+
+
+def precision_variants(w, args, b, x64, z64, r, solve):
+    """The same workload with FP32 and BF16 level-1 inverses (FP32
+    accumulation; coarse levels and FGMRES in FP64): FGMRES time to the same
+    tolerance on the same GPU, iterations, and the error of the solution and
+    of one apply against the FP64 library results."""
+    import torch
+
+    import paper_2508_04356_amd as G
+
+    out = {}
+    for prec in ("fp32", "bf16"):
+        t0 = time.perf_counter()
+        s = G.Solver(w.n, w.m, overlap=w.overlap, levels=w.levels, group=w.group, viscosity=w.viscosity,
+                     inflow=w.inflow, precision=prec, local_algebraic=w.local_algebraic,
+                     level2_layer=w.level2_layer, local_solve=solve)
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t0
+        x = torch.zeros_like(b)
+        for _ in range(max(args.warmup, 1)):
+            s.fgmres(b, x, rtol=w.rtol, restart=w.restart, max_it=w.max_it)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            info = s.fgmres(b, x, rtol=w.rtol, restart=w.restart, max_it=w.max_it)[0]
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / args.steps
+        z = torch.zeros_like(r)
+        s.apply(r, z)
+        torch.cuda.synchronize()
+        out[prec] = {"iterations": info.iterations, "time_to_tol_ms": ms, "true_rel_res": info.true_rel_res,
+                     "x_rel_err_vs_fp64": float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64)),
+                     "apply_rel_err_vs_fp64": float((z - z64).abs().max() / z64.abs().max()),
+                     "setup_s": t_setup}
+        log(f"[bench] {prec} inverses: {info.iterations} iterations, {ms:.2f} ms to tolerance, "
+            f"x err {out[prec]['x_rel_err_vs_fp64']:.1e}, apply err {out[prec]['apply_rel_err_vs_fp64']:.1e}")
+        s.close()
+    return out
 
 
 def copy_bandwidth(torch, dev, gib=1, reps=5):
@@ -386,6 +463,8 @@ def main():
                     help="also train the conv-net local solve (interior subdomains) and time FGMRES with it")
     ap.add_argument("--applies", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="C2: skip the FP32 / BF16 / learned variants timed beside plain FP64")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 1 GiB buffer three times (reference for HBM counters)")
     args = ap.parse_args()
@@ -525,8 +604,18 @@ def main():
                      "launches_per_apply": per_apply, "avg_launch_us": k_avg_us, "timed_in": timed_in,
                      "solve_bytes_per_apply_all_sets": solve_bytes, "solve_launches_per_apply_all_sets": launches},
     }
+    if args.workload == "C2" and not args.no_variants:
+        # mixed precision and the learned interior solve against plain FP64 on
+        # the same GPU, same workload and tolerance
+        out["variants"] = {"fp64": {"iterations": its[-1], "time_to_tol_ms": ms_per_step,
+                                    "true_rel_res": info.true_rel_res}}
+        out["variants"].update(precision_variants(w, args, b, x, z, r, args.local_solve))
+        args.learned = True
     if args.learned:
         out["learned"] = learned_variant(s, b, w, args.steps)
+        if "variants" in out:
+            out["variants"]["learned_fallback"] = out["learned"]["learned_fallback"]
+            out["variants"]["learned"] = out["learned"]["learned"]
     cbw = copy_bandwidth(torch, dev)
     out["roofline"]["measured_copy_gbs"] = cbw
     out["roofline"]["frac_of_copy"] = achieved / cbw

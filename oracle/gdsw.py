@@ -15,16 +15,11 @@ Definitions followed, in the paper's notation:
   null-space vector of field f (a velocity translation or the pressure
   constant) restricted to interface entity e, i.e. 1 on e's f-DOFs.
 
-Local matrices are factored by LAPACK's dense LU with partial pivoting
-(``scipy.linalg.lu_factor``).  The interior blocks A_II of the extension and
-the coarse matrix are factored by plain LU without row exchanges with the
-velocity-type unknowns first (``lu_nopivot``): the paper names no direct
-solver, and this is the textbook variant that exists for these saddle-point
-matrices (the velocity-type block is SPD and its Schur complement negative
-definite, both pinned).  The FGMRES iteration count is sensitive to this
-choice of factorisation.  The apply
-sums the local corrections in ascending subdomain order and adds the coarse
-correction last.
+Every dense factorisation -- the local matrices A_i, the interior blocks
+A_II of the extension and the coarse matrix A_0 -- is LAPACK's LU with partial
+pivoting (``scipy.linalg.lu_factor``): the paper names no direct solver, and
+this is the textbook general one.  The apply sums the local corrections in
+ascending subdomain order and adds the coarse correction last.
 
 Pins (``tests/test_oracle_gdsw.py``): Phi_Gamma is a partition of unity; the
 extension reproduces constants on subdomains away from the Dirichlet and
@@ -37,35 +32,6 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
-
-
-def lu_nopivot(M, order):
-    """Plain LU without row exchanges of M[order][:, order] (Doolittle, one
-    rank-1 elimination step per column).  Returns (L, U, order) with L unit
-    lower and U upper triangular, L U = M[order][:, order]."""
-    F = np.array(M[np.ix_(order, order)], dtype=np.float64)
-    n = F.shape[0]
-    for k in range(n - 1):
-        if F[k, k] == 0.0:
-            raise ZeroDivisionError(f"zero pivot at step {k}")
-        F[k + 1:, k] /= F[k, k]
-        F[k + 1:, k + 1:] -= np.outer(F[k + 1:, k], F[k, k + 1:])
-    return np.tril(F, -1) + np.eye(n), np.triu(F), np.asarray(order)
-
-
-def lu_nopivot_solve(fac, b):
-    L, U, order = fac
-    y = sla.solve_triangular(L, b[order], lower=True, unit_diagonal=True, check_finite=False)
-    y = sla.solve_triangular(U, y, lower=False, check_finite=False)
-    out = np.empty_like(y)
-    out[order] = y
-    return out
-
-
-def velocity_first(fields):
-    """Indices with field < 3 (velocity-type) first, then field 3, each ascending."""
-    fields = np.asarray(fields)
-    return np.concatenate([np.nonzero(fields < 3)[0], np.nonzero(fields == 3)[0]])
 
 
 def coarse_basis(A, dec):
@@ -89,9 +55,8 @@ def coarse_basis(A, dec):
         used = np.nonzero(np.any(rhs != 0.0, axis=0))[0]
         if used.size == 0:
             continue
-        # I_i is in global order, i.e. velocity DOFs first
-        fac = lu_nopivot(AII, np.arange(Ii.size))
-        PhiI = -np.stack([lu_nopivot_solve(fac, rhs[:, k]) for k in used], 1)
+        fac = sla.lu_factor(AII, check_finite=False)
+        PhiI = -sla.lu_solve(fac, rhs[:, used], check_finite=False)
         rr, cc = np.meshgrid(Ii, used, indexing="ij")
         rows.append(rr.ravel())
         cols.append(cc.ravel())
@@ -117,7 +82,7 @@ class TwoLevelGDSW:
         if dec.n_coarse > 0:
             self.Phi = coarse_basis(self.A, dec)
             self.A0 = (self.Phi.T @ (self.A @ self.Phi)).toarray()
-            self.A0_lu = lu_nopivot(self.A0, velocity_first(dec.coarse_field))
+            self.A0_lu = sla.lu_factor(self.A0, check_finite=False)
         else:
             self.Phi = None
             self.A0 = np.zeros((0, 0))
@@ -132,7 +97,8 @@ class TwoLevelGDSW:
         return sla.lu_solve(self.local_lu[i], ri, check_finite=False)
 
     def coarse_solve(self, r0):
-        return lu_nopivot_solve(self.A0_lu, r0)
+        """A_0^{-1} r_0 with the stored LU factors of A_0."""
+        return sla.lu_solve(self.A0_lu, r0, check_finite=False)
 
     def apply_local(self, r):
         """sum_i R_i^T A_i^{-1} R_i r, ascending i."""

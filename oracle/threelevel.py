@@ -27,15 +27,15 @@ pinned by ``tests/test_oracle_threelevel.py``):
 * Phi^(3) is eq. (2.4) applied to A_0, and A_0^(3) = Phi^(3)^T A_0 Phi^(3).
 * Apply order: level-1 local sum (ascending i); inside the coarse term, the
   level-2 local sum (ascending j) and then the level-3 correction.
-* Level-2 local matrices and A_0^(3) are factored like A_0: LU without row
-  exchanges, velocity-type DOFs first.
+* Level-2 local matrices, the subregion interior blocks of the level-3
+  extension and A_0^(3) are factored like A_0: LU with partial pivoting.
 """
 from __future__ import annotations
 
 import numpy as np
 import scipy.linalg as sla
 
-from .gdsw import TwoLevelGDSW, lu_nopivot, lu_nopivot_solve, velocity_first
+from .gdsw import TwoLevelGDSW
 
 
 class ThreeLevelGDSW(TwoLevelGDSW):
@@ -99,25 +99,25 @@ class ThreeLevelGDSW(TwoLevelGDSW):
             if Ij.size == 0 or self.n_coarse3 == 0:
                 continue
             rhs = A0[np.ix_(Ij, np.arange(Nc))] @ PhiG3
-            fac = lu_nopivot(A0[np.ix_(Ij, Ij)], velocity_first(c_field[Ij]))
-            Phi3[Ij, :] = -np.stack([lu_nopivot_solve(fac, rhs[:, k]) for k in range(rhs.shape[1])], 1)
+            fac = sla.lu_factor(A0[np.ix_(Ij, Ij)], check_finite=False)
+            Phi3[Ij, :] = -sla.lu_solve(fac, rhs, check_finite=False)
         self.Phi3 = Phi3
         self.A03 = Phi3.T @ A0 @ Phi3
         f3 = np.zeros(self.n_coarse3, dtype=int)
         for (E, f), k in col3.items():
             f3[k] = f
         self.coarse3_field = f3
-        self.A03_lu = lu_nopivot(self.A03, velocity_first(f3)) if self.n_coarse3 > 0 else None
+        self.A03_lu = sla.lu_factor(self.A03, check_finite=False) if self.n_coarse3 > 0 else None
         self.lu2 = []
         for S in self.S2:
             Aj = A0[np.ix_(S, S)]
-            self.lu2.append(lu_nopivot(Aj, velocity_first(c_field[S])))
+            self.lu2.append(sla.lu_factor(Aj, check_finite=False))
 
     def coarse_solve(self, r0):
         """Replaces A_0^{-1}: level-2 local sum then the level-3 correction."""
         y = np.zeros_like(r0)
         for j, S in enumerate(self.S2):
-            y[S] += lu_nopivot_solve(self.lu2[j], r0[S])
+            y[S] += sla.lu_solve(self.lu2[j], r0[S], check_finite=False)
         if self.A03_lu is not None:
-            y += self.Phi3 @ lu_nopivot_solve(self.A03_lu, self.Phi3.T @ r0)
+            y += self.Phi3 @ sla.lu_solve(self.A03_lu, self.Phi3.T @ r0, check_finite=False)
         return y

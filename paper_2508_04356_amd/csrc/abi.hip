@@ -460,7 +460,6 @@ gdsw_status gdsw_autotune(gdsw_ctx* ctx, void* stream, int32_t* chosen, double* 
     GDSW_HIP(hipEventCreate(&e1));
     KernelTimer* tm = fs.timer;
     fs.timer = nullptr;
-    int best = 1;
     for (int q = 0; q < 3; ++q) {
       fs.cw = cand[q];
       plan_schedule(fs, 1, c.arena, st, 0);
@@ -472,8 +471,10 @@ gdsw_status gdsw_autotune(gdsw_ctx* ctx, void* stream, int32_t* chosen, double* 
       float el = 0.f;
       GDSW_HIP(hipEventElapsedTime(&el, e0, e1));
       t[q] = el / 10.0;
-      if (t[q] < t[best]) best = q;
     }
+    int best = 0;  // argmin over the three measured candidates
+    for (int q = 1; q < 3; ++q)
+      if (t[q] < t[best]) best = q;
     fs.cw = cand[best];
     plan_schedule(fs, 1, c.arena, st, 0);
     fs.timer = tm;

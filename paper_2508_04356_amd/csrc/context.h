@@ -136,6 +136,7 @@ struct FactorSet {
   int max_np = 0;                    // BF16 products: right-hand sides as BF16,
   int64_t* d_xpoff = nullptr;        //   xb[32 * xpoff[f] + j * npad[f] + row]
   uint16_t* d_xb = nullptr;
+  uint64_t gen = 0;                    // bumped by every re-plan (item arrays, partial buffers)
   uint64_t algorithmic_bytes() const;  // sum n^2 * sizeof(prec)
   uint64_t alg_bytes = 0;              // algorithmic_bytes(), set when planned
   int64_t launches() const;            // solve kernel launches per pass (slot 0)
@@ -160,6 +161,7 @@ struct Context {
   struct IterGraphs {
     int restart = 0;
     const double* V = nullptr;       // workspace the graphs were captured against
+    uint64_t gen1 = 0, gen2 = 0;     // plan generations of L1 / HI they were captured against
     hipStream_t stream = nullptr;    // own stream when the caller passes the default one
     std::vector<hipGraphExec_t> exec;
   } graphs;

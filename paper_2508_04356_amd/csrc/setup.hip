@@ -130,6 +130,7 @@ void plan_gemv(FactorSet& fs, DeviceArena& A, hipStream_t st, int slot, const st
 
 void plan_gemm(FactorSet& fs, DeviceArena& A, hipStream_t st) {
   if (fs.mode != SOLVE_INVERSE || fs.count == 0) return;
+  ++fs.gen;
   gemm_choose(fs);
   const int RB = fs.gemm_rb, CW = fs.gemm_cw;
   std::vector<int4> it1, it2;
@@ -168,6 +169,7 @@ void plan_gemm(FactorSet& fs, DeviceArena& A, hipStream_t st) {
 
 void plan_schedule(FactorSet& fs, int phases, DeviceArena& A, hipStream_t st, int slot,
                    const std::vector<char>* include) {
+  ++fs.gen;  // captured graphs that hold the old item arrays must be re-captured
   if (fs.mode == SOLVE_INVERSE) {
     plan_gemv(fs, A, st, slot, include);
     return;

@@ -309,10 +309,15 @@ FgmresResult fgmres(Context& ctx, const double* b, double* x, double rtol, int r
   // apply and stays eager.
   const bool graph = use_graph && !(ctx.local_solver != 0 && ctx.learned);
   if (graph) {
-    if (ctx.graphs.V != ctx.d_V || ctx.graphs.restart != restart) {
+    // a re-plan (autotuner, schedule, learned subsets) frees and replaces the
+    // item arrays and partial buffers the captured kernels point at
+    if (ctx.graphs.V != ctx.d_V || ctx.graphs.restart != restart || ctx.graphs.gen1 != ctx.L1.gen ||
+        ctx.graphs.gen2 != ctx.HI.gen) {
       drop_graphs(ctx);
       ctx.graphs.V = ctx.d_V;
       ctx.graphs.restart = restart;
+      ctx.graphs.gen1 = ctx.L1.gen;
+      ctx.graphs.gen2 = ctx.HI.gen;
       ctx.graphs.exec.assign(restart, nullptr);
     }
     if (st == nullptr) {

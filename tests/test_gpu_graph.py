@@ -48,6 +48,7 @@ def test_autotune_keeps_results_valid():
     chunk, ms = s.autotune()
     print(f"[gpu] autotune chunk {chunk} ms {ms}", flush=True)
     assert chunk in (512, 1024, 2048) and all(t > 0 for t in ms)
+    assert chunk == (512, 1024, 2048)[min(range(3), key=lambda q: ms[q])]
     z1 = torch.zeros_like(r)
     z2 = torch.zeros_like(r)
     s.apply(r, z1)
@@ -55,4 +56,28 @@ def test_autotune_keeps_results_valid():
     torch.cuda.synchronize()
     assert torch.equal(z1, z2)
     assert float((z1 - z0).abs().max() / z0.abs().max()) < 1e-13
+    s.close()
+
+
+def test_graph_solve_after_retune():
+    """A re-plan (autotuner) replaces the item arrays and partial buffers the
+    captured iterations point at: the next graph solve must re-capture and
+    reproduce the eager solve on the new plan bitwise."""
+    s = G.Solver(12, 3)
+    b = torch.zeros(s.n_free, dtype=torch.float64, device=DEV)
+    s.rhs(b)
+    x0 = torch.zeros_like(b)
+    info0 = s.fgmres(b, x0, rtol=1e-8)[0]
+    x1 = torch.zeros_like(b)
+    info1 = s.fgmres(b, x1, rtol=1e-8, use_graph=True)[0]
+    torch.cuda.synchronize()
+    assert info1.iterations == info0.iterations and torch.equal(x1, x0)
+    chunk, ms = s.autotune()
+    print(f"[gpu] retune chunk {chunk}", flush=True)
+    x2 = torch.zeros_like(b)
+    info2 = s.fgmres(b, x2, rtol=1e-8)[0]
+    x3 = torch.zeros_like(b)
+    info3 = s.fgmres(b, x3, rtol=1e-8, use_graph=True)[0]
+    torch.cuda.synchronize()
+    assert info3.iterations == info2.iterations and torch.equal(x3, x2)
     s.close()

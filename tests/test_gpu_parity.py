@@ -5,7 +5,9 @@ either forms A_i^-1 by Gauss-Jordan without pivoting or factors without
 pivoting and inverts the diagonal tiles, so the local solves differ by about
 cond(A_i) * eps.  Setup results (A, Phi, A_0) are compared at
 1e-12 relative; preconditioner outputs at 1e-10 relative in the max norm;
-FGMRES solutions at 1e-10 relative with identical iteration counts.
+FGMRES solutions at 1e-10 relative with identical iteration counts (the
+algebraic-overlap cases, whose local problems are nearly singular, at the
+bounds stated in their tests).
 """
 import json
 import os
@@ -118,7 +120,7 @@ def test_fgmres_parity(w, solve):
     print(f"[gpu] {w.name} it gpu {info.iterations} oracle {ito} true {info.true_rel_res:.2e}", flush=True)
     assert info.iterations == ito
     assert info.true_rel_res <= w.rtol
-    assert np.linalg.norm(host(x) - xo) / np.linalg.norm(xo) < 1e-10 + 10 * w.rtol
+    assert np.linalg.norm(host(x) - xo) / np.linalg.norm(xo) < 1e-10
     s.close()
 
 
@@ -229,43 +231,63 @@ def _golden(name):
         return json.load(f)
 
 
+def _golden_vectors(name):
+    path = os.path.join(GOLDEN, f"oracle_{name}.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    with np.load(path) as f:
+        return f["x"], f["z"]
+
+
+@pytest.mark.parametrize("solve", ["inverse", "symmetric", "triangular"])
 @pytest.mark.parametrize("name", ["C1", "C2", "C2alg"])
-def test_workload_against_stored_oracle(name):
-    """Full-size workload: apply outputs at sampled DOFs, FGMRES iteration
-    count and solution samples against the stored oracle run."""
+def test_workload_against_stored_oracle(name, solve):
+    """Full-size workload in every local-solve mode: the apply on every free
+    DOF at 1e-10 (max norm, relative), the FGMRES iteration count and the
+    solution on every free DOF at 1e-10 (2-norm, relative) against the stored
+    oracle run.  The algebraic-overlap variant C2alg has nearly singular local
+    problems (cond ~ 1e5), so its count moves under rounding-level changes: it
+    must fall within the oracle's own spread under 1e-14 perturbations, and
+    when it differs from the oracle's count (a tie in the sense of the count
+    being set by rounding) the two iterates are compared through their
+    residuals: ||A (x - x_o)|| <= ||b - A x|| + ||b - A x_o||."""
     g = _golden(name)
+    xg, zg = _golden_vectors(name)
     w = workload(name)
-    s = gpu_case(w)
+    s = gpu_case(w, local_solve=solve)
     n = s.n_free
-    assert n == g["n_free"]
-    idx = np.array(g["idx"])
+    assert n == g["n_free"] == xg.size
     r = random_vector(n, seed=1)
     z = torch.zeros(n, dtype=torch.float64, device=DEV)
     s.apply(dev(r), z)
     zh = host(z)
-    assert np.abs(zh[idx] - np.array(g["z"])).max() / np.abs(np.array(g["z"])).max() < 1e-10
-    assert abs(np.linalg.norm(zh) - g["z_norm"]) / g["z_norm"] < 1e-10
+    zerr = rel_max(zh, zg)
+    print(f"[gpu] {name} {solve} apply rel err {zerr:.2e}", flush=True)
+    assert zerr < 1e-10
     b = torch.zeros(n, dtype=torch.float64, device=DEV)
     s.rhs(b)
     x = torch.zeros_like(b)
     info = s.fgmres(b, x, rtol=g["rtol"], restart=g["restart"])[0]
-    print(f"[gpu] {name} it {info.iterations} (oracle {g['iterations']}) t {info.t_solve_s:.3f}s", flush=True)
+    xh = host(x)
+    xerr = float(np.linalg.norm(xh - xg) / np.linalg.norm(xg))
+    print(f"[gpu] {name} {solve} it {info.iterations} (oracle {g['iterations']}) "
+          f"x rel err {xerr:.2e} t {info.t_solve_s:.3f}s", flush=True)
+    assert info.true_rel_res <= g["rtol"]
     spread_path = os.path.join(GOLDEN, f"oracle_{name}_spread.json")
-    if os.path.exists(spread_path):
-        # the count can be rounding-sensitive at this size: it must fall within
-        # the oracle's own spread under rounding-level perturbations
-        sp = json.load(open(spread_path))
+    sp = json.load(open(spread_path)) if os.path.exists(spread_path) else None
+    if sp is not None and sp["min"] != sp["max"]:
         lo, hi = min(sp["min"], g["iterations"]), max(sp["max"], g["iterations"])
         assert lo <= info.iterations <= hi, (info.iterations, lo, hi)
-    else:
-        assert info.iterations == g["iterations"]
-    assert info.true_rel_res <= g["rtol"]
-    # both iterates satisfy the tolerance; their difference is bounded by the
-    # conditioning of A times rtol, far above rounding
-    xh = host(x)
-    xg = np.array(g["x"])
-    assert np.abs(xh[idx] - xg).max() / np.abs(xg).max() < 1e-4
-    s.close()
+        if info.iterations != g["iterations"]:
+            print(f"[gpu] {name} {solve}: count tie within the oracle's spread {lo}..{hi}", flush=True)
+            # both iterates meet the tolerance: ||A (x - x_o)|| <= ||b - A x|| + ||b - A x_o||
+            ax = torch.zeros_like(b)
+            s.spmv(x - dev(xg), ax)
+            bn = float(torch.linalg.norm(b))
+            assert float(torch.linalg.norm(ax)) <= (info.true_rel_res + g["true_rel"]) * bn * (1 + 1e-6)
+            return
+    assert info.iterations == g["iterations"]
+    assert xerr < 1e-10
 
 
 def test_symmetric_storage_rejections():

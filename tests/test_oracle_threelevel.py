@@ -67,3 +67,48 @@ def test_three_level_fgmres_converges_to_direct(n8m4):
     r = np.random.default_rng(5).standard_normal(p.n_free)
     s = np.random.default_rng(6).standard_normal(p.n_free)
     assert abs(M(r) @ s - r @ M(s)) < 1e-10 * abs(M(r) @ s)
+
+
+@pytest.mark.parametrize("layer", [False, True])
+def test_dense_three_level_operator(layer):
+    """eq. (2.5) written out with dense inverses on n = 4, m = 4, group 2
+    (64 subdomains, 8 subregions):
+
+        B3 = sum_i R_i^T A_i^-1 R_i
+             + Phi [ sum_j R_j^T (R_j A_0 R_j^T)^-1 R_j
+                     + Phi3 (Phi3^T A_0 Phi3)^-1 Phi3^T ] Phi^T,
+
+    with the interior rows of Phi3 recomputed here from eq. (2.4) applied to
+    A_0 (the level-3 interface rows are its 0/1 partition of unity).  The
+    level-3 term is checked to matter, so dropping or rescaling it fails."""
+    p = StokesProblem(4)
+    d = Decomposition(p, 4, 1)
+    M = ThreeLevelGDSW(p.A, d, 2, level2_layer=layer)
+    A = p.A.toarray()
+    n = p.n_free
+    Phi = M.Phi.toarray()
+    A0 = Phi.T @ A @ Phi
+    assert np.abs(A0 - M.A0).max() < 1e-12 * np.abs(A0).max()
+    gam = np.array([c for c, r in enumerate(M.coarse_regions) if len(r) >= 2])
+    P3 = np.zeros_like(M.Phi3)
+    P3[gam] = M.Phi3[gam]
+    assert set(np.unique(P3[gam])) <= {0.0, 1.0}
+    for Ij in M.I2:
+        if Ij.size:
+            P3[Ij] = -np.linalg.solve(A0[np.ix_(Ij, Ij)], A0[Ij] @ P3)
+    assert np.abs(P3 - M.Phi3).max() < 1e-12 * np.abs(P3).max()
+    B = np.zeros((n, n))
+    for Si in d.S:
+        B[np.ix_(Si, Si)] += np.linalg.inv(A[np.ix_(Si, Si)])
+    C2 = np.zeros_like(A0)
+    for Sj in M.S2:
+        C2[np.ix_(Sj, Sj)] += np.linalg.inv(A0[np.ix_(Sj, Sj)])
+    C3 = P3 @ np.linalg.inv(P3.T @ A0 @ P3) @ P3.T
+    B += Phi @ (C2 + C3) @ Phi.T
+    X = np.random.default_rng(8).standard_normal((n, 3))
+    Z = M(X)
+    ref = B @ X
+    scale = np.abs(ref).max()
+    assert np.abs(Z - ref).max() < 1e-13 * scale
+    lvl3 = Phi @ C3 @ Phi.T @ X
+    assert np.abs(lvl3).max() > 1e-3 * scale
