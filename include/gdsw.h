@@ -214,6 +214,21 @@ gdsw_status gdsw_spmv(gdsw_ctx* ctx, const double* x_dev, double* y_dev, void* s
 gdsw_status gdsw_apply_precond(gdsw_ctx* ctx, const double* r_dev, double* z_dev,
                                int32_t nrhs, int64_t ld, void* stream);
 
+/* For callers that cannot allocate device memory at call time (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc):
+ * z = M^-1 r exactly as gdsw_apply_precond computes it (same kernels and
+ * summation orders, so bitwise the same result), column by column, with the
+ * partial sums of the inverse products in a static device array that the
+ * library holds once per device for the whole process (128 MiB; its device
+ * address is looked up in gdsw_setup) instead of the context's buffer.
+ * Calls no allocating routine.  Every call on a device shares that array and
+ * needs no cleared state in it; calls that overlap on one device (two
+ * streams, two threads) race.  EINVAL when the problem's partial sums exceed
+ * the array (the message gives the bytes needed), EUNSUPPORTED for
+ * GDSW_SOLVE_TRIANGULAR or a learned / disabled interior solver. */
+gdsw_status gdsw_apply_precond_noalloc(gdsw_ctx* ctx, const double* r_dev, double* z_dev,
+                                       int32_t nrhs, int64_t ld, void* stream);
+
 /* Solves A x = b with right-preconditioned FGMRES for nrhs columns from
  * x = 0: max_rhs columns at a time in lockstep when the context was set up
  * for several right-hand sides (every column keeps its own Krylov space,

@@ -77,6 +77,7 @@ _sig = {
     "gdsw_rhs": (C.c_int, [_P, _P, _P]),
     "gdsw_spmv": (C.c_int, [_P, _P, _P, _P]),
     "gdsw_apply_precond": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int64, _P]),
+    "gdsw_apply_precond_noalloc": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int64, _P]),
     "gdsw_fgmres_solve": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int64, C.POINTER(FgmresOpts),
                                     C.POINTER(FgmresInfo), _P]),
     "gdsw_expand_solution": (C.c_int, [_P, _P, _P, _P]),
@@ -223,6 +224,12 @@ class Solver:
     def apply(self, r, z, nrhs=1, ld=None, stream=None):
         ld = self.n_free if ld is None else ld
         _check(_lib.gdsw_apply_precond(self._ctx, _ptr(r), _ptr(z), nrhs, ld, _stream(stream)), self._ctx)
+        return z
+
+    def apply_noalloc(self, r, z, nrhs=1, ld=None, stream=None):
+        """gdsw_apply_precond_noalloc: the same result without any allocation."""
+        ld = self.n_free if ld is None else ld
+        _check(_lib.gdsw_apply_precond_noalloc(self._ctx, _ptr(r), _ptr(z), nrhs, ld, _stream(stream)), self._ctx)
         return z
 
     def autotune(self, stream=None):

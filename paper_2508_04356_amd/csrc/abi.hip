@@ -140,6 +140,7 @@ gdsw_status gdsw_setup(const gdsw_mesh* mesh, const gdsw_decomposition* dec, voi
     }
     const int nb = dec->tile ? dec->tile : 128;
     device_setup(c, (hipStream_t)stream, budget, nb);
+    (void)noalloc_scratch(c.device);  // device address of the no-allocation scratch, once per device
     c.t_numeric = std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count();
   });
   if (s != GDSW_OK) {
@@ -253,6 +254,18 @@ gdsw_status gdsw_apply_precond(gdsw_ctx* ctx, const double* r_dev, double* z_dev
       return;
     }
     for (int k = 0; k < nrhs; ++k) apply_precond(c, r_dev + (int64_t)k * ld, z_dev + (int64_t)k * ld, st);
+  });
+}
+
+gdsw_status gdsw_apply_precond_noalloc(gdsw_ctx* ctx, const double* r_dev, double* z_dev, int32_t nrhs, int64_t ld,
+                                       void* stream) {
+  if (gdsw_status s = check_device_ctx(ctx)) return s;
+  if (!r_dev || !z_dev) return fail(ctx, GDSW_EINVAL, "NULL vector");
+  if (nrhs < 1 || ld < ctx->c.P.n_free) return fail(ctx, GDSW_EINVAL, "need nrhs >= 1 and ld >= n_free");
+  if (r_dev == z_dev) return fail(ctx, GDSW_EINVAL, "r and z must not overlap");
+  return guarded(ctx, [&]() {
+    for (int k = 0; k < nrhs; ++k)
+      apply_precond_noalloc(ctx->c, r_dev + (int64_t)k * ld, z_dev + (int64_t)k * ld, (hipStream_t)stream);
   });
 }
 

@@ -275,6 +275,11 @@ void apply_precond(Context& ctx, const double* r, double* z, hipStream_t st, hip
 void apply_pre(Context& ctx, const double* r, hipStream_t st);
 void apply_post(Context& ctx, double* z, hipStream_t st);
 void spmv(Context& ctx, const double* x, double* y, hipStream_t st);
+// apply_precond with the product's partial sums in the library's static
+// per-device scratch array instead of the context's buffer (noalloc.hip)
+void apply_precond_noalloc(Context& ctx, const double* r, double* z, hipStream_t st);
+double* noalloc_scratch(int device);  // device address of the array (looked up once per device)
+uint64_t noalloc_scratch_bytes();
 struct FgmresResult {
   int iterations = 0, restarts = 0;
   double rel = 0, true_rel = 0;
