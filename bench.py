@@ -491,7 +491,7 @@ def main():
         run_batch(args, args.precision or "fp64")
         return
     w = workload(args.workload)
-    prec = args.precision or (w.precision if args.workload not in ("C2", "C2alg") else "fp64")
+    prec = args.precision or (w.precision if args.workload not in ("C2", "C2alg", "P16", "P32") else "fp64")
     nrhs = w.nrhs if args.nrhs is None else args.nrhs
     if nrhs > 1:
         run_multi(args, w, prec, nrhs)
@@ -505,7 +505,8 @@ def main():
     t0 = time.perf_counter()
     s = G.Solver(w.n, w.m, overlap=w.overlap, levels=w.levels, group=w.group, viscosity=w.viscosity,
                  inflow=w.inflow, tile=args.tile, precision=prec, local_algebraic=alg,
-                 level2_layer=w.level2_layer, local_solve=args.local_solve)
+                 level2_layer=w.level2_layer, local_solve=args.local_solve, pressure=w.pressure,
+                 coarse=w.coarse)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     sz = s.sizes()
@@ -582,8 +583,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if prec == "fp64" else f"f64 (local factors {prec}, fp32 accumulation)",
         "data": "synthetic: Poiseuille Stokes problem generated in-library (no dataset)",
-        "config": {"workload": f"{w.name}: {w.n}^3 Q2/Q1 hexahedra, {w.m}^3 subdomains, overlap {w.overlap}, "
-                               f"{w.levels}-level GDSW, FGMRES rtol {w.rtol:g} restart {w.restart}",
+        "config": {"workload": f"{w.name}: {w.n}^3 Q2/{'P1disc' if w.pressure == 'p1disc' else 'Q1'} hexahedra, "
+                               f"{w.m}^3 subdomains, overlap {w.overlap}, {w.levels}-level "
+                               f"{'GDSW*' if w.coarse == 'gdsw*' else 'GDSW'}, FGMRES rtol {w.rtol:g} "
+                               f"restart {w.restart}",
                    "n_free": n, "n_coarse": int(sz.n_coarse), "tile": args.tile or 128,
                    "local_problems": "algebraic overlap (closed box grown by one element)" if alg
                    else "Dirichlet u and p on the artificial boundary of the grown box"},

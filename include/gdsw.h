@@ -84,6 +84,18 @@ typedef struct {
                                     u = (c y(1-y) z(1-z), 0, 0), p = 0 exact */
   double viscosity;           /* mu > 0 */
   double inflow_amplitude;    /* c */
+  int32_t pressure_element;   /* 0 (default): Q1, continuous pressure;
+                                 1: P1-discontinuous, the paper's pair
+                                 (Section 2): 4 DOFs per hexahedron, the basis
+                                 1, 2 xi - 1, 2 eta - 1, 2 zeta - 1 on the
+                                 reference cube, numbered 4 e + k after the
+                                 velocity DOFs (element e lexicographic, x
+                                 fastest).  There is no pressure interface:
+                                 the coarse space gets one pressure column per
+                                 subdomain, constant over it (Section 3), and
+                                 the velocity columns are extended with the
+                                 velocity block alone.  Needs local_algebraic
+                                 = 1 and two levels (EINVAL otherwise). */
 } gdsw_mesh;
 
 /* Decomposition, overlap and levels (Section 2.1 and 2.2). */
@@ -126,6 +138,12 @@ typedef struct {
                                  FGMRES in lockstep with per-column stopping.
                                  With BF16 factors the columns are rounded to
                                  BF16 for the products (FP32 accumulation). */
+  int32_t coarse_space;       /* 0 (default): full GDSW, every vertex, edge and
+                                 face class its own entity; 1: GDSW* (Section
+                                 4): each vertex grouped with its adjacent
+                                 edges into one entity, an edge between two
+                                 vertices joining the one first in entity
+                                 order (smallest node id), faces on their own */
 } gdsw_decomposition;
 
 typedef struct {
@@ -144,6 +162,10 @@ typedef struct {
   double rel_res;             /* last implicit |g_{j+1}| / ||b|| */
   double true_rel_res;        /* ||b - A x|| / ||b|| recomputed at the end */
   double t_solve_s;           /* wall time of the solve (host clock) */
+  int64_t learned_solves;     /* interior local solves done by the network in
+                                 this solve (learned local solver), else 0 */
+  int64_t fallbacks;          /* of those, re-solved exactly because their
+                                 local residual exceeded tau */
 } gdsw_fgmres_info;
 
 typedef struct {
@@ -184,6 +206,12 @@ gdsw_status gdsw_setup_host(const gdsw_mesh* mesh, const gdsw_decomposition* dec
                             gdsw_ctx** out);
 
 gdsw_status gdsw_get_sizes(const gdsw_ctx* ctx, gdsw_sizes* out);
+
+/* Wall time of the two setup phases, as the paper's tables report them
+ * (Tables 1-4): symbolic (host: numbering, assembly, decomposition, overlap
+ * and interface entities) and numeric (device: local matrices, inverses or
+ * factors, Phi, A_0 and the coarse levels), in seconds. */
+gdsw_status gdsw_setup_times(const gdsw_ctx* ctx, double* symbolic_s, double* numeric_s);
 
 /* field[k] in {0,1,2,3} (u_x, u_y, u_z, p) and node_abc[3k..3k+2] the Q2
  * node coordinates (pressure nodes (i,j,k) map to (2i,2j,2k)) of free DOF k.
@@ -318,6 +346,23 @@ gdsw_status gdsw_learned_copy(gdsw_ctx* dst, const gdsw_ctx* src, void* stream);
 
 /* Interior local solves done by the network and by the LU fallback so far. */
 gdsw_status gdsw_learned_stats(const gdsw_ctx* ctx, int64_t* learned_solves, int64_t* fallbacks);
+
+/* Writes the network (FP32 master weights and the per-channel output scales)
+ * to the file `path`: "GDSWNET1", int32 grid, int32 0, int64 n_params,
+ * float sigma[4], float weights[n_params], little-endian.  Synchronises
+ * `stream`.  EINVAL if ctx has no network or the file cannot be written. */
+gdsw_status gdsw_learned_save(const gdsw_ctx* ctx, const char* path, void* stream);
+
+/* Reads such a file into ctx's network (after gdsw_learned_init), which then
+ * counts as trained.  EINVAL if the file is malformed or was written for
+ * another interior node grid. */
+gdsw_status gdsw_learned_load(gdsw_ctx* ctx, const char* path, void* stream);
+
+/* gdsw_learned_init (if needed, with `seed`), training pairs from 4 solves
+ * (if none were generated yet), `steps` Adam steps (batch 32, lr 2e-3) and,
+ * when out_weights is not NULL, gdsw_learned_save to that path. */
+gdsw_status gdsw_train_local_net(gdsw_ctx* ctx, const char* out_weights, int32_t steps, uint64_t seed,
+                                 void* stream);
 
 /* Tuning --------------------------------------------------------------------- */
 

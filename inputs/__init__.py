@@ -12,5 +12,6 @@ from .workloads import (  # noqa: F401
     random_vector,
     c3_inflow_amplitudes,
     c5_batch_draws,
+    paper_variant_cases,
     small_parity_cases,
 )

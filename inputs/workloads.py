@@ -34,6 +34,8 @@ class Workload:
     nrhs: int = 1
     local_algebraic: int = 0  # 1: algebraic overlap instead of Dirichlet u, p on the artificial boundary
     level2_layer: int = 0     # 1: level-2 local sets get one more A_0-graph layer
+    pressure: str = "q1"      # q1 | p1disc (the paper's pair)
+    coarse: str = "gdsw"      # gdsw | gdsw* (vertices grouped with adjacent edges)
     note: str = ""
 
     def with_(self, **kw) -> "Workload":
@@ -51,6 +53,10 @@ WORKLOADS: Dict[str, Workload] = {
     "C3": Workload("C3", n=24, m=6, nrhs=32, precision="fp32"),
     # 32^3 mesh, 8^3 subdomains, three levels with 2^3 grouping, FP32 level-1 factors.
     "C4": Workload("C4", n=32, m=8, levels=3, group=2, precision="fp32"),
+    # the paper's own variant: Q2/P1disc, GDSW* coarse space, algebraic overlap
+    "P16": Workload("P16", n=16, m=4, local_algebraic=1, pressure="p1disc", coarse="gdsw*"),
+    # Table 1, first row: 32^3 hexahedra (954,947 DOFs), 8^3 subdomains, 5,573 coarse DOFs
+    "P32": Workload("P32", n=32, m=8, local_algebraic=1, pressure="p1disc", coarse="gdsw*"),
 }
 
 
@@ -84,6 +90,18 @@ def c5_batch_draws(count: int = 16, seed: int = 5) -> List[Tuple[int, float, flo
     mus = 10.0 ** rng.uniform(-1.0, 1.0, size=count)
     cs = rng.uniform(0.5, 2.0, size=count)
     return [(int(a), float(b), float(c)) for a, b, c in zip(ns, mus, cs)]
+
+
+def paper_variant_cases() -> List[Workload]:
+    """Small Q2/P1disc problems (the paper's element pair and coarse spaces)."""
+    return [
+        Workload("p4m2s", n=4, m=2, local_algebraic=1, pressure="p1disc", coarse="gdsw*"),
+        Workload("p6m3s", n=6, m=3, local_algebraic=1, pressure="p1disc", coarse="gdsw*", viscosity=0.6,
+                 inflow=2.0),
+        Workload("p8m4s", n=8, m=4, local_algebraic=1, pressure="p1disc", coarse="gdsw*"),
+        Workload("p6m3f", n=6, m=3, local_algebraic=1, pressure="p1disc", coarse="gdsw"),
+        Workload("q6m3s", n=6, m=3, coarse="gdsw*"),
+    ]
 
 
 def small_parity_cases() -> List[Workload]:

@@ -28,6 +28,23 @@ Readings (pinned by ``tests/test_oracle_decomposition.py``):
 * Coarse DOF order: entities sorted by the smallest Q2 node id of a node that
   carries a free DOF of the entity, then fields u_x, u_y, u_z, p.
 * I_i: free DOFs of closed box i that are not in Gamma.
+
+The paper's own coarse space and element pair (Sections 3 and 4):
+
+* ``coarse="gdsw*"``: each vertex class is grouped with its adjacent edge
+  classes (an edge whose subdomain set lies inside the vertex's) into one
+  entity.  The paper does not say what happens to an edge between two
+  vertices; reading: it joins the adjacent vertex that comes first in the
+  entity order (the smallest node id), so entities stay disjoint and Phi_Gamma
+  stays a 0/1 partition of unity.  Faces stay entities of their own.  Every
+  entity of the grouped space is then ordered by the smallest node id of its
+  merged class.
+* Discontinuous pressure (``pressure="p1disc"``): pressure DOFs sit at element
+  centres, so none lies on Gamma; the coarse space gets one pressure column
+  per subdomain instead (constant over the subdomain), after the interface
+  columns, in subdomain order.  Its local problems need the algebraic overlap:
+  with Dirichlet velocity on the whole artificial boundary the constant
+  pressure of an interior local problem is a null vector.
 """
 from __future__ import annotations
 
@@ -47,12 +64,18 @@ def box_range_1d(coord, s, m):
 class Decomposition:
     """Structured m^3 decomposition of a ``StokesProblem``."""
 
-    def __init__(self, prob, m, overlap=1, local_dirichlet=True):
+    def __init__(self, prob, m, overlap=1, local_dirichlet=True, coarse="gdsw"):
         n = prob.n
         if n % m != 0:
             raise ValueError("n must be a multiple of m")
         if overlap < 1:
             raise ValueError("overlap must be >= 1")
+        if coarse not in ("gdsw", "gdsw*"):
+            raise ValueError("coarse must be 'gdsw' or 'gdsw*'")
+        disc = getattr(prob, "pressure", "q1") == "p1disc"
+        if disc and local_dirichlet:
+            raise ValueError("discontinuous pressure needs the algebraic overlap (local_dirichlet=False)")
+        self.coarse = coarse
         self.m = m
         self.s = n // m
         self.overlap = overlap
@@ -60,6 +83,8 @@ class Decomposition:
         s = self.s
         abc = prob.dof_node           # (n_free, 3) half-element units
         field = prob.dof_field
+        self.dof_field = field
+        self.dof_null = getattr(prob, "dof_null", np.ones(field.size))
 
         # per-axis closed-box index ranges and the subdomain set of each free DOF
         lo = np.zeros_like(abc)
@@ -102,10 +127,14 @@ class Decomposition:
         order = np.argsort(minid, kind="stable")
         rank = np.empty_like(order)
         rank[order] = np.arange(order.size)
-        self.n_ent = len(uniq)
-        self.entity_key = uniq[order]               # (lo0..2, hi0..2)
+        keys = uniq[order]
+        ent = rank[inv]
+        if coarse == "gdsw*":
+            ent, keys = self._group_vertices_and_edges(ent, keys, q2id)
+        self.n_ent = len(keys)
+        self.entity_key = keys                       # (lo0..2, hi0..2)
         self.gamma = g
-        self.gamma_entity = rank[inv]                # entity of each Gamma DOF
+        self.gamma_entity = ent                      # entity of each Gamma DOF
         self.gamma_field = field[g]
 
         # coarse columns (e, f) that carry at least one DOF
@@ -117,10 +146,47 @@ class Decomposition:
         self.n_coarse = int(has.sum())
         self.coarse_entity = np.repeat(np.arange(self.n_ent), 4).reshape(self.n_ent, 4)[has]
         self.coarse_field = np.tile(np.arange(4), (self.n_ent, 1))[has]
+        # discontinuous pressure: one constant pressure column per subdomain
+        self.sub_pressure_col = None
+        if disc:
+            self.sub_pressure_col = self.n_coarse + np.arange(self.n_sub)
+            self.coarse_entity = np.concatenate([self.coarse_entity, self.n_ent + np.arange(self.n_sub)])
+            self.coarse_field = np.concatenate([self.coarse_field, np.full(self.n_sub, 3)])
+            self.n_coarse += self.n_sub
+
+    @staticmethod
+    def _kind_size(key):
+        return int(np.prod(key[3:] - key[:3] + 1))
+
+    def _group_vertices_and_edges(self, ent, keys, q2id):
+        """GDSW*: merge each edge class (4 subdomains) into the first adjacent
+        vertex class (8 subdomains, set containing the edge's) in entity
+        order; faces and unmatched classes stay.  Returns the new entity of
+        every Gamma DOF and the keys, re-ordered by smallest node id."""
+        size = np.array([self._kind_size(k) for k in keys])
+        target = np.arange(len(keys))
+        verts = np.nonzero(size == 8)[0]
+        for e in np.nonzero(size == 4)[0]:
+            lo, hi = keys[e, :3], keys[e, 3:]
+            for v in verts:  # ascending entity order: the first match wins
+                if np.all(keys[v, :3] <= lo) and np.all(hi <= keys[v, 3:]):
+                    target[e] = v
+                    break
+        groups = np.unique(target)
+        new = np.searchsorted(groups, target)[ent]
+        minid = np.full(groups.size, np.iinfo(np.int64).max)
+        np.minimum.at(minid, new, q2id)
+        order = np.argsort(minid, kind="stable")
+        rank = np.empty_like(order)
+        rank[order] = np.arange(order.size)
+        return rank[new], keys[groups][order]
 
     # --- entity bookkeeping -------------------------------------------------
     def entity_subdomains(self, e):
-        """Sorted subdomain indices of entity e."""
+        """Sorted subdomain indices of entity e (e >= n_ent: the pressure
+        column of subdomain e - n_ent)."""
+        if e >= self.n_ent:
+            return [int(e - self.n_ent)]
         lo, hi = self.entity_key[e, :3], self.entity_key[e, 3:]
         out = []
         for K in range(lo[2], hi[2] + 1):

@@ -15,6 +15,18 @@ Definitions followed, in the paper's notation:
   null-space vector of field f (a velocity translation or the pressure
   constant) restricted to interface entity e, i.e. 1 on e's f-DOFs.
 
+Discontinuous pressure (the paper's Q2/P1disc pair, Section 3, last
+paragraph): there is no pressure interface, and the coarse space carries one
+pressure column per subdomain, constant over it (the pressure null-space
+vector on the subdomain's pressure DOFs).  The monolithic extension is then
+singular on interior subdomains (velocity fixed on the whole subdomain
+boundary leaves the constant pressure free), so this variant extends the
+velocity columns with the velocity block alone, Phi_I = -K_II^{-1} K_IGamma
+Phi_Gamma over the interior velocity DOFs, and takes the pressure columns as
+they are: the off-diagonal blocks Phi_{I,u0,p} and Phi_{I,p0,u} are zero
+(``extension="velocity"``, the default whenever subdomain pressure columns
+exist).
+
 Every dense factorisation -- the local matrices A_i, the interior blocks
 A_II of the extension and the coarse matrix A_0 -- is LAPACK's LU with partial
 pivoting (``scipy.linalg.lu_factor``): the paper names no direct solver, and
@@ -34,8 +46,13 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 
 
-def coarse_basis(A, dec):
-    """Phi (free DOFs x coarse DOFs) of eq. (2.4), as a CSR matrix."""
+def coarse_basis(A, dec, extension="monolithic"):
+    """Phi (free DOFs x coarse DOFs) of eq. (2.4), as a CSR matrix.
+
+    extension="monolithic": Phi_I = -A_II^{-1} A_IGamma Phi_Gamma with the
+    saddle-point block; "velocity": the same over the interior velocity DOFs
+    with the velocity block only, zero pressure rows, plus the subdomain
+    pressure columns (discontinuous pressure)."""
     nf = A.shape[0]
     rows, cols, vals = [], [], []
     # Phi_Gamma: indicator of each (entity, field)
@@ -48,6 +65,13 @@ def coarse_basis(A, dec):
     A = A.tocsr()
     for i in range(dec.n_sub):
         Ii = dec.I[i]
+        if extension == "velocity":
+            if dec.sub_pressure_col is not None:
+                Pi = Ii[dec.dof_field[Ii] == 3]
+                rows.append(Pi)
+                cols.append(np.full(Pi.size, dec.sub_pressure_col[i]))
+                vals.append(dec.dof_null[Pi])
+            Ii = Ii[dec.dof_field[Ii] < 3]
         if Ii.size == 0:
             continue
         AII = A[Ii][:, Ii].toarray()
@@ -70,9 +94,12 @@ def coarse_basis(A, dec):
 class TwoLevelGDSW:
     """B_GDSW of eq. (2.2) for an assembled problem and its decomposition."""
 
-    def __init__(self, A, dec, factor_local=True):
+    def __init__(self, A, dec, factor_local=True, extension=None):
         self.A = A.tocsr()
         self.dec = dec
+        if extension is None:
+            extension = "velocity" if getattr(dec, "sub_pressure_col", None) is not None else "monolithic"
+        self.extension = extension
         self.S = dec.S
         self.local_lu = []
         if factor_local:
@@ -80,7 +107,7 @@ class TwoLevelGDSW:
                 Ai = self.A[Si][:, Si].toarray()
                 self.local_lu.append(sla.lu_factor(Ai, check_finite=False))
         if dec.n_coarse > 0:
-            self.Phi = coarse_basis(self.A, dec)
+            self.Phi = coarse_basis(self.A, dec, extension)
             self.A0 = (self.Phi.T @ (self.A @ self.Phi)).toarray()
             self.A0_lu = sla.lu_factor(self.A0, check_finite=False)
         else:

@@ -22,9 +22,17 @@ Readings where the paper is silent (all pinned by tests):
   all free velocity DOFs first (Q2 nodes lexicographic with x fastest, then
   component), then every pressure DOF (Q1 nodes lexicographic).
 
-Pins: closed-form DOF counts; exact recovery of the quadratic Poiseuille
-profile with the manufactured body force, and of a flow with a linear
-pressure (``tests/test_oracle_stokes.py``).
+The paper's own pair (Section 2 and the last paragraph of Section 3), Q2
+velocity with P1-discontinuous pressure, is built with ``pressure="p1disc"``:
+four pressure DOFs per hexahedron, the basis 1, 2 xi - 1, 2 eta - 1,
+2 zeta - 1 in the element's reference coordinates (any basis of the linear
+functions spans the same space; this one holds the constant as its first
+function), numbered 4 e + k after the velocity DOFs, each attached to its
+element's centre node for the decomposition.
+
+Pins: closed-form DOF counts (both pairs); exact recovery of the quadratic
+Poiseuille profile with the manufactured body force, and of a flow with a
+linear pressure, for both pairs (``tests/test_oracle_stokes.py``).
 """
 from __future__ import annotations
 
@@ -60,12 +68,13 @@ def gauss3():
     return pts, wts
 
 
-def reference_element():
-    """Tabulate the 27 Q2 and 8 Q1 tensor-product shape functions at the
-    27 quadrature points of the reference cube.
+def reference_element(pressure="q1"):
+    """Tabulate the 27 Q2 and the pressure shape functions at the 27
+    quadrature points of the reference cube.
 
-    Local node index a = ax + 3*(ay + 3*az) for Q2, q = qx + 2*(qy + 2*qz) for Q1.
-    Returns (points[27,3], weights[27], phi[27,27], dphi[27,27,3], psi[27,8]),
+    Local node index a = ax + 3*(ay + 3*az) for Q2, q = qx + 2*(qy + 2*qz) for
+    Q1; for P1disc the four functions 1, 2x-1, 2y-1, 2z-1.
+    Returns (points[27,3], weights[27], phi[27,27], dphi[27,27,3], psi[27,np]),
     rows indexed by quadrature point.
     """
     x, w = gauss3()
@@ -88,10 +97,13 @@ def reference_element():
                                         L[0][ax] * dL[1][ay] * L[2][az],
                                         L[0][ax] * L[1][ay] * dL[2][az]])
                 ps = []
-                for qz in range(2):
-                    for qy in range(2):
-                        for qx in range(2):
-                            ps.append(N[0][qx] * N[1][qy] * N[2][qz])
+                if pressure == "p1disc":
+                    ps = [1.0, 2.0 * xi[0] - 1.0, 2.0 * xi[1] - 1.0, 2.0 * xi[2] - 1.0]
+                else:
+                    for qz in range(2):
+                        for qy in range(2):
+                            for qx in range(2):
+                                ps.append(N[0][qx] * N[1][qy] * N[2][qz])
                 phi.append(ph)
                 dphi.append(dph)
                 psi.append(ps)
@@ -99,13 +111,13 @@ def reference_element():
             np.array(psi))
 
 
-def element_matrices(h, mu):
+def element_matrices(h, mu, pressure="q1"):
     """Element blocks of eq. (2.1) on a cube of edge h.
 
     K[a, b]       = mu * int grad phi_a . grad phi_b           (27 x 27, per component)
-    B[q, a, c]    = - int psi_q d(phi_a)/dx_c                  (8 x 27 x 3)
+    B[q, a, c]    = - int psi_q d(phi_a)/dx_c                  (np x 27 x 3; np = 8 or 4)
     """
-    _, W, _, dphi, psi = reference_element()
+    _, W, _, dphi, psi = reference_element(pressure)
     # grad in physical coordinates = grad_ref / h, dx = h^3 dxi
     K = mu * h * np.einsum("q,qad,qbd->ab", W, dphi, dphi)
     B = -(h * h) * np.einsum("q,qp,qac->pac", W, psi, dphi)
@@ -125,7 +137,10 @@ class StokesProblem:
     """
 
     def __init__(self, n, viscosity=1.0, inflow=16.0, manufactured=0,
-                 dirichlet=None, force=None, chunk=2048):
+                 dirichlet=None, force=None, chunk=2048, pressure="q1"):
+        if pressure not in ("q1", "p1disc"):
+            raise ValueError("pressure must be 'q1' or 'p1disc'")
+        self.pressure = pressure
         self.n = n
         self.mu = float(viscosity)
         self.c = float(inflow)
@@ -133,7 +148,9 @@ class StokesProblem:
         N2 = 2 * n + 1
         self.n_q2 = N2 ** 3
         self.n_q1 = (n + 1) ** 3
-        self.n_full = 3 * self.n_q2 + self.n_q1
+        disc = pressure == "p1disc"
+        self.n_pdof = 4 * n ** 3 if disc else self.n_q1
+        self.n_full = 3 * self.n_q2 + self.n_pdof
 
         if dirichlet is None:
             c = self.c
@@ -167,35 +184,48 @@ class StokesProblem:
         self.q1_ijk = np.stack([pi, pj, pk], 1)
 
         # full DOF numbering: velocity 3*node + comp, pressure 3*n_q2 + pid
+        # (Q1) or 3*n_q2 + 4*e + k (P1disc, element e, basis function k)
         vel_dir = np.repeat(dir_node, 3)
-        is_dir = np.concatenate([vel_dir, np.zeros(self.n_q1, dtype=bool)])
+        is_dir = np.concatenate([vel_dir, np.zeros(self.n_pdof, dtype=bool)])
         self.full_is_dirichlet = is_dir
         self.free = np.nonzero(~is_dir)[0]
         self.dir = np.nonzero(is_dir)[0]
         self.n_u = int((~vel_dir).sum())
-        self.n_p = self.n_q1
+        self.n_p = self.n_pdof
         self.n_free = self.free.size
 
-        # per free DOF: node coordinates in half-element units and field
-        node_abc = np.concatenate([np.repeat(self.q2_abc, 3, axis=0),
-                                   2 * self.q1_ijk])
+        # per free DOF: node coordinates in half-element units and field;
+        # a P1disc pressure DOF sits at its element's centre node
+        if disc:
+            e_all = np.arange(n ** 3)
+            cen = np.stack([2 * (e_all % n) + 1, 2 * ((e_all // n) % n) + 1, 2 * (e_all // (n * n)) + 1], 1)
+            p_abc = np.repeat(cen, 4, axis=0)
+            p_null = np.tile([1.0, 0.0, 0.0, 0.0], n ** 3)
+        else:
+            p_abc = 2 * self.q1_ijk
+            p_null = np.ones(self.n_q1)
+        node_abc = np.concatenate([np.repeat(self.q2_abc, 3, axis=0), p_abc])
         field = np.concatenate([np.tile([0, 1, 2], self.n_q2),
-                                np.full(self.n_q1, 3)])
-        q2id_of_full = np.concatenate([np.repeat(ids, 3),
-                                       2 * pi + N2 * (2 * pj + N2 * 2 * pk)])
+                                np.full(self.n_pdof, 3)])
+        q2id_of_full = node_abc[:, 0] + N2 * (node_abc[:, 1] + N2 * node_abc[:, 2])
         self.full_node_abc = node_abc
         self.full_field = field
         self.dof_node = node_abc[self.free]
         self.dof_field = field[self.free]
         self.dof_q2id = q2id_of_full[self.free]
+        # value of the field's null-space vector (translation or constant
+        # pressure) on each free DOF: 1, except the linear P1disc functions
+        self.dof_null = np.concatenate([np.ones(3 * self.n_q2), p_null])[self.free]
 
         # ---- assembly --------------------------------------------------------
-        Ke, Be = element_matrices(self.h, self.mu)
-        # element DOF map: 81 velocity (a, comp) with index 3*a + comp, then 8 pressure
-        Ae = np.zeros((89, 89))
+        Ke, Be = element_matrices(self.h, self.mu, pressure)
+        npe = Be.shape[0]
+        ne_dofs = 81 + npe
+        # element DOF map: 81 velocity (a, comp) with index 3*a + comp, then the pressure
+        Ae = np.zeros((ne_dofs, ne_dofs))
         for comp in range(3):
             Ae[comp:81:3, comp:81:3] = Ke
-        Bflat = Be.reshape(8, 81)  # (q, 3*a + c)
+        Bflat = Be.reshape(npe, 81)  # (q, 3*a + c)
         Ae[81:, :81] = Bflat
         Ae[:81, 81:] = Bflat.T
         self.Ae = Ae
@@ -208,20 +238,23 @@ class StokesProblem:
         q2n = ((2 * ex[:, None] + lx) + N2 * ((2 * ey[:, None] + ly)
                                               + N2 * (2 * ez[:, None] + lz)))
         vdofs = (3 * q2n[:, :, None] + np.arange(3)).reshape(ne, 81)
-        ql = np.arange(8)
-        qx, qy, qz = ql % 2, (ql // 2) % 2, ql // 4
-        q1n = ((ex[:, None] + qx) + (n + 1) * ((ey[:, None] + qy)
-                                               + (n + 1) * (ez[:, None] + qz)))
-        pdofs = 3 * self.n_q2 + q1n
-        edofs = np.concatenate([vdofs, pdofs], 1)  # (ne, 89)
+        if disc:
+            pdofs = 3 * self.n_q2 + 4 * e[:, None] + np.arange(4)
+        else:
+            ql = np.arange(8)
+            qx, qy, qz = ql % 2, (ql // 2) % 2, ql // 4
+            q1n = ((ex[:, None] + qx) + (n + 1) * ((ey[:, None] + qy)
+                                                   + (n + 1) * (ez[:, None] + qz)))
+            pdofs = 3 * self.n_q2 + q1n
+        edofs = np.concatenate([vdofs, pdofs], 1)  # (ne, 81 + npe)
         self.element_dofs = edofs
 
         Afull = sp.csr_matrix((self.n_full, self.n_full))
         for s0 in range(0, ne, chunk):
             ed = edofs[s0:s0 + chunk]
             k = ed.shape[0]
-            rows = np.repeat(ed, 89, axis=1).ravel()
-            cols = np.tile(ed, (1, 89)).ravel()
+            rows = np.repeat(ed, ne_dofs, axis=1).ravel()
+            cols = np.tile(ed, (1, ne_dofs)).ravel()
             vals = np.tile(Ae.ravel(), k)
             Afull = Afull + sp.csr_matrix((vals, (rows, cols)),
                                           shape=(self.n_full, self.n_full))
@@ -231,7 +264,7 @@ class StokesProblem:
         # load vector F = int f . phi
         F = np.zeros(self.n_full)
         if force is not None:
-            P, W, phi, _, _ = reference_element()
+            P, W, phi, _, _ = reference_element(pressure)
             h = self.h
             for s0 in range(0, ne, chunk):
                 sl = slice(s0, s0 + chunk)
@@ -264,11 +297,27 @@ class StokesProblem:
         return x
 
     def interpolant(self, u, p):
-        """Nodal interpolant of (u, p) on the full DOF vector."""
+        """Nodal interpolant of (u, p) on the full DOF vector.  For P1disc the
+        pressure coefficients are those of a function linear in x, y, z:
+        the value at the element centre and half the change across the
+        element along each axis."""
         xyz = self.q2_abc * (self.h / 2.0)
         uv = u(xyz[:, 0], xyz[:, 1], xyz[:, 2])
-        pq = self.q1_ijk * self.h
-        pv = p(pq[:, 0], pq[:, 1], pq[:, 2])
+        if self.pressure == "p1disc":
+            n, h = self.n, self.h
+            e = np.arange(n ** 3)
+            c = np.stack([e % n, (e // n) % n, e // (n * n)], 1) * h + 0.5 * h
+            pc = np.asarray(p(c[:, 0], c[:, 1], c[:, 2]), dtype=float) * np.ones(n ** 3)
+            coef = [pc]
+            for ax in range(3):
+                d = np.zeros(3)
+                d[ax] = 0.5 * h
+                pp = np.asarray(p(c[:, 0] + d[0], c[:, 1] + d[1], c[:, 2] + d[2]), dtype=float) * np.ones(n ** 3)
+                coef.append(pp - pc)
+            pv = np.stack(coef, 1).ravel()
+        else:
+            pq = self.q1_ijk * self.h
+            pv = p(pq[:, 0], pq[:, 1], pq[:, 2])
         return np.concatenate([np.asarray(uv).T.ravel(), np.asarray(pv, dtype=float)])
 
 

@@ -29,19 +29,21 @@ _lib = C.CDLL(LIB_PATH)
 FP64, FP32, BF16 = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
 LOCAL_SOLVES = {"inverse": 0, "triangular": 1, "symmetric": 2}
+PRESSURE_ELEMENTS = {"q1": 0, "p1disc": 1}
+COARSE_SPACES = {"gdsw": 0, "gdsw*": 1}
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "ESINGULAR", 4: "ENOCONV", 5: "EDEVICE", 6: "EUNSUPPORTED"}
 
 
 class Mesh(C.Structure):
     _fields_ = [("n", C.c_int32), ("manufactured_force", C.c_int32), ("viscosity", C.c_double),
-                ("inflow_amplitude", C.c_double)]
+                ("inflow_amplitude", C.c_double), ("pressure_element", C.c_int32)]
 
 
 class Decomposition(C.Structure):
     _fields_ = [("subdomains", C.c_int32), ("overlap", C.c_int32), ("levels", C.c_int32), ("group", C.c_int32),
                 ("local_precision", C.c_int32), ("tile", C.c_int32), ("local_algebraic", C.c_int32),
                 ("level2_layer", C.c_int32), ("device_mem_budget", C.c_uint64), ("local_solve", C.c_int32),
-                ("max_rhs", C.c_int32)]
+                ("max_rhs", C.c_int32), ("coarse_space", C.c_int32)]
 
 
 class FgmresOpts(C.Structure):
@@ -51,7 +53,8 @@ class FgmresOpts(C.Structure):
 
 class FgmresInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("restarts", C.c_int32), ("rel_res", C.c_double),
-                ("true_rel_res", C.c_double), ("t_solve_s", C.c_double)]
+                ("true_rel_res", C.c_double), ("t_solve_s", C.c_double), ("learned_solves", C.c_int64),
+                ("fallbacks", C.c_int64)]
 
 
 class Sizes(C.Structure):
@@ -96,6 +99,10 @@ _sig = {
     "gdsw_set_local_solver": (C.c_int, [_P, C.c_int32, C.c_double]),
     "gdsw_learned_stats": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "gdsw_learned_copy": (C.c_int, [_P, _P, _P]),
+    "gdsw_learned_save": (C.c_int, [_P, C.c_char_p, _P]),
+    "gdsw_learned_load": (C.c_int, [_P, C.c_char_p, _P]),
+    "gdsw_train_local_net": (C.c_int, [_P, C.c_char_p, C.c_int32, C.c_uint64, _P]),
+    "gdsw_setup_times": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "gdsw_last_error": (C.c_char_p, [_P]),
     "gdsw_destroy": (None, [_P]),
     "gdsw_setup_batch": (C.c_int, [C.POINTER(Mesh), C.POINTER(Decomposition), C.c_int32, _P, C.POINTER(_P)]),
@@ -153,13 +160,13 @@ class Solver:
 
     def __init__(self, n, m, overlap=1, levels=2, group=2, precision="fp64", tile=0, viscosity=1.0,
                  inflow=16.0, manufactured=0, budget=0, host_only=False, stream=None, local_algebraic=0,
-                 level2_layer=0, local_solve="inverse", max_rhs=1):
+                 level2_layer=0, local_solve="inverse", max_rhs=1, pressure="q1", coarse="gdsw"):
         self._ctx = C.c_void_p()
-        self.mesh = Mesh(n, manufactured, viscosity, inflow)
+        self.mesh = Mesh(n, manufactured, viscosity, inflow, PRESSURE_ELEMENTS[pressure])
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         solve = LOCAL_SOLVES[local_solve] if isinstance(local_solve, str) else int(local_solve)
         self.dec = Decomposition(m, overlap, levels, group, prec, tile, int(local_algebraic), int(level2_layer),
-                                 budget, solve, int(max_rhs))
+                                 budget, solve, int(max_rhs), COARSE_SPACES[coarse])
         if host_only:
             st = _lib.gdsw_setup_host(C.byref(self.mesh), C.byref(self.dec), C.byref(self._ctx))
         else:
@@ -175,6 +182,22 @@ class Solver:
         s = Sizes()
         _check(_lib.gdsw_get_sizes(self._ctx, C.byref(s)), self._ctx)
         return s
+
+    def setup_times(self):
+        """(symbolic, numeric) setup wall time in seconds."""
+        a, b = C.c_double(), C.c_double()
+        _check(_lib.gdsw_setup_times(self._ctx, C.byref(a), C.byref(b)), self._ctx)
+        return a.value, b.value
+
+    def learned_save(self, path, stream=None):
+        _check(_lib.gdsw_learned_save(self._ctx, os.fsencode(path), _stream(stream)), self._ctx)
+
+    def learned_load(self, path, stream=None):
+        _check(_lib.gdsw_learned_load(self._ctx, os.fsencode(path), _stream(stream)), self._ctx)
+
+    def train_local_net(self, out_weights=None, steps=600, seed=0, stream=None):
+        path = os.fsencode(out_weights) if out_weights is not None else None
+        _check(_lib.gdsw_train_local_net(self._ctx, path, int(steps), int(seed), _stream(stream)), self._ctx)
 
     def dof_map(self):
         field = np.zeros(self.n_free, dtype=np.int32)

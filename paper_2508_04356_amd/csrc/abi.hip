@@ -71,6 +71,8 @@ ProblemSpec spec_of(const gdsw_mesh* mesh, const gdsw_decomposition* dec) {
   s.group = dec->group;
   s.local_dirichlet = dec->local_algebraic == 0;
   s.level2_layer = dec->level2_layer != 0;
+  s.pressure = mesh->pressure_element;
+  s.coarse = dec->coarse_space;
   if (dec->local_precision < 0 || dec->local_precision > 2) throw std::invalid_argument("bad local_precision");
   if (dec->tile != 0 && dec->tile != 64 && dec->tile != 128) throw std::invalid_argument("tile must be 0, 64 or 128");
   if (dec->local_solve != GDSW_SOLVE_INVERSE && dec->local_solve != GDSW_SOLVE_TRIANGULAR &&
@@ -300,6 +302,8 @@ gdsw_status gdsw_fgmres_solve(gdsw_ctx* ctx, const double* b_dev, double* x_dev,
             info[k0 + j].rel_res = r[j].rel;
             info[k0 + j].true_rel_res = r[j].true_rel;
             info[k0 + j].t_solve_s = t;
+            info[k0 + j].fallbacks = 0;
+            info[k0 + j].learned_solves = 0;
           }
           all_conv = all_conv && r[j].converged;
         }
@@ -308,6 +312,8 @@ gdsw_status gdsw_fgmres_solve(gdsw_ctx* ctx, const double* b_dev, double* x_dev,
     }
     for (int k = 0; k < nrhs; ++k) {
       const auto t0 = std::chrono::steady_clock::now();
+      const LearnedSolve* Ls = ctx->c.learned;
+      const int64_t fb0 = Ls ? Ls->fallbacks : 0, ls0 = Ls ? Ls->learned_solves : 0;
       FgmresResult r = fgmres(ctx->c, b_dev + (int64_t)k * ld, x_dev + (int64_t)k * ld, opts->rtol, opts->restart,
                               opts->max_it, opts->use_graph != 0, (hipStream_t)stream,
                               k == 0 ? opts->history : nullptr, k == 0 ? opts->history_len : 0);
@@ -319,6 +325,8 @@ gdsw_status gdsw_fgmres_solve(gdsw_ctx* ctx, const double* b_dev, double* x_dev,
         info[k].rel_res = r.rel;
         info[k].true_rel_res = r.true_rel;
         info[k].t_solve_s = t;
+        info[k].fallbacks = Ls ? Ls->fallbacks - fb0 : 0;
+        info[k].learned_solves = Ls ? Ls->learned_solves - ls0 : 0;
       }
       all_conv = all_conv && r.converged;
     }
@@ -572,6 +580,38 @@ gdsw_status gdsw_learned_stats(const gdsw_ctx* ctx, int64_t* learned_solves, int
   return GDSW_OK;
 }
 
+gdsw_status gdsw_learned_save(const gdsw_ctx* ctx, const char* path, void* stream) {
+  if (gdsw_status s = check_device_ctx(ctx)) return s;
+  if (!path) return fail(const_cast<gdsw_ctx*>(ctx), GDSW_EINVAL, "NULL path");
+  return guarded(const_cast<gdsw_ctx*>(ctx), [&]() { learned_save(ctx->c, path, (hipStream_t)stream); });
+}
+
+gdsw_status gdsw_learned_load(gdsw_ctx* ctx, const char* path, void* stream) {
+  if (gdsw_status s = check_device_ctx(ctx)) return s;
+  if (!path) return fail(ctx, GDSW_EINVAL, "NULL path");
+  if (!ctx->c.learned) return fail(ctx, GDSW_EINVAL, "call gdsw_learned_init first");
+  return guarded(ctx, [&]() { learned_load(ctx->c, path, (hipStream_t)stream); });
+}
+
+gdsw_status gdsw_train_local_net(gdsw_ctx* ctx, const char* out_weights, int32_t steps, uint64_t seed, void* stream) {
+  if (gdsw_status s = check_device_ctx(ctx)) return s;
+  if (steps < 1) return fail(ctx, GDSW_EINVAL, "need steps >= 1");
+  return guarded(ctx, [&]() {
+    hipStream_t st = (hipStream_t)stream;
+    learned_init(ctx->c, seed, st);
+    if (ctx->c.learned->N == 0) learned_generate(ctx->c, 4, seed, st);
+    learned_train(ctx->c, steps, 32, 2e-3, seed + 1, nullptr, st);
+    if (out_weights) learned_save(ctx->c, out_weights, st);
+  });
+}
+
+gdsw_status gdsw_setup_times(const gdsw_ctx* ctx, double* symbolic_s, double* numeric_s) {
+  if (!ctx) return fail(nullptr, GDSW_EINVAL, "NULL context");
+  if (symbolic_s) *symbolic_s = ctx->c.t_symbolic;
+  if (numeric_s) *numeric_s = ctx->c.t_numeric;
+  return GDSW_OK;
+}
+
 const char* gdsw_last_error(const gdsw_ctx* ctx) {
   if (ctx) return ctx->c.last_error.c_str();
   return g_last_error.c_str();
@@ -647,6 +687,13 @@ gdsw_status gdsw_fgmres_solve_batch(gdsw_batch* batch, const double* const* b_de
   bool all_conv = true;
   const gdsw_status s = guarded(nullptr, [&]() {
     const auto t0 = std::chrono::steady_clock::now();
+    const size_t nm = batch->members.size();
+    std::vector<int64_t> fb0(nm, 0), ls0(nm, 0);
+    for (size_t k = 0; k < nm; ++k)
+      if (const LearnedSolve* L = batch->members[k]->c.learned) {
+        fb0[k] = L->fallbacks;
+        ls0[k] = L->learned_solves;
+      }
     std::vector<FgmresResult> r =
         fgmres_batch(batch->b, b_dev, x_dev, opts->rtol, opts->restart, opts->max_it, (hipStream_t)stream);
     GDSW_HIP(hipStreamSynchronize((hipStream_t)stream));
@@ -658,6 +705,9 @@ gdsw_status gdsw_fgmres_solve_batch(gdsw_batch* batch, const double* const* b_de
         info[k].rel_res = r[k].rel;
         info[k].true_rel_res = r[k].true_rel;
         info[k].t_solve_s = t;
+        const LearnedSolve* L = batch->members[k]->c.learned;
+        info[k].fallbacks = L ? L->fallbacks - fb0[k] : 0;
+        info[k].learned_solves = L ? L->learned_solves - ls0[k] : 0;
       }
       all_conv = all_conv && r[k].converged;
     }

@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+#include "kernels.h"
+
 namespace gdsw {
 
 // Device index structures of the coarse basis Phi (eq. 2.4), passed by value.
@@ -56,6 +58,15 @@ void restrict_coarse(int nc, const CoarseView& cv, const double* r, double* out,
 void phi_rhs(int64_t total_I, const CoarseView& cv, const int32_t* rowptr, const int32_t* col, const double* val,
              double* B, hipStream_t st);
 void phi_transpose(int64_t total_I, const CoarseView& cv, const double* cm, double* rm, hipStream_t st);
+// Discontinuous pressure (velocity-only extension): in every dense A_II^(i)
+// (column-major, ld = |I_i|, the first nu[i] rows/columns velocity) the rows
+// and columns of the pressure DOFs become those of the identity; in Phi_I the
+// pressure rows are set to their fixed values: pval on the subdomain's own
+// pressure column sub_pcol[i], 0 elsewhere (pval per interior position, < 0
+// on velocity rows, which are left alone).
+void decouple_pressure(const DenseBatch& B, const int32_t* nu, int max_n, hipStream_t st);
+void phi_pressure_rows(int64_t total_I, const CoarseView& cv, const int8_t* pval, const int32_t* sub_pcol,
+                       double* phi_cm, hipStream_t st);
 void phibox(int64_t total_D, const CoarseView& cv, const BoxView& bv, double* out, hipStream_t st);
 void own_spmm(int nbox, int max_nd, const CoarseView& cv, const BoxView& bv, const double* val,
               const double* phibox_, double* W, hipStream_t st);

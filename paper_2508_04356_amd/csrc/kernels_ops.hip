@@ -308,6 +308,29 @@ __global__ void phi_rhs_kernel(int64_t total_I, CoarseView cv, const int32_t* __
   }
 }
 
+__global__ void decouple_pressure_kernel(double* __restrict__ base, const int32_t* __restrict__ N,
+                                         const int32_t* __restrict__ LD, const int64_t* __restrict__ OFF,
+                                         const int32_t* __restrict__ NU) {
+  const int f = blockIdx.y;
+  const int n = N[f], nu = NU[f];
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  double* A = base + OFF[f] + (int64_t)c * LD[f];
+  for (int r = c < nu ? nu : 0; r < n; ++r) A[r] = r == c ? 1.0 : 0.0;
+}
+
+__global__ void phi_pressure_rows_kernel(int64_t total_I, CoarseView cv, const int8_t* __restrict__ pval,
+                                         const int32_t* __restrict__ sub_pcol, double* __restrict__ B) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= total_I || pval[p] < 0) return;
+  const int i = cv.I_sub[p];
+  const int ib = cv.I_ptr[i], ni = cv.I_ptr[i + 1] - ib;
+  const int k = (int)(p - ib);
+  const int cb = cv.C_ptr[i], nc = cv.C_ptr[i + 1] - cb;
+  double* Bi = B + cv.phi_off[i];
+  for (int lc = 0; lc < nc; ++lc) Bi[(int64_t)lc * ni + k] = cv.C_idx[cb + lc] == sub_pcol[i] ? (double)pval[p] : 0.0;
+}
+
 __global__ void phi_transpose_kernel(int64_t total_I, CoarseView cv, const double* __restrict__ cm,
                                      double* __restrict__ rm) {
   const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -741,6 +764,19 @@ void phi_rhs(int64_t total_I, const CoarseView& cv, const int32_t* rowptr, const
 void phi_transpose(int64_t total_I, const CoarseView& cv, const double* cm, double* rm, hipStream_t st) {
   if (total_I == 0) return;
   phi_transpose_kernel<<<(unsigned)((total_I + 127) / 128), 128, 0, st>>>(total_I, cv, cm, rm);
+}
+
+void decouple_pressure(const DenseBatch& B, const int32_t* nu, int max_n, hipStream_t st) {
+  if (B.count == 0 || max_n == 0) return;
+  decouple_pressure_kernel<<<dim3((max_n + 127) / 128, B.count), 128, 0, st>>>(B.base, B.n, B.ld, B.off, nu);
+  GDSW_HIP(hipGetLastError());
+}
+
+void phi_pressure_rows(int64_t total_I, const CoarseView& cv, const int8_t* pval, const int32_t* sub_pcol,
+                       double* phi_cm, hipStream_t st) {
+  if (total_I == 0) return;
+  phi_pressure_rows_kernel<<<(unsigned)((total_I + 127) / 128), 128, 0, st>>>(total_I, cv, pval, sub_pcol, phi_cm);
+  GDSW_HIP(hipGetLastError());
 }
 
 void phibox(int64_t total_D, const CoarseView& cv, const BoxView& bv, double* out, hipStream_t st) {

@@ -67,6 +67,9 @@ void learned_interior_finish(Context& ctx, hipStream_t st);
 // dst's network (weights and output scales) <- src's; same interior grid.
 void learned_copy(Context& dst, const Context& src, hipStream_t st);
 void learned_release(Context& ctx);
+// the trained network (FP32 master weights and output scales) to / from a file
+void learned_save(const Context& ctx, const char* path, hipStream_t st);
+void learned_load(Context& ctx, const char* path, hipStream_t st);
 void learned_set_weights(Context& ctx, const float* host, hipStream_t st);
 void learned_get_weights(Context& ctx, float* host, int which, hipStream_t st);
 double learned_loss_grad(Context& ctx, const float* X, const float* T, int B, float* grads, hipStream_t st);

@@ -7,6 +7,10 @@
 // local residual ||r_i - A_i N(r_i)|| exceeds tau ||r_i|| is re-solved by LU.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+#include <cstring>
+#include <string>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -39,6 +43,7 @@ void learned_init(Context& ctx, uint64_t seed, hipStream_t st) {
   Problem& P = ctx.P;
   const int m = P.spec.m;
   if (m < 3) throw StatusError{6, "the learned local solve needs interior subdomains (m >= 3)"};
+  if (P.spec.pressure != 0) throw StatusError{6, "the learned local solve is built for the Q1 pressure"};
   auto L = new LearnedSolve();
   ctx.learned = L;
   DeviceArena& A = ctx.arena;
@@ -356,6 +361,51 @@ void learned_copy(Context& dst, const Context& src, hipStream_t st) {
   D->adam_t = 0;
   D->trained = S->trained;
   GDSW_HIP(hipStreamSynchronize(st));
+}
+
+// File layout (little-endian): "GDSWNET1", int32 grid, int32 reserved,
+// int64 n_params, float sigma[4], float master[n_params].
+void learned_save(const Context& ctx, const char* path, hipStream_t st) {
+  const LearnedSolve* L = ctx.learned;
+  if (!L) throw StatusError{1, "no learned local solve (call gdsw_learned_init)"};
+  std::vector<float> w(L->n_params);
+  GDSW_HIP(hipMemcpyAsync(w.data(), L->d_master, L->n_params * sizeof(float), hipMemcpyDeviceToHost, st));
+  GDSW_HIP(hipStreamSynchronize(st));
+  FILE* f = std::fopen(path, "wb");
+  if (!f) throw StatusError{1, std::string("cannot open ") + path + " for writing"};
+  const int32_t hdr[2] = {L->G, 0};
+  const int64_t np = L->n_params;
+  bool ok = std::fwrite("GDSWNET1", 1, 8, f) == 8 && std::fwrite(hdr, sizeof hdr, 1, f) == 1 &&
+            std::fwrite(&np, sizeof np, 1, f) == 1 && std::fwrite(L->sigma, sizeof(float), 4, f) == 4 &&
+            std::fwrite(w.data(), sizeof(float), w.size(), f) == w.size();
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok) throw StatusError{1, std::string("writing ") + path + " failed"};
+}
+
+void learned_load(Context& ctx, const char* path, hipStream_t st) {
+  LearnedSolve* L = ctx.learned;
+  if (!L) throw StatusError{1, "no learned local solve (call gdsw_learned_init)"};
+  FILE* f = std::fopen(path, "rb");
+  if (!f) throw StatusError{1, std::string("cannot open ") + path};
+  char magic[8] = {};
+  int32_t hdr[2] = {};
+  int64_t np = 0;
+  float sigma[4] = {};
+  bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "GDSWNET1", 8) == 0 &&
+            std::fread(hdr, sizeof hdr, 1, f) == 1 && std::fread(&np, sizeof np, 1, f) == 1;
+  if (ok && (hdr[0] != L->G || np != L->n_params)) {
+    std::fclose(f);
+    throw StatusError{1, std::string(path) + ": the network was trained for another interior node grid"};
+  }
+  std::vector<float> w(ok ? (size_t)np : 0);
+  ok = ok && std::fread(sigma, sizeof(float), 4, f) == 4 && std::fread(w.data(), sizeof(float), w.size(), f) == w.size();
+  std::fclose(f);
+  if (!ok) throw StatusError{1, std::string(path) + " is not a network file of this library"};
+  learned_set_weights(ctx, w.data(), st);
+  for (int ch = 0; ch < 4; ++ch) L->sigma[ch] = sigma[ch];
+  GDSW_HIP(hipMemcpyAsync(L->d_sigma, L->sigma, 4 * sizeof(float), hipMemcpyHostToDevice, st));
+  GDSW_HIP(hipStreamSynchronize(st));
+  L->trained = true;
 }
 
 void learned_release(Context& ctx) {

@@ -22,7 +22,7 @@ struct ElementMatrix {
   double a[89][89];  // velocity (3*node + comp) then pressure (81 + q)
 };
 
-void element_matrix(double h, double mu, ElementMatrix& E) {
+void element_matrix(double h, double mu, bool disc, ElementMatrix& E) {
   // int L_a L_b, int L_a' L_b', int N_q L_a, int N_q L_a' on [0, 1]
   static const double Mr[3][3] = {{4, 2, -1}, {2, 16, 2}, {-1, 2, 4}};
   static const double Sr[3][3] = {{7, -8, 1}, {-8, 16, -8}, {1, -8, 7}};
@@ -46,6 +46,26 @@ void element_matrix(double h, double mu, ElementMatrix& E) {
                              M[ax][bx] * M[ay][by] * S[az][bz]);
       for (int comp = 0; comp < 3; ++comp) E.a[3 * a + comp][3 * b + comp] = k;
     }
+  }
+  if (disc) {
+    // P1disc: psi = 1, 2x - 1, 2y - 1, 2z - 1 on the reference cube; per axis
+    // int f L_a and int f L_a' for f = 1 and f = 2x - 1
+    static const double I1[3] = {1.0 / 6, 2.0 / 3, 1.0 / 6}, D1[3] = {-1.0, 0.0, 1.0};
+    static const double J1[3] = {-1.0 / 6, 0.0, 1.0 / 6}, JD[3] = {2.0 / 3, -4.0 / 3, 2.0 / 3};
+    for (int q = 0; q < 4; ++q)
+      for (int a = 0; a < 27; ++a) {
+        const int ai[3] = {a % 3, (a / 3) % 3, a / 9};
+        for (int comp = 0; comp < 3; ++comp) {
+          double v = -h * h;
+          for (int ax = 0; ax < 3; ++ax) {
+            const bool lin = q == ax + 1;  // psi_q is linear along this axis
+            v *= ax == comp ? (lin ? JD[ai[ax]] : D1[ai[ax]]) : (lin ? J1[ai[ax]] : I1[ai[ax]]);
+          }
+          E.a[81 + q][3 * a + comp] = v;
+          E.a[3 * a + comp][81 + q] = v;
+        }
+      }
+    return;
   }
   for (int q = 0; q < 8; ++q) {
     const int qx = q % 2, qy = (q / 2) % 2, qz = q / 4;
@@ -106,6 +126,14 @@ void build_problem(const ProblemSpec& spec, Problem& P, int threads) {
   if (spec.levels == 3 && (spec.group < 1 || m % spec.group != 0))
     throw std::invalid_argument("three levels need m % group == 0");
   if (!(spec.mu > 0.0)) throw std::invalid_argument("viscosity must be > 0");
+  if (spec.pressure != 0 && spec.pressure != 1) throw std::invalid_argument("pressure element must be 0 (Q1) or 1 (P1disc)");
+  if (spec.coarse != 0 && spec.coarse != 1) throw std::invalid_argument("coarse space must be 0 (GDSW) or 1 (GDSW*)");
+  const bool disc = spec.pressure == 1;
+  if (disc && spec.local_dirichlet)
+    throw std::invalid_argument("the P1disc pressure needs the algebraic overlap (local_algebraic = 1): with "
+                                "Dirichlet velocity on the whole artificial boundary the constant pressure of an "
+                                "interior local problem is a null vector");
+  if (disc && spec.levels == 3) throw std::invalid_argument("three levels with the P1disc pressure are not built");
   P.spec = spec;
   P.s = n / m;
   const int N2 = 2 * n + 1, N1 = n + 1;
@@ -115,7 +143,7 @@ void build_problem(const ProblemSpec& spec, Problem& P, int threads) {
   // free velocity node: a >= 1, 1 <= b <= 2n-1, 1 <= c <= 2n-1
   const int64_t fa = 2 * n, fb = 2 * n - 1;
   P.n_u = 3 * fa * fb * fb;
-  P.n_p = (int64_t)N1 * N1 * N1;
+  P.n_p = disc ? 4 * (int64_t)n * n * n : (int64_t)N1 * N1 * N1;
   P.n_free = P.n_u + P.n_p;
   P.n_full = 3 * (int64_t)N2 * N2 * N2 + P.n_p;
   auto vel_free = [&](int a, int b, int c) { return a >= 1 && b >= 1 && b <= 2 * n - 1 && c >= 1 && c <= 2 * n - 1; };
@@ -123,6 +151,8 @@ void build_problem(const ProblemSpec& spec, Problem& P, int threads) {
     return 3 * ((int64_t)(a - 1) + fa * ((int64_t)(b - 1) + fb * (c - 1))) + comp;
   };
   auto p_dof = [&](int i, int j, int k) -> int64_t { return P.n_u + i + (int64_t)N1 * (j + (int64_t)N1 * k); };
+  // P1disc: element e = ex + n (ey + n ez), basis function k
+  auto pe_dof = [&](int64_t e, int k) -> int64_t { return P.n_u + 4 * e + k; };
   auto inflow = [&](int a, int b, int c) -> double {  // x-velocity Dirichlet data
     if (a != 0) return 0.0;
     const double y = 0.5 * h * b, z = 0.5 * h * c;
@@ -130,6 +160,7 @@ void build_problem(const ProblemSpec& spec, Problem& P, int threads) {
   };
 
   P.field.assign(P.n_free, 0);
+  P.pnull.assign(P.n_free, 1);
   P.abc.assign(3 * P.n_free, 0);
   P.full_index.assign(P.n_free, 0);
   P.dirichlet_full.assign(P.n_full, 0.0);
@@ -150,20 +181,37 @@ void build_problem(const ProblemSpec& spec, Problem& P, int threads) {
           P.dirichlet_full[3 * node] = inflow(a, b, c);
         }
       }
-  for (int k = 0; k < N1; ++k)
-    for (int j = 0; j < N1; ++j)
-      for (int i = 0; i < N1; ++i) {
-        const int64_t d = p_dof(i, j, k);
-        P.field[d] = 3;
-        P.abc[3 * d] = 2 * i;
-        P.abc[3 * d + 1] = 2 * j;
-        P.abc[3 * d + 2] = 2 * k;
-        P.full_index[d] = 3 * (int64_t)N2 * N2 * N2 + (d - P.n_u);
-      }
+  if (disc) {
+    // a P1disc pressure DOF sits at its element's centre node
+    for (int ez = 0; ez < n; ++ez)
+      for (int ey = 0; ey < n; ++ey)
+        for (int ex = 0; ex < n; ++ex)
+          for (int k = 0; k < 4; ++k) {
+            const int64_t e = ex + (int64_t)n * (ey + (int64_t)n * ez), d = pe_dof(e, k);
+            P.field[d] = 3;
+            P.pnull[d] = k == 0;
+            P.abc[3 * d] = 2 * ex + 1;
+            P.abc[3 * d + 1] = 2 * ey + 1;
+            P.abc[3 * d + 2] = 2 * ez + 1;
+            P.full_index[d] = 3 * (int64_t)N2 * N2 * N2 + (d - P.n_u);
+          }
+  } else {
+    for (int k = 0; k < N1; ++k)
+      for (int j = 0; j < N1; ++j)
+        for (int i = 0; i < N1; ++i) {
+          const int64_t d = p_dof(i, j, k);
+          P.field[d] = 3;
+          P.abc[3 * d] = 2 * i;
+          P.abc[3 * d + 1] = 2 * j;
+          P.abc[3 * d + 2] = 2 * k;
+          P.full_index[d] = 3 * (int64_t)N2 * N2 * N2 + (d - P.n_u);
+        }
+  }
 
   // ---- assembly, one row at a time ---------------------------------------
   ElementMatrix E;
-  element_matrix(h, spec.mu, E);
+  element_matrix(h, spec.mu, disc, E);
+  const int npe = disc ? 4 : 8;  // pressure functions per element
   const double gt = std::sqrt(3.0 / 5.0);
   const double gp[3] = {0.5 - 0.5 * gt, 0.5, 0.5 + 0.5 * gt};
   const double gw[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
@@ -196,6 +244,8 @@ void build_problem(const ProblemSpec& spec, Problem& P, int threads) {
           int li;
           if (fr < 3) {
             li = 3 * ((A - 2 * ex) + 3 * ((B - 2 * ey) + 3 * (Cc - 2 * ez))) + fr;
+          } else if (disc) {
+            li = 81 + (int)((r - P.n_u) % 4);
           } else {
             li = 81 + (A / 2 - ex) + 2 * ((B / 2 - ey) + 2 * (Cc / 2 - ez));
           }
@@ -210,10 +260,12 @@ void build_problem(const ProblemSpec& spec, Problem& P, int threads) {
                 rhs -= v * inflow(ga, gb, gc);
             }
           }
-          for (int q = 0; q < 8; ++q) {
+          for (int q = 0; q < npe; ++q) {
             const double v = E.a[li][81 + q];
             if (v == 0.0) continue;
-            ent.emplace_back((int32_t)p_dof(ex + q % 2, ey + (q / 2) % 2, ez + q / 4), v);
+            ent.emplace_back((int32_t)(disc ? pe_dof(ex + (int64_t)n * (ey + (int64_t)n * ez), q)
+                                            : p_dof(ex + q % 2, ey + (q / 2) % 2, ez + q / 4)),
+                             v);
           }
           if (spec.manufactured && fr == 0) {
             // int f_x phi = h^3 int L_ax dxi * int int f(y, z) L_ay L_az (3-point Gauss, exact)
@@ -280,9 +332,17 @@ void build_problem(const ProblemSpec& spec, Problem& P, int threads) {
         for (int a = lo_a; a <= hi_a; ++a)
           if (vel_free(a, b, c))
             for (int comp = 0; comp < 3; ++comp) out.push_back((int32_t)vel_dof(a, b, c, comp));
-    for (int k = (lo_c + 1) / 2; 2 * k <= hi_c; ++k)
-      for (int j = (lo_b + 1) / 2; 2 * j <= hi_b; ++j)
-        for (int i = (lo_a + 1) / 2; 2 * i <= hi_a; ++i) out.push_back((int32_t)p_dof(i, j, k));
+    if (disc) {  // elements whose centre node lies in the box
+      for (int ez = lo_c / 2; ez < n && 2 * ez + 1 <= hi_c; ++ez)
+        for (int ey = lo_b / 2; ey < n && 2 * ey + 1 <= hi_b; ++ey)
+          for (int ex = lo_a / 2; ex < n && 2 * ex + 1 <= hi_a; ++ex)
+            for (int k = 0; k < 4; ++k)
+              out.push_back((int32_t)pe_dof(ex + (int64_t)n * (ey + (int64_t)n * ez), k));
+    } else {
+      for (int k = (lo_c + 1) / 2; 2 * k <= hi_c; ++k)
+        for (int j = (lo_b + 1) / 2; 2 * j <= hi_b; ++j)
+          for (int i = (lo_a + 1) / 2; 2 * i <= hi_a; ++i) out.push_back((int32_t)p_dof(i, j, k));
+    }
   };
   P.S.resize(P.n_sub);
   P.D.resize(P.n_sub);
@@ -327,17 +387,53 @@ void build_problem(const ProblemSpec& spec, Problem& P, int threads) {
     const int64_t q2id = P.abc[3 * d] + (int64_t)N2 * (P.abc[3 * d + 1] + (int64_t)N2 * P.abc[3 * d + 2]);
     ent_min[e] = std::min(ent_min[e], q2id);
   }
-  P.n_ent = (int)ent_min.size();
-  std::vector<int> order(P.n_ent);
-  for (int e = 0; e < P.n_ent; ++e) order[e] = e;
+  const int n_cls = (int)ent_min.size();
+  std::vector<int> order(n_cls);
+  for (int e = 0; e < n_cls; ++e) order[e] = e;
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return ent_min[x] < ent_min[y]; });
-  std::vector<int> rank(P.n_ent);
-  for (int r = 0; r < P.n_ent; ++r) rank[order[r]] = r;
+  std::vector<int> rank(n_cls);
+  for (int r = 0; r < n_cls; ++r) rank[order[r]] = r;
+  std::vector<std::array<int32_t, 6>> cls_key(n_cls);
+  for (auto& kv : ent_of) cls_key[rank[kv.second]] = kv.first;
+  // entity of each class (by class rank): itself, or with GDSW* the first
+  // adjacent vertex class (in node order) whose subdomain box contains it
+  std::vector<int> target(n_cls);
+  for (int r = 0; r < n_cls; ++r) target[r] = r;
+  if (spec.coarse == 1) {
+    auto size_of = [](const std::array<int32_t, 6>& k) {
+      return (k[3] - k[0] + 1) * (k[4] - k[1] + 1) * (k[5] - k[2] + 1);
+    };
+    std::vector<int> verts;
+    for (int r = 0; r < n_cls; ++r)
+      if (size_of(cls_key[r]) == 8) verts.push_back(r);
+    for (int r = 0; r < n_cls; ++r) {
+      if (size_of(cls_key[r]) != 4) continue;
+      const auto& ke = cls_key[r];
+      for (int v : verts) {
+        const auto& kv = cls_key[v];
+        if (kv[0] <= ke[0] && kv[1] <= ke[1] && kv[2] <= ke[2] && ke[3] <= kv[3] && ke[4] <= kv[4] && ke[5] <= kv[5]) {
+          target[r] = v;
+          break;
+        }
+      }
+    }
+  }
+  // entities: the distinct targets, ordered by the smallest node id of their merged classes
+  std::vector<int64_t> grp_min(n_cls, INT64_MAX);
+  for (int r = 0; r < n_cls; ++r) grp_min[target[r]] = std::min(grp_min[target[r]], ent_min[order[r]]);
+  std::vector<int> groups;
+  for (int r = 0; r < n_cls; ++r)
+    if (target[r] == r) groups.push_back(r);
+  std::stable_sort(groups.begin(), groups.end(), [&](int x, int y) { return grp_min[x] < grp_min[y]; });
+  std::vector<int> ent_of_grp(n_cls, -1);
+  for (size_t q = 0; q < groups.size(); ++q) ent_of_grp[groups[q]] = (int)q;
+  P.n_ent = (int)groups.size();
   P.ent_key.assign(P.n_ent, {});
-  for (auto& kv : ent_of) P.ent_key[rank[kv.second]] = kv.first;
+  for (int q = 0; q < P.n_ent; ++q) P.ent_key[q] = cls_key[groups[q]];
+  auto entity_of = [&](int64_t d) { return ent_of_grp[target[rank[ent_tmp[d]]]]; };
   std::vector<std::array<int, 4>> has(P.n_ent, {0, 0, 0, 0});
   for (int64_t d = 0; d < P.n_free; ++d)
-    if (ent_tmp[d] >= 0) has[rank[ent_tmp[d]]][P.field[d]] = 1;
+    if (ent_tmp[d] >= 0) has[entity_of(d)][P.field[d]] = 1;
   std::vector<std::array<int32_t, 4>> colof(P.n_ent, {-1, -1, -1, -1});
   P.coarse_entity.clear();
   P.coarse_field.clear();
@@ -348,15 +444,30 @@ void build_problem(const ProblemSpec& spec, Problem& P, int threads) {
         P.coarse_entity.push_back(e);
         P.coarse_field.push_back(f);
       }
-  P.n_coarse = (int)P.coarse_entity.size();
   P.gamma_col.assign(P.n_free, -1);
   for (int64_t d = 0; d < P.n_free; ++d)
-    if (ent_tmp[d] >= 0) P.gamma_col[d] = colof[rank[ent_tmp[d]]][P.field[d]];
+    if (ent_tmp[d] >= 0) P.gamma_col[d] = colof[entity_of(d)][P.field[d]];
   P.C.assign(P.n_sub, {});
   for (int e = 0; e < P.n_ent; ++e)
     for (int32_t i : entity_subdomains(P, e))
       for (int f = 0; f < 4; ++f)
         if (colof[e][f] >= 0) P.C[i].push_back(colof[e][f]);
+  // discontinuous pressure: no pressure interface; one pressure column per
+  // subdomain, constant over it, after the interface columns (Section 3)
+  P.sub_pcol.clear();
+  if (disc && P.n_sub > 1) {
+    for (int K = 0; K < m; ++K)
+      for (int J = 0; J < m; ++J)
+        for (int I = 0; I < m; ++I) {
+          const int i = I + m * (J + m * K);
+          P.ent_key.push_back({I, J, K, I, J, K});
+          P.sub_pcol.push_back((int32_t)P.coarse_entity.size());
+          P.coarse_entity.push_back(P.n_ent + i);
+          P.coarse_field.push_back(3);
+          P.C[i].push_back(P.sub_pcol.back());
+        }
+  }
+  P.n_coarse = (int)P.coarse_entity.size();
   for (auto& Ci : P.C) std::sort(Ci.begin(), Ci.end());
 
   // ---- three-level bookkeeping (eq. 2.5) ---------------------------------

@@ -23,6 +23,8 @@ struct ProblemSpec {
   int manufactured = 0;
   int local_dirichlet = 1;  // 1: drop the artificial boundary of the grown box
   int level2_layer = 0;     // 1: level-2 local sets get one more A_0-graph layer
+  int pressure = 0;         // 0: Q1 (continuous); 1: P1disc (4 DOFs per hexahedron)
+  int coarse = 0;           // 0: full GDSW entities; 1: GDSW* (vertex + adjacent edges)
 };
 
 // Level-2 (coarse) structures for the three-level method (eq. 2.5).
@@ -61,8 +63,14 @@ struct Problem {
   std::vector<int8_t> multiplicity;            // closed boxes holding each DOF
 
   // interface entities and coarse columns
-  int n_ent = 0;
-  std::vector<std::array<int32_t, 6>> ent_key; // lo_x, lo_y, lo_z, hi_x, hi_y, hi_z
+  int n_ent = 0;                               // interface entities
+  std::vector<std::array<int32_t, 6>> ent_key; // lo_x, lo_y, lo_z, hi_x, hi_y, hi_z; with a
+                                               // discontinuous pressure, n_sub more keys
+                                               // (i, i): the subdomains' pressure constants
+  std::vector<int32_t> sub_pcol;               // discontinuous pressure: pressure column of
+                                               // each subdomain (constant over it), else empty
+  std::vector<int8_t> pnull;                   // per DOF: 1 where the field's null-space
+                                               // vector is 1 (0 on linear P1disc functions)
   std::vector<int32_t> gamma_col;              // per DOF: coarse column or -1
   int n_coarse = 0;
   std::vector<int32_t> coarse_entity, coarse_field;

@@ -614,14 +614,41 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
     B.count = P.n_sub;
     B.max_n = max_ni;
     extract_local(B, ctx.d_I_ptr, ctx.d_I_idx, ctx.d_rowptr, ctx.d_col, ctx.d_val, max_ni, st);
+    // discontinuous pressure: the velocity columns are extended with the
+    // velocity block alone and the pressure rows of Phi_I are fixed (the
+    // subdomain's constant pressure column), so the pressure part of A_II
+    // becomes the identity
+    const bool disc = !P.sub_pcol.empty();
+    int32_t* d_nu = nullptr;
+    int8_t* d_pval = nullptr;
+    int32_t* d_sub_pcol = nullptr;
+    if (disc) {
+      std::vector<int32_t> nu(P.n_sub, 0);
+      std::vector<int8_t> pval(total_I, -1);
+      for (int i = 0; i < P.n_sub; ++i)
+        for (int32_t q = I_ptr[i]; q < I_ptr[i + 1]; ++q) {
+          const int32_t d = I_idx[q];
+          if (P.field[d] < 3)
+            ++nu[i];
+          else
+            pval[q] = P.pnull[d];
+        }
+      d_nu = dupload(A, nu, st);
+      d_pval = dupload(A, pval, st);
+      d_sub_pcol = dupload(A, P.sub_pcol, st);
+      decouple_pressure(B, d_nu, max_ni, st);
+    }
     unsigned long long* mp = minpiv_buffer(A, P.n_sub, st);
     lu_nopiv(B, mp, st);
     check_pivots(mp, P.n_sub, 1e-14 * amax, "interior block", st);
     GDSW_HIP(hipMemsetAsync(ctx.d_phi_cm, 0, std::max<int64_t>(phi_off.back(), 1) * 8, st));
     phi_rhs(total_I, cv, ctx.d_rowptr, ctx.d_col, ctx.d_val, ctx.d_phi_cm, st);
+    if (disc) phi_pressure_rows(total_I, cv, d_pval, d_sub_pcol, ctx.d_phi_cm, st);
     lu_solve_multi(B, ctx.d_phi_cm, ctx.d_phi_off, d_nr, max_nr, st);
     phi_transpose(total_I, cv, ctx.d_phi_cm, ctx.d_phi_rm, st);
     GDSW_HIP(hipStreamSynchronize(st));
+    for (void* q : {(void*)d_nu, (void*)d_pval, (void*)d_sub_pcol})
+      if (q) A.free(q);
     A.free(aii);
     A.free(d_ni);
     A.free(d_nr);

@@ -30,8 +30,9 @@ def spread(name, k=10, eps=1e-14):
     (the size of the rounding differences between two FP64 implementations).
     Stored as oracle_<name>_spread.json."""
     w = workload(name)
-    p = StokesProblem(w.n, viscosity=w.viscosity, inflow=w.inflow, manufactured=w.manufactured)
-    d = Decomposition(p, w.m, w.overlap, local_dirichlet=not w.local_algebraic)
+    p = StokesProblem(w.n, viscosity=w.viscosity, inflow=w.inflow, manufactured=w.manufactured,
+                      pressure=w.pressure)
+    d = Decomposition(p, w.m, w.overlap, local_dirichlet=not w.local_algebraic, coarse=w.coarse)
     M = (ThreeLevelGDSW(p.A, d, w.group, level2_layer=bool(w.level2_layer)) if w.levels == 3
          else TwoLevelGDSW(p.A, d))
     counts = []
@@ -55,8 +56,9 @@ def spread(name, k=10, eps=1e-14):
 def main(name):
     w = workload(name)
     t0 = time.time()
-    p = StokesProblem(w.n, viscosity=w.viscosity, inflow=w.inflow, manufactured=w.manufactured)
-    d = Decomposition(p, w.m, w.overlap, local_dirichlet=not w.local_algebraic)
+    p = StokesProblem(w.n, viscosity=w.viscosity, inflow=w.inflow, manufactured=w.manufactured,
+                      pressure=w.pressure)
+    d = Decomposition(p, w.m, w.overlap, local_dirichlet=not w.local_algebraic, coarse=w.coarse)
     if w.levels == 3:
         M = ThreeLevelGDSW(p.A, d, w.group, level2_layer=bool(w.level2_layer))
     else:

@@ -100,3 +100,33 @@ def test_host_local_sets_match_oracle(alg):
     for i in range(d.n_sub):
         assert np.array_equal(s.local_indices(i), d.S[i])
     s.close()
+
+
+@pytest.mark.parametrize("n,m,coarse", [(4, 2, "gdsw*"), (6, 3, "gdsw*"), (6, 3, "gdsw")])
+def test_host_p1disc_setup_matches_oracle(n, m, coarse):
+    """The paper's pair and coarse spaces in the library's host setup: matrix,
+    right-hand side, DOF map, local sets and coarse dimension equal the
+    oracle's (which computes them independently in numpy)."""
+    s = G.Solver(n, m, host_only=True, pressure="p1disc", coarse=coarse, local_algebraic=1, viscosity=0.7,
+                 inflow=3.0)
+    sz = s.sizes()
+    p = StokesProblem(n, pressure="p1disc", viscosity=0.7, inflow=3.0)
+    d = Decomposition(p, m, 1, local_dirichlet=False, coarse=coarse)
+    assert sz.n_free == p.n_free and sz.n_p == 4 * n ** 3
+    rp, col, val = s.host_matrix()
+    A = sp.csr_matrix((val, col, rp), shape=(sz.n_free, sz.n_free))
+    assert abs(A - p.A).max() <= 1e-15 * abs(p.A).max()
+    assert np.abs(s.host_rhs() - p.b).max() <= 1e-14 * max(1.0, np.abs(p.b).max())
+    field, abc = s.dof_map()
+    assert np.array_equal(field, p.dof_field) and np.array_equal(abc, p.dof_node)
+    assert sz.n_entities == d.n_ent and sz.n_coarse == d.n_coarse
+    for i in range(d.n_sub):
+        assert np.array_equal(s.local_indices(i), d.S[i])
+    s.close()
+
+
+def test_host_p1disc_rejections():
+    with pytest.raises(G.GdswError):
+        G.Solver(4, 2, host_only=True, pressure="p1disc")          # needs the algebraic overlap
+    with pytest.raises(G.GdswError):
+        G.Solver(4, 2, host_only=True, pressure="p1disc", local_algebraic=1, levels=3, group=1)

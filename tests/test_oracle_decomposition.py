@@ -98,3 +98,27 @@ def test_local_dirichlet_sets_and_conditioning():
         s = np.linalg.svd(Ai, compute_uv=False)
         conds[ld] = s[0] / s[-1]
     assert conds[True] * 10 < conds[False]
+
+
+@pytest.mark.parametrize("m", [2, 3, 4])
+def test_gdsw_star_counts_brute_force(m):
+    """GDSW* (vertices grouped with their adjacent edges) on m^3 subdomains
+    with the P1disc pressure: enumerated coarse dimension equals the closed
+    form 3 [3 (m-1) m^2 + (m-1)^3] + m^3 behind Tables 1-2; every edge class
+    is absorbed, entities stay disjoint and each groups one vertex with at
+    most 6 edges (one per direction and side)."""
+    n = 2 * m
+    p = StokesProblem(n, pressure="p1disc")
+    d = Decomposition(p, m, 1, local_dirichlet=False, coarse="gdsw*")
+    assert d.n_coarse == 3 * (3 * (m - 1) * m * m + (m - 1) ** 3) + m ** 3
+    kinds = [d.entity_kind(e) for e in range(d.n_ent)]
+    assert kinds.count("edge") == 0
+    assert kinds.count("vertex") == (m - 1) ** 3 and kinds.count("face") == 3 * (m - 1) * m * m
+    full = Decomposition(p, m, 1, local_dirichlet=False, coarse="gdsw")
+    # the grouped classes are unions of the full space's classes
+    for e in range(d.n_ent):
+        members = np.unique(d.gamma[d.gamma_entity == e])
+        fe = np.unique(full.gamma_entity[np.isin(full.gamma, members)])
+        assert np.array_equal(np.unique(full.gamma[np.isin(full.gamma_entity, fe)]), members)
+        if kinds[e] == "vertex":
+            assert 1 <= fe.size <= 7

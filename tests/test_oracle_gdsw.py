@@ -190,3 +190,94 @@ def test_coarse_lu_without_pivoting_is_valid(n6m3):
     y[order] = sla.solve_triangular(U, sla.solve_triangular(L, b[order], lower=True, unit_diagonal=True))
     ref = M.coarse_solve(b)
     assert np.linalg.norm(y - ref) / np.linalg.norm(ref) < np.linalg.cond(M.A0) * 1e-14
+
+
+# --- the paper's variant: Q2/P1disc, one pressure constant per subdomain, GDSW* ---
+
+@pytest.fixture(scope="module")
+def p6m3_disc():
+    p = StokesProblem(6, viscosity=0.8, pressure="p1disc")
+    d = Decomposition(p, 3, 1, local_dirichlet=False, coarse="gdsw*")
+    return p, d, TwoLevelGDSW(p.A, d)
+
+
+def test_p1disc_coarse_columns(p6m3_disc):
+    """Velocity interface: Phi_Gamma is a 0/1 partition of unity per field;
+    pressure: one column per subdomain whose sum is the pressure null vector
+    (1 on every element's constant function, 0 on the linear ones), exactly;
+    the velocity and pressure columns do not mix (off-diagonal blocks zero)."""
+    p, d, M = p6m3_disc
+    Phi = M.Phi.toarray()
+    for f in range(3):
+        rows = d.gamma[d.gamma_field == f]
+        cols = np.nonzero(d.coarse_field == f)[0]
+        assert np.array_equal(Phi[np.ix_(rows, cols)].sum(1), np.ones(rows.size))
+    assert not np.any(d.gamma_field == 3)
+    pc = np.nonzero(d.coarse_field == 3)[0]
+    assert pc.size == d.n_sub
+    assert np.array_equal(Phi[p.n_u:][:, pc].sum(1), p.dof_null[p.n_u:])
+    assert np.all(Phi[:p.n_u][:, pc] == 0) and np.all(Phi[p.n_u:][:, d.coarse_field < 3] == 0)
+    # each pressure column lives on its own subdomain's elements
+    for i in range(d.n_sub):
+        on = np.nonzero(Phi[:, pc[i]])[0]
+        assert np.all(np.isin(on, d.box[i]))
+
+
+def test_p1disc_velocity_extension_is_harmonic_and_reproduces_constants(p6m3_disc):
+    """Velocity columns: K_II Phi_I + K_IGamma Phi_Gamma = 0 on every
+    subdomain's interior velocity rows (the velocity block alone), and the
+    translations are reproduced on the centre subdomain (no Dirichlet face);
+    A_0 is symmetric and nonsingular."""
+    p, d, M = p6m3_disc
+    A = p.A.tocsr()
+    Phi = M.Phi.tocsr()
+    vcols = np.nonzero(d.coarse_field < 3)[0]
+    R = (A[:p.n_u][:, :p.n_u] @ Phi[:p.n_u][:, vcols]).toarray()
+    for i in range(d.n_sub):
+        Iu = d.I[i][p.dof_field[d.I[i]] < 3]
+        assert np.abs(R[Iu]).max() < 1e-12 * np.abs(A).max()
+    Iu = d.I[13][p.dof_field[d.I[13]] < 3]
+    for f in range(3):
+        v = np.asarray(Phi[:, np.nonzero(d.coarse_field == f)[0]].sum(axis=1)).ravel()
+        assert np.abs(v[Iu] - (p.dof_field[Iu] == f)).max() < 1e-12
+    assert np.abs(M.A0 - M.A0.T).max() < 1e-12 * np.abs(M.A0).max()
+    assert np.linalg.cond(M.A0) < 1e8
+
+
+def test_p1disc_dense_brute_force():
+    """eq. (2.2) written out with dense inverses on 4^3 / 2^3 (Q2/P1disc, GDSW*)."""
+    p = StokesProblem(4, pressure="p1disc")
+    d = Decomposition(p, 2, 1, local_dirichlet=False, coarse="gdsw*")
+    M = TwoLevelGDSW(p.A, d)
+    A = p.A.toarray()
+    n = p.n_free
+    Md = np.zeros((n, n))
+    for Si in d.S:
+        Md[np.ix_(Si, Si)] += np.linalg.inv(A[np.ix_(Si, Si)])
+    Phi = M.Phi.toarray()
+    Md += Phi @ np.linalg.inv(Phi.T @ A @ Phi) @ Phi.T
+    X = np.random.default_rng(3).standard_normal((n, 3))
+    Z = M(X)
+    assert np.abs(Z - Md @ X).max() < 1e-11 * np.abs(Z).max()
+    x = fgmres(lambda v: p.A @ v, M, p.b, rtol=1e-12)[0]
+    xs = sla.solve(A, p.b)
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) < 1e-9
+
+
+def test_p1disc_needs_algebraic_overlap():
+    """With Dirichlet velocity on the whole artificial boundary, an interior
+    local problem's constant pressure is a null vector: refused."""
+    p = StokesProblem(6, pressure="p1disc")
+    with pytest.raises(ValueError):
+        Decomposition(p, 3, 1, local_dirichlet=True)
+    # the refused reading is indeed singular on the centre subdomain
+    d = Decomposition(p, 3, 1, local_dirichlet=False)
+    n = p.n
+    abc = p.dof_node
+    lo, hi = 2 * (2 * 1 - 1) + 1, 2 * (2 * 2 + 1) - 1   # grown box of subdomain (1,1,1), faces removed
+    S = np.nonzero(np.all((abc >= lo) & (abc <= hi), axis=1))[0]
+    Ai = p.A[S][:, S].toarray()
+    e = np.zeros(S.size)
+    e[(p.dof_field[S] == 3) & (p.dof_null[S] == 1)] = 1.0
+    assert np.abs(Ai @ e).max() < 1e-12 * np.abs(Ai).max()
+    assert d.n_sub == 27 and n == 6

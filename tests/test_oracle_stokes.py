@@ -17,6 +17,41 @@ def test_dof_counts_closed_form():
     assert [dof_count_q2p1disc(n) for n in (32, 64, 128)] == [954947, 7488643, 59312387]
 
 
+def test_p1disc_dof_counts_and_structure():
+    for n in (1, 2, 3):
+        p = StokesProblem(n, pressure="p1disc")
+        assert p.n_full == dof_count_q2p1disc(n) and p.n_p == 4 * n ** 3
+        assert abs(p.A - p.A.T).max() < 1e-15
+    p = StokesProblem(2, pressure="p1disc")
+    # each element's four pressure DOFs couple only to the 81 velocity DOFs of that element
+    Bp = p.A[p.n_u:, :p.n_u].tocsr()
+    rows_e0 = Bp[0:4]
+    assert rows_e0.count_nonzero() <= 4 * 81
+    assert p.A[p.n_u:, p.n_u:].count_nonzero() == 0
+    assert np.array_equal(p.dof_null[p.n_u:], np.tile([1.0, 0, 0, 0], 8))
+
+
+def test_p1disc_divergence_block_tensor_closed_form():
+    """B[q, a, c] = -h^2 int psi_q d(phi_a)/dxi_c with psi = 1, 2x-1, 2y-1,
+    2z-1, from hand-computed 1-D integrals: int L_a = (1/6, 2/3, 1/6),
+    int L_a' = (-1, 0, 1), int (2x-1) L_a = (-1/6, 0, 1/6),
+    int (2x-1) L_a' = (2/3, -4/3, 2/3)."""
+    h, mu = 0.5, 1.0
+    I = np.array([1 / 6, 2 / 3, 1 / 6])
+    D = np.array([-1.0, 0.0, 1.0])
+    J = np.array([-1 / 6, 0.0, 1 / 6])
+    JD = np.array([2 / 3, -4 / 3, 2 / 3])
+    k3 = lambda z, y, x: np.kron(z, np.kron(y, x))
+    ref = np.zeros((4, 27, 3))
+    ref[0, :, 0], ref[0, :, 1], ref[0, :, 2] = k3(I, I, D), k3(I, D, I), k3(D, I, I)
+    ref[1, :, 0], ref[1, :, 1], ref[1, :, 2] = k3(I, I, JD), k3(I, D, J), k3(D, I, J)
+    ref[2, :, 0], ref[2, :, 1], ref[2, :, 2] = k3(I, J, D), k3(I, JD, I), k3(D, J, I)
+    ref[3, :, 0], ref[3, :, 1], ref[3, :, 2] = k3(J, I, D), k3(J, D, I), k3(JD, I, I)
+    ref *= -h * h
+    _, B = element_matrices(h, mu, pressure="p1disc")
+    assert np.allclose(B, ref, rtol=0, atol=1e-14)
+
+
 def test_free_dofs_and_symmetry():
     p = StokesProblem(4)
     # Dirichlet nodes: x = 0 face and the four walls; interior: a in 1..8, b, c in 1..7
@@ -52,12 +87,13 @@ def test_element_matrices_tensor_closed_form(h, mu):
     assert np.allclose(B, B_ref, rtol=0, atol=1e-14 * np.abs(B_ref).max())
 
 
+@pytest.mark.parametrize("pressure", ["q1", "p1disc"])
 @pytest.mark.parametrize("n", [2, 3, 4])
-def test_manufactured_poiseuille_is_exact(n):
+def test_manufactured_poiseuille_is_exact(n, pressure):
     """With f = (2 mu c [y(1-y) + z(1-z)], 0, 0) the quadratic profile and p = 0
-    solve the continuous problem and lie in Q2/Q1, so the discrete solution is
-    their nodal interpolant."""
-    p = StokesProblem(n, viscosity=0.7, inflow=16.0, manufactured=1)
+    solve the continuous problem and lie in Q2/Q1 (and Q2/P1disc), so the
+    discrete solution is their nodal interpolant."""
+    p = StokesProblem(n, viscosity=0.7, inflow=16.0, manufactured=1, pressure=pressure)
     x = spla.spsolve(p.A.tocsc(), p.b)
     c = p.c
     ref = p.interpolant(lambda X, Y, Z: np.stack([c * Y * (1 - Y) * Z * (1 - Z), 0 * X, 0 * X]),
@@ -65,14 +101,15 @@ def test_manufactured_poiseuille_is_exact(n):
     assert np.abs(p.expand(x) - ref).max() < 1e-10
 
 
+@pytest.mark.parametrize("pressure", ["q1", "p1disc"])
 @pytest.mark.parametrize("n", [2, 3])
-def test_linear_pressure_flow_is_exact(n):
+def test_linear_pressure_flow_is_exact(n, pressure):
     """u = (c y(1-y), 0, 0), p = 2 mu c (1 - x) solves Stokes with f = 0 and the
     do-nothing condition at x = 1; Dirichlet data from u on x = 0 and the walls."""
     mu, c = 1.3, 2.0
     u = lambda X, Y, Z: np.stack([c * Y * (1 - Y) + 0 * X, 0 * X, 0 * X])
     pfun = lambda X, Y, Z: 2 * mu * c * (1 - X)
-    p = StokesProblem(n, viscosity=mu, inflow=c, dirichlet=u)
+    p = StokesProblem(n, viscosity=mu, inflow=c, dirichlet=u, pressure=pressure)
     x = spla.spsolve(p.A.tocsc(), p.b)
     assert np.abs(p.expand(x) - p.interpolant(u, pfun)).max() < 1e-10
 
