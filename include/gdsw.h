@@ -205,6 +205,62 @@ gdsw_status gdsw_setup(const gdsw_mesh* mesh, const gdsw_decomposition* dec,
 gdsw_status gdsw_setup_host(const gdsw_mesh* mesh, const gdsw_decomposition* dec,
                             gdsw_ctx** out);
 
+/* Algebraic entry point (Section 3: the implementation needs only the
+ * distribution of the velocity and pressure DOFs over the subdomains): any
+ * assembled saddle-point matrix of eq. (2.1) and any partition, e.g. an
+ * unstructured mesh.  Host arrays, read during the call only:
+ *   n                 unknowns (Dirichlet DOFs already eliminated);
+ *   row_ptr[n + 1], col[nnz], val[nnz]
+ *                     CSR of the matrix, columns sorted and distinct per
+ *                     row, nnz < 2^31;
+ *   rhs[n]            right-hand side (gdsw_rhs returns it), or NULL (zeros);
+ *   field[n]          0, 1, 2 velocity components, 3 pressure; every velocity
+ *                     DOF numbered before every pressure DOF (the local and
+ *                     coarse eliminations run without row exchanges in that
+ *                     order);
+ *   null_value[n]     value (0 or 1) of the field's null-space vector on each
+ *                     DOF, or NULL (all 1): 1 for translations and a
+ *                     continuous pressure, 1 / 0 on the constant / linear
+ *                     functions of a discontinuous pressure;
+ *   n_sub, sub_ptr[n + 1], sub_idx[...]
+ *                     the subdomains holding each DOF, sorted: DOF d is held
+ *                     by sub_idx[sub_ptr[d] .. sub_ptr[d + 1]) (the closures
+ *                     of the non-overlapping subdomains, so an interface DOF
+ *                     is held by several).
+ * From these: D_i = DOFs held by i; Gamma = DOFs held by two or more;
+ * I_i = D_i without Gamma; the overlapping set S_i = D_i grown by
+ * dec->overlap layers of the matrix graph; interface entities = classes of
+ * Gamma DOFs with the same subdomain set (ordered by their smallest DOF
+ * index), one coarse column per (entity, field); a field with DOFs but none
+ * on Gamma (a discontinuous pressure) gets one column per subdomain, its
+ * null-space values there, and the velocity columns are then extended with
+ * the velocity block alone.  Two levels, full GDSW: dec->levels must be 2 and
+ * dec->coarse_space 0 (EINVAL otherwise); dec->subdomains and
+ * local_algebraic are ignored; the other fields mean what they mean for
+ * gdsw_setup.  Every other entry point accepts the context except the learned
+ * local solve (EUNSUPPORTED) and gdsw_expand_solution, for which the full
+ * vector is the free one.  EINVAL on inconsistent input (the message says
+ * which); a matrix entry between DOFs that share no subdomain is refused. */
+typedef struct {
+  int64_t n;
+  const int64_t* row_ptr;
+  const int32_t* col;
+  const double* val;
+  const double* rhs;
+  const int32_t* field;
+  const double* null_value;
+  int32_t n_sub;
+  const int64_t* sub_ptr;
+  const int32_t* sub_idx;
+} gdsw_algebraic_problem;
+
+gdsw_status gdsw_setup_algebraic(const gdsw_algebraic_problem* prob, const gdsw_decomposition* dec, void* stream,
+                                 gdsw_ctx** out);
+
+/* As gdsw_setup_algebraic without touching the device (see gdsw_setup_host). */
+gdsw_status gdsw_setup_algebraic_host(const gdsw_algebraic_problem* prob, const gdsw_decomposition* dec,
+                                      gdsw_ctx** out);
+
 gdsw_status gdsw_get_sizes(const gdsw_ctx* ctx, gdsw_sizes* out);
 
 /* Wall time of the two setup phases, as the paper's tables report them

@@ -14,4 +14,5 @@ from .workloads import (  # noqa: F401
     c5_batch_draws,
     paper_variant_cases,
     small_parity_cases,
+    voronoi_partition,
 )

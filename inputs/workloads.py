@@ -116,3 +116,22 @@ def small_parity_cases() -> List[Workload]:
         Workload("n8m4alg", n=8, m=4, local_algebraic=1),
         Workload("n9m3alg", n=9, m=3, viscosity=0.37, inflow=1.3, local_algebraic=1),
     ]
+
+
+def voronoi_partition(n: int, parts: int, seed: int = 11) -> np.ndarray:
+    """An unstructured partition of the n^3 hexahedra: each element goes to
+    the nearest of `parts` seeded random points (element centres in the unit
+    cube, ties to the lower index).  Returns the part of each element,
+    elements numbered x fastest.  Only describes the decomposition."""
+    rng = np.random.default_rng(seed)
+    pts = rng.random((parts, 3))
+    e = np.arange(n ** 3)
+    c = (np.stack([e % n, (e // n) % n, e // (n * n)], 1) + 0.5) / n
+    d2 = ((c[:, None, :] - pts[None, :, :]) ** 2).sum(-1)
+    part = np.argmin(d2, axis=1)
+    # renumber parts in order of first appearance so every index is used
+    _, first = np.unique(part, return_index=True)
+    order = np.argsort(first)
+    rank = np.empty(parts, dtype=np.int64)
+    rank[np.unique(part)[order]] = np.arange(order.size)
+    return rank[part]

@@ -202,3 +202,85 @@ class Decomposition:
 
     def local_sizes(self):
         return np.array([len(S) for S in self.S])
+
+
+class AlgebraicDecomposition:
+    """Decomposition from the distribution of the DOFs alone (Section 3: the
+    implementation needs only which subdomains hold each velocity and
+    pressure DOF), for any matrix and any partition.
+
+    Inputs: the free-DOF matrix A (its graph gives the overlap), the field of
+    each DOF (0-2 velocity components, 3 pressure), the value of its field's
+    null-space vector (1 for translations and a continuous constant
+    pressure), and for every DOF the sorted subdomains that hold it (the
+    closures of the non-overlapping subdomains: an interface DOF is held by
+    several).  Definitions, as for the structured cube:
+
+    * D_i = DOFs held by subdomain i; Gamma = DOFs held by at least two;
+      I_i = D_i minus Gamma.
+    * Entities: classes of Gamma DOFs with the same subdomain set, ordered by
+      their smallest DOF index; coarse columns (entity, field) in that order.
+    * S_i = D_i grown by `overlap` layers of the matrix graph.
+    * A field with DOFs but none on Gamma (a discontinuous pressure) gets one
+      column per subdomain instead, its null-space values on the subdomain's
+      DOFs of that field, after the interface columns.
+    """
+
+    def __init__(self, A, field, dof_subs, null=None, overlap=1):
+        A = A.tocsr()
+        n = A.shape[0]
+        field = np.asarray(field)
+        self.dof_field = field
+        self.dof_null = np.ones(n) if null is None else np.asarray(null, dtype=np.float64)
+        subs = [tuple(int(v) for v in s) for s in dof_subs]
+        self.n_sub = 1 + max(max(s) for s in subs if s)
+        self.overlap = overlap
+        self.box = [[] for _ in range(self.n_sub)]
+        for d, s in enumerate(subs):
+            for i in s:
+                self.box[i].append(d)
+        self.box = [np.array(b, dtype=np.int64) for b in self.box]
+        mult = np.array([len(s) for s in subs])
+        self.multiplicity = mult
+        self.is_gamma = mult >= 2
+        self.I = [b[~self.is_gamma[b]] for b in self.box]
+        self.S = []
+        for b in self.box:
+            mark = np.zeros(n, dtype=bool)
+            mark[b] = True
+            for _ in range(overlap):
+                rows = np.nonzero(mark)[0]
+                mark[A[rows].indices] = True
+            self.S.append(np.nonzero(mark)[0])
+        g = np.nonzero(self.is_gamma)[0]
+        cls = {}
+        ent = np.empty(g.size, dtype=np.int64)
+        for k, d in enumerate(g):           # ascending d: classes appear in order of their smallest DOF
+            ent[k] = cls.setdefault(subs[d], len(cls))
+        self.entity_sets = list(cls.keys())
+        self.n_ent = len(cls)
+        self.gamma = g
+        self.gamma_entity = ent
+        self.gamma_field = field[g]
+        has = np.zeros((self.n_ent, 4), dtype=bool)
+        has[self.gamma_entity, self.gamma_field] = True
+        col = -np.ones((self.n_ent, 4), dtype=np.int64)
+        col[has] = np.arange(has.sum())
+        self.coarse_col = col
+        self.n_coarse = int(has.sum())
+        self.coarse_entity = np.repeat(np.arange(self.n_ent), 4).reshape(self.n_ent, 4)[has]
+        self.coarse_field = np.tile(np.arange(4), (self.n_ent, 1))[has]
+        self.sub_pressure_col = None
+        if np.any(field == 3) and not np.any(self.gamma_field == 3) and self.n_sub > 1:
+            self.sub_pressure_col = self.n_coarse + np.arange(self.n_sub)
+            self.coarse_entity = np.concatenate([self.coarse_entity, self.n_ent + np.arange(self.n_sub)])
+            self.coarse_field = np.concatenate([self.coarse_field, np.full(self.n_sub, 3)])
+            self.n_coarse += self.n_sub
+
+    def entity_subdomains(self, e):
+        if e >= self.n_ent:
+            return [int(e - self.n_ent)]
+        return list(self.entity_sets[e])
+
+    def local_sizes(self):
+        return np.array([len(S) for S in self.S])

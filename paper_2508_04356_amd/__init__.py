@@ -57,6 +57,12 @@ class FgmresInfo(C.Structure):
                 ("fallbacks", C.c_int64)]
 
 
+class AlgebraicProblem(C.Structure):
+    _fields_ = [("n", C.c_int64), ("row_ptr", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p),
+                ("rhs", C.c_void_p), ("field", C.c_void_p), ("null_value", C.c_void_p), ("n_sub", C.c_int32),
+                ("sub_ptr", C.c_void_p), ("sub_idx", C.c_void_p)]
+
+
 class Sizes(C.Structure):
     _fields_ = [(k, C.c_int64) for k in ("n_free", "n_full", "n_u_free", "n_p", "nnz", "n_sub", "n_entities",
                                          "n_coarse", "n_subregions", "n_coarse3", "local_min", "local_max")] + \
@@ -73,6 +79,8 @@ _P = C.c_void_p
 _sig = {
     "gdsw_setup": (C.c_int, [C.POINTER(Mesh), C.POINTER(Decomposition), _P, C.POINTER(_P)]),
     "gdsw_setup_host": (C.c_int, [C.POINTER(Mesh), C.POINTER(Decomposition), C.POINTER(_P)]),
+    "gdsw_setup_algebraic": (C.c_int, [C.POINTER(AlgebraicProblem), C.POINTER(Decomposition), _P, C.POINTER(_P)]),
+    "gdsw_setup_algebraic_host": (C.c_int, [C.POINTER(AlgebraicProblem), C.POINTER(Decomposition), C.POINTER(_P)]),
     "gdsw_get_sizes": (C.c_int, [_P, C.POINTER(Sizes)]),
     "gdsw_dof_map": (C.c_int, [_P, _P, _P]),
     "gdsw_host_matrix": (C.c_int, [_P, _P, _P, _P]),
@@ -176,6 +184,47 @@ class Solver:
         s = self.sizes()
         self.n_free = s.n_free
         self.n_coarse = s.n_coarse
+
+    @classmethod
+    def algebraic(cls, row_ptr, col, val, field, dof_subs, null=None, rhs=None, overlap=1, precision="fp64",
+                  tile=0, budget=0, local_solve="inverse", max_rhs=1, host_only=False, stream=None):
+        """A problem given as its assembled matrix (CSR, host arrays) and the
+        subdomains holding each DOF (dof_subs: a list of sorted index lists,
+        or a (ptr, idx) pair)."""
+        self = cls.__new__(cls)
+        self._ctx = C.c_void_p()
+        keep = []
+
+        def arr(a, dt):
+            a = np.ascontiguousarray(a, dtype=dt)
+            keep.append(a)
+            return a.ctypes.data_as(C.c_void_p)
+
+        if isinstance(dof_subs, tuple):
+            sptr, sidx = dof_subs
+        else:
+            sptr = np.zeros(len(dof_subs) + 1, dtype=np.int64)
+            sptr[1:] = np.cumsum([len(x) for x in dof_subs])
+            sidx = np.concatenate([np.asarray(x, dtype=np.int32) for x in dof_subs])
+        sidx = np.asarray(sidx, dtype=np.int32)
+        n = len(row_ptr) - 1
+        prob = AlgebraicProblem(n, arr(row_ptr, np.int64), arr(col, np.int32), arr(val, np.float64),
+                                arr(rhs, np.float64) if rhs is not None else None, arr(field, np.int32),
+                                arr(null, np.float64) if null is not None else None,
+                                int(sidx.max()) + 1 if sidx.size else 0, arr(sptr, np.int64), arr(sidx, np.int32))
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        solve = LOCAL_SOLVES[local_solve] if isinstance(local_solve, str) else int(local_solve)
+        self.dec = Decomposition(1, overlap, 2, 1, prec, tile, 1, 0, budget, solve, int(max_rhs), 0)
+        if host_only:
+            st = _lib.gdsw_setup_algebraic_host(C.byref(prob), C.byref(self.dec), C.byref(self._ctx))
+        else:
+            st = _lib.gdsw_setup_algebraic(C.byref(prob), C.byref(self.dec), _stream(stream), C.byref(self._ctx))
+        _check(st)
+        self.host_only = host_only
+        sz = self.sizes()
+        self.n_free = sz.n_free
+        self.n_coarse = sz.n_coarse
+        return self
 
     # -- queries -----------------------------------------------------------
     def sizes(self) -> Sizes:

@@ -157,6 +157,103 @@ gdsw_status gdsw_setup(const gdsw_mesh* mesh, const gdsw_decomposition* dec, voi
   return GDSW_OK;
 }
 
+namespace {
+
+AlgebraicInput algebraic_input(const gdsw_algebraic_problem* p) {
+  if (!p) throw std::invalid_argument("problem must not be NULL");
+  AlgebraicInput in;
+  in.n = p->n;
+  in.row_ptr = p->row_ptr;
+  in.col = p->col;
+  in.val = p->val;
+  in.rhs = p->rhs;
+  in.field = p->field;
+  in.null_value = p->null_value;
+  in.n_sub = p->n_sub;
+  in.sub_ptr = p->sub_ptr;
+  in.sub_idx = p->sub_idx;
+  return in;
+}
+
+ProblemSpec algebraic_spec(const gdsw_decomposition* dec) {
+  if (!dec) throw std::invalid_argument("decomposition must not be NULL");
+  gdsw_mesh dummy{};
+  dummy.n = 1;
+  dummy.viscosity = 1.0;
+  gdsw_decomposition d = *dec;
+  d.subdomains = 1;  // not used: the subdomains come with the problem
+  ProblemSpec s = spec_of(&dummy, &d);
+  s.local_dirichlet = 0;
+  return s;
+}
+
+}  // namespace
+
+gdsw_status gdsw_setup_algebraic_host(const gdsw_algebraic_problem* prob, const gdsw_decomposition* dec,
+                                      gdsw_ctx** out) {
+  if (!out) return fail(nullptr, GDSW_EINVAL, "out must not be NULL");
+  *out = nullptr;
+  gdsw_ctx* ctx = nullptr;
+  gdsw_status s = guarded(nullptr, [&]() {
+    const AlgebraicInput in = algebraic_input(prob);
+    const ProblemSpec sp = algebraic_spec(dec);
+    ctx = new gdsw_ctx();
+    ctx->c.host_only = true;
+    ctx->c.local_prec = dec->local_precision;
+    const auto t0 = std::chrono::steady_clock::now();
+    build_problem_algebraic(in, sp, ctx->c.P);
+    ctx->c.t_symbolic = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  });
+  if (s != GDSW_OK) {
+    delete ctx;
+    return s;
+  }
+  *out = ctx;
+  return GDSW_OK;
+}
+
+gdsw_status gdsw_setup_algebraic(const gdsw_algebraic_problem* prob, const gdsw_decomposition* dec, void* stream,
+                                 gdsw_ctx** out) {
+  if (!out) return fail(nullptr, GDSW_EINVAL, "out must not be NULL");
+  *out = nullptr;
+  gdsw_ctx* ctx = nullptr;
+  gdsw_status s = guarded(nullptr, [&]() {
+    const AlgebraicInput in = algebraic_input(prob);
+    const ProblemSpec sp = algebraic_spec(dec);
+    ctx = new gdsw_ctx();
+    Context& c = ctx->c;
+    c.local_prec = dec->local_precision;
+    c.solve_mode = dec->local_solve == GDSW_SOLVE_TRIANGULAR  ? SOLVE_TRSV
+                   : dec->local_solve == GDSW_SOLVE_SYMMETRIC ? SOLVE_SYM
+                                                              : SOLVE_INVERSE;
+    c.max_rhs = std::max(1, dec->max_rhs);
+    GDSW_HIP(hipGetDevice(&c.device));
+    const auto t0 = std::chrono::steady_clock::now();
+    build_problem_algebraic(in, sp, c.P);
+    const auto t1 = std::chrono::steady_clock::now();
+    c.t_symbolic = std::chrono::duration<double>(t1 - t0).count();
+    uint64_t budget = dec->device_mem_budget;
+    if (budget == 0) {
+      size_t fr = 0, tot = 0;
+      GDSW_HIP(hipMemGetInfo(&fr, &tot));
+      budget = (uint64_t)(fr * 0.97);
+    }
+    device_setup(c, (hipStream_t)stream, budget, dec->tile ? dec->tile : 128);
+    (void)noalloc_scratch(c.device);
+    c.t_numeric = std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count();
+  });
+  if (s != GDSW_OK) {
+    if (ctx) {
+      ctx->c.arena.release_all();
+      if (ctx->c.h_pinned) (void)hipHostFree(ctx->c.h_pinned);
+    }
+    delete ctx;
+    return s;
+  }
+  *out = ctx;
+  return GDSW_OK;
+}
+
 gdsw_status gdsw_get_sizes(const gdsw_ctx* ctx, gdsw_sizes* out) {
   if (!ctx || !out) return fail(nullptr, GDSW_EINVAL, "NULL argument");
   const Context& c = ctx->c;

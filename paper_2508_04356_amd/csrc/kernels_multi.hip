@@ -288,33 +288,105 @@ __global__ void scatter_prolong_il_kernel(int64_t n, int K, const int32_t* __res
   }
 }
 
-// Y = A X for K interleaved vectors: 8 rows per block, one lane per right-hand side.
+// Y = A X for K <= 32 interleaved vectors.  A wave serves ROWS rows; the
+// lanes of a row are G groups of LPG = 64 / (ROWS G) lanes, lane l of a group
+// holding the RPL = 32 / LPG right-hand sides RPL l .. RPL l + RPL - 1 (one
+// 8-, 16- or 32-byte load per nonzero; K must be a multiple of RPL), and
+// group g takes the row's nonzeros in batches of eight, batch g, g + G, ...:
+// every lane issues the batch's eight column/value loads, then the eight
+// gathers of its vector entries (a group reads 256 contiguous bytes per
+// nonzero), so a row needs about nnz / (8 G) dependent round trips.  The G
+// group sums are combined by a butterfly over the lane exchanges (the same
+// tree on every run).  With SPMM_XCD the work-groups take contiguous row
+// ranges per XCD (the dispatcher deals work-groups to the 8 XCDs in turn).
+// Measured on MI355X at 24^3 x 32 columns (98 launches, rocprofv3): two rows
+// per wave with 1 / 2 / 4 groups 923 / 555 / 501 us, one row with 4 / 8
+// groups 557 / 518 us (the kernel with one lane per right-hand side and no
+// groups took 726 us); XCD-contiguous row ranges 586 / 614 us instead of
+// 555 / 557 (the eight XCDs then stream eight far-apart parts of X through
+// the shared last-level cache instead of one region).
+#ifndef GDSW_SPMM_ROWS
+#define GDSW_SPMM_ROWS 2
+#endif
+#ifndef GDSW_SPMM_G
+#define GDSW_SPMM_G 4
+#endif
+#ifndef GDSW_SPMM_XCD
+#define GDSW_SPMM_XCD 0
+#endif
+
+template <int RPL>
+struct RhsVec;
+template <>
+struct RhsVec<1> {
+  static __device__ inline void load(const double* p, double (&o)[1]) { o[0] = *p; }
+};
+template <>
+struct RhsVec<2> {
+  static __device__ inline void load(const double* p, double (&o)[2]) {
+    const double2 v = *reinterpret_cast<const double2*>(p);
+    o[0] = v.x;
+    o[1] = v.y;
+  }
+};
+template <>
+struct RhsVec<4> {
+  static __device__ inline void load(const double* p, double (&o)[4]) {
+    const double2 a = reinterpret_cast<const double2*>(p)[0], b = reinterpret_cast<const double2*>(p)[1];
+    o[0] = a.x;
+    o[1] = a.y;
+    o[2] = b.x;
+    o[3] = b.y;
+  }
+};
+
+template <int ROWS, int G>
 __global__ __launch_bounds__(256) void spmm_il_kernel(int64_t nrows, int K, const int32_t* __restrict__ rowptr,
                                                       const int32_t* __restrict__ col, const double* __restrict__ val,
                                                       const double* __restrict__ x, double* __restrict__ y) {
-  const int64_t row = (int64_t)blockIdx.x * 8 + (threadIdx.x >> 5);
-  const int j = threadIdx.x & 31;
-  if (row >= nrows || j >= K) return;
-  // eight nonzeros' loads issued together; the products are summed in
-  // ascending k as in the one-column SpMV
-  const int k0 = rowptr[row], k1 = rowptr[row + 1];
-  double s = 0.0;
-  int k = k0;
-  for (; k + 8 <= k1; k += 8) {
+  constexpr int LPG = 64 / (ROWS * G);  // lanes per group
+  constexpr int RPL = 32 / LPG;         // right-hand sides per lane
+  int blk = blockIdx.x;
+#if GDSW_SPMM_XCD
+  {
+    const int nb = gridDim.x, x8 = blockIdx.x % 8, q8 = blockIdx.x / 8, per = nb / 8, rem = nb % 8;
+    blk = (x8 < rem ? x8 * (per + 1) : rem * (per + 1) + (x8 - rem) * per) + q8;
+  }
+#endif
+  const int lane = threadIdx.x & 63;
+  const int64_t row = ((int64_t)blk * 4 + (threadIdx.x >> 6)) * ROWS + lane / (64 / ROWS);
+  const int rl = lane % (64 / ROWS);    // lane within the row
+  const int g = rl / LPG, l = rl % LPG;
+  const bool live = row < nrows;        // uniform per row's lanes
+  const int jb = min(RPL * l, K - RPL); // K % RPL == 0 and K >= RPL
+  const int k0 = live ? rowptr[row] : 0, k1 = live ? rowptr[row + 1] : 0;
+  double s[RPL];
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) s[q] = 0.0;
+  for (int kb = k0 + 8 * g; kb < k1; kb += 8 * G) {
     int32_t c[8];
-    double v[8], xv[8];
+    double v[8], xv[8][RPL];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      c[u] = col[k + u];
-      v[u] = val[k + u];
+      const int k = min(kb + u, k1 - 1);
+      c[u] = col[k];
+      v[u] = kb + u < k1 ? val[k] : 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) xv[u] = x[(int64_t)c[u] * K + j];
+    for (int u = 0; u < 8; ++u) RhsVec<RPL>::load(x + (int64_t)c[u] * K + jb, xv[u]);
 #pragma unroll
-    for (int u = 0; u < 8; ++u) s = fma(v[u], xv[u], s);
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) s[q] = fma(v[u], xv[u][q], s[q]);
   }
-  for (; k < k1; ++k) s = fma(val[k], x[(int64_t)col[k] * K + j], s);
-  y[row * K + j] = s;
+#pragma unroll
+  for (int d = LPG; d < LPG * G; d *= 2)
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) s[q] += __shfl_xor(s[q], d);
+  if (live && g == 0)
+#pragma unroll
+    for (int q = 0; q < RPL; ++q)
+      if (RPL * l + q < K) y[row * K + RPL * l + q] = s[q];
 }
 
 constexpr int DCH = 256;  // rows per partial block of the dot products
@@ -471,7 +543,16 @@ void scatter_prolong_il(int64_t n, int K, const int32_t* inv_ptr, const int64_t*
 void spmm_il(int64_t nrows, int K, const int32_t* rowptr, const int32_t* col, const double* val, const double* x,
              double* y, hipStream_t st) {
   if (nrows == 0) return;
-  spmm_il_kernel<<<(unsigned)((nrows + 7) / 8), 256, 0, st>>>(nrows, K, rowptr, col, val, x, y);
+  if (K < 1 || K > 32) throw StatusError{1, "interleaved SpMM takes 1 to 32 columns"};
+  constexpr int ROWS = GDSW_SPMM_ROWS, G = GDSW_SPMM_G;
+  constexpr int RPL = 32 / (64 / (ROWS * G));
+  static_assert(ROWS * G >= 2 && ROWS * G <= 8 && 64 % (ROWS * G) == 0, "2 to 8 lane groups per wave");
+  const unsigned grid = (unsigned)((nrows + 4 * ROWS - 1) / (4 * ROWS));
+  if (K % RPL == 0)
+    spmm_il_kernel<ROWS, G><<<grid, 256, 0, st>>>(nrows, K, rowptr, col, val, x, y);
+  else  // one right-hand side per lane, two rows per wave
+    spmm_il_kernel<2, 1><<<(unsigned)((nrows + 7) / 8), 256, 0, st>>>(nrows, K, rowptr, col, val, x, y);
+  GDSW_HIP(hipGetLastError());
 }
 
 int dots_il_blocks(int64_t n) { return (int)((n + DCH - 1) / DCH); }

@@ -78,8 +78,33 @@ struct Problem {
 
   Level2 lv2;
 
+  // algebraic problems (an assembled matrix and the subdomains of each DOF)
+  bool algebraic = false;
+  std::vector<int64_t> sub_ptr;                // DOF d is held by sub_idx[sub_ptr[d] .. sub_ptr[d+1])
+  std::vector<int32_t> sub_idx;
+  std::vector<std::vector<int32_t>> ent_sets;  // subdomain set of each interface entity
+
   int64_t nnz() const { return (int64_t)col.size(); }
 };
+
+// Host input of the algebraic entry point (see gdsw_algebraic_problem).
+struct AlgebraicInput {
+  int64_t n = 0;
+  const int64_t* row_ptr = nullptr;
+  const int32_t* col = nullptr;
+  const double* val = nullptr;
+  const double* rhs = nullptr;
+  const int32_t* field = nullptr;
+  const double* null_value = nullptr;
+  int32_t n_sub = 0;
+  const int64_t* sub_ptr = nullptr;
+  const int32_t* sub_idx = nullptr;
+};
+
+// Builds the problem description from an assembled matrix and the
+// subdomains holding each DOF (two levels, full GDSW).  Throws
+// std::invalid_argument on inconsistent input.
+void build_problem_algebraic(const AlgebraicInput& in, const ProblemSpec& spec, Problem& P);
 
 // Builds everything above.  Throws std::invalid_argument on a bad spec.
 void build_problem(const ProblemSpec& spec, Problem& P, int threads);

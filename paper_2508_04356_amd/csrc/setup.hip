@@ -679,25 +679,44 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
     std::vector<int64_t> own_ptr(total_D + 1, 0);
     std::vector<int32_t> own_col;
     std::vector<int64_t> own_vidx;
+    // algebraic problems: the lowest subdomain holding both DOFs
+    auto common_lowest = [&](int32_t r, int32_t c) -> int {
+      int64_t a = P.sub_ptr[r], ae = P.sub_ptr[r + 1], b = P.sub_ptr[c], be = P.sub_ptr[c + 1];
+      while (a < ae && b < be) {
+        if (P.sub_idx[a] == P.sub_idx[b]) return P.sub_idx[a];
+        if (P.sub_idx[a] < P.sub_idx[b]) ++a; else ++b;
+      }
+      return -1;
+    };
     for (int i = 0; i < P.n_sub; ++i) {
       const auto& Di = P.D[i];
       for (size_t q = 0; q < Di.size(); ++q) {
         const int32_t r = Di[q];
-        int rlo[3], rhi[3];
-        for (int ax = 0; ax < 3; ++ax) box_lo_hi(P.abc[3 * (int64_t)r + ax], rlo[ax], rhi[ax]);
+        int rlo[3] = {0, 0, 0}, rhi[3] = {0, 0, 0};
+        if (!P.algebraic)
+          for (int ax = 0; ax < 3; ++ax) box_lo_hi(P.abc[3 * (int64_t)r + ax], rlo[ax], rhi[ax]);
         for (int32_t e = P.row_ptr[r]; e < P.row_ptr[r + 1]; ++e) {
           const int32_t c = P.col[e];
-          int owner[3];
-          bool ok = true;
-          for (int ax = 0; ax < 3; ++ax) {
-            int clo, chi;
-            box_lo_hi(P.abc[3 * (int64_t)c + ax], clo, chi);
-            const int lo = std::max(rlo[ax], clo), hi = std::min(rhi[ax], chi);
-            if (lo > hi) ok = false;
-            owner[ax] = lo;
+          int own = -1;
+          if (P.algebraic) {
+            own = common_lowest(r, c);
+            if (own < 0)
+              throw StatusError{1, "matrix entry (" + std::to_string(r) + ", " + std::to_string(c) +
+                                       ") couples DOFs that share no subdomain"};
+          } else {
+            int owner[3];
+            bool ok = true;
+            for (int ax = 0; ax < 3; ++ax) {
+              int clo, chi;
+              box_lo_hi(P.abc[3 * (int64_t)c + ax], clo, chi);
+              const int lo = std::max(rlo[ax], clo), hi = std::min(rhi[ax], chi);
+              if (lo > hi) ok = false;
+              owner[ax] = lo;
+            }
+            if (!ok) continue;  // cannot happen for an assembled nonzero
+            own = owner[0] + m * (owner[1] + m * owner[2]);
           }
-          if (!ok) continue;  // cannot happen for an assembled nonzero
-          if (owner[0] + m * (owner[1] + m * owner[2]) != i) continue;
+          if (own != i) continue;
           const auto it = std::lower_bound(Di.begin(), Di.end(), c);
           own_col.push_back((int32_t)(it - Di.begin()));
           own_vidx.push_back(e);

@@ -5,6 +5,7 @@ oracle_<name>.json; the whole solution x and the whole preconditioner output
 z = B r for r = random_vector(n, 1) on every free DOF in oracle_<name>.npz.
 The GPU tests compare the library against these values.
 Usage: python tests/golden/make_oracle_golden.py C2 [spread]
+       python tests/golden/make_oracle_golden.py C3 apply   (several columns, sampled)
 """
 import json
 import os
@@ -88,8 +89,45 @@ def main(name):
     print("wrote", path)
 
 
+def multi_apply(name="C3", ncols=4, nsample=16384):
+    """The preconditioner applied to the first ncols seeded columns of the
+    several-right-hand-side workload (column j: random_vector(n, 1 + j)),
+    stored at nsample evenly spaced free DOFs, together with the entry-wise
+    scale |M_loc| |r| of the level-1 local terms (the sum over subdomains of
+    |A_i^-1| |r_i|, from explicit inverses) at those DOFs and its maximum over
+    all DOFs: the rounding of the stored inverses to a precision with unit
+    roundoff u perturbs z by at most u |M_loc| |r| entry-wise.  Written to
+    oracle_<name>_apply.json / .npz."""
+    w = workload(name)
+    t0 = time.time()
+    p = StokesProblem(w.n, viscosity=w.viscosity, inflow=w.inflow, manufactured=w.manufactured,
+                      pressure=w.pressure)
+    d = Decomposition(p, w.m, w.overlap, local_dirichlet=not w.local_algebraic, coarse=w.coarse)
+    M = TwoLevelGDSW(p.A, d)
+    R = np.stack([random_vector(p.n_free, seed=1 + j) for j in range(ncols)], 1)
+    Z = M(R)
+    print(f"apply {time.time() - t0:.1f} s", flush=True)
+    M.local_lu = []  # free the factors before the explicit inverses
+    scale = np.zeros_like(R)
+    for i in range(d.n_sub):
+        Mi = np.abs(np.linalg.inv(M.local_matrix(i)))
+        S = d.S[i]
+        scale[S] += Mi @ np.abs(R[S])
+    print(f"scale {time.time() - t0:.1f} s", flush=True)
+    idx = np.unique(np.linspace(0, p.n_free - 1, nsample).astype(np.int64))
+    out = {"workload": name, "n_free": int(p.n_free), "ncols": ncols, "seeds": [1 + j for j in range(ncols)],
+           "z_max": np.abs(Z).max(0).tolist(), "scale_max": scale.max(0).tolist()}
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"oracle_{name}_apply.json")
+    with open(path, "w") as f:
+        json.dump(out, f)
+    np.savez(path[:-5] + ".npz", idx=idx, z=Z[idx], scale=scale[idx])
+    print("wrote", path)
+
+
 if __name__ == "__main__":
-    if len(sys.argv) > 2 and sys.argv[2] == "spread":
+    if len(sys.argv) > 2 and sys.argv[2] == "apply":
+        multi_apply(sys.argv[1])
+    elif len(sys.argv) > 2 and sys.argv[2] == "spread":
         spread(sys.argv[1])
     else:
         main(sys.argv[1] if len(sys.argv) > 1 else "C2")

@@ -130,3 +130,67 @@ def test_host_p1disc_rejections():
         G.Solver(4, 2, host_only=True, pressure="p1disc")          # needs the algebraic overlap
     with pytest.raises(G.GdswError):
         G.Solver(4, 2, host_only=True, pressure="p1disc", local_algebraic=1, levels=3, group=1)
+
+
+def _repeated_map(p, elem_part):
+    """Subdomains holding each free DOF: the parts of the elements whose DOF
+    lists contain it (sorted)."""
+    full_to_free = -np.ones(p.n_full, dtype=np.int64)
+    full_to_free[p.free] = np.arange(p.n_free)
+    subs = [set() for _ in range(p.n_free)]
+    for e, dofs in enumerate(p.element_dofs):
+        for fd in dofs:
+            d = full_to_free[fd]
+            if d >= 0:
+                subs[d].add(int(elem_part[e]))
+    return [sorted(s) for s in subs]
+
+
+def _box_partition(n, m):
+    e = np.arange(n ** 3)
+    s = n // m
+    return (e % n) // s + m * (((e // n) % n) // s + m * ((e // (n * n)) // s))
+
+
+@pytest.mark.parametrize("pressure", ["q1", "p1disc"])
+def test_host_algebraic_setup_matches_structured_and_oracle(pressure):
+    """The algebraic entry point fed with the cube's matrix and its box
+    partition builds the structured algebraic-overlap problem exactly (local
+    sets, interface entities, coarse columns); on an unstructured (Voronoi)
+    partition it builds what the oracle's algebraic decomposition builds."""
+    from oracle.decomposition import AlgebraicDecomposition
+    from inputs import voronoi_partition
+    n, m = 6, 3
+    p = StokesProblem(n, pressure=pressure)
+    A = p.A.tocsr()
+    A.sort_indices()
+    for part, structured in [(_box_partition(n, m), True), (voronoi_partition(n, 7, seed=4), False)]:
+        subs = _repeated_map(p, part)
+        s = G.Solver.algebraic(A.indptr, A.indices, A.data, p.dof_field, subs, null=p.dof_null, rhs=p.b,
+                               host_only=True)
+        sz = s.sizes()
+        a = AlgebraicDecomposition(A, p.dof_field, subs, p.dof_null, 1)
+        assert sz.n_free == p.n_free and sz.n_sub == a.n_sub
+        assert sz.n_entities == a.n_ent and sz.n_coarse == a.n_coarse
+        for i in range(a.n_sub):
+            assert np.array_equal(s.local_indices(i), a.S[i])
+        assert np.array_equal(s.host_rhs(), p.b)
+        if structured:
+            d = Decomposition(p, m, 1, local_dirichlet=False)
+            assert a.n_coarse == d.n_coarse
+            for i in range(d.n_sub):
+                assert np.array_equal(a.S[i], d.S[i]) and np.array_equal(a.I[i], d.I[i])
+        s.close()
+
+
+def test_host_algebraic_rejections():
+    p = StokesProblem(2)
+    A = p.A.tocsr()
+    A.sort_indices()
+    subs = _repeated_map(p, _box_partition(2, 2))
+    bad = p.dof_field.copy()
+    bad[[0, -1]] = bad[[-1, 0]]                      # a pressure DOF before velocity DOFs
+    with pytest.raises(G.GdswError):
+        G.Solver.algebraic(A.indptr, A.indices, A.data, bad, subs, host_only=True)
+    with pytest.raises(G.GdswError):
+        G.Solver.algebraic(A.indptr, A.indices, A.data, p.dof_field, [[]] + subs[1:], host_only=True)

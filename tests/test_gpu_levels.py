@@ -33,8 +33,9 @@ def rel_max(a, b):
 # restart 200 on the 12^3 cases: with restarts every 100 steps the second cycle
 # starts near the stagnation level and its length is set by rounding (the
 # oracle alone spreads over 158-166 iterations under 1e-14 perturbations)
+# (8, 4, 2, ..., 30): two restarts of a well-converging solve, counts equal
 CASES3 = [(8, 4, 2, 1.0, 16.0, 100), (12, 6, 3, 1.0, 16.0, 200), (8, 4, 2, 0.5, 2.0, 100),
-          (8, 4, 4, 1.0, 16.0, 100)]
+          (8, 4, 4, 1.0, 16.0, 100), (8, 4, 2, 1.0, 16.0, 30)]
 
 
 @pytest.mark.parametrize("n,m,g,mu,c,restart", CASES3, ids=lambda v: str(v))
@@ -116,10 +117,16 @@ def test_three_level_long_run():
 @pytest.mark.parametrize("prec,levels,solve", [("fp32", 2, "inverse"), ("bf16", 2, "inverse"), ("fp32", 3, "inverse"),
                                                ("fp32", 2, "symmetric"), ("bf16", 2, "symmetric")])
 def test_reduced_precision_factors_converge(prec, levels, solve):
-    """Local factors stored in FP32 or BF16 (FP32 accumulation); FGMRES, the
-    coarse levels and the true residual stay FP64.  The solve must reach the
-    tolerance; the error of the preconditioner against the FP64 oracle is
-    bounded by the storage rounding amplified by the local conditioning."""
+    """Local inverses stored in FP32 or BF16 (FP32 accumulation); FGMRES, the
+    coarse levels and the true residual stay FP64.  The apply against the
+    FP64 oracle: rounding the stored entries (unit roundoff u_s) and the
+    vector (to FP32) perturbs z by at most (u_s + u_32) |M_loc| |r| entry-wise
+    to first order, with |M_loc| |r| = sum_i R_i^T |A_i^-1| |R_i r| from
+    explicit inverses (max norm).  The FP32 accumulation is of the same order
+    for FP32 storage and allowed once more (bound 2 (u_s + u_32) ...), and
+    2^16 times smaller than the operand term for BF16 (bound (u_s + u_32)
+    ...).  Measured: 0.16-0.27 of the FP32 bound, 0.52 of the BF16 bound.
+    The solve must reach the tolerance."""
     n, m = 8, 4
     p = StokesProblem(n)
     d = Decomposition(p, m, 1)
@@ -128,9 +135,17 @@ def test_reduced_precision_factors_converge(prec, levels, solve):
     r = random_vector(p.n_free, seed=1)
     z = torch.zeros(p.n_free, dtype=torch.float64, device=DEV)
     s.apply(dev(r), z)
-    err = rel_max(host(z), M(r))
-    print(f"[gpu] {prec} levels={levels} {solve} apply rel err vs FP64 oracle {err:.2e}", flush=True)
-    assert err < (1e-2 if prec == "fp32" else 0.5)
+    A = p.A.tocsr()
+    scale = np.zeros(p.n_free)
+    for S in d.S:
+        scale[S] += np.abs(np.linalg.inv(A[S][:, S].toarray())) @ np.abs(r[S])
+    u32 = 2.0 ** -24
+    us = u32 if prec == "fp32" else 2.0 ** -8
+    bound = (2.0 if prec == "fp32" else 1.0) * (us + u32) * scale.max()
+    diff = float(np.abs(host(z) - M(r)).max())
+    print(f"[gpu] {prec} levels={levels} {solve} apply max error vs FP64 oracle {diff:.3e}, bound {bound:.3e} "
+          f"(ratio {diff / bound:.2f})", flush=True)
+    assert diff <= bound
     b = torch.zeros_like(z)
     s.rhs(b)
     x = torch.zeros_like(z)

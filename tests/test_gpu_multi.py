@@ -120,7 +120,7 @@ def test_lockstep_fgmres_linearity_and_parity():
     for k, c in enumerate(cs):
         assert infos[k].true_rel_res <= w.rtol
         assert np.linalg.norm(Xh[k] - c * Xh[0] / cs[0]) <= 1e-10 * np.linalg.norm(Xh[k])
-        assert np.linalg.norm(Xh[k] - c * xo) <= (1e-10 + 10 * w.rtol) * np.linalg.norm(c * xo)
+        assert np.linalg.norm(Xh[k] - c * xo) <= 1e-10 * np.linalg.norm(c * xo)
     s.close()
 
 
@@ -144,6 +144,57 @@ def test_lockstep_fgmres_independent_columns_and_masking():
         print(f"[gpu] column {k}: its {infos[k].iterations} oracle {ito}", flush=True)
         assert infos[k].iterations == ito
         assert infos[k].true_rel_res <= 1e-8
-        assert np.linalg.norm(Xh[k] - xo) <= (1e-10 + 10 * 1e-8) * np.linalg.norm(xo)
+        assert np.linalg.norm(Xh[k] - xo) <= 1e-10 * np.linalg.norm(xo)
     assert np.all(np.isfinite(Xh))
+    s.close()
+
+
+def _apply_golden():
+    import json
+    import os
+    base = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_C3_apply")
+    if not (os.path.exists(base + ".json") and os.path.exists(base + ".npz")):
+        pytest.skip("oracle_C3_apply not generated")
+    with np.load(base + ".npz") as f:
+        return json.load(open(base + ".json")), f["idx"], f["z"], f["scale"]
+
+
+U = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24, "bf16": 2.0 ** -8}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_fullsize_32_column_apply_against_stored_oracle(prec):
+    """24^3, 6^3 subdomains, 32 columns through the matrix-core products (the
+    several-right-hand-side workload's shape), the first four seeded columns
+    against the oracle at sampled DOFs.  FP64: 1e-10.  FP32 / BF16: rounding
+    the stored inverse (unit roundoff u_s) and the right-hand side (u_x: FP32
+    for FP32 storage, BF16 for BF16 storage) perturbs z entry-wise by at most
+    (u_s + u_x) |M_loc| |r| to first order (|M_loc| |r| from the oracle's
+    explicit local inverses, max over all DOFs).  The products accumulate in
+    FP32: with FP32 storage that error is of the same order and is allowed
+    once more (bound 2 (u_s + u_x) ...); with BF16 storage it is 2^16 times
+    smaller than the operand term (bound (u_s + u_x) ...).  Measured: 0.3-0.4
+    of the FP32 bound, 0.13-0.22 of the BF16 bound."""
+    g, idx, zg, scale = _apply_golden()
+    print(f"[gpu] 24^3 32-column apply {prec}", flush=True)
+    s = G.Solver(24, 6, precision=prec, max_rhs=32)
+    n = s.n_free
+    assert n == g["n_free"]
+    R = block(n, 32, seed=1)
+    Z = torch.zeros(32 * n, dtype=torch.float64, device=DEV)
+    s.apply(dev_cm(R), Z, nrhs=32)
+    Zh = host(Z).reshape(32, n).T
+    ux = U["fp32"] if prec == "fp32" else U["bf16"] if prec == "bf16" else U["fp64"]
+    for j in range(g["ncols"]):
+        diff = np.abs(Zh[idx, j] - zg[:, j])
+        if prec == "fp64":
+            err = float(diff.max() / g["z_max"][j])
+            print(f"[gpu] column {j}: rel err {err:.2e}", flush=True)
+            assert err < 1e-10
+        else:
+            bound = (2.0 if prec == "fp32" else 1.0) * (U[prec] + ux) * g["scale_max"][j]
+            print(f"[gpu] {prec} column {j}: max error {diff.max():.3e}, bound {bound:.3e} "
+                  f"(ratio {diff.max() / bound:.2f}), first-order storage term {(U[prec] + ux) * g['scale_max'][j]:.3e}",
+                  flush=True)
+            assert diff.max() <= bound
     s.close()
