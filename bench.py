@@ -116,15 +116,24 @@ TRAFFIC = {  # committed counter summaries of the dominant kernel on the 16^3 FP
     "inverse": ("gemv_part_kernel_16cubed_traffic.txt", "kernels_gemv.hip"),
     "triangular": ("trsv_step_kernel_16cubed_traffic.txt", "kernels_factor.hip"),
     "symmetric": ("symv_part_kernel_16cubed_traffic.txt", "kernels_symv.hip"),
+    "block": ("symv_part_kernel_block_16cubed_traffic.txt", "kernels_symv.hip"),
 }
 
 
-def learned_variant(s, b, w, steps):
+def learned_variant(s, b, w, steps, solve):
     """Train the conv-net local solve on method-generated pairs, then time
     FGMRES to the same tolerance with it (with and without the exact
-    fallback) beside the exact local solves."""
+    fallback) beside the exact local solves.  It replaces whole local
+    inverses, so a block-solve context gets a symmetric-tile twin here."""
     import torch
 
+    import paper_2508_04356_amd as G
+
+    own = solve == "block"
+    if own:
+        s = G.Solver(w.n, w.m, overlap=w.overlap, levels=w.levels, group=w.group, viscosity=w.viscosity,
+                     inflow=w.inflow, precision="fp64", local_algebraic=w.local_algebraic,
+                     level2_layer=w.level2_layer, local_solve="symmetric")
     t0 = time.perf_counter()
     info = s.learned_init(seed=7)
     hist = s.learned_train(solves=4, steps=600, batch=32, lr=2e-3, seed=3)
@@ -146,7 +155,10 @@ def learned_variant(s, b, w, steps):
         log(f"[bench] {name}: {inf.iterations} iterations, {res[name]['time_to_tol_ms']:.1f} ms")
     n_l, n_fb = s.learned_stats()
     res["learned_solves"], res["fallbacks"] = n_l, n_fb
+    res["local_solve"] = "symmetric" if own else solve
     s.set_local_solver("lu")
+    if own:
+        s.close()
     return res
 
 
@@ -452,7 +464,7 @@ def main():
     ap.add_argument("--precision", default=None, help="local factor precision (default: the workload's)")
     ap.add_argument("--local-algebraic", type=int, default=None,
                     help="1: algebraic overlap instead of Dirichlet u, p on the artificial boundary")
-    ap.add_argument("--local-solve", default="auto", choices=["auto", "inverse", "triangular", "symmetric"],
+    ap.add_argument("--local-solve", default="auto", choices=["auto", "inverse", "triangular", "symmetric", "block"],
                     help="auto (default): symmetric tile storage of the explicit inverses for one right-hand "
                          "side (single problems and batches), full inverses for several right-hand sides; or "
                          "one of inverse, symmetric (explicit inverses) and triangular (LU solves)")
@@ -497,7 +509,11 @@ def main():
         run_multi(args, w, prec, nrhs)
         return
     if args.local_solve == "auto":
-        args.local_solve = "symmetric"  # one right-hand side: the upper tiles, half the bytes
+        # one right-hand side: the saddle-point block solve (the velocity-block
+        # inverse and the pressure Schur complement inverse as upper tiles);
+        # the learned interior solve replaces whole local inverses, so it runs
+        # on the symmetric tiles of A_i^-1
+        args.local_solve = "symmetric" if args.learned else "block"
     alg = w.local_algebraic if args.local_algebraic is None else args.local_algebraic
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -565,7 +581,9 @@ def main():
     kname = {"inverse": "gemv_part_kernel (level-1 explicit inverses times the local vectors)",
              "symmetric": "symv_part_kernel (upper 64x64 tiles of the symmetric level-1 inverses, both products "
                           "per tile)",
-             "triangular": "trsv_step_kernel (blocked forward/backward solves of the level-1 factors)"}[args.local_solve]
+             "triangular": "trsv_step_kernel (blocked forward/backward solves of the level-1 factors)",
+             "block": "symv_part_kernel<double, 3> (upper 64x64 tiles of the velocity-block inverses L_i^-1, three "
+                      "component vectors per tile; two launches per apply)"}[args.local_solve]
     log(f"[bench] apply {t_apply_ms:.3f} ms; phases ms gather/restrict {ph[0]:.3f} solve {ph[1]:.3f}+{ph[2]:.3f} "
         f"scatter {ph[3]:.3f}; dominant kernel {k_launches} launches in the timed solves, {k_avg_us:.1f} us avg, "
         f"{k_bytes:.3e} B each -> {achieved:.0f} GB/s")
@@ -615,7 +633,7 @@ def main():
         out["variants"].update(precision_variants(w, args, b, x, z, r, args.local_solve))
         args.learned = True
     if args.learned:
-        out["learned"] = learned_variant(s, b, w, args.steps)
+        out["learned"] = learned_variant(s, b, w, args.steps, args.local_solve)
         if "variants" in out:
             out["variants"]["learned_fallback"] = out["learned"]["learned_fallback"]
             out["variants"]["learned"] = out["learned"]["learned"]

@@ -64,6 +64,19 @@ typedef enum { GDSW_FP64 = 0, GDSW_FP32 = 1, GDSW_BF16 = 2 } gdsw_precision;
 
 /* How the local solves A_i^-1 R_i r of eq. (2.2) / (2.5), and the coarse
  * solves, are carried out.  All give A_i^-1 v up to rounding.
+ *   GDSW_SOLVE_BLOCK: the local saddle-point matrix by its blocks, with no
+ *     dense n_i x n_i inverse.  The velocity block of A_i is I_3 (x) L_i (one
+ *     scalar matrix for the three components: the gradient form of the
+ *     viscous term), so with S_i = B_i K_i^-1 B_i^T the local solve is
+ *     U1 = L^-1 F, p = S^-1 (B U1 - g), u = U1 - L^-1 B^T p: L_i^-1 and S_i^-1
+ *     are formed at setup (Gauss-Jordan, FP64) and stored as upper tiles
+ *     (L_i^-1 in the local precision), B_i as sparse rows.  An apply reads
+ *     L_i^-1 twice (three vectors per pass), S_i^-1 once and B_i twice: about
+ *     a quarter of the bytes of GDSW_SOLVE_SYMMETRIC at 16^3.  EINVAL when the
+ *     velocity block lacks that structure (numbering 3 node + component,
+ *     uncoupled components with equal values) or max_rhs > 1; the learned
+ *     interior solve and batches are not offered with it.  Coarse levels use
+ *     the symmetric storage.
  *   GDSW_SOLVE_INVERSE (default): the setup forms A_i^-1 explicitly by
  *     Gauss-Jordan elimination without pivoting (velocity DOFs first; its
  *     pivots are those of the no-pivoting LU) and stores it in place of the
@@ -74,7 +87,12 @@ typedef enum { GDSW_FP64 = 0, GDSW_FP32 = 1, GDSW_BF16 = 2 } gdsw_precision;
  *     A_i is), stored as its upper triangle of 64 x 64 tiles: about half
  *     the bytes per apply.  One right-hand side per product (max_rhs <= 1,
  *     EINVAL otherwise); batches and the learned interior solve accept it. */
-typedef enum { GDSW_SOLVE_INVERSE = 0, GDSW_SOLVE_TRIANGULAR = 1, GDSW_SOLVE_SYMMETRIC = 2 } gdsw_local_solve;
+typedef enum {
+  GDSW_SOLVE_INVERSE = 0,
+  GDSW_SOLVE_TRIANGULAR = 1,
+  GDSW_SOLVE_SYMMETRIC = 2,
+  GDSW_SOLVE_BLOCK = 3
+} gdsw_local_solve;
 
 /* The mesh: structured Q2/Q1 Stokes on the unit cube (Section 4). */
 typedef struct {

@@ -28,7 +28,7 @@ _lib = C.CDLL(LIB_PATH)
 
 FP64, FP32, BF16 = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
-LOCAL_SOLVES = {"inverse": 0, "triangular": 1, "symmetric": 2}
+LOCAL_SOLVES = {"inverse": 0, "triangular": 1, "symmetric": 2, "block": 3}
 PRESSURE_ELEMENTS = {"q1": 0, "p1disc": 1}
 COARSE_SPACES = {"gdsw": 0, "gdsw*": 1}
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "ESINGULAR", 4: "ENOCONV", 5: "EDEVICE", 6: "EUNSUPPORTED"}

@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgdsw.so")
 
 HIP_SOURCES = ["kernels_factor.hip", "kernels_inverse.hip", "kernels_gemv.hip", "kernels_symv.hip", "kernels_gemm.hip", "kernels_multi.hip", "kernels_ops.hip", "kernels_learned.hip", "setup.hip", "solve.hip", "solve_multi.hip", "batch.hip",
-               "learned.hip", "noalloc.hip", "abi.hip"]
+               "learned.hip", "noalloc.hip", "block.hip", "abi.hip"]
 CXX_SOURCES = ["problem.cpp", "algebraic.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

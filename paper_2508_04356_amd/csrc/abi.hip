@@ -76,10 +76,11 @@ ProblemSpec spec_of(const gdsw_mesh* mesh, const gdsw_decomposition* dec) {
   if (dec->local_precision < 0 || dec->local_precision > 2) throw std::invalid_argument("bad local_precision");
   if (dec->tile != 0 && dec->tile != 64 && dec->tile != 128) throw std::invalid_argument("tile must be 0, 64 or 128");
   if (dec->local_solve != GDSW_SOLVE_INVERSE && dec->local_solve != GDSW_SOLVE_TRIANGULAR &&
-      dec->local_solve != GDSW_SOLVE_SYMMETRIC)
-    throw std::invalid_argument("local_solve must be GDSW_SOLVE_INVERSE, _TRIANGULAR or _SYMMETRIC");
-  if (dec->local_solve == GDSW_SOLVE_SYMMETRIC && dec->max_rhs > 1)
-    throw std::invalid_argument("GDSW_SOLVE_SYMMETRIC takes one right-hand side per product (max_rhs <= 1)");
+      dec->local_solve != GDSW_SOLVE_SYMMETRIC && dec->local_solve != GDSW_SOLVE_BLOCK)
+    throw std::invalid_argument("local_solve must be GDSW_SOLVE_INVERSE, _TRIANGULAR, _SYMMETRIC or _BLOCK");
+  if ((dec->local_solve == GDSW_SOLVE_SYMMETRIC || dec->local_solve == GDSW_SOLVE_BLOCK) && dec->max_rhs > 1)
+    throw std::invalid_argument("GDSW_SOLVE_SYMMETRIC and GDSW_SOLVE_BLOCK take one right-hand side per product "
+                                "(max_rhs <= 1)");
   if (dec->max_rhs < 0 || dec->max_rhs > 32) throw std::invalid_argument("max_rhs must be in 0..32");
   return s;
 }
@@ -127,6 +128,7 @@ gdsw_status gdsw_setup(const gdsw_mesh* mesh, const gdsw_decomposition* dec, voi
     c.local_prec = dec->local_precision;
     c.solve_mode = dec->local_solve == GDSW_SOLVE_TRIANGULAR  ? SOLVE_TRSV
                    : dec->local_solve == GDSW_SOLVE_SYMMETRIC ? SOLVE_SYM
+                   : dec->local_solve == GDSW_SOLVE_BLOCK     ? SOLVE_BLOCK
                                                               : SOLVE_INVERSE;
     c.max_rhs = std::max(1, dec->max_rhs);
     GDSW_HIP(hipGetDevice(&c.device));
@@ -225,6 +227,7 @@ gdsw_status gdsw_setup_algebraic(const gdsw_algebraic_problem* prob, const gdsw_
     c.local_prec = dec->local_precision;
     c.solve_mode = dec->local_solve == GDSW_SOLVE_TRIANGULAR  ? SOLVE_TRSV
                    : dec->local_solve == GDSW_SOLVE_SYMMETRIC ? SOLVE_SYM
+                   : dec->local_solve == GDSW_SOLVE_BLOCK     ? SOLVE_BLOCK
                                                               : SOLVE_INVERSE;
     c.max_rhs = std::max(1, dec->max_rhs);
     GDSW_HIP(hipGetDevice(&c.device));
@@ -280,8 +283,14 @@ gdsw_status gdsw_get_sizes(const gdsw_ctx* ctx, gdsw_sizes* out) {
   out->coarse_bytes = c.coarse_bytes;
   out->device_bytes = c.arena.used;
   if (!c.host_only) {
-    out->solve_bytes = c.L1.algorithmic_bytes() + c.HI.algorithmic_bytes();
-    out->solve_launches = c.L1.launches() + c.HI.launches();
+    if (c.solve_mode == SOLVE_BLOCK) {  // two passes over L_i^-1, one over S_i^-1, B twice
+      out->solve_bytes = 2 * c.L1.algorithmic_bytes() + c.LP.algorithmic_bytes() + c.HI.algorithmic_bytes() +
+                         c.blk.b_bytes;
+      out->solve_launches = 2 * c.L1.launches() + c.LP.launches() + c.HI.launches() + 3;
+    } else {
+      out->solve_bytes = c.L1.algorithmic_bytes() + c.HI.algorithmic_bytes();
+      out->solve_launches = c.L1.launches() + c.HI.launches();
+    }
   }
   return GDSW_OK;
 }
@@ -718,6 +727,8 @@ void gdsw_destroy(gdsw_ctx* ctx) {
   if (!ctx) return;
   learned_release(ctx->c);
   for (auto& e : ctx->c.timer.ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : ctx->c.it_ev)
+    if (e) (void)hipEventDestroy(e);
   release_graphs(ctx->c);
   if (ctx->c.mk.h_pinned) (void)hipHostFree(ctx->c.mk.h_pinned);
   if (ctx->c.mk.h_active) (void)hipHostFree(ctx->c.mk.h_active);

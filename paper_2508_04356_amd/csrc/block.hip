@@ -1,0 +1,132 @@
+// Block local solve: A_i^-1 from the saddle-point structure of A_i instead of
+// a dense n_i x n_i inverse.  With the gradient form of the viscous term the
+// velocity block of every local matrix is K_i = I_3 (x) L_i (the same scalar
+// matrix L_i for each component, no coupling between components), so with
+// S_i = B_i K_i^-1 B_i^T (SPD) the local solve of [K B^T; B 0] [u; p] = [f; g]
+// is
+//     U1 = L^-1 F,   p = S^-1 (B U1 - g),   u = U1 - L^-1 (B^T p)
+// (F, U1: the velocity right-hand side and solution as three component
+// vectors).  An apply reads L_i^-1 twice (upper tiles, three vectors per
+// pass), S_i^-1 once and B_i twice: at 16^3 about a quarter of the bytes of
+// the dense symmetric inverse, and the same operator up to rounding.
+#include <hip/hip_runtime.h>
+
+#include "context.h"
+#include "kernels.h"
+
+namespace gdsw {
+namespace {
+
+// Bt of subdomain f (column q = the velocity vector B[q, :]^T in component-
+// major order: entry (c, a) at c * npv + a) from the CSR rows of its
+// pressure DOFs; velocity columns outside the local set are skipped.
+__global__ void fill_bt_kernel(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                               const double* __restrict__ val, int64_t n_u, const int32_t* __restrict__ vx_ptr,
+                               const int32_t* __restrict__ vx, const int32_t* __restrict__ pr_ptr,
+                               const int32_t* __restrict__ pr, const int32_t* __restrict__ npv,
+                               const int64_t* __restrict__ off, int f0, double* __restrict__ bt) {
+  const int f = f0 + blockIdx.y;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int np = pr_ptr[f + 1] - pr_ptr[f];
+  if (q >= np) return;
+  const int nv = vx_ptr[f + 1] - vx_ptr[f];
+  const int32_t* v = vx + vx_ptr[f];
+  const int64_t ld = 3 * (int64_t)npv[f];
+  double* out = bt + off[blockIdx.y] + (int64_t)q * ld;
+  const int32_t g = pr[pr_ptr[f] + q];
+  for (int32_t e = rowptr[g]; e < rowptr[g + 1]; ++e) {
+    const int32_t c = col[e];
+    if (c >= n_u) continue;  // pressure columns (the pressure block is zero)
+    const int comp = c % 3;
+    const int32_t key = c - comp;
+    int lo = 0, hi = nv;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (v[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    if (lo < nv && v[lo] == key) out[(int64_t)comp * npv[f] + lo] = val[e];
+  }
+}
+
+// dst block f (np x np, ld npad) <- src (np x np, ld np)
+__global__ void copy_blocks_kernel(const double* __restrict__ src, const int64_t* __restrict__ soff,
+                                   const int32_t* __restrict__ N, double* __restrict__ base,
+                                   const int64_t* __restrict__ doff, const int32_t* __restrict__ LD) {
+  const int f = blockIdx.y;
+  const int n = N[f];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)n * n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e % n), c = (int)(e / n);
+    base[doff[f] + (int64_t)c * LD[f] + r] = src[soff[f] + e];
+  }
+}
+
+// Sparse row products over the work vector, LPR lanes per row: lane l sums
+// the row's entries l, l + LPR, ... in order, the lanes are combined by a
+// fixed butterfly (the same sums on every run).
+// mode 0: w[row_pos[r]] = sum - w[row_pos[r]]   (t = B U1 - g, pressure rows)
+// mode 1: out[row_pos[r]] = sum                 (B^T p, velocity rows)
+template <int LPR, int MODE>
+__global__ __launch_bounds__(256) void rowprod_kernel(int64_t nrows, const int32_t* __restrict__ row_pos,
+                                                      const int64_t* __restrict__ ptr, const int32_t* __restrict__ pos,
+                                                      const double* __restrict__ val, double* __restrict__ w,
+                                                      double* __restrict__ out) {
+  const int64_t r = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / LPR;
+  const int l = threadIdx.x % LPR;
+  const bool live = r < nrows;  // uniform over the row's lanes
+  double s = 0.0;
+  if (live)
+    for (int64_t k = ptr[r] + l; k < ptr[r + 1]; k += LPR) s = fma(val[k], w[pos[k]], s);
+#pragma unroll
+  for (int d = 1; d < LPR; d *= 2) s += __shfl_xor(s, d);
+  if (live && l == 0) {
+    if (MODE == 0)
+      w[row_pos[r]] = s - w[row_pos[r]];
+    else
+      out[row_pos[r]] = s;
+  }
+}
+
+unsigned blocks_for(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65535)); }
+
+}  // namespace
+
+void block_fill_bt(const int32_t* rowptr, const int32_t* col, const double* val, int64_t n_u,
+                   const int32_t* vx_ptr, const int32_t* vx, const int32_t* pr_ptr, const int32_t* pr,
+                   const int32_t* npv, const int64_t* off, int f0, int cnt, int max_np, double* bt, hipStream_t st) {
+  if (cnt == 0 || max_np == 0) return;
+  fill_bt_kernel<<<dim3((max_np + 127) / 128, cnt), 128, 0, st>>>(rowptr, col, val, n_u, vx_ptr, vx, pr_ptr, pr, npv,
+                                                                   off, f0, bt);
+  GDSW_HIP(hipGetLastError());
+}
+
+void copy_blocks(const double* src, const int64_t* soff, const int32_t* n, int count, int64_t max_elems,
+                 double* base, const int64_t* doff, const int32_t* ld, hipStream_t st) {
+  if (count == 0 || max_elems == 0) return;
+  copy_blocks_kernel<<<dim3(blocks_for(max_elems), count), 256, 0, st>>>(src, soff, n, base, doff, ld);
+  GDSW_HIP(hipGetLastError());
+}
+
+void block_local_solve(Context& ctx, hipStream_t st) {
+  const BlockSolve& b = ctx.blk;
+  FactorSet& L = ctx.L1;
+  if (L.count == 0) return;
+  // U1 = L^-1 F (three vectors per matrix, in place in the work vector)
+  symv_desc_launch(L.prec, L.d_desc, L.gemv[0], L.d_partial, L.partial_len, st, nullptr, L.timer,
+                   (double)L.alg_bytes, 3);
+  // t = B U1 - g in the pressure segments
+  // pressure rows hold hundreds of entries: a wave per row
+  rowprod_kernel<64, 0><<<(unsigned)((b.n_prow * 64 + 255) / 256), 256, 0, st>>>(
+      b.n_prow, b.d_prow_pos, b.d_bm_ptr, b.d_bm_pos, b.d_bm_val, ctx.d_w, nullptr);
+  // p = S^-1 t (and, with two levels, the coarse solve in the same launch)
+  local_solve_set(ctx.LP, ctx.d_w, st);
+  // w2 = B^T p, then u = U1 - L^-1 w2 (the block-row sums subtract from U1)
+  // velocity rows hold up to a few dozen: eight lanes per row
+  rowprod_kernel<8, 1><<<(unsigned)((b.n_vrow * 8 + 255) / 256), 256, 0, st>>>(
+      b.n_vrow, b.d_vrow_pos, b.d_bt_ptr, b.d_bt_pos, b.d_bt_val, ctx.d_w, b.d_w2);
+  symv_desc_launch(L.prec, b.d_desc2, L.gemv[0], L.d_partial, L.partial_len, st, nullptr, L.timer,
+                   (double)L.alg_bytes, 3);
+  GDSW_HIP(hipGetLastError());
+}
+
+}  // namespace gdsw

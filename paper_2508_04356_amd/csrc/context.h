@@ -1,11 +1,14 @@
 // Device-side context of one GDSW problem (internal to the library).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 #include <memory>
 #include <string>
+#include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "problem.h"
@@ -64,6 +67,7 @@ inline size_t elem_size(int prec) { return prec == P_FP64 ? 8 : (prec == P_FP32 
 constexpr int SOLVE_INVERSE = 0;  // explicit inverse, applied as a dense matrix-vector product
 constexpr int SOLVE_TRSV = 1;     // LU factors, blocked forward/backward substitution
 constexpr int SOLVE_SYM = 2;      // symmetric explicit inverse, upper 64 x 64 tiles only
+constexpr int SOLVE_BLOCK = 3;    // velocity block I_3 (x) L and Schur complement (block.hip)
 #ifndef GDSW_GEMV_CW
 #define GDSW_GEMV_CW 1024
 #endif
@@ -71,11 +75,14 @@ constexpr int GEMV_CW = GDSW_GEMV_CW;  // columns per matrix-vector work item
 
 // One stored inverse for the matrix-vector kernels: its entries (column-major,
 // leading dimension np, in the set's precision) and its segment of a work
-// vector (n entries, overwritten with the product).
+// vector (n entries, overwritten with the product).  The symmetric-tile
+// kernels can apply the matrix to NC vectors at once: vector k at x + k vs.
 struct GemvDesc {
   const void* a;
   double* x;
   int32_t n, np;
+  int32_t vs = 0;       // stride between the vectors of a several-vector product
+  double* y = nullptr;  // symmetric products: y -= M x instead of x <- M x
 };
 
 // HIP events around each launch of a set's dominant solve kernel (slot 0),
@@ -87,6 +94,29 @@ struct KernelTimer {
   double bytes = 0.0;                // algorithmic bytes of the recorded launches
   std::vector<hipEvent_t> ev;        // 2 * CAP events, created on first enable
 };
+
+// Launches kernel<<<grid, block, 0, st>>>(args...).  With a timer that is on
+// and not full, the dispatch itself stamps the kernel's start and end into the
+// timer's next event pair (hipExtLaunchKernel): no marker packets go between
+// the launches, which cost about 6 us of idle time each on MI355X.
+template <typename... P, typename... Args>
+void timed_launch(KernelTimer* tm, double bytes, void (*kernel)(P...), dim3 grid, dim3 block, hipStream_t st,
+                  Args... args) {
+  if (tm && tm->on && tm->used < KernelTimer::CAP) {
+    std::tuple<std::decay_t<P>...> a(args...);  // the kernel's own parameter types
+    void* ptrs[sizeof...(P) > 0 ? sizeof...(P) : 1];
+    std::apply([&](auto&... v) {
+      int i = 0;
+      ((ptrs[i++] = (void*)&v), ...);
+    }, a);
+    GDSW_HIP(hipExtLaunchKernel((const void*)kernel, grid, block, ptrs, 0, st, tm->ev[2 * tm->used],
+                                tm->ev[2 * tm->used + 1], 0));
+    ++tm->used;
+    tm->bytes += bytes;
+  } else {
+    kernel<<<grid, block, 0, st>>>(args...);
+  }
+}
 
 struct FactorSet {
   int mode = SOLVE_INVERSE;
@@ -137,12 +167,34 @@ struct FactorSet {
   int64_t* d_xpoff = nullptr;        //   xb[32 * xpoff[f] + j * npad[f] + row]
   uint16_t* d_xb = nullptr;
   uint64_t gen = 0;                    // bumped by every re-plan (item arrays, partial buffers)
+  int nc = 1;                          // symmetric storage: vectors per matrix (1, or 3 for the
+                                       // velocity blocks of the block local solve)
   uint64_t algorithmic_bytes() const;  // sum n^2 * sizeof(prec)
   uint64_t alg_bytes = 0;              // algorithmic_bytes(), set when planned
   int64_t launches() const;            // solve kernel launches per pass (slot 0)
 };
 
 struct LearnedSolve;
+
+// Block local solve (SOLVE_BLOCK): the level-1 set L1 holds L_i^-1 (upper
+// tiles, three component vectors per matrix: x, y, z at vs = npad apart in
+// the work vector), LP holds S_i^-1 (and the coarse inverse with two levels);
+// B_i as flat row lists over absolute work-vector positions.
+struct BlockSolve {
+  int64_t n_prow = 0;                // pressure rows of every local problem
+  int32_t* d_prow_pos = nullptr;     // their work positions
+  int64_t* d_bm_ptr = nullptr;       // B rows: velocity positions and values
+  int32_t* d_bm_pos = nullptr;
+  double* d_bm_val = nullptr;
+  int64_t n_vrow = 0;                // velocity rows (component, node) of every local problem
+  int32_t* d_vrow_pos = nullptr;
+  int64_t* d_bt_ptr = nullptr;       // B^T rows: pressure positions and values
+  int32_t* d_bt_pos = nullptr;
+  double* d_bt_val = nullptr;
+  double* d_w2 = nullptr;            // second work vector (B^T p, then L^-1 B^T p), n_w1
+  GemvDesc* d_desc2 = nullptr;       // L1's matrices against d_w2
+  uint64_t b_bytes = 0;              // bytes of both B row lists
+};
 
 struct Context {
   Problem P;
@@ -193,6 +245,8 @@ struct Context {
   // level-1 local solves
   FactorSet L1;      // level-1 local factors (local_prec)
   FactorSet HI;      // FP64: coarse (two levels) or level-2 + level-3 factors
+  FactorSet LP;      // block local solve: Schur complement inverses (+ coarse with two levels)
+  BlockSolve blk;
   bool merged = false;  // true when L1 also holds the coarse factor(s)
   int32_t* d_gidx = nullptr;      // wbuf position -> global DOF (or -1)
   int64_t n_w1 = 0;               // length of the level-1 work segment
@@ -253,6 +307,7 @@ struct Context {
   double* d_t1 = nullptr;          // n-vectors
   double* d_t2 = nullptr;
   double* h_pinned = nullptr;      // pinned host scalars
+  hipEvent_t it_ev[2] = {nullptr, nullptr};  // end of FGMRES iteration j, slot j % 2
   int64_t ldv = 0;
   int n_part_blocks = 0;
 
@@ -278,6 +333,13 @@ void spmv(Context& ctx, const double* x, double* y, hipStream_t st);
 // apply_precond with the product's partial sums in the library's static
 // per-device scratch array instead of the context's buffer (noalloc.hip)
 void apply_precond_noalloc(Context& ctx, const double* r, double* z, hipStream_t st);
+// block local solve of every level-1 subdomain in the work vector (block.hip)
+void block_local_solve(Context& ctx, hipStream_t st);
+void block_fill_bt(const int32_t* rowptr, const int32_t* col, const double* val, int64_t n_u,
+                   const int32_t* vx_ptr, const int32_t* vx, const int32_t* pr_ptr, const int32_t* pr,
+                   const int32_t* npv, const int64_t* off, int f0, int cnt, int max_np, double* bt, hipStream_t st);
+void copy_blocks(const double* src, const int64_t* soff, const int32_t* n, int count, int64_t max_elems,
+                 double* base, const int64_t* doff, const int32_t* ld, hipStream_t st);
 double* noalloc_scratch(int device);  // device address of the array (looked up once per device)
 uint64_t noalloc_scratch_bytes();
 struct FgmresResult {

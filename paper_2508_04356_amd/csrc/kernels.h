@@ -75,7 +75,8 @@ void symv_set(const FactorSet& fs, double* w, hipStream_t st, int slot = 0, cons
 // tiles of matrix g; items of symv_items with g for f); want (or null)
 // skips unselected matrices; tm (or null) times the tile launch.
 void symv_desc_launch(int prec, const GemvDesc* desc, const FactorSet::GemvPlan& G, double* partial,
-                      int64_t partial_len, hipStream_t st, const int32_t* want, KernelTimer* tm, double bytes);
+                      int64_t partial_len, hipStream_t st, const int32_t* want, KernelTimer* tm, double bytes,
+                      int nc = 1);
 // Shape of the set's several-column products: rows and summation columns
 // per work item and which kernel (fs.gemm_rb, gemm_cw, gemm_lds).
 void gemm_choose(FactorSet& fs);

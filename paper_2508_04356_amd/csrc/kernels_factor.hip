@@ -431,13 +431,10 @@ void trsv_launch(const FactorSet& fs, double* w, hipStream_t st, int slot, const
     if (cnt == 0) continue;
     KernelTimer* tm =
         (slot == 0 && fs.timer && fs.timer->on && fs.timer->used < KernelTimer::CAP) ? fs.timer : nullptr;
-    if (tm) GDSW_HIP(hipEventRecord(tm->ev[2 * tm->used], st));
-    trsv_step_kernel<T, NB, NW><<<cnt, 64 * NW, 0, st>>>(store, dinv, fs.d_n, fs.d_npad, fs.d_off, fs.d_doff,
-                                                         fs.d_xoff, S.d_items + S.step_start[g], w, want);
-    if (tm) {
-      GDSW_HIP(hipEventRecord(tm->ev[2 * tm->used++ + 1], st));
-      tm->bytes += (double)fs.alg_bytes / (double)fs.launches();  // average share of one sweep step
-    }
+    // bytes: the average share of one sweep step
+    timed_launch(tm, (double)fs.alg_bytes / (double)fs.launches(), trsv_step_kernel<T, NB, NW>, dim3(cnt),
+                 dim3(64 * NW), st, store, dinv, fs.d_n, fs.d_npad, fs.d_off, fs.d_doff, fs.d_xoff,
+                 S.d_items + S.step_start[g], w, want);
   }
 }
 

@@ -485,35 +485,20 @@ void gemm_launch(const FactorSet& fs, double* w, int64_t ldk, int nrhs, hipStrea
     if constexpr (sizeof(T) == 2)
       stage_bf16_kernel<<<dim3((fs.max_np + 63) / 64, fs.count), 256, 0, st>>>(fs.d_n, fs.d_npad, fs.d_xoff,
                                                                             fs.d_xpoff, wj, ldk, nr, fs.d_xb);
-    if (tm) GDSW_HIP(hipEventRecord(tm->ev[2 * tm->used], st));
+    const double bytes = (double)fs.alg_bytes;
     if constexpr (sizeof(T) == 2) {
       const uint16_t* store = static_cast<const uint16_t*>(fs.store);
-      if (nr > 16)
-        gemm_part_bf16_lds_kernel<2><<<G.n1, 256, 0, st>>>(store, fs.d_off, fs.d_n, fs.d_npad, fs.d_xpoff,
-                                                          G.d_items1, fs.d_xb, cw, part);
-      else
-        gemm_part_bf16_lds_kernel<1><<<G.n1, 256, 0, st>>>(store, fs.d_off, fs.d_n, fs.d_npad, fs.d_xpoff,
-                                                          G.d_items1, fs.d_xb, cw, part);
+      timed_launch(tm, bytes, nr > 16 ? gemm_part_bf16_lds_kernel<2> : gemm_part_bf16_lds_kernel<1>, dim3(G.n1),
+                   dim3(256), st, store, fs.d_off, fs.d_n, fs.d_npad, fs.d_xpoff, G.d_items1, fs.d_xb, cw, part);
     } else if (sizeof(T) == 8 && fs.gemm_lds) {
       const double* store = reinterpret_cast<const double*>(fs.store);
       double* pd = reinterpret_cast<double*>(part);
-      if (nr > 16)
-        gemm_part_f64_lds_kernel<2><<<G.n1, 256, 0, st>>>(store, fs.d_off, fs.d_n, fs.d_npad, fs.d_xoff, G.d_items1,
-                                                         wj, ldk, nr, cw, pd);
-      else
-        gemm_part_f64_lds_kernel<1><<<G.n1, 256, 0, st>>>(store, fs.d_off, fs.d_n, fs.d_npad, fs.d_xoff, G.d_items1,
-                                                         wj, ldk, nr, cw, pd);
+      timed_launch(tm, bytes, nr > 16 ? gemm_part_f64_lds_kernel<2> : gemm_part_f64_lds_kernel<1>, dim3(G.n1),
+                   dim3(256), st, store, fs.d_off, fs.d_n, fs.d_npad, fs.d_xoff, G.d_items1, wj, ldk, nr, cw, pd);
     } else {
-      if (nr > 16)
-        gemm_part_kernel<T, 2><<<G.n1, 256, 0, st>>>(static_cast<const T*>(fs.store), fs.d_off, fs.d_n, fs.d_npad,
-                                                     fs.d_xoff, G.d_items1, wj, ldk, nr, cw, part);
-      else
-        gemm_part_kernel<T, 1><<<G.n1, 256, 0, st>>>(static_cast<const T*>(fs.store), fs.d_off, fs.d_n, fs.d_npad,
-                                                     fs.d_xoff, G.d_items1, wj, ldk, nr, cw, part);
-    }
-    if (tm) {
-      GDSW_HIP(hipEventRecord(tm->ev[2 * tm->used++ + 1], st));
-      tm->bytes += (double)fs.alg_bytes;
+      timed_launch(tm, bytes, nr > 16 ? gemm_part_kernel<T, 2> : gemm_part_kernel<T, 1>, dim3(G.n1), dim3(256), st,
+                   static_cast<const T*>(fs.store), fs.d_off, fs.d_n, fs.d_npad, fs.d_xoff, G.d_items1, wj, ldk, nr,
+                   cw, part);
     }
     if (sizeof(T) == 8 && fs.gemm_lds)
       gemm_sum_kernel<P, DL_RB><<<G.n2, 256, 0, st>>>(fs.d_n, fs.d_xoff, G.d_items2, part, wj, ldk, nr);

@@ -125,17 +125,9 @@ void gemv_launch(const GemvDesc* desc, const FactorSet::GemvPlan& G, int cw, dou
   if (G.n1 == 0) return;
   constexpr int RB = 64 * VecW<T>::W;
   constexpr int NW = GDSW_GEMV_NW;
-  if (tm) GDSW_HIP(hipEventRecord(tm->ev[2 * tm->used], st));
-  if (cw == 512)
-    gemv_part_kernel<T, NW, 512><<<G.n1, 64 * NW, 0, st>>>(desc, G.d_items1, partial, want);
-  else if (cw == 2048)
-    gemv_part_kernel<T, NW, 2048><<<G.n1, 64 * NW, 0, st>>>(desc, G.d_items1, partial, want);
-  else
-    gemv_part_kernel<T, NW, 1024><<<G.n1, 64 * NW, 0, st>>>(desc, G.d_items1, partial, want);
-  if (tm) {
-    GDSW_HIP(hipEventRecord(tm->ev[2 * tm->used++ + 1], st));
-    tm->bytes += bytes;
-  }
+  auto* k = cw == 512 ? gemv_part_kernel<T, NW, 512>
+            : cw == 2048 ? gemv_part_kernel<T, NW, 2048> : gemv_part_kernel<T, NW, 1024>;
+  timed_launch(tm, bytes, k, dim3(G.n1), dim3(64 * NW), st, desc, G.d_items1, partial, want);
   gemv_sum_kernel<RB><<<G.n2, 256, 0, st>>>(desc, G.d_items2, partial, want);
 }
 

@@ -48,6 +48,12 @@ constexpr int SYMV_RUN = GDSW_SYMV_RUN;
 #ifndef GDSW_SYMV_NT
 #define GDSW_SYMV_NT 1  // non-temporal tile loads
 #endif
+#ifndef GDSW_SYMV_KB
+// vectors reduced per barrier round when a tile serves several: one per
+// round measured 61.4 us against 67.1 us for all three at once (16^3, the
+// velocity-block inverses, MI355X; the larger LDS footprint halves occupancy)
+#define GDSW_SYMV_KB 1
+#endif
 
 template <typename T, typename A>
 __device__ inline void tile_load16(const T* p, A (&o)[VecW<T>::W]) {
@@ -58,7 +64,9 @@ __device__ inline void tile_load16(const T* p, A (&o)[VecW<T>::W]) {
 #endif
 }
 
-template <typename T>
+// NC > 1: the tile is applied to NC vectors (x + k vs, k < NC) while it sits
+// in registers; the partial slots hold NC blocks of 64 per item slot.
+template <typename T, int NC>
 __global__ __launch_bounds__(256) void symv_part_kernel(const GemvDesc* __restrict__ desc,
                                                         const int4* __restrict__ items, double* __restrict__ prow,
                                                         double* __restrict__ pcol, const int32_t* __restrict__ want) {
@@ -67,9 +75,12 @@ __global__ __launch_bounds__(256) void symv_part_kernel(const GemvDesc* __restri
   constexpr int PPC = ST / E;          // pieces per column
   constexpr int CPT = 256 / PPC;       // columns covered by one piece per thread
   constexpr int PER = ST / CPT;        // pieces per thread
-  __shared__ Acc xi[ST], xj[SYMV_RUN][ST];  // the vector blocks of row I and of every tile of the run
-  __shared__ Acc rred[CPT][ST];        // row partials per column group
-  __shared__ Acc cred[ST][PPC + 1];    // column partials per row group
+  __shared__ Acc xi[NC][ST], xj[NC][SYMV_RUN][ST];  // the vector blocks of row I and of every tile of the run
+  // the NC vectors are reduced KB at a time (one pair of barriers per round)
+  constexpr int KB = GDSW_SYMV_KB < NC ? GDSW_SYMV_KB : NC;
+  static_assert(NC % KB == 0, "rounds of equal size");
+  __shared__ Acc rred[KB][CPT][ST];    // row partials per column group
+  __shared__ Acc cred[KB][ST][PPC + 1];  // column partials per row group
   // work-groups are dealt to the 8 XCDs in turn; for FP32 tiles XCD x takes
   // the x-th contiguous eighth of the items instead (a permutation of the
   // grid: 1032 -> 999 us at 24^3 on MI355X, while FP64 lost 1.5% and BF16
@@ -97,55 +108,81 @@ __global__ __launch_bounds__(256) void symv_part_kernel(const GemvDesc* __restri
   static_assert(SYMV_RUN * ST <= 256, "one vector entry per thread");
   const auto* xg = as_global<double>(x);
   const int ri = ST * I + (t % ST), rj = ST * J0 + (t % (SYMV_RUN * ST));
-  const double xiv = xg[min(ri, d.np - 1)], xjv = xg[min(rj, d.np - 1)];
+  double xiv[NC], xjv[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    xiv[k] = xg[(int64_t)k * d.vs + min(ri, d.np - 1)];
+    xjv[k] = xg[(int64_t)k * d.vs + min(rj, d.np - 1)];
+  }
   Acc v[PER][E], vn[PER][E];
 #pragma unroll
   for (int u = 0; u < PER; ++u) tile_load16(tiles + (t + 256 * u) * E, v[u]);
   auto store_x = [&]() {
-    if (t < ST) xi[t] = ri < n ? (Acc)xiv : (Acc)0;
-    if (t < SYMV_RUN * ST) xj[t / ST][t % ST] = rj < n ? (Acc)xjv : (Acc)0;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      if (t < ST) xi[k][t] = ri < n ? (Acc)xiv[k] : (Acc)0;
+      if (t < SYMV_RUN * ST) xj[k][t / ST][t % ST] = rj < n ? (Acc)xjv[k] : (Acc)0;
+    }
   };
   // products of tile J held in v: row part into rred, transposed part into
-  // cred; the row parts of the run's tiles all belong to block row I and are
-  // summed here (in tile order), written once, to the run's first slot
-  double racc = 0.0;
+  // cred, one vector at a time; the row parts of the run's tiles all belong
+  // to block row I and are summed here (in tile order), written once, to the
+  // run's first slot
+  double racc[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) racc[k] = 0.0;
   auto products = [&](int J) {
     const int b = J - J0;
-    __syncthreads();  // xi / xj written; the previous tile's reductions read
-    Acc rs[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) rs[e] = 0;
+    for (int k0 = 0; k0 < NC; k0 += KB) {
+      __syncthreads();  // xi / xj written; the previous round's reductions read
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {  // block row I: rows r0 .. r0 + E - 1 over columns cg + CPT u
-      const Acc xc = xj[b][cg + CPT * u];
+      for (int kk = 0; kk < KB; ++kk) {
+        const int k = k0 + kk;
+        Acc rs[E];
 #pragma unroll
-      for (int e = 0; e < E; ++e) rs[e] = fma(v[u][e], xc, rs[e]);
-    }
+        for (int e = 0; e < E; ++e) rs[e] = 0;
 #pragma unroll
-    for (int e = 0; e < E; ++e) rred[cg][r0 + e] = rs[e];
-    if (J > I) {  // uniform: block row J gets the transposed tile
+        for (int u = 0; u < PER; ++u) {  // block row I: rows r0 .. r0 + E - 1 over columns cg + CPT u
+          const Acc xc = xj[k][b][cg + CPT * u];
 #pragma unroll
-      for (int u = 0; u < PER; ++u) {
-        Acc cs = 0;
+          for (int e = 0; e < E; ++e) rs[e] = fma(v[u][e], xc, rs[e]);
+        }
 #pragma unroll
-        for (int e = 0; e < E; ++e) cs = fma(v[u][e], xi[r0 + e], cs);
-        cred[cg + CPT * u][rg] = cs;
+        for (int e = 0; e < E; ++e) rred[kk][cg][r0 + e] = rs[e];
+        if (J > I) {  // uniform: block row J gets the transposed tile
+#pragma unroll
+          for (int u = 0; u < PER; ++u) {
+            Acc cs = 0;
+#pragma unroll
+            for (int e = 0; e < E; ++e) cs = fma(v[u][e], xi[k][r0 + e], cs);
+            cred[kk][cg + CPT * u][rg] = cs;
+          }
+        }
       }
-    }
-    __syncthreads();
-    const int p = p0 + b;
-    if (t < ST) {
-      double s = 0.0;
+      __syncthreads();
+      // 2 KB sums of 64 entries (row sums of each vector of the round, then
+      // column sums), dealt to the four waves: wave q takes sums q, q + 4, ...
+      const int p = p0 + b;
+      const int l = t % ST, wq = t / ST;
 #pragma unroll
-      for (int g = 0; g < CPT; ++g) s += (double)rred[g][t];
-      racc += s;
-      if (J == J1 - 1) prow[(int64_t)p0 * ST + t] = racc;
-    } else if (t < 2 * ST && J > I) {
-      const int c = t - ST;
-      double s = 0.0;
+      for (int it = 0; it < 2 * KB; ++it) {
+        if (it % 4 != wq) continue;  // uniform per wave
+        if (it < KB) {
+          const int k = k0 + it;
+          double sr = 0.0;
 #pragma unroll
-      for (int g = 0; g < PPC; ++g) s += (double)cred[c][g];
-      pcol[(int64_t)p * ST + c] = s;
+          for (int g = 0; g < CPT; ++g) sr += (double)rred[it][g][l];
+          racc[k] += sr;
+          if (J == J1 - 1) prow[((int64_t)p0 * NC + k) * ST + l] = racc[k];
+        } else if (J > I) {
+          const int k = k0 + it - KB;
+          double sc = 0.0;
+#pragma unroll
+          for (int g = 0; g < PPC; ++g) sc += (double)cred[it - KB][l][g];
+          pcol[((int64_t)p * NC + k) * ST + l] = sc;
+        }
+      }
     }
   };
   for (int J = J0; J + 1 < J1; ++J) {
@@ -166,31 +203,47 @@ __global__ __launch_bounds__(256) void symv_part_kernel(const GemvDesc* __restri
 }
 
 // Item (g, I, P0, nt): x_g[64 I + l] = sum over the runs of block row I of
-// their row partial + sum_{K < I} pcol(K, I)[l].  The terms, in the order
-// (runs of row I from the diagonal on, then K = 0 .. I - 1), are dealt to
-// the four waves in turn; each wave sums its terms in order and the four
-// sums are added in wave order, so the result is repeatable bit for bit.
+// their row partial + sum_{K < I} pcol(K, I)[l] (with a descriptor output y:
+// y_g[64 I + l] -= that sum instead).  The terms, in the order (runs of row I
+// from the diagonal on, then K = 0 .. I - 1), are dealt to the four waves in
+// turn; each wave sums its terms in order and the four sums are added in
+// wave order, so the result is repeatable bit for bit.  All NC vectors are
+// summed in the same pass (their loads in flight together).
+template <int NC>
 __global__ __launch_bounds__(256) void symv_sum_kernel(const GemvDesc* __restrict__ desc,
                                                        const int4* __restrict__ items,
                                                        const double* __restrict__ prow,
                                                        const double* __restrict__ pcol, const int32_t* __restrict__ want) {
-  __shared__ double red[4][ST];
+  static_assert(NC <= 4, "one wave per vector for the last step");
+  __shared__ double red[4][NC][ST];
   const int4 item = items[blockIdx.x];
   const int g = item.x, I = item.y, P0 = item.z, nt = item.w;
   if (want && !want[g]) return;  // uniform over the work-group
   const int l = threadIdx.x % ST, w = threadIdx.x / ST;
   const int na = (nt - I + SYMV_RUN - 1) / SYMV_RUN;  // runs of row I
-  double s = 0.0;
+  double s[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) s[k] = 0.0;
   for (int q = w; q < na + I; q += 4) {
     const int64_t slot = q < na ? P0 + tile_index(I, I + SYMV_RUN * q, nt) : P0 + tile_index(q - na, I, nt);
-    s += (q < na ? prow : pcol)[slot * ST + l];
+    const double* src = (q < na ? prow : pcol) + slot * NC * ST + l;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) s[k] += src[k * ST];
   }
-  red[w][l] = s;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) red[w][k][l] = s[k];
   __syncthreads();
-  if (w == 0) {
-    const double x = ((red[0][l] + red[1][l]) + red[2][l]) + red[3][l];
+  if (w < NC) {  // wave k finishes vector k
+    const double x = ((red[0][w][l] + red[1][w][l]) + red[2][w][l]) + red[3][w][l];
+    const GemvDesc& d = desc[g];
     const int r = ST * I + l;
-    if (r < desc[g].n) desc[g].x[r] = x;
+    if (r < d.n) {
+      const int64_t e = (int64_t)w * d.vs + r;
+      if (d.y)
+        d.y[e] -= x;
+      else
+        d.x[e] = x;
+    }
   }
 }
 
@@ -220,19 +273,14 @@ __global__ __launch_bounds__(256) void pack_upper_kernel(const double* __restric
   }
 }
 
-template <typename T>
+template <typename T, int NC>
 void symv_launch(const GemvDesc* desc, const FactorSet::GemvPlan& G, double* partial, int64_t partial_len,
                  hipStream_t st, const int32_t* want, KernelTimer* tm, double bytes) {
   if (G.n1 == 0) return;
   double* prow = partial;
   double* pcol = partial + partial_len / 2;
-  if (tm) GDSW_HIP(hipEventRecord(tm->ev[2 * tm->used], st));
-  symv_part_kernel<T><<<G.n1, 256, 0, st>>>(desc, G.d_items1, prow, pcol, want);
-  if (tm) {
-    GDSW_HIP(hipEventRecord(tm->ev[2 * tm->used++ + 1], st));
-    tm->bytes += bytes;
-  }
-  symv_sum_kernel<<<G.n2, 256, 0, st>>>(desc, G.d_items2, prow, pcol, want);
+  timed_launch(tm, bytes, symv_part_kernel<T, NC>, dim3(G.n1), dim3(256), st, desc, G.d_items1, prow, pcol, want);
+  symv_sum_kernel<NC><<<G.n2, 256, 0, st>>>(desc, G.d_items2, prow, pcol, want);
 }
 
 }  // namespace
@@ -265,14 +313,24 @@ void pack_upper(int prec, const double* src, const int64_t* soff, const int32_t*
 }
 
 void symv_desc_launch(int prec, const GemvDesc* desc, const FactorSet::GemvPlan& G, double* partial,
-                      int64_t partial_len, hipStream_t st, const int32_t* want, KernelTimer* tm, double bytes) {
+                      int64_t partial_len, hipStream_t st, const int32_t* want, KernelTimer* tm, double bytes,
+                      int nc) {
   if (tm && (!tm->on || tm->used >= KernelTimer::CAP)) tm = nullptr;
-  if (prec == P_FP64)
-    symv_launch<double>(desc, G, partial, partial_len, st, want, tm, bytes);
-  else if (prec == P_FP32)
-    symv_launch<float>(desc, G, partial, partial_len, st, want, tm, bytes);
-  else
-    symv_launch<uint16_t>(desc, G, partial, partial_len, st, want, tm, bytes);
+  if (nc != 1 && nc != 3) throw StatusError{1, "symmetric products take 1 or 3 vectors"};
+  if (nc == 3) {
+    if (prec == P_FP64)
+      symv_launch<double, 3>(desc, G, partial, partial_len, st, want, tm, bytes);
+    else if (prec == P_FP32)
+      symv_launch<float, 3>(desc, G, partial, partial_len, st, want, tm, bytes);
+    else
+      symv_launch<uint16_t, 3>(desc, G, partial, partial_len, st, want, tm, bytes);
+  } else if (prec == P_FP64) {
+    symv_launch<double, 1>(desc, G, partial, partial_len, st, want, tm, bytes);
+  } else if (prec == P_FP32) {
+    symv_launch<float, 1>(desc, G, partial, partial_len, st, want, tm, bytes);
+  } else {
+    symv_launch<uint16_t, 1>(desc, G, partial, partial_len, st, want, tm, bytes);
+  }
   GDSW_HIP(hipGetLastError());
 }
 
@@ -281,7 +339,7 @@ void symv_set(const FactorSet& fs, double* w, hipStream_t st, int slot, const in
   if (fs.count == 0 || slot >= (int)fs.gemv.size()) return;
   if (!fs.d_desc) throw StatusError{5, "symmetric set used before its descriptors were built"};
   symv_desc_launch(fs.prec, fs.d_desc, fs.gemv[slot], fs.d_partial, fs.partial_len, st, want,
-                   slot == 0 ? fs.timer : nullptr, (double)fs.alg_bytes);
+                   slot == 0 ? fs.timer : nullptr, (double)fs.alg_bytes, fs.nc);
 }
 
 }  // namespace gdsw

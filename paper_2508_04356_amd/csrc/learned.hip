@@ -43,6 +43,7 @@ void learned_init(Context& ctx, uint64_t seed, hipStream_t st) {
   Problem& P = ctx.P;
   const int m = P.spec.m;
   if (P.algebraic) throw StatusError{6, "the learned local solve needs the structured cube's node grids"};
+  if (ctx.solve_mode == SOLVE_BLOCK) throw StatusError{6, "the learned local solve takes dense local inverses"};
   if (m < 3) throw StatusError{6, "the learned local solve needs interior subdomains (m >= 3)"};
   if (P.spec.pressure != 0) throw StatusError{6, "the learned local solve is built for the Q1 pressure"};
   auto L = new LearnedSolve();

@@ -2,6 +2,8 @@
 // coarse basis Phi (eq. 2.4), A_0 = Phi^T A Phi (eq. 2.3) and its factors.
 #include <hip/hip_runtime.h>
 
+#include <tuple>
+
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -188,7 +190,7 @@ void plan_schedule(FactorSet& fs, int phases, DeviceArena& A, hipStream_t st, in
     G.n2 = (int)it2.size();
     G.d_items1 = it1.empty() ? nullptr : dupload(A, it1, st);
     G.d_items2 = it2.empty() ? nullptr : dupload(A, it2, st);
-    const int64_t need = 2 * (fs.total_elems / 64);  // 64 row and 64 column partials per tile
+    const int64_t need = 2 * fs.nc * (fs.total_elems / 64);  // 64 row and 64 column partials per tile and vector
     if (need > fs.partial_len) {
       if (fs.d_partial) A.free(fs.d_partial);
       fs.d_partial = dalloc<double>(A, std::max<int64_t>(need, 2));
@@ -309,9 +311,9 @@ int64_t staging_offset(const FactorSet& fs, int f0, int f) {
   return o;
 }
 
-template <class Fill>
+template <class Fill, class Post>
 void factor_set(Context& ctx, FactorSet& fs, uint64_t staging_cap, double pivot_tol, const std::string& what,
-                hipStream_t st, Fill&& fill) {
+                hipStream_t st, Fill&& fill, Post&& post) {
   DeviceArena& A = ctx.arena;
   const size_t es = elem_size(fs.prec);
   fs.store = A.alloc((uint64_t)fs.total_elems * es);
@@ -376,6 +378,7 @@ void factor_set(Context& ctx, FactorSet& fs, uint64_t staging_cap, double pivot_
       gj_invert(B, Pbuf, Tbuf, tstride, mp, st);
       check_pivots(mp, cnt, pivot_tol, what, st);
       symmetrize(B, st);
+      post(B, f0, f1);  // the FP64 inverses of the chunk, before they are stored
       if (fs.mode == SOLVE_SYM) {
         // full staging matrices -> upper tiles of the store (chunk-relative offsets)
         std::vector<int64_t> doff_t(cnt);
@@ -428,6 +431,39 @@ void factor_set(Context& ctx, FactorSet& fs, uint64_t staging_cap, double pivot_
   }
 }
 
+template <class Fill>
+void factor_set(Context& ctx, FactorSet& fs, uint64_t staging_cap, double pivot_tol, const std::string& what,
+                hipStream_t st, Fill&& fill) {
+  factor_set(ctx, fs, staging_cap, pivot_tol, what, st, fill, [](DenseBatch&, int, int) {});
+}
+
+// Block local solve: the velocity block must be I_3 (x) L -- velocity DOFs
+// numbered 3 node + component, every velocity row coupling only to its own
+// component with the values of the x-component row of the same node.
+void block_check(const Problem& P) {
+  for (int64_t d = 0; d < P.n_u; ++d)
+    if (P.field[d] != d % 3)
+      throw StatusError{1, "the block local solve needs velocity DOFs numbered 3 node + component"};
+  for (int64_t r = 0; r < P.n_u; r += 3) {
+    const int32_t b0 = P.row_ptr[r], e0 = P.row_ptr[r + 1];
+    for (int c = 1; c < 3; ++c) {
+      const int32_t b = P.row_ptr[r + c], e = P.row_ptr[r + c + 1];
+      int32_t i = b0, j = b;
+      while (i < e0 && P.col[i] < P.n_u) {
+        if (j >= e || P.col[j] != P.col[i] + c || P.val[j] != P.val[i])
+          throw StatusError{1, "the block local solve needs a velocity block I_3 (x) L (row " +
+                                   std::to_string(r + c) + " differs from row " + std::to_string(r) + ")"};
+        ++i;
+        ++j;
+      }
+      if (j < e && P.col[j] < P.n_u)
+        throw StatusError{1, "the block local solve needs a velocity block I_3 (x) L"};
+    }
+    for (int32_t i = b0; i < e0 && P.col[i] < P.n_u; ++i)
+      if (P.col[i] % 3 != 0) throw StatusError{1, "the block local solve needs uncoupled velocity components"};
+  }
+}
+
 template <class T>
 void concat(const std::vector<std::vector<T>>& lists, std::vector<int32_t>& ptr, std::vector<T>& idx) {
   ptr.assign(lists.size() + 1, 0);
@@ -449,11 +485,40 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
   ctx.Nc = P.n_coarse;
   const int Nc = ctx.Nc;
 
+  const bool blockm = ctx.solve_mode == SOLVE_BLOCK;
+  // block local solve: x-component DOFs (one per local velocity node) and
+  // pressure DOFs of every overlapping set
+  std::vector<std::vector<int32_t>> bvx(blockm ? P.n_sub : 0), bpr(blockm ? P.n_sub : 0);
+  if (blockm) {
+    block_check(P);
+    for (int i = 0; i < P.n_sub; ++i) {
+      const auto& S = P.S[i];
+      for (size_t k = 0; k < S.size(); ++k) {
+        const int32_t d = S[k];
+        if (P.field[d] == 3) {
+          bpr[i].push_back(d);
+        } else if (P.field[d] == 0) {
+          if (k + 2 >= S.size() || S[k + 1] != d + 1 || S[k + 2] != d + 2)
+            throw StatusError{1, "the block local solve needs all three velocity components of a node in a set"};
+          bvx[i].push_back(d);
+        }
+      }
+      if (3 * bvx[i].size() + bpr[i].size() != S.size())
+        throw StatusError{1, "the block local solve needs all three velocity components of a node in a set"};
+    }
+  }
+
   // ---- budget pre-check (dominant terms) --------------------------------
   {
     uint64_t need = 0;
     const size_t es = elem_size(ctx.local_prec);
     for (int i = 0; i < P.n_sub; ++i) {
+      if (blockm) {
+        const uint64_t nv = round_up(std::max<int64_t>(1, (int64_t)bvx[i].size()), 64);
+        const uint64_t np = round_up(std::max<int64_t>(1, (int64_t)bpr[i].size()), 64);
+        need += (nv * nv * es + np * np * 8) / 2 + 2 * 3 * nv * np * 8 / 4;
+        continue;
+      }
       const uint64_t np = std::max<int64_t>(nb, round_up((int64_t)P.S[i].size(), nb));
       need += np * np * es + np * nb * (ctx.local_prec == P_FP64 ? 8 : 4);
     }
@@ -476,12 +541,57 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
   for (double v : P.val) amax = std::max(amax, std::fabs(v));
 
   // ---- factor sets and work vector layout ---------------------------------
-  std::vector<int32_t> l1_sizes(P.n_sub);
-  for (int i = 0; i < P.n_sub; ++i) l1_sizes[i] = (int32_t)P.S[i].size();
-  ctx.merged = (levels == 2 && ctx.local_prec == P_FP64 && Nc > 0);
-  if (ctx.merged) l1_sizes.push_back(Nc);
-  plan_factor_set(ctx.L1, l1_sizes, ctx.local_prec, nb, 0, ctx.solve_mode, A, st);
-  ctx.n_w1 = ctx.L1.total_x;
+  // level-1 work positions of every overlapping set's DOFs (P.S order)
+  std::vector<std::vector<int64_t>> lpos(P.n_sub);
+  if (blockm) {
+    // L1: L_i^-1 (three component vectors each), LP: S_i^-1 and, with two
+    // levels, the coarse inverse; per subdomain [x | y | z | p] segments
+    std::vector<int32_t> nv(P.n_sub), npr(P.n_sub);
+    for (int i = 0; i < P.n_sub; ++i) {
+      nv[i] = (int32_t)bvx[i].size();
+      npr[i] = (int32_t)bpr[i].size();
+    }
+    if (levels == 2 && Nc > 0) npr.push_back(Nc);
+    ctx.L1.nc = 3;
+    plan_factor_set(ctx.L1, nv, ctx.local_prec, 64, 0, SOLVE_SYM, A, st);
+    plan_factor_set(ctx.LP, npr, P_FP64, 64, 0, SOLVE_SYM, A, st);
+    int64_t cur = 0;
+    for (int i = 0; i < P.n_sub; ++i) {
+      ctx.L1.xoff[i] = cur;
+      cur += 3 * (int64_t)ctx.L1.npad[i];
+      ctx.LP.xoff[i] = cur;
+      cur += ctx.LP.npad[i];
+    }
+    if ((int)npr.size() > P.n_sub) {
+      ctx.LP.xoff[P.n_sub] = cur;
+      cur += ctx.LP.npad[P.n_sub];
+    }
+    ctx.n_w1 = cur;
+    GDSW_HIP(hipMemcpyAsync(ctx.L1.d_xoff, ctx.L1.xoff.data(), ctx.L1.count * sizeof(int64_t),
+                            hipMemcpyHostToDevice, st));
+    GDSW_HIP(hipMemcpyAsync(ctx.LP.d_xoff, ctx.LP.xoff.data(), ctx.LP.count * sizeof(int64_t),
+                            hipMemcpyHostToDevice, st));
+    ctx.merged = false;
+    for (int i = 0; i < P.n_sub; ++i) {
+      const int64_t vb = ctx.L1.xoff[i], npv = ctx.L1.npad[i], pb = ctx.LP.xoff[i];
+      int64_t a = 0, q = 0;
+      for (int32_t d : P.S[i]) {
+        if (P.field[d] == 3)
+          lpos[i].push_back(pb + q++);
+        else
+          lpos[i].push_back(vb + (int64_t)P.field[d] * npv + (P.field[d] == 2 ? a++ : a));
+      }
+    }
+  } else {
+    std::vector<int32_t> l1_sizes(P.n_sub);
+    for (int i = 0; i < P.n_sub; ++i) l1_sizes[i] = (int32_t)P.S[i].size();
+    ctx.merged = (levels == 2 && ctx.local_prec == P_FP64 && Nc > 0);
+    if (ctx.merged) l1_sizes.push_back(Nc);
+    plan_factor_set(ctx.L1, l1_sizes, ctx.local_prec, nb, 0, ctx.solve_mode, A, st);
+    ctx.n_w1 = ctx.L1.total_x;
+    for (int i = 0; i < P.n_sub; ++i)
+      for (size_t k = 0; k < P.S[i].size(); ++k) lpos[i].push_back(ctx.L1.xoff[i] + (int64_t)k);
+  }
   std::vector<int32_t> hi_sizes;
   const Level2& L2 = P.lv2;
   // level-2 index sets in factor order: velocity-type coarse DOFs first
@@ -494,7 +604,7 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
       if (P.coarse_field[c] == 3) o.push_back(c);
     return o;
   };
-  if (levels == 2 && !ctx.merged && Nc > 0) hi_sizes.push_back(Nc);
+  if (levels == 2 && !ctx.merged && !blockm && Nc > 0) hi_sizes.push_back(Nc);
   if (levels == 3) {
     ctx.n_sub2 = L2.n_sub;
     ctx.Nc3 = L2.n_coarse3;
@@ -505,7 +615,7 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
     }
     if (ctx.Nc3 > 0) hi_sizes.push_back(ctx.Nc3);
   }
-  plan_factor_set(ctx.HI, hi_sizes, P_FP64, nb, ctx.n_w1, ctx.solve_mode, A, st);
+  plan_factor_set(ctx.HI, hi_sizes, P_FP64, nb, ctx.n_w1, blockm ? SOLVE_SYM : ctx.solve_mode, A, st);
   ctx.n_w = ctx.n_w1 + ctx.HI.total_x;
   ctx.d_w = dalloc<double>(A, std::max<int64_t>(ctx.n_w, 1));
   GDSW_HIP(hipMemsetAsync(ctx.d_w, 0, std::max<int64_t>(ctx.n_w, 1) * 8, st));
@@ -515,9 +625,8 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
     std::vector<int32_t> gidx(ctx.n_w1, -1);
     std::vector<int32_t> cnt(n + 1, 0);
     for (int i = 0; i < P.n_sub; ++i) {
-      const int64_t xo = ctx.L1.xoff[i];
       for (size_t k = 0; k < P.S[i].size(); ++k) {
-        gidx[xo + k] = P.S[i][k];
+        gidx[lpos[i][k]] = P.S[i][k];
         cnt[P.S[i][k] + 1]++;
       }
     }
@@ -526,10 +635,9 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
     std::vector<int64_t> inv_pos(inv_ptr[n]);
     std::vector<int32_t> fill(n, 0);
     for (int i = 0; i < P.n_sub; ++i) {  // ascending i: fixed summation order
-      const int64_t xo = ctx.L1.xoff[i];
       for (size_t k = 0; k < P.S[i].size(); ++k) {
         const int32_t d = P.S[i][k];
-        inv_pos[inv_ptr[d] + fill[d]++] = xo + (int64_t)k;
+        inv_pos[inv_ptr[d] + fill[d]++] = lpos[i][k];
       }
     }
     ctx.d_gidx = dupload(A, gidx, st);
@@ -878,6 +986,133 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
   int32_t* d_S_idx = dupload(A, S_idx, st);
   int32_t* d_perm = ctx.coarse_perm.empty() ? nullptr : dupload(A, ctx.coarse_perm, st);
   const uint64_t staging_cap = std::max<uint64_t>(1ull << 30, std::min<uint64_t>(32ull << 30, budget / 4));
+  if (blockm) {
+    // L_i^-1 by Gauss-Jordan; from each chunk's FP64 inverses, before they are
+    // stored, S_i = B_i K_i^-1 B_i^T = Bt^T (L^-1 Bt) with Bt the velocity
+    // columns of B_i^T in component-major blocks (3 npad_v x np_i)
+    std::vector<int32_t> vx_ptr, vx_idx, pr_ptr, pr_idx;
+    concat(bvx, vx_ptr, vx_idx);
+    concat(bpr, pr_ptr, pr_idx);
+    int32_t* d_vx_ptr = dupload(A, vx_ptr, st);
+    int32_t* d_vx = dupload(A, vx_idx, st);
+    int32_t* d_pr_ptr = dupload(A, pr_ptr, st);
+    int32_t* d_pr = dupload(A, pr_idx, st);
+    std::vector<int64_t> soff(P.n_sub + 1, 0);
+    for (int i = 0; i < P.n_sub; ++i) soff[i + 1] = soff[i] + (int64_t)bpr[i].size() * bpr[i].size();
+    double* Sbuf = dalloc<double>(A, std::max<int64_t>(soff.back(), 1));
+    int64_t* d_soff = dupload(A, soff, st);
+    factor_set(
+        ctx, ctx.L1, staging_cap, 1e-14 * amax, "velocity block", st,
+        [&](DenseBatch& B, int f0, int f1) {
+          int mx = 0;
+          for (int f = f0; f < f1; ++f) mx = std::max(mx, (int)bvx[f].size());
+          extract_local(B, d_vx_ptr + f0, d_vx, ctx.d_rowptr, ctx.d_col, ctx.d_val, mx, st);
+        },
+        [&](DenseBatch& B, int f0, int f1) {
+          const int cnt = f1 - f0;
+          std::vector<int64_t> boff(cnt + 1, 0);
+          std::vector<int32_t> npv(cnt);
+          int max_np = 0, max_nv = 0;
+          for (int k = 0; k < cnt; ++k) {
+            npv[k] = ctx.L1.npad[f0 + k];
+            boff[k + 1] = boff[k] + 3 * (int64_t)npv[k] * bpr[f0 + k].size();
+            max_np = std::max(max_np, (int)bpr[f0 + k].size());
+            max_nv = std::max(max_nv, (int)bvx[f0 + k].size());
+          }
+          if (boff.back() == 0) return;
+          double* Bt = dalloc<double>(A, boff.back());
+          double* W = dalloc<double>(A, boff.back());
+          GDSW_HIP(hipMemsetAsync(Bt, 0, boff.back() * 8, st));
+          GDSW_HIP(hipMemsetAsync(W, 0, boff.back() * 8, st));
+          int32_t* d_npv = dupload(A, std::vector<int32_t>(ctx.L1.npad.begin(), ctx.L1.npad.end()), st);
+          int64_t* d_boff = dupload(A, boff, st);
+          block_fill_bt(ctx.d_rowptr, ctx.d_col, ctx.d_val, P.n_u, d_vx_ptr, d_vx, d_pr_ptr, d_pr, d_npv, d_boff, f0,
+                        cnt, max_np, Bt, st);
+          // staging offsets of the chunk's inverses (full npad x npad matrices)
+          std::vector<GemmDesc> g1, g2;
+          int64_t so = 0;
+          for (int k = 0; k < cnt; ++k) {
+            const int f = f0 + k, nvf = (int)bvx[f].size(), npf = (int)bpr[f].size(), ld = npv[k];
+            if (npf > 0 && nvf > 0) {
+              g1.push_back(GemmDesc{B.base + so, Bt + boff[k], W + boff[k], nvf, 3 * npf, nvf, ld, ld, ld, 0, 0});
+              g2.push_back(GemmDesc{Bt + boff[k], W + boff[k], Sbuf + soff[f], npf, npf, 3 * ld, 3 * ld, 3 * ld, npf,
+                                    1, 0});
+            }
+            so += (int64_t)ld * ld;
+          }
+          GemmDesc* d_g1 = dupload(A, g1, st);
+          GemmDesc* d_g2 = dupload(A, g2, st);
+          gemm_batched(d_g1, (int)g1.size(), max_nv, 3 * max_np, 1.0, 0.0, st);
+          gemm_batched(d_g2, (int)g2.size(), max_np, max_np, 1.0, 0.0, st);
+          GDSW_HIP(hipStreamSynchronize(st));
+          for (void* q : {(void*)Bt, (void*)W, (void*)d_npv, (void*)d_boff, (void*)d_g1, (void*)d_g2}) A.free(q);
+        });
+    int32_t* d_perm_b = ctx.coarse_perm.empty() ? nullptr : dupload(A, ctx.coarse_perm, st);
+    factor_set(ctx, ctx.LP, staging_cap, 0.0, "pressure Schur complement", st, [&](DenseBatch& B, int f0, int f1) {
+      const int nloc = std::min(f1, P.n_sub) - f0;
+      int64_t mx = 0;
+      for (int f = f0; f < f0 + nloc; ++f) mx = std::max<int64_t>(mx, (int64_t)bpr[f].size() * bpr[f].size());
+      copy_blocks(Sbuf, d_soff + f0, B.n, nloc, mx, B.base, B.off, B.ld, st);
+      if (f1 == ctx.LP.count && ctx.LP.count > P.n_sub) {
+        double* dst = B.base + staging_offset(ctx.LP, f0, ctx.LP.count - 1);
+        permute_dense(Nc, d_perm_b, ctx.d_A0, Nc, dst, ctx.LP.npad[ctx.LP.count - 1], st);
+      }
+    });
+    GDSW_HIP(hipStreamSynchronize(st));
+    for (void* q : {(void*)d_vx_ptr, (void*)d_vx, (void*)d_pr_ptr, (void*)d_pr, (void*)Sbuf, (void*)d_soff})
+      A.free(q);
+    if (d_perm_b) A.free(d_perm_b);
+    // B_i as row lists over work positions: pressure rows (velocity positions)
+    // and velocity rows (pressure positions), each subdomain in order
+    BlockSolve& b = ctx.blk;
+    std::vector<int32_t> prow_pos, bm_pos, vrow_pos, bt_pos;
+    std::vector<int64_t> bm_ptr(1, 0), bt_ptr(1, 0);
+    std::vector<double> bm_val, bt_val;
+    for (int i = 0; i < P.n_sub; ++i) {
+      const int64_t vb = ctx.L1.xoff[i], npv = ctx.L1.npad[i], pb = ctx.LP.xoff[i];
+      const auto& vx = bvx[i];
+      std::vector<std::tuple<int64_t, int64_t, double>> tr;  // (velocity position, pressure position, value)
+      for (size_t q = 0; q < bpr[i].size(); ++q) {
+        const int32_t g = bpr[i][q];
+        prow_pos.push_back((int32_t)(pb + (int64_t)q));
+        for (int32_t e = P.row_ptr[g]; e < P.row_ptr[g + 1]; ++e) {
+          const int32_t c = P.col[e];
+          if (c >= P.n_u) continue;
+          const int comp = c % 3;
+          const auto it = std::lower_bound(vx.begin(), vx.end(), c - comp);
+          if (it == vx.end() || *it != c - comp) continue;
+          const int64_t vp = vb + comp * npv + (it - vx.begin());
+          bm_pos.push_back((int32_t)vp);
+          bm_val.push_back(P.val[e]);
+          tr.emplace_back(vp, pb + (int64_t)q, P.val[e]);
+        }
+        bm_ptr.push_back((int64_t)bm_pos.size());
+      }
+      std::sort(tr.begin(), tr.end());
+      for (size_t k = 0; k < tr.size(); ++k) {
+        if (k == 0 || std::get<0>(tr[k]) != std::get<0>(tr[k - 1])) {
+          if (k > 0) bt_ptr.push_back((int64_t)bt_pos.size());
+          vrow_pos.push_back((int32_t)std::get<0>(tr[k]));
+        }
+        bt_pos.push_back((int32_t)std::get<1>(tr[k]));
+        bt_val.push_back(std::get<2>(tr[k]));
+      }
+      if (!tr.empty()) bt_ptr.push_back((int64_t)bt_pos.size());
+    }
+    b.n_prow = (int64_t)prow_pos.size();
+    b.n_vrow = (int64_t)vrow_pos.size();
+    b.d_prow_pos = dupload(A, prow_pos, st);
+    b.d_bm_ptr = dupload(A, bm_ptr, st);
+    b.d_bm_pos = dupload(A, bm_pos, st);
+    b.d_bm_val = dupload(A, bm_val, st);
+    b.d_vrow_pos = dupload(A, vrow_pos, st);
+    b.d_bt_ptr = dupload(A, bt_ptr, st);
+    b.d_bt_pos = dupload(A, bt_pos, st);
+    b.d_bt_val = dupload(A, bt_val, st);
+    b.b_bytes = (uint64_t)(bm_pos.size() + bt_pos.size()) * 12 + (uint64_t)(prow_pos.size() + vrow_pos.size()) * 12;
+    b.d_w2 = dalloc<double>(A, std::max<int64_t>(ctx.n_w1, 1));
+    GDSW_HIP(hipMemsetAsync(b.d_w2, 0, std::max<int64_t>(ctx.n_w1, 1) * 8, st));
+  } else
   factor_set(ctx, ctx.L1, staging_cap, 1e-14 * amax, "local factor", st,
              [&](DenseBatch& B, int f0, int f1) {
                const int nloc = std::min(f1, P.n_sub) - f0;
@@ -896,7 +1131,7 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
                  (void)fc;
                }
              });
-  if (!ctx.merged && ctx.HI.count > 0 && levels == 2) {
+  if (!ctx.merged && !blockm && ctx.HI.count > 0 && levels == 2) {
     factor_set(ctx, ctx.HI, staging_cap, 0.0, "coarse factor", st, [&](DenseBatch& B, int, int) {
       permute_dense(Nc, d_perm, ctx.d_A0, Nc, B.base, ctx.HI.npad[0], st);
     });
@@ -930,8 +1165,8 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
   A.free(d_S_idx);
   // coarse column -> work-vector position (two levels)
   if (Nc > 0 && levels == 2) {
-    const FactorSet& cs = ctx.merged ? ctx.L1 : ctx.HI;
-    const int fc = ctx.merged ? ctx.L1.count - 1 : 0;
+    const FactorSet& cs = blockm ? ctx.LP : ctx.merged ? ctx.L1 : ctx.HI;
+    const int fc = blockm ? ctx.LP.count - 1 : ctx.merged ? ctx.L1.count - 1 : 0;
     ctx.coarse_xoff = cs.xoff[fc];
     std::vector<int32_t> pinv(Nc);
     for (int q = 0; q < Nc; ++q) pinv[ctx.coarse_perm[q]] = (int32_t)(ctx.coarse_xoff + q);
@@ -940,14 +1175,28 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
   if (d_perm) A.free(d_perm);
   ctx.factor_bytes = 0;
   for (int f = 0; f < P.n_sub; ++f)
-    ctx.factor_bytes += (ctx.solve_mode == SOLVE_SYM ? (uint64_t)symv_tiles(ctx.L1.npad[f]) * 64 * 64
-                                                     : (uint64_t)ctx.L1.npad[f] * ctx.L1.npad[f]) *
-                        elem_size(ctx.local_prec);
+    ctx.factor_bytes += (ctx.solve_mode == SOLVE_SYM || blockm ? (uint64_t)symv_tiles(ctx.L1.npad[f]) * 64 * 64
+                                                               : (uint64_t)ctx.L1.npad[f] * ctx.L1.npad[f]) *
+                            elem_size(ctx.local_prec) +
+                        (blockm ? (uint64_t)symv_tiles(ctx.LP.npad[f]) * 64 * 64 * 8 : 0);
   ctx.coarse_bytes = (uint64_t)Nc * Nc * 8 * 2 + (uint64_t)phi_off.back() * 16;
   // descriptors of the stored inverses against the work vector
-  for (FactorSet* fs : {&ctx.L1, &ctx.HI})
-    if ((fs->mode == SOLVE_INVERSE || fs->mode == SOLVE_SYM) && fs->count > 0)
-      fs->d_desc = dupload(A, gemv_descs(*fs, ctx.d_w), st);
+  for (FactorSet* fs : {&ctx.L1, &ctx.HI, &ctx.LP})
+    if ((fs->mode == SOLVE_INVERSE || fs->mode == SOLVE_SYM) && fs->count > 0) {
+      std::vector<GemvDesc> d = gemv_descs(*fs, ctx.d_w);
+      if (fs->nc > 1)
+        for (int f = 0; f < fs->count; ++f) d[f].vs = fs->npad[f];
+      fs->d_desc = dupload(A, d, st);
+      if (blockm && fs == &ctx.L1) {
+        // L^-1 (B^T p), read from d_w2 and subtracted from U1 in the work vector
+        std::vector<GemvDesc> d2 = gemv_descs(*fs, ctx.blk.d_w2);
+        for (int f = 0; f < fs->count; ++f) {
+          d2[f].vs = fs->npad[f];
+          d2[f].y = ctx.d_w + fs->xoff[f];
+        }
+        ctx.blk.d_desc2 = dupload(A, d2, st);
+      }
+    }
   // several right-hand sides: MFMA work plans and interleaved work buffers
   if (ctx.max_rhs > 1 && ctx.solve_mode == SOLVE_INVERSE) {
     plan_gemm(ctx.L1, A, st);

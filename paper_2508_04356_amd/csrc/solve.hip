@@ -202,6 +202,8 @@ void ensure_workspace(Context& ctx, int restart) {
   ctx.d_t1 = dalloc<double>(A, ctx.ldv);
   ctx.d_t2 = dalloc<double>(A, ctx.ldv);
   if (!ctx.h_pinned) GDSW_HIP(hipHostMalloc((void**)&ctx.h_pinned, 16 * sizeof(double), hipHostMallocDefault));
+  for (hipEvent_t& e : ctx.it_ev)
+    if (!e) GDSW_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 }
 
 double read_scalar(Context& ctx, int idx, hipStream_t st) {
@@ -265,6 +267,8 @@ void apply_precond(Context& ctx, const double* r, double* z, hipStream_t st, hip
       learned_apply_interior(ctx, st);
     else
       zero_segments(gm, L->S, ctx.d_w, st);
+  } else if (ctx.solve_mode == SOLVE_BLOCK) {
+    block_local_solve(ctx, st);
   } else {
     local_solve_set(ctx.L1, ctx.d_w, st);
   }
@@ -355,7 +359,27 @@ FgmresResult fgmres(Context& ctx, const double* b, double* x, double rtol, int r
     sub_dots(V, ldv, j + 1, ctx.d_hv + restart + 1, w, n, ctx.d_part, nb, nullptr, true, st);
     arnoldi_step(j, restart, ctx.d_hv, ctx.d_hv + restart + 1, ctx.d_H, ctx.d_cs, ctx.d_sn, ctx.d_g, S, ctx.d_part,
                  nb, n, w, V + (int64_t)(j + 1) * ldv, st);
-    GDSW_HIP(hipMemcpyAsync(ctx.h_pinned, S + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    GDSW_HIP(hipMemcpyAsync(ctx.h_pinned + 10 + 2 * (j & 1), S + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  };
+  auto launch = [&](int j) {
+    if (graph) {
+      hipGraphExec_t& e = ctx.graphs.exec[j];
+      if (!e) {
+        KernelTimer* tm = ctx.L1.timer;
+        ctx.L1.timer = nullptr;  // no event nodes in the graph
+        hipGraph_t g = nullptr;
+        GDSW_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        body(j);
+        GDSW_HIP(hipStreamEndCapture(st, &g));
+        ctx.L1.timer = tm;
+        GDSW_HIP(hipGraphInstantiate(&e, g, nullptr, nullptr, 0));
+        GDSW_HIP(hipGraphDestroy(g));
+      }
+      GDSW_HIP(hipGraphLaunch(e, st));
+    } else {
+      body(j);
+    }
+    GDSW_HIP(hipEventRecord(ctx.it_ev[j & 1], st));
   };
   int it = 0;
   int cycles = 0;
@@ -373,28 +397,22 @@ FgmresResult fgmres(Context& ctx, const double* b, double* x, double rtol, int r
     }
     if (it >= max_it) break;
     scale_div_kernel<<<grid_n(n), 256, 0, st>>>(n, ctx.d_t1, S, 1, V);
+    // Iteration j + 1 is enqueued before the host waits for iteration j, so
+    // the GPU does not idle while the host reads the estimate and launches
+    // the next iteration.  If iteration j ends the cycle, iteration j + 1 has
+    // run for nothing: it writes only column j + 1 of H, g[j + 1], g[j + 2],
+    // rotation j + 1, V_{j+2} and Z_{j+1}, none of which the update with
+    // j + 1 columns below reads, and the next cycle starts afresh.  Each
+    // iteration copies its estimate to its own pinned slot (j % 2).
     int k = 0;
+    bool queued = false;  // iteration j already enqueued
     for (int j = 0; j < restart; ++j) {
-      if (graph) {
-        hipGraphExec_t& e = ctx.graphs.exec[j];
-        if (!e) {
-          KernelTimer* tm = ctx.L1.timer;
-          ctx.L1.timer = nullptr;  // no event nodes in the graph
-          hipGraph_t g = nullptr;
-          GDSW_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-          body(j);
-          GDSW_HIP(hipStreamEndCapture(st, &g));
-          ctx.L1.timer = tm;
-          GDSW_HIP(hipGraphInstantiate(&e, g, nullptr, nullptr, 0));
-          GDSW_HIP(hipGraphDestroy(g));
-        }
-        GDSW_HIP(hipGraphLaunch(e, st));
-      } else {
-        body(j);
-      }
-      GDSW_HIP(hipStreamSynchronize(st));
-      const double rel = ctx.h_pinned[0];
-      const double hn = ctx.h_pinned[1];
+      if (!queued) launch(j);
+      queued = j + 1 < restart && it + 1 < max_it;
+      if (queued) launch(j + 1);
+      GDSW_HIP(hipEventSynchronize(ctx.it_ev[j & 1]));
+      const double rel = ctx.h_pinned[10 + 2 * (j & 1)];
+      const double hn = ctx.h_pinned[11 + 2 * (j & 1)];
       if (history && it < history_len) history[it] = rel;
       ++it;
       k = j + 1;

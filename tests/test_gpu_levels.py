@@ -79,7 +79,7 @@ def test_three_level_triangular_mode_matches_inverse_mode():
     M = ThreeLevelGDSW(p.A, Decomposition(p, m, 1), g)
     r = random_vector(p.n_free, seed=4)
     zo = M(r)
-    for mode in ("triangular", "inverse", "symmetric"):
+    for mode in ("triangular", "inverse", "symmetric", "block"):
         print(f"[gpu] three-level {mode} n={n} m={m} group={g}", flush=True)
         s = G.Solver(n, m, levels=3, group=g, local_solve=mode)
         z = torch.zeros(p.n_free, dtype=torch.float64, device=DEV)

@@ -47,7 +47,7 @@ def oracle_case(w):
     return _cache[w.name]
 
 
-@pytest.mark.parametrize("solve", ["inverse", "symmetric"])
+@pytest.mark.parametrize("solve", ["inverse", "symmetric", "block"])
 @pytest.mark.parametrize("w", paper_variant_cases(), ids=lambda w: w.name)
 def test_paper_variant_parity(w, solve):
     p, d, M = oracle_case(w)
@@ -106,7 +106,7 @@ def _golden(name):
         return json.load(open(path)), f["x"], f["z"]
 
 
-@pytest.mark.parametrize("solve", ["inverse", "symmetric"])
+@pytest.mark.parametrize("solve", ["inverse", "symmetric", "block"])
 def test_paper_variant_16_cubed_against_stored_oracle(solve):
     """16^3, 4^3 subdomains, Q2/P1disc + GDSW*: apply and solution on every
     free DOF at 1e-10, equal iteration counts."""

@@ -61,7 +61,7 @@ def gpu_case(w, **kw):
                     manufactured=w.manufactured, **kw)
 
 
-@pytest.mark.parametrize("solve", ["inverse", "triangular", "symmetric"])
+@pytest.mark.parametrize("solve", ["inverse", "triangular", "symmetric", "block"])
 @pytest.mark.parametrize("w", small_parity_cases(), ids=lambda w: w.name)
 def test_setup_and_apply_parity(w, solve):
     p, d, M = oracle_case(w)
@@ -106,7 +106,7 @@ def test_tile_sizes_agree(tile):
     s.close()
 
 
-@pytest.mark.parametrize("solve", ["inverse", "symmetric"])
+@pytest.mark.parametrize("solve", ["inverse", "symmetric", "block"])
 @pytest.mark.parametrize("w", small_parity_cases()[:4], ids=lambda w: w.name)
 def test_fgmres_parity(w, solve):
     p, d, M = oracle_case(w)
@@ -239,7 +239,7 @@ def _golden_vectors(name):
         return f["x"], f["z"]
 
 
-@pytest.mark.parametrize("solve", ["inverse", "symmetric", "triangular"])
+@pytest.mark.parametrize("solve", ["inverse", "symmetric", "triangular", "block"])
 @pytest.mark.parametrize("name", ["C1", "C2", "C2alg"])
 def test_workload_against_stored_oracle(name, solve):
     """Full-size workload in every local-solve mode: the apply on every free

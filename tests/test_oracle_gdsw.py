@@ -281,3 +281,37 @@ def test_p1disc_needs_algebraic_overlap():
     e[(p.dof_field[S] == 3) & (p.dof_null[S] == 1)] = 1.0
     assert np.abs(Ai @ e).max() < 1e-12 * np.abs(Ai).max()
     assert d.n_sub == 27 and n == 6
+
+
+@pytest.mark.parametrize("pressure", ["q1", "p1disc"])
+def test_local_matrix_block_structure_and_block_solve(pressure):
+    """The block local solve's premise and identity, on the oracle's own local
+    matrices: the velocity block of A_i is I_3 (x) L_i (components uncoupled,
+    the same scalar matrix for each), and with S = B K^-1 B^T the solution of
+    A_i [u; p] = [f; g] is U1 = L^-1 F, p = S^-1 (B U1 - g), u = U1 - L^-1 B^T p
+    (equal to the direct solve to 1e-12)."""
+    p = StokesProblem(6, pressure=pressure)
+    d = Decomposition(p, 3, 1, local_dirichlet=pressure == "q1")
+    for i in (0, 13):
+        S = d.S[i]
+        Ai = p.A[S][:, S].toarray()
+        fld = p.dof_field[S]
+        vel = np.nonzero(fld < 3)[0]
+        prs = np.nonzero(fld == 3)[0]
+        K = Ai[np.ix_(vel, vel)]
+        L = K[0::3, 0::3]
+        # interleaved numbering 3 node + component; equal up to the assembly's rounding
+        assert np.abs(K - np.kron(L, np.eye(3))).max() <= 1e-14 * np.abs(K).max()
+        B = Ai[np.ix_(prs, vel)]
+        rng = np.random.default_rng(i)
+        f, g = rng.standard_normal(vel.size), rng.standard_normal(prs.size)
+        Li = np.linalg.inv(L)
+        F = f.reshape(-1, 3)                                  # row = node, column = component
+        U1 = Li @ F
+        Sc = B @ np.kron(Li, np.eye(3)) @ B.T
+        pp = np.linalg.solve(Sc, B @ U1.ravel() - g)
+        u = U1.ravel() - (Li @ (B.T @ pp).reshape(-1, 3)).ravel()
+        ref = np.linalg.solve(Ai, np.concatenate([f, g]))
+        got = np.empty_like(ref)
+        got[vel], got[prs] = u, pp
+        assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max()
