@@ -3,8 +3,12 @@
 // saddle-point matrix of eq. (2.1) is symmetric, so only the tiles (I, J)
 // with J >= I are kept (each tile column-major and contiguous), which halves
 // the bytes of the HBM-bound product.  A stored tile with J > I contributes
-// M_IJ x_J to block row I and M_IJ^T x_I to block row J; a diagonal tile
-// (stored whole) contributes M_II x_I.  A work-group reads a run of two
+// M_IJ x_J to block row I and M_IJ^T x_I to block row J; a diagonal tile,
+// stored as its upper triangle U with half the diagonal, contributes
+// U x_I + U^T x_I = M_II x_I.  Pieces that hold no needed entry are not read
+// (rows or columns past n in the last tile row and column, the part of a
+// diagonal tile below the diagonal): the tiles fetched are the upper
+// triangle, not the padded square.  A work-group reads a run of two
 // tiles of one block row (each a contiguous 32 KB read for FP64) and writes
 // one row partial for the run (block row I) and one column partial per
 // off-diagonal tile (block rows J); a second launch sums them per block row
@@ -56,12 +60,11 @@ constexpr int SYMV_RUN = GDSW_SYMV_RUN;
 #endif
 
 template <typename T, typename A>
-__device__ inline void tile_load16(const T* p, A (&o)[VecW<T>::W]) {
-#if GDSW_SYMV_NT
-  load16_nt(p, o);
-#else
-  load16(p, o);
-#endif
+__device__ inline void tile_load16(__amdgpu_buffer_rsrc_t r, uint32_t off, A (&o)[VecW<T>::W]) {
+  if constexpr (sizeof(T) == 2)
+    buf_load16_bf16<GDSW_SYMV_NT != 0>(r, off, o);
+  else
+    buf_load16<GDSW_SYMV_NT != 0>(r, off, o);
 }
 
 // NC > 1: the tile is applied to NC vectors (x + k vs, k < NC) while it sits
@@ -115,8 +118,22 @@ __global__ __launch_bounds__(256) void symv_part_kernel(const GemvDesc* __restri
     xjv[k] = xg[(int64_t)k * d.vs + min(rj, d.np - 1)];
   }
   Acc v[PER][E], vn[PER][E];
+  // piece u of tile J holds a needed entry: inside n x n, and for a
+  // diagonal tile on or above the diagonal (the packed zeros below it are
+  // not read)
+  auto need = [&](int J, int u) {
+    const int c = cg + CPT * u;
+    return ST * J + c < n && ST * I + r0 < n && (J > I || r0 <= c);
+  };
+  // the run's tiles as one buffer resource: a piece that is not needed gets
+  // an offset past its end and reads as zero without a memory access
+  const __amdgpu_buffer_rsrc_t rs = buf_rsrc(tiles, (uint32_t)((J1 - J0) * ST * ST * sizeof(T)));
+  auto load_piece = [&](int J, int u, Acc (&o)[E]) {
+    const uint32_t off = need(J, u) ? (uint32_t)(((J - J0) * ST * ST + (t + 256 * u) * E) * sizeof(T)) : BUF_SKIP;
+    tile_load16<T>(rs, off, o);
+  };
 #pragma unroll
-  for (int u = 0; u < PER; ++u) tile_load16(tiles + (t + 256 * u) * E, v[u]);
+  for (int u = 0; u < PER; ++u) load_piece(J0, u, v[u]);
   auto store_x = [&]() {
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
@@ -150,14 +167,13 @@ __global__ __launch_bounds__(256) void symv_part_kernel(const GemvDesc* __restri
         }
 #pragma unroll
         for (int e = 0; e < E; ++e) rred[kk][cg][r0 + e] = rs[e];
-        if (J > I) {  // uniform: block row J gets the transposed tile
+        // block row J gets the transposed tile (for the diagonal tile, row I)
 #pragma unroll
-          for (int u = 0; u < PER; ++u) {
-            Acc cs = 0;
+        for (int u = 0; u < PER; ++u) {
+          Acc cs = 0;
 #pragma unroll
-            for (int e = 0; e < E; ++e) cs = fma(v[u][e], xi[k][r0 + e], cs);
-            cred[kk][cg + CPT * u][rg] = cs;
-          }
+          for (int e = 0; e < E; ++e) cs = fma(v[u][e], xi[k][r0 + e], cs);
+          cred[kk][cg + CPT * u][rg] = cs;
         }
       }
       __syncthreads();
@@ -173,6 +189,12 @@ __global__ __launch_bounds__(256) void symv_part_kernel(const GemvDesc* __restri
           double sr = 0.0;
 #pragma unroll
           for (int g = 0; g < CPT; ++g) sr += (double)rred[it][g][l];
+          if (J == I) {  // uniform: the diagonal tile's transposed part belongs to row I too
+            double sc = 0.0;
+#pragma unroll
+            for (int g = 0; g < PPC; ++g) sc += (double)cred[it][l][g];
+            sr += sc;
+          }
           racc[k] += sr;
           if (J == J1 - 1) prow[((int64_t)p0 * NC + k) * ST + l] = racc[k];
         } else if (J > I) {
@@ -188,9 +210,8 @@ __global__ __launch_bounds__(256) void symv_part_kernel(const GemvDesc* __restri
   for (int J = J0; J + 1 < J1; ++J) {
     // the next tile's pieces, issued before this tile's products (unconditional
     // inside the loop, so that they stay in flight meanwhile)
-    const T* nxt = tiles + (int64_t)(J + 1 - J0) * (ST * ST);
 #pragma unroll
-    for (int u = 0; u < PER; ++u) tile_load16(nxt + (t + 256 * u) * E, vn[u]);
+    for (int u = 0; u < PER; ++u) load_piece(J + 1, u, vn[u]);
     if (J == J0) store_x();
     products(J);
 #pragma unroll
@@ -248,7 +269,9 @@ __global__ __launch_bounds__(256) void symv_sum_kernel(const GemvDesc* __restric
 }
 
 // Upper tiles of npad x npad column-major FP64 matrices, converted to the
-// storage type: block (tile t of matrix k) copies one 64 x 64 tile.
+// storage type: block (tile t of matrix k) copies one 64 x 64 tile.  A
+// diagonal tile keeps its strict upper triangle, half its diagonal and zeros
+// below, so that its row and column products together give M_II x_I.
 template <typename T>
 __global__ __launch_bounds__(256) void pack_upper_kernel(const double* __restrict__ src, const int64_t* __restrict__ soff,
                                                          const int32_t* __restrict__ NP,
@@ -265,7 +288,8 @@ __global__ __launch_bounds__(256) void pack_upper_kernel(const double* __restric
   T* d = dst + doff[k] + t * (ST * ST);
   for (int e = threadIdx.x; e < ST * ST; e += 256) {
     const int r = e & 63, c = e >> 6;
-    const double v = s[(int64_t)c * np + r];
+    double v = s[(int64_t)c * np + r];
+    if (I == J) v = r < c ? v : r == c ? 0.5 * v : 0.0;  // U with U + U^T = M_II (halving is exact)
     if constexpr (sizeof(T) == 2)
       d[e] = to_bf16((float)v);
     else

@@ -86,6 +86,47 @@ __device__ inline void load16(const uint16_t* p, float (&o)[8]) {
   }
 }
 
+// 16-byte loads through a buffer resource (raw buffer, byte offsets): an
+// offset past the resource's size reads as zero without a memory access, so
+// a piece that is not needed costs no traffic while the load instruction
+// stays unconditional (no branch around it, so the compiler's wait counts
+// stay exact and later loads stay in flight).  NT: the non-temporal hint.
+constexpr uint32_t BUF_SKIP = 0x80000000u;  // past every resource made here
+
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t bytes) {
+  // word 3 = 0x00020000: the raw 32-bit data format of the gfx9 family
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+
+template <bool NT>
+__device__ inline gdsw_u4 buf_load16(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(gdsw_u4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, NT ? 2 : 0));
+}
+template <bool NT>
+__device__ inline void buf_load16(__amdgpu_buffer_rsrc_t r, uint32_t off, double (&o)[2]) {
+  const gdsw_d2 v = __builtin_bit_cast(gdsw_d2, buf_load16<NT>(r, off));
+  o[0] = v.x;
+  o[1] = v.y;
+}
+template <bool NT>
+__device__ inline void buf_load16(__amdgpu_buffer_rsrc_t r, uint32_t off, float (&o)[4]) {
+  const gdsw_f4 v = __builtin_bit_cast(gdsw_f4, buf_load16<NT>(r, off));
+  o[0] = v.x;
+  o[1] = v.y;
+  o[2] = v.z;
+  o[3] = v.w;
+}
+template <bool NT>
+__device__ inline void buf_load16_bf16(__amdgpu_buffer_rsrc_t r, uint32_t off, float (&o)[8]) {
+  const gdsw_u4 v = buf_load16<NT>(r, off);
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    o[2 * i] = __uint_as_float(w[i] << 16);
+    o[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+  }
+}
+
 // FP32 -> BF16 bits, round to nearest even (NaN stays NaN).
 __device__ inline uint16_t to_bf16(float x) {
   uint32_t u = __float_as_uint(x);
