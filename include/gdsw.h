@@ -71,8 +71,13 @@ typedef enum { GDSW_FP64 = 0, GDSW_FP32 = 1, GDSW_BF16 = 2 } gdsw_precision;
  *     U1 = L^-1 F, p = S^-1 (B U1 - g), u = U1 - L^-1 B^T p: L_i^-1 and S_i^-1
  *     are formed at setup (Gauss-Jordan, FP64) and stored as upper tiles
  *     (L_i^-1 in the local precision), B_i as sparse rows.  An apply reads
- *     L_i^-1 twice (three vectors per pass), S_i^-1 once and B_i twice: about
- *     a quarter of the bytes of GDSW_SOLVE_SYMMETRIC at 16^3.  EINVAL when the
+ *     L_i^-1 twice (three vectors per pass), S_i^-1 once and B_i twice.
+ *     Where W_i = K_i^-1 B_i^T (formed for S_i) has fewer entries than the
+ *     upper triangle of L_i^-1 (the Q1 pressure: few pressure DOFs per local
+ *     problem), the setup keeps it (local precision) and the last step is
+ *     u = U1 - W p: L_i^-1 once, W_i once, B_i once; with the P1disc pressure
+ *     the second pass stays.  At 16^3 an apply reads about a fifth of the
+ *     bytes of GDSW_SOLVE_SYMMETRIC.  EINVAL when the
  *     velocity block lacks that structure (numbering 3 node + component,
  *     uncoupled components with equal values) or max_rhs > 1; the learned
  *     interior solve and batches are not offered with it.  Coarse levels use
@@ -198,18 +203,22 @@ typedef struct {
   uint64_t factor_bytes;      /* level-1 local factors as stored */
   uint64_t coarse_bytes;      /* coarse factors and bases (all levels) */
   uint64_t device_bytes;      /* everything the context holds on the device */
-  uint64_t solve_bytes;       /* algorithmic bytes the triangular solves of one
-                                 apply read: sum over every factor (local and
-                                 coarse) of n^2 * element size */
-  int64_t solve_launches;     /* triangular-solve kernel launches per apply */
+  uint64_t solve_bytes;       /* algorithmic bytes the local and coarse solves
+                                 of one apply read: per stored matrix n^2
+                                 (inverse, triangular) or n (n + 1) / 2
+                                 (symmetric, block) times the element size,
+                                 each pass counted; block mode adds B_i and
+                                 W_i as read */
+  int64_t solve_launches;     /* kernel launches of those solves per apply */
 } gdsw_sizes;
 
 /* Setup ------------------------------------------------------------------- */
 
 /* Builds the problem (host: numbering, assembly, decomposition, interface
  * entities; Section 3 calls this the symbolic setup) and the preconditioner
- * (device: local matrices and their LU factors, Phi, A_0 and its factors;
- * the numeric setup).  Blocks until the setup is complete.
+ * (device: local matrices and their inverses, LU factors or block factors
+ * as local_solve asks, Phi, A_0 and its inverse; the numeric setup).  Blocks
+ * until the setup is complete.
  * Errors: EINVAL for n < 1, m < 1, n % m, overlap < 1, levels not 2/3,
  * m % group (3 levels), bad precision or tile; ENOMEM when the budget check
  * fails (the message gives the bytes needed); ESINGULAR when a pivot of a
@@ -368,8 +377,8 @@ gdsw_status gdsw_local_indices(const gdsw_ctx* ctx, int32_t i, int32_t* idx_host
  * does not touch the cube's boundary); FGMRES admits the variable
  * preconditioner.  The network maps r_i / ||r_i|| on the local node grid
  * (channels u_x, u_y, u_z, p; pressure on the Q1 nodes; velocity divided by
- * mu) to A_i^-1 r_i / ||r_i|| scaled per channel.  The LU factors are kept:
- * they generate the training pairs and serve as fallback. */
+ * mu) to A_i^-1 r_i / ||r_i|| scaled per channel.  The exact local solves
+ * are kept: they generate the training pairs and serve as fallback. */
 typedef struct {
   int32_t grid;               /* nodes per axis of an interior local problem */
   int32_t subdomains;         /* interior subdomains */

@@ -283,7 +283,11 @@ gdsw_status gdsw_get_sizes(const gdsw_ctx* ctx, gdsw_sizes* out) {
   out->coarse_bytes = c.coarse_bytes;
   out->device_bytes = c.arena.used;
   if (!c.host_only) {
-    if (c.solve_mode == SOLVE_BLOCK) {  // two passes over L_i^-1, one over S_i^-1, B twice
+    if (c.solve_mode == SOLVE_BLOCK && c.blk.use_w) {  // L_i^-1 once, S_i^-1 once, B and W once
+      out->solve_bytes = c.L1.algorithmic_bytes() + c.LP.algorithmic_bytes() + c.HI.algorithmic_bytes() +
+                         c.blk.b_bytes + c.blk.w_bytes;
+      out->solve_launches = c.L1.launches() + c.LP.launches() + c.HI.launches() + 2;
+    } else if (c.solve_mode == SOLVE_BLOCK) {  // two passes over L_i^-1, one over S_i^-1, B twice
       out->solve_bytes = 2 * c.L1.algorithmic_bytes() + c.LP.algorithmic_bytes() + c.HI.algorithmic_bytes() +
                          c.blk.b_bytes;
       out->solve_launches = 2 * c.L1.launches() + c.LP.launches() + c.HI.launches() + 3;

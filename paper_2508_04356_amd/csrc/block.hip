@@ -8,11 +8,16 @@
 // (F, U1: the velocity right-hand side and solution as three component
 // vectors).  An apply reads L_i^-1 twice (upper tiles, three vectors per
 // pass), S_i^-1 once and B_i twice: at 16^3 about a quarter of the bytes of
-// the dense symmetric inverse, and the same operator up to rounding.
+// the dense symmetric inverse, and the same operator up to rounding.  Where
+// W_i = K_i^-1 B_i^T (formed at setup for S_i anyway) is smaller than the
+// upper tiles of L_i^-1 (a continuous pressure: few pressure DOFs per local
+// problem), it is kept and the last step is u = U1 - W p: one pass over
+// L_i^-1, one over W_i, B_i once.
 #include <hip/hip_runtime.h>
 
 #include "context.h"
 #include "kernels.h"
+#include "vec16.h"
 
 namespace gdsw {
 namespace {
@@ -87,6 +92,63 @@ __global__ __launch_bounds__(256) void rowprod_kernel(int64_t nrows, const int32
   }
 }
 
+// u_i -= W_i p_i for every local problem: W_i = K_i^-1 B_i^T (3 npad_i rows
+// in the velocity segment's component-major order, np_i columns,
+// column-major), p_i the pressure segment of the work vector.  Item: 64 E
+// rows of one W_i (E rows per 16-byte piece); lane l of wave q takes rows
+// r0 + E l .. + E - 1 and the columns q, q + 4, ..., eight loads in flight;
+// the four wave sums are added in wave order, so results repeat bit for bit.
+// Rows past 3 npad_i read as zero through the buffer resource.
+template <typename T>
+__global__ __launch_bounds__(256) void wp_sub_kernel(const T* __restrict__ W, const WItem* __restrict__ items,
+                                                     double* __restrict__ w) {
+  using Acc = typename VecW<T>::acc;
+  constexpr int E = VecW<T>::W;
+  constexpr int RW = 64 * E;
+  constexpr int U = 8;
+  __shared__ double ps[WP_MAX_NP];
+  __shared__ Acc red[4][RW];
+  const WItem it = items[blockIdx.x];
+  const int t = threadIdx.x, lane = t % 64, q0 = t / 64;
+  for (int k = t; k < it.np; k += 256) ps[k] = w[it.poff + k];
+  __syncthreads();
+  const __amdgpu_buffer_rsrc_t rs = buf_rsrc(W + it.woff, (uint32_t)((int64_t)it.rows * it.np * sizeof(T)));
+  const int r = it.r0 + E * lane;
+  Acc s[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) s[e] = 0;
+  for (int q = q0; q < it.np; q += 4 * U) {
+    Acc v[U][E];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int qq = q + 4 * u;
+      const uint32_t off =
+          qq < it.np && r < it.rows ? (uint32_t)(((int64_t)qq * it.rows + r) * sizeof(T)) : BUF_SKIP;
+      if constexpr (sizeof(T) == 2)
+        buf_load16_bf16<true>(rs, off, v[u]);
+      else
+        buf_load16<true>(rs, off, v[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int qq = q + 4 * u;
+      const Acc pv = qq < it.np ? (Acc)ps[qq] : (Acc)0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) s[e] = fma(v[u][e], pv, s[e]);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) red[q0][E * lane + e] = s[e];
+  __syncthreads();
+  for (int k = t; k < RW; k += 256) {
+    const int row = it.r0 + k;
+    if (row < it.rows) {
+      const double x = (((double)red[0][k] + (double)red[1][k]) + (double)red[2][k]) + (double)red[3][k];
+      w[it.voff + row] -= x;
+    }
+  }
+}
+
 unsigned blocks_for(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65535)); }
 
 }  // namespace
@@ -107,6 +169,24 @@ void copy_blocks(const double* src, const int64_t* soff, const int32_t* n, int c
   GDSW_HIP(hipGetLastError());
 }
 
+int wp_rows_per_item(int prec) { return 64 * (prec == P_FP64 ? 2 : prec == P_FP32 ? 4 : 8); }
+
+void wp_sub(int prec, const void* W, const WItem* items, int n_items, double* w, KernelTimer* tm, double bytes,
+            hipStream_t st) {
+  if (n_items == 0) return;
+  if (tm && (!tm->on || tm->used >= KernelTimer::CAP)) tm = nullptr;
+  if (prec == P_FP64)
+    timed_launch(tm, bytes, wp_sub_kernel<double>, dim3(n_items), dim3(256), st, static_cast<const double*>(W),
+                 items, w);
+  else if (prec == P_FP32)
+    timed_launch(tm, bytes, wp_sub_kernel<float>, dim3(n_items), dim3(256), st, static_cast<const float*>(W),
+                 items, w);
+  else
+    timed_launch(tm, bytes, wp_sub_kernel<uint16_t>, dim3(n_items), dim3(256), st, static_cast<const uint16_t*>(W),
+                 items, w);
+  GDSW_HIP(hipGetLastError());
+}
+
 void block_local_solve(Context& ctx, hipStream_t st) {
   const BlockSolve& b = ctx.blk;
   FactorSet& L = ctx.L1;
@@ -120,6 +200,10 @@ void block_local_solve(Context& ctx, hipStream_t st) {
       b.n_prow, b.d_prow_pos, b.d_bm_ptr, b.d_bm_pos, b.d_bm_val, ctx.d_w, nullptr);
   // p = S^-1 t (and, with two levels, the coarse solve in the same launch)
   local_solve_set(ctx.LP, ctx.d_w, st);
+  if (b.use_w) {  // u = U1 - W p
+    wp_sub(L.prec, b.d_W, b.d_witems, b.n_witems, ctx.d_w, nullptr, 0.0, st);
+    return;
+  }
   // w2 = B^T p, then u = U1 - L^-1 w2 (the block-row sums subtract from U1)
   // velocity rows hold up to a few dozen: eight lanes per row
   rowprod_kernel<8, 1><<<(unsigned)((b.n_vrow * 8 + 255) / 256), 256, 0, st>>>(

@@ -193,8 +193,28 @@ struct BlockSolve {
   double* d_bt_val = nullptr;
   double* d_w2 = nullptr;            // second work vector (B^T p, then L^-1 B^T p), n_w1
   GemvDesc* d_desc2 = nullptr;       // L1's matrices against d_w2
-  uint64_t b_bytes = 0;              // bytes of both B row lists
+  uint64_t b_bytes = 0;              // bytes of the B row lists an apply reads
+  // u = U1 - W p with W_i = K_i^-1 B_i^T kept from the setup (3 npad_i x np_i,
+  // column-major, local precision) instead of a second pass over L_i^-1,
+  // where W is the smaller read
+  bool use_w = false;
+  void* d_W = nullptr;
+  struct WItem* d_witems = nullptr;  // one per (subdomain, block of rows)
+  int n_witems = 0;
+  uint64_t w_bytes = 0;              // algorithmic bytes of W
 };
+
+// Work item of the W p product: rows r0 .. r0 + 64 E - 1 of W_i.
+struct WItem {
+  int64_t woff;   // element offset of W_i in the store
+  int64_t voff;   // work position of row 0 (velocity segment of subdomain i)
+  int64_t poff;   // work position of p_i (pressure segment)
+  int32_t rows;   // 3 npad_i
+  int32_t np;     // columns
+  int32_t r0;
+  int32_t pad;
+};
+constexpr int WP_MAX_NP = 1024;      // pressure DOFs per local problem on the W path
 
 struct Context {
   Problem P;
@@ -335,6 +355,9 @@ void spmv(Context& ctx, const double* x, double* y, hipStream_t st);
 void apply_precond_noalloc(Context& ctx, const double* r, double* z, hipStream_t st);
 // block local solve of every level-1 subdomain in the work vector (block.hip)
 void block_local_solve(Context& ctx, hipStream_t st);
+int wp_rows_per_item(int prec);
+void wp_sub(int prec, const void* W, const WItem* items, int n_items, double* w, KernelTimer* tm, double bytes,
+            hipStream_t st);
 void block_fill_bt(const int32_t* rowptr, const int32_t* col, const double* val, int64_t n_u,
                    const int32_t* vx_ptr, const int32_t* vx, const int32_t* pr_ptr, const int32_t* pr,
                    const int32_t* npv, const int64_t* off, int f0, int cnt, int max_np, double* bt, hipStream_t st);

@@ -1001,6 +1001,24 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
     for (int i = 0; i < P.n_sub; ++i) soff[i + 1] = soff[i] + (int64_t)bpr[i].size() * bpr[i].size();
     double* Sbuf = dalloc<double>(A, std::max<int64_t>(soff.back(), 1));
     int64_t* d_soff = dupload(A, soff, st);
+    // keep W_i = K_i^-1 B_i^T for the last step where it is the smaller read
+    // (its bytes against one pass over the upper tiles of L_i^-1)
+    BlockSolve& b = ctx.blk;
+    const size_t les = elem_size(ctx.local_prec);
+    std::vector<int64_t> woff(P.n_sub + 1, 0);
+    uint64_t tile_bytes = 0;
+    bool fits = true;
+    for (int i = 0; i < P.n_sub; ++i) {
+      const int64_t wi = 3 * (int64_t)ctx.L1.npad[i] * (int64_t)bpr[i].size();
+      woff[i + 1] = woff[i] + wi;
+      tile_bytes += (uint64_t)symv_tiles(ctx.L1.npad[i]) * 64 * 64 * les;
+      fits = fits && bpr[i].size() <= (size_t)WP_MAX_NP && (uint64_t)wi * les < (1ull << 31);
+    }
+    b.use_w = fits && woff.back() > 0 && (uint64_t)woff.back() * les < tile_bytes;
+    if (b.use_w) {
+      b.d_W = A.alloc((uint64_t)woff.back() * les);
+      b.w_bytes = (uint64_t)woff.back() * les;
+    }
     factor_set(
         ctx, ctx.L1, staging_cap, 1e-14 * amax, "velocity block", st,
         [&](DenseBatch& B, int f0, int f1) {
@@ -1044,6 +1062,13 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
           GemmDesc* d_g2 = dupload(A, g2, st);
           gemm_batched(d_g1, (int)g1.size(), max_nv, 3 * max_np, 1.0, 0.0, st);
           gemm_batched(d_g2, (int)g2.size(), max_np, max_np, 1.0, 0.0, st);
+          if (b.use_w) {  // the chunk's W_i, contiguous in the store as in W
+            char* dst = static_cast<char*>(b.d_W) + (size_t)woff[f0] * les;
+            if (ctx.local_prec == P_FP64)
+              GDSW_HIP(hipMemcpyAsync(dst, W, boff.back() * 8, hipMemcpyDeviceToDevice, st));
+            else
+              convert_store(ctx.local_prec, W, dst, boff.back(), st);
+          }
           GDSW_HIP(hipStreamSynchronize(st));
           for (void* q : {(void*)Bt, (void*)W, (void*)d_npv, (void*)d_boff, (void*)d_g1, (void*)d_g2}) A.free(q);
         });
@@ -1063,8 +1088,7 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
       A.free(q);
     if (d_perm_b) A.free(d_perm_b);
     // B_i as row lists over work positions: pressure rows (velocity positions)
-    // and velocity rows (pressure positions), each subdomain in order
-    BlockSolve& b = ctx.blk;
+    // and, without W, velocity rows (pressure positions), each subdomain in order
     std::vector<int32_t> prow_pos, bm_pos, vrow_pos, bt_pos;
     std::vector<int64_t> bm_ptr(1, 0), bt_ptr(1, 0);
     std::vector<double> bm_val, bt_val;
@@ -1084,7 +1108,7 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
           const int64_t vp = vb + comp * npv + (it - vx.begin());
           bm_pos.push_back((int32_t)vp);
           bm_val.push_back(P.val[e]);
-          tr.emplace_back(vp, pb + (int64_t)q, P.val[e]);
+          if (!b.use_w) tr.emplace_back(vp, pb + (int64_t)q, P.val[e]);
         }
         bm_ptr.push_back((int64_t)bm_pos.size());
       }
@@ -1105,13 +1129,26 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
     b.d_bm_ptr = dupload(A, bm_ptr, st);
     b.d_bm_pos = dupload(A, bm_pos, st);
     b.d_bm_val = dupload(A, bm_val, st);
-    b.d_vrow_pos = dupload(A, vrow_pos, st);
-    b.d_bt_ptr = dupload(A, bt_ptr, st);
-    b.d_bt_pos = dupload(A, bt_pos, st);
-    b.d_bt_val = dupload(A, bt_val, st);
     b.b_bytes = (uint64_t)(bm_pos.size() + bt_pos.size()) * 12 + (uint64_t)(prow_pos.size() + vrow_pos.size()) * 12;
-    b.d_w2 = dalloc<double>(A, std::max<int64_t>(ctx.n_w1, 1));
-    GDSW_HIP(hipMemsetAsync(b.d_w2, 0, std::max<int64_t>(ctx.n_w1, 1) * 8, st));
+    if (b.use_w) {
+      const int rw = wp_rows_per_item(ctx.local_prec);
+      std::vector<WItem> items;
+      for (int i = 0; i < P.n_sub; ++i) {
+        const int32_t rows = 3 * ctx.L1.npad[i], np = (int32_t)bpr[i].size();
+        if (np == 0) continue;
+        for (int32_t r0 = 0; r0 < rows; r0 += rw)
+          items.push_back(WItem{woff[i], ctx.L1.xoff[i], ctx.LP.xoff[i], rows, np, r0, 0});
+      }
+      b.n_witems = (int)items.size();
+      b.d_witems = dupload(A, items, st);
+    } else {
+      b.d_vrow_pos = dupload(A, vrow_pos, st);
+      b.d_bt_ptr = dupload(A, bt_ptr, st);
+      b.d_bt_pos = dupload(A, bt_pos, st);
+      b.d_bt_val = dupload(A, bt_val, st);
+      b.d_w2 = dalloc<double>(A, std::max<int64_t>(ctx.n_w1, 1));
+      GDSW_HIP(hipMemsetAsync(b.d_w2, 0, std::max<int64_t>(ctx.n_w1, 1) * 8, st));
+    }
   } else
   factor_set(ctx, ctx.L1, staging_cap, 1e-14 * amax, "local factor", st,
              [&](DenseBatch& B, int f0, int f1) {
@@ -1179,6 +1216,7 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
                                                                : (uint64_t)ctx.L1.npad[f] * ctx.L1.npad[f]) *
                             elem_size(ctx.local_prec) +
                         (blockm ? (uint64_t)symv_tiles(ctx.LP.npad[f]) * 64 * 64 * 8 : 0);
+  ctx.factor_bytes += ctx.blk.w_bytes;
   ctx.coarse_bytes = (uint64_t)Nc * Nc * 8 * 2 + (uint64_t)phi_off.back() * 16;
   // descriptors of the stored inverses against the work vector
   for (FactorSet* fs : {&ctx.L1, &ctx.HI, &ctx.LP})
@@ -1187,7 +1225,7 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
       if (fs->nc > 1)
         for (int f = 0; f < fs->count; ++f) d[f].vs = fs->npad[f];
       fs->d_desc = dupload(A, d, st);
-      if (blockm && fs == &ctx.L1) {
+      if (blockm && fs == &ctx.L1 && !ctx.blk.use_w) {
         // L^-1 (B^T p), read from d_w2 and subtracted from U1 in the work vector
         std::vector<GemvDesc> d2 = gemv_descs(*fs, ctx.blk.d_w2);
         for (int f = 0; f < fs->count; ++f) {
