@@ -467,16 +467,31 @@ gdsw_status gdsw_set_schedule(gdsw_ctx* ctx, int32_t phases, int32_t waves, void
 gdsw_status gdsw_profile_apply(gdsw_ctx* ctx, const double* r_dev, double* z_dev, void* stream,
                                double* ms);
 
-/* Launch-shape autotuner of the level-1 inverse product (GDSW_SOLVE_INVERSE):
- * times the partial-product kernel with column chunks of 512, 1024 and 2048
- * columns per work item on this context's own matrices (10 products each,
- * HIP events on `stream`), keeps the fastest and re-plans.  The chunk sets
- * the grouping of the partial sums, so results can change in the last bits;
- * they are again bitwise reproducible for the chosen chunk.  chosen (may be
- * NULL) receives the chunk, ms[3] (may be NULL) the mean time of each.
- * Call before gdsw_learned_init; EUNSUPPORTED otherwise or in triangular
- * mode.  Synchronises `stream`. */
+/* Launch-shape autotuner of the level-1 product, on this context's own
+ * matrices (10 products per candidate after 3 untimed, HIP events on
+ * `stream`); keeps the fastest and re-plans.
+ *   GDSW_SOLVE_INVERSE: column chunks of 512, 1024 and 2048 columns per work
+ *     item; chosen receives the chunk, ms[0..2] the mean time of each.
+ *   GDSW_SOLVE_SYMMETRIC and GDSW_SOLVE_BLOCK (the velocity-block tiles):
+ *     runs of 2 or 1 stored tiles per work-group, each in the plain and in
+ *     the XCD-contiguous work-group order; candidates (2, plain), (2, XCD),
+ *     (1, plain), (1, XCD) with times in ms[0..3]; chosen = 10 * run + (1 if
+ *     XCD order).
+ * The shape sets the grouping of the partial sums, so results can change in
+ * the last bits; they are again bitwise reproducible for the chosen shape.
+ * chosen and ms may be NULL.  Call before gdsw_learned_init; EUNSUPPORTED
+ * otherwise or in triangular mode.  Synchronises `stream`. */
 gdsw_status gdsw_autotune(gdsw_ctx* ctx, void* stream, int32_t* chosen, double* ms);
+
+/* Autotuner of the several-column MFMA product of the level-1 inverses
+ * (GDSW_SOLVE_INVERSE with max_rhs > 1), timed with max_rhs columns (5
+ * products per candidate).  Candidates: FP64 storage 0..2 = the direct
+ * kernel with 512 / 1024 / 2048 summation columns per work item, 3..5 = the
+ * LDS-staged kernel with 256 / 512 / 1024; FP32 and BF16 storage 0..2 = 512
+ * / 1024 / 2048 (one kernel).  chosen receives the index of the fastest,
+ * ms[0..5] the times (0 where no candidate).  Results can change in the last
+ * bits as above.  EUNSUPPORTED for other contexts.  Synchronises `stream`. */
+gdsw_status gdsw_autotune_mfma(gdsw_ctx* ctx, void* stream, int32_t* chosen, double* ms);
 
 /* Event timing of the dominant solve kernel.  While enabled, every launch of
  * the level-1 solve kernel in a full apply (the partial-product kernel of

@@ -68,7 +68,10 @@ class ConvNet:
                 self.W.append(rng.standard_normal((cout, cin, 3, 3, 3)) * scale)
                 self.b.append(np.zeros(cout))
 
-    def forward(self, X, keep=False):
+    def forward(self, X, keep=False, act_round=None):
+        """act_round: optional map applied to every layer's output (after the
+        ReLU), the storage format of a network that keeps its activations in
+        a narrower type; None keeps them exact."""
         acts = [X]
         h = X
         L = len(self.W)
@@ -76,11 +79,16 @@ class ConvNet:
             h = conv3d(h, self.W[l], self.b[l])
             if l < L - 1:
                 h = np.maximum(h, 0.0)
+            if act_round is not None:
+                h = act_round(h)
             acts.append(h)
         return (h, acts) if keep else h
 
-    def loss_and_grads(self, X, Y, mask):
-        out, acts = self.forward(X, keep=True)
+    def loss_and_grads(self, X, Y, mask, act_round=None):
+        """Loss and exact gradients of the network as evaluated, i.e. with
+        the activations as act_round leaves them (straight through the
+        rounding, which is how a network storing rounded activations trains)."""
+        out, acts = self.forward(X, keep=True, act_round=act_round)
         B = X.shape[0]
         diff = (out - Y) * mask
         loss = 0.5 * float(np.sum(diff * diff)) / B

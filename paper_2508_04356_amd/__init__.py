@@ -97,6 +97,7 @@ _sig = {
     "gdsw_local_indices": (C.c_int, [_P, C.c_int32, _P, C.POINTER(C.c_int32)]),
     "gdsw_profile_apply": (C.c_int, [_P, _P, _P, _P, _P]),
     "gdsw_autotune": (C.c_int, [_P, _P, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+    "gdsw_autotune_mfma": (C.c_int, [_P, _P, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "gdsw_kernel_timer": (C.c_int, [_P, C.c_int32]),
     "gdsw_kernel_timer_read": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_uint64)]),
     "gdsw_set_schedule": (C.c_int, [_P, C.c_int32, C.c_int32, _P]),
@@ -305,10 +306,20 @@ class Solver:
         return z
 
     def autotune(self, stream=None):
-        """Picks the column chunk of the inverse product; returns (chunk, [ms for 512, 1024, 2048])."""
+        """Picks the launch shape of the level-1 product.  Inverse mode:
+        (chunk, [ms for 512, 1024, 2048]); symmetric and block modes:
+        (10 * run + xcd, [ms for (2, 0), (2, 1), (1, 0), (1, 1)])."""
         ch = C.c_int32()
-        ms = (C.c_double * 3)()
+        ms = (C.c_double * 4)()
         _check(_lib.gdsw_autotune(self._ctx, _stream(stream), C.byref(ch), ms), self._ctx)
+        return ch.value, list(ms)[:3 if self.dec.local_solve == LOCAL_SOLVES["inverse"] else 4]
+
+    def autotune_mfma(self, stream=None):
+        """Picks the several-column MFMA product's kernel and chunk; returns
+        (index of the fastest candidate, [ms per candidate])."""
+        ch = C.c_int32()
+        ms = (C.c_double * 6)()
+        _check(_lib.gdsw_autotune_mfma(self._ctx, _stream(stream), C.byref(ch), ms), self._ctx)
         return ch.value, list(ms)
 
     def kernel_timer(self, enable):
@@ -453,8 +464,9 @@ class Batch:
         _check(_lib.gdsw_apply_precond_batch(self._b, _ptr_array(rs), _ptr_array(zs), _stream(stream)))
         return zs
 
-    def fgmres(self, bs, xs, rtol=1e-8, restart=100, max_it=1000, stream=None, raise_on_noconv=True):
-        opts = FgmresOpts(rtol, restart, max_it, 0, 0, None)
+    def fgmres(self, bs, xs, rtol=1e-8, restart=100, max_it=1000, stream=None, raise_on_noconv=True,
+               use_graph=False):
+        opts = FgmresOpts(rtol, restart, max_it, int(use_graph), 0, None)
         infos = (FgmresInfo * len(self.members))()
         st = _lib.gdsw_fgmres_solve_batch(self._b, _ptr_array(bs), _ptr_array(xs), C.byref(opts), infos,
                                           _stream(stream))

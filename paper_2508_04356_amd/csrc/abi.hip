@@ -92,6 +92,24 @@ gdsw_status check_device_ctx(const gdsw_ctx* ctx) {
   return GDSW_OK;
 }
 
+// Mean time of `reps` calls of `run` on `st` after three untimed ones.
+template <class F>
+double time_calls(hipStream_t st, int reps, F run) {
+  hipEvent_t e0, e1;
+  GDSW_HIP(hipEventCreate(&e0));
+  GDSW_HIP(hipEventCreate(&e1));
+  for (int w = 0; w < 3; ++w) run();
+  GDSW_HIP(hipEventRecord(e0, st));
+  for (int r = 0; r < reps; ++r) run();
+  GDSW_HIP(hipEventRecord(e1, st));
+  GDSW_HIP(hipEventSynchronize(e1));
+  float el = 0.f;
+  GDSW_HIP(hipEventElapsedTime(&el, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return el / reps;
+}
+
 }  // namespace
 
 extern "C" {
@@ -579,43 +597,92 @@ gdsw_status gdsw_kernel_timer_read(gdsw_ctx* ctx, double* total_ms, int64_t* lau
 gdsw_status gdsw_autotune(gdsw_ctx* ctx, void* stream, int32_t* chosen, double* ms) {
   if (gdsw_status s = check_device_ctx(ctx)) return s;
   Context& c = ctx->c;
-  if (c.solve_mode != SOLVE_INVERSE) return fail(ctx, GDSW_EUNSUPPORTED, "autotuning applies to GDSW_SOLVE_INVERSE");
+  if (c.solve_mode == SOLVE_TRSV)
+    return fail(ctx, GDSW_EUNSUPPORTED, "autotuning applies to the inverse, symmetric and block local solves");
   if (c.learned) return fail(ctx, GDSW_EUNSUPPORTED, "autotune before gdsw_learned_init");
   return guarded(ctx, [&]() {
     hipStream_t st = (hipStream_t)stream;
     FactorSet& fs = c.L1;
-    const int cand[3] = {512, 1024, 2048};
-    double t[3] = {0, 0, 0};
-    hipEvent_t e0, e1;
-    GDSW_HIP(hipEventCreate(&e0));
-    GDSW_HIP(hipEventCreate(&e1));
     KernelTimer* tm = fs.timer;
     fs.timer = nullptr;
-    for (int q = 0; q < 3; ++q) {
-      fs.cw = cand[q];
-      plan_schedule(fs, 1, c.arena, st, 0);
-      for (int w = 0; w < 3; ++w) local_solve_set(fs, c.d_w, st);
-      GDSW_HIP(hipEventRecord(e0, st));
-      for (int r = 0; r < 10; ++r) local_solve_set(fs, c.d_w, st);
-      GDSW_HIP(hipEventRecord(e1, st));
-      GDSW_HIP(hipEventSynchronize(e1));
-      float el = 0.f;
-      GDSW_HIP(hipEventElapsedTime(&el, e0, e1));
-      t[q] = el / 10.0;
+    auto once = [&]() { local_solve_set(fs, c.d_w, st); };
+    int best = 0;
+    if (c.solve_mode == SOLVE_INVERSE) {
+      // column chunk of the partial products
+      const int cand[3] = {512, 1024, 2048};
+      double t[3];
+      for (int q = 0; q < 3; ++q) {
+        fs.cw = cand[q];
+        plan_schedule(fs, 1, c.arena, st, 0);
+        t[q] = time_calls(st, 10, once);
+      }
+      for (int q = 1; q < 3; ++q)
+        if (t[q] < t[best]) best = q;  // argmin over the measured candidates
+      fs.cw = cand[best];
+      if (chosen) *chosen = fs.cw;
+      if (ms)
+        for (int q = 0; q < 3; ++q) ms[q] = t[q];
+    } else {
+      // symmetric tiles (and the block solve's velocity-block tiles): tiles
+      // per work item and the work-group order
+      const int run[4] = {2, 2, 1, 1}, xcd[4] = {0, 1, 0, 1};
+      double t[4];
+      for (int q = 0; q < 4; ++q) {
+        fs.sym_run = run[q];
+        fs.sym_xcd = xcd[q];
+        plan_schedule(fs, 1, c.arena, st, 0);
+        t[q] = time_calls(st, 10, once);
+      }
+      for (int q = 1; q < 4; ++q)
+        if (t[q] < t[best]) best = q;
+      fs.sym_run = run[best];
+      fs.sym_xcd = xcd[best];
+      if (chosen) *chosen = 10 * run[best] + xcd[best];
+      if (ms)
+        for (int q = 0; q < 4; ++q) ms[q] = t[q];
     }
-    int best = 0;  // argmin over the three measured candidates
-    for (int q = 1; q < 3; ++q)
-      if (t[q] < t[best]) best = q;
-    fs.cw = cand[best];
     plan_schedule(fs, 1, c.arena, st, 0);
     fs.timer = tm;
     GDSW_HIP(hipMemsetAsync(c.d_w, 0, std::max<int64_t>(c.n_w, 1) * sizeof(double), st));
     GDSW_HIP(hipStreamSynchronize(st));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (chosen) *chosen = fs.cw;
+  });
+}
+
+gdsw_status gdsw_autotune_mfma(gdsw_ctx* ctx, void* stream, int32_t* chosen, double* ms) {
+  if (gdsw_status s = check_device_ctx(ctx)) return s;
+  Context& c = ctx->c;
+  if (c.solve_mode != SOLVE_INVERSE || c.max_rhs < 2 || !c.d_wm)
+    return fail(ctx, GDSW_EUNSUPPORTED, "the MFMA autotuner needs GDSW_SOLVE_INVERSE and max_rhs > 1");
+  return guarded(ctx, [&]() {
+    hipStream_t st = (hipStream_t)stream;
+    FactorSet& fs = c.L1;
+    KernelTimer* tm = fs.timer;
+    fs.timer = nullptr;
+    const int K = c.max_rhs;
+    auto once = [&]() { gemm_set(fs, c.d_wm, K, K, st); };
+    // FP64: the direct kernel with 512 / 1024 / 2048 summation columns per
+    // item, then the LDS-staged kernel with 256 / 512 / 1024; FP32 and BF16
+    // have one kernel and take the first three
+    const int ncand = fs.prec == P_FP64 ? 6 : 3;
+    const int cw[6] = {512, 1024, 2048, 256, 512, 1024}, lds[6] = {0, 0, 0, 1, 1, 1};
+    double t[6];
+    int best = 0;
+    for (int q = 0; q < ncand; ++q) {
+      fs.gemm_cw_force = cw[q];
+      fs.gemm_lds_force = fs.prec == P_FP64 ? lds[q] : -1;
+      plan_gemm(fs, c.arena, st);
+      t[q] = time_calls(st, 5, once);
+      if (t[q] < t[best]) best = q;
+    }
+    fs.gemm_cw_force = cw[best];
+    fs.gemm_lds_force = fs.prec == P_FP64 ? lds[best] : -1;
+    plan_gemm(fs, c.arena, st);
+    fs.timer = tm;
+    GDSW_HIP(hipMemsetAsync(c.d_wm, 0, std::max<int64_t>(c.n_w, 1) * K * sizeof(double), st));
+    GDSW_HIP(hipStreamSynchronize(st));
+    if (chosen) *chosen = best;
     if (ms)
-      for (int q = 0; q < 3; ++q) ms[q] = t[q];
+      for (int q = 0; q < 6; ++q) ms[q] = q < ncand ? t[q] : 0.0;
   });
 }
 
@@ -807,7 +874,8 @@ gdsw_status gdsw_fgmres_solve_batch(gdsw_batch* batch, const double* const* b_de
         ls0[k] = L->learned_solves;
       }
     std::vector<FgmresResult> r =
-        fgmres_batch(batch->b, b_dev, x_dev, opts->rtol, opts->restart, opts->max_it, (hipStream_t)stream);
+        fgmres_batch(batch->b, b_dev, x_dev, opts->rtol, opts->restart, opts->max_it, (hipStream_t)stream,
+                     opts->use_graph != 0);
     GDSW_HIP(hipStreamSynchronize((hipStream_t)stream));
     const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     for (size_t k = 0; k < r.size(); ++k) {

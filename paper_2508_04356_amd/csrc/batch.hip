@@ -68,7 +68,7 @@ void build_set(Batch& b, BatchSet& S, bool level1, hipStream_t st) {
   for (int f = 0; f < S.count; ++f) {
     const int n = sd[f].n;
     if (S.sym) {  // the same tile runs and slots as the member's own plan
-      symv_items(f, sd[f].np, p, it1, it2);
+      symv_items(f, sd[f].np, p, S.plan.run, it1, it2);
       p += symv_tiles(sd[f].np);
       continue;
     }
@@ -80,6 +80,7 @@ void build_set(Batch& b, BatchSet& S, bool level1, hipStream_t st) {
   }
   DeviceArena& A = b.arena;
   S.d_desc = dupload(A, sd, st);
+  S.plan.xcd = symv_default_xcd(S.prec);
   S.plan.n1 = (int)it1.size();
   S.plan.n2 = (int)it2.size();
   S.plan.d_items1 = dupload(A, it1, st);
@@ -198,7 +199,17 @@ void batch_local_solve(Batch& b, hipStream_t st) {
   }
 }
 
+void batch_drop_graphs(Batch& b) {
+  for (auto& kv : b.graphs)
+    if (kv.second) (void)hipGraphExecDestroy(kv.second);
+  b.graphs.clear();
+  b.graph_V.clear();
+}
+
 void batch_release(Batch& b) {
+  batch_drop_graphs(b);
+  if (b.gstream) (void)hipStreamDestroy(b.gstream);
+  b.gstream = nullptr;
   for (auto& e : b.timer.ev) (void)hipEventDestroy(e);
   b.timer.ev.clear();
   for (hipStream_t l : b.lanes) (void)hipStreamSynchronize(l);

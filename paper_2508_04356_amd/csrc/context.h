@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <memory>
 #include <string>
 #include <tuple>
@@ -153,15 +154,21 @@ struct FactorSet {
     int n1 = 0, n2 = 0;
     int4* d_items1 = nullptr;
     int4* d_items2 = nullptr;
+    int run = 2;   // symmetric tiles: stored tiles per work item (1 or 2)
+    int xcd = 0;   // symmetric tiles: XCD-contiguous work-group order
   };
   std::vector<GemvPlan> gemv;
   int cw = GEMV_CW;                  // columns per partial-product item (512, 1024 or 2048)
+  int sym_run = 2;                   // symmetric tiles per item, and the order (-1: by precision)
+  int sym_xcd = -1;
   GemvDesc* d_desc = nullptr;        // per factor, built once the store and work vector exist
   double* d_partial = nullptr;
   int64_t partial_len = 0;
   GemvPlan gemm;                     // several right-hand sides (all factors)
   int gemm_rb = 0, gemm_cw = 0;      // its rows and summation columns per item
   bool gemm_lds = false;             // FP64: LDS-staged kernel (few matrices)
+  int gemm_cw_force = 0;             // autotuner's choices (0 / -1: by shape)
+  int gemm_lds_force = -1;
   void* d_partial_m = nullptr;       // 32 * rows partial sums per gemm item
   int max_np = 0;                    // BF16 products: right-hand sides as BF16,
   int64_t* d_xpoff = nullptr;        //   xb[32 * xpoff[f] + j * npad[f] + row]
@@ -406,6 +413,12 @@ struct Batch {
   std::vector<hipStream_t> lanes;
   hipEvent_t fork = nullptr;
   std::vector<hipEvent_t> join;
+  // graph replays of the lockstep iteration, one per (basis index, members
+  // in the cycle); dropped when a member's Krylov workspace moves
+  std::map<std::pair<int, std::vector<char>>, hipGraphExec_t> graphs;
+  std::vector<double*> graph_V;
+  int graph_restart = 0;
+  hipStream_t gstream = nullptr;     // capture stream when the caller passes the null stream
 };
 
 // Make every lane wait for the work queued on st so far / make st wait for
@@ -427,7 +440,8 @@ void batch_local_solve(Batch& b, hipStream_t st);
 void batch_release(Batch& b);
 void apply_precond_batch(Batch& b, const double* const* r, double* const* z, hipStream_t st);
 std::vector<FgmresResult> fgmres_batch(Batch& b, const double* const* bvec, double* const* x, double rtol,
-                                       int restart, int max_it, hipStream_t st);
+                                       int restart, int max_it, hipStream_t st, bool use_graph = false);
+void batch_drop_graphs(Batch& b);
 
 // several right-hand sides (solve_multi.hip): blocks of K <= max_rhs
 // interleaved columns (entry (d, j) at x[d * K + j])

@@ -67,7 +67,9 @@ void gemv_set(const FactorSet& fs, double* w, hipStream_t st, int slot = 0, cons
 // row sums (f, I, p0, tiles per row)), packing of full FP64 npad x npad
 // matrices (offsets soff) into tiles at doff (elements), and the product.
 int64_t symv_tiles(int npad);
-void symv_items(int f, int npad, int64_t p0, std::vector<int4>& it1, std::vector<int4>& it2);
+void symv_items(int f, int npad, int64_t p0, int run, std::vector<int4>& it1, std::vector<int4>& it2);
+// default work-group order of a precision (XCD-contiguous for FP32 tiles)
+int symv_default_xcd(int prec);
 void pack_upper(int prec, const double* src, const int64_t* soff, const int32_t* npad, int count, int max_npad,
                 const int64_t* doff, void* dst, hipStream_t st);
 void symv_set(const FactorSet& fs, double* w, hipStream_t st, int slot = 0, const int32_t* want = nullptr);

@@ -522,7 +522,7 @@ void gemm_choose(FactorSet& fs) {
     fs.gemm_rb = MultiShape<float>::RB;
   } else if (fs.prec == P_BF16) {
     fs.gemm_rb = MultiShape<uint16_t>::RB;
-  } else if (items(MultiShape<double>::RB, GEMM_CW) >= 2048) {
+  } else if (fs.gemm_lds_force == 0 || (fs.gemm_lds_force < 0 && items(MultiShape<double>::RB, GEMM_CW) >= 2048)) {
     fs.gemm_rb = MultiShape<double>::RB;  // many matrices: direct fragments, long rows per wave
   } else {
     // few matrices (a coarse level): 128-row LDS tiles and narrower
@@ -531,6 +531,7 @@ void gemm_choose(FactorSet& fs) {
     fs.gemm_rb = DL_RB;
     while (fs.gemm_cw > 256 && items(DL_RB, fs.gemm_cw) < 2048) fs.gemm_cw /= 2;
   }
+  if (fs.gemm_cw_force > 0) fs.gemm_cw = fs.gemm_cw_force;
 }
 
 void gemm_set(const FactorSet& fs, double* w, int64_t ldk, int nrhs, hipStream_t st) {

@@ -8,16 +8,16 @@
 // U x_I + U^T x_I = M_II x_I.  Pieces that hold no needed entry are not read
 // (rows or columns past n in the last tile row and column, the part of a
 // diagonal tile below the diagonal): the tiles fetched are the upper
-// triangle, not the padded square.  A work-group reads a run of two
-// tiles of one block row (each a contiguous 32 KB read for FP64) and writes
-// one row partial for the run (block row I) and one column partial per
-// off-diagonal tile (block rows J); a second launch sums them per block row
-// in a fixed order (the runs of row I from the diagonal on, then the
-// transposed tiles (0, I), (1, I), ...), so results are repeatable bit for
-// bit.  Tried and measured slower at 16^3 on MI355X: runs of 1, 3 or 4 tiles
-// (also in FP32 and BF16), staging tiles in LDS, a gap between stored tiles
-// (off the 32 KB stride), and fewer resident work-groups that each walk
-// many items.
+// triangle, not the padded square.  A work-group reads a run of one or two
+// tiles of one block row (each a contiguous 32 KB read for FP64; two by
+// default, gdsw_autotune may pick one) and writes one row partial for the
+// run (block row I) and one column partial per off-diagonal tile (block rows
+// J); a second launch sums them per block row in a fixed order (the runs of
+// row I from the diagonal on, then the transposed tiles (0, I), (1, I), ...),
+// so results are repeatable bit for bit.  Tried and measured slower at 16^3
+// on MI355X: runs of 3 or 4 tiles (also in FP32 and BF16), staging tiles in
+// LDS, a gap between stored tiles (off the 32 KB stride), and fewer resident
+// work-groups that each walk many items.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -45,10 +45,6 @@ __host__ __device__ inline int64_t tile_index(int I, int J, int nt) {
 // small LDS reductions in a fixed order.  Rows and columns past n meet zero
 // vector entries (the padded inverse is block-diagonal, so those tile
 // entries only feed outputs that are never read).
-#ifndef GDSW_SYMV_RUN
-#define GDSW_SYMV_RUN 2
-#endif
-constexpr int SYMV_RUN = GDSW_SYMV_RUN;
 #ifndef GDSW_SYMV_NT
 #define GDSW_SYMV_NT 1  // non-temporal tile loads
 #endif
@@ -69,10 +65,11 @@ __device__ inline void tile_load16(__amdgpu_buffer_rsrc_t r, uint32_t off, A (&o
 
 // NC > 1: the tile is applied to NC vectors (x + k vs, k < NC) while it sits
 // in registers; the partial slots hold NC blocks of 64 per item slot.
-template <typename T, int NC>
+template <typename T, int NC, int SYMV_RUN>
 __global__ __launch_bounds__(256) void symv_part_kernel(const GemvDesc* __restrict__ desc,
                                                         const int4* __restrict__ items, double* __restrict__ prow,
-                                                        double* __restrict__ pcol, const int32_t* __restrict__ want) {
+                                                        double* __restrict__ pcol, const int32_t* __restrict__ want,
+                                                        int xcd) {
   using Acc = typename VecW<T>::acc;
   constexpr int E = VecW<T>::W;        // rows per 16-byte piece
   constexpr int PPC = ST / E;          // pieces per column
@@ -84,12 +81,12 @@ __global__ __launch_bounds__(256) void symv_part_kernel(const GemvDesc* __restri
   static_assert(NC % KB == 0, "rounds of equal size");
   __shared__ Acc rred[KB][CPT][ST];    // row partials per column group
   __shared__ Acc cred[KB][ST][PPC + 1];  // column partials per row group
-  // work-groups are dealt to the 8 XCDs in turn; for FP32 tiles XCD x takes
+  // work-groups are dealt to the 8 XCDs in turn; with xcd set XCD x takes
   // the x-th contiguous eighth of the items instead (a permutation of the
-  // grid: 1032 -> 999 us at 24^3 on MI355X, while FP64 lost 1.5% and BF16
-  // did not change)
+  // grid: 1032 -> 999 us for FP32 tiles at 24^3 on MI355X, while FP64 lost
+  // 1.5% and BF16 did not change; the default is on for FP32 only)
   int it = blockIdx.x;
-  if constexpr (sizeof(T) == 4) {
+  if (xcd) {
     const int nb = gridDim.x, x8 = blockIdx.x % 8, q8 = blockIdx.x / 8, per = nb / 8, rem = nb % 8;
     it = (x8 < rem ? x8 * (per + 1) : rem * (per + 1) + (x8 - rem) * per) + q8;
   }
@@ -234,19 +231,20 @@ template <int NC>
 __global__ __launch_bounds__(256) void symv_sum_kernel(const GemvDesc* __restrict__ desc,
                                                        const int4* __restrict__ items,
                                                        const double* __restrict__ prow,
-                                                       const double* __restrict__ pcol, const int32_t* __restrict__ want) {
+                                                       const double* __restrict__ pcol, const int32_t* __restrict__ want,
+                                                       int run) {
   static_assert(NC <= 4, "one wave per vector for the last step");
   __shared__ double red[4][NC][ST];
   const int4 item = items[blockIdx.x];
   const int g = item.x, I = item.y, P0 = item.z, nt = item.w;
   if (want && !want[g]) return;  // uniform over the work-group
   const int l = threadIdx.x % ST, w = threadIdx.x / ST;
-  const int na = (nt - I + SYMV_RUN - 1) / SYMV_RUN;  // runs of row I
+  const int na = (nt - I + run - 1) / run;  // runs of row I
   double s[NC];
 #pragma unroll
   for (int k = 0; k < NC; ++k) s[k] = 0.0;
   for (int q = w; q < na + I; q += 4) {
-    const int64_t slot = q < na ? P0 + tile_index(I, I + SYMV_RUN * q, nt) : P0 + tile_index(q - na, I, nt);
+    const int64_t slot = q < na ? P0 + tile_index(I, I + run * q, nt) : P0 + tile_index(q - na, I, nt);
     const double* src = (q < na ? prow : pcol) + slot * NC * ST + l;
 #pragma unroll
     for (int k = 0; k < NC; ++k) s[k] += src[k * ST];
@@ -303,8 +301,13 @@ void symv_launch(const GemvDesc* desc, const FactorSet::GemvPlan& G, double* par
   if (G.n1 == 0) return;
   double* prow = partial;
   double* pcol = partial + partial_len / 2;
-  timed_launch(tm, bytes, symv_part_kernel<T, NC>, dim3(G.n1), dim3(256), st, desc, G.d_items1, prow, pcol, want);
-  symv_sum_kernel<NC><<<G.n2, 256, 0, st>>>(desc, G.d_items2, prow, pcol, want);
+  if (G.run == 1)
+    timed_launch(tm, bytes, symv_part_kernel<T, NC, 1>, dim3(G.n1), dim3(256), st, desc, G.d_items1, prow, pcol,
+                 want, G.xcd);
+  else
+    timed_launch(tm, bytes, symv_part_kernel<T, NC, 2>, dim3(G.n1), dim3(256), st, desc, G.d_items1, prow, pcol,
+                 want, G.xcd);
+  symv_sum_kernel<NC><<<G.n2, 256, 0, st>>>(desc, G.d_items2, prow, pcol, want, G.run);
 }
 
 }  // namespace
@@ -314,13 +317,16 @@ int64_t symv_tiles(int npad) {
   return nt * (nt + 1) / 2;
 }
 
-void symv_items(int f, int npad, int64_t p0, std::vector<int4>& it1, std::vector<int4>& it2) {
+void symv_items(int f, int npad, int64_t p0, int run, std::vector<int4>& it1, std::vector<int4>& it2) {
+  if (run != 1 && run != 2) throw StatusError{1, "symmetric tile runs of 1 or 2 tiles"};
   const int nt = npad / ST;
   for (int I = 0; I < nt; ++I) {
-    for (int J = I; J < nt; J += SYMV_RUN) it1.push_back(make_int4(f, I, J, (int)(p0 + tile_index(I, J, nt))));
+    for (int J = I; J < nt; J += run) it1.push_back(make_int4(f, I, J, (int)(p0 + tile_index(I, J, nt))));
     it2.push_back(make_int4(f, I, (int)p0, nt));
   }
 }
+
+int symv_default_xcd(int prec) { return prec == P_FP32 ? 1 : 0; }
 
 void pack_upper(int prec, const double* src, const int64_t* soff, const int32_t* npad, int count, int max_npad,
                 const int64_t* doff, void* dst, hipStream_t st) {

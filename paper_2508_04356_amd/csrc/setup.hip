@@ -181,9 +181,11 @@ void plan_schedule(FactorSet& fs, int phases, DeviceArena& A, hipStream_t st, in
     // stay the global tile indices
     std::vector<int4> it1, it2;
     for (int f = 0; f < fs.count; ++f)
-      if (!include || (*include)[f]) symv_items(f, fs.npad[f], fs.off[f] / (64 * 64), it1, it2);
+      if (!include || (*include)[f]) symv_items(f, fs.npad[f], fs.off[f] / (64 * 64), fs.sym_run, it1, it2);
     if ((int)fs.gemv.size() <= slot) fs.gemv.resize(slot + 1);
     FactorSet::GemvPlan& G = fs.gemv[slot];
+    G.run = fs.sym_run;
+    G.xcd = fs.sym_xcd >= 0 ? fs.sym_xcd : symv_default_xcd(fs.prec);
     if (G.d_items1) A.free(G.d_items1);
     if (G.d_items2) A.free(G.d_items2);
     G.n1 = (int)it1.size();

@@ -448,7 +448,7 @@ FgmresResult fgmres(Context& ctx, const double* b, double* x, double rtol, int r
 // local and coarse solves share one launch pair per level, and the host
 // reads every member's residual estimate after one synchronisation.
 std::vector<FgmresResult> fgmres_batch(Batch& bt, const double* const* bvec, double* const* xv, double rtol,
-                                       int restart, int max_it, hipStream_t st) {
+                                       int restart, int max_it, hipStream_t st, bool use_graph) {
   const int K = (int)bt.m.size();
   std::vector<FgmresResult> res(K);
   std::vector<double> bnorm(K, 0.0);
@@ -456,6 +456,30 @@ std::vector<FgmresResult> fgmres_batch(Batch& bt, const double* const* bvec, dou
   std::vector<int> kc(K, 0), cycles(K, 0);
   double* hp = bt.h_pinned;
   for (int k = 0; k < K; ++k) ensure_workspace(*bt.m[k], restart);
+  // Graph mode: the iteration body for basis index j and the set of members
+  // in the cycle (the forks onto the lanes, every member's kernels, the
+  // merged products and the read-back copies) is captured once and replayed
+  // whenever the same (j, set) recurs, in later cycles and solves.  The
+  // merged products read their member flags from the device, uploaded by
+  // batch_select outside the graph whenever the set changes.  Members with a
+  // learned interior solve read back counts inside the iteration and keep
+  // the batch eager.
+  bool graph = use_graph;
+  for (int k = 0; k < K; ++k) graph = graph && !batch_learned(*bt.m[k]);
+  if (graph) {
+    std::vector<double*> Vs(K);
+    for (int k = 0; k < K; ++k) Vs[k] = bt.m[k]->d_V;
+    if (Vs != bt.graph_V || bt.graph_restart != restart) {
+      batch_drop_graphs(bt);
+      bt.graph_V = Vs;
+      bt.graph_restart = restart;
+    }
+    if (st == nullptr) {
+      if (!bt.gstream) GDSW_HIP(hipStreamCreateWithFlags(&bt.gstream, hipStreamNonBlocking));
+      GDSW_HIP(hipStreamSynchronize(nullptr));  // the caller's earlier work on the default stream
+      st = bt.gstream;
+    }
+  }
   batch_fork(bt, st);
   for (int k = 0; k < K; ++k) {
     Context& c = *bt.m[k];
@@ -512,7 +536,7 @@ std::vector<FgmresResult> fgmres_batch(Batch& bt, const double* const* bvec, dou
     }
     if (running == 0) break;
     batch_select(bt, in_cycle, st);
-    for (int j = 0; j < restart && running > 0; ++j) {
+    auto body = [&](int j) {
       batch_fork(bt, st);
       for (int k = 0; k < K; ++k) {
         if (!in_cycle[k]) continue;
@@ -541,6 +565,25 @@ std::vector<FgmresResult> fgmres_batch(Batch& bt, const double* const* bvec, dou
         GDSW_HIP(hipMemcpyAsync(hp + 2 * k, c.d_scal + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, ls));
       }
       batch_join(bt, st);
+    };
+    for (int j = 0; j < restart && running > 0; ++j) {
+      if (graph) {
+        hipGraphExec_t& e = bt.graphs[std::make_pair(j, in_cycle)];
+        if (!e) {
+          const bool on = bt.timer.on;
+          bt.timer.on = false;  // no event nodes in the graph
+          hipGraph_t g = nullptr;
+          GDSW_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+          body(j);
+          GDSW_HIP(hipStreamEndCapture(st, &g));
+          bt.timer.on = on;
+          GDSW_HIP(hipGraphInstantiate(&e, g, nullptr, nullptr, 0));
+          GDSW_HIP(hipGraphDestroy(g));
+        }
+        GDSW_HIP(hipGraphLaunch(e, st));
+      } else {
+        body(j);
+      }
       GDSW_HIP(hipStreamSynchronize(st));
       bool changed = false;
       for (int k = 0; k < K; ++k) {

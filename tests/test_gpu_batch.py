@@ -70,3 +70,31 @@ def test_lockstep_batch_fgmres_is_each_members_fgmres(batch):
         assert infos[k].iterations == info1.iterations, k
         assert infos[k].true_rel_res <= 1e-8
         assert torch.equal(xs[k], x1), k
+
+
+def test_lockstep_batch_graph_replays_match_eager(batch):
+    """Graph mode: each lockstep iteration (every member's kernels on the
+    stream lanes, the merged products, the read-backs) is captured once per
+    (basis index, members still in the cycle) and replayed.  Three graph
+    solves, with eager work in between, reproduce the eager lockstep solve
+    bitwise; members drop out at different iterations, so several member
+    sets are captured."""
+    bs = []
+    for m in batch.members:
+        b = torch.zeros(m.n_free, dtype=torch.float64, device=DEV)
+        m.rhs(b)
+        bs.append(b)
+    x0 = [torch.zeros_like(b) for b in bs]
+    inf0 = batch.fgmres(bs, x0, rtol=1e-8)
+    rs = [torch.as_tensor(random_vector(m.n_free, seed=40 + k), device=DEV) for k, m in enumerate(batch.members)]
+    zs = [torch.zeros_like(r) for r in rs]
+    for rep in range(3):
+        xg = [torch.zeros_like(b) for b in bs]
+        infg = batch.fgmres(bs, xg, rtol=1e-8, use_graph=True)
+        torch.cuda.synchronize()
+        print(f"[gpu] batch graph replay {rep}: its {[i.iterations for i in infg]}", flush=True)
+        for k in range(len(bs)):
+            assert infg[k].iterations == inf0[k].iterations, k
+            assert torch.equal(xg[k], x0[k]), k
+        batch.apply(rs, zs)  # eager work between replays
+        torch.cuda.synchronize()

@@ -53,6 +53,12 @@ def solver16():
 
 
 def test_gradients_match_fp64_oracle(solver16):
+    """Loss and every gradient entry against the FP64 oracle network with the
+    GPU's storage formats: the working weights (BF16 values), BF16 inputs and
+    BF16 activations after every layer.  What is left is the GPU's FP32
+    accumulation (and the odd activation that FP32 rounds to the other BF16
+    neighbour), so each entry of dW and db must agree to 1e-4 of its layer's
+    largest entry."""
     s = solver16
     g = s.learned.grid
     rng = np.random.default_rng(0)
@@ -61,17 +67,20 @@ def test_gradients_match_fp64_oracle(solver16):
     T = rng.standard_normal((B, 4, g, g, g)).astype(np.float32)
     loss, grads = s.learned_loss_grad(X, T)
     Wf = s.learned_weights(which=1)
+    assert np.array_equal(bf16(Wf), Wf)  # the working copy holds BF16 values
     W, b = split(Wf)
     net = ConvNet(CH, weights=(W, b))
-    lo, gW, gb, _ = net.loss_and_grads(X.astype(np.float64), T.astype(np.float64), pressure_mask(g)[None])
+    lo, gW, gb, _ = net.loss_and_grads(X.astype(np.float64), T.astype(np.float64), pressure_mask(g)[None],
+                                       act_round=lambda a: bf16(a).astype(np.float64))
     Gg, Gb = split(grads)
     print(f"[gpu] loss gpu {loss:.6e} oracle {lo:.6e}", flush=True)
-    assert abs(loss - lo) / lo < 2e-2
+    assert abs(loss - lo) / lo < 1e-5
     for l in range(4):
-        ew = np.linalg.norm(Gg[l] - gW[l]) / np.linalg.norm(gW[l])
-        eb = np.linalg.norm(Gb[l] - gb[l]) / max(np.linalg.norm(gb[l]), 1e-30)
-        print(f"[gpu] layer {l}: dW rel err {ew:.2e}, db rel err {eb:.2e}", flush=True)
-        assert ew < 5e-2 and eb < 5e-2   # BF16 activations: errors grow toward layer 0
+        ew = np.abs(Gg[l] - gW[l]).max() / np.abs(gW[l]).max()
+        eb = np.abs(Gb[l] - gb[l]).max() / max(np.abs(gb[l]).max(), 1e-30)
+        print(f"[gpu] layer {l}: dW max entry err {ew:.2e}, db max entry err {eb:.2e} (of the layer's largest)",
+              flush=True)
+        assert ew < 1e-4 and eb < 1e-4
 
 
 def test_training_and_ablation(solver16):
