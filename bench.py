@@ -593,7 +593,9 @@ def main():
                           "per tile)",
              "triangular": "trsv_step_kernel (blocked forward/backward solves of the level-1 factors)",
              "block": "symv_part_kernel<double, 3> (upper 64x64 tiles of the velocity-block inverses L_i^-1, three "
-                      "component vectors per tile; two launches per apply)"}[args.local_solve]
+                      "component vectors per tile; " +
+                      ("one launch per apply: W_i = K_i^-1 B_i^T is kept for the last step)" if round(per_apply) == 1
+                       else "two launches per apply)")}[args.local_solve]
     log(f"[bench] apply {t_apply_ms:.3f} ms; phases ms gather/restrict {ph[0]:.3f} solve {ph[1]:.3f}+{ph[2]:.3f} "
         f"scatter {ph[3]:.3f}; dominant kernel {k_launches} launches in the timed solves, {k_avg_us:.1f} us avg, "
         f"{k_bytes:.3e} B each -> {achieved:.0f} GB/s")
