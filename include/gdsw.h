@@ -329,7 +329,8 @@ gdsw_status gdsw_apply_precond(gdsw_ctx* ctx, const double* r_dev, double* z_dev
  * stream capture, tight serving loops, harnesses that forbid hipMalloc):
  * z = M^-1 r exactly as gdsw_apply_precond computes it (same kernels and
  * summation orders, so bitwise the same result), column by column, with the
- * partial sums of the inverse products in a static device array that the
+ * partial sums of the inverse products (block mode: of the velocity-block,
+ * Schur complement and coarse products) in a static device array that the
  * library holds once per device for the whole process (128 MiB; its device
  * address is looked up in gdsw_setup) instead of the context's buffer.
  * Calls no allocating routine.  Every call on a device shares that array and

@@ -57,6 +57,10 @@ WORKLOADS: Dict[str, Workload] = {
     "P16": Workload("P16", n=16, m=4, local_algebraic=1, pressure="p1disc", coarse="gdsw*"),
     # Table 1, first row: 32^3 hexahedra (954,947 DOFs), 8^3 subdomains, 5,573 coarse DOFs
     "P32": Workload("P32", n=32, m=8, local_algebraic=1, pressure="p1disc", coarse="gdsw*"),
+    # a long unrestarted three-level run: 12^3 mesh, 6^3 subdomains in 3^3 subregions of 2^3, the
+    # algebraic readings on both levels (about 170 iterations)
+    "L3long": Workload("L3long", n=12, m=6, levels=3, group=2, viscosity=0.5, inflow=2.0, restart=200,
+                       local_algebraic=1, level2_layer=1),
 }
 
 

@@ -187,19 +187,28 @@ void wp_sub(int prec, const void* W, const WItem* items, int n_items, double* w,
   GDSW_HIP(hipGetLastError());
 }
 
-void block_local_solve(Context& ctx, hipStream_t st) {
+void block_local_solve(Context& ctx, hipStream_t st, double* part) {
   const BlockSolve& b = ctx.blk;
   FactorSet& L = ctx.L1;
   if (L.count == 0) return;
+  // partial sums: the sets' own buffers, or the caller's (the sets run one
+  // after the other on st, so they may share it)
+  double* pl = part ? part : L.d_partial;
+  KernelTimer* tm = part ? nullptr : L.timer;
   // U1 = L^-1 F (three vectors per matrix, in place in the work vector)
-  symv_desc_launch(L.prec, L.d_desc, L.gemv[0], L.d_partial, L.partial_len, st, nullptr, L.timer,
-                   (double)L.alg_bytes, 3);
+  symv_desc_launch(L.prec, L.d_desc, L.gemv[0], pl, L.partial_len, st, nullptr, tm, (double)L.alg_bytes, 3);
   // t = B U1 - g in the pressure segments
   // pressure rows hold hundreds of entries: a wave per row
   rowprod_kernel<64, 0><<<(unsigned)((b.n_prow * 64 + 255) / 256), 256, 0, st>>>(
       b.n_prow, b.d_prow_pos, b.d_bm_ptr, b.d_bm_pos, b.d_bm_val, ctx.d_w, nullptr);
   // p = S^-1 t (and, with two levels, the coarse solve in the same launch)
-  local_solve_set(ctx.LP, ctx.d_w, st);
+  if (part) {
+    const FactorSet& P = ctx.LP;
+    if (P.count > 0 && !P.gemv.empty())
+      symv_desc_launch(P.prec, P.d_desc, P.gemv[0], part, P.partial_len, st, nullptr, nullptr, 0.0);
+  } else {
+    local_solve_set(ctx.LP, ctx.d_w, st);
+  }
   if (b.use_w) {  // u = U1 - W p
     wp_sub(L.prec, b.d_W, b.d_witems, b.n_witems, ctx.d_w, nullptr, 0.0, st);
     return;
@@ -208,8 +217,7 @@ void block_local_solve(Context& ctx, hipStream_t st) {
   // velocity rows hold up to a few dozen: eight lanes per row
   rowprod_kernel<8, 1><<<(unsigned)((b.n_vrow * 8 + 255) / 256), 256, 0, st>>>(
       b.n_vrow, b.d_vrow_pos, b.d_bt_ptr, b.d_bt_pos, b.d_bt_val, ctx.d_w, b.d_w2);
-  symv_desc_launch(L.prec, b.d_desc2, L.gemv[0], L.d_partial, L.partial_len, st, nullptr, L.timer,
-                   (double)L.alg_bytes, 3);
+  symv_desc_launch(L.prec, b.d_desc2, L.gemv[0], pl, L.partial_len, st, nullptr, tm, (double)L.alg_bytes, 3);
   GDSW_HIP(hipGetLastError());
 }
 

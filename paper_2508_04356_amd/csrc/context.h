@@ -334,6 +334,7 @@ struct Context {
   double* d_t1 = nullptr;          // n-vectors
   double* d_t2 = nullptr;
   double* h_pinned = nullptr;      // pinned host scalars
+  double* d_pinned = nullptr;      // their device view (kernels write the FGMRES records there)
   hipEvent_t it_ev[2] = {nullptr, nullptr};  // end of FGMRES iteration j, slot j % 2
   int64_t ldv = 0;
   int n_part_blocks = 0;
@@ -361,7 +362,8 @@ void spmv(Context& ctx, const double* x, double* y, hipStream_t st);
 // per-device scratch array instead of the context's buffer (noalloc.hip)
 void apply_precond_noalloc(Context& ctx, const double* r, double* z, hipStream_t st);
 // block local solve of every level-1 subdomain in the work vector (block.hip)
-void block_local_solve(Context& ctx, hipStream_t st);
+// part (or null: the sets' own buffers): partial sums for every product
+void block_local_solve(Context& ctx, hipStream_t st, double* part = nullptr);
 int wp_rows_per_item(int prec);
 void wp_sub(int prec, const void* W, const WItem* items, int n_items, double* w, KernelTimer* tm, double bytes,
             hipStream_t st);

@@ -61,11 +61,13 @@ uint64_t noalloc_scratch_bytes() { return SCRATCH_BYTES; }
 static int64_t partial_need(const FactorSet& fs) { return fs.count == 0 ? 0 : fs.partial_len; }
 
 void apply_precond_noalloc(Context& ctx, const double* r, double* z, hipStream_t st) {
-  if (ctx.solve_mode != SOLVE_INVERSE && ctx.solve_mode != SOLVE_SYM)
-    throw StatusError{6, "the no-allocation apply covers GDSW_SOLVE_INVERSE and GDSW_SOLVE_SYMMETRIC"};
+  if (ctx.solve_mode != SOLVE_INVERSE && ctx.solve_mode != SOLVE_SYM && ctx.solve_mode != SOLVE_BLOCK)
+    throw StatusError{6, "the no-allocation apply covers the inverse, symmetric and block local solves"};
   if (ctx.local_solver != 0)
     throw StatusError{6, "the no-allocation apply covers the exact local solves (local solver 0)"};
-  const int64_t need = std::max(partial_need(ctx.L1), partial_need(ctx.HI));
+  const int64_t need =
+      std::max(std::max(partial_need(ctx.L1), partial_need(ctx.HI)),
+               ctx.solve_mode == SOLVE_BLOCK ? partial_need(ctx.LP) : (int64_t)0);
   if ((uint64_t)need * sizeof(double) > SCRATCH_BYTES)
     throw StatusError{1, "the no-allocation apply needs " + std::to_string((uint64_t)need * sizeof(double)) +
                              " bytes of scratch; the static buffer holds " + std::to_string(SCRATCH_BYTES)};
@@ -73,8 +75,10 @@ void apply_precond_noalloc(Context& ctx, const double* r, double* z, hipStream_t
   // so the array needs no clearing between calls
   double* part = noalloc_scratch(ctx.device);
   apply_pre(ctx, r, st);
-  // the two sets run one after the other on `st`, so they share the scratch
+  // the sets run one after the other on `st`, so they share the scratch
+  if (ctx.solve_mode == SOLVE_BLOCK) block_local_solve(ctx, st, part);
   for (const FactorSet* fs : {&ctx.L1, &ctx.HI}) {
+    if (fs == &ctx.L1 && ctx.solve_mode == SOLVE_BLOCK) continue;
     if (fs->count == 0 || fs->gemv.empty()) continue;
     if (!fs->d_desc) throw StatusError{5, "inverse set used before its descriptors were built"};
     if (fs->mode == SOLVE_INVERSE)

@@ -97,7 +97,7 @@ __global__ __launch_bounds__(256) void arnoldi_scale_kernel(int j, int restart, 
                                                             double* __restrict__ g, double* __restrict__ scal,
                                                             const double* __restrict__ part, int nblocks,
                                                             int64_t n, const double* __restrict__ w,
-                                                            double* __restrict__ v) {
+                                                            double* __restrict__ v, double* __restrict__ host_out) {
   __shared__ double cl[ARN_LDS + 2], cs_l[ARN_LDS], sn_l[ARN_LDS];
   __shared__ double ww;
   if (threadIdx.x < 64) {
@@ -138,6 +138,10 @@ __global__ __launch_bounds__(256) void arnoldi_scale_kernel(int j, int restart, 
     g[j + 1] = -sj * gj;
     g[j] = c * gj;
     scal[2] = fabs(g[j + 1]) / scal[5];
+    if (host_out) {  // the iteration's record straight into pinned host memory
+      host_out[0] = scal[2];
+      host_out[1] = hn;
+    }
   }
   __syncthreads();
   const int ldh = restart + 1;
@@ -147,16 +151,20 @@ __global__ __launch_bounds__(256) void arnoldi_scale_kernel(int j, int restart, 
 // column j of the Arnoldi process after the projections (part: the
 // partial blocks of ||w||^2): H, rotations, g, residual estimate, and the
 // next basis vector
-void arnoldi_step(int j, int restart, const double* h1, const double* h2, double* H, double* cs, double* sn,
+// host_out (device view of pinned host memory, or null): the kernel writes
+// the residual estimate and ||w|| there itself, so no copy follows
+bool arnoldi_step(int j, int restart, const double* h1, const double* h2, double* H, double* cs, double* sn,
                   double* g, double* scal, const double* part, int nblocks, int64_t n, const double* w, double* v,
-                  hipStream_t st) {
+                  hipStream_t st, double* host_out = nullptr) {
   if (restart <= ARN_LDS) {
-    arnoldi_scale_kernel<<<grid_n(n), 256, 0, st>>>(j, restart, h1, h2, H, cs, sn, g, scal, part, nblocks, n, w, v);
-  } else {
-    cols_dot_finish(part, nblocks, 1, scal + 4, st);
-    arnoldi_finish_kernel<<<1, 1, 0, st>>>(j, restart, h1, h2, H, cs, sn, g, scal);
-    scale_div_kernel<<<grid_n(n), 256, 0, st>>>(n, w, scal, 3, v);
+    arnoldi_scale_kernel<<<grid_n(n), 256, 0, st>>>(j, restart, h1, h2, H, cs, sn, g, scal, part, nblocks, n, w, v,
+                                                    host_out);
+    return host_out != nullptr;
   }
+  cols_dot_finish(part, nblocks, 1, scal + 4, st);
+  arnoldi_finish_kernel<<<1, 1, 0, st>>>(j, restart, h1, h2, H, cs, sn, g, scal);
+  scale_div_kernel<<<grid_n(n), 256, 0, st>>>(n, w, scal, 3, v);
+  return false;
 }
 
 // back substitution y = H[:k,:k]^-1 g[:k] into y
@@ -201,7 +209,10 @@ void ensure_workspace(Context& ctx, int restart) {
   ctx.d_scal = dalloc<double>(A, 16);
   ctx.d_t1 = dalloc<double>(A, ctx.ldv);
   ctx.d_t2 = dalloc<double>(A, ctx.ldv);
-  if (!ctx.h_pinned) GDSW_HIP(hipHostMalloc((void**)&ctx.h_pinned, 16 * sizeof(double), hipHostMallocDefault));
+  if (!ctx.h_pinned) {
+    GDSW_HIP(hipHostMalloc((void**)&ctx.h_pinned, 16 * sizeof(double), hipHostMallocDefault));
+    GDSW_HIP(hipHostGetDevicePointer((void**)&ctx.d_pinned, ctx.h_pinned, 0));
+  }
   for (hipEvent_t& e : ctx.it_ev)
     if (!e) GDSW_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 }
@@ -357,9 +368,10 @@ FgmresResult fgmres(Context& ctx, const double* b, double* x, double rtol, int r
     cols_dot(V, ldv, j + 1, w, n, ctx.d_part, nb, ctx.d_hv, st);
     sub_dots(V, ldv, j + 1, ctx.d_hv, w, n, ctx.d_part, nb, ctx.d_hv + restart + 1, false, st);
     sub_dots(V, ldv, j + 1, ctx.d_hv + restart + 1, w, n, ctx.d_part, nb, nullptr, true, st);
-    arnoldi_step(j, restart, ctx.d_hv, ctx.d_hv + restart + 1, ctx.d_H, ctx.d_cs, ctx.d_sn, ctx.d_g, S, ctx.d_part,
-                 nb, n, w, V + (int64_t)(j + 1) * ldv, st);
-    GDSW_HIP(hipMemcpyAsync(ctx.h_pinned + 10 + 2 * (j & 1), S + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (!arnoldi_step(j, restart, ctx.d_hv, ctx.d_hv + restart + 1, ctx.d_H, ctx.d_cs, ctx.d_sn, ctx.d_g, S,
+                      ctx.d_part, nb, n, w, V + (int64_t)(j + 1) * ldv, st, ctx.d_pinned + 10 + 2 * (j & 1)))
+      GDSW_HIP(hipMemcpyAsync(ctx.h_pinned + 10 + 2 * (j & 1), S + 2, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                              st));
   };
   auto launch = [&](int j) {
     if (graph) {

@@ -27,7 +27,7 @@ def _pair(s, seed, nrhs=1):
     return z0, z1
 
 
-@pytest.mark.parametrize("solve", ["symmetric", "inverse"])
+@pytest.mark.parametrize("solve", ["block", "symmetric", "inverse"])
 @pytest.mark.parametrize("levels", [2, 3])
 def test_noalloc_matches_apply(solve, levels):
     big = dict(n=12, m=3) if levels == 2 else dict(n=12, m=6, levels=3, group=3)
@@ -43,6 +43,12 @@ def test_noalloc_matches_apply(solve, levels):
     # several columns, one at a time through the same array
     z0, z1 = _pair(b, 4, nrhs=3)
     assert torch.equal(z0, z1)
+    if solve == "block":  # the paper's pressure element: the two-pass block form
+        c = G.Solver(6, 3, local_algebraic=1, pressure="p1disc", coarse="gdsw*", local_solve="block")
+        for s, seed in [(c, 5), (b, 6)]:
+            z0, z1 = _pair(s, seed)
+            assert torch.equal(z0, z1), float((z0 - z1).abs().max())
+        c.close()
     a.close()
     b.close()
 
