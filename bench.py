@@ -484,6 +484,8 @@ def main():
     ap.add_argument("--learned", action="store_true",
                     help="also train the conv-net local solve (interior subdomains) and time FGMRES with it")
     ap.add_argument("--applies", type=int, default=50)
+    ap.add_argument("--autotune", action="store_true",
+                    help="run gdsw_autotune on the level-1 product after setup (launch shape picked on this GPU)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
                     help="C2: skip the FP32 / BF16 / learned variants timed beside plain FP64")
@@ -538,6 +540,11 @@ def main():
     sz = s.sizes()
     n = sz.n_free
     log(f"[bench] setup {t_setup:.2f} s; n_free={n} Nc={sz.n_coarse} device bytes={sz.device_bytes / 1e9:.2f} GB")
+    tuned = None
+    if args.autotune:
+        code, ms = s.autotune()
+        tuned = {"chosen": code, "ms": ms}
+        log(f"[bench] autotune: chosen {code}, candidate ms {['%.4f' % t for t in ms]}")
 
     b = torch.zeros(n, dtype=torch.float64, device=dev)
     s.rhs(b)
@@ -628,10 +635,12 @@ def main():
         "setup_s": t_setup,
         "local_solve": args.local_solve,
         "graph": bool(args.graph),
+        "autotune": tuned,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": (measured_traffic(args.local_solve, round(per_apply))
-                                 if args.workload == "C2" and not alg and prec == "fp64" else None),
+                                 if args.workload == "C2" and not alg and prec == "fp64" and not args.autotune
+                                 else None),
                      "kernel": kname,
                      "bytes_per_launch": k_bytes, "launches_timed": k_launches,
                      "launches_per_apply": per_apply, "avg_launch_us": k_avg_us, "timed_in": timed_in,

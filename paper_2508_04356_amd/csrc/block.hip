@@ -17,6 +17,7 @@
 
 #include "context.h"
 #include "kernels.h"
+#include "kernels_ops.h"
 #include "vec16.h"
 
 namespace gdsw {
@@ -72,11 +73,11 @@ __global__ void copy_blocks_kernel(const double* __restrict__ src, const int64_t
 // mode 0: w[row_pos[r]] = sum - w[row_pos[r]]   (t = B U1 - g, pressure rows)
 // mode 1: out[row_pos[r]] = sum                 (B^T p, velocity rows)
 template <int LPR, int MODE>
-__global__ __launch_bounds__(256) void rowprod_kernel(int64_t nrows, const int32_t* __restrict__ row_pos,
-                                                      const int64_t* __restrict__ ptr, const int32_t* __restrict__ pos,
-                                                      const double* __restrict__ val, double* __restrict__ w,
-                                                      double* __restrict__ out) {
-  const int64_t r = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / LPR;
+__device__ inline void rowprod_rows(int64_t block, int64_t nrows, const int32_t* __restrict__ row_pos,
+                                    const int64_t* __restrict__ ptr, const int32_t* __restrict__ pos,
+                                    const double* __restrict__ val, double* __restrict__ w,
+                                    double* __restrict__ out) {
+  const int64_t r = (block * (int64_t)blockDim.x + threadIdx.x) / LPR;
   const int l = threadIdx.x % LPR;
   const bool live = r < nrows;  // uniform over the row's lanes
   double s = 0.0;
@@ -90,6 +91,36 @@ __global__ __launch_bounds__(256) void rowprod_kernel(int64_t nrows, const int32
     else
       out[row_pos[r]] = s;
   }
+}
+
+template <int LPR, int MODE>
+__global__ __launch_bounds__(256) void rowprod_kernel(int64_t nrows, const int32_t* __restrict__ row_pos,
+                                                      const int64_t* __restrict__ ptr, const int32_t* __restrict__ pos,
+                                                      const double* __restrict__ val, double* __restrict__ w,
+                                                      double* __restrict__ out) {
+  rowprod_rows<LPR, MODE>(blockIdx.x, nrows, row_pos, ptr, pos, val, w, out);
+}
+
+// t = B U1 - g (work-groups below nb_rows, a wave per pressure row) and, in
+// the same launch, the coarse restriction's per-column assembly (the other
+// work-groups, a wave per coarse column): both read only what earlier
+// launches wrote, and the next launch (the Schur complement and coarse
+// products) needs both.
+__global__ __launch_bounds__(256) void rowprod_assemble_kernel(int64_t nrows, unsigned nb_rows,
+                                                               const int32_t* __restrict__ row_pos,
+                                                               const int64_t* __restrict__ ptr,
+                                                               const int32_t* __restrict__ pos,
+                                                               const double* __restrict__ val, double* __restrict__ w,
+                                                               int nc, CoarseView cv, const double* __restrict__ r,
+                                                               const double* __restrict__ t,
+                                                               const int32_t* __restrict__ out_pos) {
+  if (blockIdx.x < nb_rows) {  // uniform over the work-group
+    rowprod_rows<64, 0>(blockIdx.x, nrows, row_pos, ptr, pos, val, w, nullptr);
+    return;
+  }
+  const int c = (int)(blockIdx.x - nb_rows) * 4 + (threadIdx.x >> 6);
+  if (c >= nc) return;  // uniform per wave
+  restrict_assemble_column(c, threadIdx.x & 63, cv, r, t, w, out_pos);
 }
 
 // u_i -= W_i p_i for every local problem: W_i = K_i^-1 B_i^T (3 npad_i rows
@@ -169,6 +200,11 @@ void copy_blocks(const double* src, const int64_t* soff, const int32_t* n, int c
   GDSW_HIP(hipGetLastError());
 }
 
+bool block_assembles_restriction(const Context& ctx) {
+  return ctx.solve_mode == SOLVE_BLOCK && ctx.P.spec.levels == 2 && ctx.Nc > 0 && ctx.n_pairs > 0 &&
+         ctx.d_pair_t != nullptr && ctx.L1.count > 0;
+}
+
 int wp_rows_per_item(int prec) { return 64 * (prec == P_FP64 ? 2 : prec == P_FP32 ? 4 : 8); }
 
 void wp_sub(int prec, const void* W, const WItem* items, int n_items, double* w, KernelTimer* tm, double bytes,
@@ -187,7 +223,7 @@ void wp_sub(int prec, const void* W, const WItem* items, int n_items, double* w,
   GDSW_HIP(hipGetLastError());
 }
 
-void block_local_solve(Context& ctx, hipStream_t st, double* part) {
+void block_local_solve(Context& ctx, hipStream_t st, double* part, const double* restrict_r) {
   const BlockSolve& b = ctx.blk;
   FactorSet& L = ctx.L1;
   if (L.count == 0) return;
@@ -199,8 +235,17 @@ void block_local_solve(Context& ctx, hipStream_t st, double* part) {
   symv_desc_launch(L.prec, L.d_desc, L.gemv[0], pl, L.partial_len, st, nullptr, tm, (double)L.alg_bytes, 3);
   // t = B U1 - g in the pressure segments
   // pressure rows hold hundreds of entries: a wave per row
-  rowprod_kernel<64, 0><<<(unsigned)((b.n_prow * 64 + 255) / 256), 256, 0, st>>>(
-      b.n_prow, b.d_prow_pos, b.d_bm_ptr, b.d_bm_pos, b.d_bm_val, ctx.d_w, nullptr);
+  const unsigned nb_rows = (unsigned)((b.n_prow * 64 + 255) / 256);
+  if (restrict_r) {  // with the coarse restriction's assembly, whose input the caller passes
+    const unsigned nb_asm = (unsigned)((ctx.Nc + 3) / 4);
+    rowprod_assemble_kernel<<<nb_rows + nb_asm, 256, 0, st>>>(b.n_prow, nb_rows, b.d_prow_pos, b.d_bm_ptr,
+                                                               b.d_bm_pos, b.d_bm_val, ctx.d_w, ctx.Nc,
+                                                               coarse_view(ctx), restrict_r, ctx.d_pair_t,
+                                                               ctx.d_coarse_pinv);
+  } else {
+    rowprod_kernel<64, 0><<<nb_rows, 256, 0, st>>>(b.n_prow, b.d_prow_pos, b.d_bm_ptr, b.d_bm_pos, b.d_bm_val,
+                                                   ctx.d_w, nullptr);
+  }
   // p = S^-1 t (and, with two levels, the coarse solve in the same launch)
   if (part) {
     const FactorSet& P = ctx.LP;

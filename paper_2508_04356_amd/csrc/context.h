@@ -305,6 +305,8 @@ struct Context {
   int64_t coarse_xoff = 0;
   int n_pairs = 0;                 // (subdomain, local coarse column) pairs
   int max_ni = 0;                  // largest interior set |I_i|
+  int32_t* d_outer = nullptr;      // DOFs in no interior set (the interface), ascending
+  int64_t n_outer = 0;
   double* d_pair_t = nullptr;      // per pair: Phi_I column^T r (restriction)
   double* d_r0 = nullptr;          // coarse vectors (three levels)
   double* d_y0 = nullptr;
@@ -362,8 +364,13 @@ void spmv(Context& ctx, const double* x, double* y, hipStream_t st);
 // per-device scratch array instead of the context's buffer (noalloc.hip)
 void apply_precond_noalloc(Context& ctx, const double* r, double* z, hipStream_t st);
 // block local solve of every level-1 subdomain in the work vector (block.hip)
-// part (or null: the sets' own buffers): partial sums for every product
-void block_local_solve(Context& ctx, hipStream_t st, double* part = nullptr);
+// part (or null: the sets' own buffers): partial sums for every product;
+// restrict_r (or null): the vector whose coarse restriction apply_pre left
+// unassembled (two levels), assembled in the launch of the B row products
+void block_local_solve(Context& ctx, hipStream_t st, double* part = nullptr, const double* restrict_r = nullptr);
+// two levels with the block solve: the coarse restriction is assembled
+// inside block_local_solve
+bool block_assembles_restriction(const Context& ctx);
 int wp_rows_per_item(int prec);
 void wp_sub(int prec, const void* W, const WItem* items, int n_items, double* w, KernelTimer* tm, double bytes,
             hipStream_t st);

@@ -28,6 +28,9 @@ struct CoarseView {
   const int32_t* cs_lc;
 };
 
+// The coarse-basis arrays of a context.
+CoarseView coarse_view(const Context& c);
+
 // Closed subdomain boxes D_i and the nonzeros of A each box owns (a nonzero
 // belongs to the lowest-numbered box holding both of its nodes), used for
 // A_0 = sum_i Phi_box_i^T A_own_i Phi_box_i.
@@ -44,17 +47,36 @@ struct BoxView {
 // z = sum_i R_i^T y_i + Phi y0.  With nsub > 0 the Phi_I y0 term runs as a
 // second, per-subdomain kernel over the column-major Phi_I (max_ni: largest
 // interior set); the result is the same either way.
+// With outer (the n_outer DOFs in no interior set) both run in one launch.
 void scatter_prolong(int64_t n, const int32_t* inv_ptr, const int64_t* inv_pos, const double* w,
                      const CoarseView& cv, const double* y0, const int32_t* y0_pos, double* z, hipStream_t st,
-                     int nsub = 0, int max_ni = 0);
+                     int nsub = 0, int max_ni = 0, const int32_t* outer = nullptr, int64_t n_outer = 0);
 // out[pos[c]] = (Phi^T r)[c].  With t (n_pairs doubles, one per (subdomain,
 // local column) pair) the interior part is first reduced per pair, then
 // assembled per column in ascending subdomain order.
 // With gcount > 0 the same launch also performs gather(gcount, gidx, r, gdst)
-// (before the restriction is assembled).
+// (before the restriction is assembled).  assemble = false leaves the
+// per-column assembly (restrict_assemble_column) to a later launch of the
+// caller's.
 void restrict_coarse(int nc, const CoarseView& cv, const double* r, double* out, const int32_t* out_pos,
                      hipStream_t st, int n_pairs = 0, double* t = nullptr, int64_t gcount = 0,
-                     const int32_t* gidx = nullptr, double* gdst = nullptr);
+                     const int32_t* gidx = nullptr, double* gdst = nullptr, bool assemble = true);
+
+// out[c] = sum of r over the Gamma DOFs of coarse column c + sum_e t[e] over
+// its (subdomain, local column) pairs in ascending subdomain order, by one
+// wave (lane 0..63; every lane of the wave calls it).
+__device__ inline void restrict_assemble_column(int c, int lane, const CoarseView& cv, const double* __restrict__ r,
+                                                const double* __restrict__ t, double* __restrict__ out,
+                                                const int32_t* __restrict__ out_pos) {
+  double s = 0.0;
+  for (int e = cv.cg_ptr[c] + lane; e < cv.cg_ptr[c + 1]; e += 64) s += r[cv.cg_dof[e]];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) {
+    for (int e = cv.cs_ptr[c]; e < cv.cs_ptr[c + 1]; ++e) s += t[e];
+    out[out_pos ? out_pos[c] : c] = s;
+  }
+}
 void phi_rhs(int64_t total_I, const CoarseView& cv, const int32_t* rowptr, const int32_t* col, const double* val,
              double* B, hipStream_t st);
 void phi_transpose(int64_t total_I, const CoarseView& cv, const double* cm, double* rm, hipStream_t st);

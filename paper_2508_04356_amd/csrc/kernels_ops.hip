@@ -227,6 +227,93 @@ __global__ __launch_bounds__(256) void phi_prolong_kernel(CoarseView cv, const d
   }
 }
 
+// The sum of a DOF's local copies (ascending subdomain): four positions,
+// then four values, loaded before they are added; the order of
+// scatter_prolong_kernel.
+__device__ inline double local_copies_sum(const int32_t* __restrict__ inv_ptr, const int64_t* __restrict__ inv_pos,
+                                          const double* __restrict__ w, int64_t d) {
+  double s = 0.0;
+  const int e0 = inv_ptr[d], e1 = inv_ptr[d + 1];
+  for (int e = e0; e < e1; e += 4) {
+    int64_t pos[4];
+    double wv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) pos[u] = inv_pos[min(e + u, e1 - 1)];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) wv[u] = w[pos[u]];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s = e + u < e1 ? s + wv[u] : s;
+  }
+  return s;
+}
+
+// z = sum_i R_i^T y_i + Phi y0 in one launch, the same sums as
+// scatter_prolong_kernel followed by phi_prolong_kernel: work-groups below
+// nsub * nblk take 64 interior rows of one subdomain (wave 0 first issues
+// the rows' local-copy sums, then every wave its share of Phi_I y0 as in
+// phi_prolong_kernel, and z = copies + Phi_I y0); the others take the
+// listed rows outside every interior set (the interface), z = copies +
+// y0[gamma_col].
+__global__ __launch_bounds__(256) void scatter_prolong_fused_kernel(CoarseView cv, const int32_t* __restrict__ inv_ptr,
+                                                                    const int64_t* __restrict__ inv_pos,
+                                                                    const double* __restrict__ w,
+                                                                    const double* __restrict__ y0,
+                                                                    const int32_t* __restrict__ y0_pos,
+                                                                    double* __restrict__ z, int nsub, int nblk,
+                                                                    const int32_t* __restrict__ outer,
+                                                                    int64_t n_outer) {
+  __shared__ double yv[256];
+  __shared__ double red[4][64];
+  const int b = blockIdx.x;
+  if (b >= nsub * nblk) {  // uniform over the work-group
+    const int64_t nb = (int64_t)gridDim.x - (int64_t)nsub * nblk;
+    for (int64_t q = (int64_t)(b - nsub * nblk) * blockDim.x + threadIdx.x; q < n_outer; q += nb * blockDim.x) {
+      const int32_t d = outer[q];
+      const double s = local_copies_sum(inv_ptr, inv_pos, w, d);
+      const int32_t gc = cv.gamma_col[d];
+      const double c = gc >= 0 ? (y0_pos ? w[y0_pos[gc]] : y0[gc]) : 0.0;
+      z[d] = s + c;
+    }
+    return;
+  }
+  const int i = b / nblk;
+  const int ib = cv.I_ptr[i], ni = cv.I_ptr[i + 1] - ib;
+  const int k0 = (b % nblk) * 64;
+  if (k0 >= ni) return;  // uniform over the work-group
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double s = 0.0;
+  int32_t d = -1;
+  if (wave == 0 && k0 + lane < ni) {
+    d = cv.I_idx[ib + k0 + lane];
+    s = local_copies_sum(inv_ptr, inv_pos, w, d);
+  }
+  const int cb = cv.C_ptr[i], nc = cv.C_ptr[i + 1] - cb;
+  const double* ph = cv.phi_cm + cv.phi_off[i] + min(k0 + lane, ni - 1);
+  double c = 0.0;
+  for (int j0 = 0; j0 < nc; j0 += 256) {
+    const int jn = min(256, nc - j0);
+    __syncthreads();
+    if ((int)threadIdx.x < jn) {
+      const int32_t cc = cv.C_idx[cb + j0 + threadIdx.x];
+      yv[threadIdx.x] = y0_pos ? w[y0_pos[cc]] : y0[cc];
+    }
+    __syncthreads();
+    for (int j = wave; j < jn; j += 32) {
+      double pv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) pv[u] = ph[(int64_t)(j0 + min(j + 4 * u, jn - 1)) * ni];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) c = j + 4 * u < jn ? fma(pv[u], yv[min(j + 4 * u, jn - 1)], c) : c;
+    }
+  }
+  red[wave][lane] = c;
+  __syncthreads();
+  if (d >= 0) {
+    const double v = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+    z[d] = (s + 0.0) + v;  // as the two kernels: copies (+ 0 coarse), then + Phi_I y0
+  }
+}
+
 // t[e] = Phi_I^(i)[:, lc]^T r[I_i] for every (subdomain, local column) pair e
 // Work-groups n_pairs and up (when gcount > 0) copy the local restrictions
 // instead, as gather_kernel does: dst[p] = r[gidx[p]] (0 where gidx < 0).
@@ -276,16 +363,8 @@ __global__ __launch_bounds__(256) void restrict_assemble_kernel(int nc_total, Co
                                                                 double* __restrict__ out,
                                                                 const int32_t* __restrict__ out_pos) {
   const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (c >= nc_total) return;
-  double s = 0.0;
-  for (int e = cv.cg_ptr[c] + lane; e < cv.cg_ptr[c + 1]; e += 64) s += r[cv.cg_dof[e]];
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-  if (lane == 0) {
-    for (int e = cv.cs_ptr[c]; e < cv.cs_ptr[c + 1]; ++e) s += t[e];
-    out[out_pos ? out_pos[c] : c] = s;
-  }
+  if (c >= nc_total) return;  // uniform per wave
+  restrict_assemble_column(c, threadIdx.x & 63, cv, r, t, out, out_pos);
 }
 
 // -(A[I_i, Gamma] Phi_Gamma) for the extension right-hand sides, column-major
@@ -732,15 +811,23 @@ void deterministic_scatter(int64_t n, const int32_t* inv_ptr, const int64_t* inv
 
 void scatter_prolong(int64_t n, const int32_t* inv_ptr, const int64_t* inv_pos, const double* w,
                      const CoarseView& cv, const double* y0, const int32_t* y0_pos, double* z, hipStream_t st,
-                     int nsub, int max_ni) {
+                     int nsub, int max_ni, const int32_t* outer, int64_t n_outer) {
   if (n == 0) return;
   const int split = nsub > 0 && max_ni > 0;
+  if (split && outer) {
+    const int nblk = (max_ni + 63) / 64;
+    const unsigned gb = n_outer > 0 ? (unsigned)grid_for(n_outer, 256, 1024) : 0;
+    scatter_prolong_fused_kernel<<<(unsigned)(nsub * nblk) + gb, 256, 0, st>>>(cv, inv_ptr, inv_pos, w, y0, y0_pos,
+                                                                              z, nsub, nblk, outer, n_outer);
+    return;
+  }
   scatter_prolong_kernel<<<grid_for(n), 256, 0, st>>>(n, inv_ptr, inv_pos, w, cv, y0, y0_pos, z, split);
   if (split) phi_prolong_kernel<<<dim3((max_ni + 63) / 64, nsub), 256, 0, st>>>(cv, w, y0, y0_pos, z);
 }
 
 void restrict_coarse(int nc, const CoarseView& cv, const double* r, double* out, const int32_t* out_pos,
-                     hipStream_t st, int n_pairs, double* t, int64_t gcount, const int32_t* gidx, double* gdst) {
+                     hipStream_t st, int n_pairs, double* t, int64_t gcount, const int32_t* gidx, double* gdst,
+                     bool assemble) {
   if (nc == 0) {
     if (gcount > 0) gather(gcount, gidx, r, gdst, st);
     return;
@@ -748,7 +835,7 @@ void restrict_coarse(int nc, const CoarseView& cv, const double* r, double* out,
   if (n_pairs > 0 && t) {
     const int gb = gcount > 0 ? grid_for(gcount, 256, 1024) : 0;
     phi_t_kernel<<<n_pairs + gb, 256, 0, st>>>(cv, r, t, n_pairs, gb > 0 ? gcount : 0, gidx, gdst);
-    restrict_assemble_kernel<<<(nc + 3) / 4, 256, 0, st>>>(nc, cv, r, t, out, out_pos);
+    if (assemble) restrict_assemble_kernel<<<(nc + 3) / 4, 256, 0, st>>>(nc, cv, r, t, out, out_pos);
   } else {
     if (gcount > 0) gather(gcount, gidx, r, gdst, st);
     restrict_kernel<<<nc, 256, 0, st>>>(nc, cv, r, out, out_pos);

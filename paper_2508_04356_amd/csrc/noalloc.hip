@@ -76,7 +76,7 @@ void apply_precond_noalloc(Context& ctx, const double* r, double* z, hipStream_t
   double* part = noalloc_scratch(ctx.device);
   apply_pre(ctx, r, st);
   // the sets run one after the other on `st`, so they share the scratch
-  if (ctx.solve_mode == SOLVE_BLOCK) block_local_solve(ctx, st, part);
+  if (ctx.solve_mode == SOLVE_BLOCK) block_local_solve(ctx, st, part, block_assembles_restriction(ctx) ? r : nullptr);
   for (const FactorSet* fs : {&ctx.L1, &ctx.HI}) {
     if (fs == &ctx.L1 && ctx.solve_mode == SOLVE_BLOCK) continue;
     if (fs->count == 0 || fs->gemv.empty()) continue;

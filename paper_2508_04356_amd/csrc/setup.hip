@@ -691,6 +691,13 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
   ctx.d_pair_t = dalloc<double>(A, std::max(ctx.n_pairs, 1));
   ctx.max_ni = 0;
   for (int i = 0; i < P.n_sub; ++i) ctx.max_ni = std::max(ctx.max_ni, I_ptr[i + 1] - I_ptr[i]);
+  {
+    std::vector<int32_t> outer;
+    for (int64_t d = 0; d < n; ++d)
+      if (dof_ipos[d] < 0) outer.push_back((int32_t)d);
+    ctx.n_outer = (int64_t)outer.size();
+    ctx.d_outer = dupload(A, outer, st);
+  }
   ctx.d_phi_cm = dalloc<double>(A, std::max<int64_t>(phi_off.back(), 1));
   ctx.d_phi_rm = dalloc<double>(A, std::max<int64_t>(phi_off.back(), 1));
   CoarseView cv{ctx.d_gamma_col, ctx.d_dof_ipos, ctx.d_I_sub, ctx.d_I_ptr, ctx.d_I_idx, ctx.d_C_ptr,

@@ -21,13 +21,14 @@
 #include "learned.h"
 
 namespace gdsw {
-namespace {
 
 CoarseView coarse_view(const Context& c) {
   return CoarseView{c.d_gamma_col, c.d_dof_ipos, c.d_I_sub,  c.d_I_ptr,  c.d_I_idx,
                     c.d_C_ptr,     c.d_C_idx,    c.d_phi_off, c.d_phi_cm, c.d_phi_rm,
                     c.d_cg_ptr,    c.d_cg_dof,   c.d_cs_ptr,  c.d_cs_sub, c.d_cs_lc};
 }
+
+namespace {
 
 __global__ void residual_kernel(int64_t n, const double* __restrict__ b, double* __restrict__ r) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -239,9 +240,10 @@ void apply_pre(Context& ctx, const double* r, hipStream_t st) {
     gather(ctx.HI.total_x, ctx.d_g2idx, ctx.d_r0, ctx.d_w + ctx.n_w1, st);
     dense_cols_dot(ctx.d_phi3, ctx.Nc, ctx.Nc, ctx.Nc3, ctx.d_r0, ctx.d_w, ctx.d_c3_pinv, st);
   } else if (ctx.Nc > 0) {
-    // the local copies are gathered by the same launch as the restriction
+    // the local copies are gathered by the same launch as the restriction;
+    // the block solve assembles the restriction in its B row launch
     restrict_coarse(ctx.Nc, cv, r, ctx.d_w, ctx.d_coarse_pinv, st, ctx.n_pairs, ctx.d_pair_t, ctx.n_w1, ctx.d_gidx,
-                    ctx.d_w);
+                    ctx.d_w, !block_assembles_restriction(ctx));
   } else {
     gather(ctx.n_w1, ctx.d_gidx, r, ctx.d_w, st);
   }
@@ -255,10 +257,10 @@ void apply_post(Context& ctx, double* z, hipStream_t st) {
     scatter2(ctx.Nc, ctx.d_inv2_ptr, ctx.d_inv2_pos, ctx.d_w, ctx.d_phi3, ctx.Nc3, ctx.d_c3_pinv, ctx.d_s2part,
              ctx.d_y0, st);
     scatter_prolong(ctx.P.n_free, ctx.d_inv_ptr, ctx.d_inv_pos, ctx.d_w, cv, ctx.d_y0, nullptr, z, st,
-                    ctx.P.n_sub, ctx.max_ni);
+                    ctx.P.n_sub, ctx.max_ni, ctx.d_outer, ctx.n_outer);
   } else if (ctx.Nc > 0) {
     scatter_prolong(ctx.P.n_free, ctx.d_inv_ptr, ctx.d_inv_pos, ctx.d_w, cv, nullptr, ctx.d_coarse_pinv, z, st,
-                    ctx.P.n_sub, ctx.max_ni);
+                    ctx.P.n_sub, ctx.max_ni, ctx.d_outer, ctx.n_outer);
   } else {
     deterministic_scatter(ctx.P.n_free, ctx.d_inv_ptr, ctx.d_inv_pos, ctx.d_w, z, st);
   }
@@ -279,7 +281,7 @@ void apply_precond(Context& ctx, const double* r, double* z, hipStream_t st, hip
     else
       zero_segments(gm, L->S, ctx.d_w, st);
   } else if (ctx.solve_mode == SOLVE_BLOCK) {
-    block_local_solve(ctx, st);
+    block_local_solve(ctx, st, nullptr, block_assembles_restriction(ctx) ? r : nullptr);
   } else {
     local_solve_set(ctx.L1, ctx.d_w, st);
   }
