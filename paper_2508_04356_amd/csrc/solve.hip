@@ -417,16 +417,24 @@ FgmresResult fgmres(Context& ctx, const double* b, double* x, double rtol, int r
     // run for nothing: it writes only column j + 1 of H, g[j + 1], g[j + 2],
     // rotation j + 1, V_{j+2} and Z_{j+1}, none of which the update with
     // j + 1 columns below reads, and the next cycle starts afresh.  Each
-    // iteration copies its estimate to its own pinned slot (j % 2).
+    // iteration writes its estimate to its own pinned slot (j % 2).
+    // Iteration j + 1 is not enqueued ahead when the estimates so far,
+    // extrapolated geometrically, put iteration j at the tolerance already
+    // (saves the wasted iteration at the end of a solve; a wrong guess only
+    // costs one host round trip).
     int k = 0;
     bool queued = false;  // iteration j already enqueued
+    double rel1 = 0.0, rel2 = 0.0;  // estimates of iterations j - 1 and j - 2 of this cycle
     for (int j = 0; j < restart; ++j) {
       if (!queued) launch(j);
-      queued = j + 1 < restart && it + 1 < max_it;
+      const bool last = j >= 2 && rel2 > 0.0 && rel1 * (rel1 / rel2) <= rtol;
+      queued = j + 1 < restart && it + 1 < max_it && !last;
       if (queued) launch(j + 1);
       GDSW_HIP(hipEventSynchronize(ctx.it_ev[j & 1]));
       const double rel = ctx.h_pinned[10 + 2 * (j & 1)];
       const double hn = ctx.h_pinned[11 + 2 * (j & 1)];
+      rel2 = rel1;
+      rel1 = rel;
       if (history && it < history_len) history[it] = rel;
       ++it;
       k = j + 1;
