@@ -110,3 +110,17 @@ def test_algebraic_box_partition_is_the_structured_problem():
     assert s1.fgmres(b, x1)[0].iterations == s2.fgmres(b, x2)[0].iterations
     s1.close()
     s2.close()
+
+
+def test_block_solve_needs_node_interleaved_velocity():
+    """The block local solve relies on K_i = I_3 (x) L_i with the velocity
+    numbered node by node (3 node + component).  An assembled matrix whose
+    free DOFs break that numbering (here: Dirichlet rows removed component
+    by component) is refused at setup with EINVAL, not solved wrongly."""
+    p = StokesProblem(6)
+    A = p.A.tocsr()
+    A.sort_indices()
+    subs = repeated_map(p, box_partition(6, 3))
+    with pytest.raises(G.GdswError, match="I_3"):
+        G.Solver.algebraic(A.indptr, A.indices, A.data, p.dof_field, subs, null=p.dof_null, rhs=p.b,
+                           local_solve="block")
