@@ -1,7 +1,7 @@
 """Properties that hold at any size, checked at the full workload sizes the
 benchmarks run (24^3 with 6^3 subdomains in FP64 / BF16, 32^3 three-level
-with FP32 local inverses), where the CPU oracle is too slow to compare
-element by element:
+with FP32 local factors; full inverses, symmetric tiles and the block local
+solve), where the CPU oracle is too slow to compare element by element:
 
 * M^-1 is symmetric (every local, coarse and level-2/3 matrix is symmetric
   and the restrictions enter as R^T ... R): <M x, y> = <x, M y>, to rounding
@@ -22,10 +22,18 @@ from inputs import random_vector  # noqa: E402
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
 
+# the benchmark's local solves at the benchmark sizes: the block solve (the
+# default of the 16^3 and 32^3 benchmarks), the symmetric tiles, the full
+# inverses
 CASES = [
     ("24^3 fp64", dict(n=24, m=6), 1e-12, 1e-11),
     ("24^3 bf16", dict(n=24, m=6, precision="bf16"), 1e-5, 1e-10),
     ("32^3 fp32 three-level", dict(n=32, m=8, levels=3, group=2, precision="fp32"), 1e-5, 1e-10),
+    ("24^3 fp64 block", dict(n=24, m=6, local_solve="block"), 1e-12, 1e-11),
+    ("32^3 fp32 three-level block", dict(n=32, m=8, levels=3, group=2, precision="fp32", local_solve="block"), 1e-5,
+     1e-10),
+    ("32^3 fp32 three-level symmetric",
+     dict(n=32, m=8, levels=3, group=2, precision="fp32", local_solve="symmetric"), 1e-5, 1e-10),
 ]
 
 
