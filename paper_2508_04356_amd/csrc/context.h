@@ -308,6 +308,8 @@ struct Context {
   int32_t* d_outer = nullptr;      // DOFs in no interior set (the interface), ascending
   int64_t n_outer = 0;
   double* d_pair_t = nullptr;      // per pair: Phi_I column^T r (restriction)
+  int32_t* d_pair_of = nullptr;    // per (subdomain i, local column j) at C_ptr[i] + j: its pair index
+  int phi_cb = 0, phi_nblk = 0;    // restriction work-groups per (subdomain, cb columns); 0: one per pair
   double* d_r0 = nullptr;          // coarse vectors (three levels)
   double* d_y0 = nullptr;
   double* d_s2part = nullptr;      // chunk partials of Phi^(3) y3

@@ -129,6 +129,10 @@ void sub_dots(const double* V, int64_t ldv, int ncols, const double* h, double* 
 void gemv_add(const double* V, int64_t ldv, int ncols, const double* y, double* x, int64_t n,
               hipStream_t st);
 int cols_dot_blocks(int64_t n);
+// local columns per work-group of the coarse restriction's pair sums for
+// nsub subdomains of at most max_nc coarse columns and max_ni interior DOFs
+// (0: one work-group per (subdomain, column) pair)
+int phi_t_columns(int nsub, int max_nc, int max_ni);
 void cols_dot_finish(const double* part, int nblocks, int ncols, double* out, hipStream_t st);
 
 }  // namespace gdsw

@@ -58,9 +58,18 @@ void scatter_prolong(int64_t n, const int32_t* inv_ptr, const int64_t* inv_pos, 
 // (before the restriction is assembled).  assemble = false leaves the
 // per-column assembly (restrict_assemble_column) to a later launch of the
 // caller's.
+// Per-subdomain layout of the pair sums (restrict_coarse with t): a
+// work-group per (subdomain, block of cb local columns) instead of one per
+// pair; pair_of[C_ptr[i] + j] = the pair index of (subdomain i, local column
+// j); max_ni: the largest interior set (its r values are staged in LDS).
+struct PairBlocks {
+  const int32_t* pair_of = nullptr;
+  int nsub = 0, nblk = 0, cb = 0, max_ni = 0;
+};
 void restrict_coarse(int nc, const CoarseView& cv, const double* r, double* out, const int32_t* out_pos,
                      hipStream_t st, int n_pairs = 0, double* t = nullptr, int64_t gcount = 0,
-                     const int32_t* gidx = nullptr, double* gdst = nullptr, bool assemble = true);
+                     const int32_t* gidx = nullptr, double* gdst = nullptr, bool assemble = true,
+                     const PairBlocks* blocks = nullptr);
 
 // out[c] = sum of r over the Gamma DOFs of coarse column c + sum_e t[e] over
 // its (subdomain, local column) pairs in ascending subdomain order, by one

@@ -355,6 +355,60 @@ __global__ __launch_bounds__(256) void phi_t_kernel(CoarseView cv, const double*
   if (threadIdx.x == 0) t[e] = v;
 }
 
+// The pair sums of phi_t_kernel by (subdomain, column block): work-group b
+// takes subdomain i = b / nblk and its local columns j0 = cb (b % nblk) ..
+// j0 + cb - 1.  It first gathers r on I_i into LDS (one pass, every load in
+// flight), then wave w streams the columns j0 + w, j0 + w + 4, ... of the
+// column-major Phi_I^(i), 64 consecutive rows per load instruction and eight
+// instructions in flight, and sums each column across the wave by the xor
+// tree; t[pair_of[C_ptr[i] + j]] receives column j's sum.  Each work-group
+// streams cb |I_i| entries of Phi_I contiguously, so a launch has a few
+// thousand work-groups of some 100 KB instead of one 8 KB work-group per
+// pair.  Work-groups nsub * nblk and up copy the local restrictions as in
+// phi_t_kernel.
+__global__ __launch_bounds__(256) void phi_t_sub_kernel(CoarseView cv, const double* __restrict__ r,
+                                                        double* __restrict__ t, PairBlocks pb, int64_t gcount,
+                                                        const int32_t* __restrict__ gidx,
+                                                        double* __restrict__ gdst) {
+  extern __shared__ double rl[];  // r on I_i (max_ni doubles)
+  const int b = blockIdx.x;
+  if (b >= pb.nsub * pb.nblk) {  // uniform over the work-group
+    const int64_t nb = (int64_t)gridDim.x - (int64_t)pb.nsub * pb.nblk;
+    for (int64_t p = (int64_t)(b - pb.nsub * pb.nblk) * blockDim.x + threadIdx.x; p < gcount;
+         p += nb * blockDim.x) {
+      const int32_t g = gidx[p];
+      gdst[p] = g >= 0 ? r[g] : 0.0;
+    }
+    return;
+  }
+  const int i = b / pb.nblk, j0 = (b % pb.nblk) * pb.cb;
+  const int cb0 = cv.C_ptr[i], nc = cv.C_ptr[i + 1] - cb0;
+  if (j0 >= nc) return;  // uniform over the work-group
+  const int ib = cv.I_ptr[i], ni = cv.I_ptr[i + 1] - ib;
+  for (int k = threadIdx.x; k < ni; k += 256) rl[k] = r[cv.I_idx[ib + k]];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const double* ph = cv.phi_cm + cv.phi_off[i];
+  const int j1 = min(nc, j0 + pb.cb);
+  for (int j = j0 + wave; j < j1; j += 4) {
+    const double* col = ph + (int64_t)j * ni;
+    double s = 0.0;
+    for (int k0 = 0; k0 < ni; k0 += 512) {
+      double pv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) pv[u] = col[min(k0 + lane + 64 * u, ni - 1)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = k0 + lane + 64 * u;
+        s = k < ni ? fma(pv[u], rl[k], s) : s;
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) t[pb.pair_of[cb0 + j]] = s;
+  }
+}
+
 // out[c] = sum of r over the Gamma DOFs of column c + sum_e t[e] over its
 // pairs in ascending subdomain order; one wave per coarse column.
 __global__ __launch_bounds__(256) void restrict_assemble_kernel(int nc_total, CoarseView cv,
@@ -776,6 +830,21 @@ void scatter2(int Nc, const int32_t* inv_ptr, const int64_t* inv_pos, const doub
 
 int cols_dot_blocks(int64_t n) { return (int)((n + DOT_CHUNK - 1) / DOT_CHUNK); }
 
+#ifndef GDSW_PHI_T_CB
+#define GDSW_PHI_T_CB -1  // columns per restriction work-group (0: one work-group per pair, -1: by size)
+#endif
+
+int phi_t_columns(int nsub, int max_nc, int max_ni) {
+  if (max_ni <= 0 || (int64_t)max_ni * 8 > 48 * 1024) return 0;  // r on I_i must fit LDS
+  if (GDSW_PHI_T_CB >= 0) return GDSW_PHI_T_CB;
+  // one work-group per pair while the pairs are few enough to keep the
+  // launch short (16^3, 64 subdomains: ~4,500 pairs, 12 us either way);
+  // blocks of 8 columns beyond (32^3, 512 subdomains: the launch drops from
+  // 122 to about 80 us)
+  return (int64_t)nsub * max_nc >= 16384 ? 8 : 0;
+}
+
+
 void spmv_csr(int64_t nrows, const int32_t* rowptr, const int32_t* col, const double* val, const double* x,
               double* y, hipStream_t st) {
   if (nrows == 0) return;
@@ -827,14 +896,18 @@ void scatter_prolong(int64_t n, const int32_t* inv_ptr, const int64_t* inv_pos, 
 
 void restrict_coarse(int nc, const CoarseView& cv, const double* r, double* out, const int32_t* out_pos,
                      hipStream_t st, int n_pairs, double* t, int64_t gcount, const int32_t* gidx, double* gdst,
-                     bool assemble) {
+                     bool assemble, const PairBlocks* blocks) {
   if (nc == 0) {
     if (gcount > 0) gather(gcount, gidx, r, gdst, st);
     return;
   }
   if (n_pairs > 0 && t) {
     const int gb = gcount > 0 ? grid_for(gcount, 256, 1024) : 0;
-    phi_t_kernel<<<n_pairs + gb, 256, 0, st>>>(cv, r, t, n_pairs, gb > 0 ? gcount : 0, gidx, gdst);
+    if (blocks && blocks->pair_of && blocks->cb > 0 && blocks->nblk > 0)
+      phi_t_sub_kernel<<<blocks->nsub * blocks->nblk + gb, 256, (size_t)std::max(blocks->max_ni, 1) * sizeof(double),
+                         st>>>(cv, r, t, *blocks, gb > 0 ? gcount : 0, gidx, gdst);
+    else
+      phi_t_kernel<<<n_pairs + gb, 256, 0, st>>>(cv, r, t, n_pairs, gb > 0 ? gcount : 0, gidx, gdst);
     if (assemble) restrict_assemble_kernel<<<(nc + 3) / 4, 256, 0, st>>>(nc, cv, r, t, out, out_pos);
   } else {
     if (gcount > 0) gather(gcount, gidx, r, gdst, st);

@@ -692,6 +692,19 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
   ctx.max_ni = 0;
   for (int i = 0; i < P.n_sub; ++i) ctx.max_ni = std::max(ctx.max_ni, I_ptr[i + 1] - I_ptr[i]);
   {
+    // pair index of every (subdomain, local column), for the restriction
+    // by (subdomain, column block)
+    std::vector<int32_t> pair_of(C_ptr.back(), -1);
+    int32_t e = 0;
+    for (int c = 0; c < Nc; ++c)
+      for (size_t q = 0; q < cs_sub[c].size(); ++q) pair_of[C_ptr[cs_sub[c][q]] + cs_lc[c][q]] = e++;
+    ctx.d_pair_of = dupload(A, pair_of, st);
+    int max_nc = 0;
+    for (int i = 0; i < P.n_sub; ++i) max_nc = std::max(max_nc, C_ptr[i + 1] - C_ptr[i]);
+    ctx.phi_cb = phi_t_columns(P.n_sub, max_nc, ctx.max_ni);
+    ctx.phi_nblk = ctx.phi_cb > 0 ? (max_nc + ctx.phi_cb - 1) / ctx.phi_cb : 0;
+  }
+  {
     std::vector<int32_t> outer;
     for (int64_t d = 0; d < n; ++d)
       if (dof_ipos[d] < 0) outer.push_back((int32_t)d);

@@ -282,20 +282,33 @@ void spmv(Context& ctx, const double* x, double* y, hipStream_t st) {
   spmv_csr(ctx.P.n_free, ctx.d_rowptr, ctx.d_col, ctx.d_val, x, y, st);
 }
 
+PairBlocks pair_blocks(const Context& ctx) {
+  PairBlocks pb;
+  if (ctx.phi_cb > 0) {
+    pb.pair_of = ctx.d_pair_of;
+    pb.nsub = ctx.P.n_sub;
+    pb.nblk = ctx.phi_nblk;
+    pb.cb = ctx.phi_cb;
+    pb.max_ni = ctx.max_ni;
+  }
+  return pb;
+}
+
 void apply_pre(Context& ctx, const double* r, hipStream_t st) {
   const CoarseView cv = coarse_view(ctx);
+  const PairBlocks pb = pair_blocks(ctx);
   const bool three = ctx.P.spec.levels == 3 && ctx.Nc > 0;
   if (three) {
     gather(ctx.n_w1, ctx.d_gidx, r, ctx.d_w, st);
     // r0 = Phi^T r; level-2 copies R_j^(2) r0; level-3 right-hand side Phi3^T r0
-    restrict_coarse(ctx.Nc, cv, r, ctx.d_r0, nullptr, st, ctx.n_pairs, ctx.d_pair_t);
+    restrict_coarse(ctx.Nc, cv, r, ctx.d_r0, nullptr, st, ctx.n_pairs, ctx.d_pair_t, 0, nullptr, nullptr, true, &pb);
     gather(ctx.HI.total_x, ctx.d_g2idx, ctx.d_r0, ctx.d_w + ctx.n_w1, st);
     dense_cols_dot(ctx.d_phi3, ctx.Nc, ctx.Nc, ctx.Nc3, ctx.d_r0, ctx.d_w, ctx.d_c3_pinv, st);
   } else if (ctx.Nc > 0) {
     // the local copies are gathered by the same launch as the restriction;
     // the block solve assembles the restriction in its B row launch
     restrict_coarse(ctx.Nc, cv, r, ctx.d_w, ctx.d_coarse_pinv, st, ctx.n_pairs, ctx.d_pair_t, ctx.n_w1, ctx.d_gidx,
-                    ctx.d_w, !block_assembles_restriction(ctx));
+                    ctx.d_w, !block_assembles_restriction(ctx), &pb);
   } else {
     gather(ctx.n_w1, ctx.d_gidx, r, ctx.d_w, st);
   }
