@@ -599,7 +599,8 @@ def main():
              "symmetric": "symv_part_kernel (upper 64x64 tiles of the symmetric level-1 inverses, both products "
                           "per tile)",
              "triangular": "trsv_step_kernel (blocked forward/backward solves of the level-1 factors)",
-             "block": "symv_part_kernel<double, 3> (upper 64x64 tiles of the velocity-block inverses L_i^-1, three "
+             "block": f"symv_part_kernel<{ {'fp64': 'double', 'fp32': 'float', 'bf16': 'uint16_t'}[prec]}, 3> "
+                      "(upper 64x64 tiles of the velocity-block inverses L_i^-1, three "
                       "component vectors per tile; " +
                       ("one launch per apply: W_i = K_i^-1 B_i^T is kept for the last step)" if round(per_apply) == 1
                        else "two launches per apply)")}[args.local_solve]
