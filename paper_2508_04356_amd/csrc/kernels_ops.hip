@@ -608,8 +608,20 @@ __global__ __launch_bounds__(256) void dense_cols_dot_kernel(const double* __res
   __shared__ double sh[256];
   const int k = blockIdx.x;
   const double* col = M + (int64_t)k * ld;
+  // thread rows t, t + 256, ... in ascending order, eight rows' loads
+  // (clamped into range) issued before their products
   double s = 0.0;
-  for (int c = threadIdx.x; c < nrows; c += 256) s = fma(col[c], v[c], s);
+  for (int c0 = 0; c0 < nrows; c0 += 256 * 8) {
+    double mv[8], vv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int c = min(c0 + (int)threadIdx.x + 256 * u, nrows - 1);
+      mv[u] = col[c];
+      vv[u] = v[c];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s = c0 + (int)threadIdx.x + 256 * u < nrows ? fma(mv[u], vv[u], s) : s;
+  }
   const double t = block_sum<256>(s, sh);
   if (threadIdx.x == 0) out[pos ? pos[k] : k] = t;
 }
@@ -630,8 +642,16 @@ __global__ __launch_bounds__(256) void scatter2_part_kernel(int Nc, const double
   if (threadIdx.x < k1 - k0) y3[threadIdx.x] = w[y3_pos[k0 + threadIdx.x]];
   __syncthreads();
   if (c >= Nc) return;
+  // ascending k, eight columns' loads (clamped into range) issued before
+  // their products
   double t = 0.0;
-  for (int k = k0; k < k1; ++k) t = fma(phi3[(int64_t)k * Nc + c], y3[k - k0], t);
+  for (int kb = k0; kb < k1; kb += 8) {
+    double pv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) pv[u] = phi3[(int64_t)min(kb + u, k1 - 1) * Nc + c];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t = kb + u < k1 ? fma(pv[u], y3[min(kb + u, k1 - 1) - k0], t) : t;
+  }
   part[(int64_t)blockIdx.y * Nc + c] = t;
 }
 
@@ -642,10 +662,28 @@ __global__ void scatter2_kernel(int Nc, const int32_t* __restrict__ inv_ptr, con
                                 double* __restrict__ y0) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= Nc) return;
+  // the local copies four positions and then four values at a time, the
+  // chunk partials four at a time, each added in ascending order
   double s = 0.0;
-  for (int e = inv_ptr[c]; e < inv_ptr[c + 1]; ++e) s += w[inv_pos[e]];
+  const int e0 = inv_ptr[c], e1 = inv_ptr[c + 1];
+  for (int e = e0; e < e1; e += 4) {
+    int64_t pos[4];
+    double wv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) pos[u] = inv_pos[min(e + u, e1 - 1)];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) wv[u] = w[pos[u]];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s = e + u < e1 ? s + wv[u] : s;
+  }
   double t = 0.0;
-  for (int q = 0; q < nchunk; ++q) t += part[(int64_t)q * Nc + c];
+  for (int q0 = 0; q0 < nchunk; q0 += 4) {
+    double pv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) pv[u] = part[(int64_t)min(q0 + u, nchunk - 1) * Nc + c];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) t = q0 + u < nchunk ? t + pv[u] : t;
+  }
   y0[c] = s + t;
 }
 
