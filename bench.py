@@ -537,9 +537,11 @@ def main():
                  coarse=w.coarse)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
+    t_sym, t_num = s.setup_times()
     sz = s.sizes()
     n = sz.n_free
-    log(f"[bench] setup {t_setup:.2f} s; n_free={n} Nc={sz.n_coarse} device bytes={sz.device_bytes / 1e9:.2f} GB")
+    log(f"[bench] setup {t_setup:.2f} s (symbolic {t_sym:.2f} s, numeric {t_num:.2f} s); n_free={n} "
+        f"Nc={sz.n_coarse} device bytes={sz.device_bytes / 1e9:.2f} GB")
     tuned = None
     if args.autotune:
         code, ms = s.autotune()
@@ -634,6 +636,8 @@ def main():
         "apply_only_per_s": 1e3 / t_apply_ms,
         "apply_phases_ms": {"gather_restrict": ph[0], "solve_l1": ph[1], "solve_coarse": ph[2], "scatter": ph[3]},
         "setup_s": t_setup,
+        "setup_symbolic_s": t_sym,
+        "setup_numeric_s": t_num,
         "local_solve": args.local_solve,
         "graph": bool(args.graph),
         "autotune": tuned,
