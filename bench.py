@@ -349,7 +349,9 @@ def run_batch(args, prec):
     torch.cuda.set_device(dev)
     draws = c5_batch_draws()
     problems = [dict(n=n, m=n // 4, viscosity=mu, inflow=c) for n, mu, c in draws]
-    solve = args.local_solve if args.local_solve != "auto" else "symmetric"
+    # the block solve by default; the learned interior solve needs whole
+    # local inverses (symmetric tiles)
+    solve = args.local_solve if args.local_solve != "auto" else ("symmetric" if args.learned else "block")
     if solve == "triangular":
         raise SystemExit("batches need explicit inverses (inverse or symmetric)")
     log(f"[bench] setup C5 batch: n = {[p['n'] for p in problems]} precision={prec} local solve {solve}")
@@ -406,9 +408,12 @@ def run_batch(args, prec):
         "graph": bool(args.graph),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": ("symv_part_kernel over the merged upper tiles of the active members' level-1 "
-                                "inverses" if solve == "symmetric" else
-                                "gemv_part_kernel over the merged level-1 inverses of the active members"),
+                     "kernel": {"symmetric": "symv_part_kernel over the merged upper tiles of the active members' "
+                                             "level-1 inverses",
+                                "block": "symv_part_kernel<double, 3> over the merged upper tiles of the active "
+                                         "members' velocity-block inverses L_i^-1",
+                                "inverse": "gemv_part_kernel over the merged level-1 inverses of the active members"}
+                               [solve],
                      "bytes_per_launch": k_bytes, "launches_timed": k_launches, "avg_launch_us": k_avg_us},
     }
     if args.learned:

@@ -519,8 +519,11 @@ void gdsw_destroy(gdsw_ctx* ctx);
  * viscosity and inflow), each with its own context, whose level-1 and
  * coarse-level inverse products run as ONE launch pair per level over the
  * matrices of every member (longest matrix first).  Every member must use
- * the same local_solve, GDSW_SOLVE_INVERSE or GDSW_SOLVE_SYMMETRIC (EINVAL
- * otherwise), and the same local_precision.  A member computes
+ * the same local_solve, GDSW_SOLVE_INVERSE, GDSW_SOLVE_SYMMETRIC or
+ * GDSW_SOLVE_BLOCK (EINVAL otherwise), and the same local_precision; with
+ * GDSW_SOLVE_BLOCK the merged launch is the velocity-block product, and
+ * each member's B row products, Schur complement product and u = U1 - W p
+ * follow on its own stream lane.  A member computes
  * exactly what it computes alone (same kernels and summation orders: the
  * results are bitwise those of the member's own gdsw_apply_precond and
  * gdsw_fgmres_solve). */

@@ -816,11 +816,12 @@ gdsw_status gdsw_setup_batch(const gdsw_mesh* meshes, const gdsw_decomposition* 
   gdsw_batch* bt = new (std::nothrow) gdsw_batch();
   if (!bt) return fail(nullptr, GDSW_ENOMEM, "host allocation failed");
   for (int k = 0; k < count; ++k) {
-    if ((decs[k].local_solve != GDSW_SOLVE_INVERSE && decs[k].local_solve != GDSW_SOLVE_SYMMETRIC) ||
+    if ((decs[k].local_solve != GDSW_SOLVE_INVERSE && decs[k].local_solve != GDSW_SOLVE_SYMMETRIC &&
+         decs[k].local_solve != GDSW_SOLVE_BLOCK) ||
         decs[k].local_solve != decs[0].local_solve) {
       gdsw_destroy_batch(bt);
       return fail(nullptr, GDSW_EINVAL,
-                  "batch members need one local_solve, GDSW_SOLVE_INVERSE or GDSW_SOLVE_SYMMETRIC");
+                  "batch members need one local_solve, GDSW_SOLVE_INVERSE, GDSW_SOLVE_SYMMETRIC or GDSW_SOLVE_BLOCK");
     }
     gdsw_ctx* c = nullptr;
     const gdsw_status s = gdsw_setup(&meshes[k], &decs[k], stream, &c);

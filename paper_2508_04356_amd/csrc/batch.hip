@@ -30,12 +30,16 @@ void build_set(Batch& b, BatchSet& S, bool level1, hipStream_t st) {
     const FactorSet& fs = level1 ? c.L1 : c.HI;
     if (fs.count == 0) continue;
     if (fs.mode != SOLVE_INVERSE && fs.mode != SOLVE_SYM)
-      throw StatusError{1, "batched solves need explicit inverses (full or symmetric)"};
+      throw StatusError{1, "batched solves need explicit inverses (full or symmetric) or the block solve"};
     if (S.prec >= 0 && S.prec != fs.prec) throw StatusError{1, "batch members must share the local precision"};
     if (S.prec >= 0 && S.sym != (fs.mode == SOLVE_SYM)) throw StatusError{1, "batch members must share the storage"};
+    if (S.prec >= 0 && S.nc != fs.nc) throw StatusError{1, "batch members must share the local solve"};
     S.prec = fs.prec;
     S.sym = fs.mode == SOLVE_SYM;
+    S.nc = fs.nc;
     std::vector<GemvDesc> d = gemv_descs(fs, c.d_w);
+    if (fs.nc > 1)  // the velocity components, npad apart (the member's own descriptors)
+      for (int f = 0; f < fs.count; ++f) d[f].vs = fs.npad[f];
     for (int f = 0; f < fs.count; ++f) {
       desc.push_back(d[f]);
       S.owner.push_back((int)k);
@@ -85,7 +89,7 @@ void build_set(Batch& b, BatchSet& S, bool level1, hipStream_t st) {
   S.plan.n2 = (int)it2.size();
   S.plan.d_items1 = dupload(A, it1, st);
   S.plan.d_items2 = dupload(A, it2, st);
-  S.partial_len = S.sym ? 2 * 64 * std::max<int64_t>(p, 1) : std::max<int64_t>(p, 1) * RB;
+  S.partial_len = S.sym ? 2 * 64 * S.nc * std::max<int64_t>(p, 1) : std::max<int64_t>(p, 1) * RB;
   S.d_partial = dalloc<double>(A, S.partial_len);
   S.h_want.assign(S.count, 1);
   S.d_want = dupload(A, S.h_want, st);
@@ -155,6 +159,10 @@ void batch_join(Batch& b, hipStream_t st) {
 
 bool batch_learned(const Context& c) { return c.local_solver != 0 && c.learned && c.learned->S > 0; }
 
+void batch_block_rest(Context& c, const double* r, hipStream_t ls) {
+  if (c.solve_mode == SOLVE_BLOCK) block_local_rest(c, ls, nullptr, block_assembles_restriction(c) ? r : nullptr);
+}
+
 void batch_save_interior(Context& c, hipStream_t ls) {
   copy_segments(learned_gridmap(c), c.learned->S, c.d_w, c.learned->d_rsave, nullptr, ls);
 }
@@ -193,7 +201,7 @@ void batch_local_solve(Batch& b, hipStream_t st) {
     KernelTimer* tm = S == &b.s1 ? &b.timer : nullptr;
     const double bytes = S == &b.s1 ? S->active_bytes : 0.0;
     if (S->sym)
-      symv_desc_launch(S->prec, S->d_desc, S->plan, S->d_partial, S->partial_len, st, S->d_want, tm, bytes);
+      symv_desc_launch(S->prec, S->d_desc, S->plan, S->d_partial, S->partial_len, st, S->d_want, tm, bytes, S->nc);
     else
       gemv_desc_launch(S->prec, S->d_desc, S->plan, GEMV_CW, S->d_partial, st, S->d_want, tm, bytes);
   }
@@ -236,7 +244,10 @@ void apply_precond_batch(Batch& b, const double* const* r, double* const* z, hip
   batch_local_solve(b, st);
   batch_learned_solves(b, all, st);
   batch_fork(b, st);
-  for (size_t k = 0; k < b.m.size(); ++k) apply_post(*b.m[k], z[k], batch_lane(b, k));
+  for (size_t k = 0; k < b.m.size(); ++k) {
+    batch_block_rest(*b.m[k], r[k], batch_lane(b, k));
+    apply_post(*b.m[k], z[k], batch_lane(b, k));
+  }
   batch_join(b, st);
   GDSW_HIP(hipGetLastError());
 }

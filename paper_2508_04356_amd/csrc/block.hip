@@ -233,6 +233,15 @@ void block_local_solve(Context& ctx, hipStream_t st, double* part, const double*
   KernelTimer* tm = part ? nullptr : L.timer;
   // U1 = L^-1 F (three vectors per matrix, in place in the work vector)
   symv_desc_launch(L.prec, L.d_desc, L.gemv[0], pl, L.partial_len, st, nullptr, tm, (double)L.alg_bytes, 3);
+  block_local_rest(ctx, st, part, restrict_r);
+}
+
+void block_local_rest(Context& ctx, hipStream_t st, double* part, const double* restrict_r) {
+  const BlockSolve& b = ctx.blk;
+  FactorSet& L = ctx.L1;
+  if (L.count == 0) return;
+  double* pl = part ? part : L.d_partial;
+  KernelTimer* tm = part ? nullptr : L.timer;
   // t = B U1 - g in the pressure segments
   // pressure rows hold hundreds of entries: a wave per row
   const unsigned nb_rows = (unsigned)((b.n_prow * 64 + 255) / 256);

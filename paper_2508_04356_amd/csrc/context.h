@@ -370,6 +370,11 @@ void apply_precond_noalloc(Context& ctx, const double* r, double* z, hipStream_t
 // restrict_r (or null): the vector whose coarse restriction apply_pre left
 // unassembled (two levels), assembled in the launch of the B row products
 void block_local_solve(Context& ctx, hipStream_t st, double* part = nullptr, const double* restrict_r = nullptr);
+// the block local solve after its velocity-block product (U1 already in the
+// work vector): the B row products, the Schur complement and coarse
+// products, and u = U1 - W p (or the second pass); for a batch whose merged
+// launch formed U1 of every member
+void block_local_rest(Context& ctx, hipStream_t st, double* part = nullptr, const double* restrict_r = nullptr);
 // two levels with the block solve: the coarse restriction is assembled
 // inside block_local_solve
 bool block_assembles_restriction(const Context& ctx);
@@ -407,6 +412,7 @@ struct BatchSet {
   double* d_partial = nullptr;
   int64_t partial_len = 0;
   bool sym = false;                  // symmetric tile storage (symv kernels)
+  int nc = 1;                        // vectors per matrix (3: the block solve's velocity-block inverses)
   int32_t* d_want = nullptr;
   std::vector<int32_t> h_want;       // host copy of the last upload
   double active_bytes = 0.0;
@@ -441,6 +447,9 @@ inline hipStream_t batch_lane(const Batch& b, size_t k) { return b.lanes[k % b.l
 // or none (2): the merged product skips those matrices; their inputs are
 // saved after the gathers and the network (or zero) fills them in after it.
 bool batch_learned(const Context& c);
+// a block-solve member's work after the merged velocity-block product (r:
+// the vector being preconditioned); nothing for the other local solves
+void batch_block_rest(Context& c, const double* r, hipStream_t ls);
 void batch_save_interior(Context& c, hipStream_t ls);
 void batch_learned_solves(Batch& b, const std::vector<char>& on, hipStream_t st);
 

@@ -642,6 +642,7 @@ std::vector<FgmresResult> fgmres_batch(Batch& bt, const double* const* bvec, dou
         double* V = c.d_V;
         double* zj = c.d_Z + (int64_t)j * c.ldv;
         double* w = c.d_t2;
+        batch_block_rest(c, V + (int64_t)j * c.ldv, ls);
         apply_post(c, zj, ls);
         spmv(c, zj, w, ls);
         cols_dot(V, c.ldv, j + 1, w, n, c.d_part, c.n_part_blocks, c.d_hv, ls);

@@ -25,7 +25,7 @@ PROBLEMS = [
 ]
 
 
-@pytest.fixture(scope="module", params=["inverse", "symmetric"])
+@pytest.fixture(scope="module", params=["inverse", "symmetric", "block"])
 def batch(request):
     print(f"[gpu] batch setup {PROBLEMS} {request.param}", flush=True)
     b = G.Batch(PROBLEMS, local_solve=request.param)
