@@ -5,11 +5,14 @@
 #include <tuple>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <numeric>
 #include <stdexcept>
+#include <string>
+#include <thread>
 
 #include "context.h"
 #include "kernels.h"
@@ -806,9 +809,15 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
       lo = (coord % two_s == 0) ? std::max(coord / two_s - 1, 0) : coord / two_s;
       hi = std::min(coord / two_s, m - 1);
     };
-    std::vector<int64_t> own_ptr(total_D + 1, 0);
-    std::vector<int32_t> own_col;
-    std::vector<int64_t> own_vidx;
+    // per DOF and axis, the box index range holding its node (structured
+    // problems), so that the loop below needs no divisions
+    std::vector<int32_t> blo, bhi;
+    if (!P.algebraic) {
+      blo.resize(3 * (size_t)n);
+      bhi.resize(3 * (size_t)n);
+      for (int64_t d = 0; d < n; ++d)
+        for (int ax = 0; ax < 3; ++ax) box_lo_hi(P.abc[3 * d + ax], blo[3 * d + ax], bhi[3 * d + ax]);
+    }
     // algebraic problems: the lowest subdomain holding both DOFs
     auto common_lowest = [&](int32_t r, int32_t c) -> int {
       int64_t a = P.sub_ptr[r], ae = P.sub_ptr[r + 1], b = P.sub_ptr[c], be = P.sub_ptr[c + 1];
@@ -818,28 +827,33 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
       }
       return -1;
     };
-    for (int i = 0; i < P.n_sub; ++i) {
+    // the owned nonzeros of every box, boxes built in parallel (each box's
+    // list in the order of its rows and of their nonzeros), then joined in
+    // box order
+    std::vector<std::vector<int32_t>> oc(P.n_sub);
+    std::vector<std::vector<int64_t>> ov(P.n_sub), oq(P.n_sub);
+    std::vector<std::string> oerr(P.n_sub);
+    auto own_box = [&](int i) {
       const auto& Di = P.D[i];
+      oq[i].assign(Di.size() + 1, 0);
       for (size_t q = 0; q < Di.size(); ++q) {
         const int32_t r = Di[q];
-        int rlo[3] = {0, 0, 0}, rhi[3] = {0, 0, 0};
-        if (!P.algebraic)
-          for (int ax = 0; ax < 3; ++ax) box_lo_hi(P.abc[3 * (int64_t)r + ax], rlo[ax], rhi[ax]);
         for (int32_t e = P.row_ptr[r]; e < P.row_ptr[r + 1]; ++e) {
           const int32_t c = P.col[e];
           int own = -1;
           if (P.algebraic) {
             own = common_lowest(r, c);
-            if (own < 0)
-              throw StatusError{1, "matrix entry (" + std::to_string(r) + ", " + std::to_string(c) +
-                                       ") couples DOFs that share no subdomain"};
+            if (own < 0) {
+              oerr[i] = "matrix entry (" + std::to_string(r) + ", " + std::to_string(c) +
+                        ") couples DOFs that share no subdomain";
+              return;
+            }
           } else {
             int owner[3];
             bool ok = true;
             for (int ax = 0; ax < 3; ++ax) {
-              int clo, chi;
-              box_lo_hi(P.abc[3 * (int64_t)c + ax], clo, chi);
-              const int lo = std::max(rlo[ax], clo), hi = std::min(rhi[ax], chi);
+              const int lo = std::max(blo[3 * (size_t)r + ax], blo[3 * (size_t)c + ax]);
+              const int hi = std::min(bhi[3 * (size_t)r + ax], bhi[3 * (size_t)c + ax]);
               if (lo > hi) ok = false;
               owner[ax] = lo;
             }
@@ -848,11 +862,40 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
           }
           if (own != i) continue;
           const auto it = std::lower_bound(Di.begin(), Di.end(), c);
-          own_col.push_back((int32_t)(it - Di.begin()));
-          own_vidx.push_back(e);
+          oc[i].push_back((int32_t)(it - Di.begin()));
+          ov[i].push_back(e);
         }
-        own_ptr[D_ptr[i] + q + 1] = (int64_t)own_col.size();
+        oq[i][q + 1] = (int64_t)oc[i].size();
       }
+    };
+    {
+      const int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+      std::atomic<int> next{0};
+      std::vector<std::thread> pool;
+      for (int t = 0; t < std::min(nt, P.n_sub); ++t)
+        pool.emplace_back([&]() {
+          for (int i = next++; i < P.n_sub; i = next++) {
+            try {
+              own_box(i);
+            } catch (const std::exception& ex) {  // (allocation) reported below, on the calling thread
+              oerr[i] = std::string("box ownership lists: ") + ex.what();
+            }
+          }
+        });
+      for (auto& th : pool) th.join();
+    }
+    for (int i = 0; i < P.n_sub; ++i)
+      if (!oerr[i].empty()) throw StatusError{1, oerr[i]};
+    std::vector<int64_t> own_ptr(total_D + 1, 0);
+    std::vector<int32_t> own_col;
+    std::vector<int64_t> own_vidx;
+    for (int i = 0; i < P.n_sub; ++i) {
+      const int64_t base = (int64_t)own_col.size();
+      for (size_t q = 0; q < P.D[i].size(); ++q) own_ptr[D_ptr[i] + q + 1] = base + oq[i][q + 1];
+      own_col.insert(own_col.end(), oc[i].begin(), oc[i].end());
+      own_vidx.insert(own_vidx.end(), ov[i].begin(), ov[i].end());
+      std::vector<int32_t>().swap(oc[i]);
+      std::vector<int64_t>().swap(ov[i]);
     }
     int32_t* d_D_ptr = dupload(A, D_ptr, st);
     int32_t* d_D_idx = dupload(A, D_idx, st);
