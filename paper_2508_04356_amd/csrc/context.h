@@ -312,7 +312,6 @@ struct Context {
   int phi_cb = 0, phi_nblk = 0;    // restriction work-groups per (subdomain, cb columns); 0: one per pair
   double* d_r0 = nullptr;          // coarse vectors (three levels)
   double* d_y0 = nullptr;
-  double* d_s2part = nullptr;      // chunk partials of Phi^(3) y3
 
   // three levels
   int Nc3 = 0;
@@ -320,7 +319,27 @@ struct Context {
   int32_t* d_g2idx = nullptr;      // level-2 work positions -> coarse index
   int32_t* d_inv2_ptr = nullptr;
   int64_t* d_inv2_pos = nullptr;
-  double* d_phi3 = nullptr;        // dense Phi^(3), column-major Nc x Nc3
+  // Phi^(3) in the layout of the level-1 basis, on the coarse DOFs: per
+  // subregion j a column-major |I2_j| x |C3_j| block, the interface part an
+  // indicator (coarse_view3)
+  int32_t* d_gcol3 = nullptr;      // per coarse DOF: its level-3 column (interface), or -1
+  int32_t* d_ipos3 = nullptr;      // per coarse DOF: position in the concatenated interiors, or -1
+  int32_t* d_i2_sub = nullptr;     // per interior position: subregion
+  int32_t* d_i2_ptr = nullptr;     // interior coarse DOFs of each subregion
+  int32_t* d_i2_idx = nullptr;
+  int32_t* d_c3_ptr = nullptr;     // level-3 columns adjacent to each subregion
+  int32_t* d_c3_idx = nullptr;
+  int64_t* d_off2 = nullptr;       // offset of each subregion's block
+  double* d_phi3_cm = nullptr;
+  int32_t* d_cg3_ptr = nullptr;    // per level-3 column: its interface coarse DOFs
+  int32_t* d_cg3_dof = nullptr;
+  int32_t* d_cs3_ptr = nullptr;    // per level-3 column: (subregion, local column) pairs
+  int32_t* d_cs3_sub = nullptr;
+  int32_t* d_cs3_lc = nullptr;
+  int n_pairs3 = 0, max_ni2 = 0;
+  double* d_pair_t3 = nullptr;
+  int32_t* d_outer3 = nullptr;     // coarse DOFs in no subregion interior
+  int64_t n_outer3 = 0;
   int32_t* d_c3_pinv = nullptr;    // level-3 column -> wbuf position
   double* d_A03 = nullptr;
 

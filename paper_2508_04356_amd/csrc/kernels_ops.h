@@ -30,6 +30,9 @@ struct CoarseView {
 
 // The coarse-basis arrays of a context.
 CoarseView coarse_view(const Context& c);
+// Three levels: the level-3 basis Phi^(3) on the coarse DOFs in the same
+// layout (subregions for subdomains, coarse DOFs for DOFs).
+CoarseView coarse_view3(const Context& c);
 
 // Closed subdomain boxes D_i and the nonzeros of A each box owns (a nonzero
 // belongs to the lowest-numbered box holding both of its nodes), used for
@@ -111,12 +114,6 @@ void phi3_rhs(int64_t total_I, int Nc, const int32_t* I_sub, const int32_t* I_pt
 void phi3_build(int64_t total_I, int Nc, const int32_t* I_sub, const int32_t* I_ptr, const int32_t* I_idx,
                 const int32_t* C_ptr, const int32_t* C_idx, const int64_t* off, const double* phiI,
                 const int32_t* gcol3, double* phi3, hipStream_t st);
-void dense_cols_dot(const double* M, int64_t ld, int nrows, int ncols, const double* v, double* out,
-                    const int32_t* pos, hipStream_t st);
-// y0 = sum_j R_j^(2)T y_j + Phi^(3) y3; part holds scatter2_part_len(Nc, Nc3) doubles
-int64_t scatter2_part_len(int Nc, int Nc3);
-void scatter2(int Nc, const int32_t* inv_ptr, const int64_t* inv_pos, const double* w, const double* phi3, int Nc3,
-              const int32_t* y3_pos, double* part, double* y0, hipStream_t st);
 void expand(int64_t nfree, const int64_t* full_index, const double* xf, double* xfull, hipStream_t st);
 
 }  // namespace gdsw

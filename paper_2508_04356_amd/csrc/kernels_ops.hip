@@ -601,92 +601,6 @@ __global__ void phi3_gamma_kernel(int Nc, const int32_t* __restrict__ gcol3, dou
   if (g >= 0) phi3[(int64_t)g * Nc + c] = 1.0;
 }
 
-// out[pos[k]] = sum_c M[k * ld + c] v[c]   (one work-group per column)
-__global__ __launch_bounds__(256) void dense_cols_dot_kernel(const double* __restrict__ M, int64_t ld, int nrows,
-                                                            const double* __restrict__ v, double* __restrict__ out,
-                                                            const int32_t* __restrict__ pos) {
-  __shared__ double sh[256];
-  const int k = blockIdx.x;
-  const double* col = M + (int64_t)k * ld;
-  // thread rows t, t + 256, ... in ascending order, eight rows' loads
-  // (clamped into range) issued before their products
-  double s = 0.0;
-  for (int c0 = 0; c0 < nrows; c0 += 256 * 8) {
-    double mv[8], vv[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int c = min(c0 + (int)threadIdx.x + 256 * u, nrows - 1);
-      mv[u] = col[c];
-      vv[u] = v[c];
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) s = c0 + (int)threadIdx.x + 256 * u < nrows ? fma(mv[u], vv[u], s) : s;
-  }
-  const double t = block_sum<256>(s, sh);
-  if (threadIdx.x == 0) out[pos ? pos[k] : k] = t;
-}
-
-// Phi^(3) y3 in column chunks: part[q * Nc + c] = sum over k in chunk q of
-// Phi^(3)[c, k] y3[k] (ascending k); one work-group per (256 rows, chunk), so
-// the dense Nc x Nc3 basis is streamed by many work-groups at once.
-constexpr int S2_CHUNK = 32;
-
-__global__ __launch_bounds__(256) void scatter2_part_kernel(int Nc, const double* __restrict__ w,
-                                                            const double* __restrict__ phi3, int Nc3,
-                                                            const int32_t* __restrict__ y3_pos,
-                                                            double* __restrict__ part) {
-  const int c = blockIdx.x * 256 + threadIdx.x;
-  const int k0 = blockIdx.y * S2_CHUNK;
-  const int k1 = min(Nc3, k0 + S2_CHUNK);
-  __shared__ double y3[S2_CHUNK];
-  if (threadIdx.x < k1 - k0) y3[threadIdx.x] = w[y3_pos[k0 + threadIdx.x]];
-  __syncthreads();
-  if (c >= Nc) return;
-  // ascending k, eight columns' loads (clamped into range) issued before
-  // their products
-  double t = 0.0;
-  for (int kb = k0; kb < k1; kb += 8) {
-    double pv[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) pv[u] = phi3[(int64_t)min(kb + u, k1 - 1) * Nc + c];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) t = kb + u < k1 ? fma(pv[u], y3[min(kb + u, k1 - 1) - k0], t) : t;
-  }
-  part[(int64_t)blockIdx.y * Nc + c] = t;
-}
-
-// y0[c] = sum of level-2 local copies (ascending subregion) + the chunk
-// partials of Phi^(3) y3 (ascending chunk)
-__global__ void scatter2_kernel(int Nc, const int32_t* __restrict__ inv_ptr, const int64_t* __restrict__ inv_pos,
-                                const double* __restrict__ w, const double* __restrict__ part, int nchunk,
-                                double* __restrict__ y0) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= Nc) return;
-  // the local copies four positions and then four values at a time, the
-  // chunk partials four at a time, each added in ascending order
-  double s = 0.0;
-  const int e0 = inv_ptr[c], e1 = inv_ptr[c + 1];
-  for (int e = e0; e < e1; e += 4) {
-    int64_t pos[4];
-    double wv[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) pos[u] = inv_pos[min(e + u, e1 - 1)];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) wv[u] = w[pos[u]];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) s = e + u < e1 ? s + wv[u] : s;
-  }
-  double t = 0.0;
-  for (int q0 = 0; q0 < nchunk; q0 += 4) {
-    double pv[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) pv[u] = part[(int64_t)min(q0 + u, nchunk - 1) * Nc + c];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) t = q0 + u < nchunk ? t + pv[u] : t;
-  }
-  y0[c] = s + t;
-}
-
 // ---- Krylov helpers --------------------------------------------------------
 constexpr int DOT_CHUNK = 256;  // rows per partial block (enough blocks to fill the device at 1e5 rows)
 
@@ -847,23 +761,6 @@ void phi3_build(int64_t total_I, int Nc, const int32_t* I_sub, const int32_t* I_
   if (total_I)
     phi3_interior_kernel<<<(unsigned)((total_I + 127) / 128), 128, 0, st>>>(total_I, Nc, I_sub, I_ptr, I_idx, C_ptr,
                                                                            C_idx, off, phiI, phi3);
-}
-
-void dense_cols_dot(const double* M, int64_t ld, int nrows, int ncols, const double* v, double* out,
-                    const int32_t* pos, hipStream_t st) {
-  if (ncols == 0) return;
-  dense_cols_dot_kernel<<<ncols, 256, 0, st>>>(M, ld, nrows, v, out, pos);
-}
-
-int64_t scatter2_part_len(int Nc, int Nc3) { return (int64_t)Nc * ((Nc3 + S2_CHUNK - 1) / S2_CHUNK); }
-
-void scatter2(int Nc, const int32_t* inv_ptr, const int64_t* inv_pos, const double* w, const double* phi3, int Nc3,
-              const int32_t* y3_pos, double* part, double* y0, hipStream_t st) {
-  if (Nc == 0) return;
-  const int nchunk = (Nc3 + S2_CHUNK - 1) / S2_CHUNK;
-  if (nchunk > 0)
-    scatter2_part_kernel<<<dim3((Nc + 255) / 256, nchunk), 256, 0, st>>>(Nc, w, phi3, Nc3, y3_pos, part);
-  scatter2_kernel<<<(Nc + 255) / 256, 256, 0, st>>>(Nc, inv_ptr, inv_pos, w, part, nchunk, y0);
 }
 
 int cols_dot_blocks(int64_t n) { return (int)((n + DOT_CHUNK - 1) / DOT_CHUNK); }

@@ -984,24 +984,62 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
     check_pivots(mp, L2.n_sub, 0.0, "level-2 interior block", st);
     phi3_rhs(total_I2, Nc, d_i2_sub, d_i2_ptr, d_i2_idx, d_c3_ptr, d_c3_idx, d_off2, d_gcol3, ctx.d_A0, phiI, st);
     lu_solve_multi(B, phiI, d_off2, d_nr2, max_nr2, st);
-    ctx.d_phi3 = dalloc<double>(A, std::max<int64_t>((int64_t)Nc * Nc3, 1));
-    GDSW_HIP(hipMemsetAsync(ctx.d_phi3, 0, std::max<int64_t>((int64_t)Nc * Nc3, 1) * 8, st));
-    phi3_build(total_I2, Nc, d_i2_sub, d_i2_ptr, d_i2_idx, d_c3_ptr, d_c3_idx, d_off2, phiI, d_gcol3, ctx.d_phi3,
-               st);
+    // the dense Phi^(3) only for forming A_0^(3) here; the apply reads the
+    // subregion blocks phiI and the interface indicator (coarse_view3)
+    double* phi3 = dalloc<double>(A, std::max<int64_t>((int64_t)Nc * Nc3, 1));
+    GDSW_HIP(hipMemsetAsync(phi3, 0, std::max<int64_t>((int64_t)Nc * Nc3, 1) * 8, st));
+    phi3_build(total_I2, Nc, d_i2_sub, d_i2_ptr, d_i2_idx, d_c3_ptr, d_c3_idx, d_off2, phiI, d_gcol3, phi3, st);
     // A_0^(3) = Phi3^T (A_0 Phi3): A_0 is row-major, i.e. A_0^T column-major
     double* T = dalloc<double>(A, std::max<int64_t>((int64_t)Nc * Nc3, 1));
     ctx.d_A03 = dalloc<double>(A, std::max<int64_t>((int64_t)Nc3 * Nc3, 1));
-    std::vector<GemmDesc> gd = {GemmDesc{ctx.d_A0, ctx.d_phi3, T, Nc, Nc3, Nc, Nc, Nc, Nc, 1, 0}};
+    std::vector<GemmDesc> gd = {GemmDesc{ctx.d_A0, phi3, T, Nc, Nc3, Nc, Nc, Nc, Nc, 1, 0}};
     GemmDesc* d_gd = dupload(A, gd, st);
     gemm_batched(d_gd, 1, Nc, Nc3, 1.0, 0.0, st);
-    std::vector<GemmDesc> gd2 = {GemmDesc{ctx.d_phi3, T, ctx.d_A03, Nc3, Nc3, Nc, Nc, Nc, Nc3, 1, 0}};
+    std::vector<GemmDesc> gd2 = {GemmDesc{phi3, T, ctx.d_A03, Nc3, Nc3, Nc, Nc, Nc, Nc3, 1, 0}};
     GemmDesc* d_gd2 = dupload(A, gd2, st);
     gemm_batched(d_gd2, 1, Nc3, Nc3, 1.0, 0.0, st);
     GDSW_HIP(hipStreamSynchronize(st));
-    for (void* q : {(void*)d_i2_ptr, (void*)d_i2_idx, (void*)d_i2_sub, (void*)d_c3_ptr, (void*)d_c3_idx,
-                    (void*)d_off2, (void*)d_aoff2, (void*)d_ni2, (void*)d_nr2, (void*)d_gcol3, (void*)aii,
-                    (void*)phiI, (void*)T, (void*)d_gd, (void*)d_gd2, (void*)mp})
+    for (void* q : {(void*)d_aoff2, (void*)d_ni2, (void*)d_nr2, (void*)aii, (void*)phi3, (void*)T, (void*)d_gd,
+                    (void*)d_gd2, (void*)mp})
       A.free(q);
+    // the level-3 view: the level-1 layout with subregions for subdomains
+    ctx.d_gcol3 = d_gcol3;
+    ctx.d_i2_sub = d_i2_sub;
+    ctx.d_i2_ptr = d_i2_ptr;
+    ctx.d_i2_idx = d_i2_idx;
+    ctx.d_c3_ptr = d_c3_ptr;
+    ctx.d_c3_idx = d_c3_idx;
+    ctx.d_off2 = d_off2;
+    ctx.d_phi3_cm = phiI;
+    ctx.max_ni2 = max_ni2;
+    {
+      std::vector<int32_t> ipos3(Nc, -1);
+      for (int64_t q = 0; q < total_I2; ++q) ipos3[i2_idx[q]] = (int32_t)q;
+      std::vector<std::vector<int32_t>> cg3(Nc3), cs3s(Nc3), cs3l(Nc3);
+      for (int c = 0; c < Nc; ++c)
+        if (L2.gamma_col3[c] >= 0) cg3[L2.gamma_col3[c]].push_back(c);
+      for (int j = 0; j < L2.n_sub; ++j)
+        for (size_t q = 0; q < L2.C[j].size(); ++q) {
+          cs3s[L2.C[j][q]].push_back(j);
+          cs3l[L2.C[j][q]].push_back((int32_t)q);
+        }
+      std::vector<int32_t> cg_ptr3, cg_dof3, cs_ptr3, cs_sub3, cs_ptr3b, cs_lc3, outer3;
+      concat(cg3, cg_ptr3, cg_dof3);
+      concat(cs3s, cs_ptr3, cs_sub3);
+      concat(cs3l, cs_ptr3b, cs_lc3);
+      for (int c = 0; c < Nc; ++c)
+        if (ipos3[c] < 0) outer3.push_back(c);
+      ctx.d_ipos3 = dupload(A, ipos3, st);
+      ctx.d_cg3_ptr = dupload(A, cg_ptr3, st);
+      ctx.d_cg3_dof = dupload(A, cg_dof3, st);
+      ctx.d_cs3_ptr = dupload(A, cs_ptr3, st);
+      ctx.d_cs3_sub = dupload(A, cs_sub3, st);
+      ctx.d_cs3_lc = dupload(A, cs_lc3, st);
+      ctx.n_pairs3 = (int)cs_sub3.size();
+      ctx.d_pair_t3 = dalloc<double>(A, std::max(ctx.n_pairs3, 1));
+      ctx.n_outer3 = (int64_t)outer3.size();
+      ctx.d_outer3 = dupload(A, outer3, st);
+    }
     // level-3 factor order: velocity-type columns first
     std::vector<int32_t> f3(Nc3, 0);
     for (int c = 0; c < Nc; ++c)
@@ -1041,7 +1079,6 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
     ctx.d_c3_pinv = dupload(A, p3, st);
     ctx.d_r0 = dalloc<double>(A, Nc);
     ctx.d_y0 = dalloc<double>(A, Nc);
-    ctx.d_s2part = dalloc<double>(A, std::max<int64_t>(1, scatter2_part_len(Nc, Nc3)));
   }
 
   // ---- level-1 local factors (and the coarse factor when merged) -----------

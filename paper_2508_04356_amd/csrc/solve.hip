@@ -28,6 +28,14 @@ CoarseView coarse_view(const Context& c) {
                     c.d_cg_ptr,    c.d_cg_dof,   c.d_cs_ptr,  c.d_cs_sub, c.d_cs_lc};
 }
 
+// (no row-major copy: the pair-sum restriction and the fused scatter read
+// only the column-major blocks)
+CoarseView coarse_view3(const Context& c) {
+  return CoarseView{c.d_gcol3,   c.d_ipos3,   c.d_i2_sub, c.d_i2_ptr,   c.d_i2_idx,
+                    c.d_c3_ptr,  c.d_c3_idx,  c.d_off2,   c.d_phi3_cm,  nullptr,
+                    c.d_cg3_ptr, c.d_cg3_dof, c.d_cs3_ptr, c.d_cs3_sub, c.d_cs3_lc};
+}
+
 namespace {
 
 __global__ void residual_kernel(int64_t n, const double* __restrict__ b, double* __restrict__ r) {
@@ -303,7 +311,10 @@ void apply_pre(Context& ctx, const double* r, hipStream_t st) {
     // r0 = Phi^T r; level-2 copies R_j^(2) r0; level-3 right-hand side Phi3^T r0
     restrict_coarse(ctx.Nc, cv, r, ctx.d_r0, nullptr, st, ctx.n_pairs, ctx.d_pair_t, 0, nullptr, nullptr, true, &pb);
     gather(ctx.HI.total_x, ctx.d_g2idx, ctx.d_r0, ctx.d_w + ctx.n_w1, st);
-    dense_cols_dot(ctx.d_phi3, ctx.Nc, ctx.Nc, ctx.Nc3, ctx.d_r0, ctx.d_w, ctx.d_c3_pinv, st);
+    // level-3 right-hand side (Phi^(3))^T r0: per-pair sums over the
+    // subregion interiors, assembled per level-3 column with its interface
+    // part
+    restrict_coarse(ctx.Nc3, coarse_view3(ctx), ctx.d_r0, ctx.d_w, ctx.d_c3_pinv, st, ctx.n_pairs3, ctx.d_pair_t3);
   } else if (ctx.Nc > 0) {
     // the local copies are gathered by the same launch as the restriction;
     // the block solve assembles the restriction in its B row launch
@@ -319,8 +330,8 @@ void apply_post(Context& ctx, double* z, hipStream_t st) {
   const bool three = ctx.P.spec.levels == 3 && ctx.Nc > 0;
   if (three) {
     // y0 = sum_j R_j^(2)T y_j + Phi3 y3, then z = sum_i R_i^T y_i + Phi y0
-    scatter2(ctx.Nc, ctx.d_inv2_ptr, ctx.d_inv2_pos, ctx.d_w, ctx.d_phi3, ctx.Nc3, ctx.d_c3_pinv, ctx.d_s2part,
-             ctx.d_y0, st);
+    scatter_prolong(ctx.Nc, ctx.d_inv2_ptr, ctx.d_inv2_pos, ctx.d_w, coarse_view3(ctx), nullptr, ctx.d_c3_pinv,
+                    ctx.d_y0, st, ctx.n_sub2, ctx.max_ni2, ctx.d_outer3, ctx.n_outer3);
     scatter_prolong(ctx.P.n_free, ctx.d_inv_ptr, ctx.d_inv_pos, ctx.d_w, cv, ctx.d_y0, nullptr, z, st,
                     ctx.P.n_sub, ctx.max_ni, ctx.d_outer, ctx.n_outer);
   } else if (ctx.Nc > 0) {
