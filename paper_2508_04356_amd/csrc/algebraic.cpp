@@ -93,6 +93,19 @@ void build_problem_algebraic(const AlgebraicInput& in, const ProblemSpec& spec_i
     }
     P.multiplicity[d] = (int8_t)std::min<int64_t>(e - b, 127);
   }
+  // every nonzero must couple DOFs of a common subdomain: A_0 is assembled
+  // from the nonzeros each subdomain owns (the lowest one holding both DOFs)
+  for (int64_t r = 0; r < n; ++r)
+    for (int64_t e = in.row_ptr[r]; e < in.row_ptr[r + 1]; ++e) {
+      const int32_t c = in.col[e];
+      int64_t a = in.sub_ptr[r], ae = in.sub_ptr[r + 1], b = in.sub_ptr[c], be = in.sub_ptr[c + 1];
+      while (a < ae && b < be && in.sub_idx[a] != in.sub_idx[b]) {
+        if (in.sub_idx[a] < in.sub_idx[b]) ++a; else ++b;
+      }
+      if (a == ae || b == be)
+        throw std::invalid_argument("matrix entry (" + std::to_string(r) + ", " + std::to_string(c) +
+                                    ") couples DOFs that share no subdomain");
+    }
   P.I.assign(P.n_sub, {});
   for (int i = 0; i < P.n_sub; ++i) {
     if (P.D[i].empty()) throw std::invalid_argument("subdomain " + std::to_string(i) + " holds no DOF");

@@ -34,17 +34,26 @@ CoarseView coarse_view(const Context& c);
 // layout (subregions for subdomains, coarse DOFs for DOFs).
 CoarseView coarse_view3(const Context& c);
 
-// Closed subdomain boxes D_i and the nonzeros of A each box owns (a nonzero
-// belongs to the lowest-numbered box holding both of its nodes), used for
-// A_0 = sum_i Phi_box_i^T A_own_i Phi_box_i.
+// Closed subdomain boxes D_i, used for A_0 = sum_i Phi_box_i^T A_own_i
+// Phi_box_i, where A_own_i holds the nonzeros box i owns: a nonzero belongs
+// to the lowest-numbered box holding both of its DOFs.
 struct BoxView {
   const int32_t* D_ptr;
-  const int32_t* D_idx;
+  const int32_t* D_idx;      // each box's DOFs, ascending
   const int32_t* D_sub;
   const int64_t* box_off;    // offset of the |D_i| x |C_i| blocks
-  const int64_t* own_ptr;    // per concatenated D position: owned entries
-  const int32_t* own_col;    // local column within D_i
-  const int64_t* own_vidx;   // index into the CSR values
+};
+
+// The boxes holding a DOF, from which the owner of a nonzero follows.
+// Structured problems (blo != null): per DOF and axis the range of box
+// indices holding its node, boxes numbered x + m (y + m z); algebraic
+// problems: per DOF the ascending list of subdomains holding it.
+struct OwnerMap {
+  const int32_t* blo;
+  const int32_t* bhi;
+  int m;
+  const int64_t* sub_ptr;
+  const int32_t* sub_idx;
 };
 
 // z = sum_i R_i^T y_i + Phi y0.  With nsub > 0 the Phi_I y0 term runs as a
@@ -102,8 +111,13 @@ void decouple_pressure(const DenseBatch& B, const int32_t* nu, int max_n, hipStr
 void phi_pressure_rows(int64_t total_I, const CoarseView& cv, const int8_t* pval, const int32_t* sub_pcol,
                        double* phi_cm, hipStream_t st);
 void phibox(int64_t total_D, const CoarseView& cv, const BoxView& bv, double* out, hipStream_t st);
-void own_spmm(int nbox, int max_nd, const CoarseView& cv, const BoxView& bv, const double* val,
-              const double* phibox_, double* W, hipStream_t st);
+// W_i = A_own_i Phi_box_i for every box (column-major, ld |D_i|); the owned
+// nonzeros of a row are found from the CSR matrix and om on the device.
+// max_nc: the largest |C_i| (at most OWN_SPMM_MAX_NC).
+constexpr int OWN_SPMM_MAX_NC = 7936;
+void own_spmm(int nbox, int max_nd, int max_nc, const CoarseView& cv, const BoxView& bv, const OwnerMap& om,
+              const int32_t* rowptr, const int32_t* col, const double* val, const double* phibox_, double* W,
+              hipStream_t st);
 void a0_assemble(int Nc, const CoarseView& cv, const double* P, const int64_t* p_off, double* A0, hipStream_t st);
 void permute_dense(int n, const int32_t* perm, const double* M, int64_t ldm, double* F, int64_t ld, hipStream_t st);
 void negate(int64_t n, double* x, hipStream_t st);

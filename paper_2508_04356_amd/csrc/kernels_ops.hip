@@ -500,23 +500,90 @@ __global__ void phibox_kernel(int64_t total_D, CoarseView cv, BoxView bv, double
   }
 }
 
-// W_i = A_own_i Phi_box_i: thread per (local row, column)
-__global__ __launch_bounds__(256) void own_spmm_kernel(CoarseView cv, BoxView bv, const double* __restrict__ val,
-                                                      const double* __restrict__ phibox, double* __restrict__ W) {
+// The owner of nonzero (r, c): the lowest-numbered box holding both DOFs,
+// -1 if none does
+__device__ inline int nonzero_owner(const OwnerMap& om, int32_t r, int32_t c) {
+  if (om.blo) {
+    int own = 0, mul = 1;
+    for (int ax = 0; ax < 3; ++ax) {
+      const int lo = max(om.blo[3 * (int64_t)r + ax], om.blo[3 * (int64_t)c + ax]);
+      const int hi = min(om.bhi[3 * (int64_t)r + ax], om.bhi[3 * (int64_t)c + ax]);
+      if (lo > hi) return -1;
+      own += lo * mul;
+      mul *= om.m;
+    }
+    return own;
+  }
+  int64_t a = om.sub_ptr[r], ae = om.sub_ptr[r + 1], b = om.sub_ptr[c], be = om.sub_ptr[c + 1];
+  while (a < ae && b < be) {
+    const int32_t x = om.sub_idx[a], y = om.sub_idx[b];
+    if (x == y) return x;
+    if (x < y) ++a; else ++b;
+  }
+  return -1;
+}
+
+// W_i = A_own_i Phi_box_i, a work-group per (row q of box i): the row's
+// nonzeros are taken OWN_T at a time, those box i owns (local column by a
+// binary search in the ascending D_i) are packed into LDS in CSR order, and
+// thread t adds them into columns t, t + OWN_T, ..., whose sums stay in LDS
+// (dynamic, |C_i| doubles).  Every column sums its owned nonzeros in CSR
+// order.
+constexpr int OWN_T = 128;
+__global__ __launch_bounds__(OWN_T) void own_spmm_kernel(CoarseView cv, BoxView bv, OwnerMap om,
+                                                        const int32_t* __restrict__ rowptr,
+                                                        const int32_t* __restrict__ col,
+                                                        const double* __restrict__ val,
+                                                        const double* __restrict__ phibox, double* __restrict__ W) {
+  extern __shared__ double acc[];
+  __shared__ int32_t lc_s[OWN_T];
+  __shared__ double v_s[OWN_T];
+  __shared__ int cnt_s[OWN_T / 64];
   const int i = blockIdx.y;
   const int db = bv.D_ptr[i], nd = bv.D_ptr[i + 1] - db;
+  const int q = blockIdx.x;
+  if (q >= nd) return;  // uniform over the work-group
   const int nc = cv.C_ptr[i + 1] - cv.C_ptr[i];
-  const int q = blockIdx.x * 2 + (threadIdx.x >> 7);
-  if (q >= nd) return;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int64_t o = bv.box_off[i];
-  const int64_t rb = bv.own_ptr[db + q], re = bv.own_ptr[db + q + 1];
-  for (int j = threadIdx.x & 127; j < nc; j += 128) {
-    double s = 0.0;
-    const double* ph = phibox + o + (int64_t)j * nd;
-    for (int64_t e = rb; e < re; ++e) s = fma(val[bv.own_vidx[e]], ph[bv.own_col[e]], s);
-    W[o + (int64_t)j * nd + q] = s;
+  const int32_t* Di = bv.D_idx + db;
+  const int32_t r = Di[q];
+  for (int j = t; j < nc; j += OWN_T) acc[j] = 0.0;
+  const int32_t e0 = rowptr[r], e1 = rowptr[r + 1];
+  for (int32_t eb = e0; eb < e1; eb += OWN_T) {
+    const int32_t e = eb + t;
+    bool owned = false;
+    int lc = 0;
+    double v = 0.0;
+    if (e < e1) {
+      const int32_t c = col[e];
+      if (nonzero_owner(om, r, c) == i) {
+        lc = lower_bound_i32(Di, nd, c);
+        owned = lc < nd && Di[lc] == c;  // always, as box i holds c
+        v = val[e];
+      }
+    }
+    const unsigned long long bal = __ballot(owned);
+    if (lane == 0) cnt_s[wave] = __popcll(bal);
+    __syncthreads();
+    const int slot = (wave ? cnt_s[0] : 0) + __popcll(bal & ((1ull << lane) - 1));
+    const int tot = cnt_s[0] + cnt_s[1];
+    if (owned) {
+      lc_s[slot] = lc;
+      v_s[slot] = v;
+    }
+    __syncthreads();
+    for (int j = t; j < nc; j += OWN_T) {
+      const double* ph = phibox + o + (int64_t)j * nd;
+      double s = acc[j];
+      for (int k = 0; k < tot; ++k) s = fma(v_s[k], ph[lc_s[k]], s);
+      acc[j] = s;
+    }
+    __syncthreads();
   }
+  for (int j = t; j < nc; j += OWN_T) W[o + (int64_t)j * nd + q] = acc[j];
 }
+static_assert(OWN_T == 128, "two waves share the packing counts");
 
 // A_0[c, :] += P_i[lc, :] over the subdomains of c in ascending order
 __global__ __launch_bounds__(256) void a0_assemble_kernel(int Nc, CoarseView cv, const double* __restrict__ P,
@@ -879,10 +946,16 @@ void phibox(int64_t total_D, const CoarseView& cv, const BoxView& bv, double* ou
   phibox_kernel<<<(unsigned)((total_D + 127) / 128), 128, 0, st>>>(total_D, cv, bv, out);
 }
 
-void own_spmm(int nbox, int max_nd, const CoarseView& cv, const BoxView& bv, const double* val,
-              const double* phibox_, double* W, hipStream_t st) {
-  if (nbox == 0) return;
-  own_spmm_kernel<<<dim3((max_nd + 1) / 2, nbox), 256, 0, st>>>(cv, bv, val, phibox_, W);
+void own_spmm(int nbox, int max_nd, int max_nc, const CoarseView& cv, const BoxView& bv, const OwnerMap& om,
+              const int32_t* rowptr, const int32_t* col, const double* val, const double* phibox_, double* W,
+              hipStream_t st) {
+  if (nbox == 0 || max_nd == 0) return;
+  if (max_nc > OWN_SPMM_MAX_NC)
+    throw StatusError{1, "A_0 assembly: more than " + std::to_string(OWN_SPMM_MAX_NC) +
+                             " coarse columns touch one subdomain"};
+  if (nbox > 65535) throw StatusError{1, "A_0 assembly: more than 65535 subdomains"};
+  own_spmm_kernel<<<dim3((unsigned)max_nd, (unsigned)nbox), OWN_T, (size_t)std::max(max_nc, 1) * sizeof(double), st>>>(
+      cv, bv, om, rowptr, col, val, phibox_, W);
 }
 
 void a0_assemble(int Nc, const CoarseView& cv, const double* P, const int64_t* p_off, double* A0, hipStream_t st) {

@@ -2,13 +2,12 @@
 // coarse basis Phi (eq. 2.4), A_0 = Phi^T A Phi (eq. 2.3) and its factors.
 #include <hip/hip_runtime.h>
 
-#include <tuple>
-
 #include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <exception>
 #include <numeric>
 #include <stdexcept>
 #include <string>
@@ -469,6 +468,31 @@ void block_check(const Problem& P) {
   }
 }
 
+// fn(i) for every i in [0, count) on up to 16 host threads (the calling
+// thread among them); an exception thrown for an item is rethrown here, that
+// of the lowest item first
+template <class F>
+void parallel_items(int count, F&& fn) {
+  const int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::exception_ptr> err(std::max(count, 0));
+  std::atomic<int> next{0};
+  auto work = [&]() {
+    for (int i = next++; i < count; i = next++) {
+      try {
+        fn(i);
+      } catch (...) {
+        err[i] = std::current_exception();
+      }
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < std::min(nt, count); ++t) pool.emplace_back(work);
+  work();
+  for (auto& th : pool) th.join();
+  for (auto& e : err)
+    if (e) std::rethrow_exception(e);
+}
+
 template <class T>
 void concat(const std::vector<std::vector<T>>& lists, std::vector<int32_t>& ptr, std::vector<T>& idx) {
   ptr.assign(lists.size() + 1, 0);
@@ -803,115 +827,42 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
       max_nd = std::max(max_nd, (int)P.D[i].size());
       max_nc = std::max(max_nc, (int)P.C[i].size());
     }
-    // owner of a nonzero: the lowest-numbered box containing both nodes
-    auto box_lo_hi = [&](int coord, int& lo, int& hi) {
-      const int two_s = 2 * s;
-      lo = (coord % two_s == 0) ? std::max(coord / two_s - 1, 0) : coord / two_s;
-      hi = std::min(coord / two_s, m - 1);
-    };
-    // per DOF and axis, the box index range holding its node (structured
-    // problems), so that the loop below needs no divisions
-    std::vector<int32_t> blo, bhi;
+    // owner of a nonzero: the lowest-numbered box holding both DOFs, found
+    // on the device from each DOF's boxes (structured problems: per axis the
+    // range of box indices holding its node; algebraic problems: the
+    // subdomain lists, whose nonzeros were checked to share one)
+    OwnerMap om{nullptr, nullptr, m, nullptr, nullptr};
+    std::vector<void*> om_bufs;
     if (!P.algebraic) {
-      blo.resize(3 * (size_t)n);
-      bhi.resize(3 * (size_t)n);
+      std::vector<int32_t> blo(3 * (size_t)n), bhi(3 * (size_t)n);
+      const int two_s = 2 * s;
       for (int64_t d = 0; d < n; ++d)
-        for (int ax = 0; ax < 3; ++ax) box_lo_hi(P.abc[3 * d + ax], blo[3 * d + ax], bhi[3 * d + ax]);
-    }
-    // algebraic problems: the lowest subdomain holding both DOFs
-    auto common_lowest = [&](int32_t r, int32_t c) -> int {
-      int64_t a = P.sub_ptr[r], ae = P.sub_ptr[r + 1], b = P.sub_ptr[c], be = P.sub_ptr[c + 1];
-      while (a < ae && b < be) {
-        if (P.sub_idx[a] == P.sub_idx[b]) return P.sub_idx[a];
-        if (P.sub_idx[a] < P.sub_idx[b]) ++a; else ++b;
-      }
-      return -1;
-    };
-    // the owned nonzeros of every box, boxes built in parallel (each box's
-    // list in the order of its rows and of their nonzeros), then joined in
-    // box order
-    std::vector<std::vector<int32_t>> oc(P.n_sub);
-    std::vector<std::vector<int64_t>> ov(P.n_sub), oq(P.n_sub);
-    std::vector<std::string> oerr(P.n_sub);
-    auto own_box = [&](int i) {
-      const auto& Di = P.D[i];
-      oq[i].assign(Di.size() + 1, 0);
-      for (size_t q = 0; q < Di.size(); ++q) {
-        const int32_t r = Di[q];
-        for (int32_t e = P.row_ptr[r]; e < P.row_ptr[r + 1]; ++e) {
-          const int32_t c = P.col[e];
-          int own = -1;
-          if (P.algebraic) {
-            own = common_lowest(r, c);
-            if (own < 0) {
-              oerr[i] = "matrix entry (" + std::to_string(r) + ", " + std::to_string(c) +
-                        ") couples DOFs that share no subdomain";
-              return;
-            }
-          } else {
-            int owner[3];
-            bool ok = true;
-            for (int ax = 0; ax < 3; ++ax) {
-              const int lo = std::max(blo[3 * (size_t)r + ax], blo[3 * (size_t)c + ax]);
-              const int hi = std::min(bhi[3 * (size_t)r + ax], bhi[3 * (size_t)c + ax]);
-              if (lo > hi) ok = false;
-              owner[ax] = lo;
-            }
-            if (!ok) continue;  // cannot happen for an assembled nonzero
-            own = owner[0] + m * (owner[1] + m * owner[2]);
-          }
-          if (own != i) continue;
-          const auto it = std::lower_bound(Di.begin(), Di.end(), c);
-          oc[i].push_back((int32_t)(it - Di.begin()));
-          ov[i].push_back(e);
+        for (int ax = 0; ax < 3; ++ax) {
+          const int coord = P.abc[3 * d + ax];
+          blo[3 * d + ax] = (coord % two_s == 0) ? std::max(coord / two_s - 1, 0) : coord / two_s;
+          bhi[3 * d + ax] = std::min(coord / two_s, m - 1);
         }
-        oq[i][q + 1] = (int64_t)oc[i].size();
-      }
-    };
-    {
-      const int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-      std::atomic<int> next{0};
-      std::vector<std::thread> pool;
-      for (int t = 0; t < std::min(nt, P.n_sub); ++t)
-        pool.emplace_back([&]() {
-          for (int i = next++; i < P.n_sub; i = next++) {
-            try {
-              own_box(i);
-            } catch (const std::exception& ex) {  // (allocation) reported below, on the calling thread
-              oerr[i] = std::string("box ownership lists: ") + ex.what();
-            }
-          }
-        });
-      for (auto& th : pool) th.join();
-    }
-    for (int i = 0; i < P.n_sub; ++i)
-      if (!oerr[i].empty()) throw StatusError{1, oerr[i]};
-    std::vector<int64_t> own_ptr(total_D + 1, 0);
-    std::vector<int32_t> own_col;
-    std::vector<int64_t> own_vidx;
-    for (int i = 0; i < P.n_sub; ++i) {
-      const int64_t base = (int64_t)own_col.size();
-      for (size_t q = 0; q < P.D[i].size(); ++q) own_ptr[D_ptr[i] + q + 1] = base + oq[i][q + 1];
-      own_col.insert(own_col.end(), oc[i].begin(), oc[i].end());
-      own_vidx.insert(own_vidx.end(), ov[i].begin(), ov[i].end());
-      std::vector<int32_t>().swap(oc[i]);
-      std::vector<int64_t>().swap(ov[i]);
+      om.blo = dupload(A, blo, st);
+      om.bhi = dupload(A, bhi, st);
+      om_bufs = {(void*)om.blo, (void*)om.bhi};
+      GDSW_HIP(hipStreamSynchronize(st));  // the host vectors go out of scope
+    } else {
+      om.sub_ptr = dupload(A, P.sub_ptr, st);
+      om.sub_idx = dupload(A, P.sub_idx, st);
+      om_bufs = {(void*)om.sub_ptr, (void*)om.sub_idx};
     }
     int32_t* d_D_ptr = dupload(A, D_ptr, st);
     int32_t* d_D_idx = dupload(A, D_idx, st);
     int32_t* d_D_sub = dupload(A, D_sub, st);
     int64_t* d_box_off = dupload(A, box_off, st);
-    int64_t* d_own_ptr = dupload(A, own_ptr, st);
-    int32_t* d_own_col = dupload(A, own_col, st);
-    int64_t* d_own_vidx = dupload(A, own_vidx, st);
     int64_t* d_p_off = dupload(A, p_off, st);
-    BoxView bv{d_D_ptr, d_D_idx, d_D_sub, d_box_off, d_own_ptr, d_own_col, d_own_vidx};
+    BoxView bv{d_D_ptr, d_D_idx, d_D_sub, d_box_off};
     double* pbox = dalloc<double>(A, std::max<int64_t>(box_off.back(), 1));
     double* W = dalloc<double>(A, std::max<int64_t>(box_off.back(), 1));
     double* Pm = dalloc<double>(A, std::max<int64_t>(p_off.back(), 1));
     GDSW_HIP(hipMemsetAsync(pbox, 0, std::max<int64_t>(box_off.back(), 1) * 8, st));
     phibox(total_D, cv, bv, pbox, st);
-    own_spmm(P.n_sub, max_nd, cv, bv, ctx.d_val, pbox, W, st);
+    own_spmm(P.n_sub, max_nd, max_nc, cv, bv, om, ctx.d_rowptr, ctx.d_col, ctx.d_val, pbox, W, st);
     std::vector<GemmDesc> gd(P.n_sub);
     for (int i = 0; i < P.n_sub; ++i) {
       const int nd = (int)P.D[i].size(), nci = (int)P.C[i].size();
@@ -923,10 +874,10 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
     GDSW_HIP(hipMemsetAsync(ctx.d_A0, 0, (int64_t)Nc * Nc * 8, st));
     a0_assemble(Nc, cv, Pm, d_p_off, ctx.d_A0, st);
     GDSW_HIP(hipStreamSynchronize(st));
-    for (void* p : {(void*)d_D_ptr, (void*)d_D_idx, (void*)d_D_sub, (void*)d_box_off, (void*)d_own_ptr,
-                    (void*)d_own_col, (void*)d_own_vidx, (void*)d_p_off, (void*)pbox, (void*)W, (void*)Pm,
-                    (void*)d_gd})
+    for (void* p : {(void*)d_D_ptr, (void*)d_D_idx, (void*)d_D_sub, (void*)d_box_off, (void*)d_p_off,
+                    (void*)pbox, (void*)W, (void*)Pm, (void*)d_gd})
       A.free(p);
+    for (void* p : om_bufs) A.free(p);
 
     // coarse factor order: velocity-type columns first, then pressure-type
     ctx.coarse_perm.clear();
@@ -1190,40 +1141,87 @@ void device_setup(Context& ctx, hipStream_t st, uint64_t budget, int nb) {
       A.free(q);
     if (d_perm_b) A.free(d_perm_b);
     // B_i as row lists over work positions: pressure rows (velocity positions)
-    // and, without W, velocity rows (pressure positions), each subdomain in order
-    std::vector<int32_t> prow_pos, bm_pos, vrow_pos, bt_pos;
-    std::vector<int64_t> bm_ptr(1, 0), bt_ptr(1, 0);
-    std::vector<double> bm_val, bt_val;
-    for (int i = 0; i < P.n_sub; ++i) {
+    // and, without W, velocity rows (pressure positions), each subdomain in
+    // order.  The subdomains are listed in parallel and joined in order.
+    struct BRows {
+      std::vector<int32_t> prow_pos, bm_pos, vrow_pos, bt_pos;
+      std::vector<int64_t> bm_end, bt_end;  // row ends within the subdomain's lists
+      std::vector<double> bm_val, bt_val;
+    };
+    std::vector<BRows> br(P.n_sub);
+    parallel_items(P.n_sub, [&](int i) {
+      BRows& o = br[i];
       const int64_t vb = ctx.L1.xoff[i], npv = ctx.L1.npad[i], pb = ctx.LP.xoff[i];
       const auto& vx = bvx[i];
-      std::vector<std::tuple<int64_t, int64_t, double>> tr;  // (velocity position, pressure position, value)
       for (size_t q = 0; q < bpr[i].size(); ++q) {
         const int32_t g = bpr[i][q];
-        prow_pos.push_back((int32_t)(pb + (int64_t)q));
+        o.prow_pos.push_back((int32_t)(pb + (int64_t)q));
         for (int32_t e = P.row_ptr[g]; e < P.row_ptr[g + 1]; ++e) {
           const int32_t c = P.col[e];
           if (c >= P.n_u) continue;
           const int comp = c % 3;
           const auto it = std::lower_bound(vx.begin(), vx.end(), c - comp);
           if (it == vx.end() || *it != c - comp) continue;
-          const int64_t vp = vb + comp * npv + (it - vx.begin());
-          bm_pos.push_back((int32_t)vp);
-          bm_val.push_back(P.val[e]);
-          if (!b.use_w) tr.emplace_back(vp, pb + (int64_t)q, P.val[e]);
+          o.bm_pos.push_back((int32_t)(vb + comp * npv + (it - vx.begin())));
+          o.bm_val.push_back(P.val[e]);
         }
-        bm_ptr.push_back((int64_t)bm_pos.size());
+        o.bm_end.push_back((int64_t)o.bm_pos.size());
       }
-      std::sort(tr.begin(), tr.end());
-      for (size_t k = 0; k < tr.size(); ++k) {
-        if (k == 0 || std::get<0>(tr[k]) != std::get<0>(tr[k - 1])) {
-          if (k > 0) bt_ptr.push_back((int64_t)bt_pos.size());
-          vrow_pos.push_back((int32_t)std::get<0>(tr[k]));
+      if (b.use_w) return;
+      // B_i^T: the entries ordered by velocity position with a stable
+      // counting sort; the pressure rows were visited in ascending order, so
+      // each velocity row lists its pressure positions in ascending order
+      const int64_t nvp = 3 * npv;
+      std::vector<int64_t> start(nvp + 1, 0);
+      for (int32_t vp : o.bm_pos) ++start[vp - vb + 1];
+      for (int64_t v = 0; v < nvp; ++v) start[v + 1] += start[v];
+      std::vector<int64_t> put(start.begin(), start.end() - 1);
+      o.bt_pos.resize(o.bm_pos.size());
+      o.bt_val.resize(o.bm_pos.size());
+      size_t e = 0;
+      for (size_t q = 0; q < bpr[i].size(); ++q)
+        for (; e < (size_t)o.bm_end[q]; ++e) {
+          const int64_t k = put[o.bm_pos[e] - vb]++;
+          o.bt_pos[k] = (int32_t)(pb + (int64_t)q);
+          o.bt_val[k] = o.bm_val[e];
         }
-        bt_pos.push_back((int32_t)std::get<1>(tr[k]));
-        bt_val.push_back(std::get<2>(tr[k]));
+      for (int64_t v = 0; v < nvp; ++v)
+        if (start[v + 1] > start[v]) {
+          o.vrow_pos.push_back((int32_t)(vb + v));
+          o.bt_end.push_back(start[v + 1]);
+        }
+    });
+    std::vector<int32_t> prow_pos, bm_pos, vrow_pos, bt_pos;
+    std::vector<int64_t> bm_ptr(1, 0), bt_ptr(1, 0);
+    std::vector<double> bm_val, bt_val;
+    {
+      size_t np_tot = 0, nm_tot = 0, nv_tot = 0, nt_tot = 0;
+      for (const BRows& o : br) {
+        np_tot += o.prow_pos.size();
+        nm_tot += o.bm_pos.size();
+        nv_tot += o.vrow_pos.size();
+        nt_tot += o.bt_pos.size();
       }
-      if (!tr.empty()) bt_ptr.push_back((int64_t)bt_pos.size());
+      prow_pos.reserve(np_tot);
+      bm_ptr.reserve(np_tot + 1);
+      bm_pos.reserve(nm_tot);
+      bm_val.reserve(nm_tot);
+      vrow_pos.reserve(nv_tot);
+      bt_ptr.reserve(nv_tot + 1);
+      bt_pos.reserve(nt_tot);
+      bt_val.reserve(nt_tot);
+    }
+    for (BRows& o : br) {
+      const int64_t m0 = (int64_t)bm_pos.size(), t0 = (int64_t)bt_pos.size();
+      prow_pos.insert(prow_pos.end(), o.prow_pos.begin(), o.prow_pos.end());
+      for (int64_t x : o.bm_end) bm_ptr.push_back(m0 + x);
+      bm_pos.insert(bm_pos.end(), o.bm_pos.begin(), o.bm_pos.end());
+      bm_val.insert(bm_val.end(), o.bm_val.begin(), o.bm_val.end());
+      vrow_pos.insert(vrow_pos.end(), o.vrow_pos.begin(), o.vrow_pos.end());
+      for (int64_t x : o.bt_end) bt_ptr.push_back(t0 + x);
+      bt_pos.insert(bt_pos.end(), o.bt_pos.begin(), o.bt_pos.end());
+      bt_val.insert(bt_val.end(), o.bt_val.begin(), o.bt_val.end());
+      o = BRows();
     }
     b.n_prow = (int64_t)prow_pos.size();
     b.n_vrow = (int64_t)vrow_pos.size();

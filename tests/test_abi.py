@@ -194,3 +194,18 @@ def test_host_algebraic_rejections():
         G.Solver.algebraic(A.indptr, A.indices, A.data, bad, subs, host_only=True)
     with pytest.raises(G.GdswError):
         G.Solver.algebraic(A.indptr, A.indices, A.data, p.dof_field, [[]] + subs[1:], host_only=True)
+
+
+def test_host_algebraic_rejects_entry_across_subdomains():
+    """A nonzero whose DOFs share no subdomain is refused at the input check
+    (A_0 is assembled from the nonzeros each subdomain owns, which needs a
+    subdomain holding both DOFs)."""
+    p = StokesProblem(2)
+    A = p.A.tocsr()
+    A.sort_indices()
+    subs = [list(s) for s in _repeated_map(p, _box_partition(2, 2))]
+    r = next(d for d in range(p.n_free) if len(subs[d]) == 1)
+    c = next(int(k) for k in A.indices[A.indptr[r]:A.indptr[r + 1]] if k != r)
+    subs[c] = [next(k for k in range(8) if k not in subs[r])]
+    with pytest.raises(G.GdswError, match="share no subdomain"):
+        G.Solver.algebraic(A.indptr, A.indices, A.data, p.dof_field, subs, host_only=True)
