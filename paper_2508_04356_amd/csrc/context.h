@@ -50,8 +50,8 @@ template <class T>
 T* dalloc(DeviceArena& A, uint64_t count) {
   return static_cast<T*>(A.alloc(count * sizeof(T)));
 }
-template <class T>
-T* dupload(DeviceArena& A, const std::vector<T>& v, hipStream_t st) {
+template <class T, class Al>
+T* dupload(DeviceArena& A, const std::vector<T, Al>& v, hipStream_t st) {
   T* p = dalloc<T>(A, v.empty() ? 1 : v.size());
   if (!v.empty()) GDSW_HIP(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
   return p;

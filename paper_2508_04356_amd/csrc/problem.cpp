@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <exception>
 #include <map>
 #include <stdexcept>
 #include <thread>
@@ -88,22 +89,24 @@ inline void box_range(int coord, int s, int m, int& lo, int& hi) {
   hi = std::min(coord / two_s, m - 1);
 }
 
+// f(t) for t in [0, nt), t = 0 on the calling thread; an exception thrown by
+// any of them is rethrown here (the lowest t first)
 template <class F>
-void parallel_for(int64_t n, int threads, F&& f) {
-  if (threads <= 1 || n < 1024) {
-    for (int64_t i = 0; i < n; ++i) f(i);
-    return;
-  }
+void run_threads(int nt, F&& f) {
+  std::vector<std::exception_ptr> err(nt);
+  auto guarded = [&](int t) {
+    try {
+      f(t);
+    } catch (...) {
+      err[t] = std::current_exception();
+    }
+  };
   std::vector<std::thread> pool;
-  const int64_t chunk = (n + threads - 1) / threads;
-  for (int t = 0; t < threads; ++t) {
-    const int64_t b = t * chunk, e = std::min(n, b + chunk);
-    if (b >= e) break;
-    pool.emplace_back([&f, b, e]() {
-      for (int64_t i = b; i < e; ++i) f(i);
-    });
-  }
+  for (int t = 1; t < nt; ++t) pool.emplace_back(guarded, t);
+  guarded(0);
   for (auto& th : pool) th.join();
+  for (auto& e : err)
+    if (e) std::rethrow_exception(e);
 }
 
 }  // namespace
@@ -220,94 +223,121 @@ void build_problem(const ProblemSpec& spec, Problem& P, int threads) {
     return a == 0 ? 2.0 * (x - 0.5) * (x - 1.0) : (a == 1 ? 4.0 * x * (1.0 - x) : 2.0 * x * (x - 0.5));
   };
 
-  std::vector<std::vector<std::pair<int32_t, double>>> rows(P.n_free);
+  // Rows are assembled in contiguous chunks, one per thread, in two passes
+  // (the first counts each row's entries, the second writes them into the
+  // CSR arrays), so the threads allocate nothing.  A row's columns lie in the neighbourhood of its
+  // node: per axis the nodes 2 elo .. 2 elo + 4 of the elements holding it
+  // (velocity) and the pressure nodes elo .. elo + 2 (Q1) or the elements
+  // elo .. elo + 1 (P1disc).  Each column has a slot there, and slot order
+  // is column order (DOFs are numbered node-major, z slowest, pressure after
+  // velocity), so the element contributions are summed per slot in element
+  // order and the touched slots are emitted in order.
+  constexpr int NVS = 5 * 5 * 5 * 3, NPS = 32;  // velocity, pressure slots (Q1 needs 27)
+  const int nth = (int)std::max<int64_t>(1, std::min<int64_t>(threads, (P.n_free + 1023) / 1024));
+  const int64_t chunk = (P.n_free + nth - 1) / nth;
+  P.row_ptr.assign(P.n_free + 1, 0);
   P.rhs.assign(P.n_free, 0.0);
-  parallel_for(P.n_free, threads, [&](int64_t r) {
-    const int A = P.abc[3 * r], B = P.abc[3 * r + 1], Cc = P.abc[3 * r + 2];
-    const int fr = P.field[r];
-    int elo[3], ehi[3];
-    const int crd[3] = {A, B, Cc};
-    for (int d = 0; d < 3; ++d) {
-      if (crd[d] % 2 == 0) {
-        elo[d] = std::max(crd[d] / 2 - 1, 0);
-        ehi[d] = std::min(crd[d] / 2, n - 1);
-      } else {
-        elo[d] = ehi[d] = (crd[d] - 1) / 2;
+  auto assemble_rows = [&](int t, bool write) {
+    const int64_t r0 = t * chunk, r1 = std::min<int64_t>(P.n_free, r0 + chunk);
+    double acc[NVS + NPS];
+    int32_t scol[NVS + NPS];
+    int64_t mark[NVS + NPS];  // the row that last touched the slot
+    std::fill(mark, mark + NVS + NPS, (int64_t)-1);
+    for (int64_t r = r0; r < r1; ++r) {
+      const int A = P.abc[3 * r], B = P.abc[3 * r + 1], Cc = P.abc[3 * r + 2];
+      const int fr = P.field[r];
+      int elo[3], ehi[3];
+      const int crd[3] = {A, B, Cc};
+      for (int d = 0; d < 3; ++d) {
+        if (crd[d] % 2 == 0) {
+          elo[d] = std::max(crd[d] / 2 - 1, 0);
+          ehi[d] = std::min(crd[d] / 2, n - 1);
+        } else {
+          elo[d] = ehi[d] = (crd[d] - 1) / 2;
+        }
       }
-    }
-    std::vector<std::pair<int32_t, double>> ent;
-    ent.reserve(720);
-    double rhs = 0.0;
-    for (int ez = elo[2]; ez <= ehi[2]; ++ez)
-      for (int ey = elo[1]; ey <= ehi[1]; ++ey)
-        for (int ex = elo[0]; ex <= ehi[0]; ++ex) {
-          int li;
-          if (fr < 3) {
-            li = 3 * ((A - 2 * ex) + 3 * ((B - 2 * ey) + 3 * (Cc - 2 * ez))) + fr;
-          } else if (disc) {
-            li = 81 + (int)((r - P.n_u) % 4);
-          } else {
-            li = 81 + (A / 2 - ex) + 2 * ((B / 2 - ey) + 2 * (Cc / 2 - ez));
-          }
-          for (int lb = 0; lb < 27; ++lb) {
-            const int ga = 2 * ex + lb % 3, gb = 2 * ey + (lb / 3) % 3, gc = 2 * ez + lb / 9;
-            for (int comp = 0; comp < 3; ++comp) {
-              const double v = E.a[li][3 * lb + comp];
+      auto add = [&](int slot, int32_t c, double v) {
+        if (mark[slot] != r) {
+          mark[slot] = r;
+          scol[slot] = c;
+          acc[slot] = v;
+        } else {
+          acc[slot] += v;
+        }
+      };
+      double rhs = 0.0;
+      for (int ez = elo[2]; ez <= ehi[2]; ++ez)
+        for (int ey = elo[1]; ey <= ehi[1]; ++ey)
+          for (int ex = elo[0]; ex <= ehi[0]; ++ex) {
+            int li;
+            if (fr < 3) {
+              li = 3 * ((A - 2 * ex) + 3 * ((B - 2 * ey) + 3 * (Cc - 2 * ez))) + fr;
+            } else if (disc) {
+              li = 81 + (int)((r - P.n_u) % 4);
+            } else {
+              li = 81 + (A / 2 - ex) + 2 * ((B / 2 - ey) + 2 * (Cc / 2 - ez));
+            }
+            for (int lb = 0; lb < 27; ++lb) {
+              const int ga = 2 * ex + lb % 3, gb = 2 * ey + (lb / 3) % 3, gc = 2 * ez + lb / 9;
+              for (int comp = 0; comp < 3; ++comp) {
+                const double v = E.a[li][3 * lb + comp];
+                if (v == 0.0) continue;
+                if (vel_free(ga, gb, gc))
+                  add(3 * ((ga - 2 * elo[0]) + 5 * ((gb - 2 * elo[1]) + 5 * (gc - 2 * elo[2]))) + comp,
+                      (int32_t)vel_dof(ga, gb, gc, comp), v);
+                else if (comp == 0)
+                  rhs -= v * inflow(ga, gb, gc);
+              }
+            }
+            for (int q = 0; q < npe; ++q) {
+              const double v = E.a[li][81 + q];
               if (v == 0.0) continue;
-              if (vel_free(ga, gb, gc))
-                ent.emplace_back((int32_t)vel_dof(ga, gb, gc, comp), v);
-              else if (comp == 0)
-                rhs -= v * inflow(ga, gb, gc);
+              if (disc)
+                add(NVS + 4 * ((ex - elo[0]) + 2 * ((ey - elo[1]) + 2 * (ez - elo[2]))) + q,
+                    (int32_t)pe_dof(ex + (int64_t)n * (ey + (int64_t)n * ez), q), v);
+              else
+                add(NVS + (ex + q % 2 - elo[0]) + 3 * ((ey + (q / 2) % 2 - elo[1]) + 3 * (ez + q / 4 - elo[2])),
+                    (int32_t)p_dof(ex + q % 2, ey + (q / 2) % 2, ez + q / 4), v);
+            }
+            if (spec.manufactured && fr == 0) {
+              // int f_x phi = h^3 int L_ax dxi * int int f(y, z) L_ay L_az (3-point Gauss, exact)
+              const int ax = A - 2 * ex, ay = B - 2 * ey, az = Cc - 2 * ez;
+              double s2 = 0.0;
+              for (int qy = 0; qy < 3; ++qy)
+                for (int qz = 0; qz < 3; ++qz) {
+                  const double y = (ey + gp[qy]) * h, z = (ez + gp[qz]) * h;
+                  const double f = 2.0 * spec.mu * spec.c * (y * (1.0 - y) + z * (1.0 - z));
+                  s2 += gw[qy] * gw[qz] * f * L2(ay, gp[qy]) * L2(az, gp[qz]);
+                }
+              rhs += h * h * h * intL[ax] * s2;
             }
           }
-          for (int q = 0; q < npe; ++q) {
-            const double v = E.a[li][81 + q];
-            if (v == 0.0) continue;
-            ent.emplace_back((int32_t)(disc ? pe_dof(ex + (int64_t)n * (ey + (int64_t)n * ez), q)
-                                            : p_dof(ex + q % 2, ey + (q / 2) % 2, ez + q / 4)),
-                             v);
-          }
-          if (spec.manufactured && fr == 0) {
-            // int f_x phi = h^3 int L_ax dxi * int int f(y, z) L_ay L_az (3-point Gauss, exact)
-            const int ax = A - 2 * ex, ay = B - 2 * ey, az = Cc - 2 * ez;
-            double s2 = 0.0;
-            for (int qy = 0; qy < 3; ++qy)
-              for (int qz = 0; qz < 3; ++qz) {
-                const double y = (ey + gp[qy]) * h, z = (ez + gp[qz]) * h;
-                const double f = 2.0 * spec.mu * spec.c * (y * (1.0 - y) + z * (1.0 - z));
-                s2 += gw[qy] * gw[qz] * f * L2(ay, gp[qy]) * L2(az, gp[qz]);
-              }
-            rhs += h * h * h * intL[ax] * s2;
-          }
+      if (!write) {  // pass 1: the row's entry count, kept in row_ptr[r + 1]
+        int32_t cnt = 0;
+        for (int k = 0; k < NVS + NPS; ++k) cnt += mark[k] == r;
+        P.row_ptr[r + 1] = cnt;
+        continue;
+      }
+      int64_t o = P.row_ptr[r];
+      for (int k = 0; k < NVS + NPS; ++k)
+        if (mark[k] == r) {
+          P.col[o] = scol[k];
+          P.val[o] = acc[k];
+          ++o;
         }
-    std::stable_sort(ent.begin(), ent.end(),
-                     [](const std::pair<int32_t, double>& x, const std::pair<int32_t, double>& y) {
-                       return x.first < y.first;
-                     });
-    auto& row = rows[r];
-    for (auto& e : ent) {
-      if (!row.empty() && row.back().first == e.first)
-        row.back().second += e.second;
-      else
-        row.push_back(e);
+      P.rhs[r] = rhs;
     }
-    P.rhs[r] = rhs;
-  });
-  P.row_ptr.assign(P.n_free + 1, 0);
-  for (int64_t r = 0; r < P.n_free; ++r) P.row_ptr[r + 1] = P.row_ptr[r] + (int32_t)rows[r].size();
-  const int64_t nnz = P.row_ptr[P.n_free];
-  if (nnz > INT32_MAX) throw std::invalid_argument("matrix too large for int32 CSR");
+  };
+  run_threads(nth, [&](int t) { assemble_rows(t, false); });
+  int64_t nnz = 0;
+  for (int64_t r = 0; r < P.n_free; ++r) {
+    nnz += P.row_ptr[r + 1];
+    if (nnz > INT32_MAX) throw std::invalid_argument("matrix too large for int32 CSR");
+    P.row_ptr[r + 1] = (int32_t)nnz;
+  }
   P.col.resize(nnz);
   P.val.resize(nnz);
-  parallel_for(P.n_free, threads, [&](int64_t r) {
-    int64_t o = P.row_ptr[r];
-    for (auto& e : rows[r]) {
-      P.col[o] = e.first;
-      P.val[o] = e.second;
-      ++o;
-    }
-    std::vector<std::pair<int32_t, double>>().swap(rows[r]);
-  });
+  run_threads(nth, [&](int t) { assemble_rows(t, true); });
 
   // ---- decomposition ----------------------------------------------------
   const int s = P.s;

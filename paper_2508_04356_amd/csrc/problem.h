@@ -7,10 +7,38 @@
 
 #include <array>
 #include <cstdint>
+#include <memory>
+#include <new>
 #include <string>
+#include <type_traits>
+#include <utility>
 #include <vector>
 
 namespace gdsw {
+
+// An allocator whose value-initialisation leaves the elements uninitialised,
+// so that resize() of a large array does not touch its pages: the matrix
+// assembly threads write (and first touch) every entry themselves.
+template <class T>
+struct NoInitAlloc : std::allocator<T> {
+  template <class U>
+  struct rebind {
+    using other = NoInitAlloc<U>;
+  };
+  NoInitAlloc() = default;
+  template <class U>
+  NoInitAlloc(const NoInitAlloc<U>&) noexcept {}
+  template <class U>
+  void construct(U* p) noexcept(std::is_nothrow_default_constructible<U>::value) {
+    ::new (static_cast<void*>(p)) U;
+  }
+  template <class U, class... Args>
+  void construct(U* p, Args&&... args) {
+    ::new (static_cast<void*>(p)) U(std::forward<Args>(args)...);
+  }
+};
+template <class T>
+using bulk_vector = std::vector<T, NoInitAlloc<T>>;
 
 struct ProblemSpec {
   int n = 4;            // elements per axis
@@ -45,8 +73,8 @@ struct Problem {
 
   // free-DOF CSR matrix (sorted columns) and lifted right-hand side
   std::vector<int32_t> row_ptr;
-  std::vector<int32_t> col;
-  std::vector<double> val;
+  bulk_vector<int32_t> col;
+  bulk_vector<double> val;
   std::vector<double> rhs;
 
   // per free DOF
