@@ -171,38 +171,58 @@ __global__ __launch_bounds__(256) void gj_update_kernel(double* __restrict__ bas
   const int64_t ld = LD[f];
   double* A = base + OFF[f];
   const double* T = Tbuf + (int64_t)f * tstride;
-  __shared__ double Xs[GB][GB + 1];  // [row][l]
-  __shared__ double Ys[GB][GB + 1];  // [l][col]
+  // The 64-deep product runs in two halves of 32 (the same k order), so the
+  // staged panels take 33 KB of LDS and four work-groups fit a CU; the
+  // tile's own entries are loaded first, their latency overlapping the
+  // staging, and the update is written as old - product.
+  constexpr int KH = GB / 2;
+  __shared__ double Xs[GB][KH + 1];  // [row][l]
+  __shared__ double Ys[KH][GB + 1];  // [l][col]
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < GB * GB; idx += 256) {
-    const int r = idx % GB, l = idx / GB;
-    Xs[r][l] = (r < rb && l < bs) ? A[(int64_t)(k0 + l) * ld + r0 + r] : 0.0;
-    Ys[r][l] = (l < cb && r < bs) ? T[(int64_t)(c0 + l) * GB + r] : 0.0;  // Ys[l = r][col = l]
-  }
-  __syncthreads();
   // 64 x 64 x 64 product on the matrix cores (v_mfma_f64_16x16x4), computed
   // transposed, D = (X Y)^T, so that a lane's results are consecutive rows
   // of the column-major tile: wave w owns the 32 x 32 quadrant (w / 2, w % 2)
   // as 2 x 2 blocks of 16 x 16; lane (i, kq) feeds A[i][kq] = Y[kq][col i]
-  // and B[kq][i] = X[row i][kq] of every 4-deep step.
+  // and B[kq][i] = X[row i][kq] of every 4-deep step.  Accumulator register
+  // t of a lane: D row kq + 4 t = tile column, D column i = tile row.
   const int lane = tid & 63, wave = tid >> 6;
   const int i = lane & 15, kq = lane >> 4;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  double cur[2][2][4];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int t4 = 0; t4 < 4; ++t4) {
+        const int r = wr + 16 * bi + i, c = wc + 16 * bj + kq + 4 * t4;
+        cur[bi][bj][t4] = (r < rb && c < cb) ? A[(int64_t)(c0 + c) * ld + r0 + r] : 0.0;
+      }
   mf64x4 acc[2][2];  // [row block][column block]
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = mf64x4{0, 0, 0, 0};
-#pragma unroll 4
-  for (int l0 = 0; l0 < GB; l0 += 4) {
-    const double x0 = Xs[wr + i][l0 + kq], x1 = Xs[wr + 16 + i][l0 + kq];
-    const double y0 = Ys[l0 + kq][wc + i], y1 = Ys[l0 + kq][wc + 16 + i];
-    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0, x0, acc[0][0], 0, 0, 0);
-    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(y1, x0, acc[0][1], 0, 0, 0);
-    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0, x1, acc[1][0], 0, 0, 0);
-    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(y1, x1, acc[1][1], 0, 0, 0);
+  for (int h = 0; h < 2; ++h) {
+    for (int idx = tid; idx < GB * KH; idx += 256) {
+      // X: rows fastest (A is column-major); Y: k fastest (T is column-major)
+      const int r = idx % GB, l = idx / GB;
+      Xs[r][l] = (r < rb && h * KH + l < bs) ? A[(int64_t)(k0 + h * KH + l) * ld + r0 + r] : 0.0;
+      const int lk = idx % KH, c = idx / KH;
+      Ys[lk][c] = (c < cb && h * KH + lk < bs) ? T[(int64_t)(c0 + c) * GB + h * KH + lk] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int l0 = 0; l0 < KH; l0 += 4) {
+      const double x0 = Xs[wr + i][l0 + kq], x1 = Xs[wr + 16 + i][l0 + kq];
+      const double y0 = Ys[l0 + kq][wc + i], y1 = Ys[l0 + kq][wc + 16 + i];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0, x0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(y1, x0, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(y0, x1, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(y1, x1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
   }
-  // accumulator register t of a lane: D row kq + 4 t = tile column, D column i = tile row
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi) {
     const int r = wr + 16 * bi + i;
@@ -212,7 +232,7 @@ __global__ __launch_bounds__(256) void gj_update_kernel(double* __restrict__ bas
 #pragma unroll
       for (int t4 = 0; t4 < 4; ++t4) {
         const int c = wc + 16 * bj + kq + 4 * t4;
-        if (c < cb) A[(int64_t)(c0 + c) * ld + r0 + r] -= acc[bi][bj][t4];
+        if (c < cb) A[(int64_t)(c0 + c) * ld + r0 + r] = cur[bi][bj][t4] - acc[bi][bj][t4];
       }
   }
 }
