@@ -30,6 +30,16 @@ def test_every_declared_symbol_is_exported_and_bound():
         assert s in G.EXPORTED, s
 
 
+def _check_sorted_rows(rp, col):
+    """Every CSR row lists distinct columns in ascending order (the assembly
+    emits a row's entries in column order without sorting them)."""
+    d = np.diff(col.astype(np.int64))
+    row_start = np.zeros(len(col), dtype=bool)
+    row_start[rp[:-1][rp[:-1] < len(col)]] = True
+    assert np.all(d[~row_start[1:]] > 0)
+    assert np.all(np.diff(rp) > 0)
+
+
 @pytest.mark.parametrize("n,m,mu,c,man", [(4, 2, 1.0, 16.0, 0), (6, 3, 0.7, 3.0, 1), (6, 2, 2.0, 1.0, 0)])
 def test_host_assembly_matches_oracle(n, m, mu, c, man):
     s = G.Solver(n, m, host_only=True, viscosity=mu, inflow=c, manufactured=man)
@@ -38,6 +48,7 @@ def test_host_assembly_matches_oracle(n, m, mu, c, man):
     assert sz.n_free == p.n_free and sz.n_full == p.n_full == dof_count_q2q1(n)
     assert sz.n_u_free == p.n_u and sz.n_p == p.n_p
     rp, col, val = s.host_matrix()
+    _check_sorted_rows(rp, col)
     A = sp.csr_matrix((val, col, rp), shape=(sz.n_free, sz.n_free))
     assert abs(A - p.A).max() <= 1e-15 * abs(p.A).max()
     assert np.abs(s.host_rhs() - p.b).max() <= 1e-14 * max(1.0, np.abs(p.b).max())
@@ -114,6 +125,7 @@ def test_host_p1disc_setup_matches_oracle(n, m, coarse):
     d = Decomposition(p, m, 1, local_dirichlet=False, coarse=coarse)
     assert sz.n_free == p.n_free and sz.n_p == 4 * n ** 3
     rp, col, val = s.host_matrix()
+    _check_sorted_rows(rp, col)
     A = sp.csr_matrix((val, col, rp), shape=(sz.n_free, sz.n_free))
     assert abs(A - p.A).max() <= 1e-15 * abs(p.A).max()
     assert np.abs(s.host_rhs() - p.b).max() <= 1e-14 * max(1.0, np.abs(p.b).max())
