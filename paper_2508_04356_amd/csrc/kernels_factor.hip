@@ -143,27 +143,45 @@ __global__ __launch_bounds__(256) void lu_update_kernel(double* __restrict__ bas
   const int rb = min(LB, n - r0), cb = min(LB, n - c0);
   const int64_t ld = LD[f];
   double* A = base + OFF[f];
-  __shared__ double Ls[LB][LB + 1];  // [row][l]
-  __shared__ double Us[LB][LB + 1];  // [l][col]
+  // The tile's own entries are loaded first (their latency overlaps the
+  // staging) and the update is written as old - product; the 64-deep product
+  // runs in two halves of 32 (l ascending, as in one pass), so the staged
+  // panels take 33 KB of LDS and four work-groups fit a CU.
+  constexpr int KH = LB / 2;
+  __shared__ double Ls[LB][KH + 1];  // [row][l]
+  __shared__ double Us[KH][LB + 1];  // [l][col]
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < LB * LB; idx += 256) {
-    const int r = idx % LB, l = idx / LB;
-    Ls[r][l] = r < rb ? A[(int64_t)(k0 + l) * ld + r0 + r] : 0.0;
-    Us[r][l] = l < cb ? A[(int64_t)(c0 + l) * ld + k0 + r] : 0.0;  // Us[l=r][col=l]
-  }
-  __syncthreads();
   const int tx = tid & 15, ty = tid >> 4;
+  double cur[4][4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int r = tx + 16 * a, c = ty + 16 * b;
+      cur[a][b] = (r < rb && c < cb) ? A[(int64_t)(c0 + c) * ld + r0 + r] : 0.0;
+    }
   double acc[4][4] = {};
-  for (int l = 0; l < LB; ++l) {
-    double av[4], bv[4];
+  for (int h = 0; h < 2; ++h) {
+    for (int idx = tid; idx < LB * KH; idx += 256) {
+      // L panel: rows fastest; U panel: k fastest (both column-major)
+      const int r = idx % LB, l = idx / LB;
+      Ls[r][l] = r < rb ? A[(int64_t)(k0 + h * KH + l) * ld + r0 + r] : 0.0;
+      const int lk = idx % KH, c = idx / KH;
+      Us[lk][c] = c < cb ? A[(int64_t)(c0 + c) * ld + k0 + h * KH + lk] : 0.0;
+    }
+    __syncthreads();
+    for (int l = 0; l < KH; ++l) {
+      double av[4], bv[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) av[a] = Ls[tx + 16 * a][l];
+      for (int a = 0; a < 4; ++a) av[a] = Ls[tx + 16 * a][l];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) bv[b] = Us[l][ty + 16 * b];
+      for (int b = 0; b < 4; ++b) bv[b] = Us[l][ty + 16 * b];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+        for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+    }
+    __syncthreads();
   }
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
@@ -172,7 +190,7 @@ __global__ __launch_bounds__(256) void lu_update_kernel(double* __restrict__ bas
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       const int r = tx + 16 * a;
-      if (r < rb) A[(int64_t)(c0 + c) * ld + r0 + r] -= acc[a][b];
+      if (r < rb) A[(int64_t)(c0 + c) * ld + r0 + r] = cur[a][b] - acc[a][b];
     }
   }
 }
