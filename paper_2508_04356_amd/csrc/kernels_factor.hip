@@ -520,18 +520,33 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
   __shared__ double Bs[16][65];
   const int tid = threadIdx.x;
   const int tx = tid & 15, ty = tid >> 4;
-  double acc[4][4] = {};
-  for (int k0 = 0; k0 < d.k; k0 += 16) {
-    for (int idx = tid; idx < 16 * 64; idx += 256) {
-      const int i = idx % 64, kk = idx / 64;
+  // the next 16-deep chunk of both operands is loaded into registers while
+  // the current one is multiplied (op(A) along its rows, or its k when
+  // transposed; B along k), then stored to LDS
+  double pa[4], pb[4];
+  auto load_chunk = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + 256 * q;
+      const int i = d.transA ? idx / 16 : idx % 64, kk = d.transA ? idx % 16 : idx / 64;
       const int r = r0 + i, kx = k0 + kk;
-      double av = 0.0;
-      if (r < d.m && kx < d.k) av = d.transA ? d.A[(int64_t)r * d.lda + kx] : d.A[(int64_t)kx * d.lda + r];
-      As[kk][i] = av;
-      const int c = c0 + i;
-      Bs[kk][i] = (c < d.n && kx < d.k) ? d.B[(int64_t)c * d.ldb + kx] : 0.0;
+      pa[q] = (r < d.m && kx < d.k) ? (d.transA ? d.A[(int64_t)r * d.lda + kx] : d.A[(int64_t)kx * d.lda + r]) : 0.0;
+      const int ib = idx / 16, kb = idx % 16;
+      const int c = c0 + ib, ky = k0 + kb;
+      pb[q] = (c < d.n && ky < d.k) ? d.B[(int64_t)c * d.ldb + ky] : 0.0;
+    }
+  };
+  double acc[4][4] = {};
+  load_chunk(0);
+  for (int k0 = 0; k0 < d.k; k0 += 16) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + 256 * q;
+      As[d.transA ? idx % 16 : idx / 64][d.transA ? idx / 16 : idx % 64] = pa[q];
+      Bs[idx % 16][idx / 16] = pb[q];
     }
     __syncthreads();
+    if (k0 + 16 < d.k) load_chunk(k0 + 16);
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk) {
       double av[4], bv[4];
